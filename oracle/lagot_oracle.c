@@ -1,0 +1,480 @@
+/*
+ * lagot_oracle.c -- plain FP64 CPU reference ("oracle") for the generalized
+ * Laguerre cells of semi-discrete partial optimal transport.
+ *
+ * TEST INFRASTRUCTURE ONLY: tests, the smoke check and the CPU-baseline leg of
+ * the benchmark call this file; the product path never does. It shares no code
+ * with the HIP kernels.
+ *
+ * What it computes (paper: section 2.2 "Free Surface", eq. (1); section 3.2
+ * "Pyramid Decomposition"; section 3.3 "Area of Spherical Patches";
+ * Algorithm 2 "Facets areas and volume of a Laguerre cell restricted to a
+ * sphere"):
+ *
+ *   C_i = box  ∩  B(p_i, sqrt(psi_i))  ∩  { x : |x-p_i|^2 - psi_i <= |x-p_j|^2 - psi_j  for all j != i }
+ *
+ * and, for each site i,
+ *   V_i  = |C_i|                       volume
+ *   K_i  = |∂B_i ∩ C_i|               free (spherical) surface area
+ *   A_ij = |C_i ∩ bisector(i,j)|       restricted Laguerre facet areas
+ *   W_iw = |C_i ∩ wall w|              box-wall facet areas (w = -x,+x,-y,+y,-z,+z)
+ *
+ * Route (written plainly, no blocking or reordering beyond the definition):
+ *   1. neighbours by brute force over all j; the bisector of (i,j) in coordinates
+ *      local to p_i is { y : n_ij . y = t_ij } with n_ij = (p_j-p_i)/d_ij and
+ *      t_ij = (d_ij^2 + psi_i - psi_j) / (2 d_ij)  (section 3.2, h_ij read as a
+ *      signed scalar with its factor 1/2);
+ *   2. the polytope box ∩ cube(p_i, 2r) ∩ half-spaces is built as explicit face
+ *      polygons by Sutherland-Hodgman clipping of every face, in ascending t;
+ *   3. every facet polygon is restricted to its disk (centre q = t n, radius
+ *      rho = sqrt(r^2 - t^2)) by the signed fan of triangles and circular sectors
+ *      around q (section 3.2: "triangles and circular sectors"); the same fan
+ *      gives the solid angle the restricted facet subtends at p_i;
+ *   4. occlusion identity (section 3.3, |K_i| = |Sigma_i| - sum of projected
+ *      facets) with the projection centre c = p_i and signed solid angles:
+ *      K_i = r^2 (4 pi [p_i in C_i] - sum_f sgn(t_f) Omega_f);
+ *   5. pyramid decomposition with F = (x - p_i)/3 (section 3.2):
+ *      V_i = (1/3) (sum_f t_f A_f + r K_i).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+
+enum { OR_OK = 0, OR_EMPTY = 1, OR_FACET_CAP = 2 };
+
+typedef struct {
+    double n[3]; /* unit outward normal of the half-space n.y <= t (local coords) */
+    double t;    /* signed distance of the plane from p_i                        */
+    long id;     /* >= 0 neighbour site, -1..-6 box wall, -7..-12 auxiliary cube  */
+} oplane;
+
+typedef struct {
+    int plane;   /* index into the plane table */
+    int nv, cap;
+    double *v;   /* nv * 3 vertices, counter-clockwise seen from outside */
+} oface;
+
+typedef struct {
+    int nf, cap;
+    oface *f;
+} opoly;
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void face_push(oface *f, const double *p)
+{
+    if (f->nv == f->cap) {
+        f->cap = f->cap ? 2 * f->cap : 8;
+        f->v = (double *)realloc(f->v, sizeof(double) * 3 * (size_t)f->cap);
+    }
+    memcpy(f->v + 3 * f->nv, p, 3 * sizeof(double));
+    f->nv++;
+}
+
+static oface *poly_new_face(opoly *P, int plane)
+{
+    if (P->nf == P->cap) {
+        P->cap = P->cap ? 2 * P->cap : 16;
+        P->f = (oface *)realloc(P->f, sizeof(oface) * (size_t)P->cap);
+    }
+    oface *f = &P->f[P->nf++];
+    f->plane = plane;
+    f->nv = 0;
+    f->cap = 0;
+    f->v = NULL;
+    return f;
+}
+
+static void poly_free(opoly *P)
+{
+    for (int k = 0; k < P->nf; ++k) free(P->f[k].v);
+    free(P->f);
+    P->f = NULL;
+    P->nf = P->cap = 0;
+}
+
+/* --- ordering of points of a planar convex set, counter-clockwise about n --- */
+typedef struct {
+    double ang;
+    double p[3];
+} angpt;
+
+static int cmp_angpt(const void *a, const void *b)
+{
+    const angpt *u = (const angpt *)a, *v = (const angpt *)b;
+    if (u->ang < v->ang) return -1;
+    if (u->ang > v->ang) return 1;
+    for (int k = 0; k < 3; ++k) {
+        if (u->p[k] < v->p[k]) return -1;
+        if (u->p[k] > v->p[k]) return 1;
+    }
+    return 0;
+}
+
+static void plane_frame(const double *n, double *e1, double *e2)
+{
+    /* e1 perpendicular to n, e2 = n x e1, so that increasing angle is counter-clockwise about n */
+    double a[3] = {0, 0, 0};
+    int k = (fabs(n[0]) <= fabs(n[1]) && fabs(n[0]) <= fabs(n[2])) ? 0 : (fabs(n[1]) <= fabs(n[2]) ? 1 : 2);
+    a[k] = 1.0;
+    double c[3];
+    cross3(n, a, c);
+    double l = sqrt(dot3(c, c));
+    for (int m = 0; m < 3; ++m) e1[m] = c[m] / l;
+    cross3(n, e1, e2);
+}
+
+/* Sort pts (count m) counter-clockwise about n, drop exact duplicates; returns new count. */
+static int order_ccw(angpt *pts, int m, const double *n)
+{
+    if (m == 0) return 0;
+    double c[3] = {0, 0, 0}, e1[3], e2[3];
+    for (int k = 0; k < m; ++k)
+        for (int q = 0; q < 3; ++q) c[q] += pts[k].p[q] / m;
+    plane_frame(n, e1, e2);
+    for (int k = 0; k < m; ++k) {
+        double d[3] = {pts[k].p[0] - c[0], pts[k].p[1] - c[1], pts[k].p[2] - c[2]};
+        pts[k].ang = atan2(dot3(d, e2), dot3(d, e1));
+    }
+    qsort(pts, (size_t)m, sizeof(angpt), cmp_angpt);
+    int w = 0;
+    for (int k = 0; k < m; ++k) {
+        if (w > 0 && memcmp(pts[w - 1].p, pts[k].p, sizeof(pts[k].p)) == 0) continue;
+        pts[w++] = pts[k];
+    }
+    if (w > 1 && memcmp(pts[0].p, pts[w - 1].p, sizeof(pts[0].p)) == 0) w--;
+    return w;
+}
+
+/* Point where the segment a-b meets plane (n,t); endpoints taken in a fixed
+ * (lexicographic) order so that the two faces sharing an edge get the same bits. */
+static void edge_cut(const double *a, const double *b, const oplane *pl, double *out)
+{
+    const double *A = a, *B = b;
+    for (int k = 0; k < 3; ++k) {
+        if (a[k] < b[k]) break;
+        if (a[k] > b[k]) {
+            A = b;
+            B = a;
+            break;
+        }
+    }
+    double sA = dot3(pl->n, A) - pl->t, sB = dot3(pl->n, B) - pl->t;
+    double s = sA / (sA - sB);
+    for (int k = 0; k < 3; ++k) out[k] = A[k] + (B[k] - A[k]) * s;
+}
+
+/* Clip polytope P by half-space n.y <= t of plane index pidx (table pl). */
+static void poly_clip(opoly *P, const oplane *pl, int pidx)
+{
+    const oplane *h = &pl[pidx];
+    int cutcap = 64, ncut = 0;
+    angpt *cut = (angpt *)malloc(sizeof(angpt) * (size_t)cutcap);
+    int w = 0;
+    for (int k = 0; k < P->nf; ++k) {
+        oface *f = &P->f[k];
+        oface g = {f->plane, 0, 0, NULL};
+        for (int e = 0; e < f->nv; ++e) {
+            const double *a = f->v + 3 * e;
+            const double *b = f->v + 3 * ((e + 1) % f->nv);
+            double sa = dot3(h->n, a) - h->t;
+            double sb = dot3(h->n, b) - h->t;
+            if (sa <= 0.0) face_push(&g, a);
+            double ip[3];
+            int has_cut = 0;
+            if (sa == 0.0) {
+                memcpy(ip, a, sizeof(ip));
+                has_cut = 1;
+            }
+            if ((sa < 0.0 && sb > 0.0) || (sa > 0.0 && sb < 0.0)) {
+                edge_cut(a, b, h, ip);
+                face_push(&g, ip);
+                has_cut = 1;
+            }
+            if (has_cut) {
+                if (ncut == cutcap) {
+                    cutcap *= 2;
+                    cut = (angpt *)realloc(cut, sizeof(angpt) * (size_t)cutcap);
+                }
+                memcpy(cut[ncut++].p, ip, sizeof(ip));
+            }
+        }
+        free(f->v);
+        if (g.nv >= 3) {
+            P->f[w++] = g;
+        } else {
+            free(g.v);
+        }
+    }
+    P->nf = w;
+    int m = order_ccw(cut, ncut, h->n);
+    if (m >= 3) {
+        oface *nf = poly_new_face(P, pidx);
+        for (int k = 0; k < m; ++k) face_push(nf, cut[k].p);
+    }
+    free(cut);
+}
+
+/* --- restriction of one facet polygon to its disk: signed fan around q --- */
+typedef struct {
+    double area;  /* planar area of the restricted facet              */
+    double omega; /* solid angle it subtends at p_i (sign of orientation only) */
+} fanacc;
+
+/* circular sector of the disk between in-plane directions u and v */
+static void fan_sector(const double *u, const double *v, const double *n, double rho2, double h, double r, fanacc *acc)
+{
+    double c[3];
+    cross3(u, v, c);
+    double phi = atan2(dot3(n, c), dot3(u, v));
+    acc->area += 0.5 * rho2 * phi;
+    acc->omega += phi * (1.0 - h / r);
+}
+
+/* triangle (q, q+A, q+B) fully inside the disk */
+static void fan_triangle(const double *A, const double *B, const double *n, double h, fanacc *acc)
+{
+    double c[3];
+    cross3(A, B, c);
+    double s = dot3(n, c);
+    acc->area += 0.5 * s;
+    double la = sqrt(dot3(A, A) + h * h), lb = sqrt(dot3(B, B) + h * h);
+    /* Van Oosterom-Strackee solid angle of the triangle with apex at height h above q */
+    acc->omega += 2.0 * atan2(s, la * lb + h * (la + lb) + h * h + dot3(A, B));
+}
+
+/* one fan piece: triangle (q, q+u, q+v) intersected with the disk of radius rho */
+static void fan_piece(const double *u, const double *v, const double *n, double rho2, double h, double r, fanacc *acc)
+{
+    double w[3] = {v[0] - u[0], v[1] - u[1], v[2] - u[2]};
+    double a = dot3(w, w);
+    if (a == 0.0) return;
+    double b = dot3(u, w);
+    double c = dot3(u, u) - rho2;
+    double disc = b * b - a * c;
+    double lo = 1.0, hi = 0.0;
+    if (disc > 0.0) {
+        double sq = sqrt(disc);
+        double s1 = (-b - sq) / a, s2 = (-b + sq) / a;
+        lo = s1 > 0.0 ? s1 : 0.0;
+        hi = s2 < 1.0 ? s2 : 1.0;
+    }
+    if (!(lo < hi)) {
+        fan_sector(u, v, n, rho2, h, r, acc);
+        return;
+    }
+    double A[3], B[3];
+    for (int k = 0; k < 3; ++k) {
+        A[k] = u[k] + lo * w[k];
+        B[k] = u[k] + hi * w[k];
+    }
+    fan_sector(u, A, n, rho2, h, r, acc);
+    fan_triangle(A, B, n, h, acc);
+    fan_sector(B, v, n, rho2, h, r, acc);
+}
+
+static fanacc restrict_face(const oface *f, const oplane *pl, double r)
+{
+    fanacc acc = {0.0, 0.0};
+    double t = pl->t, h = fabs(t);
+    double rho2 = (r - t) * (r + t);
+    if (!(rho2 > 0.0)) return acc;
+    double q[3] = {t * pl->n[0], t * pl->n[1], t * pl->n[2]};
+    for (int e = 0; e < f->nv; ++e) {
+        const double *a = f->v + 3 * e;
+        const double *b = f->v + 3 * ((e + 1) % f->nv);
+        double u[3] = {a[0] - q[0], a[1] - q[1], a[2] - q[2]};
+        double v[3] = {b[0] - q[0], b[1] - q[1], b[2] - q[2]};
+        fan_piece(u, v, pl->n, rho2, h, r, &acc);
+    }
+    return acc;
+}
+
+static int cmp_plane_t(const void *a, const void *b)
+{
+    const oplane *u = (const oplane *)a, *v = (const oplane *)b;
+    if (u->t < v->t) return -1;
+    if (u->t > v->t) return 1;
+    return (u->id < v->id) ? -1 : (u->id > v->id);
+}
+
+/*
+ * Evaluate one cell. Outputs: V, K, the 6 wall areas, up to fcap neighbour
+ * facets (id, area) with area > 0, the facet count (may exceed fcap -> status
+ * OR_FACET_CAP), and the number of planes that cut the ball (ncand).
+ */
+static int oracle_cell(long i, long n, const double *x, const double *y, const double *z, const double *psi,
+                       const double *box, double *V, double *K, double *wall, long *fj, double *fA, int fcap,
+                       int *fcount, int *ncand)
+{
+    *V = 0.0;
+    *K = 0.0;
+    for (int k = 0; k < 6; ++k) wall[k] = 0.0;
+    *fcount = 0;
+    *ncand = 0;
+    if (!(psi[i] > 0.0)) return OR_EMPTY;
+    const double r = sqrt(psi[i]);
+    const double pi3[3] = {x[i], y[i], z[i]};
+
+    int pcap = 64, np = 0;
+    oplane *pl = (oplane *)malloc(sizeof(oplane) * (size_t)pcap);
+    for (long j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double d3[3] = {x[j] - pi3[0], y[j] - pi3[1], z[j] - pi3[2]};
+        double d2 = dot3(d3, d3);
+        if (d2 == 0.0) {
+            /* coincident sites: the one with the larger weight (then lower index) owns everything */
+            if (psi[j] > psi[i] || (psi[j] == psi[i] && j < i)) {
+                free(pl);
+                return OR_EMPTY;
+            }
+            continue;
+        }
+        double d = sqrt(d2);
+        double t = (d2 + psi[i] - psi[j]) / (2.0 * d);
+        if (t <= -r) {
+            free(pl);
+            return OR_EMPTY;
+        }
+        if (t < r) {
+            if (np == pcap) {
+                pcap *= 2;
+                pl = (oplane *)realloc(pl, sizeof(oplane) * (size_t)pcap);
+            }
+            oplane *p = &pl[np++];
+            p->n[0] = d3[0] / d;
+            p->n[1] = d3[1] / d;
+            p->n[2] = d3[2] / d;
+            p->t = t;
+            p->id = j;
+        }
+    }
+    *ncand = np;
+    /* box walls: -x,+x,-y,+y,-z,+z with t = distance of p_i to the wall */
+    for (int w = 0; w < 6; ++w) {
+        int ax = w / 2;
+        double t = (w % 2 == 0) ? pi3[ax] - box[ax] : box[3 + ax] - pi3[ax];
+        if (t < r) {
+            if (np + 1 > pcap) {
+                pcap *= 2;
+                pl = (oplane *)realloc(pl, sizeof(oplane) * (size_t)pcap);
+            }
+            oplane *p = &pl[np++];
+            p->n[0] = p->n[1] = p->n[2] = 0.0;
+            p->n[ax] = (w % 2 == 0) ? -1.0 : 1.0;
+            p->t = t;
+            p->id = -1 - w;
+        }
+    }
+    qsort(pl, (size_t)np, sizeof(oplane), cmp_plane_t);
+    int inside = 1;
+    for (int k = 0; k < np; ++k)
+        if (pl[k].t < 0.0) inside = 0;
+
+    /* auxiliary cube p_i +- 2r (never a facet: it lies outside the ball) */
+    const int nreal = np;
+    pl = (oplane *)realloc(pl, sizeof(oplane) * (size_t)(np + 6));
+    opoly P = {0, 0, NULL};
+    const double L = 2.0 * r;
+    for (int w = 0; w < 6; ++w) {
+        int ax = w / 2;
+        double sgn = (w % 2 == 0) ? -1.0 : 1.0;
+        oplane *p = &pl[np + w];
+        p->n[0] = p->n[1] = p->n[2] = 0.0;
+        p->n[ax] = sgn;
+        p->t = L;
+        p->id = -7 - w;
+        angpt c4[4];
+        int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3, m = 0;
+        for (int s1 = -1; s1 <= 1; s1 += 2)
+            for (int s2 = -1; s2 <= 1; s2 += 2) {
+                c4[m].p[ax] = sgn * L;
+                c4[m].p[a1] = s1 * L;
+                c4[m].p[a2] = s2 * L;
+                m++;
+            }
+        m = order_ccw(c4, 4, p->n);
+        oface *f = poly_new_face(&P, np + w);
+        for (int k = 0; k < m; ++k) face_push(f, c4[k].p);
+    }
+    for (int k = 0; k < nreal; ++k) {
+        poly_clip(&P, pl, k);
+        if (P.nf == 0) break;
+    }
+
+    double sumTA = 0.0, sumOm = 0.0;
+    int nf = 0;
+    for (int k = 0; k < P.nf; ++k) {
+        const oface *f = &P.f[k];
+        const oplane *p = &pl[f->plane];
+        if (p->id <= -7) continue;
+        fanacc a = restrict_face(f, p, r);
+        sumTA += p->t * a.area;
+        sumOm += (p->t >= 0.0 ? 1.0 : -1.0) * a.omega;
+        if (p->id < 0) {
+            wall[-1 - p->id] = a.area;
+        } else if (a.area > 0.0) {
+            if (nf < fcap) {
+                fj[nf] = p->id;
+                fA[nf] = a.area;
+            }
+            nf++;
+        }
+    }
+    poly_free(&P);
+    free(pl);
+    if (P.nf == 0 && !inside) {
+        /* the half-spaces alone are empty inside the cube: no volume, no surface */
+    }
+    *K = r * r * (4.0 * OR_PI * inside - sumOm);
+    *V = (sumTA + r * (*K)) / 3.0;
+    *fcount = nf;
+    return nf > fcap ? OR_FACET_CAP : OR_OK;
+}
+
+/*
+ * Evaluate m cells (indices idx[0..m), or all n cells when idx == NULL).
+ * Per evaluated cell c: V[c], K[c], wall[6c..6c+6), facets fj/fA[c*fcap ..],
+ * fcount[c], ncand[c], status[c]. OpenMP over cells.
+ */
+int oracle_cells(long n, const double *x, const double *y, const double *z, const double *psi,
+                 const double *box, const long *idx, long m, double *V, double *K, double *wall, long *fj,
+                 double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads)
+{
+    long cnt = idx ? m : n;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long c = 0; c < cnt; ++c) {
+        long i = idx ? idx[c] : c;
+        status[c] = oracle_cell(i, n, x, y, z, psi, box, &V[c], &K[c], &wall[6 * c], &fj[(size_t)c * fcap],
+                                &fA[(size_t)c * fcap], fcap, &fcount[c], &ncand[c]);
+    }
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

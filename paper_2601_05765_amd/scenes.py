@@ -1,0 +1,236 @@
+"""Seeded synthetic particle sets shaped like the paper's scenes.
+
+This module only draws inputs: site positions, prescribed volumes, initial
+weights and velocities. It holds none of the method's arithmetic, so both the
+FP64 oracle (test infrastructure) and the HIP path can be fed from it.
+
+Canonical form of every scene:
+  * positions are drawn in float64 and rounded to float32 (the float32 values
+    ARE the input; the oracle promotes them back to float64 exactly);
+  * prescribed volumes ``nu`` and weights ``psi`` are float64;
+  * the domain is the unit box [0,1]^3.
+
+Scene recipes (sizes follow the workloads the solver is measured on):
+  slab_uniform   N sites uniform in [0,1]^2 x [0,0.4], nu = 0.3/N       (1,000 sites)
+  dam_break      jittered cubic lattice filling the lower 40% of the box,
+                 nu summing to 0.35                                       (100,000 sites)
+  splash         lattice slab (60%) + 200 log-normal spheres (40%),
+                 log-normal nu summing to 0.3, random velocities          (2,000,000 sites)
+  batch          256 instances with N log-uniform in [500, 50,000]
+  The default start weight gives every ball the radius 1.2 (3 nu / 4 pi)^(1/3).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BOX_LO = (0.0, 0.0, 0.0)
+BOX_HI = (1.0, 1.0, 1.0)
+
+
+@dataclass
+class Scene:
+    name: str
+    x: np.ndarray          # float32 [N]
+    y: np.ndarray          # float32 [N]
+    z: np.ndarray          # float32 [N]
+    nu: np.ndarray         # float64 [N]  prescribed volumes
+    psi0: np.ndarray       # float64 [N]  start weights (psi = r^2)
+    vel: np.ndarray | None = None   # float64 [N,3] (splash only)
+    box: tuple = (BOX_LO, BOX_HI)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def xyz64(self) -> np.ndarray:
+        return np.stack([self.x, self.y, self.z], axis=1).astype(np.float64)
+
+
+def default_psi0(nu: np.ndarray, radius_factor: float = 1.2) -> np.ndarray:
+    """Start weights: ball radius radius_factor * (3 nu / 4 pi)^(1/3), psi = r^2."""
+    r = radius_factor * np.cbrt(3.0 * np.asarray(nu, np.float64) / (4.0 * math.pi))
+    return r * r
+
+
+def _f32(a: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _jittered_lattice(rng, h, nx, ny, nz, origin=(0.0, 0.0, 0.0), jitter=0.3):
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    p = np.stack([(i.ravel() + 0.5) * h + origin[0],
+                  (j.ravel() + 0.5) * h + origin[1],
+                  (k.ravel() + 0.5) * h + origin[2]], axis=1)
+    p += rng.uniform(-jitter * h, jitter * h, size=p.shape)
+    return p
+
+
+def _keep_lowest_z(p, n):
+    order = np.lexsort((np.arange(p.shape[0]), p[:, 2]))  # z, ties by index
+    return p[np.sort(order[:n])]
+
+
+def _inside_box(p, eps=1e-6):
+    return np.clip(p, eps, 1.0 - eps)
+
+
+def slab_uniform(n: int = 1000, seed: int = 0, zmax: float = 0.4, total: float = 0.3) -> Scene:
+    """N sites uniform in [0,1]^2 x [0,zmax], equal volumes summing to ``total``."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0.0, 1.0, size=(n, 3))
+    p[:, 2] *= zmax
+    p = _inside_box(p)
+    nu = np.full(n, total / n)
+    return Scene("slab_uniform", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, default_psi0(nu),
+                 meta={"seed": seed, "n": n})
+
+
+def dam_break(n: int = 100_000, seed: int = 0, fill: float = 0.4, total: float = 0.35,
+              jitter: float = 0.3) -> Scene:
+    """Jittered cubic lattice (jitter +-0.3 spacing) filling the lower ``fill`` of the box."""
+    rng = np.random.default_rng(seed)
+    h = (fill / n) ** (1.0 / 3.0)
+    nxy = int(math.floor(1.0 / h))
+    nz = int(math.ceil(n / (nxy * nxy))) + 1
+    p = _jittered_lattice(rng, h, nxy, nxy, nz, jitter=jitter)
+    p = _keep_lowest_z(p, n)
+    p = _inside_box(p)
+    nu = np.full(n, total / n)
+    return Scene("dam_break", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, default_psi0(nu),
+                 meta={"seed": seed, "n": n, "h": h, "lattice": (nxy, nxy, nz)})
+
+
+def _sphere_points(rng, centre, R, count, jitter=0.3):
+    """``count`` points of a jittered lattice closest to ``centre`` (spacing fit to the ball)."""
+    vol = 4.0 / 3.0 * math.pi * R ** 3
+    s = (vol / count) ** (1.0 / 3.0)
+    for _ in range(200):
+        m = int(math.ceil(R / s)) + 2
+        ax = (np.arange(-m, m + 1) + 0.0) * s
+        gx, gy, gz = np.meshgrid(ax, ax, ax, indexing="ij")
+        q = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+        q += rng.uniform(-jitter * s, jitter * s, size=q.shape)
+        d2 = (q * q).sum(1)
+        inside = d2 <= R * R
+        if inside.sum() >= count:
+            order = np.argsort(d2, kind="stable")[:count]
+            return q[order] + np.asarray(centre)
+        s *= 0.99
+    raise RuntimeError("sphere lattice could not be filled")
+
+
+def splash(n: int = 2_000_000, seed: int = 0, n_spheres: int = 200, slab_frac: float = 0.6,
+           total: float = 0.3) -> Scene:
+    """Crown-splash-like scene: lattice slab + log-normal spheres, log-normal volumes."""
+    rng = np.random.default_rng(seed)
+    n_slab = int(round(slab_frac * n))
+    n_sph = n - n_slab
+    h = (0.2 / n_slab) ** (1.0 / 3.0)
+    nxy = int(math.floor(1.0 / h))
+    nz = int(math.ceil(n_slab / (nxy * nxy))) + 1
+    slab = _keep_lowest_z(_jittered_lattice(rng, h, nxy, nxy, nz), n_slab)
+    radii = np.clip(rng.lognormal(math.log(0.03), 0.5, size=n_spheres), 0.01, 0.12)
+    centres = []
+    for R in radii:
+        for _ in range(100000):
+            c = np.array([rng.uniform(R, 1 - R), rng.uniform(R, 1 - R), rng.uniform(0.2 + R, 1 - R)])
+            if all(np.linalg.norm(c - c2) > R + R2 for c2, R2 in centres):
+                centres.append((c, R))
+                break
+        else:
+            raise RuntimeError("could not place sphere")
+    vols = np.array([R ** 3 for _, R in centres])
+    quota = vols / vols.sum() * n_sph
+    counts = np.floor(quota).astype(np.int64)
+    rem = n_sph - counts.sum()
+    counts[np.argsort(-(quota - counts), kind="stable")[:rem]] += 1
+    parts = [slab] + [_sphere_points(rng, c, R, int(k)) for (c, R), k in zip(centres, counts)]
+    p = _inside_box(np.concatenate(parts, axis=0))
+    nu = rng.lognormal(0.0, 0.2, size=n)
+    nu *= total / nu.sum()
+    vel = rng.normal(0.0, 0.5, size=(n, 3))
+    return Scene("splash", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, default_psi0(nu), vel=vel,
+                 meta={"seed": seed, "n": n, "n_slab": n_slab, "spheres": len(centres)})
+
+
+def sphere_cluster(n: int, seed: int, total: float = 0.35, fill: float = 0.40) -> Scene:
+    """K in 2..6 overlapping spheres of a common radius; the lattice fills their union."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(2, 7))
+    centres = rng.uniform(0.25, 0.75, size=(k, 3))
+    s = (fill / n) ** (1.0 / 3.0)
+    m = int(math.floor(1.0 / s))
+    lat = _jittered_lattice(rng, s, m, m, m)
+    d2 = ((lat[:, None, :] - centres[None, :, :]) ** 2).sum(-1).min(1)
+    lo, hi = 0.0, 1.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if (d2 <= mid * mid).sum() >= n:
+            hi = mid
+        else:
+            lo = mid
+    order = np.argsort(d2, kind="stable")[:n]
+    p = _inside_box(lat[np.sort(order)])
+    nu = np.full(n, total / n)
+    return Scene("sphere_cluster", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, default_psi0(nu),
+                 meta={"seed": seed, "n": n, "spheres": k, "R": hi})
+
+
+def batch_instances(count: int = 256, base_seed: int = 1000, n_lo: int = 500, n_hi: int = 50_000):
+    """Independent instances of uneven size: slab layout for even seeds, sphere cluster for odd."""
+    out = []
+    for b in range(count):
+        seed = base_seed + b
+        rng = np.random.default_rng(seed)
+        nb = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        if seed % 2 == 0:
+            sc = dam_break(nb, seed=seed)
+        else:
+            sc = sphere_cluster(nb, seed=seed)
+        sc.meta["instance"] = b
+        out.append(sc)
+    return out
+
+
+def advect(scene: Scene, dt: float = 2e-3) -> Scene:
+    """x <- x + dt v with mirror reflection at the walls (velocity component negated)."""
+    assert scene.vel is not None
+    p = scene.xyz64() + dt * scene.vel
+    v = scene.vel.copy()
+    lo = p < 0.0
+    p[lo] = -p[lo]
+    v[lo] = -v[lo]
+    hi = p > 1.0
+    p[hi] = 2.0 - p[hi]
+    v[hi] = -v[hi]
+    p = _inside_box(p)
+    return Scene(scene.name, _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), scene.nu.copy(),
+                 scene.psi0.copy(), vel=v, box=scene.box, meta=dict(scene.meta))
+
+
+def with_velocity(scene: Scene, seed: int, sigma: float = 0.5) -> Scene:
+    rng = np.random.default_rng(seed)
+    scene.vel = rng.normal(0.0, sigma, size=(scene.n, 3))
+    return scene
+
+
+def random_small(n: int, seed: int, lo: float = 0.15, hi: float = 0.85, r_lo: float = 0.08,
+                 r_hi: float = 0.22) -> Scene:
+    """Tiny random configurations for brute-force pins (overlapping balls, walls nearby)."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(lo, hi, size=(n, 3))
+    r = rng.uniform(r_lo, r_hi, size=n)
+    nu = np.full(n, 1e-3)
+    return Scene("random_small", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, r * r,
+                 meta={"seed": seed, "n": n})
+
+
+CONFIGS = {
+    "c1_slab_1k": lambda seed=0: slab_uniform(1000, seed),
+    "c2_dam_100k": lambda seed=0: dam_break(100_000, seed),
+    "c3_splash_2m": lambda seed=0: splash(2_000_000, seed),
+}
