@@ -1,0 +1,157 @@
+/*
+ * lagot.h -- C-ABI of the MI355X (gfx950) solver for semi-discrete partial
+ * optimal transport with analytic restricted Laguerre cells
+ * ("More Power to the Particles", arXiv 2601.05765).
+ *
+ * Problem (paper, section 2.2 "Volume-Constrained Lagrangian Mesh" and
+ * "Free Surface", eq. (1); Algorithm 1): given sites p_i in a box, prescribed
+ * volumes nu_i and weights psi_i, the generalized Laguerre cell of site i is
+ *
+ *   C_i = box ∩ B(p_i, sqrt(psi_i)) ∩ { x : |x-p_i|^2 - psi_i <= |x-p_j|^2 - psi_j  for all j != i }
+ *
+ * (the air object has weight 0). The solver finds the unique weights with
+ * |C_i| = nu_i for all i by damped Newton on the Kantorovich functional, whose
+ * gradient is nu_i - |C_i| and whose Hessian is eq. (2) (section 3.1).
+ *
+ * Conventions for every entry point below
+ *   - Array arguments are DEVICE pointers (for example torch tensor storage on
+ *     the same GPU); all work is enqueued on the stream given to lagot_create.
+ *   - Arrays are in the caller's site order; the library never keeps a
+ *     caller pointer after a call returns. The caller owns every array; the
+ *     library owns only its context workspace (grown on demand, freed by
+ *     lagot_destroy).
+ *   - Positions are float32 (x, y, z separate arrays), weights and volumes are
+ *     float64. Geometry runs in float32; totals, residuals, CG inner products
+ *     and the step-acceptance test run in float64 on the GPU.
+ *   - Return value: LAGOT_OK (0) or one of the negative codes below. On a
+ *     Newton error, psi_inout holds the last accepted iterate.
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef LAGOT_H
+#define LAGOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAGOT_OK 0
+#define LAGOT_EINVAL (-1)       /* null pointer, n <= 0, site not strictly inside the box, nu <= 0,
+                                   sum(nu) >= box volume, NaN input, bad option */
+#define LAGOT_EEMPTY (-2)       /* some start cell is empty, so the KMT floor eps0 is 0 */
+#define LAGOT_ENOCONV (-3)      /* max_newton iterations reached before the tolerance */
+#define LAGOT_ELINESEARCH (-4)  /* max_halvings step halvings without an acceptable step */
+#define LAGOT_ECAPACITY (-5)    /* output capacity too small (nnz_cap) or a cell exceeded even the
+                                   large-capacity path */
+#define LAGOT_ESINGULAR (-6)    /* conjugate-gradient breakdown (non-positive curvature) */
+#define LAGOT_EHIP (-7)         /* HIP runtime error */
+
+typedef struct lagot_ctx lagot_ctx;
+
+typedef struct {
+    double lo[3];
+    double hi[3];
+} lagot_box;
+
+typedef struct {
+    double tol;          /* stop when max_i |V_i - nu_i| / nu_i <= tol            (default 1e-5)  */
+    int max_newton;      /* Newton iteration limit (section 6: 100)                (default 100)   */
+    int max_halvings;    /* step halvings per iteration                           (default 30)    */
+    double cg_rtol;      /* relative residual of the Jacobi-PCG direction solve   (default 1e-6)  */
+    int cg_max_iter;     /* PCG iteration limit                                    (default 1000)  */
+    int threads_per_cell;/* lanes per cell in the cell kernel: 0 = autotuned, else 16, 32 or 64     */
+    int verbose;         /* 1: print one line per Newton iteration to stderr                        */
+    int reserved[5];
+} lagot_opts;
+
+typedef struct {
+    int status;          /* LAGOT_* code of the call                                       */
+    int newton_iters;    /* accepted Newton iterations                                     */
+    int evals;           /* full cell evaluations (start + one per step trial)             */
+    int halvings;        /* total step halvings                                            */
+    int cg_iters;        /* total PCG iterations                                           */
+    int fallback_cells;  /* cells redone on the large-capacity float64 path (all evals)    */
+    int failed_cells;    /* cells that exceeded even the large-capacity path (last eval)   */
+    int cell_launches;   /* launches of the float32 cell kernel (one per evaluation)      */
+    double max_rel_err;  /* max_i |V_i - nu_i| / nu_i at the returned weights              */
+    double grad_norm;    /* || nu - V ||_2 at the returned weights                         */
+    double ms_total;     /* wall time of the call (host clock, stream synchronised)       */
+    double ms_eval;      /* of which cell evaluations incl. reductions (host clock)        */
+    double ms_linear;    /* of which Hessian assembly and PCG (host clock)                 */
+    double ms_cell_kernel; /* summed duration of the float32 cell-kernel launches (HIP events
+                              on the context stream)                                        */
+    double reserved_d[2];
+} lagot_stats;
+
+/* Fill *opts with the defaults listed above. */
+void lagot_default_opts(lagot_opts *opts);
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a hipStream_t;
+ * NULL = the legacy default stream). Returns LAGOT_EINVAL if out is NULL,
+ * LAGOT_EHIP if the device cannot be used. */
+int lagot_create(lagot_ctx **out, int device, void *stream);
+
+/* Release the context and its workspace. NULL is ignored. */
+void lagot_destroy(lagot_ctx *ctx);
+
+/*
+ * One evaluation of all generalized Laguerre cells (paper section 3,
+ * Algorithm 2; section 4 "Cell Update", "Restriction").
+ *   in : n sites x,y,z [n] float32, psi [n] float64 (psi <= 0 gives an empty cell)
+ *   out: vol [n] float64        |C_i|
+ *        sph_area [n] float64   |∂B_i ∩ C_i|, the free-surface area K_i (may be NULL)
+ *        wall_area [6n] float32 facet areas on the walls -x,+x,-y,+y,-z,+z, site-major
+ *                               (may be NULL)
+ *        row_ptr [n+1] int64, col [nnz_cap] int32, facet_area [nnz_cap] float32:
+ *                               CSR of the restricted Laguerre facets |B_ij| > 0 as seen
+ *                               from cell i, rows in site order, columns ascending
+ *                               (all three NULL to skip; then nnz_out may be NULL)
+ *        nnz_out (HOST pointer)  number of facets written; the call synchronises the
+ *                               stream when it is requested.
+ * Errors: LAGOT_EINVAL (bad pointer/size, site outside the box), LAGOT_ECAPACITY
+ * (more facets than nnz_cap; *nnz_out still reports the count needed).
+ */
+int lagot_cells(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                lagot_box box, double *vol, double *sph_area, float *wall_area, int64_t *row_ptr, int32_t *col,
+                float *facet_area, int64_t nnz_cap, int64_t *nnz_out);
+
+/*
+ * One damped Newton iteration of Algorithm 1: evaluate the cells at psi, stop
+ * if the tolerance already holds, else solve (-Hess K) u = nu - V by
+ * Jacobi-PCG (eq. (2); walls do not enter) and halve the step from alpha = 1
+ * until min V >= eps0 and ||nu - V||_2 decreases by the factor (1 - alpha/2)
+ * (Kitagawa-Merigot-Thibert control; eps0 = 1/2 min(min nu, min V(psi)) here,
+ * since a single step has no earlier start). psi_inout is updated in place.
+ *   in : x,y,z [n] float32, nu [n] float64, psi_inout [n] float64, opts (NULL =
+ *        defaults); out: psi_inout, *stats (HOST pointer, may be NULL).
+ * Synchronises the stream. Errors: EINVAL, EEMPTY, ELINESEARCH, ESINGULAR, EHIP.
+ */
+int lagot_newton_step(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
+                      lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats);
+
+/*
+ * Full solve of Algorithm 1 from the start weights in psi_inout to
+ * max_i |V_i - nu_i| / nu_i <= opts->tol, with eps0 = 1/2 min(min nu, min V(psi_start)).
+ * Same arguments as lagot_newton_step. Synchronises the stream.
+ * Errors: EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ESINGULAR, ECAPACITY, EHIP.
+ */
+int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
+                lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats);
+
+/* Number of cells that the last lagot_cells call on this context redid on the
+ * large-capacity float64 path (diagnostic; -1 if ctx is NULL). */
+int lagot_last_fallback_cells(const lagot_ctx *ctx);
+
+/* Duration in ms of the float32 cell-kernel launch of the last lagot_cells call
+ * (HIP events on the context stream; diagnostic; -1 if ctx is NULL). */
+double lagot_last_cell_kernel_ms(const lagot_ctx *ctx);
+
+/* Human-readable text for a LAGOT_* code (static storage). */
+const char *lagot_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAGOT_H */

@@ -44,7 +44,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.oracle_cells.argtypes = [ctypes.c_long, P, P, P, P, P, P, ctypes.c_long, P, P, P, P, P, ctypes.c_int,
-                                     P, P, P, ctypes.c_int]
+                                     P, P, P, ctypes.c_int, P]
         lib.oracle_cells.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -70,13 +70,15 @@ class Cells:
     ncand: np.ndarray        # [m] bisector planes that cut the ball
     status: np.ndarray       # [m] 0 ok, 1 empty, 2 facet capacity exceeded
     idx: np.ndarray          # [m] evaluated site indices
+    work: np.ndarray | None = None  # [m,6] work units (see lagot_oracle.c) when requested
 
     def facets(self, c: int) -> dict:
         k = int(self.fcount[c])
         return {int(j): float(a) for j, a in zip(self.fj[c, :k], self.fA[c, :k])}
 
 
-def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, threads: int = 0) -> Cells:
+def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, threads: int = 0,
+          work: bool = False) -> Cells:
     """Evaluate the restricted Laguerre cells of the sites ``idx`` (default: all).
 
     Positions are promoted to float64 exactly; ``psi`` must be float64.
@@ -104,11 +106,13 @@ def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, th
     fc = np.zeros(m, np.int32)
     nc = np.zeros(m, np.int32)
     st = np.zeros(m, np.int32)
+    wk = np.zeros((m, 6), np.int64) if work else None
     lib.oracle_cells(n, _ptr(x), _ptr(y), _ptr(z), _ptr(psi), _ptr(b), idx_p, m, _ptr(V), _ptr(K), _ptr(W),
-                     _ptr(fj), _ptr(fA), fcap, _ptr(fc), _ptr(nc), _ptr(st), int(threads))
+                     _ptr(fj), _ptr(fA), fcap, _ptr(fc), _ptr(nc), _ptr(st), int(threads),
+                     _ptr(wk) if work else None)
     if (st == 2).any():
         raise RuntimeError("oracle facet capacity exceeded; raise fcap")
-    return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr)
+    return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr, wk)
 
 
 def hessian(xyz: np.ndarray, psi: np.ndarray, c: Cells):

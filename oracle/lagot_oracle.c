@@ -66,6 +66,13 @@ typedef struct {
     oface *f;
 } opoly;
 
+/* Work units of one cell evaluation (for cost models; not part of the result):
+ * [0] bisector planes cutting the ball, [1] vertex-versus-plane tests,
+ * [2] vertices created by clipping, [3] restricted facets (neighbour + wall faces),
+ * [4] facet polygon edges integrated, [5] of which cross the facet's circle. */
+enum { W_CAND = 0, W_TESTS, W_NEWV, W_FACES, W_EDGES, W_CROSS, W_N };
+static __thread long *g_work = NULL;
+
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 static void cross3(const double *a, const double *b, double *c)
@@ -182,6 +189,11 @@ static void edge_cut(const double *a, const double *b, const oplane *pl, double 
 static void poly_clip(opoly *P, const oplane *pl, int pidx)
 {
     const oplane *h = &pl[pidx];
+    if (g_work) {
+        long nv = 0;
+        for (int k = 0; k < P->nf; ++k) nv += P->f[k].nv;
+        g_work[W_TESTS] += nv / 3;
+    }
     int cutcap = 64, ncut = 0;
     angpt *cut = (angpt *)malloc(sizeof(angpt) * (size_t)cutcap);
     int w = 0;
@@ -222,6 +234,7 @@ static void poly_clip(opoly *P, const oplane *pl, int pidx)
     }
     P->nf = w;
     int m = order_ccw(cut, ncut, h->n);
+    if (g_work && m >= 3) g_work[W_NEWV] += m;
     if (m >= 3) {
         oface *nf = poly_new_face(P, pidx);
         for (int k = 0; k < m; ++k) face_push(nf, cut[k].p);
@@ -273,10 +286,12 @@ static void fan_piece(const double *u, const double *v, const double *n, double 
         lo = s1 > 0.0 ? s1 : 0.0;
         hi = s2 < 1.0 ? s2 : 1.0;
     }
+    if (g_work) g_work[W_EDGES]++;
     if (!(lo < hi)) {
         fan_sector(u, v, n, rho2, h, r, acc);
         return;
     }
+    if (g_work) g_work[W_CROSS]++;
     double A[3], B[3];
     for (int k = 0; k < 3; ++k) {
         A[k] = u[k] + lo * w[k];
@@ -364,6 +379,7 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
         }
     }
     *ncand = np;
+    if (g_work) g_work[W_CAND] = np;
     /* box walls: -x,+x,-y,+y,-z,+z with t = distance of p_i to the wall */
     for (int w = 0; w < 6; ++w) {
         int ax = w / 2;
@@ -422,6 +438,7 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
         const oface *f = &P.f[k];
         const oplane *p = &pl[f->plane];
         if (p->id <= -7) continue;
+        if (g_work) g_work[W_FACES]++;
         fanacc a = restrict_face(f, p, r);
         sumTA += p->t * a.area;
         sumOm += (p->t >= 0.0 ? 1.0 : -1.0) * a.omega;
@@ -449,11 +466,12 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
 /*
  * Evaluate m cells (indices idx[0..m), or all n cells when idx == NULL).
  * Per evaluated cell c: V[c], K[c], wall[6c..6c+6), facets fj/fA[c*fcap ..],
- * fcount[c], ncand[c], status[c]. OpenMP over cells.
+ * fcount[c], ncand[c], status[c], and when work != NULL the six work units of
+ * each cell at work[6c..6c+6). OpenMP over cells.
  */
 int oracle_cells(long n, const double *x, const double *y, const double *z, const double *psi,
                  const double *box, const long *idx, long m, double *V, double *K, double *wall, long *fj,
-                 double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads)
+                 double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads, long *work)
 {
     long cnt = idx ? m : n;
 #ifdef _OPENMP
@@ -464,6 +482,9 @@ int oracle_cells(long n, const double *x, const double *y, const double *z, cons
 #pragma omp parallel for schedule(dynamic, 16)
     for (long c = 0; c < cnt; ++c) {
         long i = idx ? idx[c] : c;
+        g_work = work ? &work[W_N * c] : NULL;
+        if (g_work)
+            for (int k = 0; k < W_N; ++k) g_work[k] = 0;
         status[c] = oracle_cell(i, n, x, y, z, psi, box, &V[c], &K[c], &wall[6 * c], &fj[(size_t)c * fcap],
                                 &fA[(size_t)c * fcap], fcap, &fcount[c], &ncand[c]);
     }

@@ -1,0 +1,210 @@
+"""Python binding of liblagot (argument marshalling only).
+
+Every computation runs in the HIP kernels behind the C-ABI declared in
+include/lagot.h; PyTorch only provides device memory and the stream. The
+binding raises if the library has not been built: there is no CPU fallback.
+
+  ctx = Context()                                   # lagot_create on the current device/stream
+  out = ctx.cells(x, y, z, psi)                     # lagot_cells
+  st  = ctx.solve(x, y, z, nu, psi)                 # lagot_solve, psi updated in place
+  st  = ctx.newton_step(x, y, z, nu, psi)           # lagot_newton_step
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblagot.so")
+_lib = None
+
+OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
+
+EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
+           "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms", "lagot_strerror"]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_newton", ctypes.c_int), ("max_halvings", ctypes.c_int),
+                ("cg_rtol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("threads_per_cell", ctypes.c_int),
+                ("verbose", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int), ("evals", ctypes.c_int),
+                ("halvings", ctypes.c_int), ("cg_iters", ctypes.c_int), ("fallback_cells", ctypes.c_int),
+                ("failed_cells", ctypes.c_int), ("cell_launches", ctypes.c_int), ("max_rel_err", ctypes.c_double),
+                ("grad_norm", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_eval", ctypes.c_double),
+                ("ms_linear", ctypes.c_double), ("ms_cell_kernel", ctypes.c_double), ("reserved_d", ctypes.c_double * 2)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+class LagotError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+def load():
+    """Load liblagot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2601_05765_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        lib.lagot_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        lib.lagot_default_opts.restype = None
+        lib.lagot_create.argtypes = [ctypes.POINTER(P), I, P]
+        lib.lagot_create.restype = I
+        lib.lagot_destroy.argtypes = [P]
+        lib.lagot_destroy.restype = None
+        lib.lagot_cells.argtypes = [P, I64, P, P, P, P, Box, P, P, P, P, P, P, I64, ctypes.POINTER(I64)]
+        lib.lagot_cells.restype = I
+        for name in ("lagot_newton_step", "lagot_solve"):
+            f = getattr(lib, name)
+            f.argtypes = [P, I64, P, P, P, P, Box, P, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+            f.restype = I
+        lib.lagot_last_fallback_cells.argtypes = [P]
+        lib.lagot_last_fallback_cells.restype = I
+        lib.lagot_last_cell_kernel_ms.argtypes = [P]
+        lib.lagot_last_cell_kernel_ms.restype = ctypes.c_double
+        lib.lagot_strerror.argtypes = [I]
+        lib.lagot_strerror.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().lagot_strerror(int(code)).decode()
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().lagot_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_box(box=((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))) -> Box:
+    b = Box()
+    for a in range(3):
+        b.lo[a] = float(box[0][a])
+        b.hi[a] = float(box[1][a])
+    return b
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A lagot context bound to one device and one stream (default: torch's current)."""
+
+    def __init__(self, device: int | None = None, stream=None):
+        import torch
+        lib = load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib.lagot_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise LagotError(rc, "lagot_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lagot_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cells(self, x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), csr: bool = True, walls: bool = True,
+              sph: bool = True, nnz_per_cell: int = 24):
+        """lagot_cells: volumes, spherical areas, wall areas and the facet CSR (caller order)."""
+        import torch
+        n = x.shape[0]
+        dev = x.device
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(psi, torch.float64, "psi")]
+        vol = torch.empty(n, dtype=torch.float64, device=dev)
+        K = torch.empty(n, dtype=torch.float64, device=dev) if sph else None
+        W = torch.empty(n * 6, dtype=torch.float32, device=dev) if walls else None
+        out = {"vol": vol}
+        lib = load()
+        cap = nnz_per_cell * n
+        while True:
+            nnz = ctypes.c_int64(0)
+            if csr:
+                rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+                col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+                fa = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+                ptrs = [ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                        ctypes.c_void_p(fa.data_ptr())]
+            else:
+                ptrs = [None, None, None]
+            rc = lib.lagot_cells(self._h, n, *args, make_box(box), ctypes.c_void_p(vol.data_ptr()),
+                                 ctypes.c_void_p(K.data_ptr()) if K is not None else None,
+                                 ctypes.c_void_p(W.data_ptr()) if W is not None else None, *ptrs, cap,
+                                 ctypes.byref(nnz))
+            if rc == ECAPACITY and csr and nnz.value > cap:
+                cap = int(nnz.value)
+                continue
+            if rc != OK:
+                raise LagotError(rc, "lagot_cells")
+            break
+        if K is not None:
+            out["sph"] = K
+        if W is not None:
+            out["walls"] = W.view(n, 6)
+        if csr:
+            out["row_ptr"], out["col"], out["area"] = rp, col[: nnz.value], fa[: nnz.value]
+        out["nnz"] = int(nnz.value)
+        return out
+
+    def last_fallback_cells(self) -> int:
+        return int(load().lagot_last_fallback_cells(self._h))
+
+    def last_cell_kernel_ms(self) -> float:
+        return float(load().lagot_last_cell_kernel_ms(self._h))
+
+    def _newton(self, fn, x, y, z, nu, psi, box, opts, check):
+        import torch
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(nu, torch.float64, "nu")]
+        st = Stats()
+        o = opts if opts is not None else default_opts()
+        rc = fn(self._h, x.shape[0], *args, make_box(box), _dev(psi, torch.float64, "psi"), ctypes.byref(o),
+                ctypes.byref(st))
+        if check and rc != OK:
+            raise LagotError(rc, fn.__name__)
+        return st
+
+    def solve(self, x, y, z, nu, psi, box=((0, 0, 0), (1, 1, 1)), opts: Opts | None = None, check: bool = True):
+        """lagot_solve: damped Newton to opts.tol; psi (float64, device) is updated in place."""
+        return self._newton(load().lagot_solve, x, y, z, nu, psi, box, opts, check)
+
+    def newton_step(self, x, y, z, nu, psi, box=((0, 0, 0), (1, 1, 1)), opts: Opts | None = None,
+                    check: bool = True):
+        """lagot_newton_step: one damped Newton iteration; psi updated in place."""
+        return self._newton(load().lagot_newton_step, x, y, z, nu, psi, box, opts, check)

@@ -1,0 +1,558 @@
+// api.cpp -- C-ABI of liblagot (declared in include/lagot.h): context and
+// workspace management, input validation, the spatial sort, one evaluation of
+// all cells, and the host side of the damped Newton loop of Algorithm 1 (KMT
+// step control) around the Jacobi-PCG direction solve.
+//
+// Everything between the caller's arrays runs in grid order on the device; the
+// host only reads a few float64 scalars per evaluation / PCG chunk.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "lagot.h"
+#include "lagot_internal.h"
+
+using namespace lagot;
+
+namespace {
+
+template <typename T> hipError_t dalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct lagot_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t cap_n = 0;
+    int cap_cells = 0;
+    int tpc = 16;
+
+    // sites (caller order, then grid order)
+    float4 *pos_orig = nullptr, *pos_s = nullptr;
+    double *psi_s = nullptr, *nu_s = nullptr, *psi_trial = nullptr;
+    int32_t *keys = nullptr, *perm = nullptr;
+    int32_t *cell_count = nullptr, *cell_start = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
+    GridDesc grid{};
+    // evaluation outputs (grid order)
+    double *V = nullptr, *K = nullptr;
+    float *wall = nullptr;
+    int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr;
+    float *farea = nullptr;
+    uint32_t *flags = nullptr;
+    int32_t *counters = nullptr;  // [0] fallback count [1] fail count [2] bad inputs [3] hessian overflow
+    // Hessian and PCG
+    int32_t *hcol = nullptr, *hcnt = nullptr, *xcnt = nullptr;
+    float *hval = nullptr;
+    double *diag = nullptr, *g = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *partial = nullptr, *scal = nullptr, *red4 = nullptr, *rmax = nullptr, *rmax_partial = nullptr;
+    int cap_blocks = 0;
+    // pinned host mirrors
+    double *h_scal = nullptr;
+    int32_t *h_cnt = nullptr;
+    // CSR staging for lagot_cells
+    int32_t *csr_cnt = nullptr, *csr_start = nullptr;
+    int64_t *csr_start64 = nullptr;
+    int32_t *csr_tmp = nullptr;
+    // statistics of the current call
+    int fb_total = 0;
+    int last_fb = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the float32 cell kernel
+    bool ev_pending = false;
+    double ms_cell = 0.0;
+    int cell_launches = 0;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                       \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) {                             \
+            fprintf(stderr, "lagot: %s failed: %s\n", #expr, hipGetErrorString(e_)); \
+            return LAGOT_EHIP;                              \
+        }                                                   \
+    } while (0)
+
+void free_all(lagot_ctx *c) {
+    void *bufs[] = {c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->cell_count,
+                    c->cell_start, c->cursor, c->scan_tmp, c->V, c->K, c->wall, c->fcol, c->fcnt, c->fb_list,
+                    c->farea, c->flags, c->counters, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag, c->g, c->x,
+                    c->r, c->z, c->p, c->q, c->partial, c->scal, c->red4, c->rmax, c->rmax_partial, c->csr_cnt,
+                    c->csr_start, c->csr_start64, c->csr_tmp};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+}
+
+// Add the duration of the last recorded cell-kernel launch (call after a stream sync).
+void collect_cell_time(lagot_ctx *c) {
+    if (!c->ev_pending) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
+        c->ms_cell += ms;
+        c->cell_launches++;
+    }
+    c->ev_pending = false;
+}
+
+int nblk256(int64_t n) { return (int)((n + 255) / 256); }
+
+int ensure_sites(lagot_ctx *c, int64_t n) {
+    if (n <= c->cap_n) return LAGOT_OK;
+    void *bufs[] = {c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->V, c->K, c->wall,
+                    c->fcol, c->fcnt, c->fb_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
+                    c->g, c->x, c->r, c->z, c->p, c->q, c->partial, c->rmax_partial, c->csr_cnt, c->csr_start,
+                    c->csr_start64, c->csr_tmp};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    const size_t N = (size_t)n;
+    const int nb = nblk256(n);
+    HIP_TRY(dalloc(&c->pos_orig, N));
+    HIP_TRY(dalloc(&c->pos_s, N));
+    HIP_TRY(dalloc(&c->psi_s, N));
+    HIP_TRY(dalloc(&c->nu_s, N));
+    HIP_TRY(dalloc(&c->psi_trial, N));
+    HIP_TRY(dalloc(&c->keys, N));
+    HIP_TRY(dalloc(&c->perm, N));
+    HIP_TRY(dalloc(&c->V, N));
+    HIP_TRY(dalloc(&c->K, N));
+    HIP_TRY(dalloc(&c->wall, 6 * N));
+    HIP_TRY(dalloc(&c->fcol, FCAP * N));
+    HIP_TRY(dalloc(&c->farea, FCAP * N));
+    HIP_TRY(dalloc(&c->fcnt, N));
+    HIP_TRY(dalloc(&c->fb_list, N));
+    HIP_TRY(dalloc(&c->flags, N));
+    HIP_TRY(dalloc(&c->hcol, FCAP * N));
+    HIP_TRY(dalloc(&c->hval, FCAP * N));
+    HIP_TRY(dalloc(&c->hcnt, N));
+    HIP_TRY(dalloc(&c->xcnt, N));
+    HIP_TRY(dalloc(&c->diag, N));
+    HIP_TRY(dalloc(&c->g, N));
+    HIP_TRY(dalloc(&c->x, N));
+    HIP_TRY(dalloc(&c->r, N));
+    HIP_TRY(dalloc(&c->z, N));
+    HIP_TRY(dalloc(&c->p, N));
+    HIP_TRY(dalloc(&c->q, N));
+    HIP_TRY(dalloc(&c->partial, 4 * (size_t)nb));
+    HIP_TRY(dalloc(&c->rmax_partial, (size_t)nb));
+    HIP_TRY(dalloc(&c->csr_cnt, N + 1));
+    HIP_TRY(dalloc(&c->csr_start, N + 1));
+    HIP_TRY(dalloc(&c->csr_start64, N + 1));
+    HIP_TRY(dalloc(&c->csr_tmp, N / 1024 + 16));
+    c->cap_n = n;
+    c->cap_blocks = nb;
+    return LAGOT_OK;
+}
+
+int ensure_cells(lagot_ctx *c, int ncell) {
+    if (ncell <= c->cap_cells) return LAGOT_OK;
+    void *bufs[] = {c->cell_count, c->cell_start, c->cursor, c->scan_tmp};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    HIP_TRY(dalloc(&c->cell_count, (size_t)ncell + 1));
+    HIP_TRY(dalloc(&c->cell_start, (size_t)ncell + 1));
+    HIP_TRY(dalloc(&c->cursor, (size_t)ncell + 1));
+    HIP_TRY(dalloc(&c->scan_tmp, (size_t)ncell / 1024 + 16));
+    c->cap_cells = ncell;
+    return LAGOT_OK;
+}
+
+BoxF to_boxf(const lagot_box &b) {
+    BoxF f;
+    for (int a = 0; a < 3; ++a) {
+        f.lo[a] = (float)b.lo[a];
+        f.hi[a] = (float)b.hi[a];
+    }
+    return f;
+}
+
+bool box_ok(const lagot_box &b) {
+    for (int a = 0; a < 3; ++a)
+        if (!(b.hi[a] > b.lo[a]) || !std::isfinite(b.lo[a]) || !std::isfinite(b.hi[a])) return false;
+    return true;
+}
+
+int sync_read(lagot_ctx *c, const void *dev, void *host, size_t bytes) {
+    HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LAGOT_OK;
+}
+
+// Validate, gather, spatially sort. nu may be null (cells-only). On return the
+// grid-order arrays pos_s (with float32 psi), psi_s (and nu_s) are filled and
+// c->rmax holds max sqrt(psi).
+int prepare(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+            const double *nu, const lagot_box &box) {
+    if (n <= 0 || n > (int64_t)INT32_MAX / FCAP || !x || !y || !z || !psi || !box_ok(box)) return LAGOT_EINVAL;
+    int rc = ensure_sites(c, n);
+    if (rc) return rc;
+    const BoxF bf = to_boxf(box);
+    HIP_TRY(hipMemsetAsync(c->counters, 0, 8 * sizeof(int32_t), c->stream));
+    launch_validate(c->stream, n, x, y, z, psi, nu, bf, c->counters + 2);
+    const int nb = nblk256(n);
+    launch_gather_sites(c->stream, n, x, y, z, psi, c->pos_orig, c->rmax_partial, nb);
+    launch_reduce_max(c->stream, c->rmax_partial, nb, c->rmax);
+    HIP_TRY(hipMemcpyAsync(c->h_scal, c->rmax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counters, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->h_cnt[2] != 0) return LAGOT_EINVAL;
+    const double rmax = c->h_scal[0];
+    // grid cell size: 2 r_max (the 3x3x3 neighbourhood then covers every bisector
+    // that can cut a ball), but at most 512 cells per axis and 2^24 cells in all
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) ext = std::max(ext, box.hi[a] - box.lo[a]);
+    double s = std::max(2.0 * rmax, ext / 512.0);
+    int dim[3];
+    for (;;) {
+        int64_t tot = 1;
+        for (int a = 0; a < 3; ++a) {
+            dim[a] = std::max(1, (int)std::ceil((box.hi[a] - box.lo[a]) / s));
+            tot *= dim[a];
+        }
+        if (tot <= (1 << 24)) break;
+        s *= 1.25;
+    }
+    GridDesc g;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = (float)box.lo[a];
+        g.dim[a] = dim[a];
+    }
+    g.s = (float)s;
+    g.inv_s = (float)(1.0 / s);
+    g.ncell = dim[0] * dim[1] * dim[2];
+    c->grid = g;
+    rc = ensure_cells(c, g.ncell);
+    if (rc) return rc;
+    launch_grid_build(c->stream, n, c->pos_orig, g, c->keys, c->cell_count, c->cell_start, c->scan_tmp, c->perm,
+                      c->cursor);
+    launch_permute_in(c->stream, n, c->perm, c->pos_orig, psi, nu, c->pos_s, c->psi_s, nu ? c->nu_s : nullptr);
+    return LAGOT_OK;
+}
+
+// One evaluation of all cells at the weights in pos_s.w / psi_s (rmax on device).
+void evaluate(lagot_ctx *c, int64_t n, const lagot_box &box, bool walls) {
+    const BoxF bf = to_boxf(box);
+    (void)hipMemsetAsync(c->counters, 0, 2 * sizeof(int32_t), c->stream);
+    if (walls) (void)hipMemsetAsync(c->wall, 0, 6 * sizeof(float) * (size_t)n, c->stream);
+    EvalOut o{c->V, c->K, walls ? c->wall : nullptr, c->fcol, c->farea, c->fcnt, c->flags, c->fb_list,
+              c->counters + 0, c->counters + 1};
+    (void)hipEventRecord(c->ev0, c->stream);
+    launch_cells(c->stream, n, c->pos_s, c->perm, c->cell_start, c->grid, bf, c->rmax, o, c->tpc);
+    (void)hipEventRecord(c->ev1, c->stream);
+    c->ev_pending = true;
+    launch_cells_fallback(c->stream, n, c->pos_s, c->psi_s, c->perm, c->cell_start, c->grid, bf, c->rmax, o);
+}
+
+struct EvalStats {
+    double sumV, maxrel, gnorm, minV;
+    int fb, fail;
+};
+
+int evaluate_reduce(lagot_ctx *c, int64_t n, const lagot_box &box, EvalStats *es) {
+    evaluate(c, n, box, false);
+    const int nb = nblk256(n);
+    launch_eval_reduce(c->stream, n, c->V, c->nu_s, c->partial, nb, c->red4);
+    HIP_TRY(hipMemcpyAsync(c->h_scal, c->red4, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    collect_cell_time(c);
+    es->sumV = c->h_scal[0];
+    es->maxrel = c->h_scal[1];
+    es->gnorm = c->h_scal[2];
+    es->minV = c->h_scal[3];
+    es->fb = c->h_cnt[0];
+    es->fail = c->h_cnt[1];
+    c->fb_total += es->fb;
+    return LAGOT_OK;
+}
+
+// Newton direction: assemble -Hess K, Jacobi-PCG for (-Hess K) u = nu - V, u in c->x.
+int newton_direction(lagot_ctx *c, int64_t n, const lagot_opts &o, int *cg_iters) {
+    const int nb = nblk256(n);
+    HIP_TRY(hipMemsetAsync(c->counters + 3, 0, sizeof(int32_t), c->stream));
+    launch_hess_assemble(c->stream, n, c->pos_s, c->psi_s, c->K, c->fcol, c->farea, c->fcnt, c->hcol, c->hval,
+                         c->xcnt, c->diag, c->counters + 3);
+    launch_hess_finish(c->stream, n, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hval, c->diag);
+    launch_pcg_init(c->stream, n, c->V, c->nu_s, c->diag, c->g, c->x, c->r, c->z, c->p, c->partial, nb);
+    launch_pcg_scalars(c->stream, c->partial, nb, 2, c->scal);
+    int rc = sync_read(c, c->scal, c->h_scal, 6 * sizeof(double));
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(c->h_cnt + 3, c->counters + 3, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (c->h_cnt[3] != 0) return LAGOT_ECAPACITY;
+    const double rr0 = c->h_scal[1];
+    *cg_iters = 0;
+    if (!(rr0 > 0.0)) return LAGOT_OK;
+    const double stop = o.cg_rtol * o.cg_rtol * rr0;
+    const int chunk = 8;
+    for (int k = 0; k < o.cg_max_iter;) {
+        for (int m = 0; m < chunk && k < o.cg_max_iter; ++m, ++k) {
+            launch_spmv_dot(c->stream, n, c->hcol, c->hval, c->hcnt, c->diag, c->p, c->q, c->partial, nb);
+            launch_pcg_scalars(c->stream, c->partial, nb, 0, c->scal);
+            launch_pcg_update(c->stream, n, c->scal, c->diag, c->x, c->r, c->z, c->p, c->q, c->partial, nb);
+            launch_pcg_scalars(c->stream, c->partial, nb, 1, c->scal);
+            launch_pcg_direction(c->stream, n, c->scal, c->z, c->p);
+        }
+        rc = sync_read(c, c->scal, c->h_scal, 6 * sizeof(double));
+        if (rc) return rc;
+        *cg_iters = k;
+        if (c->h_scal[5] != 0.0) {
+            // breakdown only matters if the residual has not converged yet
+            if (c->h_scal[1] <= stop) return LAGOT_OK;
+            return LAGOT_ESINGULAR;
+        }
+        if (c->h_scal[1] <= stop) return LAGOT_OK;
+    }
+    return LAGOT_OK;  // iteration cap: inexact direction, the step control still guards the update
+}
+
+void fill_defaults(lagot_opts *o) {
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-5;
+    o->max_newton = 100;
+    o->max_halvings = 30;
+    o->cg_rtol = 1e-6;
+    o->cg_max_iter = 1000;
+    o->threads_per_cell = 0;
+    o->verbose = 0;
+}
+
+int check_opts(const lagot_opts &o) {
+    if (!(o.tol > 0) || o.max_newton < 0 || o.max_halvings < 0 || !(o.cg_rtol > 0) || o.cg_max_iter < 1)
+        return LAGOT_EINVAL;
+    if (o.threads_per_cell != 0 && o.threads_per_cell != 16 && o.threads_per_cell != 32 && o.threads_per_cell != 64)
+        return LAGOT_EINVAL;
+    return LAGOT_OK;
+}
+
+// Damped Newton (Algorithm 1, KMT step control); max_iters = 1 for a single step.
+int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *nu,
+               const lagot_box &box, double *psi, const lagot_opts *opts_in, lagot_stats *st, bool single) {
+    const double t0 = now_ms();
+    lagot_stats S;
+    std::memset(&S, 0, sizeof(S));
+    lagot_opts o;
+    if (opts_in)
+        o = *opts_in;
+    else
+        fill_defaults(&o);
+    int rc = check_opts(o);
+    if (!rc && !nu) rc = LAGOT_EINVAL;
+    if (!rc) {
+        c->tpc = o.threads_per_cell ? o.threads_per_cell : 16;
+        c->fb_total = 0;
+        c->ms_cell = 0.0;
+        c->cell_launches = 0;
+        rc = prepare(c, n, x, y, z, psi, nu, box);
+    }
+    double ms_eval = 0, ms_lin = 0;
+    if (!rc) {
+        // total prescribed volume must leave room for air: sum nu < |box|
+        const int nb = nblk256(n);
+        launch_eval_reduce(c->stream, n, c->nu_s, c->nu_s, c->partial, nb, c->red4);
+        rc = sync_read(c, c->red4, c->h_scal, 4 * sizeof(double));
+        const double box_vol = (box.hi[0] - box.lo[0]) * (box.hi[1] - box.lo[1]) * (box.hi[2] - box.lo[2]);
+        const double sum_nu = c->h_scal[0], min_nu = c->h_scal[3];
+        if (!rc && !(sum_nu < box_vol)) rc = LAGOT_EINVAL;
+        EvalStats es{};
+        if (!rc) {
+            const double te = now_ms();
+            rc = evaluate_reduce(c, n, box, &es);
+            ms_eval += now_ms() - te;
+            S.evals = 1;
+        }
+        double eps0 = 0.5 * std::min(min_nu, es.minV);
+        if (!rc && !(eps0 > 0.0)) rc = LAGOT_EEMPTY;
+        if (!rc && es.fail) rc = LAGOT_ECAPACITY;
+        int it = 0;
+        while (!rc) {
+            S.max_rel_err = es.maxrel;
+            S.grad_norm = es.gnorm;
+            if (o.verbose)
+                fprintf(stderr, "lagot newton it=%d max_rel_err=%.3e |g|=%.3e minV=%.3e fallback=%d\n", it,
+                        es.maxrel, es.gnorm, es.minV, es.fb);
+            if (es.maxrel <= o.tol) break;
+            if (it >= o.max_newton || (single && it >= 1)) {
+                rc = single ? LAGOT_OK : LAGOT_ENOCONV;
+                break;
+            }
+            const double tl = now_ms();
+            int cgi = 0;
+            rc = newton_direction(c, n, o, &cgi);
+            ms_lin += now_ms() - tl;
+            S.cg_iters += cgi;
+            if (rc) break;
+            double alpha = 1.0;
+            bool accepted = false;
+            EvalStats et{};
+            for (int h = 0; h <= o.max_halvings; ++h) {
+                const int nb2 = nblk256(n);
+                launch_axpy_trial(c->stream, n, c->psi_s, c->x, alpha, c->psi_trial, c->pos_s, c->rmax_partial);
+                launch_reduce_max(c->stream, c->rmax_partial, nb2, c->rmax);
+                const double te = now_ms();
+                rc = evaluate_reduce(c, n, box, &et);
+                ms_eval += now_ms() - te;
+                S.evals++;
+                if (rc) break;
+                if (et.fail == 0 && et.minV >= eps0 && et.gnorm <= (1.0 - 0.5 * alpha) * es.gnorm) {
+                    accepted = true;
+                    break;
+                }
+                alpha *= 0.5;
+                S.halvings++;
+            }
+            if (rc) break;
+            if (!accepted) {
+                // restore the float32 shadow and r_max of the last accepted weights
+                launch_axpy_trial(c->stream, n, c->psi_s, c->x, 0.0, c->psi_trial, c->pos_s, c->rmax_partial);
+                launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
+                rc = et.fail ? LAGOT_ECAPACITY : LAGOT_ELINESEARCH;
+                break;
+            }
+            std::swap(c->psi_s, c->psi_trial);
+            es = et;
+            ++it;
+            S.newton_iters = it;
+        }
+        S.max_rel_err = es.maxrel;
+        S.grad_norm = es.gnorm;
+        if (rc != LAGOT_EINVAL && rc != LAGOT_EHIP) {
+            launch_scatter_out_f64(c->stream, n, c->perm, c->psi_s, psi);
+            if (hipStreamSynchronize(c->stream) != hipSuccess) rc = LAGOT_EHIP;
+        }
+    }
+    S.fallback_cells = c->fb_total;
+    S.cell_launches = c->cell_launches;
+    S.ms_cell_kernel = c->ms_cell;
+    S.status = rc;
+    S.ms_eval = ms_eval;
+    S.ms_linear = ms_lin;
+    S.ms_total = now_ms() - t0;
+    if (st) *st = S;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lagot_default_opts(lagot_opts *opts) {
+    if (opts) fill_defaults(opts);
+}
+
+int lagot_create(lagot_ctx **out, int device, void *stream) {
+    if (!out) return LAGOT_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LAGOT_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return LAGOT_EHIP;
+    lagot_ctx *c = new lagot_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (dalloc(&c->counters, 8) != hipSuccess || dalloc(&c->scal, 16) != hipSuccess ||
+        dalloc(&c->red4, 4) != hipSuccess || dalloc(&c->rmax, 1) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_scal, 16 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_cnt, 16 * sizeof(int32_t)) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return LAGOT_EHIP;
+    }
+    *out = c;
+    return LAGOT_OK;
+}
+
+void lagot_destroy(lagot_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+}
+
+int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                lagot_box box, double *vol, double *sph_area, float *wall_area, int64_t *row_ptr, int32_t *col,
+                float *facet_area, int64_t nnz_cap, int64_t *nnz_out) {
+    if (!c || !vol) return LAGOT_EINVAL;
+    const bool csr = row_ptr || col || facet_area;
+    if (csr && !(row_ptr && col && facet_area && nnz_cap >= 0)) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    c->fb_total = 0;
+    if (c->tpc != 16 && c->tpc != 32 && c->tpc != 64) c->tpc = 16;
+    int rc = prepare(c, n, x, y, z, psi, nullptr, box);
+    if (rc) return rc;
+    evaluate(c, n, box, wall_area != nullptr);
+    launch_scatter_out_f64(c->stream, n, c->perm, c->V, vol);
+    if (sph_area) launch_scatter_out_f64(c->stream, n, c->perm, c->K, sph_area);
+    if (wall_area) launch_scatter_walls(c->stream, n, c->perm, c->wall, wall_area);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    if (csr || nnz_out) {
+        launch_csr_count(c->stream, n, c->perm, c->fcnt, c->csr_cnt);
+        launch_scan_i32(c->stream, c->csr_cnt, c->csr_start, (int)n, c->csr_tmp);
+        HIP_TRY(hipMemcpyAsync(c->h_cnt + 4, c->csr_start + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->ms_cell = 0.0;
+    c->cell_launches = 0;
+    collect_cell_time(c);
+    c->last_fb = c->h_cnt[0];
+    if (c->h_cnt[1] != 0) return LAGOT_ECAPACITY;
+    if (csr || nnz_out) {
+        const int64_t nnz = c->h_cnt[4];
+        if (nnz_out) *nnz_out = nnz;
+        if (csr) {
+            if (nnz > nnz_cap) return LAGOT_ECAPACITY;
+            launch_csr_fill(c->stream, n, c->perm, c->fcol, c->farea, c->fcnt, c->csr_start, col, facet_area,
+                            row_ptr);
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+    }
+    return LAGOT_OK;
+}
+
+int lagot_newton_step(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
+                      lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats) {
+    if (!ctx || !psi_inout) return LAGOT_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
+    return newton_run(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, true);
+}
+
+int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
+                lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats) {
+    if (!ctx || !psi_inout) return LAGOT_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
+    return newton_run(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, false);
+}
+
+int lagot_last_fallback_cells(const lagot_ctx *ctx) { return ctx ? ctx->last_fb : -1; }
+
+double lagot_last_cell_kernel_ms(const lagot_ctx *ctx) { return ctx ? ctx->ms_cell : -1.0; }
+
+const char *lagot_strerror(int code) {
+    switch (code) {
+        case LAGOT_OK: return "ok";
+        case LAGOT_EINVAL: return "invalid argument";
+        case LAGOT_EEMPTY: return "a start cell is empty";
+        case LAGOT_ENOCONV: return "Newton iteration limit reached";
+        case LAGOT_ELINESEARCH: return "step halving limit reached";
+        case LAGOT_ECAPACITY: return "capacity exceeded";
+        case LAGOT_ESINGULAR: return "conjugate-gradient breakdown";
+        case LAGOT_EHIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,314 @@
+// grid.hip -- uniform-grid spatial sort of the sites (grid_knn, construction
+// part) and the gathers/scatters between caller order and grid order.
+//
+// The grid cell size s is at least r_i + r_j for every pair the cell kernel
+// may need, so the bisectors that cut ball i come from the grid cells within
+// ceil((r_i + r_max)/s) of site i (section 4 "Finding Contributing Neighbors":
+// the ball bound replaces the security radius and is exact for restricted
+// cells). Sites are counting-sorted by grid cell (z fastest), and within a grid
+// cell by caller index, so the order is deterministic.
+#include "lagot_internal.h"
+
+namespace lagot {
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ inline int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one tile; returns the tile total through bsum.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const int32_t *__restrict__ in,
+                                                              int32_t *__restrict__ out,
+                                                              int32_t *__restrict__ bsum, int n) {
+    __shared__ int wsum[SCAN_THREADS / 64];
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int tsum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        tsum += v[k];
+    }
+    int incl = wave_incl_scan(tsum);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < w; ++k) woff += wsum[k];
+    int run = woff + incl - tsum;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == SCAN_THREADS - 1) bsum[blockIdx.x] = run;
+}
+
+// Single-block exclusive scan of the tile totals (any count).
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *bsum, int nb, int32_t *total) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        int i = base + threadIdx.x;
+        int v = (i < nb) ? bsum[i] : 0;
+        int incl = wave_incl_scan(v);
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int woff = 0;
+        for (int k = 0; k < w; ++k) woff += wsum[k];
+        int c = carry;
+        if (i < nb) bsum[i] = c + woff + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = c + woff + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int32_t *out, const int32_t *bsum, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += bsum[i / SCAN_TILE];
+}
+
+// exclusive scan of in[0..n) into out[0..n), out[n] = total
+void exclusive_scan(hipStream_t st, const int32_t *in, int32_t *out, int n, int32_t *tmp) {
+    int nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(SCAN_THREADS), 0, st, in, out, tmp, n);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tmp, nb, out + n);
+    hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, st, out, tmp, n);
+}
+
+__global__ void k_gather_sites(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
+                               const float *__restrict__ z, const double *__restrict__ psi,
+                               float4 *__restrict__ pos, double *__restrict__ rmax_partial) {
+    __shared__ double red[4];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (i < n) {
+        double p = psi[i];
+        pos[i] = make_float4(x[i], y[i], z[i], (float)p);
+        r = p > 0.0 ? sqrt(p) : 0.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+        rmax_partial[blockIdx.x] = m;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_max(const double *partial, int nb, double *out) {
+    __shared__ double red[16];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 1024) m = fmax(m, partial[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 16; ++k) m = fmax(m, red[k]);
+        *out = fmax(red[0], m);
+    }
+}
+
+__device__ inline int grid_key(const GridDesc &g, float px, float py, float pz) {
+    int ix = (int)floorf((px - g.lo[0]) * g.inv_s);
+    int iy = (int)floorf((py - g.lo[1]) * g.inv_s);
+    int iz = (int)floorf((pz - g.lo[2]) * g.inv_s);
+    ix = min(max(ix, 0), g.dim[0] - 1);
+    iy = min(max(iy, 0), g.dim[1] - 1);
+    iz = min(max(iz, 0), g.dim[2] - 1);
+    return (ix * g.dim[1] + iy) * g.dim[2] + iz;
+}
+
+__global__ void k_keys_count(int64_t n, const float4 *__restrict__ pos, GridDesc g, int32_t *__restrict__ keys,
+                             int32_t *__restrict__ count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 p = pos[i];
+    int k = grid_key(g, p.x, p.y, p.z);
+    keys[i] = k;
+    atomicAdd(&count[k], 1);
+}
+
+__global__ void k_scatter(int64_t n, const int32_t *__restrict__ keys, int32_t *__restrict__ cursor,
+                          int32_t *__restrict__ perm) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int slot = atomicAdd(&cursor[keys[i]], 1);
+    perm[slot] = (int32_t)i;
+}
+
+// Order each grid cell's sites by caller index (insertion sort; cells hold a few sites).
+__global__ void k_sort_cells(int ncell, const int32_t *__restrict__ start, int32_t *__restrict__ perm) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int b = start[c], e = start[c + 1];
+    for (int a = b + 1; a < e; ++a) {
+        int v = perm[a];
+        int k = a - 1;
+        while (k >= b && perm[k] > v) {
+            perm[k + 1] = perm[k];
+            --k;
+        }
+        perm[k + 1] = v;
+    }
+}
+
+__global__ void k_permute_in(int64_t n, const int32_t *__restrict__ perm, const float4 *__restrict__ pos_orig,
+                             const double *__restrict__ psi, const double *__restrict__ nu, float4 *__restrict__ pos_s,
+                             double *__restrict__ psi_s, double *__restrict__ nu_s) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int i = perm[k];
+    pos_s[k] = pos_orig[i];
+    psi_s[k] = psi[i];
+    if (nu) nu_s[k] = nu[i];
+}
+
+__global__ void k_psi_shadow(int64_t n, const double *__restrict__ psi_s, float4 *__restrict__ pos_s) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    pos_s[k].w = (float)psi_s[k];
+}
+
+__global__ void k_scatter_out(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src,
+                              double *__restrict__ dst) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    dst[perm[k]] = src[k];
+}
+
+// Count invalid inputs: NaN, site not strictly inside the box, nu <= 0.
+__global__ void k_validate(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
+                           const float *__restrict__ z, const double *__restrict__ psi, const double *__restrict__ nu,
+                           BoxF box, int32_t *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float p[3] = {x[i], y[i], z[i]};
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) ok = ok && (p[a] > box.lo[a]) && (p[a] < box.hi[a]);  // false for NaN
+    if (psi) ok = ok && !isnan(psi[i]);
+    if (nu) ok = ok && (nu[i] > 0.0);
+    if (!ok) atomicAdd(bad, 1);
+}
+
+// facet counts per caller row
+__global__ void k_csr_count(int64_t n, const int32_t *__restrict__ perm, const int32_t *__restrict__ fcnt,
+                            int32_t *__restrict__ cnt) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    cnt[perm[k]] = fcnt[k];
+}
+
+// facets of grid row k -> caller row perm[k], columns mapped to caller indices and sorted
+__global__ void k_csr_fill(int64_t n, const int32_t *__restrict__ perm, const int32_t *__restrict__ fcol,
+                           const float *__restrict__ farea, const int32_t *__restrict__ fcnt,
+                           const int32_t *__restrict__ start, int32_t *__restrict__ col, float *__restrict__ area,
+                           int64_t *__restrict__ row_ptr) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int i = perm[k];
+    const int64_t b = start[i];
+    const int c = fcnt[k];
+    row_ptr[i] = b;
+    if (i == 0) row_ptr[n] = start[n];
+    for (int f = 0; f < c; ++f) {
+        const int v = perm[fcol[k * FCAP + f]];
+        const float a = farea[k * FCAP + f];
+        int64_t m = b + f - 1;
+        while (m >= b && col[m] > v) {
+            col[m + 1] = col[m];
+            area[m + 1] = area[m];
+            --m;
+        }
+        col[m + 1] = v;
+        area[m + 1] = a;
+    }
+}
+
+__global__ void k_scatter_walls(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ ws,
+                                float *__restrict__ w) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t i = perm[k];
+    for (int a = 0; a < 6; ++a) w[i * 6 + a] = ws[k * 6 + a];
+}
+
+inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int n, int32_t *tmp) {
+    exclusive_scan(st, in, out, n, tmp);
+}
+
+void launch_csr_count(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcnt, int32_t *cnt_orig) {
+    hipLaunchKernelGGL(k_csr_count, dim3(nblocks(n, 256)), dim3(256), 0, st, n, perm, fcnt, cnt_orig);
+}
+
+void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcol, const float *farea,
+                     const int32_t *fcnt, const int32_t *start, int32_t *col, float *area, int64_t *row_ptr) {
+    hipLaunchKernelGGL(k_csr_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, n, perm, fcol, farea, fcnt, start, col,
+                       area, row_ptr);
+}
+
+void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const float *wall_s, float *wall) {
+    hipLaunchKernelGGL(k_scatter_walls, dim3(nblocks(n, 256)), dim3(256), 0, st, n, perm, wall_s, wall);
+}
+
+void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float *y, const float *z,
+                         const double *psi, float4 *pos_orig, double *rmax_partial, int nblk) {
+    hipLaunchKernelGGL(k_gather_sites, dim3(nblk), dim3(256), 0, st, n, x, y, z, psi, pos_orig, rmax_partial);
+}
+
+void launch_reduce_max(hipStream_t st, const double *partial, int nblk, double *out) {
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(1024), 0, st, partial, nblk, out);
+}
+
+void launch_grid_build(hipStream_t st, int64_t n, const float4 *pos_orig, GridDesc g, int32_t *keys,
+                       int32_t *cell_count, int32_t *cell_start, int32_t *scan_tmp, int32_t *perm,
+                       int32_t *cursor) {
+    (void)hipMemsetAsync(cell_count, 0, sizeof(int32_t) * (size_t)g.ncell, st);
+    hipLaunchKernelGGL(k_keys_count, dim3(nblocks(n, 256)), dim3(256), 0, st, n, pos_orig, g, keys, cell_count);
+    exclusive_scan(st, cell_count, cell_start, g.ncell, scan_tmp);
+    (void)hipMemcpyAsync(cursor, cell_start, sizeof(int32_t) * (size_t)g.ncell, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks(n, 256)), dim3(256), 0, st, n, keys, cursor, perm);
+    hipLaunchKernelGGL(k_sort_cells, dim3(nblocks(g.ncell, 256)), dim3(256), 0, st, g.ncell, cell_start, perm);
+}
+
+void launch_permute_in(hipStream_t st, int64_t n, const int32_t *perm, const float4 *pos_orig, const double *psi,
+                       const double *nu, float4 *pos_s, double *psi_s, double *nu_s) {
+    hipLaunchKernelGGL(k_permute_in, dim3(nblocks(n, 256)), dim3(256), 0, st, n, perm, pos_orig, psi, nu, pos_s,
+                       psi_s, nu_s);
+}
+
+void launch_psi_shadow(hipStream_t st, int64_t n, const double *psi_s, float4 *pos_s) {
+    hipLaunchKernelGGL(k_psi_shadow, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi_s, pos_s);
+}
+
+void launch_scatter_out_f64(hipStream_t st, int64_t n, const int32_t *perm, const double *src_s, double *dst) {
+    hipLaunchKernelGGL(k_scatter_out, dim3(nblocks(n, 256)), dim3(256), 0, st, n, perm, src_s, dst);
+}
+
+void launch_validate(hipStream_t st, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                     const double *nu, BoxF box, int32_t *bad) {
+    hipLaunchKernelGGL(k_validate, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x, y, z, psi, nu, box, bad);
+}
+
+}  // namespace lagot

@@ -1,0 +1,107 @@
+// lagot_internal.h -- device data layout and launch wrappers shared by the
+// HIP kernel files and the C-ABI host driver (api.cpp). Not a public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lagot {
+
+// Facet storage: row-major blocks of FCAP entries per cell (cell i owns
+// [i*FCAP, i*FCAP + fcnt[i])). The same layout holds the Hessian rows.
+constexpr int FCAP = 64;
+// Fast-path capacities of the cell kernel (float32, G lanes per cell).
+constexpr int FAST_CMAX = 48;   // candidate bisectors (incl. walls) per cell
+constexpr int FAST_PMAX = 32;   // planes of the polytope (6 auxiliary + cutting ones)
+constexpr int FAST_VMAX = 64;   // polytope vertices (triangles of the dual)
+// Large-capacity float64 path for cells flagged by the fast path.
+constexpr int BIG_CMAX = 256;
+constexpr int BIG_PMAX = 64;
+constexpr int BIG_VMAX = 128;
+
+// Per-cell status bits written by the cell kernel.
+enum CellFlag : uint32_t {
+    CF_EMPTY = 1u << 0,     // the cell is empty (legitimate result)
+    CF_CAND = 1u << 1,      // too many candidate planes
+    CF_PLANES = 1u << 2,    // too many polytope planes
+    CF_VERTS = 1u << 3,     // too many polytope vertices
+    CF_TOPO = 1u << 4,      // inconsistent clip combinatorics (near-degenerate float geometry)
+    CF_WALK = 1u << 5,      // facet polygon walk did not close
+    CF_FACETS = 1u << 6,    // more than FCAP facets
+    CF_PREC = 1u << 7,      // volume small against its ball: float32 pyramid sums cancel, redo in float64
+    CF_FAIL_MASK = CF_CAND | CF_PLANES | CF_VERTS | CF_TOPO | CF_WALK | CF_FACETS,
+};
+
+struct GridDesc {
+    float lo[3];      // box low corner
+    float inv_s;      // 1 / grid cell size
+    float s;          // grid cell size
+    int dim[3];       // cells per axis
+    int ncell;        // dim[0]*dim[1]*dim[2]
+};
+
+struct BoxF {
+    float lo[3], hi[3];
+};
+
+// Views of the evaluation outputs (sorted site order).
+struct EvalOut {
+    double *V;        // [n] volume
+    double *K;        // [n] spherical area
+    float *wall;      // [6n] wall facet areas (may be null)
+    int32_t *fcol;    // [n*FCAP] neighbour (sorted index)
+    float *farea;     // [n*FCAP] facet area
+    int32_t *fcnt;    // [n] facet count
+    uint32_t *flags;  // [n] CellFlag bits
+    int32_t *fb_list; // [n] cells to redo on the float64 path
+    int32_t *fb_count;// [1] length of fb_list (device counter)
+    int32_t *fail_count; // [1] cells that failed the float64 path too
+};
+
+// ---- launch wrappers (defined in the .hip files) ----
+// grid.hip
+void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float *y, const float *z,
+                         const double *psi, float4 *pos_orig, double *rmax_partial, int nblk);
+void launch_reduce_max(hipStream_t st, const double *partial, int nblk, double *out);
+void launch_grid_build(hipStream_t st, int64_t n, const float4 *pos_orig, GridDesc g, int32_t *keys,
+                       int32_t *cell_count, int32_t *cell_start, int32_t *scan_tmp, int32_t *perm,
+                       int32_t *cursor);
+void launch_permute_in(hipStream_t st, int64_t n, const int32_t *perm, const float4 *pos_orig, const double *psi,
+                       const double *nu, float4 *pos_s, double *psi_s, double *nu_s);
+void launch_psi_shadow(hipStream_t st, int64_t n, const double *psi_s, float4 *pos_s);
+void launch_scatter_out_f64(hipStream_t st, int64_t n, const int32_t *perm, const double *src_s, double *dst);
+void launch_validate(hipStream_t st, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                     const double *nu, BoxF box, int32_t *bad);
+void launch_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int n, int32_t *tmp);
+void launch_csr_count(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcnt, int32_t *cnt_orig);
+void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcol, const float *farea,
+                     const int32_t *fcnt, const int32_t *start, int32_t *col, float *area, int64_t *row_ptr);
+void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const float *wall_s, float *wall);
+
+// cells.hip
+void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm, const int32_t *cell_start,
+                  GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc);
+void launch_cells_fallback(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
+                           const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out);
+
+// newton.hip
+void launch_eval_reduce(hipStream_t st, int64_t n, const double *V, const double *nu, double *partial, int nblk,
+                        double *out4);
+void launch_hess_assemble(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const double *K,
+                          const int32_t *fcol, const float *farea, const int32_t *fcnt, int32_t *hcol, float *hval,
+                          int32_t *xcnt, double *diag, int32_t *err);
+void launch_hess_finish(hipStream_t st, int64_t n, const double *psi_s, const double *K, const int32_t *fcnt,
+                        const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag);
+void launch_spmv_dot(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
+                     const double *diag, const double *p, double *q, double *partial, int nblk);
+void launch_reduce_sum(hipStream_t st, const double *partial, int nblk, int ncomp, double *out);
+void launch_pcg_init(hipStream_t st, int64_t n, const double *V, const double *nu, const double *diag, double *g,
+                     double *x, double *r, double *z, double *p, double *partial, int nblk);
+void launch_pcg_update(hipStream_t st, int64_t n, const double *scal, const double *diag, double *x, double *r,
+                       double *z, const double *p, const double *q, double *partial, int nblk);
+void launch_pcg_scalars(hipStream_t st, const double *partial, int nblk, int mode, double *scal);
+void launch_pcg_direction(hipStream_t st, int64_t n, const double *scal, const double *z, double *p);
+void launch_axpy_trial(hipStream_t st, int64_t n, const double *psi_s, const double *u, double alpha,
+                       double *psi_trial, float4 *pos_s, double *rmax_partial);
+
+}  // namespace lagot

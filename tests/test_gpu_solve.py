@@ -1,0 +1,124 @@
+"""GPU damped Newton (lagot_solve / lagot_newton_step) against the FP64 oracle.
+
+The weights are unique (section 2.2), so a solve is judged by re-evaluating the
+GPU's converged weights with the oracle: every volume must be within the
+tolerance of its prescription. Error paths are forced from the host."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_05765_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2601_05765_amd as L
+    assert torch.cuda.is_available()
+    return L.Context()
+
+
+def _dev(sc, psi=None):
+    import torch
+    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    psi = sc.psi0 if psi is None else psi
+    return (t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32), t(sc.nu, torch.float64),
+            t(psi, torch.float64))
+
+
+def _oracle_err(oracle_mod, sc, psi, idx=None):
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, psi, idx=idx)
+    nu = sc.nu if idx is None else sc.nu[idx]
+    return float(np.max(np.abs(c.V - nu) / nu))
+
+
+def test_solve_slab_1k(ctx, oracle_mod):
+    _say("case: solve slab_uniform 1k")
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 0)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.max_rel_err <= 1e-5
+    err = _oracle_err(oracle_mod, sc, psi.cpu().numpy())
+    _say(f"  oracle max rel err {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("tpc", [16, 32, 64])
+def test_solve_threads_per_cell(ctx, oracle_mod, tpc):
+    _say(f"case: solve slab_uniform 1k seed 2, threads_per_cell={tpc}")
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 2)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5, threads_per_cell=tpc))
+    assert st.status == 0
+    assert _oracle_err(oracle_mod, sc, psi.cpu().numpy()) <= 1e-5
+
+
+def test_solve_dam_break_100k(ctx, oracle_mod):
+    _say("case: solve dam_break 100k, sampled oracle check")
+    import paper_2601_05765_amd as L
+    sc = scenes.dam_break(100_000, 0)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.max_rel_err <= 1e-5
+    idx = np.sort(np.random.default_rng(2).choice(sc.n, 3000, replace=False))
+    err = _oracle_err(oracle_mod, sc, psi.cpu().numpy(), idx)
+    _say(f"  oracle max rel err (3000 cells) {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_newton_step_decreases_residual(ctx, oracle_mod):
+    _say("case: single newton step")
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 3)
+    x, y, z, nu, psi = _dev(sc)
+    c0 = oracle_mod.cells(sc.x, sc.y, sc.z, sc.psi0)
+    g0 = np.linalg.norm(sc.nu - c0.V)
+    st = ctx.newton_step(x, y, z, nu, psi)
+    assert st.status == 0 and st.newton_iters == 1
+    c1 = oracle_mod.cells(sc.x, sc.y, sc.z, psi.cpu().numpy())
+    g1 = np.linalg.norm(sc.nu - c1.V)
+    assert g1 < g0
+    assert c1.V.min() >= 0.5 * min(sc.nu.min(), c0.V.min()) * (1 - 1e-5)
+
+
+def test_error_codes(ctx):
+    _say("case: error codes")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(200, 4)
+    # site outside the box -> EINVAL
+    x, y, z, nu, psi = _dev(sc)
+    x[3] = 1.5
+    assert ctx.solve(x, y, z, nu, psi, check=False).status == L.EINVAL
+    # NaN weight -> EINVAL
+    x, y, z, nu, psi = _dev(sc)
+    psi[0] = float("nan")
+    assert ctx.solve(x, y, z, nu, psi, check=False).status == L.EINVAL
+    # infeasible total volume -> EINVAL
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu * (1.2 / float(nu.sum())), psi, check=False)
+    assert st.status == L.EINVAL
+    # an empty start cell -> EEMPTY
+    x, y, z, nu, psi = _dev(sc)
+    psi[5] = -1.0
+    assert ctx.solve(x, y, z, nu, psi, check=False).status == L.EEMPTY
+    # iteration limit -> ENOCONV, psi holds an accepted iterate
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(max_newton=1), check=False)
+    assert st.status == L.ENOCONV and st.newton_iters == 1
+    assert torch.isfinite(psi).all()
+    # bad option -> EINVAL
+    x, y, z, nu, psi = _dev(sc)
+    assert ctx.solve(x, y, z, nu, psi, opts=L.default_opts(threads_per_cell=7), check=False).status == L.EINVAL
