@@ -175,7 +175,7 @@ def main(argv=None):
         achieved = fpc * args.n / (ms_kernel / 1000.0) / 1e12
         line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                            "kernel": "k_cells_fast<16> (fused clip + ball integration, float32)",
+                            "kernel": "k_cells_fast<32> (fused clip + ball integration, float32)",
                             "flops_per_cell": fpc, "ms_per_launch": ms_kernel,
                             "work_units_per_cell": dict(zip(["cand", "tests", "newv", "faces", "edges", "cross"],
                                                             [float(v) for v in work_mean]))}

@@ -60,7 +60,8 @@ typedef struct {
     int max_halvings;    /* step halvings per iteration                           (default 30)    */
     double cg_rtol;      /* relative residual of the Jacobi-PCG direction solve   (default 1e-6)  */
     int cg_max_iter;     /* PCG iteration limit                                    (default 1000)  */
-    int threads_per_cell;/* lanes per cell in the cell kernel: 0 = autotuned, else 16, 32 or 64     */
+    int threads_per_cell;/* lanes per cell in the cell kernel: 0 = the context's default, else 8, 16,
+                            32 or 64                                                             */
     int verbose;         /* 1: print one line per Newton iteration to stderr                        */
     int reserved[5];
 } lagot_opts;
@@ -138,6 +139,10 @@ int lagot_newton_step(lagot_ctx *ctx, int64_t n, const float *x, const float *y,
  */
 int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
                 lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats);
+
+/* Lanes per cell (8, 16, 32 or 64) used by lagot_cells and by solves whose options leave
+ * threads_per_cell at 0 (default 32). Returns LAGOT_EINVAL for other values. */
+int lagot_set_threads_per_cell(lagot_ctx *ctx, int threads_per_cell);
 
 /* Number of cells that the last lagot_cells call on this context redid on the
  * large-capacity float64 path (diagnostic; -1 if ctx is NULL). */

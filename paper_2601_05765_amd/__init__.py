@@ -21,7 +21,8 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms", "lagot_strerror"]
+           "lagot_set_threads_per_cell", "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms",
+           "lagot_strerror"]
 
 
 class Box(ctypes.Structure):
@@ -71,6 +72,8 @@ def load():
             f = getattr(lib, name)
             f.argtypes = [P, I64, P, P, P, P, Box, P, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
             f.restype = I
+        lib.lagot_set_threads_per_cell.argtypes = [P, I]
+        lib.lagot_set_threads_per_cell.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
         lib.lagot_last_fallback_cells.restype = I
         lib.lagot_last_cell_kernel_ms.argtypes = [P]
@@ -181,6 +184,11 @@ class Context:
             out["row_ptr"], out["col"], out["area"] = rp, col[: nnz.value], fa[: nnz.value]
         out["nnz"] = int(nnz.value)
         return out
+
+    def set_threads_per_cell(self, tpc: int) -> None:
+        rc = load().lagot_set_threads_per_cell(self._h, int(tpc))
+        if rc != OK:
+            raise LagotError(rc, "lagot_set_threads_per_cell")
 
     def last_fallback_cells(self) -> int:
         return int(load().lagot_last_fallback_cells(self._h))

@@ -7,6 +7,7 @@
 // host only reads a few float64 scalars per evaluation / PCG chunk.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -36,7 +37,8 @@ struct lagot_ctx {
     hipStream_t stream = nullptr;
     int64_t cap_n = 0;
     int cap_cells = 0;
-    int tpc = 16;
+    int tpc = 32;
+    int tpc_default = 32;  // lanes per cell when the options leave it to the library
 
     // sites (caller order, then grid order)
     float4 *pos_orig = nullptr, *pos_s = nullptr;
@@ -55,6 +57,7 @@ struct lagot_ctx {
     int32_t *hcol = nullptr, *hcnt = nullptr, *xcnt = nullptr;
     float *hval = nullptr;
     double *diag = nullptr, *g = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *p2 = nullptr;
     double *partial = nullptr, *scal = nullptr, *red4 = nullptr, *rmax = nullptr, *rmax_partial = nullptr;
     int cap_blocks = 0;
     // pinned host mirrors
@@ -89,7 +92,7 @@ void free_all(lagot_ctx *c) {
                     c->cell_start, c->cursor, c->scan_tmp, c->V, c->K, c->wall, c->fcol, c->fcnt, c->fb_list,
                     c->farea, c->flags, c->counters, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag, c->g, c->x,
                     c->r, c->z, c->p, c->q, c->partial, c->scal, c->red4, c->rmax, c->rmax_partial, c->csr_cnt,
-                    c->csr_start, c->csr_start64, c->csr_tmp};
+                    c->csr_start, c->csr_start64, c->csr_tmp, c->p2};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -116,7 +119,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     void *bufs[] = {c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->V, c->K, c->wall,
                     c->fcol, c->fcnt, c->fb_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
                     c->g, c->x, c->r, c->z, c->p, c->q, c->partial, c->rmax_partial, c->csr_cnt, c->csr_start,
-                    c->csr_start64, c->csr_tmp};
+                    c->csr_start64, c->csr_tmp, c->p2};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     const size_t N = (size_t)n;
@@ -147,7 +150,8 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->z, N));
     HIP_TRY(dalloc(&c->p, N));
     HIP_TRY(dalloc(&c->q, N));
-    HIP_TRY(dalloc(&c->partial, 4 * (size_t)nb));
+    HIP_TRY(dalloc(&c->p2, N));
+    HIP_TRY(dalloc(&c->partial, std::max<size_t>(4 * (size_t)nb, 5 * 512 + (size_t)spmv_blocks(n) + 64)));
     HIP_TRY(dalloc(&c->rmax_partial, (size_t)nb));
     HIP_TRY(dalloc(&c->csr_cnt, N + 1));
     HIP_TRY(dalloc(&c->csr_start, N + 1));
@@ -281,42 +285,47 @@ int evaluate_reduce(lagot_ctx *c, int64_t n, const lagot_box &box, EvalStats *es
 }
 
 // Newton direction: assemble -Hess K, Jacobi-PCG for (-Hess K) u = nu - V, u in c->x.
+// Iterations are enqueued in chunks without host syncs; the kernels of a chunk
+// turn into no-ops once the residual meets the tolerance (device-side test).
 int newton_direction(lagot_ctx *c, int64_t n, const lagot_opts &o, int *cg_iters) {
-    const int nb = nblk256(n);
     HIP_TRY(hipMemsetAsync(c->counters + 3, 0, sizeof(int32_t), c->stream));
     launch_hess_assemble(c->stream, n, c->pos_s, c->psi_s, c->K, c->fcol, c->farea, c->fcnt, c->hcol, c->hval,
                          c->xcnt, c->diag, c->counters + 3);
     launch_hess_finish(c->stream, n, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hval, c->diag);
-    launch_pcg_init(c->stream, n, c->V, c->nu_s, c->diag, c->g, c->x, c->r, c->z, c->p, c->partial, nb);
-    launch_pcg_scalars(c->stream, c->partial, nb, 2, c->scal);
-    int rc = sync_read(c, c->scal, c->h_scal, 6 * sizeof(double));
-    if (rc) return rc;
-    HIP_TRY(hipMemcpy(c->h_cnt + 3, c->counters + 3, sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (c->h_cnt[3] != 0) return LAGOT_ECAPACITY;
-    const double rr0 = c->h_scal[1];
+    const int nb = pcg_blocks(n);
+    double *RZ = c->partial, *RR = c->partial + 2 * nb, *R0 = c->partial + 4 * nb, *PQ = c->partial + 5 * nb;
+    // PQ holds one partial per SpMV block
+    int32_t *state = c->counters + 4;
+    const double rtol2 = o.cg_rtol * o.cg_rtol;
+    launch_pcg_init(c->stream, n, nb, c->V, c->nu_s, c->diag, c->g, c->x, c->r, c->z, RZ, RR, R0, state);
     *cg_iters = 0;
-    if (!(rr0 > 0.0)) return LAGOT_OK;
-    const double stop = o.cg_rtol * o.cg_rtol * rr0;
-    const int chunk = 8;
-    for (int k = 0; k < o.cg_max_iter;) {
+    double *pb[2] = {c->p, c->p2};
+    const int chunk = 16;
+    int k = 0;
+    for (;;) {
         for (int m = 0; m < chunk && k < o.cg_max_iter; ++m, ++k) {
-            launch_spmv_dot(c->stream, n, c->hcol, c->hval, c->hcnt, c->diag, c->p, c->q, c->partial, nb);
-            launch_pcg_scalars(c->stream, c->partial, nb, 0, c->scal);
-            launch_pcg_update(c->stream, n, c->scal, c->diag, c->x, c->r, c->z, c->p, c->q, c->partial, nb);
-            launch_pcg_scalars(c->stream, c->partial, nb, 1, c->scal);
-            launch_pcg_direction(c->stream, n, c->scal, c->z, c->p);
+            launch_pcg_spmv(c->stream, n, k, nb, rtol2, R0, c->hcol, c->hval, c->hcnt, c->diag, c->z,
+                            pb[(k + 1) & 1], pb[k & 1], c->q, RZ, RR, PQ, state);
+            launch_pcg_update(c->stream, n, k, nb, rtol2, R0, c->diag, c->x, c->r, c->z, pb[k & 1], c->q, RZ, RR,
+                              PQ, state);
         }
-        rc = sync_read(c, c->scal, c->h_scal, 6 * sizeof(double));
-        if (rc) return rc;
-        *cg_iters = k;
-        if (c->h_scal[5] != 0.0) {
-            // breakdown only matters if the residual has not converged yet
-            if (c->h_scal[1] <= stop) return LAGOT_OK;
-            return LAGOT_ESINGULAR;
+        HIP_TRY(hipMemcpyAsync(c->h_cnt + 3, c->counters + 3, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (c->h_cnt[3] != 0) return LAGOT_ECAPACITY;
+        const int done_iters = c->h_cnt[4], breakdown = c->h_cnt[5], converged = c->h_cnt[6];
+        *cg_iters = done_iters;
+        if (breakdown) {
+            // non-positive curvature before the tolerance was met
+            launch_pcg_status(c->stream, nb, RR, R0, state, c->scal);
+            int rc = sync_read(c, c->scal, c->h_scal, 2 * sizeof(double));
+            if (rc) return rc;
+            if (!(c->h_scal[0] <= rtol2 * c->h_scal[1])) return LAGOT_ESINGULAR;
+            break;
         }
-        if (c->h_scal[1] <= stop) return LAGOT_OK;
+        if (converged || done_iters < k || k >= o.cg_max_iter) break;
     }
-    return LAGOT_OK;  // iteration cap: inexact direction, the step control still guards the update
+    return LAGOT_OK;  // at the iteration cap the direction is inexact; the step control still guards it
 }
 
 void fill_defaults(lagot_opts *o) {
@@ -330,11 +339,12 @@ void fill_defaults(lagot_opts *o) {
     o->verbose = 0;
 }
 
+bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
+
 int check_opts(const lagot_opts &o) {
     if (!(o.tol > 0) || o.max_newton < 0 || o.max_halvings < 0 || !(o.cg_rtol > 0) || o.cg_max_iter < 1)
         return LAGOT_EINVAL;
-    if (o.threads_per_cell != 0 && o.threads_per_cell != 16 && o.threads_per_cell != 32 && o.threads_per_cell != 64)
-        return LAGOT_EINVAL;
+    if (!valid_tpc(o.threads_per_cell) && o.threads_per_cell != 0) return LAGOT_EINVAL;
     return LAGOT_OK;
 }
 
@@ -352,7 +362,7 @@ int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const fl
     int rc = check_opts(o);
     if (!rc && !nu) rc = LAGOT_EINVAL;
     if (!rc) {
-        c->tpc = o.threads_per_cell ? o.threads_per_cell : 16;
+        c->tpc = o.threads_per_cell ? o.threads_per_cell : c->tpc_default;
         c->fb_total = 0;
         c->ms_cell = 0.0;
         c->cell_launches = 0;
@@ -491,7 +501,7 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     if (csr && !(row_ptr && col && facet_area && nnz_cap >= 0)) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     c->fb_total = 0;
-    if (c->tpc != 16 && c->tpc != 32 && c->tpc != 64) c->tpc = 16;
+    c->tpc = c->tpc_default;
     int rc = prepare(c, n, x, y, z, psi, nullptr, box);
     if (rc) return rc;
     evaluate(c, n, box, wall_area != nullptr);
@@ -535,6 +545,12 @@ int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const
     if (!ctx || !psi_inout) return LAGOT_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
     return newton_run(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, false);
+}
+
+int lagot_set_threads_per_cell(lagot_ctx *ctx, int threads_per_cell) {
+    if (!ctx || !valid_tpc(threads_per_cell)) return LAGOT_EINVAL;
+    ctx->tpc_default = threads_per_cell;
+    return LAGOT_OK;
 }
 
 int lagot_last_fallback_cells(const lagot_ctx *ctx) { return ctx ? ctx->last_fb : -1; }

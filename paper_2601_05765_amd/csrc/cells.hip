@@ -5,11 +5,13 @@
 // ball (ball_cell_integrate, section 3.2-3.3 and Algorithm 2).
 //
 // Mapping (MI355X, wave64): one 64-lane workgroup holds 64/G cells, G lanes per
-// cell. A cell lives in LDS: its candidate planes, the polytope as a set of
-// vertex triangles (each vertex stores the three planes meeting there, in
-// counter-clockwise order seen from outside, plus its position), and small
-// per-plane tables. Lanes of a group own strided vertex slots and planes;
-// ballots give ranks; all cross-lane traffic goes through LDS.
+// cell. The polytope is a set of vertex triangles (each vertex stores the three
+// planes meeting there, counter-clockwise seen from outside, and its position
+// relative to p_i); lane l of a group keeps vertex slots l, l+G, ... in
+// registers. LDS holds only what lanes exchange: the candidate planes, the
+// plane table, per-plane bitmasks and the two ends of every cut edge, and for
+// the integration the vertex records and a directed-edge -> slot table.
+// Ballots give ranks; three barriers per clipping plane.
 //
 // Clipping by a plane k: vertices beyond k are marked; for every plane x the
 // removed triangles around it give an out-set and an in-set of neighbour planes
@@ -32,7 +34,6 @@ namespace lagot {
 namespace {
 
 constexpr uint32_t TRI_INVALID = 0xFFFFFFFFu;
-constexpr uint32_t TRI_REMOVED = 0x80000000u;
 constexpr double PI_D = 3.14159265358979323846;
 
 template <int PMAX> struct MaskType { using T = uint32_t; };
@@ -81,17 +82,19 @@ template <typename R> __device__ inline R atan2_(R y, R x);
 template <> __device__ inline float atan2_<float>(float y, float x) { return atan2f(y, x); }
 template <> __device__ inline double atan2_<double>(double y, double x) { return atan2(y, x); }
 
-// Signed circular sector of the disk between in-plane directions u and v.
-template <typename R>
-__device__ inline void sector(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny, R nz, R half_rho2, R cone, R &A,
-                              R &Om) {
-    R cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
-    R phi = atan2_<R>(dot3(nx, ny, nz, cx, cy, cz), dot3(ux, uy, uz, vx, vy, vz));
-    A += half_rho2 * phi;
-    Om += cone * phi;
-}
+template <typename R> __device__ inline R rcp_(R v);
+template <> __device__ inline float rcp_<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <> __device__ inline double rcp_<double>(double v) { return 1.0 / v; }
 
-// One fan piece: triangle (q, q+u, q+v) ∩ disk(q, rho). h = |t|, cone = 1 - h/r.
+// One fan piece: triangle (q, q+u, q+v) ∩ disk(q, rho), signed by the orientation of
+// (u, v) about n. h = |t|, cone = 1 - h/r. Adds its planar area to A and the solid
+// angle it subtends at p_i (apex at height h above q) to Om.
+//   - no crossing of the circle: one circular sector of angle phi = angle(u, v):
+//       area rho^2 phi / 2, solid angle phi (1 - h/r)
+//   - crossing at a = u + lo w, b = u + hi w: sectors (u, a) and (b, v) plus the
+//     triangle (q, a, b) inside the disk (Van Oosterom-Strackee with the apex at h).
+//     The two sector angles are parts of one angle below pi, so they are summed as
+//     the argument of the product of their complex numbers (one atan2).
 template <typename R>
 __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny, R nz, R rho2, R h, R cone, R &A,
                                  R &Om) {
@@ -104,51 +107,74 @@ __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny,
     R lo = R(1), hi = R(0);
     if (disc > R(0)) {
         const R sq = sqrt(disc);
-        const R ia = R(1) / a;
+        const R ia = rcp_<R>(a);
         lo = fmax((-b - sq) * ia, R(0));
         hi = fmin((-b + sq) * ia, R(1));
     }
     const R half_rho2 = R(0.5) * rho2;
     if (!(lo < hi)) {
-        sector<R>(ux, uy, uz, vx, vy, vz, nx, ny, nz, half_rho2, cone, A, Om);
+        const R cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+        const R phi = atan2_<R>(dot3(nx, ny, nz, cx, cy, cz), dot3(ux, uy, uz, vx, vy, vz));
+        A += half_rho2 * phi;
+        Om += cone * phi;
         return;
     }
     const R ax = ux + lo * wx, ay = uy + lo * wy, az = uz + lo * wz;
     const R bx = ux + hi * wx, by = uy + hi * wy, bz = uz + hi * wz;
-    sector<R>(ux, uy, uz, ax, ay, az, nx, ny, nz, half_rho2, cone, A, Om);
-    sector<R>(bx, by, bz, vx, vy, vz, nx, ny, nz, half_rho2, cone, A, Om);
-    // triangle (q, q+a, q+b) inside the disk: planar area and Van Oosterom-Strackee solid angle
+    // sector (u, a) and sector (b, v) as complex numbers (cos-part, sin-part)
+    R c1 = dot3(ux, uy, uz, ax, ay, az);
+    R s1 = nx * (uy * az - uz * ay) + ny * (uz * ax - ux * az) + nz * (ux * ay - uy * ax);
+    R c2 = dot3(bx, by, bz, vx, vy, vz);
+    R s2 = nx * (by * vz - bz * vy) + ny * (bz * vx - bx * vz) + nz * (bx * vy - by * vx);
+    if (c1 == R(0) && s1 == R(0)) c1 = R(1);
+    if (c2 == R(0) && s2 == R(0)) c2 = R(1);
+    const R phi = atan2_<R>(c1 * s2 + s1 * c2, c1 * c2 - s1 * s2);
+    A += half_rho2 * phi;
+    Om += cone * phi;
+    // triangle (q, q+a, q+b) inside the disk: planar area and solid angle
     const R cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
-    const R s = dot3(nx, ny, nz, cx, cy, cz);
-    A += R(0.5) * s;
+    const R st = dot3(nx, ny, nz, cx, cy, cz);
+    A += R(0.5) * st;
     const R h2 = h * h;
     const R la = sqrt(dot3(ax, ay, az, ax, ay, az) + h2);
     const R lb = sqrt(dot3(bx, by, bz, bx, by, bz) + h2);
-    Om += R(2) * atan2_<R>(s, la * lb + h * (la + lb) + h2 + dot3(ax, ay, az, bx, by, bz));
+    Om += R(2) * atan2_<R>(st, la * lb + h * (la + lb) + h2 + dot3(ax, ay, az, bx, by, bz));
 }
+
+// Vertex record of the integration phase: position relative to p_i and its three planes.
+template <typename R> struct alignas(16) VRec {
+    R x, y, z;
+    uint32_t t;
+};
 
 template <typename R, int CMAX, int PMAX, int VMAX> struct CellSmem {
     using M = typename MaskType<PMAX>::T;
-    R cand[CMAX][4];       // candidate plane: unit normal, signed distance t
-    int32_t cid[CMAX];     // neighbour (grid-order index) or -1-w for wall w
-    uint8_t corder[CMAX];  // candidates in ascending t
-    R pl[PMAX][4];         // polytope planes (0..5 auxiliary cube)
+    R pl[PMAX][4];   // planes of the polytope (0..5: auxiliary cube): unit normal, t
     int32_t pid[PMAX];
-    uint32_t tri[VMAX];    // vertex = planes (a,b,c) packed, TRI_INVALID if free
-    R vp[VMAX][3];         // vertex position relative to p_i
     union {
         struct {
-            M mout[PMAX];
-            M min[PMAX];
-            uint8_t nxt[PMAX];
-            uint8_t newl[PMAX];
-            uint8_t rslot[PMAX];
-            uint8_t kslot[PMAX];
-            R newpos[PMAX][3];  // positions of the new vertices, by rank
+            R csort[CMAX][4];   // candidate planes in ascending t
+            int32_t csid[CMAX]; // neighbour (grid-order index) or -1-w for wall w
+            union {
+                struct {        // discovery order
+                    R cand[CMAX][4];
+                    int32_t cid[CMAX];
+                } d;
+                struct {        // clipping
+                    M mout[PMAX];       // per plane: heads of the removed triangles' edges leaving it
+                    M min[PMAX];        //            tails of the removed triangles' edges entering it
+                    uint8_t nxt[PMAX];  // boundary plane -> next plane along the cut (0xFF otherwise)
+                    uint8_t newl[PMAX]; // boundary planes by rank
+                    R kpos[PMAX][3];    // kept end of the cut edge x∩nxt[x]
+                    R rpos[PMAX][3];    // removed end
+                } k;
+            } x;
         } c;
-        struct {
-            uint8_t eslot[PMAX][PMAX];  // directed edge a->b  ->  vertex slot holding it
-            uint8_t fstart[PMAX];
+        struct {            // integration
+            VRec<R> rec[VMAX];
+            uint32_t succ[VMAX];         // successor slot on each of the vertex's three faces
+            uint8_t eslot[PMAX][PMAX];   // directed edge a->b -> slot of the vertex holding it
+            uint32_t fstart[PMAX];
             R farea[PMAX];
         } g;
     } u;
@@ -169,11 +195,16 @@ struct CellArgs {
 template <typename R, int G, int CMAX, int PMAX, int VMAX>
 __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMAX, VMAX> &S, bool fast) {
     using M = typename MaskType<PMAX>::T;
-    static_assert(VMAX <= 255 && PMAX <= 64 && CMAX <= 256, "slot indices are bytes");
+    constexpr int NS = VMAX / G;  // vertex slots per lane (registers); slot id = k * G + lane
+    static_assert(NS * G == VMAX, "VMAX must be a multiple of G");
+    static_assert(VMAX <= 255 && PMAX <= 64 && CMAX <= 256, "slot and plane indices are bytes");
     const int gl = (int)(threadIdx.x & (G - 1));
     const unsigned long long below = lanes_below<G>();
     const bool act = cell >= 0;
     uint32_t flags = 0;
+    auto &D = S.u.c.x.d;
+    auto &KT = S.u.c.x.k;
+    auto &GT = S.u.g;
 
     R px = 0, py = 0, pz = 0, psi_i = 0;
     if (act) {
@@ -187,7 +218,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     if (act && !live) flags |= CF_EMPTY;
     const R r = live ? sqrt(psi_i) : R(0);
 
-    // ---------------- candidate bisectors: grid cells within r + r_max ----------------
+    // ---------------- candidate bisectors: sites within r + r_max ----------------
     int ncand = 0;
     bool inside = true;
     bool empty = false;
@@ -199,11 +230,21 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             lo3[a] = max((int)floorf((pp[a] - reach - A.g.lo[a]) * A.g.inv_s), 0);
             hi3[a] = min((int)floorf((pp[a] + reach - A.g.lo[a]) * A.g.inv_s), A.g.dim[a] - 1);
         }
-        for (int ix = lo3[0]; ix <= hi3[0]; ++ix) {
-            for (int iy = lo3[1]; iy <= hi3[1]; ++iy) {
+        const int nyc = hi3[1] - lo3[1] + 1;
+        const int ncol = (hi3[0] - lo3[0] + 1) * nyc;
+        // columns of grid cells (z-runs are contiguous in grid order), G at a time
+        for (int c0 = 0; c0 < ncol; c0 += G) {
+            int cbeg = 0, cend = 0;
+            if (c0 + gl < ncol) {
+                const int ix = lo3[0] + (c0 + gl) / nyc, iy = lo3[1] + (c0 + gl) % nyc;
                 const int col = (ix * A.g.dim[1] + iy) * A.g.dim[2];
-                const int beg = A.cell_start[col + lo3[2]];
-                const int end = A.cell_start[col + hi3[2] + 1];
+                cbeg = A.cell_start[col + lo3[2]];
+                cend = A.cell_start[col + hi3[2] + 1];
+            }
+            const int cn = min(G, ncol - c0);
+            for (int cc = 0; cc < cn; ++cc) {
+                const int beg = __shfl(cbeg, (int)(threadIdx.x & (64 - G)) + cc, 64);
+                const int end = __shfl(cend, (int)(threadIdx.x & (64 - G)) + cc, 64);
                 for (int base = beg; base < end; base += G) {
                     const int j = base + gl;
                     bool keep = false, kill = false, neg = false;
@@ -234,11 +275,11 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                     if (keep) {
                         const int c = ncand + popc(b & below);
                         if (c < CMAX) {
-                            S.cand[c][0] = nx;
-                            S.cand[c][1] = ny;
-                            S.cand[c][2] = nz;
-                            S.cand[c][3] = t;
-                            S.cid[c] = j;
+                            D.cand[c][0] = nx;
+                            D.cand[c][1] = ny;
+                            D.cand[c][2] = nz;
+                            D.cand[c][3] = t;
+                            D.cid[c] = j;
                         }
                     }
                     ncand += popc(b);
@@ -262,11 +303,12 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 const int c = ncand + popc(b & below);
                 if (c < CMAX) {
                     const int ax = gl >> 1;
-                    S.cand[c][0] = ax == 0 ? ((gl & 1) ? R(1) : R(-1)) : R(0);
-                    S.cand[c][1] = ax == 1 ? ((gl & 1) ? R(1) : R(-1)) : R(0);
-                    S.cand[c][2] = ax == 2 ? ((gl & 1) ? R(1) : R(-1)) : R(0);
-                    S.cand[c][3] = t;
-                    S.cid[c] = -1 - gl;
+                    const R sg = (gl & 1) ? R(1) : R(-1);
+                    D.cand[c][0] = ax == 0 ? sg : R(0);
+                    D.cand[c][1] = ax == 1 ? sg : R(0);
+                    D.cand[c][2] = ax == 2 ? sg : R(0);
+                    D.cand[c][3] = t;
+                    D.cid[c] = -1 - gl;
                 }
             }
             ncand += popc(b);
@@ -281,39 +323,60 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     }
     __syncthreads();
 
-    // ---------------- order candidates by t (ties by id) ----------------
+    // ---------------- candidates in ascending t (ties by id); masks cleared ----------------
     if (live) {
         for (int c = gl; c < ncand; c += G) {
-            const R tc = S.cand[c][3];
-            const int ic = S.cid[c];
+            const R tc = D.cand[c][3];
+            const int ic = D.cid[c];
             int rank = 0;
             for (int c2 = 0; c2 < ncand; ++c2) {
-                const R t2 = S.cand[c2][3];
-                rank += (t2 < tc) || (t2 == tc && S.cid[c2] < ic);
+                const R t2 = D.cand[c2][3];
+                rank += (t2 < tc) || (t2 == tc && D.cid[c2] < ic);
             }
-            S.corder[rank] = (uint8_t)c;
-        }
-        // auxiliary cube p_i +- L (outside the ball, never a facet)
-        const R L = R(1.05) * r;
-        if (gl < 6) {
-            const int ax = gl >> 1;
-            const R sg = (gl & 1) ? R(1) : R(-1);
-            S.pl[gl][0] = ax == 0 ? sg : R(0);
-            S.pl[gl][1] = ax == 1 ? sg : R(0);
-            S.pl[gl][2] = ax == 2 ? sg : R(0);
-            S.pl[gl][3] = L;
-            S.pid[gl] = -7 - gl;
-        }
-        if (gl < 8) {
-            const int sx = (gl & 1) ? 1 : -1, sy = (gl & 2) ? 1 : -1, sz = (gl & 4) ? 1 : -1;
-            const int a = sx < 0 ? 0 : 1, b = sy < 0 ? 2 : 3, c = sz < 0 ? 4 : 5;
-            S.tri[gl] = (sx * sy * sz > 0) ? pack3(a, b, c) : pack3(a, c, b);
-            S.vp[gl][0] = sx * L;
-            S.vp[gl][1] = sy * L;
-            S.vp[gl][2] = sz * L;
+            rank = min(rank, CMAX - 1);
+            S.u.c.csort[rank][0] = D.cand[c][0];
+            S.u.c.csort[rank][1] = D.cand[c][1];
+            S.u.c.csort[rank][2] = D.cand[c][2];
+            S.u.c.csort[rank][3] = tc;
+            S.u.c.csid[rank] = ic;
         }
     }
-    int np = 6, ntri = 8, hw = 8, nface = 6;
+    __syncthreads();  // the discovery staging is dead from here on (the clip tables overlap it)
+    if (live) {
+        for (int p = gl; p < PMAX; p += G) {
+            KT.mout[p] = 0;
+            KT.min[p] = 0;
+        }
+    }
+    // auxiliary cube p_i +- L (outside the ball, never a facet); planes 0..5 = -x,+x,-y,+y,-z,+z
+    const R L = R(1.05) * r;
+    if (live && gl < 6) {
+        const int ax = gl >> 1;
+        const R sg = (gl & 1) ? R(1) : R(-1);
+        S.pl[gl][0] = ax == 0 ? sg : R(0);
+        S.pl[gl][1] = ax == 1 ? sg : R(0);
+        S.pl[gl][2] = ax == 2 ? sg : R(0);
+        S.pl[gl][3] = L;
+        S.pid[gl] = -7 - gl;
+    }
+    // vertex slots in registers; the cube's corners go to slots 0..7
+    uint32_t tri[NS];
+    R vx[NS], vy[NS], vz[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        tri[k] = TRI_INVALID;
+        vx[k] = vy[k] = vz[k] = R(0);
+        const int s = k * G + gl;
+        if (live && s < 8) {
+            const int sx = (s & 1) ? 1 : -1, sy = (s & 2) ? 1 : -1, sz = (s & 4) ? 1 : -1;
+            const int a = sx < 0 ? 0 : 1, b = sy < 0 ? 2 : 3, c = sz < 0 ? 4 : 5;
+            tri[k] = (sx * sy * sz > 0) ? pack3(a, b, c) : pack3(a, c, b);
+            vx[k] = sx * L;
+            vy[k] = sy * L;
+            vz[k] = sz * L;
+        }
+    }
+    int np = 6, ntri = 8, nface = 6;
     __syncthreads();
 
     // ---------------- clip by the candidates in ascending t ----------------
@@ -321,27 +384,19 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     for (int it = 0; it < maxc; ++it) {
         const bool go = live && it < ncand;
         R nx = 0, ny = 0, nz = 0, t = 0;
-        int cidx = 0;
         if (go) {
-            cidx = min((int)S.corder[it], CMAX - 1);
-            nx = S.cand[cidx][0];
-            ny = S.cand[cidx][1];
-            nz = S.cand[cidx][2];
-            t = S.cand[cidx][3];
+            nx = S.u.c.csort[it][0];
+            ny = S.u.c.csort[it][1];
+            nz = S.u.c.csort[it][2];
+            t = S.u.c.csort[it][3];
         }
+        // vertices beyond the plane
+        bool rem[NS];
         int nrem = 0;
-        if (go) {
-            for (int s = gl; s - gl < hw; s += G) {
-                bool out = false;
-                if (s < hw) {
-                    const uint32_t u = S.tri[s];
-                    if (u != TRI_INVALID) {
-                        out = dot3(nx, ny, nz, S.vp[s][0], S.vp[s][1], S.vp[s][2]) > t;
-                        if (out) S.tri[s] = u | TRI_REMOVED;
-                    }
-                }
-                nrem += popc(gballot<G>(out));
-            }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            rem[k] = go && tri[k] != TRI_INVALID && (nx * vx[k] + ny * vy[k] + nz * vz[k] > t);
+            nrem += popc(gballot<G>(rem[k]));
         }
         bool cut = go && nrem > 0;
         if (cut && nrem == ntri) {  // the half-space misses the polytope: empty cell
@@ -354,90 +409,74 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             live = false;
             cut = false;
         }
-        __syncthreads();
+        // edges of the removed triangles, per plane
         if (cut) {
-            for (int p = gl; p < np; p += G) {
-                S.u.c.mout[p] = 0;
-                S.u.c.min[p] = 0;
-                S.u.c.nxt[p] = 0xFF;
-                S.u.c.rslot[p] = 0;
-                S.u.c.kslot[p] = 0;
-            }
-        }
-        __syncthreads();
-        if (cut) {
-            for (int s = gl; s < hw; s += G) {
-                const uint32_t u = S.tri[s];
-                if (u != TRI_INVALID && (u & TRI_REMOVED)) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                if (rem[k]) {
+                    const uint32_t u = tri[k];
                     const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-                    atomicOr(&S.u.c.mout[a], (M)1 << b);
-                    atomicOr(&S.u.c.mout[b], (M)1 << c);
-                    atomicOr(&S.u.c.mout[c], (M)1 << a);
-                    atomicOr(&S.u.c.min[b], (M)1 << a);
-                    atomicOr(&S.u.c.min[c], (M)1 << b);
-                    atomicOr(&S.u.c.min[a], (M)1 << c);
+                    atomicOr(&KT.mout[a], (M)1 << b);
+                    atomicOr(&KT.mout[b], (M)1 << c);
+                    atomicOr(&KT.mout[c], (M)1 << a);
+                    atomicOr(&KT.min[b], (M)1 << a);
+                    atomicOr(&KT.min[c], (M)1 << b);
+                    atomicOr(&KT.min[a], (M)1 << c);
                 }
             }
         }
         __syncthreads();
+        // boundary of the cut: plane x with out \ in = {y}; masks are cleared for the next plane
         int nnew = 0, ninterior = 0;
         bool bad = false;
         if (cut) {
             for (int p = gl; p - gl < np; p += G) {
                 bool bnd = false, intr = false;
                 if (p < np) {
-                    const M mo = S.u.c.mout[p], mi = S.u.c.min[p];
+                    const M mo = KT.mout[p], mi = KT.min[p];
+                    KT.mout[p] = 0;
+                    KT.min[p] = 0;
                     const M e = mo & ~mi;
+                    uint8_t nx8 = 0xFF;
                     if (e) {
                         bnd = true;
                         bad = bad || popc(e) != 1 || popc((M)(mi & ~mo)) != 1;
-                        S.u.c.nxt[p] = (uint8_t)ctz_(e);
+                        nx8 = (uint8_t)ctz_(e);
                     } else if (mo) {
                         intr = true;
                     }
+                    KT.nxt[p] = nx8;
                 }
                 const unsigned long long b = gballot<G>(bnd);
-                if (bnd) S.u.c.newl[nnew + popc(b & below)] = (uint8_t)p;
+                if (bnd) KT.newl[nnew + popc(b & below)] = (uint8_t)p;
                 nnew += popc(b);
                 ninterior += popc(gballot<G>(intr));
             }
             bad = gballot<G>(bad) != 0;
         }
         __syncthreads();
+        // the two ends of every cut edge; removed slots are freed
         if (cut) {
-            for (int s = gl; s < hw; s += G) {
-                const uint32_t u = S.tri[s];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const uint32_t u = tri[k];
                 if (u == TRI_INVALID) continue;
                 const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-                if (u & TRI_REMOVED) {
-                    if (S.u.c.nxt[a] == b) S.u.c.rslot[a] = (uint8_t)s;
-                    if (S.u.c.nxt[b] == c) S.u.c.rslot[b] = (uint8_t)s;
-                    if (S.u.c.nxt[c] == a) S.u.c.rslot[c] = (uint8_t)s;
+                const int na = KT.nxt[a], nb = KT.nxt[b], nc = KT.nxt[c];
+                if (rem[k]) {
+                    if (na == b) { KT.rpos[a][0] = vx[k]; KT.rpos[a][1] = vy[k]; KT.rpos[a][2] = vz[k]; }
+                    if (nb == c) { KT.rpos[b][0] = vx[k]; KT.rpos[b][1] = vy[k]; KT.rpos[b][2] = vz[k]; }
+                    if (nc == a) { KT.rpos[c][0] = vx[k]; KT.rpos[c][1] = vy[k]; KT.rpos[c][2] = vz[k]; }
+                    tri[k] = TRI_INVALID;
                 } else {
-                    if (S.u.c.nxt[b] == a) S.u.c.kslot[b] = (uint8_t)s;
-                    if (S.u.c.nxt[c] == b) S.u.c.kslot[c] = (uint8_t)s;
-                    if (S.u.c.nxt[a] == c) S.u.c.kslot[a] = (uint8_t)s;
+                    if (nb == a) { KT.kpos[b][0] = vx[k]; KT.kpos[b][1] = vy[k]; KT.kpos[b][2] = vz[k]; }
+                    if (nc == b) { KT.kpos[c][0] = vx[k]; KT.kpos[c][1] = vy[k]; KT.kpos[c][2] = vz[k]; }
+                    if (na == c) { KT.kpos[a][0] = vx[k]; KT.kpos[a][1] = vy[k]; KT.kpos[a][2] = vz[k]; }
                 }
             }
         }
         __syncthreads();
-        // new vertices: on edge x∩nxt[x], between its kept and its removed end.
-        // All positions are read before any slot is reused (removed slots are free).
-        if (cut) {
-            for (int k = gl; k < nnew; k += G) {
-                const int p = S.u.c.newl[k];
-                const int ks = S.u.c.kslot[p], rs = S.u.c.rslot[p];
-                const R ax = S.vp[ks][0], ay = S.vp[ks][1], az = S.vp[ks][2];
-                const R bx = S.vp[rs][0], by = S.vp[rs][1], bz = S.vp[rs][2];
-                const R sa = dot3(nx, ny, nz, ax, ay, az) - t;
-                const R sb = dot3(nx, ny, nz, bx, by, bz) - t;
-                const R lam = (sb > sa) ? sa / (sa - sb) : R(0.5);
-                S.u.c.newpos[k][0] = ax + lam * (bx - ax);
-                S.u.c.newpos[k][1] = ay + lam * (by - ay);
-                S.u.c.newpos[k][2] = az + lam * (bz - az);
-            }
-        }
-        __syncthreads();
+        // new vertices (x, nxt[x], k) into free slots, in rank order
         if (cut) {
             const int knew = np;
             if (gl == 0) {
@@ -445,31 +484,29 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 S.pl[knew][1] = ny;
                 S.pl[knew][2] = nz;
                 S.pl[knew][3] = t;
-                S.pid[knew] = S.cid[cidx];
+                S.pid[knew] = S.u.c.csid[it];
             }
-            int fbase = 0, top = 0;
-            for (int j = 0; j * G < VMAX; ++j) {
-                const int s = j * G + gl;
-                const uint32_t u = (s < hw) ? S.tri[s] : TRI_INVALID;
-                const bool isfree = (u == TRI_INVALID) || (u & TRI_REMOVED);
+            int fbase = 0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const bool isfree = tri[k] == TRI_INVALID;
                 const unsigned long long b = gballot<G>(isfree);
                 const int frank = fbase + popc(b & below);
                 fbase += popc(b);
-                if (isfree) {
-                    if (frank < nnew) {
-                        const int p = S.u.c.newl[frank];
-                        const int q = S.u.c.nxt[p];
-                        S.vp[s][0] = S.u.c.newpos[frank][0];
-                        S.vp[s][1] = S.u.c.newpos[frank][1];
-                        S.vp[s][2] = S.u.c.newpos[frank][2];
-                        S.tri[s] = pack3(p, q, knew);
-                        top = s + 1;
-                    } else if (s < hw) {
-                        S.tri[s] = TRI_INVALID;
-                    }
+                if (isfree && frank < nnew) {
+                    const int p = KT.newl[frank];
+                    const int q = KT.nxt[p];
+                    const R ax = KT.kpos[p][0], ay = KT.kpos[p][1], az = KT.kpos[p][2];
+                    const R bx = KT.rpos[p][0], by = KT.rpos[p][1], bz = KT.rpos[p][2];
+                    const R sa = nx * ax + ny * ay + nz * az - t;
+                    const R sb = nx * bx + ny * by + nz * bz - t;
+                    const R lam = (sb > sa) ? sa * rcp_<R>(sa - sb) : R(0.5);
+                    vx[k] = ax + lam * (bx - ax);
+                    vy[k] = ay + lam * (by - ay);
+                    vz[k] = az + lam * (bz - az);
+                    tri[k] = pack3(p, q, knew);
                 }
             }
-            hw = max(hw, gmax<G>(top));
             if (fbase < nnew) {
                 flags |= CF_VERTS;
                 live = false;
@@ -482,25 +519,40 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 live = false;
             }
         }
-        __syncthreads();
     }
 
     // ---------------- restriction to the ball and integration ----------------
+    __syncthreads();
     if (live) {
-        for (int p = gl; p < np; p += G) S.u.g.fstart[p] = 0xFF;
+        for (int p = gl; p < np; p += G) GT.fstart[p] = 0xFFu;
     }
     __syncthreads();
     if (live) {
-        for (int s = gl; s < hw; s += G) {
-            const uint32_t u = S.tri[s];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const uint32_t u = tri[k];
+            if (u == TRI_INVALID) continue;
+            const int s = k * G + gl;
+            const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
+            GT.rec[s] = VRec<R>{vx[k], vy[k], vz[k], u};
+            GT.eslot[a][b] = (uint8_t)s;
+            GT.eslot[b][c] = (uint8_t)s;
+            GT.eslot[c][a] = (uint8_t)s;
+            atomicMin(&GT.fstart[a], (uint32_t)s);
+            atomicMin(&GT.fstart[b], (uint32_t)s);
+            atomicMin(&GT.fstart[c], (uint32_t)s);
+        }
+    }
+    __syncthreads();
+    // successor of vertex (a,b,c) counter-clockwise on face a is the vertex holding edge a->c
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const uint32_t u = tri[k];
             if (u == TRI_INVALID) continue;
             const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-            S.u.g.eslot[a][b] = (uint8_t)s;
-            S.u.g.eslot[b][c] = (uint8_t)s;
-            S.u.g.eslot[c][a] = (uint8_t)s;
-            S.u.g.fstart[a] = (uint8_t)s;
-            S.u.g.fstart[b] = (uint8_t)s;
-            S.u.g.fstart[c] = (uint8_t)s;
+            GT.succ[k * G + gl] = (uint32_t)GT.eslot[a][c] | ((uint32_t)GT.eslot[b][a] << 8) |
+                                     ((uint32_t)GT.eslot[c][b] << 16);
         }
     }
     __syncthreads();
@@ -510,39 +562,44 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         const R cone_den = R(1) / r;
         for (int p = gl; p < np; p += G) {
             R Af = 0, Of = 0;
-            const int s0 = S.u.g.fstart[p];
-            if (p >= 6 && s0 != 0xFF) {
+            const uint32_t s0 = GT.fstart[p];
+            if (p >= 6 && s0 < (uint32_t)VMAX) {
                 const R nx = S.pl[p][0], ny = S.pl[p][1], nz = S.pl[p][2], t = S.pl[p][3];
                 const R h = fabs(t);
                 const R rho2 = (r - t) * (r + t);
                 const R cone = R(1) - h * cone_den;
                 const R qx = t * nx, qy = t * ny, qz = t * nz;
-                int s = s0, steps = 0;
-                R ux = S.vp[s][0] - qx, uy = S.vp[s][1] - qy, uz = S.vp[s][2] - qz;
+                VRec<R> rc = GT.rec[s0];
+                uint32_t sc = GT.succ[s0];
+                R ux = rc.x - qx, uy = rc.y - qy, uz = rc.z - qz;
+                uint32_t s = s0;
+                int steps = 0;
                 do {
-                    const uint32_t u = S.tri[s];
+                    const uint32_t u = rc.t;
                     const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-                    const int third = (a == p) ? c : ((b == p) ? a : ((c == p) ? b : -1));
-                    if (third < 0 || u == TRI_INVALID) {
+                    const int rot = (a == p) ? 0 : ((b == p) ? 1 : ((c == p) ? 2 : -1));
+                    if (rot < 0) {
                         walk_bad = true;
                         break;
                     }
-                    const int sn = S.u.g.eslot[p][third];
-                    if (sn >= hw || ++steps > VMAX) {
+                    const uint32_t sn = (sc >> (8 * rot)) & 0xFF;
+                    if (sn >= (uint32_t)VMAX || ++steps > VMAX) {
                         walk_bad = true;
                         break;
                     }
-                    const R vx = S.vp[sn][0] - qx, vy = S.vp[sn][1] - qy, vz = S.vp[sn][2] - qz;
-                    fan_piece<R>(ux, uy, uz, vx, vy, vz, nx, ny, nz, rho2, h, cone, Af, Of);
-                    ux = vx;
-                    uy = vy;
-                    uz = vz;
+                    rc = GT.rec[sn];
+                    sc = GT.succ[sn];
+                    const R vx2 = rc.x - qx, vy2 = rc.y - qy, vz2 = rc.z - qz;
+                    fan_piece<R>(ux, uy, uz, vx2, vy2, vz2, nx, ny, nz, rho2, h, cone, Af, Of);
+                    ux = vx2;
+                    uy = vy2;
+                    uz = vz2;
                     s = sn;
                 } while (s != s0);
                 sum_tA += (double)t * (double)Af;
                 sum_om += (t >= R(0)) ? (double)Of : -(double)Of;
             }
-            S.u.g.farea[p] = Af;
+            GT.farea[p] = Af;
         }
         if (gballot<G>(walk_bad)) {
             flags |= CF_WALK;
@@ -563,7 +620,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             float a = 0.f;
             int id = -100;
             if (p < np && p >= 6) {
-                a = (float)S.u.g.farea[p];
+                a = (float)GT.farea[p];
                 id = S.pid[p];
                 isf = id >= 0 && a > 0.f;
                 if (id < 0 && o.wall) o.wall[cell * 6 + (-1 - id)] = a;
@@ -589,6 +646,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             const double rd = (double)r;
             K = rd * rd * (4.0 * PI_D * (inside ? 1.0 : 0.0) - sum_om);
             V = (sum_tA + rd * K) / 3.0;
+            if (!(V == V) || !(K == K)) flags |= CF_TOPO;
         }
         // a cell much smaller than its ball is a difference of large pyramid terms:
         // float32 would lose the relative accuracy, so it is redone in float64
@@ -629,7 +687,9 @@ __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
 void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm, const int32_t *cell_start,
                   GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc) {
     CellArgs a{n, pos_s, nullptr, perm, cell_start, g, box, rmax, out};
-    if (tpc == 32) {
+    if (tpc == 8) {
+        hipLaunchKernelGGL(k_cells_fast<8>, dim3((unsigned)((n + 7) / 8)), dim3(64), 0, st, a);
+    } else if (tpc == 32) {
         hipLaunchKernelGGL(k_cells_fast<32>, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, a);
     } else if (tpc == 64) {
         hipLaunchKernelGGL(k_cells_fast<64>, dim3((unsigned)n), dim3(64), 0, st, a);

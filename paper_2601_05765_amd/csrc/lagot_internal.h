@@ -92,15 +92,18 @@ void launch_hess_assemble(hipStream_t st, int64_t n, const float4 *pos_s, const 
                           int32_t *xcnt, double *diag, int32_t *err);
 void launch_hess_finish(hipStream_t st, int64_t n, const double *psi_s, const double *K, const int32_t *fcnt,
                         const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag);
-void launch_spmv_dot(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
-                     const double *diag, const double *p, double *q, double *partial, int nblk);
-void launch_reduce_sum(hipStream_t st, const double *partial, int nblk, int ncomp, double *out);
-void launch_pcg_init(hipStream_t st, int64_t n, const double *V, const double *nu, const double *diag, double *g,
-                     double *x, double *r, double *z, double *p, double *partial, int nblk);
-void launch_pcg_update(hipStream_t st, int64_t n, const double *scal, const double *diag, double *x, double *r,
-                       double *z, const double *p, const double *q, double *partial, int nblk);
-void launch_pcg_scalars(hipStream_t st, const double *partial, int nblk, int mode, double *scal);
-void launch_pcg_direction(hipStream_t st, int64_t n, const double *scal, const double *z, double *p);
+int pcg_blocks(int64_t n);
+int spmv_blocks(int64_t n);
+void launch_pcg_init(hipStream_t st, int64_t n, int nb, const double *V, const double *nu, const double *diag,
+                     double *g, double *x, double *r, double *z, double *RZ, double *RR, double *R0, int32_t *state);
+void launch_pcg_spmv(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const int32_t *hcol,
+                     const float *hval, const int32_t *hcnt, const double *diag, const double *z, const double *p_old,
+                     double *p_new, double *q, const double *RZ, const double *RR, double *PQ, const int32_t *state);
+void launch_pcg_update(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const double *diag,
+                       double *x, double *r, double *z, const double *p, const double *q, double *RZ, double *RR,
+                       const double *PQ, int32_t *state);
+void launch_pcg_status(hipStream_t st, int nb, const double *RR, const double *R0, const int32_t *state,
+                       double *scal);
 void launch_axpy_trial(hipStream_t st, int64_t n, const double *psi_s, const double *u, double alpha,
                        double *psi_trial, float4 *pos_s, double *rmax_partial);
 

@@ -11,6 +11,8 @@
 // Precision: facet areas and matrix values are float32; V, K, the diagonal,
 // every vector of the conjugate gradients, every inner product and every
 // reduction are float64, with fixed-order two-level reductions (deterministic).
+#include <algorithm>
+
 #include "lagot_internal.h"
 
 namespace lagot {
@@ -98,27 +100,32 @@ __global__ __launch_bounds__(1024) void k_eval_final(const double *partial, int 
 }
 
 // Row i of -Hess K: one entry per facet of cell i; a facet that cell j does not
-// list is appended to row j as well (union pattern).
+// list is appended to row j as well (union pattern). One thread per facet slot;
+// the partner row is read with 16-byte loads and searched in registers.
 __global__ void k_hess_assemble(int64_t n, const float4 *__restrict__ pos, const int32_t *__restrict__ fcol,
                                 const float *__restrict__ farea, const int32_t *__restrict__ fcnt,
                                 int32_t *__restrict__ hcol, float *__restrict__ hval, int32_t *__restrict__ xcnt,
                                 int32_t *__restrict__ err) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / 16;
+    const int f0 = (int)(t & 15);
     if (i >= n) return;
     const int ci = fcnt[i];
-    const float4 pi = pos[i];
-    for (int f = 0; f < ci; ++f) {
+    for (int f = f0; f < ci; f += 16) {
         const int j = fcol[i * FCAP + f];
         const float a = farea[i * FCAP + f];
         const int cj = fcnt[j];
-        float a2 = -1.f;
-        for (int f2 = 0; f2 < cj; ++f2) {
-            if (fcol[(int64_t)j * FCAP + f2] == (int32_t)i) {
-                a2 = farea[(int64_t)j * FCAP + f2];
-                break;
-            }
+        const int4 *rowj = reinterpret_cast<const int4 *>(fcol + (int64_t)j * FCAP);
+        int pos2 = -1;
+        for (int q = 0; q < (cj + 3) / 4 && pos2 < 0; ++q) {
+            const int4 v = rowj[q];
+            if (v.x == (int32_t)i && 4 * q + 0 < cj) pos2 = 4 * q + 0;
+            else if (v.y == (int32_t)i && 4 * q + 1 < cj) pos2 = 4 * q + 1;
+            else if (v.z == (int32_t)i && 4 * q + 2 < cj) pos2 = 4 * q + 2;
+            else if (v.w == (int32_t)i && 4 * q + 3 < cj) pos2 = 4 * q + 3;
         }
-        const float4 pj = pos[j];
+        const float a2 = pos2 >= 0 ? farea[(int64_t)j * FCAP + pos2] : -1.f;
+        const float4 pi = pos[i], pj = pos[j];
         const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
         const float d = sqrtf(dx * dx + dy * dy + dz * dz);
         const float abar = (a2 >= 0.f) ? 0.5f * (a + a2) : a;
@@ -152,47 +159,58 @@ __global__ void k_hess_finish(int64_t n, const double *__restrict__ psi, const d
     diag[i] = s;
 }
 
-// q = (D - W) p ; partial sums of p.q
-__global__ __launch_bounds__(RB) void k_spmv_dot(int64_t n, const int32_t *__restrict__ hcol,
-                                                  const float *__restrict__ hval, const int32_t *__restrict__ hcnt,
-                                                  const double *__restrict__ diag, const double *__restrict__ p,
-                                                  double *__restrict__ q, double *__restrict__ partial) {
-    __shared__ double sh[RB / 64];
-    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
-    double pq = 0.0;
-    if (i < n) {
-        const double pi = p[i];
-        double acc = diag[i] * pi;
-        const int c = hcnt[i];
-        for (int f = 0; f < c; ++f) acc -= (double)hval[i * FCAP + f] * p[hcol[i * FCAP + f]];
-        q[i] = acc;
-        pq = pi * acc;
-    }
-    pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = pq;
+
+
+// ---- Jacobi-PCG, two fused kernels per iteration -----------------------------
+// Every kernel runs a fixed grid of nb <= 512 blocks (grid-stride loops) and
+// leaves one partial per block. The scalars an iteration needs (alpha, beta, the
+// stop test) are recomputed by every block from the previous kernel's partials,
+// summed in block order: deterministic, with no atomics and no device fences
+// (a device-scope fence writes back the XCD's L2 on this part).
+// Partials: RZ[2][nb], RR[2][nb] (slot k%2 holds the residual of iteration k), PQ[nb].
+// state (int32): [0] iterations done, [1] breakdown, [2] converged.
+
+__device__ inline double sum_partials(const double *v, int nb, double *sh) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nb; k += RB) s += v[k];
+    return block_sum(s, sh);
 }
 
-__global__ __launch_bounds__(1024) void k_reduce_sum(const double *partial, int nb, int ncomp, double *out) {
-    __shared__ double sh[16];
-    for (int c = 0; c < ncomp; ++c) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += 1024) s += partial[c * nb + b];
-        s = block_sum(s, sh);
-        if (threadIdx.x == 0) out[c] = s;
-        __syncthreads();
+// Four block-ordered sums in one pass and one block reduction (lanes fold in a fixed order).
+__device__ inline void sum_partials4(const double *a, const double *b, const double *c, const double *d, int na,
+                                     int nd, double *out, double (*sh)[4]) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < na; k += RB) {
+        s[0] += a[k];
+        s[1] += b[k];
+        s[2] += c[k];
+    }
+    for (int k = threadIdx.x; k < nd; k += RB) s[3] += d[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int o = 32; o > 0; o >>= 1) s[q] += __shfl_xor(s[q], o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 4; ++q) sh[w][q] = s[q];
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+        double t = 0.0;
+        for (int k = 0; k < RB / 64; ++k) t += sh[k][q];
+        out[q] = t;
     }
 }
 
-// g = nu - V (0 on empty rows), x = 0, r = g, z = r / D, p = z ; partials of r.z and r.r
-__global__ __launch_bounds__(RB) void k_pcg_init(int64_t n, const double *__restrict__ V,
+// g = nu - V (0 on empty rows), x = 0, r = g, z = r / D ; partials of r.z, r.r into slot 0
+__global__ __launch_bounds__(RB) void k_pcg_init(int64_t n, int nb, const double *__restrict__ V,
                                                   const double *__restrict__ nu, const double *__restrict__ diag,
                                                   double *__restrict__ g, double *__restrict__ x,
                                                   double *__restrict__ r, double *__restrict__ z,
-                                                  double *__restrict__ p, double *__restrict__ partial) {
+                                                  double *__restrict__ RZ, double *__restrict__ RR,
+                                                  double *__restrict__ R0, int32_t *__restrict__ state) {
     __shared__ double sh[RB / 64];
-    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
     double rz = 0.0, rr = 0.0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nb * RB) {
         const double d = diag[i];
         const double gi = d > 0.0 ? nu[i] - V[i] : 0.0;
         const double zi = d > 0.0 ? gi / d : 0.0;
@@ -200,85 +218,125 @@ __global__ __launch_bounds__(RB) void k_pcg_init(int64_t n, const double *__rest
         x[i] = 0.0;
         r[i] = gi;
         z[i] = zi;
-        p[i] = zi;
-        rz = gi * zi;
-        rr = gi * gi;
+        rz += gi * zi;
+        rr += gi * gi;
     }
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        partial[blockIdx.x] = rz;
-        partial[gridDim.x + blockIdx.x] = rr;
+        RZ[blockIdx.x] = rz;
+        RR[blockIdx.x] = rr;
+        R0[blockIdx.x] = rr;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        state[0] = 0;
+        state[1] = 0;
+        state[2] = 0;
     }
 }
 
-// scal: [0] rz  [1] rr  [2] pq  [3] alpha  [4] beta  [5] breakdown flag
-// x += alpha p ; r -= alpha q ; z = r / D ; partials of r.z, r.r
-__global__ __launch_bounds__(RB) void k_pcg_update(int64_t n, const double *__restrict__ scal,
+// p_k = z + beta p_{k-1} (p_0 = z); q = (D - W) p_k; one partial of p.q per block.
+// Four lanes per row (rows hold ~6-20 facets), one row per lane quad, no grid stride:
+// the gathers of a row are issued together and every row is in flight at once.
+constexpr int SPMV_LANES = 4;
+constexpr int SPMV_ROWS = RB / SPMV_LANES;
+
+__global__ __launch_bounds__(RB) void k_pcg_spmv(int64_t n, int k, int nb, double rtol2, const double *__restrict__ R0,
+                                                  const int32_t *__restrict__ hcol, const float *__restrict__ hval,
+                                                  const int32_t *__restrict__ hcnt, const double *__restrict__ diag,
+                                                  const double *__restrict__ z, const double *__restrict__ p_old,
+                                                  double *__restrict__ p_new, double *__restrict__ q,
+                                                  const double *__restrict__ RZ, const double *__restrict__ RR,
+                                                  double *__restrict__ PQ, const int32_t *__restrict__ state) {
+    __shared__ double sh[RB / 64];
+    __shared__ double sh4[RB / 64][4];
+    if (state[1] != 0) return;
+    double S4[4];
+    sum_partials4(R0, RR + (k & 1) * nb, RZ + (k & 1) * nb, RZ + ((k + 1) & 1) * nb, nb, k > 0 ? nb : 0, S4, sh4);
+    const double stop = rtol2 * S4[0], rr = S4[1], rz = S4[2], rz_old = S4[3];
+    if (rr <= stop) return;
+    const double beta = (k > 0 && rz_old > 0.0) ? rz / rz_old : 0.0;
+    const int l = threadIdx.x & (SPMV_LANES - 1);
+    const int64_t row = (int64_t)blockIdx.x * SPMV_ROWS + (threadIdx.x / SPMV_LANES);
+    double acc = 0.0, pq = 0.0;
+    if (row < n) {
+        const int c = hcnt[row];
+        const int32_t *cr = hcol + row * FCAP;
+        const float *vr = hval + row * FCAP;
+#pragma unroll 4
+        for (int f = l; f < c; f += SPMV_LANES) {
+            const int j = cr[f];
+            const double pj = k == 0 ? z[j] : z[j] + beta * p_old[j];
+            acc += (double)vr[f] * pj;
+        }
+    }
+#pragma unroll
+    for (int o = SPMV_LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SPMV_LANES);
+    if (row < n && l == 0) {
+        const double pi = k == 0 ? z[row] : z[row] + beta * p_old[row];
+        const double qi = diag[row] * pi - acc;
+        p_new[row] = pi;
+        q[row] = qi;
+        pq = pi * qi;
+    }
+    pq = block_sum(pq, sh);
+    if (threadIdx.x == 0) PQ[blockIdx.x] = pq;
+}
+
+// alpha = rz / (p.q); x += alpha p; r -= alpha q; z = r / D; partials of r.z, r.r into slot (k+1)%2
+__global__ __launch_bounds__(RB) void k_pcg_update(int64_t n, int k, int nb, int npq, double rtol2,
+                                                    const double *__restrict__ R0,
                                                     const double *__restrict__ diag, double *__restrict__ x,
                                                     double *__restrict__ r, double *__restrict__ z,
                                                     const double *__restrict__ p, const double *__restrict__ q,
-                                                    double *__restrict__ partial) {
+                                                    double *__restrict__ RZ, double *__restrict__ RR,
+                                                    const double *__restrict__ PQ, int32_t *__restrict__ state) {
     __shared__ double sh[RB / 64];
-    const double alpha = scal[3];
-    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (i < n) {
+    __shared__ double sh4[RB / 64][4];
+    if (state[1] != 0) return;
+    double S4[4];
+    sum_partials4(R0, RR + (k & 1) * nb, RZ + (k & 1) * nb, PQ, nb, npq, S4, sh4);
+    const double stop = rtol2 * S4[0], rr = S4[1], rz = S4[2], pq = S4[3];
+    if (rr <= stop) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) state[2] = 1;
+        return;
+    }
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) state[1] = 1;
+        return;
+    }
+    const double alpha = rz / pq;
+    double rzn = 0.0, rrn = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nb * RB) {
         const double d = diag[i];
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
         const double zi = d > 0.0 ? ri / d : 0.0;
         z[i] = zi;
-        rz = ri * zi;
-        rr = ri * ri;
+        rzn += ri * zi;
+        rrn += ri * ri;
     }
-    rz = block_sum(rz, sh);
-    rr = block_sum(rr, sh);
+    rzn = block_sum(rzn, sh);
+    rrn = block_sum(rrn, sh);
     if (threadIdx.x == 0) {
-        partial[blockIdx.x] = rz;
-        partial[gridDim.x + blockIdx.x] = rr;
+        RZ[((k + 1) & 1) * nb + blockIdx.x] = rzn;
+        RR[((k + 1) & 1) * nb + blockIdx.x] = rrn;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) state[0] = k + 1;
 }
 
-// mode 0: pq partials -> scal[2], alpha = rz / pq -> scal[3]
-// mode 1: (rz_new, rr_new) partials -> beta = rz_new / rz -> scal[4], scal[0] = rz_new, scal[1] = rr_new
-// mode 2: (rz, rr) partials of the initial residual -> scal[0], scal[1]
-__global__ __launch_bounds__(1024) void k_pcg_scalars(const double *partial, int nb, int mode, double *scal) {
-    __shared__ double sh[16];
-    double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nb; k += 1024) {
-        a += partial[k];
-        if (mode != 0) b += partial[nb + k];
-    }
-    a = block_sum(a, sh);
-    b = block_sum(b, sh);
+// Residual of the latest iterate into scal: [0] r.r, [1] r0.r0
+__global__ __launch_bounds__(RB) void k_pcg_status(int nb, const double *__restrict__ RR, const double *__restrict__ R0,
+                                                    const int32_t *__restrict__ state, double *__restrict__ scal) {
+    __shared__ double sh[RB / 64];
+    const int it = state[0];
+    const double rr = sum_partials(RR + (it & 1) * nb, nb, sh);
+    const double r0 = sum_partials(R0, nb, sh);
     if (threadIdx.x == 0) {
-        if (mode == 0) {
-            scal[2] = a;
-            if (!(a > 0.0)) {
-                scal[5] = 1.0;
-                scal[3] = 0.0;
-            } else {
-                scal[3] = scal[0] / a;
-            }
-        } else if (mode == 1) {
-            scal[4] = scal[0] > 0.0 ? a / scal[0] : 0.0;
-            scal[0] = a;
-            scal[1] = b;
-        } else {
-            scal[0] = a;
-            scal[1] = b;
-            scal[5] = 0.0;
-        }
+        scal[0] = rr;
+        scal[1] = r0;
     }
-}
-
-__global__ void k_pcg_direction(int64_t n, const double *__restrict__ scal, const double *__restrict__ z,
-                                double *__restrict__ p) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    p[i] = z[i] + scal[4] * p[i];
 }
 
 __global__ void k_axpy_trial(int64_t n, const double *__restrict__ psi, const double *__restrict__ u, double alpha,
@@ -315,8 +373,8 @@ void launch_hess_assemble(hipStream_t st, int64_t n, const float4 *pos_s, const 
     (void)K;
     (void)diag;
     (void)hipMemsetAsync(xcnt, 0, sizeof(int32_t) * (size_t)n, st);
-    hipLaunchKernelGGL(k_hess_assemble, dim3(nblocks(n, 128)), dim3(128), 0, st, n, pos_s, fcol, farea, fcnt, hcol,
-                       hval, xcnt, err);
+    hipLaunchKernelGGL(k_hess_assemble, dim3(nblocks(n * 16, 256)), dim3(256), 0, st, n, pos_s, fcol, farea, fcnt,
+                       hcol, hval, xcnt, err);
 }
 
 void launch_hess_finish(hipStream_t st, int64_t n, const double *psi_s, const double *K, const int32_t *fcnt,
@@ -325,31 +383,31 @@ void launch_hess_finish(hipStream_t st, int64_t n, const double *psi_s, const do
                        diag);
 }
 
-void launch_spmv_dot(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
-                     const double *diag, const double *p, double *q, double *partial, int nblk) {
-    hipLaunchKernelGGL(k_spmv_dot, dim3(nblk), dim3(RB), 0, st, n, hcol, hval, hcnt, diag, p, q, partial);
+int pcg_blocks(int64_t n) { return (int)std::min<int64_t>(512, std::max<int64_t>(1, (n + RB - 1) / RB)); }
+int spmv_blocks(int64_t n) { return (int)((n + SPMV_ROWS - 1) / SPMV_ROWS); }
+
+void launch_pcg_init(hipStream_t st, int64_t n, int nb, const double *V, const double *nu, const double *diag,
+                     double *g, double *x, double *r, double *z, double *RZ, double *RR, double *R0, int32_t *state) {
+    hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(RB), 0, st, n, nb, V, nu, diag, g, x, r, z, RZ, RR, R0, state);
 }
 
-void launch_reduce_sum(hipStream_t st, const double *partial, int nblk, int ncomp, double *out) {
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(1024), 0, st, partial, nblk, ncomp, out);
+void launch_pcg_spmv(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const int32_t *hcol,
+                     const float *hval, const int32_t *hcnt, const double *diag, const double *z, const double *p_old,
+                     double *p_new, double *q, const double *RZ, const double *RR, double *PQ, const int32_t *state) {
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(spmv_blocks(n)), dim3(RB), 0, st, n, k, nb, rtol2, R0, hcol, hval, hcnt, diag, z, p_old, p_new,
+                       q, RZ, RR, PQ, state);
 }
 
-void launch_pcg_init(hipStream_t st, int64_t n, const double *V, const double *nu, const double *diag, double *g,
-                     double *x, double *r, double *z, double *p, double *partial, int nblk) {
-    hipLaunchKernelGGL(k_pcg_init, dim3(nblk), dim3(RB), 0, st, n, V, nu, diag, g, x, r, z, p, partial);
+void launch_pcg_update(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const double *diag,
+                       double *x, double *r, double *z, const double *p, const double *q, double *RZ, double *RR,
+                       const double *PQ, int32_t *state) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(RB), 0, st, n, k, nb, spmv_blocks(n), rtol2, R0, diag, x, r, z, p, q, RZ, RR, PQ,
+                       state);
 }
 
-void launch_pcg_update(hipStream_t st, int64_t n, const double *scal, const double *diag, double *x, double *r,
-                       double *z, const double *p, const double *q, double *partial, int nblk) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(nblk), dim3(RB), 0, st, n, scal, diag, x, r, z, p, q, partial);
-}
-
-void launch_pcg_scalars(hipStream_t st, const double *partial, int nblk, int mode, double *scal) {
-    hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(1024), 0, st, partial, nblk, mode, scal);
-}
-
-void launch_pcg_direction(hipStream_t st, int64_t n, const double *scal, const double *z, double *p) {
-    hipLaunchKernelGGL(k_pcg_direction, dim3(nblocks(n, 256)), dim3(256), 0, st, n, scal, z, p);
+void launch_pcg_status(hipStream_t st, int nb, const double *RR, const double *R0, const int32_t *state,
+                       double *scal) {
+    hipLaunchKernelGGL(k_pcg_status, dim3(1), dim3(RB), 0, st, nb, RR, R0, state, scal);
 }
 
 void launch_axpy_trial(hipStream_t st, int64_t n, const double *psi_s, const double *u, double alpha,

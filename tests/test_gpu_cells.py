@@ -102,6 +102,18 @@ def test_slab_1k_all_cells(ctx, oracle_mod):
     assert out["nnz"] <= int(orc.fcount.sum()) + 10
 
 
+@pytest.mark.parametrize("tpc", [8, 32, 64])
+def test_slab_1k_lanes_per_cell(ctx, oracle_mod, tpc):
+    _say(f"case: slab_uniform 1k, {tpc} lanes per cell")
+    sc = scenes.slab_uniform(1000, 3)
+    ctx.set_threads_per_cell(tpc)
+    try:
+        out, orc = _run(ctx, oracle_mod, sc.x, sc.y, sc.z, sc.psi0)
+    finally:
+        ctx.set_threads_per_cell(32)
+    assert_close(compare(out, orc, sc.psi0))
+
+
 def test_slab_1k_perturbed_weights(ctx, oracle_mod):
     _say("case: slab_uniform 1k, perturbed weights")
     sc = scenes.slab_uniform(1000, 1)

@@ -53,7 +53,7 @@ def test_solve_slab_1k(ctx, oracle_mod):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("tpc", [16, 32, 64])
+@pytest.mark.parametrize("tpc", [8, 16, 32, 64])
 def test_solve_threads_per_cell(ctx, oracle_mod, tpc):
     _say(f"case: solve slab_uniform 1k seed 2, threads_per_cell={tpc}")
     import paper_2601_05765_amd as L
