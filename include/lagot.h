@@ -63,7 +63,10 @@ typedef struct {
     int threads_per_cell;/* lanes per cell in the cell kernel: 0 = the context's default, else 8, 16,
                             32 or 64                                                             */
     int verbose;         /* 1: print one line per Newton iteration to stderr                        */
-    int reserved[5];
+    int use_learned;     /* 1: try the learned warm start (lagot_mlp_set_params) before Newton       */
+    int empty_start_fallback; /* 1 (default): if a start cell is empty (KMT needs eps0 > 0),
+                            restart from the default weights psi_i = (1.2 (3 nu_i / 4 pi)^(1/3))^2 */
+    int reserved[3];
 } lagot_opts;
 
 typedef struct {
@@ -75,6 +78,8 @@ typedef struct {
     int fallback_cells;  /* cells redone on the large-capacity float64 path (all evals)    */
     int failed_cells;    /* cells that exceeded even the large-capacity path (last eval)   */
     int cell_launches;   /* launches of the float32 cell kernel (one per evaluation)      */
+    int learned_accepted;/* 1 if the learned guess replaced the start weights             */
+    int default_start;   /* 1 if an empty start cell forced the default start weights     */
     double max_rel_err;  /* max_i |V_i - nu_i| / nu_i at the returned weights              */
     double grad_norm;    /* || nu - V ||_2 at the returned weights                         */
     double ms_total;     /* wall time of the call (host clock, stream synchronised)       */
@@ -82,7 +87,8 @@ typedef struct {
     double ms_linear;    /* of which Hessian assembly and PCG (host clock)                 */
     double ms_cell_kernel; /* summed duration of the float32 cell-kernel launches (HIP events
                               on the context stream)                                        */
-    double reserved_d[2];
+    double ms_learned;   /* of which the learned warm start (features, network, its check) */
+    double reserved_d[1];
 } lagot_stats;
 
 /* Fill *opts with the defaults listed above. */
@@ -139,6 +145,51 @@ int lagot_newton_step(lagot_ctx *ctx, int64_t n, const float *x, const float *y,
  */
 int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
                 lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats);
+
+/*
+ * Learned warm start (not part of the paper's method; its guess only replaces the
+ * start weights of lagot_solve when opts->use_learned is set, every cell of the guess
+ * has positive volume and ||nu - V||_2 is smaller than at the given start; Newton then
+ * runs to tolerance as usual).
+ * Inputs of site i (64 bf16, row-major n x 64): offsets (p_j - p_i)/s_i of its 16 nearest
+ * sites in ascending (distance, index), psi_prev_i / s_i^2, nu_i / mean(nu), and the
+ * relative volume mismatch (nu - V)/nu under the previous weights of site i and of its
+ * 13 nearest sites; s_i = nu_i^(1/3). Network 64 -> 128 -> 128 -> 128 -> 1 with GELU (erf form), output
+ * (psi_new_i - psi_prev_i) / s_i^2. Parameters: LAGOT_MLP_NPARAMS float32 laid out as
+ * W1[64][128], b1[128], W2[128][128], b2[128], W3[128][128], b3[128], w4[128], b4[1]
+ * (row-major, input index first). Products run in bf16 on MFMA with float32 accumulation.
+ */
+#define LAGOT_MLP_NPARAMS 41473
+
+/* Load float32 parameters (device pointer, LAGOT_MLP_NPARAMS values) into the context
+ * and reset the Adam state. Errors: EINVAL, EHIP. */
+int lagot_mlp_set_params(lagot_ctx *ctx, const float *params);
+
+/* Copy the context's float32 parameters to `params` (device). EINVAL if none are set. */
+int lagot_mlp_get_params(lagot_ctx *ctx, float *params);
+
+/* The 16 nearest sites (caller indices, int32 [n x 16], may be NULL) and the network
+ * inputs (bf16 as uint16 [n x 64], may be NULL) of every site, in caller order, from
+ * positions, previous weights psi_prev [n] float64 and volumes nu [n] float64 (the
+ * cells are evaluated at psi_prev for the mismatch inputs).
+ * Errors: EINVAL, ECAPACITY (fewer than 17 sites), EHIP. */
+int lagot_features(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *psi_prev,
+                   const double *nu, lagot_box box, int32_t *nbr, uint16_t *feats);
+
+/* Network output for m input rows (bf16 [m x 64], device) into out [m] float32.
+ * Synchronises the stream. Errors: EINVAL (no parameters), EHIP. */
+int lagot_mlp_forward(lagot_ctx *ctx, int64_t m, const uint16_t *feats, float *out);
+
+/* One Adam step (lr; beta 0.9, 0.999; eps 1e-8) on the mean squared error of the rows
+ * batch_idx[0..batch) (device int32) of feats [nrows x 64] against targets [nrows]
+ * (float32, device). *loss (HOST, may be NULL) receives the batch loss before the
+ * step (the call then synchronises). Errors: EINVAL, EHIP. */
+int lagot_mlp_train_step(lagot_ctx *ctx, int64_t nrows, const uint16_t *feats, const float *targets,
+                         const int32_t *batch_idx, int32_t batch, float lr, float *loss);
+
+/* Gradient of the last lagot_mlp_train_step's batch loss with respect to the parameters
+ * (device float32 [LAGOT_MLP_NPARAMS]; diagnostic). */
+int lagot_mlp_last_grads(lagot_ctx *ctx, float *grads);
 
 /* Lanes per cell (8, 16, 32 or 64) used by lagot_cells and by solves whose options leave
  * threads_per_cell at 0 (default 32). Returns LAGOT_EINVAL for other values. */

@@ -1,11 +1,13 @@
 """FP64 reference of the learned warm start (TEST INFRASTRUCTURE ONLY).
 
 The warm start predicts each site's weight increment for the next solve from its
-local neighbourhood. Inputs per site i (50 values, zero-padded to 64):
+local neighbourhood. Inputs per site i (64 values):
   * the offsets (p_j - p_i) / s_i of its 16 nearest sites j (ascending
     (distance, index)), s_i = nu_i^(1/3)                                 -> 48
   * psi_prev_i / s_i^2                                                    -> 1
   * nu_i / mean(nu)                                                       -> 1
+  * (nu - V) / nu under the previous weights, of site i and of its 13
+    nearest sites (V: the cells at the current positions, weights psi_prev) -> 14
 Network: 64 -> 128 -> 128 -> 128 -> 1, GELU (erf form) after each hidden layer,
 linear output = (psi_new_i - psi_prev_i) / s_i^2.
 Training: mean squared error, Adam (beta1 0.9, beta2 0.999, eps 1e-8).
@@ -34,8 +36,10 @@ def knn(P: np.ndarray, k: int = N_NEI, idx=None) -> np.ndarray:
     return out
 
 
-def features(P: np.ndarray, psi_prev: np.ndarray, nu: np.ndarray, nbr: np.ndarray, idx=None) -> np.ndarray:
-    """The 64 inputs of each site (rows follow idx, default all sites)."""
+def features(P: np.ndarray, psi_prev: np.ndarray, nu: np.ndarray, nbr: np.ndarray, V: np.ndarray,
+             idx=None) -> np.ndarray:
+    """The 64 inputs of each site (rows follow idx, default all sites); V = volumes of all
+    cells at the current positions under psi_prev."""
     n = P.shape[0]
     idx = np.arange(n) if idx is None else np.asarray(idx)
     s = np.cbrt(nu[idx])
@@ -44,6 +48,9 @@ def features(P: np.ndarray, psi_prev: np.ndarray, nu: np.ndarray, nbr: np.ndarra
     X[:, :3 * N_NEI] = off.reshape(len(idx), 3 * N_NEI)
     X[:, 3 * N_NEI] = psi_prev[idx] / s ** 2
     X[:, 3 * N_NEI + 1] = nu[idx] / nu.mean()
+    res = (nu - V) / nu
+    X[:, 50] = res[idx]
+    X[:, 51:64] = res[nbr[:, :13]]
     return X
 
 

@@ -22,7 +22,9 @@ OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
            "lagot_set_threads_per_cell", "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms",
-           "lagot_strerror"]
+           "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
+           "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
+MLP_NPARAMS = 41473
 
 
 class Box(ctypes.Structure):
@@ -32,15 +34,18 @@ class Box(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_newton", ctypes.c_int), ("max_halvings", ctypes.c_int),
                 ("cg_rtol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("threads_per_cell", ctypes.c_int),
-                ("verbose", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("verbose", ctypes.c_int), ("use_learned", ctypes.c_int), ("empty_start_fallback", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int), ("evals", ctypes.c_int),
                 ("halvings", ctypes.c_int), ("cg_iters", ctypes.c_int), ("fallback_cells", ctypes.c_int),
-                ("failed_cells", ctypes.c_int), ("cell_launches", ctypes.c_int), ("max_rel_err", ctypes.c_double),
-                ("grad_norm", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_eval", ctypes.c_double),
-                ("ms_linear", ctypes.c_double), ("ms_cell_kernel", ctypes.c_double), ("reserved_d", ctypes.c_double * 2)]
+                ("failed_cells", ctypes.c_int), ("cell_launches", ctypes.c_int), ("learned_accepted", ctypes.c_int),
+                ("default_start", ctypes.c_int), ("max_rel_err", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("ms_eval", ctypes.c_double), ("ms_linear", ctypes.c_double),
+                ("ms_cell_kernel", ctypes.c_double), ("ms_learned", ctypes.c_double),
+                ("reserved_d", ctypes.c_double * 1)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
@@ -72,6 +77,16 @@ def load():
             f = getattr(lib, name)
             f.argtypes = [P, I64, P, P, P, P, Box, P, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
             f.restype = I
+        lib.lagot_mlp_set_params.argtypes = [P, P]
+        lib.lagot_mlp_get_params.argtypes = [P, P]
+        lib.lagot_mlp_last_grads.argtypes = [P, P]
+        lib.lagot_features.argtypes = [P, I64, P, P, P, P, P, Box, P, P]
+        lib.lagot_mlp_forward.argtypes = [P, I64, P, P]
+        lib.lagot_mlp_train_step.argtypes = [P, I64, P, P, P, ctypes.c_int32, ctypes.c_float,
+                                             ctypes.POINTER(ctypes.c_float)]
+        for f in ("lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_mlp_last_grads", "lagot_features",
+                  "lagot_mlp_forward", "lagot_mlp_train_step"):
+            getattr(lib, f).restype = I
         lib.lagot_set_threads_per_cell.argtypes = [P, I]
         lib.lagot_set_threads_per_cell.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
@@ -189,6 +204,64 @@ class Context:
         rc = load().lagot_set_threads_per_cell(self._h, int(tpc))
         if rc != OK:
             raise LagotError(rc, "lagot_set_threads_per_cell")
+
+    # ---- learned warm start ----
+    def mlp_set_params(self, params):
+        import torch
+        rc = load().lagot_mlp_set_params(self._h, _dev(params, torch.float32, "params"))
+        if rc != OK:
+            raise LagotError(rc, "lagot_mlp_set_params")
+
+    def mlp_get_params(self):
+        import torch
+        out = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=f"cuda:{self.device}")
+        rc = load().lagot_mlp_get_params(self._h, ctypes.c_void_p(out.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_mlp_get_params")
+        return out
+
+    def mlp_last_grads(self):
+        import torch
+        out = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=f"cuda:{self.device}")
+        rc = load().lagot_mlp_last_grads(self._h, ctypes.c_void_p(out.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_mlp_last_grads")
+        return out
+
+    def features(self, x, y, z, psi_prev, nu, box=((0, 0, 0), (1, 1, 1)), want_nbr: bool = True):
+        """lagot_features: (nbr int32 [n,16] caller indices, inputs bf16-as-int16 [n,64])."""
+        import torch
+        n = x.shape[0]
+        nbr = torch.empty((n, 16), dtype=torch.int32, device=x.device) if want_nbr else None
+        feats = torch.empty((n, 64), dtype=torch.int16, device=x.device)
+        rc = load().lagot_features(self._h, n, _dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"),
+                                   _dev(z, torch.float32, "z"), _dev(psi_prev, torch.float64, "psi_prev"),
+                                   _dev(nu, torch.float64, "nu"), make_box(box),
+                                   ctypes.c_void_p(nbr.data_ptr()) if nbr is not None else None,
+                                   ctypes.c_void_p(feats.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_features")
+        return nbr, feats
+
+    def mlp_forward(self, feats):
+        import torch
+        out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        rc = load().lagot_mlp_forward(self._h, feats.shape[0], _dev(feats, torch.int16, "feats"),
+                                      ctypes.c_void_p(out.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_mlp_forward")
+        return out
+
+    def mlp_train_step(self, feats, targets, batch_idx, lr: float, want_loss: bool = True):
+        import torch
+        loss = ctypes.c_float(0.0)
+        rc = load().lagot_mlp_train_step(self._h, feats.shape[0], _dev(feats, torch.int16, "feats"),
+                                         _dev(targets, torch.float32, "targets"),
+                                         _dev(batch_idx, torch.int32, "batch_idx"), batch_idx.shape[0],
+                                         float(lr), ctypes.byref(loss) if want_loss else None)
+        if rc != OK:
+            raise LagotError(rc, "lagot_mlp_train_step")
+        return float(loss.value) if want_loss else None
 
     def last_fallback_cells(self) -> int:
         return int(load().lagot_last_fallback_cells(self._h))

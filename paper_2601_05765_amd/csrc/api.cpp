@@ -70,6 +70,22 @@ struct lagot_ctx {
     // statistics of the current call
     int fb_total = 0;
     int last_fb = 0;
+    // learned warm start: float32 master parameters, bf16 copy, Adam moments
+    float *mlp_p = nullptr, *mlp_g = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr;
+    uint16_t *mlp_pb = nullptr;
+    int mlp_t = 0;
+    bool mlp_set = false;
+    double *nusum = nullptr;
+    int32_t *nbr_s = nullptr;        // [n*16] grid order (caller indices)
+    uint16_t *feat_s = nullptr;      // [n*64] bf16 inputs, grid order
+    uint16_t *inf_a = nullptr, *inf_b = nullptr;  // [n*128] bf16 hidden activations
+    float *mlp_out = nullptr;        // [n]
+    int64_t cap_inf = 0;
+    // training workspace (batch rows)
+    int cap_batch = 0;
+    uint16_t *tX = nullptr, *tH1 = nullptr, *tH2 = nullptr, *tH3 = nullptr, *tdZb = nullptr;
+    float *tZ1 = nullptr, *tZ2 = nullptr, *tZ3 = nullptr, *tdZ = nullptr, *ty = nullptr, *tt = nullptr,
+          *tdy = nullptr, *tpart = nullptr, *tloss = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the float32 cell kernel
     bool ev_pending = false;
     double ms_cell = 0.0;
@@ -97,6 +113,11 @@ void free_all(lagot_ctx *c) {
         if (b) (void)hipFree(b);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    void *mbufs[] = {c->mlp_p, c->mlp_g, c->mlp_m1, c->mlp_m2, c->mlp_pb, c->nusum, c->nbr_s, c->feat_s, c->inf_a,
+                     c->inf_b, c->mlp_out, c->tX, c->tH1, c->tH2, c->tH3, c->tdZb, c->tZ1, c->tZ2, c->tZ3, c->tdZ,
+                     c->ty, c->tt, c->tdy, c->tpart, c->tloss};
+    for (void *b : mbufs)
+        if (b) (void)hipFree(b);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
@@ -255,7 +276,7 @@ void evaluate(lagot_ctx *c, int64_t n, const lagot_box &box, bool walls) {
     EvalOut o{c->V, c->K, walls ? c->wall : nullptr, c->fcol, c->farea, c->fcnt, c->flags, c->fb_list,
               c->counters + 0, c->counters + 1};
     (void)hipEventRecord(c->ev0, c->stream);
-    launch_cells(c->stream, n, c->pos_s, c->perm, c->cell_start, c->grid, bf, c->rmax, o, c->tpc);
+    launch_cells(c->stream, n, c->pos_s, c->psi_s, c->perm, c->cell_start, c->grid, bf, c->rmax, o, c->tpc);
     (void)hipEventRecord(c->ev1, c->stream);
     c->ev_pending = true;
     launch_cells_fallback(c->stream, n, c->pos_s, c->psi_s, c->perm, c->cell_start, c->grid, bf, c->rmax, o);
@@ -328,6 +349,85 @@ int newton_direction(lagot_ctx *c, int64_t n, const lagot_opts &o, int *cg_iters
     return LAGOT_OK;  // at the iteration cap the direction is inexact; the step control still guards it
 }
 
+// ---- learned warm start ------------------------------------------------------
+int ensure_mlp(lagot_ctx *c) {
+    if (c->mlp_p) return LAGOT_OK;
+    HIP_TRY(dalloc(&c->mlp_p, MLP_NPARAMS));
+    HIP_TRY(dalloc(&c->mlp_g, MLP_NPARAMS));
+    HIP_TRY(dalloc(&c->mlp_m1, MLP_NPARAMS));
+    HIP_TRY(dalloc(&c->mlp_m2, MLP_NPARAMS));
+    HIP_TRY(dalloc(&c->mlp_pb, MLP_NPARAMS));
+    if (!c->nusum) HIP_TRY(dalloc(&c->nusum, 1));
+    return LAGOT_OK;
+}
+
+int ensure_inference(lagot_ctx *c, int64_t n) {
+    if (!c->nusum) HIP_TRY(dalloc(&c->nusum, 1));
+    if (n <= c->cap_inf) return LAGOT_OK;
+    void *bufs[] = {c->nbr_s, c->feat_s, c->inf_a, c->inf_b, c->mlp_out};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    HIP_TRY(dalloc(&c->nbr_s, (size_t)n * N_NEI));
+    HIP_TRY(dalloc(&c->feat_s, (size_t)n * MLP_IN));
+    HIP_TRY(dalloc(&c->inf_a, (size_t)n * MLP_HID));
+    HIP_TRY(dalloc(&c->inf_b, (size_t)n * MLP_HID));
+    HIP_TRY(dalloc(&c->mlp_out, (size_t)n));
+    c->cap_inf = n;
+    return LAGOT_OK;
+}
+
+int ensure_batch(lagot_ctx *c, int b) {
+    if (b <= c->cap_batch) return LAGOT_OK;
+    void *bufs[] = {c->tX, c->tH1, c->tH2, c->tH3, c->tdZb, c->tZ1, c->tZ2, c->tZ3, c->tdZ, c->ty, c->tt, c->tdy,
+                    c->tpart, c->tloss};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    const size_t B = (size_t)b;
+    HIP_TRY(dalloc(&c->tX, B * MLP_IN));
+    HIP_TRY(dalloc(&c->tH1, B * MLP_HID));
+    HIP_TRY(dalloc(&c->tH2, B * MLP_HID));
+    HIP_TRY(dalloc(&c->tH3, B * MLP_HID));
+    HIP_TRY(dalloc(&c->tdZb, B * MLP_HID));
+    HIP_TRY(dalloc(&c->tZ1, B * MLP_HID));
+    HIP_TRY(dalloc(&c->tZ2, B * MLP_HID));
+    HIP_TRY(dalloc(&c->tZ3, B * MLP_HID));
+    HIP_TRY(dalloc(&c->tdZ, B * MLP_HID));
+    HIP_TRY(dalloc(&c->ty, B));
+    HIP_TRY(dalloc(&c->tt, B));
+    HIP_TRY(dalloc(&c->tdy, B));
+    HIP_TRY(dalloc(&c->tpart, 4096 * (size_t)MLP_HID + B));
+    HIP_TRY(dalloc(&c->tloss, B / 256 + 8));
+    c->cap_batch = b;
+    return LAGOT_OK;
+}
+
+// forward of m rows of bf16 inputs X into out (float32); hidden activations ping-pong in a/b
+void mlp_forward_dev(lagot_ctx *c, int m, const uint16_t *X, uint16_t *a, uint16_t *b, float *out) {
+    const float *P = c->mlp_p;
+    const uint16_t *PB = c->mlp_pb;
+    launch_gemm(c->stream, false, false, MLP_EPI_BIAS_GELU, X, PB + MLP_OFF_W1, m, MLP_HID, MLP_IN, nullptr, a,
+                P + MLP_OFF_B1, nullptr);
+    launch_gemm(c->stream, false, false, MLP_EPI_BIAS_GELU, a, PB + MLP_OFF_W2, m, MLP_HID, MLP_HID, nullptr, b,
+                P + MLP_OFF_B2, nullptr);
+    launch_gemm(c->stream, false, false, MLP_EPI_BIAS_GELU, b, PB + MLP_OFF_W3, m, MLP_HID, MLP_HID, nullptr, a,
+                P + MLP_OFF_B3, nullptr);
+    launch_out_layer(c->stream, m, a, P + MLP_OFF_W4, P + MLP_OFF_B4, out, nullptr, nullptr, nullptr);
+}
+
+// Inputs of every site in grid order (needs prepare() with psi = psi_prev and nu, and
+// the cell volumes at psi_prev in c->V).
+int build_features(lagot_ctx *c, int64_t n) {
+    int rc = ensure_inference(c, n);
+    if (rc) return rc;
+    const int nb = nblk256(n);
+    launch_eval_reduce(c->stream, n, c->nu_s, c->nu_s, c->partial, nb, c->red4);
+    HIP_TRY(hipMemcpyAsync(c->nusum, c->red4, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->counters + 7, 0, sizeof(int32_t), c->stream));
+    launch_knn_features(c->stream, n, c->pos_s, c->perm, c->cell_start, c->grid, c->psi_s, c->nu_s, c->nusum, c->V,
+                        c->nbr_s, c->feat_s, c->counters + 7);
+    return LAGOT_OK;
+}
+
 void fill_defaults(lagot_opts *o) {
     std::memset(o, 0, sizeof(*o));
     o->tol = 1e-5;
@@ -337,6 +437,8 @@ void fill_defaults(lagot_opts *o) {
     o->cg_max_iter = 1000;
     o->threads_per_cell = 0;
     o->verbose = 0;
+    o->use_learned = 0;
+    o->empty_start_fallback = 1;
 }
 
 bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
@@ -384,6 +486,38 @@ int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const fl
             ms_eval += now_ms() - te;
             S.evals = 1;
         }
+        // learned warm start: accepted only if every cell keeps volume and ||nu - V|| drops
+        if (!rc && !single && o.use_learned && c->mlp_set && es.fail == 0) {
+            const double tg = now_ms();
+            rc = build_features(c, n);
+            if (!rc) {
+                mlp_forward_dev(c, (int)n, c->feat_s, c->inf_a, c->inf_b, c->mlp_out);
+                launch_apply_guess(c->stream, n, c->psi_s, c->nu_s, c->mlp_out, c->psi_trial, c->pos_s,
+                                   c->rmax_partial);
+                launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
+                EvalStats eg{};
+                rc = evaluate_reduce(c, n, box, &eg);
+                S.evals++;
+                if (!rc && eg.fail == 0 && eg.minV > 0.0 && eg.gnorm < es.gnorm) {
+                    std::swap(c->psi_s, c->psi_trial);
+                    es = eg;
+                    S.learned_accepted = 1;
+                } else if (!rc) {
+                    launch_psi_shadow(c->stream, n, c->psi_s, c->pos_s);
+                    launch_gather_rmax(c->stream, n, c->psi_s, c->rmax_partial);
+                    launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
+                }
+            }
+            S.ms_learned = now_ms() - tg;
+        }
+        // a start with an empty cell (eps0 = 0) is replaced by the default start weights
+        if (!rc && !(es.minV > 0.0) && o.empty_start_fallback) {
+            launch_default_start(c->stream, n, c->nu_s, c->psi_s, c->pos_s, c->rmax_partial);
+            launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
+            rc = evaluate_reduce(c, n, box, &es);
+            S.evals++;
+            S.default_start = 1;
+        }
         double eps0 = 0.5 * std::min(min_nu, es.minV);
         if (!rc && !(eps0 > 0.0)) rc = LAGOT_EEMPTY;
         if (!rc && es.fail) rc = LAGOT_ECAPACITY;
@@ -427,7 +561,8 @@ int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const fl
             if (rc) break;
             if (!accepted) {
                 // restore the float32 shadow and r_max of the last accepted weights
-                launch_axpy_trial(c->stream, n, c->psi_s, c->x, 0.0, c->psi_trial, c->pos_s, c->rmax_partial);
+                launch_psi_shadow(c->stream, n, c->psi_s, c->pos_s);
+                launch_gather_rmax(c->stream, n, c->psi_s, c->rmax_partial);
                 launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
                 rc = et.fail ? LAGOT_ECAPACITY : LAGOT_ELINESEARCH;
                 break;
@@ -545,6 +680,117 @@ int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const
     if (!ctx || !psi_inout) return LAGOT_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
     return newton_run(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, false);
+}
+
+int lagot_mlp_set_params(lagot_ctx *c, const float *params) {
+    if (!c || !params) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->mlp_p, params, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->mlp_m1, 0, sizeof(float) * MLP_NPARAMS, c->stream));
+    HIP_TRY(hipMemsetAsync(c->mlp_m2, 0, sizeof(float) * MLP_NPARAMS, c->stream));
+    launch_to_bf16(c->stream, MLP_NPARAMS, c->mlp_p, c->mlp_pb);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->mlp_t = 0;
+    c->mlp_set = true;
+    return LAGOT_OK;
+}
+
+int lagot_mlp_get_params(lagot_ctx *c, float *params) {
+    if (!c || !params || !c->mlp_set) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    HIP_TRY(hipMemcpyAsync(params, c->mlp_p, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LAGOT_OK;
+}
+
+int lagot_features(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi_prev,
+                   const double *nu, lagot_box box, int32_t *nbr, uint16_t *feats) {
+    if (!c || !nu || (!nbr && !feats)) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    int rc = prepare(c, n, x, y, z, psi_prev, nu, box);
+    if (rc) return rc;
+    evaluate(c, n, box, false);  // volumes under the previous weights are inputs too
+    rc = build_features(c, n);
+    if (rc) return rc;
+    if (nbr) launch_scatter_rows(c->stream, n, N_NEI * 4, c->perm, c->nbr_s, nbr);
+    if (feats) launch_scatter_rows(c->stream, n, MLP_IN * 2, c->perm, c->feat_s, feats);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 7, c->counters + 7, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return c->h_cnt[7] ? LAGOT_ECAPACITY : LAGOT_OK;
+}
+
+int lagot_mlp_forward(lagot_ctx *c, int64_t m, const uint16_t *feats, float *out) {
+    if (!c || !feats || !out || m <= 0 || m > INT32_MAX / MLP_HID || !c->mlp_set) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    int rc = ensure_inference(c, m);
+    if (rc) return rc;
+    mlp_forward_dev(c, (int)m, feats, c->inf_a, c->inf_b, out);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LAGOT_OK;
+}
+
+int lagot_mlp_train_step(lagot_ctx *c, int64_t nrows, const uint16_t *feats, const float *targets,
+                         const int32_t *batch_idx, int32_t batch, float lr, float *loss) {
+    if (!c || !feats || !targets || !batch_idx || batch <= 0 || nrows <= 0 || !c->mlp_set || !(lr > 0.f))
+        return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    int rc = ensure_batch(c, batch);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    const int B = batch;
+    float *P = c->mlp_p, *G = c->mlp_g;
+    const uint16_t *PB = c->mlp_pb;
+    launch_gather_rows(st, B, batch_idx, feats, targets, c->tX, c->tt);
+    // forward, keeping pre-activations
+    launch_gemm(st, false, false, MLP_EPI_BIAS_GELU, c->tX, PB + MLP_OFF_W1, B, MLP_HID, MLP_IN, c->tZ1, c->tH1,
+                P + MLP_OFF_B1, nullptr);
+    launch_gemm(st, false, false, MLP_EPI_BIAS_GELU, c->tH1, PB + MLP_OFF_W2, B, MLP_HID, MLP_HID, c->tZ2, c->tH2,
+                P + MLP_OFF_B2, nullptr);
+    launch_gemm(st, false, false, MLP_EPI_BIAS_GELU, c->tH2, PB + MLP_OFF_W3, B, MLP_HID, MLP_HID, c->tZ3, c->tH3,
+                P + MLP_OFF_B3, nullptr);
+    launch_out_layer(st, B, c->tH3, P + MLP_OFF_W4, P + MLP_OFF_B4, c->ty, c->tt, c->tdy, c->tloss);
+    // backward
+    launch_colsum(st, B, MLP_HID, nullptr, c->tH3, c->tdy, c->tpart, 4096, G + MLP_OFF_W4);
+    launch_colsum(st, B, 1, c->tdy, nullptr, nullptr, c->tpart, 4096, G + MLP_OFF_B4);
+    launch_out_back(st, B, c->tdy, P + MLP_OFF_W4, c->tZ3, c->tdZ, c->tdZb);
+    launch_gemm(st, true, false, MLP_EPI_STORE, c->tH2, c->tdZb, MLP_HID, MLP_HID, B, G + MLP_OFF_W3, nullptr, nullptr,
+                nullptr);
+    launch_colsum(st, B, MLP_HID, c->tdZ, nullptr, nullptr, c->tpart, 4096, G + MLP_OFF_B3);
+    launch_gemm(st, false, true, MLP_EPI_GELU_BACK, c->tdZb, PB + MLP_OFF_W3, B, MLP_HID, MLP_HID, c->tdZ, c->tdZb,
+                nullptr, c->tZ2);
+    launch_gemm(st, true, false, MLP_EPI_STORE, c->tH1, c->tdZb, MLP_HID, MLP_HID, B, G + MLP_OFF_W2, nullptr, nullptr,
+                nullptr);
+    launch_colsum(st, B, MLP_HID, c->tdZ, nullptr, nullptr, c->tpart, 4096, G + MLP_OFF_B2);
+    launch_gemm(st, false, true, MLP_EPI_GELU_BACK, c->tdZb, PB + MLP_OFF_W2, B, MLP_HID, MLP_HID, c->tdZ, c->tdZb,
+                nullptr, c->tZ1);
+    launch_gemm(st, true, false, MLP_EPI_STORE, c->tX, c->tdZb, MLP_IN, MLP_HID, B, G + MLP_OFF_W1, nullptr, nullptr,
+                nullptr);
+    launch_colsum(st, B, MLP_HID, c->tdZ, nullptr, nullptr, c->tpart, 4096, G + MLP_OFF_B1);
+    // Adam
+    c->mlp_t++;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)c->mlp_t), c2 = 1.f - powf(b2, (float)c->mlp_t);
+    launch_adam(st, MLP_NPARAMS, P, G, c->mlp_m1, c->mlp_m2, lr, b1, b2, 1e-8f, c1, c2, c->mlp_pb);
+    if (loss) {
+        const int nlb = (B + 255) / 256;
+        std::vector<float> h(nlb);
+        HIP_TRY(hipMemcpyAsync(h.data(), c->tloss, sizeof(float) * nlb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double sum = 0.0;
+        for (float v : h) sum += v;
+        *loss = (float)(sum / B);
+    }
+    return LAGOT_OK;
+}
+
+int lagot_mlp_last_grads(lagot_ctx *c, float *grads) {
+    if (!c || !grads || !c->mlp_set) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    HIP_TRY(hipMemcpyAsync(grads, c->mlp_g, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LAGOT_OK;
 }
 
 int lagot_set_threads_per_cell(lagot_ctx *ctx, int threads_per_cell) {

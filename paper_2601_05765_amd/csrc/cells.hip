@@ -183,7 +183,7 @@ template <typename R, int CMAX, int PMAX, int VMAX> struct CellSmem {
 struct CellArgs {
     int64_t n;
     const float4 *pos_s;      // x, y, z, float32 psi (grid order)
-    const double *psi_s;      // float64 psi (grid order); used by the float64 path
+    const double *psi_s;      // float64 psi (grid order)
     const int32_t *perm;      // grid order -> caller index (tie rule for coincident sites)
     const int32_t *cell_start;
     GridDesc g;
@@ -207,12 +207,14 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     auto &GT = S.u.g;
 
     R px = 0, py = 0, pz = 0, psi_i = 0;
+    double psi_i64 = 0.0;
     if (act) {
         const float4 p4 = A.pos_s[cell];
         px = p4.x;
         py = p4.y;
         pz = p4.z;
-        psi_i = fast ? (R)p4.w : (R)A.psi_s[cell];
+        psi_i64 = A.psi_s[cell];
+        psi_i = (R)psi_i64;
     }
     bool live = act && (psi_i > R(0));
     if (act && !live) flags |= CF_EMPTY;
@@ -251,12 +253,15 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                     R nx = 0, ny = 0, nz = 0, t = 0;
                     if (j < end && j != cell) {
                         const float4 q4 = A.pos_s[j];
-                        const R psi_j = fast ? (R)q4.w : (R)A.psi_s[j];
+                        // the weight difference is formed from the float64 weights: for close
+                        // sites t ~ (psi_i - psi_j) / 2d amplifies any rounding of the weights
+                        const double psi_j64 = A.psi_s[j];
+                        const R dpsi = (R)(psi_i64 - psi_j64);
                         const R dx = (R)q4.x - px, dy = (R)q4.y - py, dz = (R)q4.z - pz;
                         const R d2 = dot3(dx, dy, dz, dx, dy, dz);
                         if (d2 > R(0)) {
                             const R id = rsqrt_<R>(d2);
-                            t = (d2 + psi_i - psi_j) * (R(0.5) * id);
+                            t = (d2 + dpsi) * (R(0.5) * id);
                             if (t <= -r) {
                                 kill = true;
                             } else if (t < r) {
@@ -268,7 +273,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                             }
                         } else {
                             // coincident sites: the larger weight, then the lower caller index, owns the point
-                            kill = psi_j > psi_i || (psi_j == psi_i && A.perm[j] < A.perm[cell]);
+                            kill = psi_j64 > psi_i64 || (psi_j64 == psi_i64 && A.perm[j] < A.perm[cell]);
                         }
                     }
                     const unsigned long long b = gballot<G>(keep);
@@ -684,9 +689,9 @@ __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
 
 }  // namespace
 
-void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm, const int32_t *cell_start,
-                  GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc) {
-    CellArgs a{n, pos_s, nullptr, perm, cell_start, g, box, rmax, out};
+void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
+                  const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc) {
+    CellArgs a{n, pos_s, psi_s, perm, cell_start, g, box, rmax, out};
     if (tpc == 8) {
         hipLaunchKernelGGL(k_cells_fast<8>, dim3((unsigned)((n + 7) / 8)), dim3(64), 0, st, a);
     } else if (tpc == 32) {

@@ -250,9 +250,65 @@ __global__ void k_scatter_walls(int64_t n, const int32_t *__restrict__ perm, con
     for (int a = 0; a < 6; ++a) w[i * 6 + a] = ws[k * 6 + a];
 }
 
+__global__ void k_rmax_partial(int64_t n, const double *__restrict__ psi, double *__restrict__ partial) {
+    __shared__ double red[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (i < n) {
+        const double p = psi[i];
+        r = p > 0.0 ? sqrt(p) : 0.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// default start weights: ball radius 1.2 (3 nu / 4 pi)^(1/3)
+__global__ void k_default_start(int64_t n, const double *__restrict__ nu, double *__restrict__ psi,
+                                float4 *__restrict__ pos, double *__restrict__ partial) {
+    __shared__ double red[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (i < n) {
+        r = 1.2 * cbrt(3.0 * nu[i] / (4.0 * 3.14159265358979323846));
+        psi[i] = r * r;
+        pos[i].w = (float)(r * r);
+    }
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// dst row perm[k] = src row k, rows of `chunks` 16-byte words
+__global__ void k_scatter_rows(int64_t n, int chunks, const int32_t *__restrict__ perm, const uint4 *__restrict__ src,
+                               uint4 *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * chunks) return;
+    const int64_t k = e / chunks;
+    const int c = (int)(e % chunks);
+    dst[(int64_t)perm[k] * chunks + c] = src[k * chunks + c];
+}
+
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_default_start(hipStream_t st, int64_t n, const double *nu_s, double *psi_s, float4 *pos_s,
+                          double *rmax_partial) {
+    hipLaunchKernelGGL(k_default_start, dim3(nblocks(n, 256)), dim3(256), 0, st, n, nu_s, psi_s, pos_s, rmax_partial);
+}
+
+void launch_gather_rmax(hipStream_t st, int64_t n, const double *psi, double *partial) {
+    hipLaunchKernelGGL(k_rmax_partial, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi, partial);
+}
+
+void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t *perm, const void *src, void *dst) {
+    const int chunks = row_bytes / 16;
+    hipLaunchKernelGGL(k_scatter_rows, dim3(nblocks(n * chunks, 256)), dim3(256), 0, st, n, chunks, perm,
+                       (const uint4 *)src, (uint4 *)dst);
+}
 
 void launch_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int n, int32_t *tmp) {
     exclusive_scan(st, in, out, n, tmp);

@@ -10,6 +10,12 @@ namespace lagot {
 // Facet storage: row-major blocks of FCAP entries per cell (cell i owns
 // [i*FCAP, i*FCAP + fcnt[i])). The same layout holds the Hessian rows.
 constexpr int FCAP = 64;
+// Learned warm start: nearest sites per input, network sizes, flat parameter layout
+// (W1 64x128, b1, W2 128x128, b2, W3 128x128, b3, w4 128, b4), float32.
+constexpr int N_NEI = 16;
+constexpr int MLP_IN = 64, MLP_HID = 128;
+constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 8192, MLP_OFF_W2 = 8320, MLP_OFF_B2 = 24704, MLP_OFF_W3 = 24832,
+              MLP_OFF_B3 = 41216, MLP_OFF_W4 = 41344, MLP_OFF_B4 = 41472, MLP_NPARAMS = 41473;
 // Fast-path capacities of the cell kernel (float32, G lanes per cell).
 constexpr int FAST_CMAX = 48;   // candidate bisectors (incl. walls) per cell
 constexpr int FAST_PMAX = 32;   // planes of the polytope (6 auxiliary + cutting ones)
@@ -77,10 +83,12 @@ void launch_csr_count(hipStream_t st, int64_t n, const int32_t *perm, const int3
 void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcol, const float *farea,
                      const int32_t *fcnt, const int32_t *start, int32_t *col, float *area, int64_t *row_ptr);
 void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const float *wall_s, float *wall);
+void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t *perm, const void *src, void *dst);
+void launch_gather_rmax(hipStream_t st, int64_t n, const double *psi, double *partial);
 
 // cells.hip
-void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm, const int32_t *cell_start,
-                  GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc);
+void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
+                  const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc);
 void launch_cells_fallback(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
                            const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out);
 
@@ -106,5 +114,28 @@ void launch_pcg_status(hipStream_t st, int nb, const double *RR, const double *R
                        double *scal);
 void launch_axpy_trial(hipStream_t st, int64_t n, const double *psi_s, const double *u, double alpha,
                        double *psi_trial, float4 *pos_s, double *rmax_partial);
+
+// mlp.hip
+void launch_knn_features(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm,
+                         const int32_t *cell_start, GridDesc g, const double *psi_prev_s, const double *nu_s,
+                         const double *nu_sum, const double *V_s, int32_t *nbr, uint16_t *feat, int32_t *err);
+void launch_default_start(hipStream_t st, int64_t n, const double *nu_s, double *psi_s, float4 *pos_s,
+                          double *rmax_partial);
+void launch_gemm(hipStream_t st, bool ta, bool tb, int epi, const uint16_t *A, const uint16_t *B, int M, int N, int K,
+                 float *C, uint16_t *Cb, const float *bias, const float *Zaux);
+void launch_out_layer(hipStream_t st, int m, const uint16_t *H, const float *w4, const float *b4, float *y,
+                      const float *t, float *dy, float *loss_part);
+void launch_out_back(hipStream_t st, int m, const float *dy, const float *w4, const float *Z, float *dZ,
+                     uint16_t *dZb);
+void launch_colsum(hipStream_t st, int m, int ncol, const float *X, const uint16_t *Xb, const float *w, float *part,
+                   int max_part_blocks, float *out);
+void launch_adam(hipStream_t st, int64_t np, float *p, const float *g, float *m1, float *m2, float lr, float b1,
+                 float b2, float eps, float c1, float c2, uint16_t *pb);
+void launch_to_bf16(hipStream_t st, int64_t n, const float *x, uint16_t *y);
+void launch_gather_rows(hipStream_t st, int m, const int32_t *idx, const uint16_t *F, const float *T, uint16_t *Fb,
+                        float *Tb);
+void launch_apply_guess(hipStream_t st, int64_t n, const double *psi_prev, const double *nu, const float *out,
+                        double *psi_new, float4 *pos_s, double *rmax_partial);
+enum { MLP_EPI_STORE = 0, MLP_EPI_BIAS_GELU = 1, MLP_EPI_GELU_BACK = 2 };
 
 }  // namespace lagot

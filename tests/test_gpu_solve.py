@@ -110,10 +110,14 @@ def test_error_codes(ctx):
     x, y, z, nu, psi = _dev(sc)
     st = ctx.solve(x, y, z, nu * (1.2 / float(nu.sum())), psi, check=False)
     assert st.status == L.EINVAL
-    # an empty start cell -> EEMPTY
+    # an empty start cell -> EEMPTY without the default-start fallback, solved with it
     x, y, z, nu, psi = _dev(sc)
     psi[5] = -1.0
-    assert ctx.solve(x, y, z, nu, psi, check=False).status == L.EEMPTY
+    assert ctx.solve(x, y, z, nu, psi, opts=L.default_opts(empty_start_fallback=0), check=False).status == L.EEMPTY
+    x, y, z, nu, psi = _dev(sc)
+    psi[5] = -1.0
+    st = ctx.solve(x, y, z, nu, psi, check=False)
+    assert st.status == 0 and st.default_start == 1
     # iteration limit -> ENOCONV, psi holds an accepted iterate
     x, y, z, nu, psi = _dev(sc)
     st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(max_newton=1), check=False)

@@ -32,14 +32,18 @@ def test_features_layout():
     P = rng.uniform(size=(40, 3))
     nu = rng.uniform(1e-4, 2e-4, size=40)
     psi = rng.uniform(1e-3, 2e-3, size=40)
+    V = rng.uniform(0.5e-4, 2.5e-4, size=40)
     nb = mlp.knn(P)
-    F = mlp.features(P, psi, nu, nb)
+    F = mlp.features(P, psi, nu, nb, V)
     s = np.cbrt(nu)
     i = 7
     assert np.allclose(F[i, :3], (P[nb[i, 0]] - P[i]) / s[i])
+    assert np.allclose(F[i, 45:48], (P[nb[i, 15]] - P[i]) / s[i])
     assert F[i, 48] == pytest.approx(psi[i] / s[i] ** 2)
     assert F[i, 49] == pytest.approx(nu[i] / nu.mean())
-    assert np.all(F[:, 50:] == 0)
+    assert F[i, 50] == pytest.approx((nu[i] - V[i]) / nu[i])
+    j = nb[i, 12]
+    assert F[i, 63] == pytest.approx((nu[j] - V[j]) / nu[j])
 
 
 def test_gelu_closed_form():
