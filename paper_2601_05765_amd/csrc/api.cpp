@@ -268,18 +268,19 @@ int prepare(lagot_ctx *c, int64_t n, const float *x, const float *y, const float
     return LAGOT_OK;
 }
 
-// One evaluation of all cells at the weights in pos_s.w / psi_s (rmax on device).
-void evaluate(lagot_ctx *c, int64_t n, const lagot_box &box, bool walls) {
+// One evaluation of all cells at the float64 weights psi_eval (grid order), whose
+// float32 shadow is pos_s.w (r_max on device).
+void evaluate(lagot_ctx *c, int64_t n, const lagot_box &box, bool walls, const double *psi_eval) {
     const BoxF bf = to_boxf(box);
     (void)hipMemsetAsync(c->counters, 0, 2 * sizeof(int32_t), c->stream);
     if (walls) (void)hipMemsetAsync(c->wall, 0, 6 * sizeof(float) * (size_t)n, c->stream);
     EvalOut o{c->V, c->K, walls ? c->wall : nullptr, c->fcol, c->farea, c->fcnt, c->flags, c->fb_list,
               c->counters + 0, c->counters + 1};
     (void)hipEventRecord(c->ev0, c->stream);
-    launch_cells(c->stream, n, c->pos_s, c->psi_s, c->perm, c->cell_start, c->grid, bf, c->rmax, o, c->tpc);
+    launch_cells(c->stream, n, c->pos_s, psi_eval, c->perm, c->cell_start, c->grid, bf, c->rmax, o, c->tpc);
     (void)hipEventRecord(c->ev1, c->stream);
     c->ev_pending = true;
-    launch_cells_fallback(c->stream, n, c->pos_s, c->psi_s, c->perm, c->cell_start, c->grid, bf, c->rmax, o);
+    launch_cells_fallback(c->stream, n, c->pos_s, psi_eval, c->perm, c->cell_start, c->grid, bf, c->rmax, o);
 }
 
 struct EvalStats {
@@ -287,8 +288,8 @@ struct EvalStats {
     int fb, fail;
 };
 
-int evaluate_reduce(lagot_ctx *c, int64_t n, const lagot_box &box, EvalStats *es) {
-    evaluate(c, n, box, false);
+int evaluate_reduce(lagot_ctx *c, int64_t n, const lagot_box &box, EvalStats *es, const double *psi_eval) {
+    evaluate(c, n, box, false, psi_eval);
     const int nb = nblk256(n);
     launch_eval_reduce(c->stream, n, c->V, c->nu_s, c->partial, nb, c->red4);
     HIP_TRY(hipMemcpyAsync(c->h_scal, c->red4, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -482,7 +483,7 @@ int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const fl
         EvalStats es{};
         if (!rc) {
             const double te = now_ms();
-            rc = evaluate_reduce(c, n, box, &es);
+            rc = evaluate_reduce(c, n, box, &es, c->psi_s);
             ms_eval += now_ms() - te;
             S.evals = 1;
         }
@@ -496,7 +497,7 @@ int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const fl
                                    c->rmax_partial);
                 launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
                 EvalStats eg{};
-                rc = evaluate_reduce(c, n, box, &eg);
+                rc = evaluate_reduce(c, n, box, &eg, c->psi_trial);
                 S.evals++;
                 if (!rc && eg.fail == 0 && eg.minV > 0.0 && eg.gnorm < es.gnorm) {
                     std::swap(c->psi_s, c->psi_trial);
@@ -514,7 +515,7 @@ int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const fl
         if (!rc && !(es.minV > 0.0) && o.empty_start_fallback) {
             launch_default_start(c->stream, n, c->nu_s, c->psi_s, c->pos_s, c->rmax_partial);
             launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
-            rc = evaluate_reduce(c, n, box, &es);
+            rc = evaluate_reduce(c, n, box, &es, c->psi_s);
             S.evals++;
             S.default_start = 1;
         }
@@ -547,7 +548,7 @@ int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const fl
                 launch_axpy_trial(c->stream, n, c->psi_s, c->x, alpha, c->psi_trial, c->pos_s, c->rmax_partial);
                 launch_reduce_max(c->stream, c->rmax_partial, nb2, c->rmax);
                 const double te = now_ms();
-                rc = evaluate_reduce(c, n, box, &et);
+                rc = evaluate_reduce(c, n, box, &et, c->psi_trial);
                 ms_eval += now_ms() - te;
                 S.evals++;
                 if (rc) break;
@@ -639,7 +640,7 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     c->tpc = c->tpc_default;
     int rc = prepare(c, n, x, y, z, psi, nullptr, box);
     if (rc) return rc;
-    evaluate(c, n, box, wall_area != nullptr);
+    evaluate(c, n, box, wall_area != nullptr, c->psi_s);
     launch_scatter_out_f64(c->stream, n, c->perm, c->V, vol);
     if (sph_area) launch_scatter_out_f64(c->stream, n, c->perm, c->K, sph_area);
     if (wall_area) launch_scatter_walls(c->stream, n, c->perm, c->wall, wall_area);
@@ -711,7 +712,7 @@ int lagot_features(lagot_ctx *c, int64_t n, const float *x, const float *y, cons
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     int rc = prepare(c, n, x, y, z, psi_prev, nu, box);
     if (rc) return rc;
-    evaluate(c, n, box, false);  // volumes under the previous weights are inputs too
+    evaluate(c, n, box, false, c->psi_s);  // volumes under the previous weights are inputs too
     rc = build_features(c, n);
     if (rc) return rc;
     if (nbr) launch_scatter_rows(c->stream, n, N_NEI * 4, c->perm, c->nbr_s, nbr);
