@@ -66,11 +66,14 @@ typedef struct {
     int use_learned;     /* 1: try the learned warm start (lagot_mlp_set_params) before Newton       */
     int empty_start_fallback; /* 1 (default): if a start cell is empty (KMT needs eps0 > 0),
                             restart from the default weights psi_i = (1.2 (3 nu_i / 4 pi)^(1/3))^2 */
-    int reserved[3];
+    int autotune;        /* 1: when threads_per_cell is 0, time the cell kernel with 16, 32 and 64
+                            lanes per cell on the first solve of each size and density class and
+                            keep the fastest in the context (default 0: the context's default) */
+    int reserved[2];
 } lagot_opts;
 
 typedef struct {
-    int status;          /* LAGOT_* code of the call                                       */
+    int status;          /* LAGOT_* code of the call (of the instance, for a batched call) */
     int newton_iters;    /* accepted Newton iterations                                     */
     int evals;           /* full cell evaluations (start + one per step trial)             */
     int halvings;        /* total step halvings                                            */
@@ -147,10 +150,35 @@ int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const
                 lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats);
 
 /*
- * Learned warm start (not part of the paper's method; its guess only replaces the
- * start weights of lagot_solve when opts->use_learned is set, every cell of the guess
- * has positive volume and ||nu - V||_2 is smaller than at the given start; Newton then
- * runs to tolerance as usual).
+ * Many independent solves in one call (each instance is a full lagot_solve problem:
+ * its own sites, prescribed volumes, box and start weights). Instance b owns the rows
+ * [offsets[b], offsets[b+1]) of the concatenated arrays x, y, z, nu, psi_inout.
+ * Every kernel serves all instances at once (one launch per step of Algorithm 1 for
+ * the whole batch); each instance keeps its own eps0, step length, iteration count and
+ * stopping test, and stops independently.
+ *   in : n_inst >= 1; offsets (HOST, int64 [n_inst+1], offsets[0] = 0, strictly
+ *        increasing: every instance has at least one site); boxes (HOST, [n_inst]);
+ *        x, y, z [N] float32, nu [N] float64, psi_inout [N] float64 (device, N =
+ *        offsets[n_inst]); opts as for lagot_solve (use_learned must be 0).
+ *   out: psi_inout; per_inst (HOST, [n_inst], may be NULL): the statistics of each
+ *        instance (status, iterations, evaluations, residuals; the ms_* fields are
+ *        those of the whole call).
+ * Returns LAGOT_OK if every instance converged, else the status of the first
+ * instance that did not. The call validates every instance before solving any:
+ * one invalid instance makes the call return LAGOT_EINVAL with nothing solved.
+ * Synchronises the stream.
+ */
+int lagot_solve_batched(lagot_ctx *ctx, int32_t n_inst, const int64_t *offsets, const float *x, const float *y,
+                        const float *z, const double *nu, const lagot_box *boxes, double *psi_inout,
+                        const lagot_opts *opts, lagot_stats *per_inst);
+
+/*
+ * Learned warm start (not part of the paper's method). With opts->use_learned set,
+ * lagot_solve evaluates the network's guess like a Newton trial step from the given
+ * start weights: it replaces them only if every cell of the guess keeps at least the
+ * KMT floor eps0 = 1/2 min(min nu, min V(psi_start)) and ||nu - V||_2 is smaller than
+ * at the start; eps0 stays that of the given start, and Newton then runs to the
+ * tolerance as usual.
  * Inputs of site i (64 bf16, row-major n x 64): offsets (p_j - p_i)/s_i of its 16 nearest
  * sites in ascending (distance, index), psi_prev_i / s_i^2, nu_i / mean(nu), and the
  * relative volume mismatch (nu - V)/nu under the previous weights of site i and of its

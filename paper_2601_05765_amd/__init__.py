@@ -8,6 +8,7 @@ binding raises if the library has not been built: there is no CPU fallback.
   out = ctx.cells(x, y, z, psi)                     # lagot_cells
   st  = ctx.solve(x, y, z, nu, psi)                 # lagot_solve, psi updated in place
   st  = ctx.newton_step(x, y, z, nu, psi)           # lagot_newton_step
+  sts = ctx.solve_batched(offsets, x, y, z, nu, psi, boxes)   # lagot_solve_batched
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_set_threads_per_cell", "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
@@ -35,7 +36,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_newton", ctypes.c_int), ("max_halvings", ctypes.c_int),
                 ("cg_rtol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("threads_per_cell", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("use_learned", ctypes.c_int), ("empty_start_fallback", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -77,6 +78,9 @@ def load():
             f = getattr(lib, name)
             f.argtypes = [P, I64, P, P, P, P, Box, P, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
             f.restype = I
+        lib.lagot_solve_batched.argtypes = [P, ctypes.c_int32, ctypes.POINTER(I64), P, P, P, P, ctypes.POINTER(Box),
+                                            P, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+        lib.lagot_solve_batched.restype = I
         lib.lagot_mlp_set_params.argtypes = [P, P]
         lib.lagot_mlp_get_params.argtypes = [P, P]
         lib.lagot_mlp_last_grads.argtypes = [P, P]
@@ -289,3 +293,27 @@ class Context:
                     check: bool = True):
         """lagot_newton_step: one damped Newton iteration; psi updated in place."""
         return self._newton(load().lagot_newton_step, x, y, z, nu, psi, box, opts, check)
+
+    def solve_batched(self, offsets, x, y, z, nu, psi, boxes=None, opts: Opts | None = None, check: bool = True):
+        """lagot_solve_batched: instance b owns rows offsets[b]:offsets[b+1] of the concatenated
+        device arrays; psi is updated in place. Returns the per-instance Stats list."""
+        import torch
+        offs = [int(v) for v in offsets]
+        B = len(offs) - 1
+        if B < 1:
+            raise ValueError("offsets needs at least two entries")
+        if boxes is None:
+            boxes = [((0, 0, 0), (1, 1, 1))] * B
+        if len(boxes) != B:
+            raise ValueError("one box per instance")
+        c_off = (ctypes.c_int64 * (B + 1))(*offs)
+        c_box = (Box * B)(*[make_box(b) for b in boxes])
+        stats = (Stats * B)()
+        o = opts if opts is not None else default_opts()
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(nu, torch.float64, "nu")]
+        rc = load().lagot_solve_batched(self._h, B, c_off, *args, c_box, _dev(psi, torch.float64, "psi"),
+                                        ctypes.byref(o), stats)
+        if check and rc != OK:
+            raise LagotError(rc, "lagot_solve_batched")
+        return list(stats)

@@ -1,10 +1,13 @@
 // api.cpp -- C-ABI of liblagot (declared in include/lagot.h): context and
-// workspace management, input validation, the spatial sort, one evaluation of
-// all cells, and the host side of the damped Newton loop of Algorithm 1 (KMT
-// step control) around the Jacobi-PCG direction solve.
+// workspace management, input validation, the per-instance spatial sort, cell
+// evaluations, and the host side of the damped Newton loop of Algorithm 1
+// (KMT step control) around the Jacobi-PCG direction solve.
 //
-// Everything between the caller's arrays runs in grid order on the device; the
-// host only reads a few float64 scalars per evaluation / PCG chunk.
+// Every solve is a batch of B >= 1 independent instances (lagot_solve is the
+// case B = 1). Everything between the caller's arrays runs in grid order on the
+// device; the decisions of Algorithm 1 (stop, accept, halve, fail) are taken per
+// instance by device control kernels, and the host only reads a histogram of
+// instance phases between the steps of a Newton iteration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "lagot.h"
@@ -37,45 +41,63 @@ struct lagot_ctx {
     hipStream_t stream = nullptr;
     int64_t cap_n = 0;
     int cap_cells = 0;
+    int cap_B = 0, cap_T = 0;
     int tpc = 32;
     int tpc_default = 32;  // lanes per cell when the options leave it to the library
+    std::map<int, int> tpc_tuned;  // autotuner: size/density class -> lanes per cell
+    int cg_chunk = 16;             // PCG launches between host checks (adapted per solve)
+
+    // the current call: B instances, T tiles, n rows
+    int B = 0, T = 0;
+    int64_t n = 0;
+    int ncell_total = 0;
+    std::vector<GridDesc> h_grid;
 
     // sites (caller order, then grid order)
     float4 *pos_orig = nullptr, *pos_s = nullptr;
     double *psi_s = nullptr, *nu_s = nullptr, *psi_trial = nullptr;
-    int32_t *keys = nullptr, *perm = nullptr;
+    int32_t *keys = nullptr, *perm = nullptr, *inst = nullptr;
     int32_t *cell_count = nullptr, *cell_start = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
-    GridDesc grid{};
+    // instances and tiles
+    int32_t *off = nullptr, *tile_inst = nullptr, *tile_row = nullptr, *first_tile = nullptr;
+    GridDesc *grid = nullptr;
+    BoxF *box = nullptr;
+    double *rmax = nullptr;
+    int32_t *phase = nullptr;
+    InstCtl *ctl = nullptr;
+    double *ev = nullptr, *ev2 = nullptr, *ev_nu = nullptr, *part_ev = nullptr;
+    int32_t *fb_inst = nullptr, *fail_inst = nullptr, *bad_inst = nullptr, *herr = nullptr, *counts = nullptr;
+    int32_t *misc = nullptr;  // [0] float64 work-list length [1] feature errors [2] kbase [3] remaining
     // evaluation outputs (grid order)
     double *V = nullptr, *K = nullptr;
     float *wall = nullptr;
     int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr;
     float *farea = nullptr;
     uint32_t *flags = nullptr;
-    int32_t *counters = nullptr;  // [0] fallback count [1] fail count [2] bad inputs [3] hessian overflow
     // Hessian and PCG
     int32_t *hcol = nullptr, *hcnt = nullptr, *xcnt = nullptr;
     float *hval = nullptr;
-    double *diag = nullptr, *g = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-    double *p2 = nullptr;
-    double *partial = nullptr, *scal = nullptr, *red4 = nullptr, *rmax = nullptr, *rmax_partial = nullptr;
-    int cap_blocks = 0;
-    // pinned host mirrors
-    double *h_scal = nullptr;
-    int32_t *h_cnt = nullptr;
+    double *diag = nullptr;
+    double *cg_vec = nullptr;   // r[2], w[2], s[2], p, x: 8 vectors of cap_n
+    double *cg_part = nullptr;  // 7 * cap_T
+    double *cg_cgs = nullptr;   // 4 * cap_B
+    int32_t *cg_cgst = nullptr; // 4 * cap_B
+    // pinned host staging (uploads) and read-back
+    char *h_stage = nullptr;
+    size_t cap_stage = 0;
+    char *h_rd = nullptr;
+    size_t cap_rd = 0;
+    int32_t *h_cnt = nullptr;  // [16]
     // CSR staging for lagot_cells
     int32_t *csr_cnt = nullptr, *csr_start = nullptr;
-    int64_t *csr_start64 = nullptr;
     int32_t *csr_tmp = nullptr;
     // statistics of the current call
-    int fb_total = 0;
     int last_fb = 0;
     // learned warm start: float32 master parameters, bf16 copy, Adam moments
     float *mlp_p = nullptr, *mlp_g = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr;
     uint16_t *mlp_pb = nullptr;
     int mlp_t = 0;
     bool mlp_set = false;
-    double *nusum = nullptr;
     int32_t *nbr_s = nullptr;        // [n*16] grid order (caller indices)
     uint16_t *feat_s = nullptr;      // [n*64] bf16 inputs, grid order
     uint16_t *inf_a = nullptr, *inf_b = nullptr;  // [n*128] bf16 hidden activations
@@ -103,21 +125,34 @@ namespace {
         }                                                   \
     } while (0)
 
+template <typename... P> void free_ptrs(P *&...ps) {
+    ((ps ? (void)hipFree((void *)ps) : (void)0), ...);
+    ((ps = nullptr), ...);
+}
+
+void free_sites(lagot_ctx *c) {
+    free_ptrs(c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->inst, c->V, c->K, c->wall,
+              c->fcol, c->fcnt, c->fb_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
+              c->cg_vec, c->csr_cnt, c->csr_start, c->csr_tmp);
+    c->cap_n = 0;
+}
+
+void free_inst(lagot_ctx *c) {
+    free_ptrs(c->off, c->tile_inst, c->tile_row, c->first_tile, c->grid, c->box, c->rmax, c->phase, c->ctl, c->ev,
+              c->ev2, c->ev_nu, c->part_ev, c->fb_inst, c->fail_inst, c->bad_inst, c->herr, c->cg_part, c->cg_cgs,
+              c->cg_cgst);
+}
+
 void free_all(lagot_ctx *c) {
-    void *bufs[] = {c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->cell_count,
-                    c->cell_start, c->cursor, c->scan_tmp, c->V, c->K, c->wall, c->fcol, c->fcnt, c->fb_list,
-                    c->farea, c->flags, c->counters, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag, c->g, c->x,
-                    c->r, c->z, c->p, c->q, c->partial, c->scal, c->red4, c->rmax, c->rmax_partial, c->csr_cnt,
-                    c->csr_start, c->csr_start64, c->csr_tmp, c->p2};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
-    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    free_sites(c);
+    free_inst(c);
+    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->h_rd) (void)hipHostFree(c->h_rd);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
-    void *mbufs[] = {c->mlp_p, c->mlp_g, c->mlp_m1, c->mlp_m2, c->mlp_pb, c->nusum, c->nbr_s, c->feat_s, c->inf_a,
-                     c->inf_b, c->mlp_out, c->tX, c->tH1, c->tH2, c->tH3, c->tdZb, c->tZ1, c->tZ2, c->tZ3, c->tdZ,
-                     c->ty, c->tt, c->tdy, c->tpart, c->tloss};
-    for (void *b : mbufs)
-        if (b) (void)hipFree(b);
+    free_ptrs(c->mlp_p, c->mlp_g, c->mlp_m1, c->mlp_m2, c->mlp_pb, c->nbr_s, c->feat_s, c->inf_a, c->inf_b,
+              c->mlp_out, c->tX, c->tH1, c->tH2, c->tH3, c->tdZb, c->tZ1, c->tZ2, c->tZ3, c->tdZ, c->ty, c->tt,
+              c->tdy, c->tpart, c->tloss);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
@@ -133,18 +168,10 @@ void collect_cell_time(lagot_ctx *c) {
     c->ev_pending = false;
 }
 
-int nblk256(int64_t n) { return (int)((n + 255) / 256); }
-
 int ensure_sites(lagot_ctx *c, int64_t n) {
     if (n <= c->cap_n) return LAGOT_OK;
-    void *bufs[] = {c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->V, c->K, c->wall,
-                    c->fcol, c->fcnt, c->fb_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
-                    c->g, c->x, c->r, c->z, c->p, c->q, c->partial, c->rmax_partial, c->csr_cnt, c->csr_start,
-                    c->csr_start64, c->csr_tmp, c->p2};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
+    free_sites(c);
     const size_t N = (size_t)n;
-    const int nb = nblk256(n);
     HIP_TRY(dalloc(&c->pos_orig, N));
     HIP_TRY(dalloc(&c->pos_s, N));
     HIP_TRY(dalloc(&c->psi_s, N));
@@ -152,6 +179,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->psi_trial, N));
     HIP_TRY(dalloc(&c->keys, N));
     HIP_TRY(dalloc(&c->perm, N));
+    HIP_TRY(dalloc(&c->inst, N));
     HIP_TRY(dalloc(&c->V, N));
     HIP_TRY(dalloc(&c->K, N));
     HIP_TRY(dalloc(&c->wall, 6 * N));
@@ -165,29 +193,50 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->hcnt, N));
     HIP_TRY(dalloc(&c->xcnt, N));
     HIP_TRY(dalloc(&c->diag, N));
-    HIP_TRY(dalloc(&c->g, N));
-    HIP_TRY(dalloc(&c->x, N));
-    HIP_TRY(dalloc(&c->r, N));
-    HIP_TRY(dalloc(&c->z, N));
-    HIP_TRY(dalloc(&c->p, N));
-    HIP_TRY(dalloc(&c->q, N));
-    HIP_TRY(dalloc(&c->p2, N));
-    HIP_TRY(dalloc(&c->partial, std::max<size_t>(4 * (size_t)nb, 5 * 512 + (size_t)spmv_blocks(n) + 64)));
-    HIP_TRY(dalloc(&c->rmax_partial, (size_t)nb));
+    HIP_TRY(dalloc(&c->cg_vec, 8 * N));
     HIP_TRY(dalloc(&c->csr_cnt, N + 1));
     HIP_TRY(dalloc(&c->csr_start, N + 1));
-    HIP_TRY(dalloc(&c->csr_start64, N + 1));
     HIP_TRY(dalloc(&c->csr_tmp, N / 1024 + 16));
     c->cap_n = n;
-    c->cap_blocks = nb;
+    return LAGOT_OK;
+}
+
+int ensure_inst(lagot_ctx *c, int B, int T) {
+    if (B <= c->cap_B && T <= c->cap_T) return LAGOT_OK;
+    free_inst(c);
+    B = std::max(B, c->cap_B);
+    T = std::max(T, c->cap_T);
+    c->cap_B = c->cap_T = 0;
+    const size_t b = (size_t)B, t = (size_t)T;
+    HIP_TRY(dalloc(&c->off, b + 1));
+    HIP_TRY(dalloc(&c->tile_inst, t));
+    HIP_TRY(dalloc(&c->tile_row, t));
+    HIP_TRY(dalloc(&c->first_tile, b + 1));
+    HIP_TRY(dalloc(&c->grid, b));
+    HIP_TRY(dalloc(&c->box, b));
+    HIP_TRY(dalloc(&c->rmax, b));
+    HIP_TRY(dalloc(&c->phase, b));
+    HIP_TRY(dalloc(&c->ctl, b));
+    HIP_TRY(dalloc(&c->ev, 4 * b));
+    HIP_TRY(dalloc(&c->ev2, 4 * b));
+    HIP_TRY(dalloc(&c->ev_nu, 4 * b));
+    HIP_TRY(dalloc(&c->part_ev, 4 * t));
+    HIP_TRY(dalloc(&c->fb_inst, b));
+    HIP_TRY(dalloc(&c->fail_inst, b));
+    HIP_TRY(dalloc(&c->bad_inst, b));
+    HIP_TRY(dalloc(&c->herr, b));
+    HIP_TRY(dalloc(&c->cg_part, 7 * t));
+    HIP_TRY(dalloc(&c->cg_cgs, 4 * b));
+    HIP_TRY(dalloc(&c->cg_cgst, 4 * b));
+    c->cap_B = B;
+    c->cap_T = T;
     return LAGOT_OK;
 }
 
 int ensure_cells(lagot_ctx *c, int ncell) {
     if (ncell <= c->cap_cells) return LAGOT_OK;
-    void *bufs[] = {c->cell_count, c->cell_start, c->cursor, c->scan_tmp};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
+    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp);
+    c->cap_cells = 0;
     HIP_TRY(dalloc(&c->cell_count, (size_t)ncell + 1));
     HIP_TRY(dalloc(&c->cell_start, (size_t)ncell + 1));
     HIP_TRY(dalloc(&c->cursor, (size_t)ncell + 1));
@@ -196,13 +245,15 @@ int ensure_cells(lagot_ctx *c, int ncell) {
     return LAGOT_OK;
 }
 
-BoxF to_boxf(const lagot_box &b) {
-    BoxF f;
-    for (int a = 0; a < 3; ++a) {
-        f.lo[a] = (float)b.lo[a];
-        f.hi[a] = (float)b.hi[a];
-    }
-    return f;
+int ensure_pinned(char **p, size_t *cap, size_t bytes) {
+    if (bytes <= *cap) return LAGOT_OK;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    bytes = std::max<size_t>(bytes, 4096);
+    HIP_TRY(hipHostMalloc((void **)p, bytes));
+    *cap = bytes;
+    return LAGOT_OK;
 }
 
 bool box_ok(const lagot_box &b) {
@@ -211,143 +262,200 @@ bool box_ok(const lagot_box &b) {
     return true;
 }
 
-int sync_read(lagot_ctx *c, const void *dev, void *host, size_t bytes) {
-    HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return LAGOT_OK;
+double box_volume(const lagot_box &b) {
+    return (b.hi[0] - b.lo[0]) * (b.hi[1] - b.lo[1]) * (b.hi[2] - b.lo[2]);
 }
 
-// Validate, gather, spatially sort. nu may be null (cells-only). On return the
-// grid-order arrays pos_s (with float32 psi), psi_s (and nu_s) are filled and
-// c->rmax holds max sqrt(psi).
-int prepare(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
-            const double *nu, const lagot_box &box) {
-    if (n <= 0 || n > (int64_t)INT32_MAX / FCAP || !x || !y || !z || !psi || !box_ok(box)) return LAGOT_EINVAL;
-    int rc = ensure_sites(c, n);
-    if (rc) return rc;
-    const BoxF bf = to_boxf(box);
-    HIP_TRY(hipMemsetAsync(c->counters, 0, 8 * sizeof(int32_t), c->stream));
-    launch_validate(c->stream, n, x, y, z, psi, nu, bf, c->counters + 2);
-    const int nb = nblk256(n);
-    launch_gather_sites(c->stream, n, x, y, z, psi, c->pos_orig, c->rmax_partial, nb);
-    launch_reduce_max(c->stream, c->rmax_partial, nb, c->rmax);
-    HIP_TRY(hipMemcpyAsync(c->h_scal, c->rmax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counters, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (c->h_cnt[2] != 0) return LAGOT_EINVAL;
-    const double rmax = c->h_scal[0];
-    // grid cell size: 2 r_max (the 3x3x3 neighbourhood then covers every bisector
-    // that can cut a ball), but at most 512 cells per axis and 2^24 cells in all
-    double ext = 0.0;
-    for (int a = 0; a < 3; ++a) ext = std::max(ext, box.hi[a] - box.lo[a]);
-    double s = std::max(2.0 * rmax, ext / 512.0);
-    int dim[3];
-    for (;;) {
-        int64_t tot = 1;
-        for (int a = 0; a < 3; ++a) {
-            dim[a] = std::max(1, (int)std::ceil((box.hi[a] - box.lo[a]) / s));
-            tot *= dim[a];
-        }
-        if (tot <= (1 << 24)) break;
-        s *= 1.25;
-    }
-    GridDesc g;
-    for (int a = 0; a < 3; ++a) {
-        g.lo[a] = (float)box.lo[a];
-        g.dim[a] = dim[a];
-    }
-    g.s = (float)s;
-    g.inv_s = (float)(1.0 / s);
-    g.ncell = dim[0] * dim[1] * dim[2];
-    c->grid = g;
-    rc = ensure_cells(c, g.ncell);
-    if (rc) return rc;
-    launch_grid_build(c->stream, n, c->pos_orig, g, c->keys, c->cell_count, c->cell_start, c->scan_tmp, c->perm,
-                      c->cursor);
-    launch_permute_in(c->stream, n, c->perm, c->pos_orig, psi, nu, c->pos_s, c->psi_s, nu ? c->nu_s : nullptr);
-    return LAGOT_OK;
-}
-
-// One evaluation of all cells at the float64 weights psi_eval (grid order), whose
-// float32 shadow is pos_s.w (r_max on device).
-void evaluate(lagot_ctx *c, int64_t n, const lagot_box &box, bool walls, const double *psi_eval) {
-    const BoxF bf = to_boxf(box);
-    (void)hipMemsetAsync(c->counters, 0, 2 * sizeof(int32_t), c->stream);
-    if (walls) (void)hipMemsetAsync(c->wall, 0, 6 * sizeof(float) * (size_t)n, c->stream);
-    EvalOut o{c->V, c->K, walls ? c->wall : nullptr, c->fcol, c->farea, c->fcnt, c->flags, c->fb_list,
-              c->counters + 0, c->counters + 1};
-    (void)hipEventRecord(c->ev0, c->stream);
-    launch_cells(c->stream, n, c->pos_s, psi_eval, c->perm, c->cell_start, c->grid, bf, c->rmax, o, c->tpc);
-    (void)hipEventRecord(c->ev1, c->stream);
-    c->ev_pending = true;
-    launch_cells_fallback(c->stream, n, c->pos_s, psi_eval, c->perm, c->cell_start, c->grid, bf, c->rmax, o);
-}
-
-struct EvalStats {
-    double sumV, maxrel, gnorm, minV;
-    int fb, fail;
-};
-
-int evaluate_reduce(lagot_ctx *c, int64_t n, const lagot_box &box, EvalStats *es, const double *psi_eval) {
-    evaluate(c, n, box, false, psi_eval);
-    const int nb = nblk256(n);
-    launch_eval_reduce(c->stream, n, c->V, c->nu_s, c->partial, nb, c->red4);
-    HIP_TRY(hipMemcpyAsync(c->h_scal, c->red4, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+int sync(lagot_ctx *c) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     collect_cell_time(c);
-    es->sumV = c->h_scal[0];
-    es->maxrel = c->h_scal[1];
-    es->gnorm = c->h_scal[2];
-    es->minV = c->h_scal[3];
-    es->fb = c->h_cnt[0];
-    es->fail = c->h_cnt[1];
-    c->fb_total += es->fb;
     return LAGOT_OK;
 }
 
-// Newton direction: assemble -Hess K, Jacobi-PCG for (-Hess K) u = nu - V, u in c->x.
-// Iterations are enqueued in chunks without host syncs; the kernels of a chunk
-// turn into no-ops once the residual meets the tolerance (device-side test).
-int newton_direction(lagot_ctx *c, int64_t n, const lagot_opts &o, int *cg_iters) {
-    HIP_TRY(hipMemsetAsync(c->counters + 3, 0, sizeof(int32_t), c->stream));
-    launch_hess_assemble(c->stream, n, c->pos_s, c->psi_s, c->K, c->fcol, c->farea, c->fcnt, c->hcol, c->hval,
-                         c->xcnt, c->diag, c->counters + 3);
-    launch_hess_finish(c->stream, n, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hval, c->diag);
-    const int nb = pcg_blocks(n);
-    double *RZ = c->partial, *RR = c->partial + 2 * nb, *R0 = c->partial + 4 * nb, *PQ = c->partial + 5 * nb;
-    // PQ holds one partial per SpMV block
-    int32_t *state = c->counters + 4;
-    const double rtol2 = o.cg_rtol * o.cg_rtol;
-    launch_pcg_init(c->stream, n, nb, c->V, c->nu_s, c->diag, c->g, c->x, c->r, c->z, RZ, RR, R0, state);
-    *cg_iters = 0;
-    double *pb[2] = {c->p, c->p2};
-    const int chunk = 16;
-    int k = 0;
-    for (;;) {
-        for (int m = 0; m < chunk && k < o.cg_max_iter; ++m, ++k) {
-            launch_pcg_spmv(c->stream, n, k, nb, rtol2, R0, c->hcol, c->hval, c->hcnt, c->diag, c->z,
-                            pb[(k + 1) & 1], pb[k & 1], c->q, RZ, RR, PQ, state);
-            launch_pcg_update(c->stream, n, k, nb, rtol2, R0, c->diag, c->x, c->r, c->z, pb[k & 1], c->q, RZ, RR,
-                              PQ, state);
-        }
-        HIP_TRY(hipMemcpyAsync(c->h_cnt + 3, c->counters + 3, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                               c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        if (c->h_cnt[3] != 0) return LAGOT_ECAPACITY;
-        const int done_iters = c->h_cnt[4], breakdown = c->h_cnt[5], converged = c->h_cnt[6];
-        *cg_iters = done_iters;
-        if (breakdown) {
-            // non-positive curvature before the tolerance was met
-            launch_pcg_status(c->stream, nb, RR, R0, state, c->scal);
-            int rc = sync_read(c, c->scal, c->h_scal, 2 * sizeof(double));
-            if (rc) return rc;
-            if (!(c->h_scal[0] <= rtol2 * c->h_scal[1])) return LAGOT_ESINGULAR;
-            break;
-        }
-        if (converged || done_iters < k || k >= o.cg_max_iter) break;
+Batch batch(const lagot_ctx *c) {
+    Batch b;
+    b.B = c->B;
+    b.T = c->T;
+    b.off = c->off;
+    b.tile_inst = c->tile_inst;
+    b.tile_row = c->tile_row;
+    b.first_tile = c->first_tile;
+    b.inst = c->inst;
+    b.grid = c->grid;
+    b.box = c->box;
+    b.rmax = c->rmax;
+    b.phase = c->phase;
+    return b;
+}
+
+CgBufs cg_bufs(const lagot_ctx *c) {
+    CgBufs g;
+    const size_t N = (size_t)c->cap_n;
+    for (int q = 0; q < 2; ++q) {
+        g.r[q] = c->cg_vec + (0 + q) * N;
+        g.w[q] = c->cg_vec + (2 + q) * N;
+        g.s[q] = c->cg_vec + (4 + q) * N;
     }
-    return LAGOT_OK;  // at the iteration cap the direction is inexact; the step control still guards it
+    g.p = c->cg_vec + 6 * N;
+    g.x = c->cg_vec + 7 * N;
+    g.part = c->cg_part;
+    g.cgs = c->cg_cgs;
+    g.cgst = c->cg_cgst;
+    g.kbase = c->misc + 2;
+    g.remaining = c->misc + 3;
+    return g;
+}
+
+// Validate the instances and sort each one spatially. On return the grid-order
+// arrays pos_s (with float32 psi), psi_s (and nu_s) are filled, rmax[b] holds
+// max sqrt(psi) of each instance, ev_nu[4b+0] = sum nu and ev_nu[4b+3] = min nu
+// (when nu is given). bad (host, B entries, may be null) flags invalid instances.
+int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const float *y, const float *z,
+            const double *psi, const double *nu, const lagot_box *boxes, std::vector<int> *bad) {
+    if (B <= 0 || !offs || !boxes || !x || !y || !z || !psi) return LAGOT_EINVAL;
+    if (offs[0] != 0) return LAGOT_EINVAL;
+    for (int b = 0; b < B; ++b)
+        if (!(offs[b + 1] > offs[b]) || !box_ok(boxes[b])) return LAGOT_EINVAL;
+    const int64_t n = offs[B];
+    if (n > (int64_t)INT32_MAX / FCAP) return LAGOT_EINVAL;
+    int64_t T64 = 0;
+    for (int b = 0; b < B; ++b) T64 += (offs[b + 1] - offs[b] + TILE - 1) / TILE;
+    const int T = (int)T64;
+    int rc = ensure_sites(c, n);
+    if (!rc) rc = ensure_inst(c, B, T);
+    if (rc) return rc;
+    c->B = B;
+    c->T = T;
+    c->n = n;
+    // tile table, boxes and (below) grids, staged in pinned memory
+    const size_t stage = sizeof(int32_t) * (2 * (size_t)(B + 1) + 2 * (size_t)T) + sizeof(BoxF) * B +
+                         sizeof(GridDesc) * B + 64;
+    rc = ensure_pinned(&c->h_stage, &c->cap_stage, stage);
+    if (rc) return rc;
+    int32_t *h_off = (int32_t *)c->h_stage;
+    int32_t *h_first = h_off + (B + 1);
+    int32_t *h_tinst = h_first + (B + 1);
+    int32_t *h_trow = h_tinst + T;
+    BoxF *h_box = (BoxF *)(h_trow + T);
+    GridDesc *h_g = (GridDesc *)(h_box + B);
+    int t = 0;
+    for (int b = 0; b < B; ++b) {
+        h_off[b] = (int32_t)offs[b];
+        h_first[b] = t;
+        for (int64_t r = offs[b]; r < offs[b + 1]; r += TILE) {
+            h_tinst[t] = b;
+            h_trow[t] = (int32_t)r;
+            ++t;
+        }
+        for (int a = 0; a < 3; ++a) {
+            h_box[b].lo[a] = (float)boxes[b].lo[a];
+            h_box[b].hi[a] = (float)boxes[b].hi[a];
+        }
+    }
+    h_off[B] = (int32_t)n;
+    h_first[B] = T;
+    hipStream_t st = c->stream;
+    HIP_TRY(hipMemcpyAsync(c->off, h_off, sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->first_tile, h_first, sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->tile_inst, h_tinst, sizeof(int32_t) * T, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->tile_row, h_trow, sizeof(int32_t) * T, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->box, h_box, sizeof(BoxF) * B, hipMemcpyHostToDevice, st));
+    const Batch bt = batch(c);
+    launch_fill_inst(st, bt, c->inst);
+    launch_zero_i32(st, c->bad_inst, B);
+    launch_validate(st, n, bt, x, y, z, psi, nu, c->bad_inst);
+    launch_gather_sites(st, n, x, y, z, psi, c->pos_orig);
+    launch_rmax(st, bt, -1, psi, c->rmax);
+    if (nu) launch_eval_reduce(st, bt, -1, nu, nu, c->part_ev, c->ev_nu);
+    // read back: bad counts, r_max, nu statistics
+    const size_t ibytes = ((sizeof(int32_t) * B + 63) / 64) * 64;
+    rc = ensure_pinned(&c->h_rd, &c->cap_rd, ibytes + sizeof(double) * 5 * B + 64);
+    if (rc) return rc;
+    int32_t *r_bad = (int32_t *)c->h_rd;
+    double *r_rmax = (double *)(c->h_rd + ibytes);
+    double *r_nu = r_rmax + B;
+    HIP_TRY(hipMemcpyAsync(r_bad, c->bad_inst, sizeof(int32_t) * B, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(r_rmax, c->rmax, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    if (nu) HIP_TRY(hipMemcpyAsync(r_nu, c->ev_nu, sizeof(double) * 4 * B, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    bool any_bad = false;
+    for (int b = 0; b < B; ++b) {
+        // every site strictly inside its box, no NaN, nu > 0, and room for air: sum nu < |box|
+        bool ok = r_bad[b] == 0 && std::isfinite(r_rmax[b]);
+        if (nu) ok = ok && r_nu[4 * b] < box_volume(boxes[b]);
+        if (bad) (*bad)[b] = !ok;
+        any_bad = any_bad || !ok;
+    }
+    if (any_bad) return LAGOT_EINVAL;
+    // one grid per instance: cell size 2 r_max (the 3x3x3 neighbourhood then covers
+    // every bisector that can cut a ball), at most 512 cells per axis and 2^24 cells
+    c->h_grid.resize(B);
+    int64_t total = 0;
+    for (int b = 0; b < B; ++b) {
+        const lagot_box &bx = boxes[b];
+        double ext = 0.0;
+        for (int a = 0; a < 3; ++a) ext = std::max(ext, bx.hi[a] - bx.lo[a]);
+        double s = std::max(2.0 * r_rmax[b], ext / 512.0);
+        int dim[3];
+        for (;;) {
+            int64_t tot = 1;
+            for (int a = 0; a < 3; ++a) {
+                dim[a] = std::max(1, (int)std::ceil((bx.hi[a] - bx.lo[a]) / s));
+                tot *= dim[a];
+            }
+            if (tot <= (1 << 24)) break;
+            s *= 1.25;
+        }
+        GridDesc g;
+        for (int a = 0; a < 3; ++a) {
+            g.lo[a] = (float)bx.lo[a];
+            g.dim[a] = dim[a];
+        }
+        g.s = (float)s;
+        g.inv_s = (float)(1.0 / s);
+        g.ncell = dim[0] * dim[1] * dim[2];
+        g.base = (int)total;
+        total += g.ncell;
+        if (total > ((int64_t)1 << 28)) return LAGOT_ECAPACITY;
+        c->h_grid[b] = g;
+    }
+    c->ncell_total = (int)total;
+    rc = ensure_cells(c, c->ncell_total);
+    if (rc) return rc;
+    std::memcpy(h_g, c->h_grid.data(), sizeof(GridDesc) * B);
+    HIP_TRY(hipMemcpyAsync(c->grid, h_g, sizeof(GridDesc) * B, hipMemcpyHostToDevice, st));
+    launch_grid_build(st, n, bt, c->ncell_total, c->pos_orig, c->keys, c->cell_count, c->cell_start, c->scan_tmp,
+                      c->perm, c->cursor);
+    launch_permute_in(st, n, c->perm, c->pos_orig, psi, nu, c->pos_s, c->psi_s, nu ? c->nu_s : nullptr);
+    return LAGOT_OK;
+}
+
+EvalOut eval_out(lagot_ctx *c, bool walls) {
+    EvalOut o{c->V, c->K, walls ? c->wall : nullptr, c->fcol, c->farea, c->fcnt, c->flags, c->fb_list, c->misc + 0,
+              c->fb_inst, c->fail_inst};
+    return o;
+}
+
+// Cells of the instances in phase `want` (< 0: all) at the float64 weights psi_eval
+// (grid order; float32 shadow in pos_s.w, r_max per instance on the device); the
+// per-instance statistics go to ev_out when it is given.
+void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double *ev_out) {
+    const Batch bt = batch(c);
+    const EvalOut o = eval_out(c, walls);
+    launch_eval_begin(c->stream, bt, want, o);
+    if (walls) (void)hipMemsetAsync(c->wall, 0, 6 * sizeof(float) * (size_t)c->n, c->stream);
+    (void)hipEventRecord(c->ev0, c->stream);
+    launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, c->tpc);
+    (void)hipEventRecord(c->ev1, c->stream);
+    c->ev_pending = true;
+    launch_cells_fallback(c->stream, bt, c->pos_s, psi_eval, c->perm, c->cell_start, o);
+    if (ev_out) launch_eval_reduce(c->stream, bt, want, c->V, c->nu_s, c->part_ev, ev_out);
+}
+
+// Phase histogram written by the last control kernel -> h_cnt[0..7].
+int read_counts(lagot_ctx *c) {
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counts, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
 }
 
 // ---- learned warm start ------------------------------------------------------
@@ -358,16 +466,13 @@ int ensure_mlp(lagot_ctx *c) {
     HIP_TRY(dalloc(&c->mlp_m1, MLP_NPARAMS));
     HIP_TRY(dalloc(&c->mlp_m2, MLP_NPARAMS));
     HIP_TRY(dalloc(&c->mlp_pb, MLP_NPARAMS));
-    if (!c->nusum) HIP_TRY(dalloc(&c->nusum, 1));
     return LAGOT_OK;
 }
 
 int ensure_inference(lagot_ctx *c, int64_t n) {
-    if (!c->nusum) HIP_TRY(dalloc(&c->nusum, 1));
     if (n <= c->cap_inf) return LAGOT_OK;
-    void *bufs[] = {c->nbr_s, c->feat_s, c->inf_a, c->inf_b, c->mlp_out};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
+    free_ptrs(c->nbr_s, c->feat_s, c->inf_a, c->inf_b, c->mlp_out);
+    c->cap_inf = 0;
     HIP_TRY(dalloc(&c->nbr_s, (size_t)n * N_NEI));
     HIP_TRY(dalloc(&c->feat_s, (size_t)n * MLP_IN));
     HIP_TRY(dalloc(&c->inf_a, (size_t)n * MLP_HID));
@@ -379,10 +484,9 @@ int ensure_inference(lagot_ctx *c, int64_t n) {
 
 int ensure_batch(lagot_ctx *c, int b) {
     if (b <= c->cap_batch) return LAGOT_OK;
-    void *bufs[] = {c->tX, c->tH1, c->tH2, c->tH3, c->tdZb, c->tZ1, c->tZ2, c->tZ3, c->tdZ, c->ty, c->tt, c->tdy,
-                    c->tpart, c->tloss};
-    for (void *p : bufs)
-        if (p) (void)hipFree(p);
+    free_ptrs(c->tX, c->tH1, c->tH2, c->tH3, c->tdZb, c->tZ1, c->tZ2, c->tZ3, c->tdZ, c->ty, c->tt, c->tdy, c->tpart,
+              c->tloss);
+    c->cap_batch = 0;
     const size_t B = (size_t)b;
     HIP_TRY(dalloc(&c->tX, B * MLP_IN));
     HIP_TRY(dalloc(&c->tH1, B * MLP_HID));
@@ -415,17 +519,15 @@ void mlp_forward_dev(lagot_ctx *c, int m, const uint16_t *X, uint16_t *a, uint16
     launch_out_layer(c->stream, m, a, P + MLP_OFF_W4, P + MLP_OFF_B4, out, nullptr, nullptr, nullptr);
 }
 
-// Inputs of every site in grid order (needs prepare() with psi = psi_prev and nu, and
-// the cell volumes at psi_prev in c->V).
-int build_features(lagot_ctx *c, int64_t n) {
-    int rc = ensure_inference(c, n);
+// Inputs of every site in grid order (one instance; needs prepare() with psi =
+// psi_prev and nu, and the cell volumes at psi_prev in c->V).
+int build_features(lagot_ctx *c) {
+    int rc = ensure_inference(c, c->n);
     if (rc) return rc;
-    const int nb = nblk256(n);
-    launch_eval_reduce(c->stream, n, c->nu_s, c->nu_s, c->partial, nb, c->red4);
-    HIP_TRY(hipMemcpyAsync(c->nusum, c->red4, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemsetAsync(c->counters + 7, 0, sizeof(int32_t), c->stream));
-    launch_knn_features(c->stream, n, c->pos_s, c->perm, c->cell_start, c->grid, c->psi_s, c->nu_s, c->nusum, c->V,
-                        c->nbr_s, c->feat_s, c->counters + 7);
+    launch_zero_i32(c->stream, c->misc + 1, 1);
+    // ev_nu[0] holds sum nu of the (single) instance
+    launch_knn_features(c->stream, c->n, c->pos_s, c->perm, c->cell_start, c->h_grid[0], c->psi_s, c->nu_s, c->ev_nu,
+                        c->V, c->nbr_s, c->feat_s, c->misc + 1);
     return LAGOT_OK;
 }
 
@@ -440,6 +542,7 @@ void fill_defaults(lagot_opts *o) {
     o->verbose = 0;
     o->use_learned = 0;
     o->empty_start_fallback = 1;
+    o->autotune = 0;
 }
 
 bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
@@ -451,143 +554,266 @@ int check_opts(const lagot_opts &o) {
     return LAGOT_OK;
 }
 
-// Damped Newton (Algorithm 1, KMT step control); max_iters = 1 for a single step.
-int newton_run(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *nu,
-               const lagot_box &box, double *psi, const lagot_opts *opts_in, lagot_stats *st, bool single) {
+// Autotuner: time the float32 cell kernel with 16, 32 and 64 lanes per cell at the
+// start weights and keep the fastest for this class of problem (log2 of the mean
+// instance size, log2 of the sites per ball volume); later calls of the class reuse it.
+int autotune_tpc(lagot_ctx *c) {
+    std::vector<double> r(c->B);
+    HIP_TRY(hipMemcpyAsync(r.data(), c->rmax, sizeof(double) * c->B, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double rm = 0.0, vol = 0.0;
+    for (int b = 0; b < c->B; ++b) {
+        rm = std::max(rm, r[b]);
+        const GridDesc &g = c->h_grid[b];
+        vol += (double)g.dim[0] * g.dim[1] * g.dim[2] * g.s * g.s * g.s;
+    }
+    const double per_ball = (double)c->n * (4.0 / 3.0) * M_PI * rm * rm * rm / std::max(vol, 1e-300);
+    const int key = (int)std::floor(std::log2((double)c->n / c->B)) * 64 +
+                    std::min(63, std::max(0, (int)std::floor(std::log2(per_ball + 1e-30)) + 32));
+    auto it = c->tpc_tuned.find(key);
+    if (it != c->tpc_tuned.end()) {
+        c->tpc = it->second;
+        return LAGOT_OK;
+    }
+    const int cand[3] = {16, 32, 64};
+    float best = 1e30f;
+    int best_t = c->tpc_default;
+    for (int t : cand) {
+        c->tpc = t;
+        for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
+            evaluate(c, -1, c->psi_s, false, nullptr);
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        c->ev_pending = false;
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    c->tpc = best_t;
+    c->tpc_tuned[key] = best_t;
+    return LAGOT_OK;
+}
+
+// One Jacobi-PCG direction solve for every ACTIVE instance, then ACTIVE -> TRIAL.
+int newton_direction(lagot_ctx *c, const lagot_opts &o) {
+    const Batch bt = batch(c);
+    const CgBufs cg = cg_bufs(c);
+    hipStream_t st = c->stream;
+    launch_hess_assemble(st, c->n, bt, PH_ACTIVE, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval, c->xcnt,
+                         c->herr);
+    launch_hess_finish(st, c->n, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hval, c->diag);
+    launch_cg_init(st, bt, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt, cg);
+    const double rtol2 = o.cg_rtol * o.cg_rtol;
+    const int cap = o.cg_max_iter;
+    int k = 0;
+    while (k < cap) {
+        const int m = std::min(c->cg_chunk, cap - k);
+        for (int q = 0; q < m; ++q) launch_cg_iter(st, bt, q, rtol2, cap, c->hcol, c->hval, c->hcnt, c->diag, cg);
+        launch_cg_advance(st, bt, m, cap, cg);
+        k += m;
+        HIP_TRY(hipMemcpyAsync(c->h_cnt + 8, c->misc + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        int rc = sync(c);
+        if (rc) return rc;
+        if (c->h_cnt[8] == 0) break;
+    }
+    // chunk length for the next direction: about this solve's iteration count
+    c->cg_chunk = std::min(64, std::max(8, (k + 3) / 4 * 4));
+    launch_cg_finish(st, bt, rtol2, cg, c->herr, c->ctl, c->phase);
+    return LAGOT_OK;
+}
+
+struct CallTimes {
+    double eval = 0, lin = 0, learned = 0;
+    int extra_evals = 0;
+};
+
+// Learned guess for a single instance, evaluated like a trial step from the start
+// weights: kept if every cell keeps eps0 and the residual drops.
+int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
+    *accepted = 0;
+    const Batch bt = batch(c);
+    hipStream_t st = c->stream;
+    double *h = (double *)c->h_rd;  // [0..3] start, [4..7] guess, [8] min nu
+    int32_t *hf = (int32_t *)(h + 12);
+    HIP_TRY(hipMemcpyAsync(h, c->ev, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h + 8, c->ev_nu + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int rc = sync(c);
+    if (rc) return rc;
+    const double eps0 = 0.5 * std::min(h[8], h[3]);
+    if (hf[0] != 0 || !(eps0 > 0.0)) return LAGOT_OK;  // Newton handles this start itself
     const double t0 = now_ms();
-    lagot_stats S;
-    std::memset(&S, 0, sizeof(S));
+    rc = build_features(c);
+    if (rc) return rc;
+    mlp_forward_dev(c, (int)c->n, c->feat_s, c->inf_a, c->inf_b, c->mlp_out);
+    launch_apply_guess(st, c->n, c->psi_s, c->nu_s, c->mlp_out, c->psi_trial, c->pos_s);
+    launch_rmax(st, bt, -1, c->psi_trial, c->rmax);
+    evaluate(c, -1, c->psi_trial, false, c->ev2);
+    tm.extra_evals++;
+    HIP_TRY(hipMemcpyAsync(h + 4, c->ev2, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf + 2, c->misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    rc = sync(c);
+    if (rc) return rc;
+    if (hf[2] == 0 && hf[1] == 0 && h[7] >= eps0 && h[6] < h[2]) {
+        HIP_TRY(hipMemcpyAsync(c->psi_s, c->psi_trial, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st));
+        *accepted = 1;
+    } else {
+        // back to the start weights; the cell outputs must describe them again
+        launch_psi_shadow(st, c->n, c->psi_s, c->pos_s);
+        launch_rmax(st, bt, -1, c->psi_s, c->rmax);
+        evaluate(c, -1, c->psi_s, false, c->ev);
+        tm.extra_evals++;
+        rc = sync(c);
+        if (rc) return rc;
+    }
+    tm.learned += now_ms() - t0;
+    return LAGOT_OK;
+}
+
+// Damped Newton (Algorithm 1, KMT step control) for every instance of the call;
+// single = true takes at most one Newton iteration per instance.
+int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const float *y, const float *z,
+               const double *nu, const lagot_box *boxes, double *psi, const lagot_opts *opts_in,
+               lagot_stats *stats, bool single) {
+    const double t0 = now_ms();
     lagot_opts o;
     if (opts_in)
         o = *opts_in;
     else
         fill_defaults(&o);
+    std::vector<int> bad(std::max(B, 1), 0);
+    auto fail_all = [&](int rc) {
+        if (stats)
+            for (int b = 0; b < B; ++b) {
+                std::memset(&stats[b], 0, sizeof(lagot_stats));
+                stats[b].status = rc;
+                stats[b].ms_total = now_ms() - t0;
+            }
+        return rc;
+    };
     int rc = check_opts(o);
-    if (!rc && !nu) rc = LAGOT_EINVAL;
-    if (!rc) {
-        c->tpc = o.threads_per_cell ? o.threads_per_cell : c->tpc_default;
-        c->fb_total = 0;
+    if (!rc && (!nu || !psi)) rc = LAGOT_EINVAL;
+    if (!rc && o.use_learned && B != 1) rc = LAGOT_EINVAL;
+    if (rc) return fail_all(rc);
+    c->tpc = o.threads_per_cell ? o.threads_per_cell : c->tpc_default;
+    c->ms_cell = 0.0;
+    c->cell_launches = 0;
+    c->ev_pending = false;
+    rc = prepare(c, B, offs, x, y, z, psi, nu, boxes, &bad);
+    if (rc) return fail_all(rc);
+    if (o.autotune && o.threads_per_cell == 0) {
+        rc = autotune_tpc(c);
+        if (rc) return fail_all(rc);
         c->ms_cell = 0.0;
         c->cell_launches = 0;
-        rc = prepare(c, n, x, y, z, psi, nu, box);
     }
-    double ms_eval = 0, ms_lin = 0;
-    if (!rc) {
-        // total prescribed volume must leave room for air: sum nu < |box|
-        const int nb = nblk256(n);
-        launch_eval_reduce(c->stream, n, c->nu_s, c->nu_s, c->partial, nb, c->red4);
-        rc = sync_read(c, c->red4, c->h_scal, 4 * sizeof(double));
-        const double box_vol = (box.hi[0] - box.lo[0]) * (box.hi[1] - box.lo[1]) * (box.hi[2] - box.lo[2]);
-        const double sum_nu = c->h_scal[0], min_nu = c->h_scal[3];
-        if (!rc && !(sum_nu < box_vol)) rc = LAGOT_EINVAL;
-        EvalStats es{};
-        if (!rc) {
-            const double te = now_ms();
-            rc = evaluate_reduce(c, n, box, &es, c->psi_s);
-            ms_eval += now_ms() - te;
-            S.evals = 1;
-        }
-        // learned warm start: accepted only if every cell keeps volume and ||nu - V|| drops
-        if (!rc && !single && o.use_learned && c->mlp_set && es.fail == 0) {
-            const double tg = now_ms();
-            rc = build_features(c, n);
-            if (!rc) {
-                mlp_forward_dev(c, (int)n, c->feat_s, c->inf_a, c->inf_b, c->mlp_out);
-                launch_apply_guess(c->stream, n, c->psi_s, c->nu_s, c->mlp_out, c->psi_trial, c->pos_s,
-                                   c->rmax_partial);
-                launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
-                EvalStats eg{};
-                rc = evaluate_reduce(c, n, box, &eg, c->psi_trial);
-                S.evals++;
-                if (!rc && eg.fail == 0 && eg.minV > 0.0 && eg.gnorm < es.gnorm) {
-                    std::swap(c->psi_s, c->psi_trial);
-                    es = eg;
-                    S.learned_accepted = 1;
-                } else if (!rc) {
-                    launch_psi_shadow(c->stream, n, c->psi_s, c->pos_s);
-                    launch_gather_rmax(c->stream, n, c->psi_s, c->rmax_partial);
-                    launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
-                }
-            }
-            S.ms_learned = now_ms() - tg;
-        }
-        // a start with an empty cell (eps0 = 0) is replaced by the default start weights
-        if (!rc && !(es.minV > 0.0) && o.empty_start_fallback) {
-            launch_default_start(c->stream, n, c->nu_s, c->psi_s, c->pos_s, c->rmax_partial);
-            launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
-            rc = evaluate_reduce(c, n, box, &es, c->psi_s);
-            S.evals++;
-            S.default_start = 1;
-        }
-        double eps0 = 0.5 * std::min(min_nu, es.minV);
-        if (!rc && !(eps0 > 0.0)) rc = LAGOT_EEMPTY;
-        if (!rc && es.fail) rc = LAGOT_ECAPACITY;
-        int it = 0;
-        while (!rc) {
-            S.max_rel_err = es.maxrel;
-            S.grad_norm = es.gnorm;
-            if (o.verbose)
-                fprintf(stderr, "lagot newton it=%d max_rel_err=%.3e |g|=%.3e minV=%.3e fallback=%d\n", it,
-                        es.maxrel, es.gnorm, es.minV, es.fb);
-            if (es.maxrel <= o.tol) break;
-            if (it >= o.max_newton || (single && it >= 1)) {
-                rc = single ? LAGOT_OK : LAGOT_ENOCONV;
-                break;
-            }
-            const double tl = now_ms();
-            int cgi = 0;
-            rc = newton_direction(c, n, o, &cgi);
-            ms_lin += now_ms() - tl;
-            S.cg_iters += cgi;
-            if (rc) break;
-            double alpha = 1.0;
-            bool accepted = false;
-            EvalStats et{};
-            for (int h = 0; h <= o.max_halvings; ++h) {
-                const int nb2 = nblk256(n);
-                launch_axpy_trial(c->stream, n, c->psi_s, c->x, alpha, c->psi_trial, c->pos_s, c->rmax_partial);
-                launch_reduce_max(c->stream, c->rmax_partial, nb2, c->rmax);
-                const double te = now_ms();
-                rc = evaluate_reduce(c, n, box, &et, c->psi_trial);
-                ms_eval += now_ms() - te;
-                S.evals++;
-                if (rc) break;
-                if (et.fail == 0 && et.minV >= eps0 && et.gnorm <= (1.0 - 0.5 * alpha) * es.gnorm) {
-                    accepted = true;
-                    break;
-                }
-                alpha *= 0.5;
-                S.halvings++;
-            }
-            if (rc) break;
-            if (!accepted) {
-                // restore the float32 shadow and r_max of the last accepted weights
-                launch_psi_shadow(c->stream, n, c->psi_s, c->pos_s);
-                launch_gather_rmax(c->stream, n, c->psi_s, c->rmax_partial);
-                launch_reduce_max(c->stream, c->rmax_partial, nblk256(n), c->rmax);
-                rc = et.fail ? LAGOT_ECAPACITY : LAGOT_ELINESEARCH;
-                break;
-            }
-            std::swap(c->psi_s, c->psi_trial);
-            es = et;
-            ++it;
-            S.newton_iters = it;
-        }
-        S.max_rel_err = es.maxrel;
-        S.grad_norm = es.gnorm;
-        if (rc != LAGOT_EINVAL && rc != LAGOT_EHIP) {
-            launch_scatter_out_f64(c->stream, n, c->perm, c->psi_s, psi);
-            if (hipStreamSynchronize(c->stream) != hipSuccess) rc = LAGOT_EHIP;
-        }
+    const Batch bt = batch(c);
+    hipStream_t st = c->stream;
+    CtlOpts co{o.tol, o.max_newton, o.max_halvings, single ? 1 : 0, o.empty_start_fallback ? 1 : 0};
+    CallTimes tm;
+    int learned = 0;
+    launch_zero_i32(st, c->fb_inst, B);
+    launch_ctl_init(st, bt, c->ctl, c->phase);
+    double te = now_ms();
+    evaluate(c, PH_START, c->psi_s, false, c->ev);
+    if (o.use_learned && c->mlp_set) {
+        rc = learned_guess(c, tm, &learned);
+        if (rc) return fail_all(rc);
     }
-    S.fallback_cells = c->fb_total;
-    S.cell_launches = c->cell_launches;
-    S.ms_cell_kernel = c->ms_cell;
-    S.status = rc;
-    S.ms_eval = ms_eval;
-    S.ms_linear = ms_lin;
-    S.ms_total = now_ms() - t0;
-    if (st) *st = S;
+    // the KMT floor eps0 comes from the given start weights (ev); a kept guess supplies
+    // the statistics of the first iterate (ev2)
+    launch_ctl_start(st, bt, co, PH_START, learned ? c->ev2 : c->ev, c->ev_nu, c->ev, c->fail_inst, c->ctl, c->phase,
+                     c->counts);
+    rc = read_counts(c);
+    if (rc) return fail_all(rc);
+    if (c->h_cnt[PH_RESTART] > 0) {
+        launch_default_start(st, bt, PH_RESTART, c->nu_s, c->psi_s, c->pos_s);
+        launch_rmax(st, bt, PH_RESTART, c->psi_s, c->rmax);
+        evaluate(c, PH_RESTART, c->psi_s, false, c->ev);
+        launch_ctl_start(st, bt, co, PH_RESTART, c->ev, c->ev_nu, c->ev, c->fail_inst, c->ctl, c->phase, c->counts);
+        rc = read_counts(c);
+        if (rc) return fail_all(rc);
+    }
+    tm.eval += now_ms() - te - tm.learned;
+    int round = 0;
+    while (c->h_cnt[PH_ACTIVE] > 0) {
+        const double tl = now_ms();
+        rc = newton_direction(c, o);
+        if (rc) return fail_all(rc);
+        tm.lin += now_ms() - tl;
+        te = now_ms();
+        for (int h = 0; h <= o.max_halvings; ++h) {
+            launch_axpy_trial(st, bt, c->ctl, c->psi_s, cg_bufs(c).x, c->psi_trial, c->pos_s);
+            launch_rmax(st, bt, PH_TRIAL, c->psi_trial, c->rmax);
+            evaluate(c, PH_TRIAL, c->psi_trial, false, c->ev);
+            launch_ctl_decide(st, bt, co, c->ev, c->fail_inst, c->ctl, c->phase);
+            launch_accept_rows(st, bt, c->ctl, c->psi_s, c->psi_trial, c->pos_s);
+            launch_ctl_commit(st, bt, co, c->ctl, c->phase, c->counts);
+            rc = read_counts(c);
+            if (rc) return fail_all(rc);
+            if (c->h_cnt[PH_TRIAL] == 0) break;
+        }
+        tm.eval += now_ms() - te;
+        ++round;
+        if (o.verbose)
+            fprintf(stderr, "lagot newton round %d: active %d done %d failed %d\n", round, c->h_cnt[PH_ACTIVE],
+                    c->h_cnt[PH_DONE], c->h_cnt[PH_FAILED]);
+    }
+    // weights back to caller order (every instance holds its last accepted iterate)
+    launch_scatter_out_f64(st, c->n, c->perm, c->psi_s, psi);
+    std::vector<InstCtl> hc(B);
+    std::vector<int32_t> hfb(B), hfail(B);
+    HIP_TRY(hipMemcpyAsync(hc.data(), c->ctl, sizeof(InstCtl) * B, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hfb.data(), c->fb_inst, sizeof(int32_t) * B, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hfail.data(), c->fail_inst, sizeof(int32_t) * B, hipMemcpyDeviceToHost, st));
+    rc = sync(c);
+    if (rc) return fail_all(rc);
+    const double ms_total = now_ms() - t0;
+    int first = LAGOT_OK;
+    for (int b = 0; b < B; ++b) {
+        const InstCtl &q = hc[b];
+        if (first == LAGOT_OK && q.status != LAGOT_OK) first = q.status;
+        if (!stats) continue;
+        lagot_stats &S = stats[b];
+        std::memset(&S, 0, sizeof(S));
+        S.status = q.status;
+        S.newton_iters = q.iters;
+        S.evals = q.evals + (B == 1 ? tm.extra_evals : 0);
+        S.halvings = q.halvings;
+        S.cg_iters = q.cg_iters;
+        S.fallback_cells = hfb[b];
+        S.failed_cells = hfail[b];
+        S.cell_launches = c->cell_launches;
+        S.learned_accepted = learned;
+        S.default_start = q.default_start;
+        S.max_rel_err = q.maxrel;
+        S.grad_norm = q.gnorm;
+        S.ms_total = ms_total;
+        S.ms_eval = tm.eval;
+        S.ms_linear = tm.lin;
+        S.ms_cell_kernel = c->ms_cell;
+        S.ms_learned = tm.learned;
+    }
+    return first;
+}
+
+int single_instance(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *nu,
+                    const lagot_box &box, double *psi, const lagot_opts *opts, lagot_stats *stats, bool single) {
+    if (n <= 0) {
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->status = LAGOT_EINVAL;
+        }
+        return LAGOT_EINVAL;
+    }
+    const int64_t offs[2] = {0, n};
+    lagot_stats S;
+    const int rc = newton_run(c, 1, offs, x, y, z, nu, &box, psi, opts, &S, single);
+    if (stats) *stats = S;
     return rc;
 }
 
@@ -608,9 +834,7 @@ int lagot_create(lagot_ctx **out, int device, void *stream) {
     lagot_ctx *c = new lagot_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
-    if (dalloc(&c->counters, 8) != hipSuccess || dalloc(&c->scal, 16) != hipSuccess ||
-        dalloc(&c->red4, 4) != hipSuccess || dalloc(&c->rmax, 1) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_scal, 16 * sizeof(double)) != hipSuccess ||
+    if (dalloc(&c->counts, 8) != hipSuccess || dalloc(&c->misc, 8) != hipSuccess ||
         hipHostMalloc((void **)&c->h_cnt, 16 * sizeof(int32_t)) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         free_all(c);
@@ -632,28 +856,32 @@ void lagot_destroy(lagot_ctx *ctx) {
 int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
                 lagot_box box, double *vol, double *sph_area, float *wall_area, int64_t *row_ptr, int32_t *col,
                 float *facet_area, int64_t nnz_cap, int64_t *nnz_out) {
-    if (!c || !vol) return LAGOT_EINVAL;
+    if (!c || !vol || n <= 0) return LAGOT_EINVAL;
     const bool csr = row_ptr || col || facet_area;
     if (csr && !(row_ptr && col && facet_area && nnz_cap >= 0)) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
-    c->fb_total = 0;
     c->tpc = c->tpc_default;
-    int rc = prepare(c, n, x, y, z, psi, nullptr, box);
-    if (rc) return rc;
-    evaluate(c, n, box, wall_area != nullptr, c->psi_s);
-    launch_scatter_out_f64(c->stream, n, c->perm, c->V, vol);
-    if (sph_area) launch_scatter_out_f64(c->stream, n, c->perm, c->K, sph_area);
-    if (wall_area) launch_scatter_walls(c->stream, n, c->perm, c->wall, wall_area);
-    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    if (csr || nnz_out) {
-        launch_csr_count(c->stream, n, c->perm, c->fcnt, c->csr_cnt);
-        launch_scan_i32(c->stream, c->csr_cnt, c->csr_start, (int)n, c->csr_tmp);
-        HIP_TRY(hipMemcpyAsync(c->h_cnt + 4, c->csr_start + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    }
-    HIP_TRY(hipStreamSynchronize(c->stream));
     c->ms_cell = 0.0;
     c->cell_launches = 0;
-    collect_cell_time(c);
+    c->ev_pending = false;
+    const int64_t offs[2] = {0, n};
+    int rc = prepare(c, 1, offs, x, y, z, psi, nullptr, &box, nullptr);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    launch_zero_i32(st, c->fb_inst, 1);
+    evaluate(c, -1, c->psi_s, wall_area != nullptr, nullptr);
+    launch_scatter_out_f64(st, n, c->perm, c->V, vol);
+    if (sph_area) launch_scatter_out_f64(st, n, c->perm, c->K, sph_area);
+    if (wall_area) launch_scatter_walls(st, n, c->perm, c->wall, wall_area);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->misc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (csr || nnz_out) {
+        launch_csr_count(st, n, c->perm, c->fcnt, c->csr_cnt);
+        launch_scan_i32(st, c->csr_cnt, c->csr_start, (int)n, c->csr_tmp);
+        HIP_TRY(hipMemcpyAsync(c->h_cnt + 4, c->csr_start + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
+    rc = sync(c);
+    if (rc) return rc;
     c->last_fb = c->h_cnt[0];
     if (c->h_cnt[1] != 0) return LAGOT_ECAPACITY;
     if (csr || nnz_out) {
@@ -661,9 +889,8 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
         if (nnz_out) *nnz_out = nnz;
         if (csr) {
             if (nnz > nnz_cap) return LAGOT_ECAPACITY;
-            launch_csr_fill(c->stream, n, c->perm, c->fcol, c->farea, c->fcnt, c->csr_start, col, facet_area,
-                            row_ptr);
-            HIP_TRY(hipStreamSynchronize(c->stream));
+            launch_csr_fill(st, n, c->perm, c->fcol, c->farea, c->fcnt, c->csr_start, col, facet_area, row_ptr);
+            HIP_TRY(hipStreamSynchronize(st));
         }
     }
     return LAGOT_OK;
@@ -673,14 +900,22 @@ int lagot_newton_step(lagot_ctx *ctx, int64_t n, const float *x, const float *y,
                       lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats) {
     if (!ctx || !psi_inout) return LAGOT_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
-    return newton_run(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, true);
+    return single_instance(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, true);
 }
 
 int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
                 lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats) {
     if (!ctx || !psi_inout) return LAGOT_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
-    return newton_run(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, false);
+    return single_instance(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, false);
+}
+
+int lagot_solve_batched(lagot_ctx *ctx, int32_t n_inst, const int64_t *offsets, const float *x, const float *y,
+                        const float *z, const double *nu, const lagot_box *boxes, double *psi_inout,
+                        const lagot_opts *opts, lagot_stats *per_inst) {
+    if (!ctx || !psi_inout || n_inst <= 0 || !offsets || !boxes) return LAGOT_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
+    return newton_run(ctx, n_inst, offsets, x, y, z, nu, boxes, psi_inout, opts, per_inst, false);
 }
 
 int lagot_mlp_set_params(lagot_ctx *c, const float *params) {
@@ -708,17 +943,22 @@ int lagot_mlp_get_params(lagot_ctx *c, float *params) {
 
 int lagot_features(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi_prev,
                    const double *nu, lagot_box box, int32_t *nbr, uint16_t *feats) {
-    if (!c || !nu || (!nbr && !feats)) return LAGOT_EINVAL;
+    if (!c || !nu || (!nbr && !feats) || n <= 0) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
-    int rc = prepare(c, n, x, y, z, psi_prev, nu, box);
+    c->tpc = c->tpc_default;
+    c->ev_pending = false;
+    const int64_t offs[2] = {0, n};
+    int rc = prepare(c, 1, offs, x, y, z, psi_prev, nu, &box, nullptr);
     if (rc) return rc;
-    evaluate(c, n, box, false, c->psi_s);  // volumes under the previous weights are inputs too
-    rc = build_features(c, n);
+    launch_zero_i32(c->stream, c->fb_inst, 1);
+    evaluate(c, -1, c->psi_s, false, nullptr);  // volumes under the previous weights are inputs too
+    rc = build_features(c);
     if (rc) return rc;
     if (nbr) launch_scatter_rows(c->stream, n, N_NEI * 4, c->perm, c->nbr_s, nbr);
     if (feats) launch_scatter_rows(c->stream, n, MLP_IN * 2, c->perm, c->feat_s, feats);
-    HIP_TRY(hipMemcpyAsync(c->h_cnt + 7, c->counters + 7, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 7, c->misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    rc = sync(c);
+    if (rc) return rc;
     return c->h_cnt[7] ? LAGOT_ECAPACITY : LAGOT_OK;
 }
 

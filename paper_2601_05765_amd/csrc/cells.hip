@@ -183,12 +183,11 @@ template <typename R, int CMAX, int PMAX, int VMAX> struct CellSmem {
 struct CellArgs {
     int64_t n;
     const float4 *pos_s;      // x, y, z, float32 psi (grid order)
-    const double *psi_s;      // float64 psi (grid order)
+    const double *psi_s;      // float64 psi being evaluated (grid order)
     const int32_t *perm;      // grid order -> caller index (tie rule for coincident sites)
     const int32_t *cell_start;
-    GridDesc g;
-    BoxF box;
-    const double *rmax;
+    Batch bt;                 // instance of each row, its grid, box and r_max
+    int want;                 // evaluate the instances in this phase (< 0: all)
     EvalOut out;
 };
 
@@ -208,6 +207,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
 
     R px = 0, py = 0, pz = 0, psi_i = 0;
     double psi_i64 = 0.0;
+    const int inst = act ? A.bt.inst[cell] : 0;
     if (act) {
         const float4 p4 = A.pos_s[cell];
         px = p4.x;
@@ -225,12 +225,13 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     bool inside = true;
     bool empty = false;
     if (live) {
-        const float reach = ((float)r + (float)(*A.rmax)) * 1.0001f;
+        const GridDesc gd = A.bt.grid[inst];
+        const float reach = ((float)r + (float)A.bt.rmax[inst]) * 1.0001f;
         int lo3[3], hi3[3];
         const float pp[3] = {(float)px, (float)py, (float)pz};
         for (int a = 0; a < 3; ++a) {
-            lo3[a] = max((int)floorf((pp[a] - reach - A.g.lo[a]) * A.g.inv_s), 0);
-            hi3[a] = min((int)floorf((pp[a] + reach - A.g.lo[a]) * A.g.inv_s), A.g.dim[a] - 1);
+            lo3[a] = max((int)floorf((pp[a] - reach - gd.lo[a]) * gd.inv_s), 0);
+            hi3[a] = min((int)floorf((pp[a] + reach - gd.lo[a]) * gd.inv_s), gd.dim[a] - 1);
         }
         const int nyc = hi3[1] - lo3[1] + 1;
         const int ncol = (hi3[0] - lo3[0] + 1) * nyc;
@@ -239,7 +240,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             int cbeg = 0, cend = 0;
             if (c0 + gl < ncol) {
                 const int ix = lo3[0] + (c0 + gl) / nyc, iy = lo3[1] + (c0 + gl) % nyc;
-                const int col = (ix * A.g.dim[1] + iy) * A.g.dim[2];
+                const int col = gd.base + (ix * gd.dim[1] + iy) * gd.dim[2];
                 cbeg = A.cell_start[col + lo3[2]];
                 cend = A.cell_start[col + hi3[2] + 1];
             }
@@ -295,12 +296,13 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
         // box walls -x,+x,-y,+y,-z,+z: t = distance from p_i to the wall
         {
+            const BoxF box = A.bt.box[inst];
             bool keep = false;
             R t = 0;
             if (gl < 6) {
                 const int ax = gl >> 1;
                 const R pc = ax == 0 ? px : (ax == 1 ? py : pz);
-                t = (gl & 1) ? (R)A.box.hi[ax] - pc : pc - (R)A.box.lo[ax];
+                t = (gl & 1) ? (R)box.hi[ax] - pc : pc - (R)box.lo[ax];
                 keep = t < r;
             }
             const unsigned long long b = gballot<G>(keep);
@@ -663,8 +665,9 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         if (fast && (flags & (CF_FAIL_MASK | CF_PREC))) {
             const int slot = atomicAdd(o.fb_count, 1);
             o.fb_list[slot] = (int32_t)cell;
+            atomicAdd(o.fb_inst + inst, 1);
         } else if (!fast && (flags & CF_FAIL_MASK)) {
-            atomicAdd(o.fail_count, 1);
+            atomicAdd(o.fail_inst + inst, 1);
         }
     }
 }
@@ -673,8 +676,9 @@ template <int G>
 __global__ __launch_bounds__(64) void k_cells_fast(CellArgs A) {
     __shared__ CellSmem<float, FAST_CMAX, FAST_PMAX, FAST_VMAX> smem[64 / G];
     const int gi = (int)(threadIdx.x / G);
-    const int64_t cell = (int64_t)blockIdx.x * (64 / G) + gi;
-    cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX>(cell < A.n ? cell : -1, A, smem[gi], true);
+    int64_t cell = (int64_t)blockIdx.x * (64 / G) + gi;
+    if (cell >= A.n || !selected(A.bt, A.want, A.bt.inst[cell])) cell = -1;
+    cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX>(cell, A, smem[gi], true);
 }
 
 __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
@@ -687,11 +691,23 @@ __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
     }
 }
 
+// Clears the per-evaluation counters: the float64 work list and the failure
+// counts of the selected instances (a kernel, so the sequence can be captured).
+__global__ __launch_bounds__(1024) void k_eval_begin(Batch bt, int want, EvalOut o) {
+    if (threadIdx.x == 0) *o.fb_count = 0;
+    for (int b = threadIdx.x; b < bt.B; b += 1024)
+        if (selected(bt, want, b)) o.fail_inst[b] = 0;
+}
+
 }  // namespace
 
-void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
-                  const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc) {
-    CellArgs a{n, pos_s, psi_s, perm, cell_start, g, box, rmax, out};
+void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out) {
+    hipLaunchKernelGGL(k_eval_begin, dim3(1), dim3(1024), 0, st, bt, want, out);
+}
+
+void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s, const double *psi,
+                  const int32_t *perm, const int32_t *cell_start, EvalOut out, int tpc) {
+    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out};
     if (tpc == 8) {
         hipLaunchKernelGGL(k_cells_fast<8>, dim3((unsigned)((n + 7) / 8)), dim3(64), 0, st, a);
     } else if (tpc == 32) {
@@ -703,9 +719,11 @@ void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const double *
     }
 }
 
-void launch_cells_fallback(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
-                           const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out) {
-    CellArgs a{n, pos_s, psi_s, perm, cell_start, g, box, rmax, out};
+// The float64 path takes the cells listed by the float32 pass (all of them from
+// selected instances); it reads the list length on the device.
+void launch_cells_fallback(hipStream_t st, const Batch &bt, const float4 *pos_s, const double *psi,
+                           const int32_t *perm, const int32_t *cell_start, EvalOut out) {
+    CellArgs a{0, pos_s, psi, perm, cell_start, bt, -1, out};
     hipLaunchKernelGGL(k_cells_big, dim3(512), dim3(64), 0, st, a);
 }
 

@@ -6,7 +6,10 @@
 // ceil((r_i + r_max)/s) of site i (section 4 "Finding Contributing Neighbors":
 // the ball bound replaces the security radius and is exact for restricted
 // cells). Sites are counting-sorted by grid cell (z fastest), and within a grid
-// cell by caller index, so the order is deterministic.
+// cell by caller index, so the order is deterministic. In a batched call every
+// instance has its own grid (its own box and r_max); the grids are laid end to
+// end in one cell array, so one sort orders all instances and keeps each one in
+// its own row range.
 #include "lagot_internal.h"
 
 namespace lagot {
@@ -94,36 +97,46 @@ void exclusive_scan(hipStream_t st, const int32_t *in, int32_t *out, int n, int3
 
 __global__ void k_gather_sites(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
                                const float *__restrict__ z, const double *__restrict__ psi,
-                               float4 *__restrict__ pos, double *__restrict__ rmax_partial) {
-    __shared__ double red[4];
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                               float4 *__restrict__ pos) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pos[i] = make_float4(x[i], y[i], z[i], (float)psi[i]);
+}
+
+__global__ void k_zero_i32(int32_t *p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// instance of every row, from the tile table (one 64-lane block per tile)
+__global__ __launch_bounds__(TILE) void k_fill_inst(Batch bt, int32_t *__restrict__ inst) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    const int row = bt.tile_row[t] + (int)threadIdx.x;
+    if (row < bt.off[b + 1]) inst[row] = b;
+}
+
+__global__ __launch_bounds__(1024) void k_rmax_zero(Batch bt, int want, double *__restrict__ rmax) {
+    for (int b = threadIdx.x; b < bt.B; b += 1024)
+        if (selected(bt, want, b)) rmax[b] = 0.0;
+}
+
+// rmax[b] = max over rows of sqrt(psi); a tile lies in one instance, so one
+// wave-wide max and one atomic per tile (max is order-independent: deterministic)
+__global__ __launch_bounds__(TILE) void k_rmax_tiles(Batch bt, int want, const double *__restrict__ psi,
+                                                      double *__restrict__ rmax) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (!selected(bt, want, b)) return;
+    const int row = bt.tile_row[t] + (int)threadIdx.x;
     double r = 0.0;
-    if (i < n) {
-        double p = psi[i];
-        pos[i] = make_float4(x[i], y[i], z[i], (float)p);
+    if (row < bt.off[b + 1]) {
+        const double p = psi[row];
         r = p > 0.0 ? sqrt(p) : 0.0;
     }
     for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
-        rmax_partial[blockIdx.x] = m;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_reduce_max(const double *partial, int nb, double *out) {
-    __shared__ double red[16];
-    double m = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 1024) m = fmax(m, partial[i]);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < 16; ++k) m = fmax(m, red[k]);
-        *out = fmax(red[0], m);
-    }
+    // non-negative doubles order like their bit patterns
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(rmax + b), (unsigned long long)__double_as_longlong(r));
 }
 
 __device__ inline int grid_key(const GridDesc &g, float px, float py, float pz) {
@@ -136,12 +149,13 @@ __device__ inline int grid_key(const GridDesc &g, float px, float py, float pz) 
     return (ix * g.dim[1] + iy) * g.dim[2] + iz;
 }
 
-__global__ void k_keys_count(int64_t n, const float4 *__restrict__ pos, GridDesc g, int32_t *__restrict__ keys,
+__global__ void k_keys_count(int64_t n, Batch bt, const float4 *__restrict__ pos, int32_t *__restrict__ keys,
                              int32_t *__restrict__ count) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const GridDesc g = bt.grid[bt.inst[i]];
     float4 p = pos[i];
-    int k = grid_key(g, p.x, p.y, p.z);
+    int k = g.base + grid_key(g, p.x, p.y, p.z);
     keys[i] = k;
     atomicAdd(&count[k], 1);
 }
@@ -194,18 +208,20 @@ __global__ void k_scatter_out(int64_t n, const int32_t *__restrict__ perm, const
     dst[perm[k]] = src[k];
 }
 
-// Count invalid inputs: NaN, site not strictly inside the box, nu <= 0.
-__global__ void k_validate(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
+// Count invalid inputs per instance: NaN, site not strictly inside its box, nu <= 0.
+__global__ void k_validate(int64_t n, Batch bt, const float *__restrict__ x, const float *__restrict__ y,
                            const float *__restrict__ z, const double *__restrict__ psi, const double *__restrict__ nu,
-                           BoxF box, int32_t *bad) {
+                           int32_t *bad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int b = bt.inst[i];
+    const BoxF box = bt.box[b];
     float p[3] = {x[i], y[i], z[i]};
     bool ok = true;
     for (int a = 0; a < 3; ++a) ok = ok && (p[a] > box.lo[a]) && (p[a] < box.hi[a]);  // false for NaN
     if (psi) ok = ok && !isnan(psi[i]);
     if (nu) ok = ok && (nu[i] > 0.0);
-    if (!ok) atomicAdd(bad, 1);
+    if (!ok) atomicAdd(bad + b, 1);
 }
 
 // facet counts per caller row
@@ -250,35 +266,17 @@ __global__ void k_scatter_walls(int64_t n, const int32_t *__restrict__ perm, con
     for (int a = 0; a < 6; ++a) w[i * 6 + a] = ws[k * 6 + a];
 }
 
-__global__ void k_rmax_partial(int64_t n, const double *__restrict__ psi, double *__restrict__ partial) {
-    __shared__ double red[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double r = 0.0;
-    if (i < n) {
-        const double p = psi[i];
-        r = p > 0.0 ? sqrt(p) : 0.0;
-    }
-    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-}
-
-// default start weights: ball radius 1.2 (3 nu / 4 pi)^(1/3)
-__global__ void k_default_start(int64_t n, const double *__restrict__ nu, double *__restrict__ psi,
-                                float4 *__restrict__ pos, double *__restrict__ partial) {
-    __shared__ double red[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double r = 0.0;
-    if (i < n) {
-        r = 1.2 * cbrt(3.0 * nu[i] / (4.0 * 3.14159265358979323846));
-        psi[i] = r * r;
-        pos[i].w = (float)(r * r);
-    }
-    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+// default start weights of the selected instances: ball radius 1.2 (3 nu / 4 pi)^(1/3)
+__global__ __launch_bounds__(TILE) void k_default_start(Batch bt, int want, const double *__restrict__ nu,
+                                                         double *__restrict__ psi, float4 *__restrict__ pos) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (!selected(bt, want, b)) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    if (i >= bt.off[b + 1]) return;
+    const double r = 1.2 * cbrt(3.0 * nu[i] / (4.0 * 3.14159265358979323846));
+    psi[i] = r * r;
+    pos[i].w = (float)(r * r);
 }
 
 // dst row perm[k] = src row k, rows of `chunks` 16-byte words
@@ -295,13 +293,22 @@ inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_default_start(hipStream_t st, int64_t n, const double *nu_s, double *psi_s, float4 *pos_s,
-                          double *rmax_partial) {
-    hipLaunchKernelGGL(k_default_start, dim3(nblocks(n, 256)), dim3(256), 0, st, n, nu_s, psi_s, pos_s, rmax_partial);
+void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *nu_s, double *psi_s,
+                          float4 *pos_s) {
+    hipLaunchKernelGGL(k_default_start, dim3(bt.T), dim3(TILE), 0, st, bt, want, nu_s, psi_s, pos_s);
 }
 
-void launch_gather_rmax(hipStream_t st, int64_t n, const double *psi, double *partial) {
-    hipLaunchKernelGGL(k_rmax_partial, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi, partial);
+void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst) {
+    hipLaunchKernelGGL(k_fill_inst, dim3(bt.T), dim3(TILE), 0, st, bt, inst);
+}
+
+void launch_zero_i32(hipStream_t st, int32_t *p, int64_t count) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(nblocks(count, 256)), dim3(256), 0, st, p, count);
+}
+
+void launch_rmax(hipStream_t st, const Batch &bt, int want, const double *psi, double *rmax) {
+    hipLaunchKernelGGL(k_rmax_zero, dim3(1), dim3(1024), 0, st, bt, want, rmax);
+    hipLaunchKernelGGL(k_rmax_tiles, dim3(bt.T), dim3(TILE), 0, st, bt, want, psi, rmax);
 }
 
 void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t *perm, const void *src, void *dst) {
@@ -329,23 +336,22 @@ void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const 
 }
 
 void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float *y, const float *z,
-                         const double *psi, float4 *pos_orig, double *rmax_partial, int nblk) {
-    hipLaunchKernelGGL(k_gather_sites, dim3(nblk), dim3(256), 0, st, n, x, y, z, psi, pos_orig, rmax_partial);
+                         const double *psi, float4 *pos_orig) {
+    hipLaunchKernelGGL(k_gather_sites, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x, y, z, psi, pos_orig);
 }
 
-void launch_reduce_max(hipStream_t st, const double *partial, int nblk, double *out) {
-    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(1024), 0, st, partial, nblk, out);
-}
-
-void launch_grid_build(hipStream_t st, int64_t n, const float4 *pos_orig, GridDesc g, int32_t *keys,
-                       int32_t *cell_count, int32_t *cell_start, int32_t *scan_tmp, int32_t *perm,
+// Counting sort by (instance grid base + cell): cell_count is cleared with a
+// kernel, not a memset, so the sequence can be captured in a graph.
+void launch_grid_build(hipStream_t st, int64_t n, const Batch &bt, int ncell_total, const float4 *pos_orig,
+                       int32_t *keys, int32_t *cell_count, int32_t *cell_start, int32_t *scan_tmp, int32_t *perm,
                        int32_t *cursor) {
-    (void)hipMemsetAsync(cell_count, 0, sizeof(int32_t) * (size_t)g.ncell, st);
-    hipLaunchKernelGGL(k_keys_count, dim3(nblocks(n, 256)), dim3(256), 0, st, n, pos_orig, g, keys, cell_count);
-    exclusive_scan(st, cell_count, cell_start, g.ncell, scan_tmp);
-    (void)hipMemcpyAsync(cursor, cell_start, sizeof(int32_t) * (size_t)g.ncell, hipMemcpyDeviceToDevice, st);
+    launch_zero_i32(st, cell_count, ncell_total);
+    hipLaunchKernelGGL(k_keys_count, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, pos_orig, keys, cell_count);
+    exclusive_scan(st, cell_count, cell_start, ncell_total, scan_tmp);
+    (void)hipMemcpyAsync(cursor, cell_start, sizeof(int32_t) * (size_t)ncell_total, hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(n, 256)), dim3(256), 0, st, n, keys, cursor, perm);
-    hipLaunchKernelGGL(k_sort_cells, dim3(nblocks(g.ncell, 256)), dim3(256), 0, st, g.ncell, cell_start, perm);
+    hipLaunchKernelGGL(k_sort_cells, dim3(nblocks(ncell_total, 256)), dim3(256), 0, st, ncell_total, cell_start,
+                       perm);
 }
 
 void launch_permute_in(hipStream_t st, int64_t n, const int32_t *perm, const float4 *pos_orig, const double *psi,
@@ -362,9 +368,9 @@ void launch_scatter_out_f64(hipStream_t st, int64_t n, const int32_t *perm, cons
     hipLaunchKernelGGL(k_scatter_out, dim3(nblocks(n, 256)), dim3(256), 0, st, n, perm, src_s, dst);
 }
 
-void launch_validate(hipStream_t st, int64_t n, const float *x, const float *y, const float *z, const double *psi,
-                     const double *nu, BoxF box, int32_t *bad) {
-    hipLaunchKernelGGL(k_validate, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x, y, z, psi, nu, box, bad);
+void launch_validate(hipStream_t st, int64_t n, const Batch &bt, const float *x, const float *y, const float *z,
+                     const double *psi, const double *nu, int32_t *bad_inst) {
+    hipLaunchKernelGGL(k_validate, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, x, y, z, psi, nu, bad_inst);
 }
 
 }  // namespace lagot

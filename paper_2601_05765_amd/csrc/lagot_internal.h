@@ -44,10 +44,68 @@ struct GridDesc {
     float s;          // grid cell size
     int dim[3];       // cells per axis
     int ncell;        // dim[0]*dim[1]*dim[2]
+    int base;         // first entry of this grid in the shared cell_start array
 };
 
 struct BoxF {
     float lo[3], hi[3];
+};
+
+// ---- instances -------------------------------------------------------------
+// A call solves B independent instances (B = 1 for lagot_solve). Instance b owns
+// rows [off[b], off[b+1]) in caller order and in grid order alike: each instance
+// has its own grid over its own box, and the spatial sort never moves a site out
+// of its instance's range. Row-parallel kernels run over TILE-row tiles that
+// never straddle two instances, so per-instance reductions are sums over a
+// contiguous run of tile partials (fixed order, deterministic).
+constexpr int TILE = 64;
+
+// Per-instance control phase (device array, read by every kernel that may skip
+// an instance).
+enum Phase : int32_t {
+    PH_DONE = 0,     // converged (or a single step taken): nothing more to do
+    PH_ACTIVE = 1,   // accepted iterate above tolerance: needs a Newton direction
+    PH_TRIAL = 2,    // in the step-size search
+    PH_ACCEPT = 3,   // trial accepted in this round (transient)
+    PH_FAILED = 4,   // stopped with an error status
+    PH_START = 5,    // initial evaluation pending
+    PH_RESTART = 6,  // empty start cell: restart from the default weights
+};
+
+struct Batch {
+    int B;                       // instances
+    int T;                       // tiles
+    const int32_t *off;          // [B+1] first row of each instance
+    const int32_t *tile_inst;    // [T] instance of each tile
+    const int32_t *tile_row;     // [T] first row of each tile
+    const int32_t *first_tile;   // [B+1] first tile of each instance
+    const int32_t *inst;         // [n] instance of each row
+    const GridDesc *grid;        // [B]
+    const BoxF *box;             // [B]
+    const double *rmax;          // [B] max sqrt(psi) over the instance (weights being evaluated)
+    const int32_t *phase;        // [B] Phase
+};
+
+// Does instance b take part in a launch that selects phase `want` (< 0: all)?
+__device__ inline bool selected(const Batch &bt, int want, int b) { return want < 0 || bt.phase[b] == want; }
+
+// Newton state of one instance (device, one record per instance).
+struct InstCtl {
+    double eps0;       // KMT volume floor: 0.5 min(min nu, min V(psi_start))
+    double alpha;      // current step length of the step-size search
+    double gnorm;      // ||nu - V||_2 at the accepted iterate
+    double maxrel;     // max |V - nu| / nu at the accepted iterate
+    double minV;       // min V at the accepted iterate
+    double sumV;       // sum V at the accepted iterate
+    int iters, evals, halvings, hstep, cg_iters, status, default_start, learned;
+    int restore;       // the float32 shadow must be reset to the accepted weights
+    int pad[3];
+};
+
+// Newton options as the device control kernels see them.
+struct CtlOpts {
+    double tol;
+    int max_newton, max_halvings, single, allow_restart;
 };
 
 // Views of the evaluation outputs (sorted site order).
@@ -61,66 +119,92 @@ struct EvalOut {
     uint32_t *flags;  // [n] CellFlag bits
     int32_t *fb_list; // [n] cells to redo on the float64 path
     int32_t *fb_count;// [1] length of fb_list (device counter)
-    int32_t *fail_count; // [1] cells that failed the float64 path too
+    int32_t *fb_inst; // [B] cells sent to the float64 path, per instance (accumulates over a call)
+    int32_t *fail_inst; // [B] cells that failed the float64 path too, per instance (per evaluation)
+};
+
+// Conjugate-gradient vectors and scalars (Chronopoulos-Gear form, one kernel per
+// iteration). r, w = A u and s = A p are kept for two iterations (slot k % 2 is
+// read by iteration k, slot (k+1) % 2 written), so that a row can rebuild the
+// next preconditioned residual of any neighbour from that neighbour's stored
+// values; p and x are touched by their own row only.
+struct CgBufs {
+    double *r[2], *w[2], *s[2];
+    double *p, *x;           // x: the Newton direction
+    double *part;            // tile partials: gamma[2][T], delta[2][T], rho[2][T], rho0[T]
+    double *cgs;             // [B][4] alpha and gamma of iterations k%2 = 0, 1
+    int32_t *cgst;           // [B][4] iterations done, breakdown, converged, unused
+    int32_t *kbase;          // [1] index of the first iteration of the next chunk
+    int32_t *remaining;      // [1] instances still iterating after the last chunk
 };
 
 // ---- launch wrappers (defined in the .hip files) ----
 // grid.hip
+void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst);
+void launch_zero_i32(hipStream_t st, int32_t *p, int64_t count);
+void launch_validate(hipStream_t st, int64_t n, const Batch &bt, const float *x, const float *y, const float *z,
+                     const double *psi, const double *nu, int32_t *bad_inst);
 void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float *y, const float *z,
-                         const double *psi, float4 *pos_orig, double *rmax_partial, int nblk);
-void launch_reduce_max(hipStream_t st, const double *partial, int nblk, double *out);
-void launch_grid_build(hipStream_t st, int64_t n, const float4 *pos_orig, GridDesc g, int32_t *keys,
-                       int32_t *cell_count, int32_t *cell_start, int32_t *scan_tmp, int32_t *perm,
+                         const double *psi, float4 *pos_orig);
+// rmax[b] = max sqrt(max(psi, 0)) over the rows of every selected instance
+void launch_rmax(hipStream_t st, const Batch &bt, int want, const double *psi, double *rmax);
+void launch_grid_build(hipStream_t st, int64_t n, const Batch &bt, int ncell_total, const float4 *pos_orig,
+                       int32_t *keys, int32_t *cell_count, int32_t *cell_start, int32_t *scan_tmp, int32_t *perm,
                        int32_t *cursor);
 void launch_permute_in(hipStream_t st, int64_t n, const int32_t *perm, const float4 *pos_orig, const double *psi,
                        const double *nu, float4 *pos_s, double *psi_s, double *nu_s);
 void launch_psi_shadow(hipStream_t st, int64_t n, const double *psi_s, float4 *pos_s);
 void launch_scatter_out_f64(hipStream_t st, int64_t n, const int32_t *perm, const double *src_s, double *dst);
-void launch_validate(hipStream_t st, int64_t n, const float *x, const float *y, const float *z, const double *psi,
-                     const double *nu, BoxF box, int32_t *bad);
 void launch_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int n, int32_t *tmp);
 void launch_csr_count(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcnt, int32_t *cnt_orig);
 void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcol, const float *farea,
                      const int32_t *fcnt, const int32_t *start, int32_t *col, float *area, int64_t *row_ptr);
 void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const float *wall_s, float *wall);
 void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t *perm, const void *src, void *dst);
-void launch_gather_rmax(hipStream_t st, int64_t n, const double *psi, double *partial);
+void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *nu_s, double *psi_s,
+                          float4 *pos_s);
 
 // cells.hip
-void launch_cells(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
-                  const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out, int tpc);
-void launch_cells_fallback(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const int32_t *perm,
-                           const int32_t *cell_start, GridDesc g, BoxF box, const double *rmax, EvalOut out);
+// Cells of the selected instances at the float64 weights psi (float32 shadow in pos_s.w).
+void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out);
+void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s, const double *psi,
+                  const int32_t *perm, const int32_t *cell_start, EvalOut out, int tpc);
+void launch_cells_fallback(hipStream_t st, const Batch &bt, const float4 *pos_s, const double *psi,
+                           const int32_t *perm, const int32_t *cell_start, EvalOut out);
 
 // newton.hip
-void launch_eval_reduce(hipStream_t st, int64_t n, const double *V, const double *nu, double *partial, int nblk,
-                        double *out4);
-void launch_hess_assemble(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const double *K,
+// ev[4b..4b+3] = sum V, max |V - nu| / nu, ||nu - V||_2, min V of every selected instance
+void launch_eval_reduce(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu, double *part,
+                        double *ev);
+void launch_hess_assemble(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                           const int32_t *fcol, const float *farea, const int32_t *fcnt, int32_t *hcol, float *hval,
-                          int32_t *xcnt, double *diag, int32_t *err);
-void launch_hess_finish(hipStream_t st, int64_t n, const double *psi_s, const double *K, const int32_t *fcnt,
-                        const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag);
-int pcg_blocks(int64_t n);
-int spmv_blocks(int64_t n);
-void launch_pcg_init(hipStream_t st, int64_t n, int nb, const double *V, const double *nu, const double *diag,
-                     double *g, double *x, double *r, double *z, double *RZ, double *RR, double *R0, int32_t *state);
-void launch_pcg_spmv(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const int32_t *hcol,
-                     const float *hval, const int32_t *hcnt, const double *diag, const double *z, const double *p_old,
-                     double *p_new, double *q, const double *RZ, const double *RR, double *PQ, const int32_t *state);
-void launch_pcg_update(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const double *diag,
-                       double *x, double *r, double *z, const double *p, const double *q, double *RZ, double *RR,
-                       const double *PQ, int32_t *state);
-void launch_pcg_status(hipStream_t st, int nb, const double *RR, const double *R0, const int32_t *state,
-                       double *scal);
-void launch_axpy_trial(hipStream_t st, int64_t n, const double *psi_s, const double *u, double alpha,
-                       double *psi_trial, float4 *pos_s, double *rmax_partial);
+                          int32_t *xcnt, int32_t *herr);
+void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, const double *psi_s, const double *K,
+                        const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag);
+void launch_cg_init(hipStream_t st, const Batch &bt, const double *V, const double *nu, const double *diag,
+                    const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg);
+void launch_cg_iter(hipStream_t st, const Batch &bt, int m, double rtol2, int cap, const int32_t *hcol,
+                    const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg);
+void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg);
+void launch_cg_finish(hipStream_t st, const Batch &bt, double rtol2, CgBufs cg, const int32_t *herr, InstCtl *ctl,
+                      int32_t *phase);
+void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase);
+// ev: statistics of the first iterate; ev_floor: of the given start weights (eps0)
+void launch_ctl_start(hipStream_t st, const Batch &bt, CtlOpts o, int from_phase, const double *ev,
+                      const double *ev_nu, const double *ev_floor, const int32_t *fail_inst, InstCtl *ctl,
+                      int32_t *phase, int32_t *counts);
+void launch_axpy_trial(hipStream_t st, const Batch &bt, const InstCtl *ctl, const double *psi_s, const double *u,
+                       double *psi_trial, float4 *pos_s);
+void launch_ctl_decide(hipStream_t st, const Batch &bt, CtlOpts o, const double *ev, const int32_t *fail_inst,
+                       InstCtl *ctl, int32_t *phase);
+void launch_accept_rows(hipStream_t st, const Batch &bt, const InstCtl *ctl, double *psi_s, const double *psi_trial,
+                        float4 *pos_s);
+void launch_ctl_commit(hipStream_t st, const Batch &bt, CtlOpts o, InstCtl *ctl, int32_t *phase, int32_t *counts);
 
 // mlp.hip
 void launch_knn_features(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm,
                          const int32_t *cell_start, GridDesc g, const double *psi_prev_s, const double *nu_s,
                          const double *nu_sum, const double *V_s, int32_t *nbr, uint16_t *feat, int32_t *err);
-void launch_default_start(hipStream_t st, int64_t n, const double *nu_s, double *psi_s, float4 *pos_s,
-                          double *rmax_partial);
 void launch_gemm(hipStream_t st, bool ta, bool tb, int epi, const uint16_t *A, const uint16_t *B, int M, int N, int K,
                  float *C, uint16_t *Cb, const float *bias, const float *Zaux);
 void launch_out_layer(hipStream_t st, int m, const uint16_t *H, const float *w4, const float *b4, float *y,
@@ -135,7 +219,7 @@ void launch_to_bf16(hipStream_t st, int64_t n, const float *x, uint16_t *y);
 void launch_gather_rows(hipStream_t st, int m, const int32_t *idx, const uint16_t *F, const float *T, uint16_t *Fb,
                         float *Tb);
 void launch_apply_guess(hipStream_t st, int64_t n, const double *psi_prev, const double *nu, const float *out,
-                        double *psi_new, float4 *pos_s, double *rmax_partial);
+                        double *psi_new, float4 *pos_s);
 enum { MLP_EPI_STORE = 0, MLP_EPI_BIAS_GELU = 1, MLP_EPI_GELU_BACK = 2 };
 
 }  // namespace lagot

@@ -321,22 +321,13 @@ __global__ void k_gather_rows(int m, const int32_t *__restrict__ idx, const uint
 
 // psi_guess = psi_prev + s^2 * out, s = nu^(1/3) (grid order)
 __global__ void k_apply_guess(int64_t n, const double *__restrict__ psi_prev, const double *__restrict__ nu,
-                              const float *__restrict__ out, double *__restrict__ psi_new, float4 *__restrict__ pos_s,
-                              double *__restrict__ rmax_partial) {
-    __shared__ double red[4];
+                              const float *__restrict__ out, double *__restrict__ psi_new, float4 *__restrict__ pos_s) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double rr = 0.0;
-    if (i < n) {
-        const double s = cbrt(nu[i]);
-        const double v = psi_prev[i] + s * s * (double)out[i];
-        psi_new[i] = v;
-        pos_s[i].w = (float)v;
-        rr = v > 0.0 ? sqrt(v) : 0.0;
-    }
-    for (int o = 32; o > 0; o >>= 1) rr = fmax(rr, __shfl_xor(rr, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rr;
-    __syncthreads();
-    if (threadIdx.x == 0) rmax_partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (i >= n) return;
+    const double s = cbrt(nu[i]);
+    const double v = psi_prev[i] + s * s * (double)out[i];
+    psi_new[i] = v;
+    pos_s[i].w = (float)v;
 }
 
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
@@ -395,9 +386,8 @@ void launch_gather_rows(hipStream_t st, int m, const int32_t *idx, const uint16_
 }
 
 void launch_apply_guess(hipStream_t st, int64_t n, const double *psi_prev, const double *nu, const float *out,
-                        double *psi_new, float4 *pos_s, double *rmax_partial) {
-    hipLaunchKernelGGL(k_apply_guess, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi_prev, nu, out, psi_new, pos_s,
-                       rmax_partial);
+                        double *psi_new, float4 *pos_s) {
+    hipLaunchKernelGGL(k_apply_guess, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi_prev, nu, out, psi_new, pos_s);
 }
 
 }  // namespace lagot

@@ -11,6 +11,12 @@
 // Precision: facet areas and matrix values are float32; V, K, the diagonal,
 // every vector of the conjugate gradients, every inner product and every
 // reduction are float64, with fixed-order two-level reductions (deterministic).
+//
+// Batches: every kernel serves B independent instances at once. Row kernels run
+// over the tile table (a tile lies in one instance) and skip instances whose
+// control phase is not the one a launch selects; per-instance reductions sum the
+// instance's run of tile partials; the step-size control of Algorithm 1 runs per
+// instance in small control kernels, so the host only reads phase counts.
 #include <algorithm>
 
 #include "lagot_internal.h"
@@ -53,63 +59,86 @@ __device__ inline double block_min(double v, double *sh) {
     return s;
 }
 
-// partial[0*nb+b] = sum V, [1] = max |V-nu|/nu, [2] = sum (nu-V)^2, [3] = min V
-__global__ __launch_bounds__(RB) void k_eval_partial(int64_t n, const double *__restrict__ V,
-                                                      const double *__restrict__ nu, double *__restrict__ partial) {
-    __shared__ double sh[RB / 64];
+// ---- per-instance evaluation statistics ----------------------------------------
+// part[q*T + t], q = 0..3: sum V, max |V-nu|/nu, sum (nu-V)^2, min V over tile t
+__global__ __launch_bounds__(TILE) void k_eval_partial(Batch bt, int want, const double *__restrict__ V,
+                                                        const double *__restrict__ nu, double *__restrict__ part) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (!selected(bt, want, b)) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
     double sv = 0.0, mx = 0.0, g2 = 0.0, mn = 1e300;
-    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
-        const double v = V[i], b = nu[i];
-        sv += v;
-        mx = fmax(mx, fabs(v - b) / b);
-        g2 += (b - v) * (b - v);
-        mn = fmin(mn, v);
+    if (i < bt.off[b + 1]) {
+        const double v = V[i], c = nu[i];
+        sv = v;
+        mx = fabs(v - c) / c;
+        g2 = (c - v) * (c - v);
+        mn = v;
     }
-    const int nb = gridDim.x;
-    sv = block_sum(sv, sh);
-    mx = block_max(mx, sh);
-    g2 = block_sum(g2, sh);
-    mn = block_min(mn, sh);
+    for (int o = 32; o > 0; o >>= 1) {
+        sv += __shfl_xor(sv, o, 64);
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        g2 += __shfl_xor(g2, o, 64);
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+    }
     if (threadIdx.x == 0) {
-        partial[0 * nb + blockIdx.x] = sv;
-        partial[1 * nb + blockIdx.x] = mx;
-        partial[2 * nb + blockIdx.x] = g2;
-        partial[3 * nb + blockIdx.x] = mn;
+        const int T = bt.T;
+        part[t] = sv;
+        part[T + t] = mx;
+        part[2 * T + t] = g2;
+        part[3 * T + t] = mn;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_eval_final(const double *partial, int nb, double *out4) {
-    __shared__ double sh[16];
+__global__ __launch_bounds__(RB) void k_eval_final(Batch bt, int want, const double *__restrict__ part,
+                                                    double *__restrict__ ev) {
+    __shared__ double sh[RB / 64];
+    const int b = blockIdx.x;
+    if (!selected(bt, want, b)) return;
+    const int T = bt.T, t0 = bt.first_tile[b], t1 = bt.first_tile[b + 1];
     double sv = 0.0, mx = 0.0, g2 = 0.0, mn = 1e300;
-    for (int b = threadIdx.x; b < nb; b += 1024) {
-        sv += partial[b];
-        mx = fmax(mx, partial[nb + b]);
-        g2 += partial[2 * nb + b];
-        mn = fmin(mn, partial[3 * nb + b]);
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += RB) {
+        sv += part[t];
+        mx = fmax(mx, part[T + t]);
+        g2 += part[2 * T + t];
+        mn = fmin(mn, part[3 * T + t]);
     }
     sv = block_sum(sv, sh);
     mx = block_max(mx, sh);
     g2 = block_sum(g2, sh);
     mn = block_min(mn, sh);
     if (threadIdx.x == 0) {
-        out4[0] = sv;
-        out4[1] = mx;
-        out4[2] = sqrt(g2);
-        out4[3] = mn;
+        ev[4 * b + 0] = sv;
+        ev[4 * b + 1] = mx;
+        ev[4 * b + 2] = sqrt(g2);
+        ev[4 * b + 3] = mn;
     }
+}
+
+// ---- Hessian assembly ---------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_hess_begin(Batch bt, int want, int32_t *__restrict__ xcnt,
+                                                      int32_t *__restrict__ herr) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (!selected(bt, want, b)) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    if (i < bt.off[b + 1]) xcnt[i] = 0;
+    if (t == bt.first_tile[b] && threadIdx.x == 0) herr[b] = 0;
 }
 
 // Row i of -Hess K: one entry per facet of cell i; a facet that cell j does not
 // list is appended to row j as well (union pattern). One thread per facet slot;
 // the partner row is read with 16-byte loads and searched in registers.
-__global__ void k_hess_assemble(int64_t n, const float4 *__restrict__ pos, const int32_t *__restrict__ fcol,
-                                const float *__restrict__ farea, const int32_t *__restrict__ fcnt,
-                                int32_t *__restrict__ hcol, float *__restrict__ hval, int32_t *__restrict__ xcnt,
-                                int32_t *__restrict__ err) {
+__global__ void k_hess_assemble(int64_t n, Batch bt, int want, const float4 *__restrict__ pos,
+                                const int32_t *__restrict__ fcol, const float *__restrict__ farea,
+                                const int32_t *__restrict__ fcnt, int32_t *__restrict__ hcol,
+                                float *__restrict__ hval, int32_t *__restrict__ xcnt, int32_t *__restrict__ herr) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / 16;
     const int f0 = (int)(t & 15);
     if (i >= n) return;
+    const int b = bt.inst[i];
+    if (!selected(bt, want, b)) return;
     const int ci = fcnt[i];
     for (int f = f0; f < ci; f += 16) {
         const int j = fcol[i * FCAP + f];
@@ -139,17 +168,18 @@ __global__ void k_hess_assemble(int64_t n, const float4 *__restrict__ pos, const
                 hcol[(int64_t)j * FCAP + slot] = (int32_t)i;
                 hval[(int64_t)j * FCAP + slot] = w;
             } else {
-                atomicAdd(err, 1);
+                atomicAdd(herr + b, 1);
             }
         }
     }
 }
 
-__global__ void k_hess_finish(int64_t n, const double *__restrict__ psi, const double *__restrict__ K,
-                              const int32_t *__restrict__ fcnt, const int32_t *__restrict__ xcnt,
-                              int32_t *__restrict__ hcnt, const float *__restrict__ hval, double *__restrict__ diag) {
+__global__ void k_hess_finish(int64_t n, Batch bt, int want, const double *__restrict__ psi,
+                              const double *__restrict__ K, const int32_t *__restrict__ fcnt,
+                              const int32_t *__restrict__ xcnt, int32_t *__restrict__ hcnt,
+                              const float *__restrict__ hval, double *__restrict__ diag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || !selected(bt, want, bt.inst[i])) return;
     const int c = min(fcnt[i] + xcnt[i], FCAP);
     hcnt[i] = c;
     double s = 0.0;
@@ -159,33 +189,30 @@ __global__ void k_hess_finish(int64_t n, const double *__restrict__ psi, const d
     diag[i] = s;
 }
 
+// ---- Jacobi-PCG, one kernel per iteration (Chronopoulos-Gear form) ------------
+// Preconditioned CG on (D - W) x = g with M = diag(D - W). With u = M^-1 r and
+// w = A u, one iteration k needs only gamma_k = (r_k, u_k) and
+// delta_k = (w_k, u_k), both summed in the same pass:
+//   beta_k = gamma_k / gamma_{k-1},  alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+//   p_k = u_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}  (= A p_k)
+//   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k,  w_{k+1} = A u_{k+1}.
+// A row needs u_{k+1} of its neighbours; it rebuilds it from their stored r_k, w_k,
+// s_{k-1} and the two scalars (same arithmetic as the owner), so no grid-wide
+// barrier separates the vector update from the product. Every block recomputes
+// the scalars from its instance's tile partials in a fixed order: deterministic,
+// no atomics, no device-scope fences (a device-scope fence writes back the XCD's
+// L2 on this part). The stop test is ||r_k|| <= rtol ||r_0||.
+constexpr int LANES = 4;  // lanes per row: rows hold ~6-20 entries; one tile per block
 
-
-// ---- Jacobi-PCG, two fused kernels per iteration -----------------------------
-// Every kernel runs a fixed grid of nb <= 512 blocks (grid-stride loops) and
-// leaves one partial per block. The scalars an iteration needs (alpha, beta, the
-// stop test) are recomputed by every block from the previous kernel's partials,
-// summed in block order: deterministic, with no atomics and no device fences
-// (a device-scope fence writes back the XCD's L2 on this part).
-// Partials: RZ[2][nb], RR[2][nb] (slot k%2 holds the residual of iteration k), PQ[nb].
-// state (int32): [0] iterations done, [1] breakdown, [2] converged.
-
-__device__ inline double sum_partials(const double *v, int nb, double *sh) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nb; k += RB) s += v[k];
-    return block_sum(s, sh);
-}
-
-// Four block-ordered sums in one pass and one block reduction (lanes fold in a fixed order).
-__device__ inline void sum_partials4(const double *a, const double *b, const double *c, const double *d, int na,
-                                     int nd, double *out, double (*sh)[4]) {
+__device__ inline void sum_range(const double *a, const double *b, const double *c, const double *d, int t0, int t1,
+                                 double *out, double (*sh)[4]) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < na; k += RB) {
-        s[0] += a[k];
-        s[1] += b[k];
-        s[2] += c[k];
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += RB) {
+        s[0] += a[t];
+        s[1] += b[t];
+        s[2] += c[t];
+        s[3] += d[t];
     }
-    for (int k = threadIdx.x; k < nd; k += RB) s[3] += d[k];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         for (int o = 32; o > 0; o >>= 1) s[q] += __shfl_xor(s[q], o, 64);
@@ -195,225 +222,452 @@ __device__ inline void sum_partials4(const double *a, const double *b, const dou
         for (int q = 0; q < 4; ++q) sh[w][q] = s[q];
     __syncthreads();
     for (int q = 0; q < 4; ++q) {
-        double t = 0.0;
-        for (int k = 0; k < RB / 64; ++k) t += sh[k][q];
-        out[q] = t;
+        double v = 0.0;
+        for (int k = 0; k < RB / 64; ++k) v += sh[k][q];
+        out[q] = v;
     }
 }
 
-// g = nu - V (0 on empty rows), x = 0, r = g, z = r / D ; partials of r.z, r.r into slot 0
-__global__ __launch_bounds__(RB) void k_pcg_init(int64_t n, int nb, const double *__restrict__ V,
-                                                  const double *__restrict__ nu, const double *__restrict__ diag,
-                                                  double *__restrict__ g, double *__restrict__ x,
-                                                  double *__restrict__ r, double *__restrict__ z,
-                                                  double *__restrict__ RZ, double *__restrict__ RR,
-                                                  double *__restrict__ R0, int32_t *__restrict__ state) {
-    __shared__ double sh[RB / 64];
-    double rz = 0.0, rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nb * RB) {
-        const double d = diag[i];
-        const double gi = d > 0.0 ? nu[i] - V[i] : 0.0;
-        const double zi = d > 0.0 ? gi / d : 0.0;
-        g[i] = gi;
-        x[i] = 0.0;
-        r[i] = gi;
-        z[i] = zi;
-        rz += gi * zi;
-        rr += gi * gi;
+__device__ inline void block_sum3(double &a, double &b, double &c, double (*sh)[4]) {
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+        c += __shfl_xor(c, o, 64);
     }
-    rz = block_sum(rz, sh);
-    rr = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        RZ[blockIdx.x] = rz;
-        RR[blockIdx.x] = rr;
-        R0[blockIdx.x] = rr;
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sh[w][0] = a;
+        sh[w][1] = b;
+        sh[w][2] = c;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        state[0] = 0;
-        state[1] = 0;
-        state[2] = 0;
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int k = 0; k < RB / 64; ++k) {
+        a += sh[k][0];
+        b += sh[k][1];
+        c += sh[k][2];
     }
 }
 
-// p_k = z + beta p_{k-1} (p_0 = z); q = (D - W) p_k; one partial of p.q per block.
-// Four lanes per row (rows hold ~6-20 facets), one row per lane quad, no grid stride:
-// the gathers of a row are issued together and every row is in flight at once.
-constexpr int SPMV_LANES = 4;
-constexpr int SPMV_ROWS = RB / SPMV_LANES;
+// partial slots: gamma[2][T], delta[2][T], rho[2][T], rho0[T]
+__device__ inline double *P_GAM(const CgBufs &cg, int T, int slot) { return cg.part + slot * T; }
+__device__ inline double *P_DEL(const CgBufs &cg, int T, int slot) { return cg.part + (2 + slot) * T; }
+__device__ inline double *P_RHO(const CgBufs &cg, int T, int slot) { return cg.part + (4 + slot) * T; }
+__device__ inline double *P_RHO0(const CgBufs &cg, int T) { return cg.part + 6 * T; }
 
-__global__ __launch_bounds__(RB) void k_pcg_spmv(int64_t n, int k, int nb, double rtol2, const double *__restrict__ R0,
-                                                  const int32_t *__restrict__ hcol, const float *__restrict__ hval,
-                                                  const int32_t *__restrict__ hcnt, const double *__restrict__ diag,
-                                                  const double *__restrict__ z, const double *__restrict__ p_old,
-                                                  double *__restrict__ p_new, double *__restrict__ q,
-                                                  const double *__restrict__ RZ, const double *__restrict__ RR,
-                                                  double *__restrict__ PQ, const int32_t *__restrict__ state) {
-    __shared__ double sh[RB / 64];
-    __shared__ double sh4[RB / 64][4];
-    if (state[1] != 0) return;
-    double S4[4];
-    sum_partials4(R0, RR + (k & 1) * nb, RZ + (k & 1) * nb, RZ + ((k + 1) & 1) * nb, nb, k > 0 ? nb : 0, S4, sh4);
-    const double stop = rtol2 * S4[0], rr = S4[1], rz = S4[2], rz_old = S4[3];
-    if (rr <= stop) return;
-    const double beta = (k > 0 && rz_old > 0.0) ? rz / rz_old : 0.0;
-    const int l = threadIdx.x & (SPMV_LANES - 1);
-    const int64_t row = (int64_t)blockIdx.x * SPMV_ROWS + (threadIdx.x / SPMV_LANES);
-    double acc = 0.0, pq = 0.0;
-    if (row < n) {
+// r_0 = g = nu - V (0 on empty rows), u_0 = r_0 / D, w_0 = A u_0, s_{-1} = p_{-1} = x_0 = 0
+__global__ __launch_bounds__(RB) void k_cg_init(Batch bt, const double *__restrict__ V, const double *__restrict__ nu,
+                                                 const double *__restrict__ diag, const int32_t *__restrict__ hcol,
+                                                 const float *__restrict__ hval, const int32_t *__restrict__ hcnt,
+                                                 CgBufs cg) {
+    __shared__ double sh[RB / 64][4];
+    const int t = blockIdx.x;
+    if (t == 0 && threadIdx.x == 0) *cg.kbase = 0;
+    const int b = bt.tile_inst[t];
+    if (bt.phase[b] != PH_ACTIVE) return;
+    const int T = bt.T;
+    const int l = threadIdx.x & (LANES - 1);
+    const int row = bt.tile_row[t] + (int)(threadIdx.x / LANES);
+    const bool has = row < bt.off[b + 1];
+    double acc = 0.0;
+    if (has) {
         const int c = hcnt[row];
-        const int32_t *cr = hcol + row * FCAP;
-        const float *vr = hval + row * FCAP;
-#pragma unroll 4
-        for (int f = l; f < c; f += SPMV_LANES) {
+        const int32_t *cr = hcol + (int64_t)row * FCAP;
+        const float *vr = hval + (int64_t)row * FCAP;
+        for (int f = l; f < c; f += LANES) {
             const int j = cr[f];
-            const double pj = k == 0 ? z[j] : z[j] + beta * p_old[j];
-            acc += (double)vr[f] * pj;
+            const double dj = diag[j];
+            const double uj = dj > 0.0 ? (nu[j] - V[j]) / dj : 0.0;
+            acc += (double)vr[f] * uj;
         }
     }
 #pragma unroll
-    for (int o = SPMV_LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SPMV_LANES);
-    if (row < n && l == 0) {
-        const double pi = k == 0 ? z[row] : z[row] + beta * p_old[row];
-        const double qi = diag[row] * pi - acc;
-        p_new[row] = pi;
-        q[row] = qi;
-        pq = pi * qi;
+    for (int o = LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LANES);
+    double gp = 0.0, dp = 0.0, rp = 0.0;
+    if (has && l == 0) {
+        const double d = diag[row];
+        const double g = d > 0.0 ? nu[row] - V[row] : 0.0;
+        const double u = d > 0.0 ? (nu[row] - V[row]) / d : 0.0;
+        const double w = d * u - acc;
+        cg.r[0][row] = g;
+        cg.w[0][row] = w;
+        cg.s[0][row] = 0.0;
+        cg.p[row] = 0.0;
+        cg.x[row] = 0.0;
+        gp = g * u;
+        dp = w * u;
+        rp = g * g;
     }
-    pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) PQ[blockIdx.x] = pq;
+    block_sum3(gp, dp, rp, sh);
+    if (threadIdx.x == 0) {
+        P_GAM(cg, T, 0)[t] = gp;
+        P_DEL(cg, T, 0)[t] = dp;
+        P_RHO(cg, T, 0)[t] = rp;
+        P_RHO0(cg, T)[t] = rp;
+    }
+    if (t == bt.first_tile[b] && threadIdx.x == 0) {
+        int32_t *st = cg.cgst + 4 * b;
+        st[0] = 0;
+        st[1] = 0;
+        st[2] = 0;
+        st[3] = 0;
+    }
 }
 
-// alpha = rz / (p.q); x += alpha p; r -= alpha q; z = r / D; partials of r.z, r.r into slot (k+1)%2
-__global__ __launch_bounds__(RB) void k_pcg_update(int64_t n, int k, int nb, int npq, double rtol2,
-                                                    const double *__restrict__ R0,
-                                                    const double *__restrict__ diag, double *__restrict__ x,
-                                                    double *__restrict__ r, double *__restrict__ z,
-                                                    const double *__restrict__ p, const double *__restrict__ q,
-                                                    double *__restrict__ RZ, double *__restrict__ RR,
-                                                    const double *__restrict__ PQ, int32_t *__restrict__ state) {
-    __shared__ double sh[RB / 64];
-    __shared__ double sh4[RB / 64][4];
-    if (state[1] != 0) return;
-    double S4[4];
-    sum_partials4(R0, RR + (k & 1) * nb, RZ + (k & 1) * nb, PQ, nb, npq, S4, sh4);
-    const double stop = rtol2 * S4[0], rr = S4[1], rz = S4[2], pq = S4[3];
-    if (rr <= stop) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) state[2] = 1;
+// Iteration k = *kbase + m (the host advances kbase after a chunk of launches, so a
+// chunk has fixed arguments and can be replayed as a graph).
+__global__ __launch_bounds__(RB) void k_cg_iter(Batch bt, int m, double rtol2, int cap,
+                                                 const int32_t *__restrict__ hcol, const float *__restrict__ hval,
+                                                 const int32_t *__restrict__ hcnt, const double *__restrict__ diag,
+                                                 CgBufs cg) {
+    __shared__ double sh[RB / 64][4];
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (bt.phase[b] != PH_ACTIVE) return;
+    int32_t *st = cg.cgst + 4 * b;
+    if (st[1] != 0 || st[2] != 0) return;
+    const int k = *cg.kbase + m;
+    if (k >= cap) return;
+    const int T = bt.T;
+    const int t0 = bt.first_tile[b], t1 = bt.first_tile[b + 1];
+    const int cur = k & 1, nxt = cur ^ 1;
+    double S[4];
+    sum_range(P_GAM(cg, T, cur), P_DEL(cg, T, cur), P_RHO(cg, T, cur), P_RHO0(cg, T), t0, t1, S, sh);
+    const double gam = S[0], del = S[1], rho = S[2], rho0 = S[3];
+    const bool lead = t == t0 && threadIdx.x == 0;
+    if (rho <= rtol2 * rho0) {
+        if (lead) {
+            st[2] = 1;
+            st[0] = k;
+        }
         return;
     }
-    if (!(pq > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) state[1] = 1;
+    double alpha, beta = 0.0;
+    if (k == 0) {
+        alpha = gam / del;
+    } else {
+        const double a_prev = cg.cgs[4 * b + 2 * nxt], g_prev = cg.cgs[4 * b + 2 * nxt + 1];
+        beta = gam / g_prev;
+        alpha = gam / (del - beta * gam / a_prev);
+    }
+    if (!(alpha > 0.0) || !(alpha < 1e300)) {  // non-positive curvature (or NaN)
+        if (lead) {
+            st[1] = 1;
+            st[0] = k;
+        }
         return;
     }
-    const double alpha = rz / pq;
-    double rzn = 0.0, rrn = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nb * RB) {
-        const double d = diag[i];
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        const double zi = d > 0.0 ? ri / d : 0.0;
-        z[i] = zi;
-        rzn += ri * zi;
-        rrn += ri * ri;
+    if (lead) {
+        cg.cgs[4 * b + 2 * cur] = alpha;
+        cg.cgs[4 * b + 2 * cur + 1] = gam;
+        st[0] = k + 1;
     }
-    rzn = block_sum(rzn, sh);
-    rrn = block_sum(rrn, sh);
+    const double *rc = cg.r[cur], *wc = cg.w[cur], *sc = cg.s[cur];
+    const int l = threadIdx.x & (LANES - 1);
+    const int row = bt.tile_row[t] + (int)(threadIdx.x / LANES);
+    const bool has = row < bt.off[b + 1];
+    double acc = 0.0;
+    if (has) {
+        const int c = hcnt[row];
+        const int32_t *cr = hcol + (int64_t)row * FCAP;
+        const float *vr = hval + (int64_t)row * FCAP;
+#pragma unroll 2
+        for (int f = l; f < c; f += LANES) {
+            const int j = cr[f];
+            const double dj = diag[j];
+            const double sj = fma(beta, sc[j], wc[j]);
+            const double uj = dj > 0.0 ? fma(-alpha, sj, rc[j]) / dj : 0.0;
+            acc += (double)vr[f] * uj;
+        }
+    }
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LANES);
+    double gp = 0.0, dp = 0.0, rp = 0.0;
+    if (has && l == 0) {
+        const double d = diag[row];
+        const double rk = rc[row];
+        const double uk = d > 0.0 ? rk / d : 0.0;
+        const double pk = fma(beta, cg.p[row], uk);
+        const double sk = fma(beta, sc[row], wc[row]);
+        cg.x[row] = fma(alpha, pk, cg.x[row]);
+        const double r1 = fma(-alpha, sk, rk);
+        const double u1 = d > 0.0 ? r1 / d : 0.0;
+        const double w1 = d * u1 - acc;
+        cg.p[row] = pk;
+        cg.s[nxt][row] = sk;
+        cg.r[nxt][row] = r1;
+        cg.w[nxt][row] = w1;
+        gp = r1 * u1;
+        dp = w1 * u1;
+        rp = r1 * r1;
+    }
+    block_sum3(gp, dp, rp, sh);
     if (threadIdx.x == 0) {
-        RZ[((k + 1) & 1) * nb + blockIdx.x] = rzn;
-        RR[((k + 1) & 1) * nb + blockIdx.x] = rrn;
+        P_GAM(cg, T, nxt)[t] = gp;
+        P_DEL(cg, T, nxt)[t] = dp;
+        P_RHO(cg, T, nxt)[t] = rp;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) state[0] = k + 1;
 }
 
-// Residual of the latest iterate into scal: [0] r.r, [1] r0.r0
-__global__ __launch_bounds__(RB) void k_pcg_status(int nb, const double *__restrict__ RR, const double *__restrict__ R0,
-                                                    const int32_t *__restrict__ state, double *__restrict__ scal) {
-    __shared__ double sh[RB / 64];
-    const int it = state[0];
-    const double rr = sum_partials(RR + (it & 1) * nb, nb, sh);
-    const double r0 = sum_partials(R0, nb, sh);
-    if (threadIdx.x == 0) {
-        scal[0] = rr;
-        scal[1] = r0;
-    }
-}
-
-__global__ void k_axpy_trial(int64_t n, const double *__restrict__ psi, const double *__restrict__ u, double alpha,
-                             double *__restrict__ out, float4 *__restrict__ pos_s, double *__restrict__ rmax_partial) {
-    __shared__ double red[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double rr = 0.0;
-    if (i < n) {
-        const double v = psi[i] + alpha * u[i];
-        out[i] = v;
-        pos_s[i].w = (float)v;
-        rr = v > 0.0 ? sqrt(v) : 0.0;
-    }
-    for (int o = 32; o > 0; o >>= 1) rr = fmax(rr, __shfl_xor(rr, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rr;
+// After a chunk: advance kbase; count instances still iterating.
+__global__ __launch_bounds__(1024) void k_cg_advance(Batch bt, int chunk, int cap, CgBufs cg) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    if (threadIdx.x == 0) rmax_partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int mine = 0;
+    for (int b = threadIdx.x; b < bt.B; b += 1024) {
+        const int32_t *st = cg.cgst + 4 * b;
+        mine += bt.phase[b] == PH_ACTIVE && st[1] == 0 && st[2] == 0 && st[0] < cap;
+    }
+    if (mine) atomicAdd(&cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *cg.kbase += chunk;
+        *cg.remaining = cnt;
+    }
+}
+
+// End of the direction solve: ACTIVE -> TRIAL with alpha = 1, or FAILED.
+__global__ __launch_bounds__(RB) void k_cg_finish(Batch bt, double rtol2, CgBufs cg, const int32_t *__restrict__ herr,
+                                                   InstCtl *__restrict__ ctl, int32_t *__restrict__ phase) {
+    __shared__ double sh[RB / 64][4];
+    const int b = blockIdx.x;
+    if (phase[b] != PH_ACTIVE) return;
+    const int32_t *st = cg.cgst + 4 * b;
+    const int it = st[0];
+    const int T = bt.T;
+    double S[4];
+    sum_range(P_RHO(cg, T, it & 1), P_RHO0(cg, T), P_RHO0(cg, T), P_RHO0(cg, T), bt.first_tile[b],
+              bt.first_tile[b + 1], S, sh);
+    if (threadIdx.x != 0) return;
+    InstCtl &c = ctl[b];
+    c.cg_iters += it;
+    // a breakdown is harmless once the residual already meets the tolerance
+    const bool singular = st[1] != 0 && !(S[0] <= rtol2 * S[1]);
+    if (herr[b] != 0) {
+        c.status = -5;  // LAGOT_ECAPACITY
+        phase[b] = PH_FAILED;
+    } else if (singular) {
+        c.status = -6;  // LAGOT_ESINGULAR
+        phase[b] = PH_FAILED;
+    } else {
+        c.alpha = 1.0;
+        c.hstep = 0;
+        phase[b] = PH_TRIAL;
+    }
+}
+
+// ---- step-size control of Algorithm 1, per instance -----------------------------
+__device__ inline void count_phases(const int32_t *phase, int B, int32_t *counts) {
+    __shared__ int h[8];
+    if (threadIdx.x < 8) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x) atomicAdd(&h[phase[b] & 7], 1);
+    __syncthreads();
+    if (threadIdx.x < 8) counts[threadIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(1024) void k_ctl_init(Batch bt, InstCtl *__restrict__ ctl, int32_t *__restrict__ phase) {
+    for (int b = threadIdx.x; b < bt.B; b += 1024) {
+        InstCtl c{};
+        c.alpha = 1.0;
+        ctl[b] = c;
+        phase[b] = PH_START;
+    }
+}
+
+// After the evaluation at the start weights: eps0 = 0.5 min(min nu, min V(psi_start))
+// with psi_start the given start (ev_floor); ev describes the first iterate (the given
+// start, or a kept learned guess).
+__global__ __launch_bounds__(1024) void k_ctl_start(Batch bt, CtlOpts o, int from_phase, const double *__restrict__ ev,
+                                                     const double *__restrict__ ev_nu,
+                                                     const double *__restrict__ ev_floor,
+                                                     const int32_t *__restrict__ fail_inst, InstCtl *__restrict__ ctl,
+                                                     int32_t *__restrict__ phase, int32_t *__restrict__ counts) {
+    for (int b = threadIdx.x; b < bt.B; b += 1024) {
+        if (phase[b] != from_phase) continue;
+        InstCtl &c = ctl[b];
+        c.evals += 1;
+        if (from_phase == PH_RESTART) c.default_start = 1;
+        c.sumV = ev[4 * b + 0];
+        c.maxrel = ev[4 * b + 1];
+        c.gnorm = ev[4 * b + 2];
+        c.minV = ev[4 * b + 3];
+        if (!(c.minV > 0.0) && o.allow_restart && !c.default_start) {
+            phase[b] = PH_RESTART;
+            continue;
+        }
+        c.eps0 = 0.5 * fmin(ev_nu[4 * b + 3], ev_floor[4 * b + 3]);
+        int ph = PH_ACTIVE;
+        if (!(c.eps0 > 0.0)) {
+            c.status = -2;  // LAGOT_EEMPTY
+            ph = PH_FAILED;
+        } else if (fail_inst[b] != 0) {
+            c.status = -5;  // LAGOT_ECAPACITY
+            ph = PH_FAILED;
+        } else if (c.maxrel <= o.tol) {
+            ph = PH_DONE;
+        } else if (o.max_newton <= 0) {
+            if (!o.single) c.status = -3;  // LAGOT_ENOCONV
+            ph = o.single ? PH_DONE : PH_FAILED;
+        }
+        phase[b] = ph;
+    }
+    __syncthreads();
+    count_phases(phase, bt.B, counts);
+}
+
+// trial weights psi + alpha u of every instance in the step-size search
+__global__ __launch_bounds__(TILE) void k_axpy_trial(Batch bt, const InstCtl *__restrict__ ctl,
+                                                      const double *__restrict__ psi, const double *__restrict__ u,
+                                                      double *__restrict__ out, float4 *__restrict__ pos) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (bt.phase[b] != PH_TRIAL) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    if (i >= bt.off[b + 1]) return;
+    const double v = fma(ctl[b].alpha, u[i], psi[i]);
+    out[i] = v;
+    pos[i].w = (float)v;
+}
+
+// KMT test of the trial: every cell keeps volume eps0 and ||g|| <= (1 - alpha/2) ||g_accepted||.
+__global__ __launch_bounds__(1024) void k_ctl_decide(Batch bt, CtlOpts o, const double *__restrict__ ev,
+                                                      const int32_t *__restrict__ fail_inst,
+                                                      InstCtl *__restrict__ ctl, int32_t *__restrict__ phase) {
+    for (int b = threadIdx.x; b < bt.B; b += 1024) {
+        if (phase[b] != PH_TRIAL) continue;
+        InstCtl &c = ctl[b];
+        c.evals += 1;
+        const double sumV = ev[4 * b + 0], maxrel = ev[4 * b + 1], gnorm = ev[4 * b + 2], minV = ev[4 * b + 3];
+        if (fail_inst[b] == 0 && minV >= c.eps0 && gnorm <= (1.0 - 0.5 * c.alpha) * c.gnorm) {
+            c.sumV = sumV;
+            c.maxrel = maxrel;
+            c.gnorm = gnorm;
+            c.minV = minV;
+            phase[b] = PH_ACCEPT;
+        } else {
+            c.alpha *= 0.5;
+            c.halvings += 1;
+            c.hstep += 1;
+            if (c.hstep > o.max_halvings) {
+                c.status = fail_inst[b] != 0 ? -5 : -4;  // LAGOT_ECAPACITY : LAGOT_ELINESEARCH
+                c.restore = 1;
+                phase[b] = PH_FAILED;
+            }
+        }
+    }
+}
+
+// accepted trials become the iterate; a failed search puts back the float32 shadow
+__global__ __launch_bounds__(TILE) void k_accept_rows(Batch bt, const InstCtl *__restrict__ ctl,
+                                                       double *__restrict__ psi, const double *__restrict__ trial,
+                                                       float4 *__restrict__ pos) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    const int ph = bt.phase[b];
+    const bool acc = ph == PH_ACCEPT, rst = ph == PH_FAILED && ctl[b].restore;
+    if (!acc && !rst) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    if (i >= bt.off[b + 1]) return;
+    if (acc)
+        psi[i] = trial[i];
+    else
+        pos[i].w = (float)psi[i];
+}
+
+__global__ __launch_bounds__(1024) void k_ctl_commit(Batch bt, CtlOpts o, InstCtl *__restrict__ ctl,
+                                                      int32_t *__restrict__ phase, int32_t *__restrict__ counts) {
+    for (int b = threadIdx.x; b < bt.B; b += 1024) {
+        InstCtl &c = ctl[b];
+        c.restore = 0;
+        if (phase[b] != PH_ACCEPT) continue;
+        c.iters += 1;
+        int ph = PH_ACTIVE;
+        if (c.maxrel <= o.tol || o.single) {
+            ph = PH_DONE;
+        } else if (c.iters >= o.max_newton) {
+            c.status = -3;  // LAGOT_ENOCONV
+            ph = PH_FAILED;
+        }
+        phase[b] = ph;
+    }
+    __syncthreads();
+    count_phases(phase, bt.B, counts);
 }
 
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_eval_reduce(hipStream_t st, int64_t n, const double *V, const double *nu, double *partial, int nblk,
-                        double *out4) {
-    hipLaunchKernelGGL(k_eval_partial, dim3(nblk), dim3(RB), 0, st, n, V, nu, partial);
-    hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(1024), 0, st, partial, nblk, out4);
+void launch_eval_reduce(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu, double *part,
+                        double *ev) {
+    hipLaunchKernelGGL(k_eval_partial, dim3(bt.T), dim3(TILE), 0, st, bt, want, V, nu, part);
+    hipLaunchKernelGGL(k_eval_final, dim3(bt.B), dim3(RB), 0, st, bt, want, part, ev);
 }
 
-void launch_hess_assemble(hipStream_t st, int64_t n, const float4 *pos_s, const double *psi_s, const double *K,
+void launch_hess_assemble(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                           const int32_t *fcol, const float *farea, const int32_t *fcnt, int32_t *hcol, float *hval,
-                          int32_t *xcnt, double *diag, int32_t *err) {
-    (void)psi_s;
-    (void)K;
-    (void)diag;
-    (void)hipMemsetAsync(xcnt, 0, sizeof(int32_t) * (size_t)n, st);
-    hipLaunchKernelGGL(k_hess_assemble, dim3(nblocks(n * 16, 256)), dim3(256), 0, st, n, pos_s, fcol, farea, fcnt,
-                       hcol, hval, xcnt, err);
+                          int32_t *xcnt, int32_t *herr) {
+    hipLaunchKernelGGL(k_hess_begin, dim3(bt.T), dim3(TILE), 0, st, bt, want, xcnt, herr);
+    hipLaunchKernelGGL(k_hess_assemble, dim3(nblocks(n * 16, 256)), dim3(256), 0, st, n, bt, want, pos_s, fcol, farea,
+                       fcnt, hcol, hval, xcnt, herr);
 }
 
-void launch_hess_finish(hipStream_t st, int64_t n, const double *psi_s, const double *K, const int32_t *fcnt,
-                        const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag) {
-    hipLaunchKernelGGL(k_hess_finish, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi_s, K, fcnt, xcnt, hcnt, hval,
-                       diag);
+void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, const double *psi_s, const double *K,
+                        const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag) {
+    hipLaunchKernelGGL(k_hess_finish, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, psi_s, K, fcnt, xcnt,
+                       hcnt, hval, diag);
 }
 
-int pcg_blocks(int64_t n) { return (int)std::min<int64_t>(512, std::max<int64_t>(1, (n + RB - 1) / RB)); }
-int spmv_blocks(int64_t n) { return (int)((n + SPMV_ROWS - 1) / SPMV_ROWS); }
-
-void launch_pcg_init(hipStream_t st, int64_t n, int nb, const double *V, const double *nu, const double *diag,
-                     double *g, double *x, double *r, double *z, double *RZ, double *RR, double *R0, int32_t *state) {
-    hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(RB), 0, st, n, nb, V, nu, diag, g, x, r, z, RZ, RR, R0, state);
+void launch_cg_init(hipStream_t st, const Batch &bt, const double *V, const double *nu, const double *diag,
+                    const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg) {
+    hipLaunchKernelGGL(k_cg_init, dim3(bt.T), dim3(RB), 0, st, bt, V, nu, diag, hcol, hval, hcnt, cg);
 }
 
-void launch_pcg_spmv(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const int32_t *hcol,
-                     const float *hval, const int32_t *hcnt, const double *diag, const double *z, const double *p_old,
-                     double *p_new, double *q, const double *RZ, const double *RR, double *PQ, const int32_t *state) {
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(spmv_blocks(n)), dim3(RB), 0, st, n, k, nb, rtol2, R0, hcol, hval, hcnt, diag, z, p_old, p_new,
-                       q, RZ, RR, PQ, state);
+void launch_cg_iter(hipStream_t st, const Batch &bt, int m, double rtol2, int cap, const int32_t *hcol,
+                    const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg) {
+    hipLaunchKernelGGL(k_cg_iter, dim3(bt.T), dim3(RB), 0, st, bt, m, rtol2, cap, hcol, hval, hcnt, diag, cg);
 }
 
-void launch_pcg_update(hipStream_t st, int64_t n, int k, int nb, double rtol2, const double *R0, const double *diag,
-                       double *x, double *r, double *z, const double *p, const double *q, double *RZ, double *RR,
-                       const double *PQ, int32_t *state) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(RB), 0, st, n, k, nb, spmv_blocks(n), rtol2, R0, diag, x, r, z, p, q, RZ, RR, PQ,
-                       state);
+void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg) {
+    hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1024), 0, st, bt, chunk, cap, cg);
 }
 
-void launch_pcg_status(hipStream_t st, int nb, const double *RR, const double *R0, const int32_t *state,
-                       double *scal) {
-    hipLaunchKernelGGL(k_pcg_status, dim3(1), dim3(RB), 0, st, nb, RR, R0, state, scal);
+void launch_cg_finish(hipStream_t st, const Batch &bt, double rtol2, CgBufs cg, const int32_t *herr, InstCtl *ctl,
+                      int32_t *phase) {
+    hipLaunchKernelGGL(k_cg_finish, dim3(bt.B), dim3(RB), 0, st, bt, rtol2, cg, herr, ctl, phase);
 }
 
-void launch_axpy_trial(hipStream_t st, int64_t n, const double *psi_s, const double *u, double alpha,
-                       double *psi_trial, float4 *pos_s, double *rmax_partial) {
-    hipLaunchKernelGGL(k_axpy_trial, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi_s, u, alpha, psi_trial, pos_s,
-                       rmax_partial);
+void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase) {
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1024), 0, st, bt, ctl, phase);
+}
+
+void launch_ctl_start(hipStream_t st, const Batch &bt, CtlOpts o, int from_phase, const double *ev,
+                      const double *ev_nu, const double *ev_floor, const int32_t *fail_inst, InstCtl *ctl,
+                      int32_t *phase, int32_t *counts) {
+    hipLaunchKernelGGL(k_ctl_start, dim3(1), dim3(1024), 0, st, bt, o, from_phase, ev, ev_nu, ev_floor, fail_inst, ctl,
+                       phase, counts);
+}
+
+void launch_axpy_trial(hipStream_t st, const Batch &bt, const InstCtl *ctl, const double *psi_s, const double *u,
+                       double *psi_trial, float4 *pos_s) {
+    hipLaunchKernelGGL(k_axpy_trial, dim3(bt.T), dim3(TILE), 0, st, bt, ctl, psi_s, u, psi_trial, pos_s);
+}
+
+void launch_ctl_decide(hipStream_t st, const Batch &bt, CtlOpts o, const double *ev, const int32_t *fail_inst,
+                       InstCtl *ctl, int32_t *phase) {
+    hipLaunchKernelGGL(k_ctl_decide, dim3(1), dim3(1024), 0, st, bt, o, ev, fail_inst, ctl, phase);
+}
+
+void launch_accept_rows(hipStream_t st, const Batch &bt, const InstCtl *ctl, double *psi_s, const double *psi_trial,
+                        float4 *pos_s) {
+    hipLaunchKernelGGL(k_accept_rows, dim3(bt.T), dim3(TILE), 0, st, bt, ctl, psi_s, psi_trial, pos_s);
+}
+
+void launch_ctl_commit(hipStream_t st, const Batch &bt, CtlOpts o, InstCtl *ctl, int32_t *phase, int32_t *counts) {
+    hipLaunchKernelGGL(k_ctl_commit, dim3(1), dim3(1024), 0, st, bt, o, ctl, phase, counts);
 }
 
 }  // namespace lagot

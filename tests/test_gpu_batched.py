@@ -1,0 +1,144 @@
+"""Batched solves (lagot_solve_batched) against the FP64 oracle, through the C-ABI.
+
+Each instance has a unique solution (section 2.2), so every instance of a batch is
+judged like a single solve: the oracle re-evaluates its returned weights and every
+volume must be within the tolerance. Instances must not influence each other:
+their statuses are independent, and a batch returns what the instances return
+when solved one at a time (up to the tolerance)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_05765_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2601_05765_amd as L
+    assert torch.cuda.is_available()
+    return L.Context()
+
+
+def _concat(insts, psis=None):
+    import torch
+    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    offs = np.concatenate([[0], np.cumsum([s.n for s in insts])]).astype(np.int64)
+    cat = lambda f: np.concatenate([f(s) for s in insts])
+    psis = [s.psi0 for s in insts] if psis is None else psis
+    return (offs, t(cat(lambda s: s.x), torch.float32), t(cat(lambda s: s.y), torch.float32),
+            t(cat(lambda s: s.z), torch.float32), t(cat(lambda s: s.nu), torch.float64),
+            t(np.concatenate(psis), torch.float64))
+
+
+def _oracle_err(oracle_mod, sc, psi, box=((0, 0, 0), (1, 1, 1)), idx=None):
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, psi, box=box, idx=idx)
+    nu = sc.nu if idx is None else sc.nu[idx]
+    return float(np.max(np.abs(c.V - nu) / nu))
+
+
+def _scaled(sc, f):
+    """The same problem in the box [0, f]^3 (a similarity: weights scale by f^2)."""
+    return scenes.Scene(sc.name + f"_x{f}", (sc.x.astype(np.float64) * f).astype(np.float32),
+                        (sc.y.astype(np.float64) * f).astype(np.float32),
+                        (sc.z.astype(np.float64) * f).astype(np.float32), sc.nu * f ** 3, sc.psi0 * f * f,
+                        box=((0, 0, 0), (f, f, f)), meta=dict(sc.meta))
+
+
+def test_batch_small_mixed_layouts(ctx, oracle_mod):
+    _say("case: batch of 12 instances (slab / sphere cluster), 200..3000 sites")
+    insts = scenes.batch_instances(12, base_seed=2000, n_lo=200, n_hi=3000)
+    offs, x, y, z, nu, psi = _concat(insts)
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi)
+    out = psi.cpu().numpy()
+    for b, (sc, st) in enumerate(zip(insts, sts)):
+        _say(f"  inst {b} n={sc.n} status={st.status} it={st.newton_iters} evals={st.evals} "
+             f"err={st.max_rel_err:.2e}")
+        assert st.status == 0 and st.max_rel_err <= 1e-5
+        assert _oracle_err(oracle_mod, sc, out[offs[b]:offs[b + 1]]) <= 1e-5
+
+
+def test_batch_matches_single_solves(ctx):
+    _say("case: batch of 5 vs the same instances solved one at a time")
+    import paper_2601_05765_amd as L
+    insts = scenes.batch_instances(5, base_seed=3000, n_lo=300, n_hi=2000)
+    offs, x, y, z, nu, psi = _concat(insts)
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi)
+    got = psi.cpu().numpy()
+    for b, sc in enumerate(insts):
+        _, xb, yb, zb, nub, pb = _concat([sc])
+        st1 = ctx.solve(xb, yb, zb, nub, pb, opts=L.default_opts())
+        assert st1.status == 0 and sts[b].status == 0
+        # both meet the tolerance; the weights are unique, so they agree closely
+        ref = pb.cpu().numpy()
+        assert np.max(np.abs(got[offs[b]:offs[b + 1]] - ref) / np.abs(ref)) <= 1e-3
+        assert sts[b].newton_iters == st1.newton_iters
+
+
+def test_batch_heterogeneous_boxes(ctx, oracle_mod):
+    _say("case: batch with boxes [0,1]^3, [0,2]^3, [0,0.5]^3")
+    base = scenes.batch_instances(3, base_seed=4000, n_lo=400, n_hi=1500)
+    insts = [base[0], _scaled(base[1], 2.0), _scaled(base[2], 0.5)]
+    boxes = [s.box for s in insts]
+    offs, x, y, z, nu, psi = _concat(insts)
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi, boxes=boxes)
+    out = psi.cpu().numpy()
+    for b, (sc, st) in enumerate(zip(insts, sts)):
+        assert st.status == 0 and st.max_rel_err <= 1e-5
+        assert _oracle_err(oracle_mod, sc, out[offs[b]:offs[b + 1]], box=sc.box) <= 1e-5
+
+
+def test_batch_statuses_are_independent(ctx):
+    _say("case: one instance with an empty start cell (no fallback), the others converge")
+    import paper_2601_05765_amd as L
+    insts = scenes.batch_instances(4, base_seed=5000, n_lo=300, n_hi=800)
+    psis = [s.psi0.copy() for s in insts]
+    psis[2][7] = -1.0
+    offs, x, y, z, nu, psi = _concat(insts, psis)
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi, opts=L.default_opts(empty_start_fallback=0), check=False)
+    assert [s.status for s in sts] == [0, 0, L.EEMPTY, 0]
+    # the failed instance keeps its start weights
+    assert np.array_equal(psi.cpu().numpy()[offs[2]:offs[3]], psis[2])
+    # with the fallback it restarts from the default weights and converges
+    offs, x, y, z, nu, psi = _concat(insts, psis)
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi)
+    assert all(s.status == 0 for s in sts) and sts[2].default_start == 1 and sts[0].default_start == 0
+
+
+def test_batch_rejects_invalid_instance(ctx):
+    _say("case: a site outside its box makes the whole call EINVAL, nothing solved")
+    import paper_2601_05765_amd as L
+    insts = scenes.batch_instances(3, base_seed=6000, n_lo=200, n_hi=500)
+    offs, x, y, z, nu, psi = _concat(insts)
+    x[int(offs[1]) + 3] = 1.5
+    before = psi.clone()
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi, check=False)
+    assert all(s.status == L.EINVAL for s in sts)
+    assert bool((psi == before).all())
+    with pytest.raises(ValueError):
+        ctx.solve_batched([0], x, y, z, nu, psi)
+
+
+def test_batch_256_instances_full_size(ctx, oracle_mod):
+    _say("case: 256 instances, N log-uniform in [500, 50000] (slab / sphere cluster)")
+    import paper_2601_05765_amd as L
+    insts = scenes.batch_instances(256)
+    offs, x, y, z, nu, psi = _concat(insts)
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    _say(f"  N={int(offs[-1])} ms={sts[0].ms_total:.1f} max it={max(s.newton_iters for s in sts)} "
+         f"fallback={sum(s.fallback_cells for s in sts)}")
+    assert all(s.status == 0 and s.max_rel_err <= 1e-5 for s in sts)
+    out = psi.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for b in rng.choice(256, 4, replace=False):
+        sc = insts[b]
+        idx = np.sort(rng.choice(sc.n, min(sc.n, 400), replace=False))
+        assert _oracle_err(oracle_mod, sc, out[offs[b]:offs[b + 1]], idx=idx) <= 1e-5
