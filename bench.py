@@ -75,6 +75,80 @@ def cpu_baseline(sc, psi, seconds_target: float = 15.0):
                       f"neighbours, FP64, one evaluation each ({dt:.1f} s)"}, c.work.mean(axis=0)
 
 
+def batched_section(ctx, L, scenes, reps: int = 3):
+    """256 independent instances (N log-uniform in [500, 50000], slab or sphere cluster) in one
+    lagot_solve_batched call, against the same instances solved one at a time."""
+    import torch
+    insts = scenes.batch_instances(256)
+    offs = np.concatenate([[0], np.cumsum([s.n for s in insts])]).astype(np.int64)
+    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    cat = lambda f: np.concatenate([f(s) for s in insts])
+    x, y, z = (t(cat(lambda s: s.x), torch.float32), t(cat(lambda s: s.y), torch.float32),
+               t(cat(lambda s: s.z), torch.float32))
+    nu, psi0 = t(cat(lambda s: s.nu), torch.float64), t(cat(lambda s: s.psi0), torch.float64)
+    opts = L.default_opts(tol=1e-5, autotune=1)
+    p = psi0.clone()
+    ctx.solve_batched(offs, x, y, z, nu, p, opts=opts)  # warm-up (and autotuning)
+    ms = []
+    for _ in range(reps):
+        p = psi0.clone()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sts = ctx.solve_batched(offs, x, y, z, nu, p, opts=opts)
+        torch.cuda.synchronize()
+        ms.append(1000.0 * (time.perf_counter() - a))
+    assert all(s.status == 0 for s in sts)
+    cell_evals = sum(s.evals * (offs[b + 1] - offs[b]) for b, s in enumerate(sts))
+    singles = []
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for sc in insts:
+        ps = t(sc.psi0, torch.float64)
+        ctx.solve(t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32), t(sc.nu, torch.float64),
+                  ps, opts=opts)
+    torch.cuda.synchronize()
+    singles = 1000.0 * (time.perf_counter() - a)
+    med = float(np.median(ms))
+    return {"instances": 256, "sites": int(offs[-1]), "ms_per_batched_solve": med,
+            "cells_per_s": float(cell_evals / (med / 1000.0)),
+            "newton_iters_max": max(s.newton_iters for s in sts),
+            "newton_iters_mean": float(np.mean([s.newton_iters for s in sts])),
+            "max_rel_err": max(s.max_rel_err for s in sts),
+            "ms_one_at_a_time": singles, "speedup_vs_one_at_a_time": singles / med}
+
+
+def learned_section(ctx, L, scenes, n_seeds: int, train_steps: int, steps: int):
+    """Learned warm start: train the network on the solver's own pairs (dam-break seeds
+    1..n_seeds, train_steps advect-and-solve steps each), then an advect-and-solve sequence
+    of a test scene (seed 77) from the previous step's weights, plain and with the guess."""
+    import torch
+    from paper_2601_05765_amd import warmstart
+    t0 = time.perf_counter()
+    F, T = warmstart.generate_pairs(ctx, seeds=range(1, n_seeds + 1), n=100_000, steps=train_steps,
+                                    log=lambda *a: None)
+    t_pairs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = warmstart.train(ctx, F, T, epochs=8, batch=4096, lr=1e-3, log=lambda *a: None)
+    t_train = time.perf_counter() - t0
+    sc = scenes.with_velocity(scenes.dam_break(100_000, 77), seed=777)
+    x, y, z = (torch.tensor(a, device="cuda") for a in (sc.x, sc.y, sc.z))
+    nu, psi = torch.tensor(sc.nu, device="cuda"), torch.tensor(sc.psi0, device="cuda")
+    ctx.solve(x, y, z, nu, psi)
+    quiet = lambda *a: None
+    warmstart.sequence(ctx, sc, 1, psi_start=psi, use_learned=True, log=quiet)  # warm-up
+    a = warmstart.sequence(ctx, sc, steps, psi_start=psi, use_learned=False, log=quiet)
+    b = warmstart.sequence(ctx, sc, steps, psi_start=psi, use_learned=True, log=quiet)
+    return {"pairs": int(F.shape[0]), "s_pairs": t_pairs, "s_train": t_train, "loss_first": hist[0],
+            "loss_last": hist[-1], "target_var": float(T.double().var().item()),
+            "steps": steps,
+            "ms_per_solve_plain": float(np.mean([r["ms"] for r in a])),
+            "ms_per_solve_learned": float(np.mean([r["ms"] for r in b])),
+            "newton_iters_plain": [r["newton_iters"] for r in a],
+            "newton_iters_learned": [r["newton_iters"] for r in b],
+            "guess_accepted": [r["learned_accepted"] for r in b],
+            "status_plain": [r["status"] for r in a], "status_learned": [r["status"] for r in b]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +158,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eval-reps", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched solve")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--learned-seeds", type=int, default=6, help="training scenes (100k sites each)")
+    ap.add_argument("--learned-steps", type=int, default=4, help="advect-and-solve steps per training scene")
+    ap.add_argument("--sequence-steps", type=int, default=5)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded design is described in "
@@ -104,7 +183,8 @@ def main(argv=None):
     x, y, z, nu = t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32), t(sc.nu, torch.float64)
     psi0 = t(sc.psi0, torch.float64)
     ctx = L.Context()
-    opts = L.default_opts(tol=1e-5)
+    # the autotuner picks lanes per cell and the PCG block shape during the warm-up
+    opts = L.default_opts(tol=1e-5, autotune=1)
 
     for _ in range(args.warmup):
         p = psi0.clone()
@@ -160,6 +240,11 @@ def main(argv=None):
                       "cells_per_s_kernel": args.n / (float(np.median(k_ms)) / 1000.0),
                       "ms_lagot_cells": float(np.median(ev_ms)), "ms_cell_kernel": float(np.median(k_ms))},
     }
+    if not args.no_batched:
+        line["batched"] = batched_section(ctx, L, scenes)
+    if not args.no_learned:
+        line["learned"] = learned_section(ctx, L, scenes, args.learned_seeds, args.learned_steps,
+                                          args.sequence_steps)
     work_mean = None
     if not args.no_cpu_baseline:
         cb, work_start = cpu_baseline(sc, sc.psi0, args.cpu_seconds)

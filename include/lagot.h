@@ -64,11 +64,14 @@ typedef struct {
                             32 or 64                                                             */
     int verbose;         /* 1: print one line per Newton iteration to stderr                        */
     int use_learned;     /* 1: try the learned warm start (lagot_mlp_set_params) before Newton       */
-    int empty_start_fallback; /* 1 (default): if a start cell is empty (KMT needs eps0 > 0),
-                            restart from the default weights psi_i = (1.2 (3 nu_i / 4 pi)^(1/3))^2 */
+    int empty_start_fallback; /* 1 (default): if a start cell is empty (KMT needs eps0 > 0), give
+                            the empty cells the default weight psi_i = (1.2 (3 nu_i / 4 pi)^(1/3))^2
+                            (at least), and if a cell is still empty restart from the default
+                            weights everywhere; 0: return LAGOT_EEMPTY                          */
     int autotune;        /* 1: when threads_per_cell is 0, time the cell kernel with 16, 32 and 64
-                            lanes per cell on the first solve of each size and density class and
-                            keep the fastest in the context (default 0: the context's default) */
+                            lanes per cell, and the PCG kernels with four block shapes, on the
+                            first solve of each size and density class, and keep the fastest in
+                            the context (default 0: the context's defaults)                    */
     int reserved[2];
 } lagot_opts;
 
@@ -83,6 +86,9 @@ typedef struct {
     int cell_launches;   /* launches of the float32 cell kernel (one per evaluation)      */
     int learned_accepted;/* 1 if the learned guess replaced the start weights             */
     int default_start;   /* 1 if an empty start cell forced the default start weights     */
+    int repaired_start;  /* 1 if empty start cells were given the default weight (the other
+                            weights kept)                                                   */
+    int reserved_i;
     double max_rel_err;  /* max_i |V_i - nu_i| / nu_i at the returned weights              */
     double grad_norm;    /* || nu - V ||_2 at the returned weights                         */
     double ms_total;     /* wall time of the call (host clock, stream synchronised)       */
@@ -176,9 +182,9 @@ int lagot_solve_batched(lagot_ctx *ctx, int32_t n_inst, const int64_t *offsets, 
  * Learned warm start (not part of the paper's method). With opts->use_learned set,
  * lagot_solve evaluates the network's guess like a Newton trial step from the given
  * start weights: it replaces them only if every cell of the guess keeps at least the
- * KMT floor eps0 = 1/2 min(min nu, min V(psi_start)) and ||nu - V||_2 is smaller than
- * at the start; eps0 stays that of the given start, and Newton then runs to the
- * tolerance as usual.
+ * KMT floor eps0 = 1/2 min(min nu, min V(psi_start)) and both ||nu - V||_2 and
+ * max_i |V_i - nu_i| / nu_i are smaller than at the start; eps0 stays that of the
+ * given start, and Newton then runs to the tolerance as usual.
  * Inputs of site i (64 bf16, row-major n x 64): offsets (p_j - p_i)/s_i of its 16 nearest
  * sites in ascending (distance, index), psi_prev_i / s_i^2, nu_i / mean(nu), and the
  * relative volume mismatch (nu - V)/nu under the previous weights of site i and of its
@@ -222,6 +228,14 @@ int lagot_mlp_last_grads(lagot_ctx *ctx, float *grads);
 /* Lanes per cell (8, 16, 32 or 64) used by lagot_cells and by solves whose options leave
  * threads_per_cell at 0 (default 32). Returns LAGOT_EINVAL for other values. */
 int lagot_set_threads_per_cell(lagot_ctx *ctx, int threads_per_cell);
+
+/* Block shape of the Jacobi-PCG kernels (one kernel per CG iteration) for solves whose
+ * options do not set autotune: lanes per matrix row (1, 2, 4 or 8) and rows per
+ * workgroup (64, 128 or 256; at most 128 with 8 lanes). Default 4 and 64. With
+ * opts->autotune the first direction solve of each size/density class times the shapes
+ * 2x128, 4x128, 2x64 and 4x64 and keeps the fastest. Affects speed only.
+ * Returns LAGOT_EINVAL for other shapes. */
+int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block);
 
 /* Number of cells that the last lagot_cells call on this context redid on the
  * large-capacity float64 path (diagnostic; -1 if ctx is NULL). */

@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int), ("evals", ctypes.c_int),
                 ("halvings", ctypes.c_int), ("cg_iters", ctypes.c_int), ("fallback_cells", ctypes.c_int),
                 ("failed_cells", ctypes.c_int), ("cell_launches", ctypes.c_int), ("learned_accepted", ctypes.c_int),
-                ("default_start", ctypes.c_int), ("max_rel_err", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("default_start", ctypes.c_int), ("repaired_start", ctypes.c_int), ("reserved_i", ctypes.c_int),
+                ("max_rel_err", ctypes.c_double), ("grad_norm", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_eval", ctypes.c_double), ("ms_linear", ctypes.c_double),
                 ("ms_cell_kernel", ctypes.c_double), ("ms_learned", ctypes.c_double),
                 ("reserved_d", ctypes.c_double * 1)]
@@ -93,6 +94,8 @@ def load():
             getattr(lib, f).restype = I
         lib.lagot_set_threads_per_cell.argtypes = [P, I]
         lib.lagot_set_threads_per_cell.restype = I
+        lib.lagot_set_cg_shape.argtypes = [P, I, I]
+        lib.lagot_set_cg_shape.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
         lib.lagot_last_fallback_cells.restype = I
         lib.lagot_last_cell_kernel_ms.argtypes = [P]
@@ -203,6 +206,11 @@ class Context:
             out["row_ptr"], out["col"], out["area"] = rp, col[: nnz.value], fa[: nnz.value]
         out["nnz"] = int(nnz.value)
         return out
+
+    def set_cg_shape(self, lanes_per_row: int, rows_per_block: int) -> None:
+        rc = load().lagot_set_cg_shape(self._h, int(lanes_per_row), int(rows_per_block))
+        if rc != OK:
+            raise LagotError(rc, "lagot_set_cg_shape")
 
     def set_threads_per_cell(self, tpc: int) -> None:
         rc = load().lagot_set_threads_per_cell(self._h, int(tpc))

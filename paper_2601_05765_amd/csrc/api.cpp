@@ -44,8 +44,15 @@ struct lagot_ctx {
     int cap_B = 0, cap_T = 0;
     int tpc = 32;
     int tpc_default = 32;  // lanes per cell when the options leave it to the library
-    std::map<int, int> tpc_tuned;  // autotuner: size/density class -> lanes per cell
+    struct Tuned {
+        int tpc = 32, cg_lanes = 4, cg_sub = 64;
+        bool cg = false;  // the CG shape has been timed too
+    };
+    std::map<int, Tuned> tuned;    // autotuner: size/density class -> shapes
+    int tune_key = -1;             // class whose CG shape the next direction solve times
     int cg_chunk = 16;             // PCG launches between host checks (adapted per solve)
+    int cg_lanes = 4, cg_sub = 64; // PCG block shape of the current call: lanes per row, rows per block
+    int cg_lanes_def = 4, cg_sub_def = 64;  // ... when the options do not ask for the autotuner
 
     // the current call: B instances, T tiles, n rows
     int B = 0, T = 0;
@@ -74,12 +81,18 @@ struct lagot_ctx {
     int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr;
     float *farea = nullptr;
     uint32_t *flags = nullptr;
+    // second set of evaluation outputs (learned guess: evaluated aside, swapped in if kept)
+    double *V2 = nullptr, *K2 = nullptr;
+    int32_t *fcol2 = nullptr, *fcnt2 = nullptr;
+    float *farea2 = nullptr;
+    uint32_t *flags2 = nullptr;
+    int64_t cap_alt = 0;
     // Hessian and PCG
     int32_t *hcol = nullptr, *hcnt = nullptr, *xcnt = nullptr;
     float *hval = nullptr;
     double *diag = nullptr;
-    double *cg_vec = nullptr;   // r[2], w[2], s[2], p, x: 8 vectors of cap_n
-    double *cg_part = nullptr;  // 7 * cap_T
+    double *cg_vec = nullptr;   // rws[2] (4 doubles per row each), p, x: 10 doubles per row
+    double *cg_part = nullptr;  // 7 * 4 * cap_T
     double *cg_cgs = nullptr;   // 4 * cap_B
     int32_t *cg_cgst = nullptr; // 4 * cap_B
     // pinned host staging (uploads) and read-back
@@ -143,7 +156,36 @@ void free_inst(lagot_ctx *c) {
               c->cg_cgst);
 }
 
+void free_alt(lagot_ctx *c) {
+    free_ptrs(c->V2, c->K2, c->fcol2, c->fcnt2, c->farea2, c->flags2);
+    c->cap_alt = 0;
+}
+
+int ensure_alt(lagot_ctx *c, int64_t n) {
+    if (n <= c->cap_alt) return LAGOT_OK;
+    free_alt(c);
+    const size_t N = (size_t)n;
+    HIP_TRY(dalloc(&c->V2, N));
+    HIP_TRY(dalloc(&c->K2, N));
+    HIP_TRY(dalloc(&c->fcol2, FCAP * N));
+    HIP_TRY(dalloc(&c->farea2, FCAP * N));
+    HIP_TRY(dalloc(&c->fcnt2, N));
+    HIP_TRY(dalloc(&c->flags2, N));
+    c->cap_alt = n;
+    return LAGOT_OK;
+}
+
+void swap_alt(lagot_ctx *c) {
+    std::swap(c->V, c->V2);
+    std::swap(c->K, c->K2);
+    std::swap(c->fcol, c->fcol2);
+    std::swap(c->farea, c->farea2);
+    std::swap(c->fcnt, c->fcnt2);
+    std::swap(c->flags, c->flags2);
+}
+
 void free_all(lagot_ctx *c) {
+    free_alt(c);
     free_sites(c);
     free_inst(c);
     free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc);
@@ -193,7 +235,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->hcnt, N));
     HIP_TRY(dalloc(&c->xcnt, N));
     HIP_TRY(dalloc(&c->diag, N));
-    HIP_TRY(dalloc(&c->cg_vec, 8 * N));
+    HIP_TRY(dalloc(&c->cg_vec, 10 * N));
     HIP_TRY(dalloc(&c->csr_cnt, N + 1));
     HIP_TRY(dalloc(&c->csr_start, N + 1));
     HIP_TRY(dalloc(&c->csr_tmp, N / 1024 + 16));
@@ -225,7 +267,7 @@ int ensure_inst(lagot_ctx *c, int B, int T) {
     HIP_TRY(dalloc(&c->fail_inst, b));
     HIP_TRY(dalloc(&c->bad_inst, b));
     HIP_TRY(dalloc(&c->herr, b));
-    HIP_TRY(dalloc(&c->cg_part, 7 * t));
+    HIP_TRY(dalloc(&c->cg_part, 7 * 4 * t));  // per quarter tile
     HIP_TRY(dalloc(&c->cg_cgs, 4 * b));
     HIP_TRY(dalloc(&c->cg_cgst, 4 * b));
     c->cap_B = B;
@@ -291,13 +333,9 @@ Batch batch(const lagot_ctx *c) {
 CgBufs cg_bufs(const lagot_ctx *c) {
     CgBufs g;
     const size_t N = (size_t)c->cap_n;
-    for (int q = 0; q < 2; ++q) {
-        g.r[q] = c->cg_vec + (0 + q) * N;
-        g.w[q] = c->cg_vec + (2 + q) * N;
-        g.s[q] = c->cg_vec + (4 + q) * N;
-    }
-    g.p = c->cg_vec + 6 * N;
-    g.x = c->cg_vec + 7 * N;
+    for (int q = 0; q < 2; ++q) g.rws[q] = reinterpret_cast<RWSD *>(c->cg_vec + 4 * q * N);
+    g.p = c->cg_vec + 8 * N;
+    g.x = c->cg_vec + 9 * N;
     g.part = c->cg_part;
     g.cgs = c->cg_cgs;
     g.cgst = c->cg_cgst;
@@ -570,9 +608,15 @@ int autotune_tpc(lagot_ctx *c) {
     const double per_ball = (double)c->n * (4.0 / 3.0) * M_PI * rm * rm * rm / std::max(vol, 1e-300);
     const int key = (int)std::floor(std::log2((double)c->n / c->B)) * 64 +
                     std::min(63, std::max(0, (int)std::floor(std::log2(per_ball + 1e-30)) + 32));
-    auto it = c->tpc_tuned.find(key);
-    if (it != c->tpc_tuned.end()) {
-        c->tpc = it->second;
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+        c->tpc = it->second.tpc;
+        if (it->second.cg) {
+            c->cg_lanes = it->second.cg_lanes;
+            c->cg_sub = it->second.cg_sub;
+        } else {
+            c->tune_key = key;
+        }
         return LAGOT_OK;
     }
     const int cand[3] = {16, 32, 64};
@@ -593,25 +637,25 @@ int autotune_tpc(lagot_ctx *c) {
         }
     }
     c->tpc = best_t;
-    c->tpc_tuned[key] = best_t;
+    c->tuned[key].tpc = best_t;
+    c->tune_key = key;
     return LAGOT_OK;
 }
 
-// One Jacobi-PCG direction solve for every ACTIVE instance, then ACTIVE -> TRIAL.
-int newton_direction(lagot_ctx *c, const lagot_opts &o) {
+// Jacobi-PCG for every ACTIVE instance with the context's block shape: chunks of
+// launches, then the count of instances still iterating is read back.
+int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched) {
     const Batch bt = batch(c);
     const CgBufs cg = cg_bufs(c);
     hipStream_t st = c->stream;
-    launch_hess_assemble(st, c->n, bt, PH_ACTIVE, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval, c->xcnt,
-                         c->herr);
-    launch_hess_finish(st, c->n, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hval, c->diag);
-    launch_cg_init(st, bt, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt, cg);
+    launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt, cg);
     const double rtol2 = o.cg_rtol * o.cg_rtol;
     const int cap = o.cg_max_iter;
     int k = 0;
     while (k < cap) {
         const int m = std::min(c->cg_chunk, cap - k);
-        for (int q = 0; q < m; ++q) launch_cg_iter(st, bt, q, rtol2, cap, c->hcol, c->hval, c->hcnt, c->diag, cg);
+        for (int q = 0; q < m; ++q)
+            launch_cg_iter(st, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hcol, c->hval, c->hcnt, c->diag, cg);
         launch_cg_advance(st, bt, m, cap, cg);
         k += m;
         HIP_TRY(hipMemcpyAsync(c->h_cnt + 8, c->misc + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -619,9 +663,57 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o) {
         if (rc) return rc;
         if (c->h_cnt[8] == 0) break;
     }
+    *launched = k;
+    return LAGOT_OK;
+}
+
+// One Jacobi-PCG direction solve for every ACTIVE instance, then ACTIVE -> TRIAL.
+// When the autotuner asks for it, the solve is first run with each candidate block
+// shape (the same system each time) and the fastest shape is kept for the class.
+int newton_direction(lagot_ctx *c, const lagot_opts &o) {
+    const Batch bt = batch(c);
+    hipStream_t st = c->stream;
+    launch_hess_assemble(st, c->n, bt, PH_ACTIVE, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval, c->xcnt,
+                         c->herr);
+    launch_hess_finish(st, c->n, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hval, c->diag);
+    int k = 0, rc;
+    if (c->tune_key >= 0) {
+        static const int shapes[4][2] = {{2, 128}, {4, 128}, {2, 64}, {4, 64}};
+        double best = 1e300;
+        int bl = c->cg_lanes, bs = c->cg_sub;
+        for (const auto &sh : shapes) {
+            c->cg_lanes = sh[0];
+            c->cg_sub = sh[1];
+            rc = sync(c);
+            if (rc) return rc;
+            const double t0 = now_ms();
+            rc = run_cg(c, o, &k);
+            if (rc) return rc;
+            const double ms = now_ms() - t0;
+            if (ms < best) {
+                best = ms;
+                bl = sh[0];
+                bs = sh[1];
+            }
+        }
+        auto &tu = c->tuned[c->tune_key];
+        tu.cg_lanes = bl;
+        tu.cg_sub = bs;
+        tu.cg = true;
+        c->tune_key = -1;
+        c->cg_lanes = bl;
+        c->cg_sub = bs;
+        if (!(bl == shapes[3][0] && bs == shapes[3][1])) {
+            rc = run_cg(c, o, &k);  // the direction of the kept shape
+            if (rc) return rc;
+        }
+    } else {
+        rc = run_cg(c, o, &k);
+        if (rc) return rc;
+    }
     // chunk length for the next direction: about this solve's iteration count
     c->cg_chunk = std::min(64, std::max(8, (k + 3) / 4 * 4));
-    launch_cg_finish(st, bt, rtol2, cg, c->herr, c->ctl, c->phase);
+    launch_cg_finish(st, bt, c->cg_sub, o.cg_rtol * o.cg_rtol, cg_bufs(c), c->herr, c->ctl, c->phase);
     return LAGOT_OK;
 }
 
@@ -631,7 +723,8 @@ struct CallTimes {
 };
 
 // Learned guess for a single instance, evaluated like a trial step from the start
-// weights: kept if every cell keeps eps0 and the residual drops.
+// weights into the second set of outputs: kept if every cell keeps eps0 and both the
+// residual norm and the largest relative volume error (the stop test) drop.
 int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
     *accepted = 0;
     const Batch bt = batch(c);
@@ -647,28 +740,29 @@ int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
     if (hf[0] != 0 || !(eps0 > 0.0)) return LAGOT_OK;  // Newton handles this start itself
     const double t0 = now_ms();
     rc = build_features(c);
+    if (!rc) rc = ensure_alt(c, c->n);
     if (rc) return rc;
     mlp_forward_dev(c, (int)c->n, c->feat_s, c->inf_a, c->inf_b, c->mlp_out);
     launch_apply_guess(st, c->n, c->psi_s, c->nu_s, c->mlp_out, c->psi_trial, c->pos_s);
     launch_rmax(st, bt, -1, c->psi_trial, c->rmax);
+    swap_alt(c);  // the guess's cells go to the second output set
     evaluate(c, -1, c->psi_trial, false, c->ev2);
+    swap_alt(c);
     tm.extra_evals++;
     HIP_TRY(hipMemcpyAsync(h + 4, c->ev2, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(hf + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(hf + 2, c->misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     rc = sync(c);
     if (rc) return rc;
-    if (hf[2] == 0 && hf[1] == 0 && h[7] >= eps0 && h[6] < h[2]) {
+    if (hf[2] == 0 && hf[1] == 0 && h[7] >= eps0 && h[6] < h[2] && h[5] < h[1]) {
         HIP_TRY(hipMemcpyAsync(c->psi_s, c->psi_trial, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st));
+        swap_alt(c);
         *accepted = 1;
     } else {
-        // back to the start weights; the cell outputs must describe them again
+        // back to the start weights, whose cells are still in the first output set
         launch_psi_shadow(st, c->n, c->psi_s, c->pos_s);
         launch_rmax(st, bt, -1, c->psi_s, c->rmax);
-        evaluate(c, -1, c->psi_s, false, c->ev);
-        tm.extra_evals++;
-        rc = sync(c);
-        if (rc) return rc;
+        launch_zero_i32(st, c->fail_inst, 1);  // the start had no failed cell (checked above)
     }
     tm.learned += now_ms() - t0;
     return LAGOT_OK;
@@ -705,6 +799,9 @@ int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const f
     c->ev_pending = false;
     rc = prepare(c, B, offs, x, y, z, psi, nu, boxes, &bad);
     if (rc) return fail_all(rc);
+    c->tune_key = -1;
+    c->cg_lanes = c->cg_lanes_def;
+    c->cg_sub = c->cg_sub_def;
     if (o.autotune && o.threads_per_cell == 0) {
         rc = autotune_tpc(c);
         if (rc) return fail_all(rc);
@@ -730,6 +827,15 @@ int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const f
                      c->counts);
     rc = read_counts(c);
     if (rc) return fail_all(rc);
+    if (c->h_cnt[PH_REPAIR] > 0) {
+        launch_repair_empty(st, bt, PH_REPAIR, c->V, c->nu_s, c->cell_start, c->psi_s, c->psi_trial, c->pos_s);
+        std::swap(c->psi_s, c->psi_trial);
+        launch_rmax(st, bt, PH_REPAIR, c->psi_s, c->rmax);
+        evaluate(c, PH_REPAIR, c->psi_s, false, c->ev);
+        launch_ctl_start(st, bt, co, PH_REPAIR, c->ev, c->ev_nu, c->ev, c->fail_inst, c->ctl, c->phase, c->counts);
+        rc = read_counts(c);
+        if (rc) return fail_all(rc);
+    }
     if (c->h_cnt[PH_RESTART] > 0) {
         launch_default_start(st, bt, PH_RESTART, c->nu_s, c->psi_s, c->pos_s);
         launch_rmax(st, bt, PH_RESTART, c->psi_s, c->rmax);
@@ -790,6 +896,7 @@ int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const f
         S.cell_launches = c->cell_launches;
         S.learned_accepted = learned;
         S.default_start = q.default_start;
+        S.repaired_start = q.repaired;
         S.max_rel_err = q.maxrel;
         S.grad_norm = q.gnorm;
         S.ms_total = ms_total;
@@ -1037,6 +1144,13 @@ int lagot_mlp_last_grads(lagot_ctx *c, float *grads) {
 int lagot_set_threads_per_cell(lagot_ctx *ctx, int threads_per_cell) {
     if (!ctx || !valid_tpc(threads_per_cell)) return LAGOT_EINVAL;
     ctx->tpc_default = threads_per_cell;
+    return LAGOT_OK;
+}
+
+int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block) {
+    if (!ctx || !cg_shape_ok(lanes_per_row, rows_per_block)) return LAGOT_EINVAL;
+    ctx->cg_lanes = ctx->cg_lanes_def = lanes_per_row;
+    ctx->cg_sub = ctx->cg_sub_def = rows_per_block;
     return LAGOT_OK;
 }
 

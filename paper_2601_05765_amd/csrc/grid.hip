@@ -120,10 +120,11 @@ __global__ __launch_bounds__(1024) void k_rmax_zero(Batch bt, int want, double *
         if (selected(bt, want, b)) rmax[b] = 0.0;
 }
 
-// rmax[b] = max over rows of sqrt(psi); a tile lies in one instance, so one
-// wave-wide max and one atomic per tile (max is order-independent: deterministic)
+// rmax[b] = max over rows of sqrt(psi). A tile lies in one instance: a block-wide
+// max and one atomic per tile (max is order-independent: deterministic).
 __global__ __launch_bounds__(TILE) void k_rmax_tiles(Batch bt, int want, const double *__restrict__ psi,
                                                       double *__restrict__ rmax) {
+    __shared__ double sh[TILE / 64];
     const int t = blockIdx.x;
     const int b = bt.tile_inst[t];
     if (!selected(bt, want, b)) return;
@@ -134,9 +135,13 @@ __global__ __launch_bounds__(TILE) void k_rmax_tiles(Batch bt, int want, const d
         r = p > 0.0 ? sqrt(p) : 0.0;
     }
     for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
-    // non-negative doubles order like their bit patterns
-    if (threadIdx.x == 0)
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < TILE / 64; ++w) r = fmax(r, sh[w]);
+        // non-negative doubles order like their bit patterns
         atomicMax(reinterpret_cast<unsigned long long *>(rmax + b), (unsigned long long)__double_as_longlong(r));
+    }
 }
 
 __device__ inline int grid_key(const GridDesc &g, float px, float py, float pz) {
@@ -279,6 +284,60 @@ __global__ __launch_bounds__(TILE) void k_default_start(Batch bt, int want, cons
     pos[i].w = (float)(r * r);
 }
 
+// A start cell that is empty gets the smallest weight that puts its site inside
+// every power half-space: with psi_i >= psi_j - d_ij^2 for all j, every bisector has
+// t_ij >= 0, so p_i lies in C_i and the cell is not empty; at equality the nearest
+// bisector passes through p_i and the neighbour keeps t_ji = d_ij > 0, so nearly
+// coincident pairs keep both cells. New weight: max(psi_i, max_j (psi_j - d_ij^2))
+// (the default weight if that is not positive), capped at twice the default weight
+// (a much heavier neighbour is left to the full restart). Only sites within
+// 2 max(r_max, r_i) can matter (farther bisectors miss the ball). The other weights
+// keep the warm start. One thread per row; weights are read from psi and written to
+// psi_out (every row: a copy where nothing changes), so the result does not depend
+// on the order in which rows are repaired.
+__global__ __launch_bounds__(TILE) void k_repair_empty(Batch bt, int want, const double *__restrict__ V,
+                                                        const double *__restrict__ nu, const int32_t *__restrict__ cell_start,
+                                                        const double *__restrict__ psi, double *__restrict__ psi_out,
+                                                        float4 *__restrict__ pos) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    if (i >= bt.off[b + 1]) return;
+    if (!selected(bt, want, b) || V[i] > 0.0) {
+        psi_out[i] = psi[i];
+        return;
+    }
+    const double rd2 = pow(1.2 * cbrt(3.0 * nu[i] / (4.0 * 3.14159265358979323846)), 2.0);
+    const double p0 = psi[i];
+    const double cap = fmax(p0, 2.0 * rd2);
+    const GridDesc g = bt.grid[b];
+    const float4 pi = pos[i];
+    const float reach = 2.0f * fmaxf((float)bt.rmax[b], (float)sqrt(cap)) * 1.0001f;
+    const float pp[3] = {pi.x, pi.y, pi.z};
+    int lo3[3], hi3[3];
+    for (int a = 0; a < 3; ++a) {
+        lo3[a] = max((int)floorf((pp[a] - reach - g.lo[a]) * g.inv_s), 0);
+        hi3[a] = min((int)floorf((pp[a] + reach - g.lo[a]) * g.inv_s), g.dim[a] - 1);
+    }
+    double m = -1e300;
+    for (int ix = lo3[0]; ix <= hi3[0]; ++ix)
+        for (int iy = lo3[1]; iy <= hi3[1]; ++iy) {
+            const int col = g.base + (ix * g.dim[1] + iy) * g.dim[2];
+            const int beg = cell_start[col + lo3[2]], end = cell_start[col + hi3[2] + 1];
+            for (int j = beg; j < end; ++j) {
+                if (j == i) continue;
+                const float4 q = pos[j];  // x, y, z only (.w of repaired rows changes)
+                const double dx = (double)q.x - pi.x, dy = (double)q.y - pi.y, dz = (double)q.z - pi.z;
+                m = fmax(m, psi[j] - (dx * dx + dy * dy + dz * dz));
+            }
+        }
+    double w = fmax(p0, m);
+    if (!(w > 0.0)) w = rd2;
+    w = fmin(w, cap);
+    psi_out[i] = w;
+    pos[i].w = (float)w;
+}
+
 // dst row perm[k] = src row k, rows of `chunks` 16-byte words
 __global__ void k_scatter_rows(int64_t n, int chunks, const int32_t *__restrict__ perm, const uint4 *__restrict__ src,
                                uint4 *__restrict__ dst) {
@@ -296,6 +355,12 @@ inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *nu_s, double *psi_s,
                           float4 *pos_s) {
     hipLaunchKernelGGL(k_default_start, dim3(bt.T), dim3(TILE), 0, st, bt, want, nu_s, psi_s, pos_s);
+}
+
+void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu_s,
+                         const int32_t *cell_start, const double *psi_s, double *psi_out, float4 *pos_s) {
+    hipLaunchKernelGGL(k_repair_empty, dim3(bt.T), dim3(TILE), 0, st, bt, want, V, nu_s, cell_start, psi_s, psi_out,
+                       pos_s);
 }
 
 void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst) {

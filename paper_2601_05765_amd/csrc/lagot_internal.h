@@ -57,8 +57,9 @@ struct BoxF {
 // has its own grid over its own box, and the spatial sort never moves a site out
 // of its instance's range. Row-parallel kernels run over TILE-row tiles that
 // never straddle two instances, so per-instance reductions are sums over a
-// contiguous run of tile partials (fixed order, deterministic).
-constexpr int TILE = 64;
+// contiguous run of tile partials (fixed order, deterministic). A tile is one
+// workgroup: TILE threads for row-wise kernels, 4 x TILE for the sparse products.
+constexpr int TILE = 256;
 
 // Per-instance control phase (device array, read by every kernel that may skip
 // an instance).
@@ -69,7 +70,8 @@ enum Phase : int32_t {
     PH_ACCEPT = 3,   // trial accepted in this round (transient)
     PH_FAILED = 4,   // stopped with an error status
     PH_START = 5,    // initial evaluation pending
-    PH_RESTART = 6,  // empty start cell: restart from the default weights
+    PH_RESTART = 6,  // empty start cell after a repair: restart from the default weights
+    PH_REPAIR = 7,   // empty start cell: raise the weights of the empty cells to the default
 };
 
 struct Batch {
@@ -99,7 +101,8 @@ struct InstCtl {
     double sumV;       // sum V at the accepted iterate
     int iters, evals, halvings, hstep, cg_iters, status, default_start, learned;
     int restore;       // the float32 shadow must be reset to the accepted weights
-    int pad[3];
+    int repaired;      // empty start cells were given the default weight
+    int pad[2];
 };
 
 // Newton options as the device control kernels see them.
@@ -124,14 +127,18 @@ struct EvalOut {
 };
 
 // Conjugate-gradient vectors and scalars (Chronopoulos-Gear form, one kernel per
-// iteration). r, w = A u and s = A p are kept for two iterations (slot k % 2 is
-// read by iteration k, slot (k+1) % 2 written), so that a row can rebuild the
-// next preconditioned residual of any neighbour from that neighbour's stored
-// values; p and x are touched by their own row only.
+// iteration). Per row, r, w = A u, s = A p and the Jacobi diagonal D form one 32-byte
+// record, kept for two iterations (slot k % 2 is read by iteration k, slot (k+1) % 2
+// written), so that a row can rebuild the next preconditioned residual of any
+// neighbour from one record load; p and x are touched by their own row only.
+struct RWSD {
+    double r, w, s, d;
+};
 struct CgBufs {
-    double *r[2], *w[2], *s[2];
+    RWSD *rws[2];
     double *p, *x;           // x: the Newton direction
-    double *part;            // tile partials: gamma[2][T], delta[2][T], rho[2][T], rho0[T]
+    double *part;            // partials per quarter tile (NS = 4T): gamma[2][NS], delta[2][NS],
+                             // rho[2][NS], rho0[NS]
     double *cgs;             // [B][4] alpha and gamma of iterations k%2 = 0, 1
     int32_t *cgst;           // [B][4] iterations done, breakdown, converged, unused
     int32_t *kbase;          // [1] index of the first iteration of the next chunk
@@ -163,6 +170,10 @@ void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const 
 void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t *perm, const void *src, void *dst);
 void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *nu_s, double *psi_s,
                           float4 *pos_s);
+// psi_out = psi_s, except that empty cells (V <= 0) of the selected instances get
+// max(psi, default weight, weights of the neighbours whose power region contains the ball)
+void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu_s,
+                         const int32_t *cell_start, const double *psi_s, double *psi_out, float4 *pos_s);
 
 // cells.hip
 // Cells of the selected instances at the float64 weights psi (float32 shadow in pos_s.w).
@@ -181,13 +192,16 @@ void launch_hess_assemble(hipStream_t st, int64_t n, const Batch &bt, int want, 
                           int32_t *xcnt, int32_t *herr);
 void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, const double *psi_s, const double *K,
                         const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag);
-void launch_cg_init(hipStream_t st, const Batch &bt, const double *V, const double *nu, const double *diag,
-                    const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg);
-void launch_cg_iter(hipStream_t st, const Batch &bt, int m, double rtol2, int cap, const int32_t *hcol,
-                    const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg);
+// CG block shape: `lanes` lanes per row (1, 2, 4 or 8), `sub` rows per block (64, 128
+// or 256; 8 lanes with at most 128 rows)
+bool cg_shape_ok(int lanes, int sub);
+void launch_cg_init(hipStream_t st, const Batch &bt, int lanes, int sub, const double *V, const double *nu,
+                    const double *diag, const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg);
+void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
+                    const int32_t *hcol, const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg);
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg);
-void launch_cg_finish(hipStream_t st, const Batch &bt, double rtol2, CgBufs cg, const int32_t *herr, InstCtl *ctl,
-                      int32_t *phase);
+void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, CgBufs cg, const int32_t *herr,
+                      InstCtl *ctl, int32_t *phase);
 void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase);
 // ev: statistics of the first iterate; ev_floor: of the given start weights (eps0)
 void launch_ctl_start(hipStream_t st, const Batch &bt, CtlOpts o, int from_phase, const double *ev,

@@ -33,7 +33,29 @@ __device__ inline float gelu_grad(float x) {
 // ---------------- 16 nearest sites and the network inputs ----------------
 // One thread per site (grid order). Sorted top-16 kept in registers (static
 // indices). Distances in float64 without contraction (the float32 inputs make
-// the differences and their squares exact), ties by caller index.
+// the differences and their squares exact), ties by caller index. The search
+// grows by shells of grid cells (ring R adds the cells at Chebyshev distance R
+// from the site's cell) and stops once the 16th distance is within R cell sizes,
+// which every unvisited cell is beyond. A candidate is compared with the current
+// 16th entry first; only closer ones run the insertion pass.
+__device__ inline void knn_offer(double kd, int ki, int kj, double (&D)[N_NEI], int (&I)[N_NEI], int (&J)[N_NEI]) {
+    if (!(kd < D[N_NEI - 1] || (kd == D[N_NEI - 1] && ki < I[N_NEI - 1]))) return;
+#pragma unroll
+    for (int m = 0; m < N_NEI; ++m) {
+        const bool less = kd < D[m] || (kd == D[m] && ki < I[m]);
+        if (less) {
+            const double td = D[m];
+            const int ti = I[m], tj = J[m];
+            D[m] = kd;
+            I[m] = ki;
+            J[m] = kj;
+            kd = td;
+            ki = ti;
+            kj = tj;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_knn_features(int64_t n, const float4 *__restrict__ pos_s,
                                                        const int32_t *__restrict__ perm,
                                                        const int32_t *__restrict__ cell_start, GridDesc g,
@@ -57,42 +79,31 @@ __global__ __launch_bounds__(256) void k_knn_features(int64_t n, const float4 *_
     const float pp[3] = {p.x, p.y, p.z};
     for (int a = 0; a < 3; ++a) c3[a] = min(max((int)floorf((pp[a] - g.lo[a]) * g.inv_s), 0), g.dim[a] - 1);
     int found = 0;
-    for (int R = 1;; ++R) {
-        found = 0;
-#pragma unroll
-        for (int m = 0; m < N_NEI; ++m) {
-            D[m] = 1e300;
-            I[m] = 0x7FFFFFFF;
-            J[m] = -1;
-        }
+    for (int R = 0;; ++R) {
         const int x0 = max(c3[0] - R, 0), x1 = min(c3[0] + R, g.dim[0] - 1);
         const int y0 = max(c3[1] - R, 0), y1 = min(c3[1] + R, g.dim[1] - 1);
         const int z0 = max(c3[2] - R, 0), z1 = min(c3[2] + R, g.dim[2] - 1);
         for (int ix = x0; ix <= x1; ++ix)
             for (int iy = y0; iy <= y1; ++iy) {
                 const int col = (ix * g.dim[1] + iy) * g.dim[2];
-                const int beg = cell_start[col + z0], end = cell_start[col + z1 + 1];
-                for (int j = beg; j < end; ++j) {
-                    if (j == k) continue;
-                    const float4 q = pos_s[j];
-                    const double dx = (double)q.x - (double)p.x, dy = (double)q.y - (double)p.y,
-                                 dz = (double)q.z - (double)p.z;
-                    double kd = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-                    int ki = perm[j], kj = j;
-                    ++found;
-#pragma unroll
-                    for (int m = 0; m < N_NEI; ++m) {
-                        const bool less = kd < D[m] || (kd == D[m] && ki < I[m]);
-                        if (less) {
-                            const double td = D[m];
-                            const int ti = I[m], tj = J[m];
-                            D[m] = kd;
-                            I[m] = ki;
-                            J[m] = kj;
-                            kd = td;
-                            ki = ti;
-                            kj = tj;
-                        }
+                // columns inside the previous ring contribute only their two new end cells
+                const bool inner = abs(ix - c3[0]) < R && abs(iy - c3[1]) < R;
+                for (int part = 0; part < (inner ? 2 : 1); ++part) {
+                    int za = z0, zb = z1;
+                    if (inner) {
+                        za = zb = part == 0 ? c3[2] - R : c3[2] + R;
+                        if (za < 0 || za >= g.dim[2]) continue;
+                    }
+                    const int beg = cell_start[col + za], end = cell_start[col + zb + 1];
+                    for (int j = beg; j < end; ++j) {
+                        if (j == k) continue;
+                        const float4 q = pos_s[j];
+                        const double dx = (double)q.x - (double)p.x, dy = (double)q.y - (double)p.y,
+                                     dz = (double)q.z - (double)p.z;
+                        const double kd =
+                            __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+                        ++found;
+                        knn_offer(kd, perm[j], j, D, I, J);
                     }
                 }
             }

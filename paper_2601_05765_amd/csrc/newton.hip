@@ -63,6 +63,7 @@ __device__ inline double block_min(double v, double *sh) {
 // part[q*T + t], q = 0..3: sum V, max |V-nu|/nu, sum (nu-V)^2, min V over tile t
 __global__ __launch_bounds__(TILE) void k_eval_partial(Batch bt, int want, const double *__restrict__ V,
                                                         const double *__restrict__ nu, double *__restrict__ part) {
+    __shared__ double sh[TILE / 64];
     const int t = blockIdx.x;
     const int b = bt.tile_inst[t];
     if (!selected(bt, want, b)) return;
@@ -75,12 +76,10 @@ __global__ __launch_bounds__(TILE) void k_eval_partial(Batch bt, int want, const
         g2 = (c - v) * (c - v);
         mn = v;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        sv += __shfl_xor(sv, o, 64);
-        mx = fmax(mx, __shfl_xor(mx, o, 64));
-        g2 += __shfl_xor(g2, o, 64);
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-    }
+    sv = block_sum(sv, sh);
+    mx = block_max(mx, sh);
+    g2 = block_sum(g2, sh);
+    mn = block_min(mn, sh);
     if (threadIdx.x == 0) {
         const int T = bt.T;
         part[t] = sv;
@@ -202,12 +201,18 @@ __global__ void k_hess_finish(int64_t n, Batch bt, int want, const double *__res
 // the scalars from its instance's tile partials in a fixed order: deterministic,
 // no atomics, no device-scope fences (a device-scope fence writes back the XCD's
 // L2 on this part). The stop test is ||r_k|| <= rtol ||r_0||.
-constexpr int LANES = 4;  // lanes per row: rows hold ~6-20 entries; one tile per block
+// Block shapes of the conjugate-gradient kernels: LANES lanes per row (rows hold
+// ~6-20 entries) and SUB rows per block (a block covers a sub-tile; partials are kept
+// per sub-tile, so SUB sets how many partials every block sums). Chosen per context
+// (lagot_set_cg_shape / the autotuner); the partial buffers are sized for SUB = 64.
+constexpr int PF = 4;              // row entries per lane fetched before the scalars are known
 
+// Four fixed-order sums over the partials t0..t1-1 (any block size, multiple of 64;
+// sh holds one row per wave).
 __device__ inline void sum_range(const double *a, const double *b, const double *c, const double *d, int t0, int t1,
                                  double *out, double (*sh)[4]) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int t = t0 + (int)threadIdx.x; t < t1; t += RB) {
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += (int)blockDim.x) {
         s[0] += a[t];
         s[1] += b[t];
         s[2] += c[t];
@@ -223,7 +228,7 @@ __device__ inline void sum_range(const double *a, const double *b, const double 
     __syncthreads();
     for (int q = 0; q < 4; ++q) {
         double v = 0.0;
-        for (int k = 0; k < RB / 64; ++k) v += sh[k][q];
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v += sh[k][q];
         out[q] = v;
     }
 }
@@ -243,32 +248,47 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double (*sh)[
     }
     __syncthreads();
     a = b = c = 0.0;
-    for (int k = 0; k < RB / 64; ++k) {
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
         a += sh[k][0];
         b += sh[k][1];
         c += sh[k][2];
     }
 }
 
-// partial slots: gamma[2][T], delta[2][T], rho[2][T], rho0[T]
-__device__ inline double *P_GAM(const CgBufs &cg, int T, int slot) { return cg.part + slot * T; }
-__device__ inline double *P_DEL(const CgBufs &cg, int T, int slot) { return cg.part + (2 + slot) * T; }
-__device__ inline double *P_RHO(const CgBufs &cg, int T, int slot) { return cg.part + (4 + slot) * T; }
-__device__ inline double *P_RHO0(const CgBufs &cg, int T) { return cg.part + 6 * T; }
+__device__ inline RWSD load_rwsd(const RWSD *a, int i) {
+    const double2 *p = reinterpret_cast<const double2 *>(a + i);
+    const double2 lo = p[0], hi = p[1];
+    return RWSD{lo.x, lo.y, hi.x, hi.y};
+}
+__device__ inline void store_rwsd(RWSD *a, int i, double r, double w, double s, double d) {
+    double2 *p = reinterpret_cast<double2 *>(a + i);
+    p[0] = make_double2(r, w);
+    p[1] = make_double2(s, d);
+}
+
+// partial slots (per sub-tile, NS = SPT * T of them): gamma[2][NS], delta[2][NS],
+// rho[2][NS], rho0[NS]
+__device__ inline double *P_GAM(const CgBufs &cg, int NS, int slot) { return cg.part + slot * NS; }
+__device__ inline double *P_DEL(const CgBufs &cg, int NS, int slot) { return cg.part + (2 + slot) * NS; }
+__device__ inline double *P_RHO(const CgBufs &cg, int NS, int slot) { return cg.part + (4 + slot) * NS; }
+__device__ inline double *P_RHO0(const CgBufs &cg, int NS) { return cg.part + 6 * NS; }
 
 // r_0 = g = nu - V (0 on empty rows), u_0 = r_0 / D, w_0 = A u_0, s_{-1} = p_{-1} = x_0 = 0
-__global__ __launch_bounds__(RB) void k_cg_init(Batch bt, const double *__restrict__ V, const double *__restrict__ nu,
+template <int LANES, int SUB>
+__global__ __launch_bounds__(LANES * SUB) void k_cg_init(Batch bt, const double *__restrict__ V, const double *__restrict__ nu,
                                                  const double *__restrict__ diag, const int32_t *__restrict__ hcol,
                                                  const float *__restrict__ hval, const int32_t *__restrict__ hcnt,
                                                  CgBufs cg) {
-    __shared__ double sh[RB / 64][4];
-    const int t = blockIdx.x;
-    if (t == 0 && threadIdx.x == 0) *cg.kbase = 0;
+    constexpr int SPT = TILE / SUB;
+    __shared__ double sh[LANES * SUB / 64][4];
+    const int q = blockIdx.x;
+    const int t = q / SPT;
+    if (q == 0 && threadIdx.x == 0) *cg.kbase = 0;
     const int b = bt.tile_inst[t];
     if (bt.phase[b] != PH_ACTIVE) return;
-    const int T = bt.T;
+    const int NS = SPT * bt.T;
     const int l = threadIdx.x & (LANES - 1);
-    const int row = bt.tile_row[t] + (int)(threadIdx.x / LANES);
+    const int row = bt.tile_row[t] + (q % SPT) * SUB + (int)(threadIdx.x / LANES);
     const bool has = row < bt.off[b + 1];
     double acc = 0.0;
     if (has) {
@@ -290,9 +310,7 @@ __global__ __launch_bounds__(RB) void k_cg_init(Batch bt, const double *__restri
         const double g = d > 0.0 ? nu[row] - V[row] : 0.0;
         const double u = d > 0.0 ? (nu[row] - V[row]) / d : 0.0;
         const double w = d * u - acc;
-        cg.r[0][row] = g;
-        cg.w[0][row] = w;
-        cg.s[0][row] = 0.0;
+        store_rwsd(cg.rws[0], row, g, w, 0.0, d);
         cg.p[row] = 0.0;
         cg.x[row] = 0.0;
         gp = g * u;
@@ -301,12 +319,12 @@ __global__ __launch_bounds__(RB) void k_cg_init(Batch bt, const double *__restri
     }
     block_sum3(gp, dp, rp, sh);
     if (threadIdx.x == 0) {
-        P_GAM(cg, T, 0)[t] = gp;
-        P_DEL(cg, T, 0)[t] = dp;
-        P_RHO(cg, T, 0)[t] = rp;
-        P_RHO0(cg, T)[t] = rp;
+        P_GAM(cg, NS, 0)[q] = gp;
+        P_DEL(cg, NS, 0)[q] = dp;
+        P_RHO(cg, NS, 0)[q] = rp;
+        P_RHO0(cg, NS)[q] = rp;
     }
-    if (t == bt.first_tile[b] && threadIdx.x == 0) {
+    if (q == SPT * bt.first_tile[b] && threadIdx.x == 0) {
         int32_t *st = cg.cgst + 4 * b;
         st[0] = 0;
         st[1] = 0;
@@ -316,26 +334,61 @@ __global__ __launch_bounds__(RB) void k_cg_init(Batch bt, const double *__restri
 }
 
 // Iteration k = *kbase + m (the host advances kbase after a chunk of launches, so a
-// chunk has fixed arguments and can be replayed as a graph).
-__global__ __launch_bounds__(RB) void k_cg_iter(Batch bt, int m, double rtol2, int cap,
+// chunk has fixed arguments and can be replayed as a graph). The loads that do not
+// depend on the iteration's scalars (the row's entries, the neighbours' r, w, s, D)
+// are issued before the partial sums that give the scalars, so their latencies overlap.
+template <int LANES, int SUB>
+__global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double rtol2, int cap,
                                                  const int32_t *__restrict__ hcol, const float *__restrict__ hval,
                                                  const int32_t *__restrict__ hcnt, const double *__restrict__ diag,
                                                  CgBufs cg) {
-    __shared__ double sh[RB / 64][4];
-    const int t = blockIdx.x;
+    constexpr int SPT = TILE / SUB;
+    __shared__ double sh[LANES * SUB / 64][4];
+    const int q = blockIdx.x;
+    const int t = q / SPT;
     const int b = bt.tile_inst[t];
-    if (bt.phase[b] != PH_ACTIVE) return;
-    int32_t *st = cg.cgst + 4 * b;
-    if (st[1] != 0 || st[2] != 0) return;
+    const int row = bt.tile_row[t] + (q % SPT) * SUB + (int)(threadIdx.x / LANES);
     const int k = *cg.kbase + m;
-    if (k >= cap) return;
-    const int T = bt.T;
-    const int t0 = bt.first_tile[b], t1 = bt.first_tile[b + 1];
+    int32_t *st = cg.cgst + 4 * b;
+    const int4 st4 = *reinterpret_cast<const int4 *>(st);
+    if (bt.phase[b] != PH_ACTIVE || st4.y != 0 || st4.z != 0 || k >= cap) return;
+    const int NS = SPT * bt.T;
+    const int t0 = SPT * bt.first_tile[b], t1 = SPT * bt.first_tile[b + 1];
+    const int end = bt.off[b + 1];
     const int cur = k & 1, nxt = cur ^ 1;
+    const double2 prev = *reinterpret_cast<const double2 *>(cg.cgs + 4 * b + 2 * nxt);  // alpha, gamma of k-1
+    const RWSD *cur_rec = cg.rws[cur];
+    const int l = threadIdx.x & (LANES - 1);
+    const bool has = row < end;
+    // scalar-independent loads
+    int c = 0;
+    RWSD own{0.0, 0.0, 0.0, 0.0};
+    double pk_1 = 0.0, xk = 0.0;
+    float vv[PF];
+    RWSD nb[PF];
+    if (has) {
+        c = hcnt[row];
+        own = load_rwsd(cur_rec, row);
+        pk_1 = cg.p[row];
+        xk = cg.x[row];
+    }
+    const int32_t *cr = hcol + (int64_t)row * FCAP;
+    const float *vr = hval + (int64_t)row * FCAP;
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+        const int f = l + LANES * e;
+        vv[e] = 0.f;
+        nb[e] = RWSD{0.0, 0.0, 0.0, 0.0};
+        if (f < c) {
+            vv[e] = vr[f];
+            nb[e] = load_rwsd(cur_rec, cr[f]);
+        }
+    }
+    const double d = own.d, rk = own.r, wk = own.w, sk_1 = own.s;
     double S[4];
-    sum_range(P_GAM(cg, T, cur), P_DEL(cg, T, cur), P_RHO(cg, T, cur), P_RHO0(cg, T), t0, t1, S, sh);
+    sum_range(P_GAM(cg, NS, cur), P_DEL(cg, NS, cur), P_RHO(cg, NS, cur), P_RHO0(cg, NS), t0, t1, S, sh);
     const double gam = S[0], del = S[1], rho = S[2], rho0 = S[3];
-    const bool lead = t == t0 && threadIdx.x == 0;
+    const bool lead = q == t0 && threadIdx.x == 0;
     if (rho <= rtol2 * rho0) {
         if (lead) {
             st[2] = 1;
@@ -347,9 +400,8 @@ __global__ __launch_bounds__(RB) void k_cg_iter(Batch bt, int m, double rtol2, i
     if (k == 0) {
         alpha = gam / del;
     } else {
-        const double a_prev = cg.cgs[4 * b + 2 * nxt], g_prev = cg.cgs[4 * b + 2 * nxt + 1];
-        beta = gam / g_prev;
-        alpha = gam / (del - beta * gam / a_prev);
+        beta = gam / prev.y;
+        alpha = gam / (del - beta * gam / prev.x);
     }
     if (!(alpha > 0.0) || !(alpha < 1e300)) {  // non-positive curvature (or NaN)
         if (lead) {
@@ -363,50 +415,42 @@ __global__ __launch_bounds__(RB) void k_cg_iter(Batch bt, int m, double rtol2, i
         cg.cgs[4 * b + 2 * cur + 1] = gam;
         st[0] = k + 1;
     }
-    const double *rc = cg.r[cur], *wc = cg.w[cur], *sc = cg.s[cur];
-    const int l = threadIdx.x & (LANES - 1);
-    const int row = bt.tile_row[t] + (int)(threadIdx.x / LANES);
-    const bool has = row < bt.off[b + 1];
+    // u_{k+1} of a neighbour from its stored r_k, w_k, s_{k-1} (same arithmetic as its owner)
     double acc = 0.0;
-    if (has) {
-        const int c = hcnt[row];
-        const int32_t *cr = hcol + (int64_t)row * FCAP;
-        const float *vr = hval + (int64_t)row * FCAP;
-#pragma unroll 2
-        for (int f = l; f < c; f += LANES) {
-            const int j = cr[f];
-            const double dj = diag[j];
-            const double sj = fma(beta, sc[j], wc[j]);
-            const double uj = dj > 0.0 ? fma(-alpha, sj, rc[j]) / dj : 0.0;
-            acc += (double)vr[f] * uj;
-        }
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+        const double s1 = fma(beta, nb[e].s, nb[e].w);
+        const double uj = nb[e].d > 0.0 ? fma(-alpha, s1, nb[e].r) / nb[e].d : 0.0;
+        acc += (double)vv[e] * uj;
+    }
+    for (int f = l + LANES * PF; f < c; f += LANES) {
+        const RWSD o = load_rwsd(cur_rec, cr[f]);
+        const double s1 = fma(beta, o.s, o.w);
+        const double uj = o.d > 0.0 ? fma(-alpha, s1, o.r) / o.d : 0.0;
+        acc += (double)vr[f] * uj;
     }
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LANES);
     double gp = 0.0, dp = 0.0, rp = 0.0;
     if (has && l == 0) {
-        const double d = diag[row];
-        const double rk = rc[row];
         const double uk = d > 0.0 ? rk / d : 0.0;
-        const double pk = fma(beta, cg.p[row], uk);
-        const double sk = fma(beta, sc[row], wc[row]);
-        cg.x[row] = fma(alpha, pk, cg.x[row]);
+        const double pk = fma(beta, pk_1, uk);
+        const double sk = fma(beta, sk_1, wk);
+        cg.x[row] = fma(alpha, pk, xk);
         const double r1 = fma(-alpha, sk, rk);
         const double u1 = d > 0.0 ? r1 / d : 0.0;
         const double w1 = d * u1 - acc;
         cg.p[row] = pk;
-        cg.s[nxt][row] = sk;
-        cg.r[nxt][row] = r1;
-        cg.w[nxt][row] = w1;
+        store_rwsd(cg.rws[nxt], row, r1, w1, sk, d);
         gp = r1 * u1;
         dp = w1 * u1;
         rp = r1 * r1;
     }
     block_sum3(gp, dp, rp, sh);
     if (threadIdx.x == 0) {
-        P_GAM(cg, T, nxt)[t] = gp;
-        P_DEL(cg, T, nxt)[t] = dp;
-        P_RHO(cg, T, nxt)[t] = rp;
+        P_GAM(cg, NS, nxt)[q] = gp;
+        P_DEL(cg, NS, nxt)[q] = dp;
+        P_RHO(cg, NS, nxt)[q] = rp;
     }
 }
 
@@ -429,17 +473,18 @@ __global__ __launch_bounds__(1024) void k_cg_advance(Batch bt, int chunk, int ca
 }
 
 // End of the direction solve: ACTIVE -> TRIAL with alpha = 1, or FAILED.
-__global__ __launch_bounds__(RB) void k_cg_finish(Batch bt, double rtol2, CgBufs cg, const int32_t *__restrict__ herr,
-                                                   InstCtl *__restrict__ ctl, int32_t *__restrict__ phase) {
+__global__ __launch_bounds__(RB) void k_cg_finish(Batch bt, int SPT, double rtol2, CgBufs cg,
+                                                   const int32_t *__restrict__ herr, InstCtl *__restrict__ ctl,
+                                                   int32_t *__restrict__ phase) {
     __shared__ double sh[RB / 64][4];
     const int b = blockIdx.x;
     if (phase[b] != PH_ACTIVE) return;
     const int32_t *st = cg.cgst + 4 * b;
     const int it = st[0];
-    const int T = bt.T;
+    const int NS = SPT * bt.T;
     double S[4];
-    sum_range(P_RHO(cg, T, it & 1), P_RHO0(cg, T), P_RHO0(cg, T), P_RHO0(cg, T), bt.first_tile[b],
-              bt.first_tile[b + 1], S, sh);
+    sum_range(P_RHO(cg, NS, it & 1), P_RHO0(cg, NS), P_RHO0(cg, NS), P_RHO0(cg, NS), SPT * bt.first_tile[b],
+              SPT * bt.first_tile[b + 1], S, sh);
     if (threadIdx.x != 0) return;
     InstCtl &c = ctl[b];
     c.cg_iters += it;
@@ -489,13 +534,16 @@ __global__ __launch_bounds__(1024) void k_ctl_start(Batch bt, CtlOpts o, int fro
         if (phase[b] != from_phase) continue;
         InstCtl &c = ctl[b];
         c.evals += 1;
+        if (from_phase == PH_REPAIR) c.repaired = 1;
         if (from_phase == PH_RESTART) c.default_start = 1;
         c.sumV = ev[4 * b + 0];
         c.maxrel = ev[4 * b + 1];
         c.gnorm = ev[4 * b + 2];
         c.minV = ev[4 * b + 3];
-        if (!(c.minV > 0.0) && o.allow_restart && !c.default_start) {
-            phase[b] = PH_RESTART;
+        // an empty start cell: first raise the empty cells' weights, then restart from
+        // the default weights, then give up (eps0 would be 0)
+        if (!(c.minV > 0.0) && o.allow_restart && from_phase != PH_RESTART) {
+            phase[b] = from_phase == PH_START ? PH_REPAIR : PH_RESTART;
             continue;
         }
         c.eps0 = 0.5 * fmin(ev_nu[4 * b + 3], ev_floor[4 * b + 3]);
@@ -621,23 +669,42 @@ void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, co
                        hcnt, hval, diag);
 }
 
-void launch_cg_init(hipStream_t st, const Batch &bt, const double *V, const double *nu, const double *diag,
-                    const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg) {
-    hipLaunchKernelGGL(k_cg_init, dim3(bt.T), dim3(RB), 0, st, bt, V, nu, diag, hcol, hval, hcnt, cg);
+// shape = 4 * log2(lanes) + log2(SUB / 64): lanes in {1, 2, 4, 8}, SUB in {64, 128, 256}
+#define LAGOT_CG_SHAPES(X) X(1, 64) X(1, 128) X(1, 256) X(2, 64) X(2, 128) X(2, 256) X(4, 64) X(4, 128) X(4, 256) \
+    X(8, 64) X(8, 128)
+
+bool cg_shape_ok(int lanes, int sub) {
+#define X(L, S) if (lanes == L && sub == S) return true;
+    LAGOT_CG_SHAPES(X)
+#undef X
+    return false;
 }
 
-void launch_cg_iter(hipStream_t st, const Batch &bt, int m, double rtol2, int cap, const int32_t *hcol,
-                    const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg) {
-    hipLaunchKernelGGL(k_cg_iter, dim3(bt.T), dim3(RB), 0, st, bt, m, rtol2, cap, hcol, hval, hcnt, diag, cg);
+void launch_cg_init(hipStream_t st, const Batch &bt, int lanes, int sub, const double *V, const double *nu,
+                    const double *diag, const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg) {
+    const dim3 grid((TILE / sub) * bt.T), block(lanes * sub);
+#define X(L, S) \
+    if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_init<L, S>), grid, block, 0, st, bt, V, nu, diag, hcol, hval, hcnt, cg); return; }
+    LAGOT_CG_SHAPES(X)
+#undef X
+}
+
+void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
+                    const int32_t *hcol, const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg) {
+    const dim3 grid((TILE / sub) * bt.T), block(lanes * sub);
+#define X(L, S) \
+    if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_iter<L, S>), grid, block, 0, st, bt, m, rtol2, cap, hcol, hval, hcnt, diag, cg); return; }
+    LAGOT_CG_SHAPES(X)
+#undef X
 }
 
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg) {
     hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1024), 0, st, bt, chunk, cap, cg);
 }
 
-void launch_cg_finish(hipStream_t st, const Batch &bt, double rtol2, CgBufs cg, const int32_t *herr, InstCtl *ctl,
-                      int32_t *phase) {
-    hipLaunchKernelGGL(k_cg_finish, dim3(bt.B), dim3(RB), 0, st, bt, rtol2, cg, herr, ctl, phase);
+void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, CgBufs cg, const int32_t *herr,
+                      InstCtl *ctl, int32_t *phase) {
+    hipLaunchKernelGGL(k_cg_finish, dim3(bt.B), dim3(RB), 0, st, bt, TILE / sub, rtol2, cg, herr, ctl, phase);
 }
 
 void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase) {

@@ -2,10 +2,11 @@
 the GPU through the C-ABI (lagot_features, lagot_mlp_train_step), and the
 comparison against the previous-step warm start.
 
-A training pair is (inputs of a state, target): the state is a dam-break scene
-one advection step (dt, velocities N(0, sigma^2) per axis) after a converged solve
-psi_a; the target is (psi_b - psi_a) / s_i^2 where psi_b is the converged weight
-vector at the advected positions and s_i = nu_i^(1/3). The network's guess is only
+A training pair is (inputs of a state, target): the state is a dam-break scene one
+advection step (dt, velocities N(0, sigma^2) per axis) after a converged solve psi_a,
+taken along an advect-and-solve sequence (so that later, more disordered states are
+in the training distribution too); the target is (psi_b - psi_a) / s_i^2 where psi_b
+is the converged weight vector at the advected positions and s_i = nu_i^(1/3). The network's guess is only
 ever a start for Newton: lagot_solve accepts it when every cell keeps positive
 volume and the residual norm drops, and runs to the tolerance either way.
 """
@@ -37,28 +38,34 @@ def init_params(seed: int = 0) -> np.ndarray:
 
 
 def generate_pairs(ctx, seeds, n: int = 100_000, dt: float = 2e-3, sigma: float = 0.5, tol: float = 1e-5,
-                   log=print):
-    """Solve cold, advect once, solve warm; return device (inputs int16 [M,64], targets float32 [M])."""
+                   steps: int = 1, log=print):
+    """For each seed: solve cold, then `steps` times advect and solve warm from the previous
+    weights; every warm solve gives one pair per site. Returns device (inputs int16 [M,64],
+    targets float32 [M])."""
     import torch
     import paper_2601_05765_amd as L
     feats, targets = [], []
     opts = L.default_opts(tol=tol)
     for seed in seeds:
         sc = scenes.with_velocity(scenes.dam_break(n, seed), seed=10_000 + seed, sigma=sigma)
-        x, y, z, nu = _t(sc.x, torch.float32), _t(sc.y, torch.float32), _t(sc.z, torch.float32), _t(sc.nu,
-                                                                                                     torch.float64)
-        psi_a = _t(sc.psi0, torch.float64)
-        ctx.solve(x, y, z, nu, psi_a, opts=opts)
-        sc1 = scenes.advect(sc, dt)
-        x1, y1, z1 = _t(sc1.x, torch.float32), _t(sc1.y, torch.float32), _t(sc1.z, torch.float32)
-        psi_b = psi_a.clone()
-        st = ctx.solve(x1, y1, z1, nu, psi_b, opts=opts)
-        _, f = ctx.features(x1, y1, z1, psi_a, nu, want_nbr=False)
+        nu = _t(sc.nu, torch.float64)
         s2 = np.cbrt(sc.nu) ** 2
-        tgt = (psi_b.cpu().numpy() - psi_a.cpu().numpy()) / s2
-        feats.append(f)
-        targets.append(_t(tgt, torch.float32))
-        log(f"pairs seed {seed}: warm solve {st.newton_iters} iterations, target rms {np.sqrt(np.mean(tgt ** 2)):.3e}")
+        psi = _t(sc.psi0, torch.float64)
+        ctx.solve(_t(sc.x, torch.float32), _t(sc.y, torch.float32), _t(sc.z, torch.float32), nu, psi, opts=opts)
+        cur = sc
+        for k in range(steps):
+            cur = scenes.advect(cur, dt)
+            x1, y1, z1 = _t(cur.x, torch.float32), _t(cur.y, torch.float32), _t(cur.z, torch.float32)
+            psi_a = psi.clone()
+            st = ctx.solve(x1, y1, z1, nu, psi, opts=opts, check=False)
+            if st.status != 0:
+                break
+            _, f = ctx.features(x1, y1, z1, psi_a, nu, want_nbr=False)
+            tgt = (psi.cpu().numpy() - psi_a.cpu().numpy()) / s2
+            feats.append(f)
+            targets.append(_t(tgt, torch.float32))
+            log(f"pairs seed {seed} step {k + 1}: warm solve {st.newton_iters} iterations, "
+                f"target rms {np.sqrt(np.mean(tgt ** 2)):.3e}")
     return torch.cat(feats), torch.cat(targets)
 
 
@@ -87,7 +94,8 @@ def train(ctx, feats, targets, epochs: int = 6, batch: int = 4096, lr: float = 1
 
 def sequence(ctx, sc, steps: int, dt: float = 2e-3, use_learned: bool = False, tol: float = 1e-5, psi_start=None,
              log=print):
-    """Advect-and-solve sequence from converged weights; per-step solve statistics."""
+    """Advect-and-solve sequence from converged weights; per-step solve statistics (a failed
+    solve is recorded and the sequence goes on from its last accepted weights)."""
     import torch
     import paper_2601_05765_amd as L
     nu = _t(sc.nu, torch.float64)
@@ -99,11 +107,11 @@ def sequence(ctx, sc, steps: int, dt: float = 2e-3, use_learned: bool = False, t
         x, y, z = _t(cur.x, torch.float32), _t(cur.y, torch.float32), _t(cur.z, torch.float32)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=tol, use_learned=int(use_learned)))
+        st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=tol, use_learned=int(use_learned)), check=False)
         torch.cuda.synchronize()
         ms = 1000 * (time.perf_counter() - t0)
-        out.append({"step": k + 1, "ms": ms, "newton_iters": st.newton_iters, "evals": st.evals,
-                    "cg_iters": st.cg_iters, "learned_accepted": st.learned_accepted,
+        out.append({"step": k + 1, "ms": ms, "status": st.status, "newton_iters": st.newton_iters,
+                    "evals": st.evals, "cg_iters": st.cg_iters, "learned_accepted": st.learned_accepted,
                     "max_rel_err": st.max_rel_err})
         log(f"step {k + 1}: {'learned' if use_learned else 'plain'} {ms:.1f} ms, {st.newton_iters} it, "
             f"accepted={st.learned_accepted}")

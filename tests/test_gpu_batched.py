@@ -107,10 +107,10 @@ def test_batch_statuses_are_independent(ctx):
     assert [s.status for s in sts] == [0, 0, L.EEMPTY, 0]
     # the failed instance keeps its start weights
     assert np.array_equal(psi.cpu().numpy()[offs[2]:offs[3]], psis[2])
-    # with the fallback it restarts from the default weights and converges
+    # with the fallback its empty cell gets the default weight and it converges
     offs, x, y, z, nu, psi = _concat(insts, psis)
     sts = ctx.solve_batched(offs, x, y, z, nu, psi)
-    assert all(s.status == 0 for s in sts) and sts[2].default_start == 1 and sts[0].default_start == 0
+    assert all(s.status == 0 for s in sts) and sts[2].repaired_start == 1 and sts[0].repaired_start == 0
 
 
 def test_batch_rejects_invalid_instance(ctx):

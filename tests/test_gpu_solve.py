@@ -64,6 +64,35 @@ def test_solve_threads_per_cell(ctx, oracle_mod, tpc):
     assert _oracle_err(oracle_mod, sc, psi.cpu().numpy()) <= 1e-5
 
 
+@pytest.mark.parametrize("shape", [(1, 64), (1, 256), (2, 128), (4, 64), (4, 256), (8, 128)])
+def test_solve_cg_shapes(ctx, oracle_mod, shape):
+    _say(f"case: solve slab_uniform 1k seed 2, PCG block shape {shape}")
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 2)
+    x, y, z, nu, psi = _dev(sc)
+    ctx.set_cg_shape(*shape)
+    try:
+        st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    finally:
+        ctx.set_cg_shape(4, 64)
+    assert st.status == 0
+    assert _oracle_err(oracle_mod, sc, psi.cpu().numpy()) <= 1e-5
+
+
+def test_autotuned_solves(oracle_mod):
+    _say("case: autotuned solves (lanes per cell and PCG shape timed on the first call)")
+    import paper_2601_05765_amd as L
+    c2 = L.Context()
+    sc = scenes.slab_uniform(1000, 7)
+    for _ in range(2):
+        x, y, z, nu, psi = _dev(sc)
+        st = c2.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5, autotune=1))
+        assert st.status == 0
+        assert _oracle_err(oracle_mod, sc, psi.cpu().numpy()) <= 1e-5
+    with pytest.raises(L.LagotError):
+        c2.set_cg_shape(3, 64)
+
+
 def test_solve_dam_break_100k(ctx, oracle_mod):
     _say("case: solve dam_break 100k, sampled oracle check")
     import paper_2601_05765_amd as L
@@ -144,7 +173,13 @@ def test_error_codes(ctx):
     x, y, z, nu, psi = _dev(sc)
     psi[5] = -1.0
     st = ctx.solve(x, y, z, nu, psi, check=False)
-    assert st.status == 0 and st.default_start == 1
+    # the empty cell gets the default weight, the other start weights are kept
+    assert st.status == 0 and st.repaired_start == 1 and st.default_start == 0
+    # a cell swallowed by a heavy neighbour stays empty after the repair: full default start
+    x, y, z, nu, psi = _dev(sc)
+    psi[11] = 400.0 * float(psi[11])
+    st = ctx.solve(x, y, z, nu, psi, check=False)
+    assert st.status == 0 and st.repaired_start == 1 and st.default_start == 1
     # iteration limit -> ENOCONV, psi holds an accepted iterate
     x, y, z, nu, psi = _dev(sc)
     st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(max_newton=1), check=False)
