@@ -72,7 +72,12 @@ typedef struct {
                             lanes per cell, and the PCG kernels with four block shapes, on the
                             first solve of each size and density class, and keep the fastest in
                             the context (default 0: the context's defaults)                    */
-    int reserved[2];
+    int use_graph;       /* 1: capture the launch sequences of a Newton iteration (Hessian + PCG set-up,
+                            a chunk of PCG iterations, one step-size trial) as HIP graphs once per
+                            call and replay them; the call then runs on a private stream of the
+                            context, ordered after earlier work on the context's stream. Results
+                            are identical to eager launches (default 0)                         */
+    int reserved[1];
 } lagot_opts;
 
 typedef struct {

@@ -122,6 +122,13 @@ struct lagot_ctx {
     float *tZ1 = nullptr, *tZ2 = nullptr, *tZ3 = nullptr, *tdZ = nullptr, *ty = nullptr, *tt = nullptr,
           *tdy = nullptr, *tpart = nullptr, *tloss = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the float32 cell kernel
+    // graph mode: a private stream (default priority) and the graphs of the current call
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr;
+    hipGraphExec_t g_dir = nullptr, g_trial = nullptr;
+    std::map<int, hipGraphExec_t> g_cg;  // by chunk length
+    bool graph_events = true;            // event records can be captured (timing inside graphs)
+    bool capturing = false;
     bool ev_pending = false;
     double ms_cell = 0.0;
     int cell_launches = 0;
@@ -195,6 +202,8 @@ void free_all(lagot_ctx *c) {
     free_ptrs(c->mlp_p, c->mlp_g, c->mlp_m1, c->mlp_m2, c->mlp_pb, c->nbr_s, c->feat_s, c->inf_a, c->inf_b,
               c->mlp_out, c->tX, c->tH1, c->tH2, c->tH3, c->tdZb, c->tZ1, c->tZ2, c->tZ3, c->tdZ, c->ty, c->tt,
               c->tdy, c->tpart, c->tloss);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
@@ -480,12 +489,13 @@ EvalOut eval_out(lagot_ctx *c, bool walls) {
 void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double *ev_out) {
     const Batch bt = batch(c);
     const EvalOut o = eval_out(c, walls);
+    const bool timed = !c->capturing || c->graph_events;
     launch_eval_begin(c->stream, bt, want, o);
     if (walls) (void)hipMemsetAsync(c->wall, 0, 6 * sizeof(float) * (size_t)c->n, c->stream);
-    (void)hipEventRecord(c->ev0, c->stream);
+    if (timed) (void)hipEventRecord(c->ev0, c->stream);
     launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, c->tpc);
-    (void)hipEventRecord(c->ev1, c->stream);
-    c->ev_pending = true;
+    if (timed) (void)hipEventRecord(c->ev1, c->stream);
+    if (!c->capturing) c->ev_pending = true;
     launch_cells_fallback(c->stream, bt, c->pos_s, psi_eval, c->perm, c->cell_start, o);
     if (ev_out) launch_eval_reduce(c->stream, bt, want, c->V, c->nu_s, c->part_ev, ev_out);
 }
@@ -642,21 +652,65 @@ int autotune_tpc(lagot_ctx *c) {
     return LAGOT_OK;
 }
 
+// ---- graph mode ---------------------------------------------------------------
+void drop_graphs(lagot_ctx *c) {
+    if (c->g_dir) (void)hipGraphExecDestroy(c->g_dir);
+    if (c->g_trial) (void)hipGraphExecDestroy(c->g_trial);
+    for (auto &kv : c->g_cg) (void)hipGraphExecDestroy(kv.second);
+    c->g_dir = c->g_trial = nullptr;
+    c->g_cg.clear();
+}
+
+// Capture what `enqueue` launches on the context stream into an executable graph.
+template <typename F> int capture(lagot_ctx *c, F &&enqueue, hipGraphExec_t *out) {
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    enqueue();
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || !g) {
+        fprintf(stderr, "lagot: graph capture failed: %s\n", hipGetErrorString(e));
+        return LAGOT_EHIP;
+    }
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        fprintf(stderr, "lagot: graph instantiation failed: %s\n", hipGetErrorString(e2));
+        return LAGOT_EHIP;
+    }
+    return LAGOT_OK;
+}
+
 // Jacobi-PCG for every ACTIVE instance with the context's block shape: chunks of
 // launches, then the count of instances still iterating is read back.
-int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched) {
+int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, bool graph) {
     const Batch bt = batch(c);
     const CgBufs cg = cg_bufs(c);
     hipStream_t st = c->stream;
-    launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt, cg);
+    if (with_init)
+        launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt, cg);
     const double rtol2 = o.cg_rtol * o.cg_rtol;
     const int cap = o.cg_max_iter;
     int k = 0;
     while (k < cap) {
         const int m = std::min(c->cg_chunk, cap - k);
-        for (int q = 0; q < m; ++q)
-            launch_cg_iter(st, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hcol, c->hval, c->hcnt, c->diag, cg);
-        launch_cg_advance(st, bt, m, cap, cg);
+        auto chunk = [&]() {
+            for (int q = 0; q < m; ++q)
+                launch_cg_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hcol, c->hval, c->hcnt,
+                               c->diag, cg);
+            launch_cg_advance(c->stream, bt, m, cap, cg);
+        };
+        if (graph) {
+            hipGraphExec_t &ex = c->g_cg[m];
+            if (!ex) {
+                int rc = capture(c, chunk, &ex);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(ex, st));
+        } else {
+            chunk();
+        }
         k += m;
         HIP_TRY(hipMemcpyAsync(c->h_cnt + 8, c->misc + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         int rc = sync(c);
@@ -670,14 +724,34 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched) {
 // One Jacobi-PCG direction solve for every ACTIVE instance, then ACTIVE -> TRIAL.
 // When the autotuner asks for it, the solve is first run with each candidate block
 // shape (the same system each time) and the fastest shape is kept for the class.
-int newton_direction(lagot_ctx *c, const lagot_opts &o) {
+int newton_direction(lagot_ctx *c, const lagot_opts &o, bool graph) {
     const Batch bt = batch(c);
     hipStream_t st = c->stream;
-    launch_hess_assemble(st, c->n, bt, PH_ACTIVE, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval, c->xcnt,
-                         c->herr);
-    launch_hess_finish(st, c->n, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hval, c->diag);
+    auto assemble = [&](bool with_init) {
+        launch_hess_assemble(c->stream, c->n, bt, PH_ACTIVE, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval,
+                             c->xcnt, c->herr);
+        launch_hess_finish(c->stream, c->n, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hcol,
+                           c->hval, c->diag);
+        if (with_init)
+            launch_cg_init(c->stream, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt,
+                           cg_bufs(c));
+    };
     int k = 0, rc;
-    if (c->tune_key >= 0) {
+    if (c->tune_key < 0) {
+        // Hessian, PCG set-up, PCG chunks
+        if (graph) {
+            if (!c->g_dir) {
+                rc = capture(c, [&]() { assemble(true); }, &c->g_dir);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(c->g_dir, st));
+        } else {
+            assemble(true);
+        }
+        rc = run_cg(c, o, &k, false, graph);
+        if (rc) return rc;
+    } else {
+        assemble(false);
         static const int shapes[4][2] = {{2, 128}, {4, 128}, {2, 64}, {4, 64}};
         double best = 1e300;
         int bl = c->cg_lanes, bs = c->cg_sub;
@@ -687,7 +761,7 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o) {
             rc = sync(c);
             if (rc) return rc;
             const double t0 = now_ms();
-            rc = run_cg(c, o, &k);
+            rc = run_cg(c, o, &k, true, false);
             if (rc) return rc;
             const double ms = now_ms() - t0;
             if (ms < best) {
@@ -704,12 +778,9 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o) {
         c->cg_lanes = bl;
         c->cg_sub = bs;
         if (!(bl == shapes[3][0] && bs == shapes[3][1])) {
-            rc = run_cg(c, o, &k);  // the direction of the kept shape
+            rc = run_cg(c, o, &k, true, false);  // the direction of the kept shape
             if (rc) return rc;
         }
-    } else {
-        rc = run_cg(c, o, &k);
-        if (rc) return rc;
     }
     // chunk length for the next direction: about this solve's iteration count
     c->cg_chunk = std::min(64, std::max(8, (k + 3) / 4 * 4));
@@ -770,15 +841,10 @@ int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
 
 // Damped Newton (Algorithm 1, KMT step control) for every instance of the call;
 // single = true takes at most one Newton iteration per instance.
-int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const float *y, const float *z,
-               const double *nu, const lagot_box *boxes, double *psi, const lagot_opts *opts_in,
-               lagot_stats *stats, bool single) {
-    const double t0 = now_ms();
-    lagot_opts o;
-    if (opts_in)
-        o = *opts_in;
-    else
-        fill_defaults(&o);
+int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, const float *y, const float *z,
+                    const double *nu, const lagot_box *boxes, double *psi, const lagot_opts &o, lagot_stats *stats,
+                    bool single, double t0) {
+    const bool graph = o.use_graph != 0;
     std::vector<int> bad(std::max(B, 1), 0);
     auto fail_all = [&](int rc) {
         if (stats)
@@ -848,17 +914,34 @@ int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const f
     int round = 0;
     while (c->h_cnt[PH_ACTIVE] > 0) {
         const double tl = now_ms();
-        rc = newton_direction(c, o);
+        rc = newton_direction(c, o, graph);
         if (rc) return fail_all(rc);
         tm.lin += now_ms() - tl;
         te = now_ms();
-        for (int h = 0; h <= o.max_halvings; ++h) {
-            launch_axpy_trial(st, bt, c->ctl, c->psi_s, cg_bufs(c).x, c->psi_trial, c->pos_s);
-            launch_rmax(st, bt, PH_TRIAL, c->psi_trial, c->rmax);
+        // one step-size trial of every instance in the search (Alg. 1, KMT test on the device)
+        auto trial = [&]() {
+            launch_axpy_trial(c->stream, bt, c->ctl, c->psi_s, cg_bufs(c).x, c->psi_trial, c->pos_s);
+            launch_rmax(c->stream, bt, PH_TRIAL, c->psi_trial, c->rmax);
             evaluate(c, PH_TRIAL, c->psi_trial, false, c->ev);
-            launch_ctl_decide(st, bt, co, c->ev, c->fail_inst, c->ctl, c->phase);
-            launch_accept_rows(st, bt, c->ctl, c->psi_s, c->psi_trial, c->pos_s);
-            launch_ctl_commit(st, bt, co, c->ctl, c->phase, c->counts);
+            launch_ctl_decide(c->stream, bt, co, c->ev, c->fail_inst, c->ctl, c->phase);
+            launch_accept_rows(c->stream, bt, c->ctl, c->psi_s, c->psi_trial, c->pos_s);
+            launch_ctl_commit(c->stream, bt, co, c->ctl, c->phase, c->counts);
+        };
+        for (int h = 0; h <= o.max_halvings; ++h) {
+            if (graph) {
+                if (!c->g_trial) {
+                    rc = capture(c, trial, &c->g_trial);
+                    if (rc && c->graph_events) {  // no event nodes on this runtime: capture untimed
+                        c->graph_events = false;
+                        rc = capture(c, trial, &c->g_trial);
+                    }
+                    if (rc) return fail_all(rc);
+                }
+                if (hipGraphLaunch(c->g_trial, st) != hipSuccess) return fail_all(LAGOT_EHIP);
+                c->ev_pending = c->graph_events;
+            } else {
+                trial();
+            }
             rc = read_counts(c);
             if (rc) return fail_all(rc);
             if (c->h_cnt[PH_TRIAL] == 0) break;
@@ -906,6 +989,33 @@ int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const f
         S.ms_learned = tm.learned;
     }
     return first;
+}
+
+int newton_run(lagot_ctx *c, int B, const int64_t *offs, const float *x, const float *y, const float *z,
+               const double *nu, const lagot_box *boxes, double *psi, const lagot_opts *opts_in,
+               lagot_stats *stats, bool single) {
+    const double t0 = now_ms();
+    lagot_opts o;
+    if (opts_in)
+        o = *opts_in;
+    else
+        fill_defaults(&o);
+    if (!o.use_graph) return newton_run_impl(c, B, offs, x, y, z, nu, boxes, psi, o, stats, single, t0);
+    // graph mode: the call runs on the context's private stream (a legacy default stream
+    // cannot be captured), after everything already enqueued on the context's stream
+    if (!c->gstream) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(c->ev_in, c->stream));
+    HIP_TRY(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+    hipStream_t user = c->stream;
+    c->stream = c->gstream;
+    const int rc = newton_run_impl(c, B, offs, x, y, z, nu, boxes, psi, o, stats, single, t0);
+    (void)hipStreamSynchronize(c->gstream);
+    c->stream = user;
+    drop_graphs(c);
+    return rc;
 }
 
 int single_instance(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *nu,

@@ -191,7 +191,8 @@ void launch_hess_assemble(hipStream_t st, int64_t n, const Batch &bt, int want, 
                           const int32_t *fcol, const float *farea, const int32_t *fcnt, int32_t *hcol, float *hval,
                           int32_t *xcnt, int32_t *herr);
 void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, const double *psi_s, const double *K,
-                        const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag);
+                        const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, int32_t *hcol, float *hval,
+                        double *diag);
 // CG block shape: `lanes` lanes per row (1, 2, 4 or 8), `sub` rows per block (64, 128
 // or 256; 8 lanes with at most 128 rows)
 bool cg_shape_ok(int lanes, int sub);

@@ -173,14 +173,32 @@ __global__ void k_hess_assemble(int64_t n, Batch bt, int want, const float4 *__r
     }
 }
 
+// Row length, diagonal; the entries appended by the union pattern arrive in atomic
+// order and are sorted by column here, so every later sum over the row is in a fixed
+// order (deterministic results).
 __global__ void k_hess_finish(int64_t n, Batch bt, int want, const double *__restrict__ psi,
                               const double *__restrict__ K, const int32_t *__restrict__ fcnt,
                               const int32_t *__restrict__ xcnt, int32_t *__restrict__ hcnt,
-                              const float *__restrict__ hval, double *__restrict__ diag) {
+                              int32_t *__restrict__ hcol, float *__restrict__ hval, double *__restrict__ diag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !selected(bt, want, bt.inst[i])) return;
-    const int c = min(fcnt[i] + xcnt[i], FCAP);
+    const int f0 = fcnt[i];
+    const int c = min(f0 + xcnt[i], FCAP);
     hcnt[i] = c;
+    int32_t *cr = hcol + i * FCAP;
+    float *vr = hval + i * FCAP;
+    for (int a = f0 + 1; a < c; ++a) {
+        const int32_t key = cr[a];
+        const float v = vr[a];
+        int b = a - 1;
+        while (b >= f0 && cr[b] > key) {
+            cr[b + 1] = cr[b];
+            vr[b + 1] = vr[b];
+            --b;
+        }
+        cr[b + 1] = key;
+        vr[b + 1] = v;
+    }
     double s = 0.0;
     for (int f = 0; f < c; ++f) s += (double)hval[i * FCAP + f];
     const double p = psi[i];
@@ -664,9 +682,10 @@ void launch_hess_assemble(hipStream_t st, int64_t n, const Batch &bt, int want, 
 }
 
 void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, const double *psi_s, const double *K,
-                        const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, const float *hval, double *diag) {
+                        const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, int32_t *hcol, float *hval,
+                        double *diag) {
     hipLaunchKernelGGL(k_hess_finish, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, psi_s, K, fcnt, xcnt,
-                       hcnt, hval, diag);
+                       hcnt, hcol, hval, diag);
 }
 
 // shape = 4 * log2(lanes) + log2(SUB / 64): lanes in {1, 2, 4, 8}, SUB in {64, 128, 256}
