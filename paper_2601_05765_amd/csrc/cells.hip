@@ -171,9 +171,12 @@ template <typename R, int CMAX, int PMAX, int VMAX> struct CellSmem {
             } x;
         } c;
         struct {            // integration
+            // rec and eslot are contiguous: once the successors are known, eslot holds the
+            // list of fan pieces, and then both hold the pieces' (area, solid angle)
             VRec<R> rec[VMAX];
-            uint32_t succ[VMAX];         // successor slot on each of the vertex's three faces
             uint8_t eslot[PMAX][PMAX];   // directed edge a->b -> slot of the vertex holding it
+            uint32_t succ[VMAX];         // successor slot on each of the vertex's three faces
+            uint32_t trs[VMAX];          // the vertex's three planes (packed)
             uint32_t fstart[PMAX];
             R farea[PMAX];
         } g;
@@ -235,24 +238,39 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
         const int nyc = hi3[1] - lo3[1] + 1;
         const int ncol = (hi3[0] - lo3[0] + 1) * nyc;
-        // columns of grid cells (z-runs are contiguous in grid order), G at a time
+        // columns of grid cells (z-runs are contiguous in grid order), G columns at a time;
+        // the sites of those columns are numbered consecutively (prefix sum over the lanes)
+        // and taken G at a time, each lane finding its column by a binary search
+        const int gbase = (int)(threadIdx.x & (64 - G));
         for (int c0 = 0; c0 < ncol; c0 += G) {
-            int cbeg = 0, cend = 0;
+            int cbeg = 0, cnt = 0;
             if (c0 + gl < ncol) {
                 const int ix = lo3[0] + (c0 + gl) / nyc, iy = lo3[1] + (c0 + gl) % nyc;
                 const int col = gd.base + (ix * gd.dim[1] + iy) * gd.dim[2];
                 cbeg = A.cell_start[col + lo3[2]];
-                cend = A.cell_start[col + hi3[2] + 1];
+                cnt = A.cell_start[col + hi3[2] + 1] - cbeg;
             }
-            const int cn = min(G, ncol - c0);
-            for (int cc = 0; cc < cn; ++cc) {
-                const int beg = __shfl(cbeg, (int)(threadIdx.x & (64 - G)) + cc, 64);
-                const int end = __shfl(cend, (int)(threadIdx.x & (64 - G)) + cc, 64);
-                for (int base = beg; base < end; base += G) {
-                    const int j = base + gl;
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) {
+                const int v = __shfl_up(incl, o, G);
+                if (gl >= o) incl += v;
+            }
+            const int excl = incl - cnt;
+            const int total = __shfl(incl, gbase + G - 1, 64);
+            for (int b0 = 0; b0 < total; b0 += G) {
+                const int idx = b0 + gl;
+                int cidx = 0;  // number of columns whose sites all come before idx
+#pragma unroll
+                for (int step = G / 2; step >= 1; step >>= 1) {
+                    const int v = __shfl(incl, gbase + cidx + step - 1, 64);
+                    if (v <= idx) cidx += step;
+                }
+                const int j = __shfl(cbeg, gbase + cidx, 64) + (idx - __shfl(excl, gbase + cidx, 64));
+                {
                     bool keep = false, kill = false, neg = false;
                     R nx = 0, ny = 0, nz = 0, t = 0;
-                    if (j < end && j != cell) {
+                    if (idx < total && j != cell) {
                         const float4 q4 = A.pos_s[j];
                         // the weight difference is formed from the float64 weights: for close
                         // sites t ~ (psi_i - psi_j) / 2d amplifies any rounding of the weights
@@ -296,13 +314,15 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
         // box walls -x,+x,-y,+y,-z,+z: t = distance from p_i to the wall
         {
-            const BoxF box = A.bt.box[inst];
+            // lane gl < 6 reads its own bound (lo[0..2], hi[0..2]) straight from the box array
+            const float *bnd = &A.bt.box[inst].lo[0];
             bool keep = false;
             R t = 0;
             if (gl < 6) {
                 const int ax = gl >> 1;
                 const R pc = ax == 0 ? px : (ax == 1 ? py : pz);
-                t = (gl & 1) ? (R)box.hi[ax] - pc : pc - (R)box.lo[ax];
+                const R w = (R)bnd[(gl & 1) * 3 + ax];
+                t = (gl & 1) ? w - pc : pc - w;
                 keep = t < r;
             }
             const unsigned long long b = gballot<G>(keep);
@@ -529,6 +549,12 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     }
 
     // ---------------- restriction to the ball and integration ----------------
+    // Every (vertex, facet through it) pair is one fan piece: the edge from the vertex to
+    // its counter-clockwise successor on that facet. The pieces are listed, spread over
+    // all lanes of the cell, and summed per facet in the facet's walk order (fixed order:
+    // deterministic).
+    static_assert(sizeof(GT.rec) + sizeof(GT.eslot) >= sizeof(R) * 6 * VMAX, "piece storage");
+    static_assert(sizeof(GT.eslot) >= sizeof(uint16_t) * 3 * VMAX, "piece list storage");
     __syncthreads();
     if (live) {
         for (int p = gl; p < np; p += G) GT.fstart[p] = 0xFFu;
@@ -542,6 +568,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             const int s = k * G + gl;
             const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
             GT.rec[s] = VRec<R>{vx[k], vy[k], vz[k], u};
+            GT.trs[s] = u;
             GT.eslot[a][b] = (uint8_t)s;
             GT.eslot[b][c] = (uint8_t)s;
             GT.eslot[c][a] = (uint8_t)s;
@@ -552,66 +579,113 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     }
     __syncthreads();
     // successor of vertex (a,b,c) counter-clockwise on face a is the vertex holding edge a->c
+    uint32_t sc_k[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        sc_k[k] = 0xFFFFFFFFu;
+        const uint32_t u = tri[k];
+        if (live && u != TRI_INVALID) {
+            const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
+            sc_k[k] = (uint32_t)GT.eslot[a][c] | ((uint32_t)GT.eslot[b][a] << 8) | ((uint32_t)GT.eslot[c][b] << 16);
+        }
+    }
+    __syncthreads();  // eslot is dead from here on: it takes the piece list
+    uint16_t *plist = reinterpret_cast<uint16_t *>(&GT.eslot[0][0]);
+    int npc = 0;
     if (live) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const uint32_t u = tri[k];
-            if (u == TRI_INVALID) continue;
-            const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-            GT.succ[k * G + gl] = (uint32_t)GT.eslot[a][c] | ((uint32_t)GT.eslot[b][a] << 8) |
-                                     ((uint32_t)GT.eslot[c][b] << 16);
+            const int s = k * G + gl;
+            if (u != TRI_INVALID) GT.succ[s] = sc_k[k];
+#pragma unroll
+            for (int rot = 0; rot < 3; ++rot) {
+                const bool want = u != TRI_INVALID && (int)((u >> (8 * rot)) & 0xFFu) >= 6;
+                const unsigned long long bm = gballot<G>(want);
+                if (want) plist[npc + popc(bm & below)] = (uint16_t)(3 * s + rot);
+                npc += popc(bm);
+            }
         }
     }
     __syncthreads();
-    double sum_tA = 0.0, sum_om = 0.0;
+    // the pieces, G at a time
+    constexpr int MAXR = 3 * NS;
+    R pa[MAXR], po[MAXR];
+    int pc[MAXR];
     bool walk_bad = false;
-    if (live) {
-        const R cone_den = R(1) / r;
-        for (int p = gl; p < np; p += G) {
-            R Af = 0, Of = 0;
-            const uint32_t s0 = GT.fstart[p];
-            if (p >= 6 && s0 < (uint32_t)VMAX) {
-                const R nx = S.pl[p][0], ny = S.pl[p][1], nz = S.pl[p][2], t = S.pl[p][3];
+    const R cone_den = live ? R(1) / r : R(0);
+#pragma unroll
+    for (int rr = 0; rr < MAXR; ++rr) {
+        pa[rr] = po[rr] = R(0);
+        pc[rr] = -1;
+        const int idx = rr * G + gl;
+        if (live && idx < npc) {
+            const int code = plist[idx];
+            pc[rr] = code;
+            const int sv = code / 3, rot = code - 3 * sv;
+            const uint32_t u = GT.trs[sv];
+            const int f = (int)((u >> (8 * rot)) & 0xFFu);
+            const uint32_t sn = (GT.succ[sv] >> (8 * rot)) & 0xFFu;
+            if (sn >= (uint32_t)VMAX) {
+                walk_bad = true;
+            } else {
+                const R nx = S.pl[f][0], ny = S.pl[f][1], nz = S.pl[f][2], t = S.pl[f][3];
                 const R h = fabs(t);
                 const R rho2 = (r - t) * (r + t);
                 const R cone = R(1) - h * cone_den;
                 const R qx = t * nx, qy = t * ny, qz = t * nz;
-                VRec<R> rc = GT.rec[s0];
-                uint32_t sc = GT.succ[s0];
-                R ux = rc.x - qx, uy = rc.y - qy, uz = rc.z - qz;
-                uint32_t s = s0;
+                const VRec<R> P = GT.rec[sv], Q = GT.rec[sn];
+                fan_piece<R>(P.x - qx, P.y - qy, P.z - qz, Q.x - qx, Q.y - qy, Q.z - qz, nx, ny, nz, rho2, h, cone,
+                             pa[rr], po[rr]);
+            }
+        }
+    }
+    __syncthreads();  // rec and the list are dead: they take the pieces
+    R(*pieces)[2] = reinterpret_cast<R(*)[2]>(&GT.rec[0]);
+#pragma unroll
+    for (int rr = 0; rr < MAXR; ++rr) {
+        if (pc[rr] >= 0) {
+            pieces[pc[rr]][0] = pa[rr];
+            pieces[pc[rr]][1] = po[rr];
+        }
+    }
+    __syncthreads();
+    // per facet: sum its pieces in walk order from its lowest slot
+    double sum_tA = 0.0, sum_om = 0.0;
+    if (live) {
+        for (int p = gl; p < np; p += G) {
+            R Af = 0, Of = 0;
+            const uint32_t s0 = GT.fstart[p];
+            if (p >= 6 && s0 < (uint32_t)VMAX) {
+                uint32_t sv = s0;
                 int steps = 0;
                 do {
-                    const uint32_t u = rc.t;
-                    const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-                    const int rot = (a == p) ? 0 : ((b == p) ? 1 : ((c == p) ? 2 : -1));
+                    const uint32_t u = GT.trs[sv];
+                    const int rot = ((int)(u & 0xFFu) == p) ? 0
+                                  : (((int)((u >> 8) & 0xFFu) == p) ? 1 : (((int)((u >> 16) & 0xFFu) == p) ? 2 : -1));
                     if (rot < 0) {
                         walk_bad = true;
                         break;
                     }
-                    const uint32_t sn = (sc >> (8 * rot)) & 0xFF;
+                    Af += pieces[3 * sv + rot][0];
+                    Of += pieces[3 * sv + rot][1];
+                    const uint32_t sn = (GT.succ[sv] >> (8 * rot)) & 0xFFu;
                     if (sn >= (uint32_t)VMAX || ++steps > VMAX) {
                         walk_bad = true;
                         break;
                     }
-                    rc = GT.rec[sn];
-                    sc = GT.succ[sn];
-                    const R vx2 = rc.x - qx, vy2 = rc.y - qy, vz2 = rc.z - qz;
-                    fan_piece<R>(ux, uy, uz, vx2, vy2, vz2, nx, ny, nz, rho2, h, cone, Af, Of);
-                    ux = vx2;
-                    uy = vy2;
-                    uz = vz2;
-                    s = sn;
-                } while (s != s0);
+                    sv = sn;
+                } while (sv != s0);
+                const R t = S.pl[p][3];
                 sum_tA += (double)t * (double)Af;
                 sum_om += (t >= R(0)) ? (double)Of : -(double)Of;
             }
             GT.farea[p] = Af;
         }
-        if (gballot<G>(walk_bad)) {
-            flags |= CF_WALK;
-            live = false;
-        }
+    }
+    if (gballot<G>(walk_bad)) {
+        flags |= CF_WALK;
+        live = false;
     }
     sum_tA = gsum<G>(sum_tA);
     sum_om = gsum<G>(sum_om);
