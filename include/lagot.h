@@ -62,7 +62,8 @@ typedef struct {
     int cg_max_iter;     /* PCG iteration limit                                    (default 1000)  */
     int threads_per_cell;/* lanes per cell in the cell kernel: 0 = the context's default, else 8, 16,
                             32 or 64                                                             */
-    int verbose;         /* 1: print one line per Newton iteration to stderr                        */
+    int verbose;         /* 1: one line per Newton iteration to stderr; 2: also the first instance's
+                            step length, residuals, fallback count and r_max                     */
     int use_learned;     /* 1: try the learned warm start (lagot_mlp_set_params) before Newton       */
     int empty_start_fallback; /* 1 (default): if a start cell is empty (KMT needs eps0 > 0), give
                             the empty cells the default weight psi_i = (1.2 (3 nu_i / 4 pi)^(1/3))^2

@@ -948,9 +948,24 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
         }
         tm.eval += now_ms() - te;
         ++round;
-        if (o.verbose)
-            fprintf(stderr, "lagot newton round %d: active %d done %d failed %d\n", round, c->h_cnt[PH_ACTIVE],
-                    c->h_cnt[PH_DONE], c->h_cnt[PH_FAILED]);
+        if (o.verbose) {
+            fprintf(stderr, "lagot newton round %d: active %d done %d failed %d (linear %.1f ms, eval %.1f ms)\n",
+                    round, c->h_cnt[PH_ACTIVE], c->h_cnt[PH_DONE], c->h_cnt[PH_FAILED], tm.lin, tm.eval);
+            if (o.verbose > 1) {  // state of the first instance
+                InstCtl q;
+                int32_t fb = 0;
+                double rm = 0.0;
+                HIP_TRY(hipMemcpyAsync(&q, c->ctl, sizeof(q), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&fb, c->fb_inst, sizeof(fb), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&rm, c->rmax, sizeof(rm), hipMemcpyDeviceToHost, st));
+                rc = sync(c);
+                if (rc) return fail_all(rc);
+                fprintf(stderr,
+                        "  inst 0: alpha %.3g |g| %.3e maxrel %.3e minV %.3e evals %d halvings %d cg %d "
+                        "fallback %d r_max %.4g cell kernel %.1f ms\n",
+                        q.alpha, q.gnorm, q.maxrel, q.minV, q.evals, q.halvings, q.cg_iters, fb, rm, c->ms_cell);
+            }
+        }
     }
     // weights back to caller order (every instance holds its last accepted iterate)
     launch_scatter_out_f64(st, c->n, c->perm, c->psi_s, psi);

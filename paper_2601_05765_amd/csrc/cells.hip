@@ -224,24 +224,37 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     const R r = live ? sqrt(psi_i) : R(0);
 
     // ---------------- candidate bisectors: sites within r + r_max ----------------
+    // Normally every candidate (|t| < r) is kept. When there are more than CMAX, a
+    // counting pass picks tau = r 2^(-k/2), the largest with at most CMAX candidates
+    // below it, and only those are kept. After clipping, a restricted cell that stays
+    // within distance tau of p_i cannot be cut by the others (exact); otherwise the
+    // others are tested against the polytope and the ones that cut it are clipped too.
     int ncand = 0;
     bool inside = true;
     bool empty = false;
+    R tau = r;
+    bool overflow = false;
+    GridDesc gd{};
+    int lo3[3] = {0, 0, 0}, hi3[3] = {-1, -1, -1};
+    int nyc = 1, ncol = 0;
+    const int gbase = (int)(threadIdx.x & (64 - G));
     if (live) {
-        const GridDesc gd = A.bt.grid[inst];
+        gd = A.bt.grid[inst];
         const float reach = ((float)r + (float)A.bt.rmax[inst]) * 1.0001f;
-        int lo3[3], hi3[3];
         const float pp[3] = {(float)px, (float)py, (float)pz};
         for (int a = 0; a < 3; ++a) {
             lo3[a] = max((int)floorf((pp[a] - reach - gd.lo[a]) * gd.inv_s), 0);
             hi3[a] = min((int)floorf((pp[a] + reach - gd.lo[a]) * gd.inv_s), gd.dim[a] - 1);
         }
-        const int nyc = hi3[1] - lo3[1] + 1;
-        const int ncol = (hi3[0] - lo3[0] + 1) * nyc;
-        // columns of grid cells (z-runs are contiguous in grid order), G columns at a time;
-        // the sites of those columns are numbered consecutively (prefix sum over the lanes)
-        // and taken G at a time, each lane finding its column by a binary search
-        const int gbase = (int)(threadIdx.x & (64 - G));
+        nyc = hi3[1] - lo3[1] + 1;
+        ncol = (hi3[0] - lo3[0] + 1) * nyc;
+    }
+    // Visit every site of the block, G at a time, then the six box walls. f sees per
+    // lane: keep (a candidate: |t| < r), kill (the site empties the cell), neg (p_i is
+    // behind the bisector), the plane (n, t) and its id (site, or -1-w for wall w).
+    // The sites of up to G grid columns are numbered consecutively (prefix sum over
+    // the lanes); each lane finds its column by a binary search over shuffled sums.
+    auto scan = [&](auto &&f) {
         for (int c0 = 0; c0 < ncol; c0 += G) {
             int cbeg = 0, cnt = 0;
             if (c0 + gl < ncol) {
@@ -267,114 +280,142 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                     if (v <= idx) cidx += step;
                 }
                 const int j = __shfl(cbeg, gbase + cidx, 64) + (idx - __shfl(excl, gbase + cidx, 64));
-                {
-                    bool keep = false, kill = false, neg = false;
-                    R nx = 0, ny = 0, nz = 0, t = 0;
-                    if (idx < total && j != cell) {
-                        const float4 q4 = A.pos_s[j];
-                        // the weight difference is formed from the float64 weights: for close
-                        // sites t ~ (psi_i - psi_j) / 2d amplifies any rounding of the weights
-                        const double psi_j64 = A.psi_s[j];
-                        const R dpsi = (R)(psi_i64 - psi_j64);
-                        const R dx = (R)q4.x - px, dy = (R)q4.y - py, dz = (R)q4.z - pz;
-                        const R d2 = dot3(dx, dy, dz, dx, dy, dz);
-                        if (d2 > R(0)) {
-                            const R id = rsqrt_<R>(d2);
-                            t = (d2 + dpsi) * (R(0.5) * id);
-                            if (t <= -r) {
-                                kill = true;
-                            } else if (t < r) {
-                                keep = true;
-                                neg = t < R(0);
-                                nx = dx * id;
-                                ny = dy * id;
-                                nz = dz * id;
-                            }
-                        } else {
-                            // coincident sites: the larger weight, then the lower caller index, owns the point
-                            kill = psi_j64 > psi_i64 || (psi_j64 == psi_i64 && A.perm[j] < A.perm[cell]);
+                bool keep = false, kill = false, neg = false;
+                R nx = 0, ny = 0, nz = 0, t = 0;
+                if (idx < total && j != cell) {
+                    const float4 q4 = A.pos_s[j];
+                    // the weight difference is formed from the float64 weights: for close
+                    // sites t ~ (psi_i - psi_j) / 2d amplifies any rounding of the weights
+                    const double psi_j64 = A.psi_s[j];
+                    const R dpsi = (R)(psi_i64 - psi_j64);
+                    const R dx = (R)q4.x - px, dy = (R)q4.y - py, dz = (R)q4.z - pz;
+                    const R d2 = dot3(dx, dy, dz, dx, dy, dz);
+                    if (d2 > R(0)) {
+                        const R id = rsqrt_<R>(d2);
+                        t = (d2 + dpsi) * (R(0.5) * id);
+                        if (t <= -r) {
+                            kill = true;
+                        } else if (t < r) {
+                            keep = true;
+                            neg = t < R(0);
+                            nx = dx * id;
+                            ny = dy * id;
+                            nz = dz * id;
                         }
+                    } else {
+                        // coincident sites: the larger weight, then the lower caller index, owns the point
+                        kill = psi_j64 > psi_i64 || (psi_j64 == psi_i64 && A.perm[j] < A.perm[cell]);
                     }
-                    const unsigned long long b = gballot<G>(keep);
-                    if (keep) {
-                        const int c = ncand + popc(b & below);
-                        if (c < CMAX) {
-                            D.cand[c][0] = nx;
-                            D.cand[c][1] = ny;
-                            D.cand[c][2] = nz;
-                            D.cand[c][3] = t;
-                            D.cid[c] = j;
-                        }
-                    }
-                    ncand += popc(b);
-                    if (gballot<G>(kill)) empty = true;
-                    if (gballot<G>(neg)) inside = false;
                 }
+                f(keep, kill, neg, nx, ny, nz, t, j);
             }
         }
-        // box walls -x,+x,-y,+y,-z,+z: t = distance from p_i to the wall
-        {
-            // lane gl < 6 reads its own bound (lo[0..2], hi[0..2]) straight from the box array
+        // box walls -x,+x,-y,+y,-z,+z: t = distance from p_i to the wall; lane gl < 6 reads
+        // its own bound (lo[0..2], hi[0..2]) straight from the box array
+        bool keep = false;
+        R nx = 0, ny = 0, nz = 0, t = 0;
+        if (live && gl < 6) {
             const float *bnd = &A.bt.box[inst].lo[0];
-            bool keep = false;
-            R t = 0;
-            if (gl < 6) {
-                const int ax = gl >> 1;
-                const R pc = ax == 0 ? px : (ax == 1 ? py : pz);
-                const R w = (R)bnd[(gl & 1) * 3 + ax];
-                t = (gl & 1) ? w - pc : pc - w;
-                keep = t < r;
-            }
-            const unsigned long long b = gballot<G>(keep);
-            if (keep) {
+            const int ax = gl >> 1;
+            const R pc = ax == 0 ? px : (ax == 1 ? py : pz);
+            const R w = (R)bnd[(gl & 1) * 3 + ax];
+            t = (gl & 1) ? w - pc : pc - w;
+            keep = t < r;
+            const R sg = (gl & 1) ? R(1) : R(-1);
+            nx = ax == 0 ? sg : R(0);
+            ny = ax == 1 ? sg : R(0);
+            nz = ax == 2 ? sg : R(0);
+        }
+        f(keep, false, false, nx, ny, nz, t, -1 - gl);
+    };
+    // keep the candidates with t < thr
+    auto collect = [&](R thr) {
+        ncand = 0;
+        scan([&](bool keep, bool kill, bool neg, R nx, R ny, R nz, R t, int id) {
+            const bool k2 = keep && t < thr;
+            const unsigned long long b = gballot<G>(k2);
+            if (k2) {
                 const int c = ncand + popc(b & below);
                 if (c < CMAX) {
-                    const int ax = gl >> 1;
-                    const R sg = (gl & 1) ? R(1) : R(-1);
-                    D.cand[c][0] = ax == 0 ? sg : R(0);
-                    D.cand[c][1] = ax == 1 ? sg : R(0);
-                    D.cand[c][2] = ax == 2 ? sg : R(0);
+                    D.cand[c][0] = nx;
+                    D.cand[c][1] = ny;
+                    D.cand[c][2] = nz;
                     D.cand[c][3] = t;
-                    D.cid[c] = -1 - gl;
+                    D.cid[c] = id;
                 }
             }
             ncand += popc(b);
+            if (gballot<G>(kill)) empty = true;
+            if (gballot<G>(neg)) inside = false;
+        });
+    };
+    if (live) collect(r);
+    if (live && !empty && ncand > CMAX) {
+        constexpr int NT = 12;
+        R thr[NT];
+        int cnt[NT];
+        R f = R(0.70710678118654752);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            thr[k] = r * f;
+            cnt[k] = 0;
+            f *= R(0.70710678118654752);
         }
-        if (empty) {
-            flags |= CF_EMPTY;
-            live = false;
-        } else if (ncand > CMAX) {
-            flags |= CF_CAND;
-            live = false;
+        scan([&](bool keep, bool, bool, R, R, R, R t, int) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k) cnt[k] += (keep && t < thr[k]) ? 1 : 0;
+        });
+        int kk = -1;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const int tot = gsum<G>(cnt[k]);
+            if (kk < 0 && tot <= CMAX) kk = k;
         }
+        if (kk >= 0) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k)
+                if (k == kk) tau = thr[k];
+            overflow = true;
+            collect(tau);
+        }
+    }
+    if (empty) {
+        flags |= CF_EMPTY;
+        live = false;
+    } else if (live && ncand > CMAX) {
+        flags |= CF_CAND;
+        live = false;
     }
     __syncthreads();
 
     // ---------------- candidates in ascending t (ties by id); masks cleared ----------------
-    if (live) {
-        for (int c = gl; c < ncand; c += G) {
-            const R tc = D.cand[c][3];
-            const int ic = D.cid[c];
-            int rank = 0;
-            for (int c2 = 0; c2 < ncand; ++c2) {
-                const R t2 = D.cand[c2][3];
-                rank += (t2 < tc) || (t2 == tc && D.cid[c2] < ic);
+    auto rank_round = [&](int count) {
+        if (live) {
+            for (int c = gl; c < count; c += G) {
+                const R tc = D.cand[c][3];
+                const int ic = D.cid[c];
+                int rank = 0;
+                for (int c2 = 0; c2 < count; ++c2) {
+                    const R t2 = D.cand[c2][3];
+                    rank += (t2 < tc) || (t2 == tc && D.cid[c2] < ic);
+                }
+                rank = min(rank, CMAX - 1);
+                S.u.c.csort[rank][0] = D.cand[c][0];
+                S.u.c.csort[rank][1] = D.cand[c][1];
+                S.u.c.csort[rank][2] = D.cand[c][2];
+                S.u.c.csort[rank][3] = tc;
+                S.u.c.csid[rank] = ic;
             }
-            rank = min(rank, CMAX - 1);
-            S.u.c.csort[rank][0] = D.cand[c][0];
-            S.u.c.csort[rank][1] = D.cand[c][1];
-            S.u.c.csort[rank][2] = D.cand[c][2];
-            S.u.c.csort[rank][3] = tc;
-            S.u.c.csid[rank] = ic;
         }
-    }
-    __syncthreads();  // the discovery staging is dead from here on (the clip tables overlap it)
-    if (live) {
-        for (int p = gl; p < PMAX; p += G) {
-            KT.mout[p] = 0;
-            KT.min[p] = 0;
+        __syncthreads();  // the discovery staging is dead from here on (the clip tables overlap it)
+        if (live) {
+            for (int p = gl; p < PMAX; p += G) {
+                KT.mout[p] = 0;
+                KT.min[p] = 0;
+            }
         }
-    }
+    };
+    rank_round(ncand);
     // auxiliary cube p_i +- L (outside the ball, never a facet); planes 0..5 = -x,+x,-y,+y,-z,+z
     const R L = R(1.05) * r;
     if (live && gl < 6) {
@@ -405,146 +446,201 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     }
     int np = 6, ntri = 8, nface = 6;
     __syncthreads();
-
-    // ---------------- clip by the candidates in ascending t ----------------
-    const int maxc = gmax<64>(live ? ncand : 0);
-    for (int it = 0; it < maxc; ++it) {
-        const bool go = live && it < ncand;
-        R nx = 0, ny = 0, nz = 0, t = 0;
-        if (go) {
-            nx = S.u.c.csort[it][0];
-            ny = S.u.c.csort[it][1];
-            nz = S.u.c.csort[it][2];
-            t = S.u.c.csort[it][3];
-        }
-        // vertices beyond the plane
-        bool rem[NS];
-        int nrem = 0;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            rem[k] = go && tri[k] != TRI_INVALID && (nx * vx[k] + ny * vy[k] + nz * vz[k] > t);
-            nrem += popc(gballot<G>(rem[k]));
-        }
-        bool cut = go && nrem > 0;
-        if (cut && nrem == ntri) {  // the half-space misses the polytope: empty cell
-            flags |= CF_EMPTY;
-            live = false;
-            cut = false;
-        }
-        if (cut && np >= PMAX) {
-            flags |= CF_PLANES;
-            live = false;
-            cut = false;
-        }
-        // edges of the removed triangles, per plane
-        if (cut) {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                if (rem[k]) {
-                    const uint32_t u = tri[k];
-                    const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-                    atomicOr(&KT.mout[a], (M)1 << b);
-                    atomicOr(&KT.mout[b], (M)1 << c);
-                    atomicOr(&KT.mout[c], (M)1 << a);
-                    atomicOr(&KT.min[b], (M)1 << a);
-                    atomicOr(&KT.min[c], (M)1 << b);
-                    atomicOr(&KT.min[a], (M)1 << c);
-                }
+    // clip by the planes csort[0..count) in ascending t (every lane of the workgroup
+    // runs the same number of iterations: the loop holds barriers)
+    auto clip_round = [&](int count) {
+        const int maxc = gmax<64>(live ? count : 0);
+        for (int it = 0; it < maxc; ++it) {
+            const bool go = live && it < count;
+            R nx = 0, ny = 0, nz = 0, t = 0;
+            if (go) {
+                nx = S.u.c.csort[it][0];
+                ny = S.u.c.csort[it][1];
+                nz = S.u.c.csort[it][2];
+                t = S.u.c.csort[it][3];
             }
-        }
-        __syncthreads();
-        // boundary of the cut: plane x with out \ in = {y}; masks are cleared for the next plane
-        int nnew = 0, ninterior = 0;
-        bool bad = false;
-        if (cut) {
-            for (int p = gl; p - gl < np; p += G) {
-                bool bnd = false, intr = false;
-                if (p < np) {
-                    const M mo = KT.mout[p], mi = KT.min[p];
-                    KT.mout[p] = 0;
-                    KT.min[p] = 0;
-                    const M e = mo & ~mi;
-                    uint8_t nx8 = 0xFF;
-                    if (e) {
-                        bnd = true;
-                        bad = bad || popc(e) != 1 || popc((M)(mi & ~mo)) != 1;
-                        nx8 = (uint8_t)ctz_(e);
-                    } else if (mo) {
-                        intr = true;
+            // vertices beyond the plane
+            bool rem[NS];
+            int nrem = 0;
+    #pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                rem[k] = go && tri[k] != TRI_INVALID && (nx * vx[k] + ny * vy[k] + nz * vz[k] > t);
+                nrem += popc(gballot<G>(rem[k]));
+            }
+            bool cut = go && nrem > 0;
+            if (cut && nrem == ntri) {  // the half-space misses the polytope: empty cell
+                flags |= CF_EMPTY;
+                live = false;
+                cut = false;
+            }
+            if (cut && np >= PMAX) {
+                flags |= CF_PLANES;
+                live = false;
+                cut = false;
+            }
+            // edges of the removed triangles, per plane
+            if (cut) {
+    #pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    if (rem[k]) {
+                        const uint32_t u = tri[k];
+                        const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
+                        atomicOr(&KT.mout[a], (M)1 << b);
+                        atomicOr(&KT.mout[b], (M)1 << c);
+                        atomicOr(&KT.mout[c], (M)1 << a);
+                        atomicOr(&KT.min[b], (M)1 << a);
+                        atomicOr(&KT.min[c], (M)1 << b);
+                        atomicOr(&KT.min[a], (M)1 << c);
                     }
-                    KT.nxt[p] = nx8;
                 }
-                const unsigned long long b = gballot<G>(bnd);
-                if (bnd) KT.newl[nnew + popc(b & below)] = (uint8_t)p;
-                nnew += popc(b);
-                ninterior += popc(gballot<G>(intr));
             }
-            bad = gballot<G>(bad) != 0;
+            __syncthreads();
+            // boundary of the cut: plane x with out \ in = {y}; masks are cleared for the next plane
+            int nnew = 0, ninterior = 0;
+            bool bad = false;
+            if (cut) {
+                for (int p = gl; p - gl < np; p += G) {
+                    bool bnd = false, intr = false;
+                    if (p < np) {
+                        const M mo = KT.mout[p], mi = KT.min[p];
+                        KT.mout[p] = 0;
+                        KT.min[p] = 0;
+                        const M e = mo & ~mi;
+                        uint8_t nx8 = 0xFF;
+                        if (e) {
+                            bnd = true;
+                            bad = bad || popc(e) != 1 || popc((M)(mi & ~mo)) != 1;
+                            nx8 = (uint8_t)ctz_(e);
+                        } else if (mo) {
+                            intr = true;
+                        }
+                        KT.nxt[p] = nx8;
+                    }
+                    const unsigned long long b = gballot<G>(bnd);
+                    if (bnd) KT.newl[nnew + popc(b & below)] = (uint8_t)p;
+                    nnew += popc(b);
+                    ninterior += popc(gballot<G>(intr));
+                }
+                bad = gballot<G>(bad) != 0;
+            }
+            __syncthreads();
+            // the two ends of every cut edge; removed slots are freed
+            if (cut) {
+    #pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    const uint32_t u = tri[k];
+                    if (u == TRI_INVALID) continue;
+                    const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
+                    const int na = KT.nxt[a], nb = KT.nxt[b], nc = KT.nxt[c];
+                    if (rem[k]) {
+                        if (na == b) { KT.rpos[a][0] = vx[k]; KT.rpos[a][1] = vy[k]; KT.rpos[a][2] = vz[k]; }
+                        if (nb == c) { KT.rpos[b][0] = vx[k]; KT.rpos[b][1] = vy[k]; KT.rpos[b][2] = vz[k]; }
+                        if (nc == a) { KT.rpos[c][0] = vx[k]; KT.rpos[c][1] = vy[k]; KT.rpos[c][2] = vz[k]; }
+                        tri[k] = TRI_INVALID;
+                    } else {
+                        if (nb == a) { KT.kpos[b][0] = vx[k]; KT.kpos[b][1] = vy[k]; KT.kpos[b][2] = vz[k]; }
+                        if (nc == b) { KT.kpos[c][0] = vx[k]; KT.kpos[c][1] = vy[k]; KT.kpos[c][2] = vz[k]; }
+                        if (na == c) { KT.kpos[a][0] = vx[k]; KT.kpos[a][1] = vy[k]; KT.kpos[a][2] = vz[k]; }
+                    }
+                }
+            }
+            __syncthreads();
+            // new vertices (x, nxt[x], k) into free slots, in rank order
+            if (cut) {
+                const int knew = np;
+                if (gl == 0) {
+                    S.pl[knew][0] = nx;
+                    S.pl[knew][1] = ny;
+                    S.pl[knew][2] = nz;
+                    S.pl[knew][3] = t;
+                    S.pid[knew] = S.u.c.csid[it];
+                }
+                int fbase = 0;
+    #pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    const bool isfree = tri[k] == TRI_INVALID;
+                    const unsigned long long b = gballot<G>(isfree);
+                    const int frank = fbase + popc(b & below);
+                    fbase += popc(b);
+                    if (isfree && frank < nnew) {
+                        const int p = KT.newl[frank];
+                        const int q = KT.nxt[p];
+                        const R ax = KT.kpos[p][0], ay = KT.kpos[p][1], az = KT.kpos[p][2];
+                        const R bx = KT.rpos[p][0], by = KT.rpos[p][1], bz = KT.rpos[p][2];
+                        const R sa = nx * ax + ny * ay + nz * az - t;
+                        const R sb = nx * bx + ny * by + nz * bz - t;
+                        const R lam = (sb > sa) ? sa * rcp_<R>(sa - sb) : R(0.5);
+                        vx[k] = ax + lam * (bx - ax);
+                        vy[k] = ay + lam * (by - ay);
+                        vz[k] = az + lam * (bz - az);
+                        tri[k] = pack3(p, q, knew);
+                    }
+                }
+                if (fbase < nnew) {
+                    flags |= CF_VERTS;
+                    live = false;
+                }
+                ntri = ntri - nrem + nnew;
+                nface = nface - ninterior + 1;
+                np++;
+                if (bad || ntri != 2 * nface - 4) {
+                    flags |= CF_TOPO;
+                    live = false;
+                }
+            }
         }
-        __syncthreads();
-        // the two ends of every cut edge; removed slots are freed
-        if (cut) {
+    };
+
+    clip_round(ncand);
+
+    // ---------------- overflow: the candidates with t >= tau ----------------
+    if (__any(overflow && live)) {
+        R v2 = R(0);
 #pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                const uint32_t u = tri[k];
-                if (u == TRI_INVALID) continue;
-                const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
-                const int na = KT.nxt[a], nb = KT.nxt[b], nc = KT.nxt[c];
-                if (rem[k]) {
-                    if (na == b) { KT.rpos[a][0] = vx[k]; KT.rpos[a][1] = vy[k]; KT.rpos[a][2] = vz[k]; }
-                    if (nb == c) { KT.rpos[b][0] = vx[k]; KT.rpos[b][1] = vy[k]; KT.rpos[b][2] = vz[k]; }
-                    if (nc == a) { KT.rpos[c][0] = vx[k]; KT.rpos[c][1] = vy[k]; KT.rpos[c][2] = vz[k]; }
-                    tri[k] = TRI_INVALID;
-                } else {
-                    if (nb == a) { KT.kpos[b][0] = vx[k]; KT.kpos[b][1] = vy[k]; KT.kpos[b][2] = vz[k]; }
-                    if (nc == b) { KT.kpos[c][0] = vx[k]; KT.kpos[c][1] = vy[k]; KT.kpos[c][2] = vz[k]; }
-                    if (na == c) { KT.kpos[a][0] = vx[k]; KT.kpos[a][1] = vy[k]; KT.kpos[a][2] = vz[k]; }
-                }
-            }
-        }
-        __syncthreads();
-        // new vertices (x, nxt[x], k) into free slots, in rank order
-        if (cut) {
-            const int knew = np;
-            if (gl == 0) {
-                S.pl[knew][0] = nx;
-                S.pl[knew][1] = ny;
-                S.pl[knew][2] = nz;
-                S.pl[knew][3] = t;
-                S.pid[knew] = S.u.c.csid[it];
-            }
-            int fbase = 0;
+        for (int k = 0; k < NS; ++k)
+            if (tri[k] != TRI_INVALID) v2 = fmax(v2, vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
 #pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                const bool isfree = tri[k] == TRI_INVALID;
-                const unsigned long long b = gballot<G>(isfree);
-                const int frank = fbase + popc(b & below);
-                fbase += popc(b);
-                if (isfree && frank < nnew) {
-                    const int p = KT.newl[frank];
-                    const int q = KT.nxt[p];
-                    const R ax = KT.kpos[p][0], ay = KT.kpos[p][1], az = KT.kpos[p][2];
-                    const R bx = KT.rpos[p][0], by = KT.rpos[p][1], bz = KT.rpos[p][2];
-                    const R sa = nx * ax + ny * ay + nz * az - t;
-                    const R sb = nx * bx + ny * by + nz * bz - t;
-                    const R lam = (sb > sa) ? sa * rcp_<R>(sa - sb) : R(0.5);
-                    vx[k] = ax + lam * (bx - ax);
-                    vy[k] = ay + lam * (by - ay);
-                    vz[k] = az + lam * (bz - az);
-                    tri[k] = pack3(p, q, knew);
+        for (int o = G / 2; o > 0; o >>= 1) v2 = fmax(v2, __shfl_xor(v2, o, 64));
+        // the restricted cell lies within min(max vertex distance, r) of p_i
+        const R reff = v2 > r * r ? r : sqrt(v2);
+        int nc2 = 0;
+        __syncthreads();  // the clip tables become the staging list
+        if (overflow && live && reff >= tau) {
+            scan([&](bool keep, bool, bool, R nx, R ny, R nz, R t, int id) {
+                unsigned long long pm = gballot<G>(keep && t >= tau && t < reff);
+                while (pm) {
+                    const int q = __ffsll((long long)pm) - 1;
+                    pm &= pm - 1;
+                    const R qx = __shfl(nx, gbase + q, 64), qy = __shfl(ny, gbase + q, 64),
+                            qz = __shfl(nz, gbase + q, 64), qt = __shfl(t, gbase + q, 64);
+                    const int qid = __shfl(id, gbase + q, 64);
+                    bool beyond = false;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k)
+                        beyond = beyond || (tri[k] != TRI_INVALID && qx * vx[k] + qy * vy[k] + qz * vz[k] > qt);
+                    if (gballot<G>(beyond)) {
+                        if (gl == 0 && nc2 < CMAX) {
+                            D.cand[nc2][0] = qx;
+                            D.cand[nc2][1] = qy;
+                            D.cand[nc2][2] = qz;
+                            D.cand[nc2][3] = qt;
+                            D.cid[nc2] = qid;
+                        }
+                        ++nc2;
+                    }
                 }
-            }
-            if (fbase < nnew) {
-                flags |= CF_VERTS;
+            });
+            if (nc2 > CMAX) {
+                flags |= CF_CAND;
                 live = false;
             }
-            ntri = ntri - nrem + nnew;
-            nface = nface - ninterior + 1;
-            np++;
-            if (bad || ntri != 2 * nface - 4) {
-                flags |= CF_TOPO;
-                live = false;
-            }
+        }
+        __syncthreads();
+        if (__any(live && nc2 > 0)) {
+            const int c2 = live ? nc2 : 0;
+            rank_round(c2);
+            __syncthreads();
+            clip_round(c2);
         }
     }
 
@@ -750,7 +846,7 @@ template <int G>
 __global__ __launch_bounds__(64) void k_cells_fast(CellArgs A) {
     __shared__ CellSmem<float, FAST_CMAX, FAST_PMAX, FAST_VMAX> smem[64 / G];
     const int gi = (int)(threadIdx.x / G);
-    int64_t cell = (int64_t)blockIdx.x * (64 / G) + gi;
+    int64_t cell = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * (64 / G) + gi;
     if (cell >= A.n || !selected(A.bt, A.want, A.bt.inst[cell])) cell = -1;
     cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX>(cell, A, smem[gi], true);
 }

@@ -289,8 +289,9 @@ __global__ __launch_bounds__(TILE) void k_default_start(Batch bt, int want, cons
 // t_ij >= 0, so p_i lies in C_i and the cell is not empty; at equality the nearest
 // bisector passes through p_i and the neighbour keeps t_ji = d_ij > 0, so nearly
 // coincident pairs keep both cells. New weight: max(psi_i, max_j (psi_j - d_ij^2))
-// (the default weight if that is not positive), capped at twice the default weight
-// (a much heavier neighbour is left to the full restart). Only sites within
+// (the default weight if that is not positive), capped at twice the larger of the
+// default weight and the mean weight of the sites searched (a neighbour much heavier
+// than its surroundings is left to the full restart). Only sites within
 // 2 max(r_max, r_i) can matter (farther bisectors miss the ball). The other weights
 // keep the warm start. One thread per row; weights are read from psi and written to
 // psi_out (every row: a copy where nothing changes), so the result does not depend
@@ -309,17 +310,17 @@ __global__ __launch_bounds__(TILE) void k_repair_empty(Batch bt, int want, const
     }
     const double rd2 = pow(1.2 * cbrt(3.0 * nu[i] / (4.0 * 3.14159265358979323846)), 2.0);
     const double p0 = psi[i];
-    const double cap = fmax(p0, 2.0 * rd2);
     const GridDesc g = bt.grid[b];
     const float4 pi = pos[i];
-    const float reach = 2.0f * fmaxf((float)bt.rmax[b], (float)sqrt(cap)) * 1.0001f;
+    const float reach = 2.0f * (float)bt.rmax[b] * 1.0001f;
     const float pp[3] = {pi.x, pi.y, pi.z};
     int lo3[3], hi3[3];
     for (int a = 0; a < 3; ++a) {
         lo3[a] = max((int)floorf((pp[a] - reach - g.lo[a]) * g.inv_s), 0);
         hi3[a] = min((int)floorf((pp[a] + reach - g.lo[a]) * g.inv_s), g.dim[a] - 1);
     }
-    double m = -1e300;
+    double m = -1e300, wsum = 0.0;
+    int wn = 0;
     for (int ix = lo3[0]; ix <= hi3[0]; ++ix)
         for (int iy = lo3[1]; iy <= hi3[1]; ++iy) {
             const int col = g.base + (ix * g.dim[1] + iy) * g.dim[2];
@@ -329,8 +330,11 @@ __global__ __launch_bounds__(TILE) void k_repair_empty(Batch bt, int want, const
                 const float4 q = pos[j];  // x, y, z only (.w of repaired rows changes)
                 const double dx = (double)q.x - pi.x, dy = (double)q.y - pi.y, dz = (double)q.z - pi.z;
                 m = fmax(m, psi[j] - (dx * dx + dy * dy + dz * dz));
+                wsum += psi[j];
+                ++wn;
             }
         }
+    const double cap = fmax(p0, 2.0 * fmax(rd2, wn > 0 ? wsum / wn : 0.0));
     double w = fmax(p0, m);
     if (!(w > 0.0)) w = rd2;
     w = fmin(w, cap);

@@ -88,6 +88,19 @@ struct Batch {
     const int32_t *phase;        // [B] Phase
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD w mod 8),
+// and each XCD has its own L2. This maps the hardware workgroup id to a logical one
+// so that each XCD works through one contiguous run of logical ids: neighbouring
+// rows (grid order = space order) then share an L2. A bijection on [0, n).
+constexpr int NXCD = 8;
+__device__ inline int xcd_block(int w, int n) {
+    const int per = n / NXCD, rem = n % NXCD;  // XCD x gets per + (x < rem) ids
+    const int x = w % NXCD, k = w / NXCD;
+    if (k < per) return x * per + min(x, rem) + k;
+    // the last round (w >= per * NXCD): only XCDs x < rem have an id left
+    return x * per + x + per;
+}
+
 // Does instance b take part in a launch that selects phase `want` (< 0: all)?
 __device__ inline bool selected(const Batch &bt, int want, int b) { return want < 0 || bt.phase[b] == want; }
 

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_knn_features(int64_t n, const float4 *_
                                                        const double *__restrict__ V_s,
                                                        int32_t *__restrict__ nbr_out, uint16_t *__restrict__ feat,
                                                        int32_t *__restrict__ err) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const float4 p = pos_s[k];
     double D[N_NEI];

@@ -132,7 +132,7 @@ __global__ void k_hess_assemble(int64_t n, Batch bt, int want, const float4 *__r
                                 const int32_t *__restrict__ fcol, const float *__restrict__ farea,
                                 const int32_t *__restrict__ fcnt, int32_t *__restrict__ hcol,
                                 float *__restrict__ hval, int32_t *__restrict__ xcnt, int32_t *__restrict__ herr) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t i = t / 16;
     const int f0 = (int)(t & 15);
     if (i >= n) return;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_init(Batch bt, const double 
                                                  CgBufs cg) {
     constexpr int SPT = TILE / SUB;
     __shared__ double sh[LANES * SUB / 64][4];
-    const int q = blockIdx.x;
+    const int q = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int t = q / SPT;
     if (q == 0 && threadIdx.x == 0) *cg.kbase = 0;
     const int b = bt.tile_inst[t];
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
                                                  CgBufs cg) {
     constexpr int SPT = TILE / SUB;
     __shared__ double sh[LANES * SUB / 64][4];
-    const int q = blockIdx.x;
+    const int q = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int t = q / SPT;
     const int b = bt.tile_inst[t];
     const int row = bt.tile_row[t] + (q % SPT) * SUB + (int)(threadIdx.x / LANES);

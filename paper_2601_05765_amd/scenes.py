@@ -180,6 +180,23 @@ def sphere_cluster(n: int, seed: int, total: float = 0.35, fill: float = 0.40) -
                  meta={"seed": seed, "n": n, "spheres": k, "R": hi})
 
 
+def overpacked_sphere(n: int = 2500, over: float = 1.72, seed: int = 0, R: float = 0.15) -> Scene:
+    """One sphere of radius R at the box centre filled with a jittered lattice of n
+    sites whose prescribed volumes add up to `over` times the sphere's volume (the
+    packing of the splash scene's spheres): the converged balls overlap hundreds of
+    neighbours."""
+    rng = np.random.default_rng(seed)
+    vol = 4.0 / 3.0 * math.pi * R ** 3
+    h = (vol / n) ** (1.0 / 3.0)
+    g = np.arange(-R - h, R + h, h)
+    p = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    p = p + rng.uniform(-0.3 * h, 0.3 * h, p.shape)
+    p = p[np.argsort(np.linalg.norm(p, axis=1), kind="stable")[:n]] + 0.5
+    nu = np.full(n, over * vol / n)
+    return Scene("overpacked_sphere", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, default_psi0(nu),
+                 meta={"seed": seed, "n": n, "over": over, "h": h})
+
+
 def batch_instances(count: int = 256, base_seed: int = 1000, n_lo: int = 500, n_hi: int = 50_000):
     """Independent instances of uneven size: slab layout for even seeds, sphere cluster for odd."""
     out = []

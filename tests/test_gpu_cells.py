@@ -146,3 +146,28 @@ def test_empty_cells(ctx, oracle_mod):
     assert V[0] == 0 and V[2] == 0 and V[3] == 0
     assert V[1] == pytest.approx(orc.V[1], rel=1e-6)
     assert out["nnz"] == 0
+
+
+@pytest.fixture(scope="module")
+def overpacked(oracle_mod):
+    """A sphere packed 1.72x and its converged weights (oracle): ~500 candidate
+    bisectors per cell, far beyond the kernels' candidate capacities."""
+    sc = scenes.overpacked_sphere(2500, 1.72, 0)
+    psi, st = oracle_mod.newton_solve(sc.xyz64(), sc.nu, sc.psi0, tol=1e-7)
+    assert st.status == "ok"
+    return sc, psi
+
+
+@pytest.mark.parametrize("tpc", [16, 32, 64])
+def test_overpacked_sphere_cells(ctx, oracle_mod, overpacked, tpc):
+    _say(f"case: over-packed sphere at converged weights, lanes per cell {tpc}")
+    sc, psi = overpacked
+    ctx.set_threads_per_cell(tpc)
+    try:
+        out, c = _run(ctx, oracle_mod, sc.x, sc.y, sc.z, psi)
+    finally:
+        ctx.set_threads_per_cell(32)
+    _say(f"  oracle candidates per cell: median {int(np.median(c.ncand))} max {int(c.ncand.max())}")
+    rep = compare(out, c, psi)
+    _say(f"  {rep} fallback {ctx.last_fallback_cells()}")
+    assert_close(rep)

@@ -149,6 +149,19 @@ def test_trial_evaluations_use_trial_weights(ctx, oracle_mod):
     assert float(np.max(np.abs(c.V - nu) / nu)) <= 1e-5
 
 
+def test_solve_overpacked_sphere(ctx, oracle_mod):
+    """A sphere packed 1.72x (the splash scene's spheres): the converged balls overlap
+    ~500 neighbours each, beyond every candidate capacity of the cell kernels."""
+    _say("case: solve over-packed sphere (2500 sites, 1.72x)")
+    import paper_2601_05765_amd as L
+    sc = scenes.overpacked_sphere(2500, 1.72, 1)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.max_rel_err <= 1e-5
+    assert _oracle_err(oracle_mod, sc, psi.cpu().numpy()) <= 1e-5
+
+
 def test_error_codes(ctx):
     _say("case: error codes")
     import torch
