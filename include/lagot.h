@@ -66,9 +66,12 @@ typedef struct {
                             step length, residuals, fallback count and r_max                     */
     int use_learned;     /* 1: try the learned warm start (lagot_mlp_set_params) before Newton       */
     int empty_start_fallback; /* 1 (default): if a start cell is empty (KMT needs eps0 > 0), give
-                            the empty cells the default weight psi_i = (1.2 (3 nu_i / 4 pi)^(1/3))^2
-                            (at least), and if a cell is still empty restart from the default
-                            weights everywhere; 0: return LAGOT_EEMPTY                          */
+                            each empty cell the weight of the neighbour j* that swallows its site
+                            most (max psi_j - d_ij^2), so that their bisector is the mid-plane
+                            (bounded so no other neighbour loses its site, and by twice the
+                            local mean weight), and if a cell is still empty restart from the
+                            default start: the common weight (1.2 (3 nu_mean / 4 pi)^(1/3))^2 of
+                            the instance (a Voronoi start, no empty cell); 0: LAGOT_EEMPTY      */
     int autotune;        /* 1: when threads_per_cell is 0, time the cell kernel with 16, 32 and 64
                             lanes per cell, and the PCG kernels with four block shapes, on the
                             first solve of each size and density class, and keep the fastest in
@@ -246,6 +249,17 @@ int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block);
 /* Number of cells that the last lagot_cells call on this context redid on the
  * large-capacity float64 path (diagnostic; -1 if ctx is NULL). */
 int lagot_last_fallback_cells(const lagot_ctx *ctx);
+
+/* Per-bit cell counts of the last evaluation on this context (lagot_cells or the
+ * last evaluation of a solve), a diagnostic of why cells took the float64 path.
+ * counts[k] for k < 8: cells whose final result has bit k; counts[8 + k]: cells that
+ * the float32 pass sent to the float64 path with reason bit k. Bits: 0 empty cell,
+ * 1 too many candidate bisectors, 2 too many polytope planes, 3 too many vertices,
+ * 4 inconsistent clip combinatorics, 5 facet walk not closed, 6 too many facets,
+ * 7 float32 relative accuracy insufficient (volume small against its terms).
+ *   out: counts [16] HOST array. Synchronises the stream.
+ * Errors: EINVAL (null pointer or nothing evaluated yet), EHIP. */
+int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts);
 
 /* Duration in ms of the float32 cell-kernel launch of the last lagot_cells call
  * (HIP events on the context stream; diagnostic; -1 if ctx is NULL). */

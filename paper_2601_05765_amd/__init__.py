@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_cell_kernel_ms",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
@@ -96,6 +96,8 @@ def load():
         lib.lagot_set_threads_per_cell.restype = I
         lib.lagot_set_cg_shape.argtypes = [P, I, I]
         lib.lagot_set_cg_shape.restype = I
+        lib.lagot_last_flag_counts.argtypes = [P, P]
+        lib.lagot_last_flag_counts.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
         lib.lagot_last_fallback_cells.restype = I
         lib.lagot_last_cell_kernel_ms.argtypes = [P]
@@ -277,6 +279,17 @@ class Context:
 
     def last_fallback_cells(self) -> int:
         return int(load().lagot_last_fallback_cells(self._h))
+
+    FLAG_NAMES = ("empty", "candidates", "planes", "vertices", "topology", "walk", "facets", "precision")
+
+    def last_flag_counts(self) -> dict:
+        """lagot_last_flag_counts: {"final": {name: cells}, "float64_reasons": {name: cells}}."""
+        buf = (ctypes.c_int64 * 16)()
+        rc = load().lagot_last_flag_counts(self._h, ctypes.cast(buf, ctypes.c_void_p))
+        if rc != OK:
+            raise LagotError(rc, "lagot_last_flag_counts")
+        return {"final": {k: int(buf[i]) for i, k in enumerate(self.FLAG_NAMES)},
+                "float64_reasons": {k: int(buf[8 + i]) for i, k in enumerate(self.FLAG_NAMES)}}
 
     def last_cell_kernel_ms(self) -> float:
         return float(load().lagot_last_cell_kernel_ms(self._h))

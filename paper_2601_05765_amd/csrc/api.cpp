@@ -75,10 +75,11 @@ struct lagot_ctx {
     double *ev = nullptr, *ev2 = nullptr, *ev_nu = nullptr, *part_ev = nullptr;
     int32_t *fb_inst = nullptr, *fail_inst = nullptr, *bad_inst = nullptr, *herr = nullptr, *counts = nullptr;
     int32_t *misc = nullptr;  // [0] float64 work-list length [1] feature errors [2] kbase [3] remaining
+                              // [4] overflow work-list length
     // evaluation outputs (grid order)
     double *V = nullptr, *K = nullptr;
     float *wall = nullptr;
-    int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr;
+    int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr, *ovf_list = nullptr;
     float *farea = nullptr;
     uint32_t *flags = nullptr;
     // second set of evaluation outputs (learned guess: evaluated aside, swapped in if kept)
@@ -152,7 +153,7 @@ template <typename... P> void free_ptrs(P *&...ps) {
 
 void free_sites(lagot_ctx *c) {
     free_ptrs(c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->inst, c->V, c->K, c->wall,
-              c->fcol, c->fcnt, c->fb_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
+              c->fcol, c->fcnt, c->fb_list, c->ovf_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
               c->cg_vec, c->csr_cnt, c->csr_start, c->csr_tmp);
     c->cap_n = 0;
 }
@@ -238,6 +239,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->farea, FCAP * N));
     HIP_TRY(dalloc(&c->fcnt, N));
     HIP_TRY(dalloc(&c->fb_list, N));
+    HIP_TRY(dalloc(&c->ovf_list, N));
     HIP_TRY(dalloc(&c->flags, N));
     HIP_TRY(dalloc(&c->hcol, FCAP * N));
     HIP_TRY(dalloc(&c->hval, FCAP * N));
@@ -479,7 +481,7 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
 
 EvalOut eval_out(lagot_ctx *c, bool walls) {
     EvalOut o{c->V, c->K, walls ? c->wall : nullptr, c->fcol, c->farea, c->fcnt, c->flags, c->fb_list, c->misc + 0,
-              c->fb_inst, c->fail_inst};
+              c->fb_inst, c->fail_inst, c->ovf_list, c->misc + 4};
     return o;
 }
 
@@ -903,7 +905,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
         if (rc) return fail_all(rc);
     }
     if (c->h_cnt[PH_RESTART] > 0) {
-        launch_default_start(st, bt, PH_RESTART, c->nu_s, c->psi_s, c->pos_s);
+        launch_default_start(st, bt, PH_RESTART, c->ev_nu, c->psi_s, c->pos_s);
         launch_rmax(st, bt, PH_RESTART, c->psi_s, c->rmax);
         evaluate(c, PH_RESTART, c->psi_s, false, c->ev);
         launch_ctl_start(st, bt, co, PH_RESTART, c->ev, c->ev_nu, c->ev, c->fail_inst, c->ctl, c->phase, c->counts);
@@ -953,17 +955,18 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
                     round, c->h_cnt[PH_ACTIVE], c->h_cnt[PH_DONE], c->h_cnt[PH_FAILED], tm.lin, tm.eval);
             if (o.verbose > 1) {  // state of the first instance
                 InstCtl q;
-                int32_t fb = 0;
+                int32_t fb = 0, fl = 0;
                 double rm = 0.0;
                 HIP_TRY(hipMemcpyAsync(&q, c->ctl, sizeof(q), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&fb, c->fb_inst, sizeof(fb), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&fl, c->fail_inst, sizeof(fl), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&rm, c->rmax, sizeof(rm), hipMemcpyDeviceToHost, st));
                 rc = sync(c);
                 if (rc) return fail_all(rc);
                 fprintf(stderr,
                         "  inst 0: alpha %.3g |g| %.3e maxrel %.3e minV %.3e evals %d halvings %d cg %d "
-                        "fallback %d r_max %.4g cell kernel %.1f ms\n",
-                        q.alpha, q.gnorm, q.maxrel, q.minV, q.evals, q.halvings, q.cg_iters, fb, rm, c->ms_cell);
+                        "fallback %d failed (last evaluation) %d r_max %.4g cell kernel %.1f ms\n",
+                        q.alpha, q.gnorm, q.maxrel, q.minV, q.evals, q.halvings, q.cg_iters, fb, fl, rm, c->ms_cell);
             }
         }
     }
@@ -1280,6 +1283,19 @@ int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block) {
 }
 
 int lagot_last_fallback_cells(const lagot_ctx *ctx) { return ctx ? ctx->last_fb : -1; }
+
+int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts) {
+    if (!ctx || !counts || ctx->n <= 0 || !ctx->flags) return LAGOT_EINVAL;
+    std::vector<uint32_t> f((size_t)ctx->n);
+    HIP_TRY(hipMemcpyAsync(f.data(), ctx->flags, sizeof(uint32_t) * (size_t)ctx->n, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    const int rc = sync(ctx);
+    if (rc) return rc;
+    for (int k = 0; k < 16; ++k) counts[k] = 0;
+    for (uint32_t v : f)
+        for (int k = 0; k < 16; ++k) counts[k] += (v >> k) & 1u;
+    return LAGOT_OK;
+}
 
 double lagot_last_cell_kernel_ms(const lagot_ctx *ctx) { return ctx ? ctx->ms_cell : -1.0; }
 

@@ -194,8 +194,15 @@ struct CellArgs {
     EvalOut out;
 };
 
-template <typename R, int G, int CMAX, int PMAX, int VMAX>
-__device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMAX, VMAX> &S, bool fast) {
+template <typename R, int G, int CMAX, int PMAX, int VMAX, int MODE>
+__device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMAX, VMAX> &S) {
+    // MODE 0: the fast pass (a cell with more than CMAX candidates is deferred to the
+    // overflow list); 1: the overflow pass (threshold ladder and clip rounds); 2: the
+    // large-capacity pass for the cells that passes 0 and 1 cannot finish (capacity, or
+    // float32 accuracy).
+    constexpr bool fast = MODE < 2;
+    constexpr bool rounds = MODE >= 1;
+    bool deferred = false;
     using M = typename MaskType<PMAX>::T;
     constexpr int NS = VMAX / G;  // vertex slots per lane (registers); slot id = k * G + lane
     static_assert(NS * G == VMAX, "VMAX must be a multiple of G");
@@ -293,6 +300,17 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                     if (d2 > R(0)) {
                         const R id = rsqrt_<R>(d2);
                         t = (d2 + dpsi) * (R(0.5) * id);
+                        if constexpr (sizeof(R) == 4) {
+                            // d^2 and the weight difference nearly cancel (large weights):
+                            // the float32 offset would carry their rounding, so it is
+                            // formed in float64 (the float32 differences are exact there)
+                            if (fabs(dpsi) > d2 && t > -r && t < r) {
+                                const double ex = (double)q4.x - (double)px, ey = (double)q4.y - (double)py,
+                                             ez = (double)q4.z - (double)pz;
+                                const double e2 = ex * ex + ey * ey + ez * ez;
+                                t = (R)((e2 + (psi_i64 - psi_j64)) / (2.0 * sqrt(e2)));
+                            }
+                        }
                         if (t <= -r) {
                             kill = true;
                         } else if (t < r) {
@@ -317,7 +335,10 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         if (live && gl < 6) {
             const float *bnd = &A.bt.box[inst].lo[0];
             const int ax = gl >> 1;
-            const R pc = ax == 0 ? px : (ax == 1 ? py : pz);
+            // select values, not the captured references (a select of references becomes
+            // an indexed load from the closure, which then stays in scratch memory)
+            const R cx = px, cy = py, cz = pz;
+            const R pc = ax == 0 ? cx : (ax == 1 ? cy : cz);
             const R w = (R)bnd[(gl & 1) * 3 + ax];
             t = (gl & 1) ? w - pc : pc - w;
             keep = t < r;
@@ -350,16 +371,20 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         });
     };
     if (live) collect(r);
-    if (live && !empty && ncand > CMAX) {
-        constexpr int NT = 12;
+    if (!rounds && live && !empty && ncand > CMAX) {
+        deferred = true;
+        live = false;
+    }
+    if (rounds && live && !empty && ncand > CMAX) {
+        constexpr int NT = 18;  // tau = r 2^(-k/3), k = 1..18 (down to r / 64)
         R thr[NT];
         int cnt[NT];
-        R f = R(0.70710678118654752);
+        R f = R(0.79370052598409974);
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             thr[k] = r * f;
             cnt[k] = 0;
-            f *= R(0.70710678118654752);
+            f *= R(0.79370052598409974);
         }
         scan([&](bool keep, bool, bool, R, R, R, R t, int) {
 #pragma unroll
@@ -415,7 +440,6 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             }
         }
     };
-    rank_round(ncand);
     // auxiliary cube p_i +- L (outside the ball, never a facet); planes 0..5 = -x,+x,-y,+y,-z,+z
     const R L = R(1.05) * r;
     if (live && gl < 6) {
@@ -446,11 +470,81 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     }
     int np = 6, ntri = 8, nface = 6;
     __syncthreads();
+    // Drops the planes (index >= 6) that no vertex uses any more: a plane that cut
+    // the polytope can lose its whole face to later planes, and long clip sequences
+    // would otherwise run out of plane slots. Between clip steps the cut tables are
+    // free: nxt flags the planes in use, newl maps old to new index, kpos/rpos hold
+    // the kept planes and min their ids (min is cleared again for the next step).
+    // Called by every lane of the workgroup (it holds barriers).
+    auto compact = [&]() {
+        uint8_t *used = KT.nxt;
+        uint8_t *map = KT.newl;
+        R *tpl = &KT.kpos[0][0];
+        int32_t *tid = reinterpret_cast<int32_t *>(&KT.min[0]);
+        static_assert(sizeof(KT.kpos) + sizeof(KT.rpos) >= sizeof(R) * 4 * PMAX, "plane staging");
+        static_assert(sizeof(KT.min) >= sizeof(int32_t) * PMAX, "id staging");
+        if (live)
+            for (int p = gl; p < np; p += G) used[p] = p < 6 ? 1 : 0;
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const uint32_t u = tri[k];
+                if (u == TRI_INVALID) continue;
+                used[u & 0xFF] = 1;
+                used[(u >> 8) & 0xFF] = 1;
+                used[(u >> 16) & 0xFF] = 1;
+            }
+        }
+        __syncthreads();
+        int nk = 0;
+        if (live) {
+            for (int p = gl; p - gl < np; p += G) {
+                const bool keep = p < np && used[p];
+                const unsigned long long b = gballot<G>(keep);
+                const int to = nk + popc(b & below);
+                nk += popc(b);
+                if (p < np) map[p] = keep ? (uint8_t)to : (uint8_t)0xFF;
+                if (keep) {
+                    tpl[4 * to + 0] = S.pl[p][0];
+                    tpl[4 * to + 1] = S.pl[p][1];
+                    tpl[4 * to + 2] = S.pl[p][2];
+                    tpl[4 * to + 3] = S.pl[p][3];
+                    tid[to] = S.pid[p];
+                }
+            }
+        }
+        __syncthreads();
+        if (live) {
+            for (int p = gl; p < nk; p += G) {
+                S.pl[p][0] = tpl[4 * p + 0];
+                S.pl[p][1] = tpl[4 * p + 1];
+                S.pl[p][2] = tpl[4 * p + 2];
+                S.pl[p][3] = tpl[4 * p + 3];
+                S.pid[p] = tid[p];
+            }
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const uint32_t u = tri[k];
+                if (u == TRI_INVALID) continue;
+                tri[k] = pack3(map[u & 0xFF], map[(u >> 8) & 0xFF], map[(u >> 16) & 0xFF]);
+            }
+        }
+        __syncthreads();
+        if (live) {
+            for (int p = gl; p < PMAX; p += G) KT.min[p] = 0;
+            np = nk;
+        }
+        __syncthreads();
+    };
     // clip by the planes csort[0..count) in ascending t (every lane of the workgroup
     // runs the same number of iterations: the loop holds barriers)
     auto clip_round = [&](int count) {
         const int maxc = gmax<64>(live ? count : 0);
         for (int it = 0; it < maxc; ++it) {
+            if constexpr (rounds) {  // long clip sequences: free the slots of dead planes
+                if (__any(live && it < count && np >= PMAX - 1)) compact();
+            }
             const bool go = live && it < count;
             R nx = 0, ny = 0, nz = 0, t = 0;
             if (go) {
@@ -591,10 +685,21 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
     };
 
-    clip_round(ncand);
-
-    // ---------------- overflow: the candidates with t >= tau ----------------
-    if (__any(overflow && live)) {
+    // Clip rounds. Round 0 clips the discovered candidates. A cell whose discovery
+    // overflowed then runs rounds over the candidates with tau <= t < r_eff (r_eff
+    // bounds the current polytope) that cut the polytope and are not yet among its
+    // planes: the first CMAX found are clipped in ascending t, and a round that leaves
+    // none out is its last. Clipping by any subset is exact (the cell is the
+    // intersection of all the half-spaces); each round only shrinks the polytope.
+    // One loop holds the only copy of the clipping code.
+    int count = ncand, nclip = ncand;
+    bool more = overflow && live;
+    for (int round = 0;; ++round) {
+        rank_round(count);
+        __syncthreads();
+        clip_round(nclip);
+        if (!rounds || round >= OVERFLOW_ROUNDS || !__any(more && live)) break;
+        compact();
         R v2 = R(0);
 #pragma unroll
         for (int k = 0; k < NS; ++k)
@@ -605,7 +710,8 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         const R reff = v2 > r * r ? r : sqrt(v2);
         int nc2 = 0;
         __syncthreads();  // the clip tables become the staging list
-        if (overflow && live && reff >= tau) {
+        if (more && live && reff >= tau) {
+            const int npl = np;
             scan([&](bool keep, bool, bool, R nx, R ny, R nz, R t, int id) {
                 unsigned long long pm = gballot<G>(keep && t >= tau && t < reff);
                 while (pm) {
@@ -618,29 +724,59 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
 #pragma unroll
                     for (int k = 0; k < NS; ++k)
                         beyond = beyond || (tri[k] != TRI_INVALID && qx * vx[k] + qy * vy[k] + qz * vz[k] > qt);
-                    if (gballot<G>(beyond)) {
-                        if (gl == 0 && nc2 < CMAX) {
-                            D.cand[nc2][0] = qx;
-                            D.cand[nc2][1] = qy;
-                            D.cand[nc2][2] = qz;
-                            D.cand[nc2][3] = qt;
-                            D.cid[nc2] = qid;
-                        }
-                        ++nc2;
+                    if (!gballot<G>(beyond)) continue;
+                    bool known = false;  // a plane of the polytope (rounding can put its vertices beyond it)
+                    for (int pp = 6 + gl; pp < npl; pp += G) known = known || S.pid[pp] == qid;
+                    if (gballot<G>(known)) continue;
+                    if (gl == 0 && nc2 < CMAX) {
+                        D.cand[nc2][0] = qx;
+                        D.cand[nc2][1] = qy;
+                        D.cand[nc2][2] = qz;
+                        D.cand[nc2][3] = qt;
+                        D.cid[nc2] = qid;
                     }
+                    ++nc2;
                 }
             });
-            if (nc2 > CMAX) {
-                flags |= CF_CAND;
-                live = false;
-            }
         }
         __syncthreads();
-        if (__any(live && nc2 > 0)) {
-            const int c2 = live ? nc2 : 0;
-            rank_round(c2);
-            __syncthreads();
-            clip_round(c2);
+        // the nearest (in t) of the collected cutters, as many as free plane slots allow
+        count = (more && live) ? min(nc2, CMAX) : 0;
+        nclip = min(count, PMAX - 1 - np);
+        more = more && live && nc2 > nclip;
+        if (more && nclip <= 0) {
+            flags |= CF_PLANES;
+            live = false;
+            more = false;
+        }
+    }
+    if (more && live) {
+        flags |= CF_CAND;
+        live = false;
+    }
+    // Each vertex again from its three planes (Cramer's rule): clipping places new
+    // vertices by interpolation along edges whose ends carry the rounding of earlier
+    // clips, which compounds over long clip sequences. Kept where the planes are well
+    // conditioned (|det| of the unit normals > 0.05), else the interpolated position.
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const uint32_t u = tri[k];
+            if (u == TRI_INVALID) continue;
+            const int a = u & 0xFF, b = (u >> 8) & 0xFF, c = (u >> 16) & 0xFF;
+            const R ax = S.pl[a][0], ay = S.pl[a][1], az = S.pl[a][2], at = S.pl[a][3];
+            const R bx = S.pl[b][0], by = S.pl[b][1], bz = S.pl[b][2], bt = S.pl[b][3];
+            const R cx = S.pl[c][0], cy = S.pl[c][1], cz = S.pl[c][2], ct = S.pl[c][3];
+            const R bcx = by * cz - bz * cy, bcy = bz * cx - bx * cz, bcz = bx * cy - by * cx;
+            const R cax = cy * az - cz * ay, cay = cz * ax - cx * az, caz = cx * ay - cy * ax;
+            const R abx = ay * bz - az * by, aby = az * bx - ax * bz, abz = ax * by - ay * bx;
+            const R det = ax * bcx + ay * bcy + az * bcz;
+            if (fabs(det) > R(0.05)) {
+                const R inv = R(1) / det;
+                vx[k] = (at * bcx + bt * cax + ct * abx) * inv;
+                vy[k] = (at * bcy + bt * cay + ct * aby) * inv;
+                vz[k] = (at * bcz + bt * caz + ct * abz) * inv;
+            }
         }
     }
 
@@ -746,8 +882,18 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
     }
     __syncthreads();
+    // a polytope whose vertices all lie in the ball lies in it (both convex): the cell
+    // has no spherical part (K = 0 exactly, not the difference 4 pi - sum of solid
+    // angles) and V is the pyramid sum alone
+    R v2max = R(0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        if (tri[k] != TRI_INVALID) v2max = fmax(v2max, vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v2max = fmax(v2max, __shfl_xor(v2max, o, 64));
+    const bool in_ball = v2max < r * r;
     // per facet: sum its pieces in walk order from its lowest slot
-    double sum_tA = 0.0, sum_om = 0.0;
+    double sum_tA = 0.0, sum_om = 0.0, sum_tA_abs = 0.0;
     if (live) {
         for (int p = gl; p < np; p += G) {
             R Af = 0, Of = 0;
@@ -774,6 +920,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 } while (sv != s0);
                 const R t = S.pl[p][3];
                 sum_tA += (double)t * (double)Af;
+                sum_tA_abs += fabs((double)t * (double)Af);
                 sum_om += (t >= R(0)) ? (double)Of : -(double)Of;
             }
             GT.farea[p] = Af;
@@ -784,12 +931,17 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         live = false;
     }
     sum_tA = gsum<G>(sum_tA);
+    sum_tA_abs = gsum<G>(sum_tA_abs);
     sum_om = gsum<G>(sum_om);
     __syncthreads();
 
     // ---------------- outputs ----------------
     if (!act) return;
     const EvalOut &o = A.out;
+    if (deferred) {
+        if (gl == 0) o.ovf_list[atomicAdd(o.ovf_count, 1)] = (int32_t)cell;
+        return;
+    }
     int nf = 0;
     if (live) {
         for (int p = gl; p - gl < np; p += G) {
@@ -821,17 +973,20 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         double V = 0.0, K = 0.0;
         if (live) {
             const double rd = (double)r;
-            K = rd * rd * (4.0 * PI_D * (inside ? 1.0 : 0.0) - sum_om);
+            K = in_ball ? 0.0 : rd * rd * (4.0 * PI_D * (inside ? 1.0 : 0.0) - sum_om);
             V = (sum_tA + rd * K) / 3.0;
             if (!(V == V) || !(K == K)) flags |= CF_TOPO;
         }
-        // a cell much smaller than its ball is a difference of large pyramid terms:
-        // float32 would lose the relative accuracy, so it is redone in float64
-        if (fast && live && V < 0.05 * (4.0 / 3.0) * PI_D * (double)r * (double)r * (double)r) flags |= CF_PREC;
+        // a cell much smaller than its terms is a difference of large ones (with a
+        // spherical part: of the ball's size; without: pyramids from a site far from its
+        // cell): float32 would lose the relative accuracy, so it is redone in float64
+        const double scale = in_ball ? sum_tA_abs / 3.0 : (4.0 / 3.0) * PI_D * (double)r * (double)r * (double)r;
+        if (fast && sizeof(R) == 4 && live && V < 0.05 * scale) flags |= CF_PREC;
         o.V[cell] = V;
         o.K[cell] = K;
         o.fcnt[cell] = live ? nf : 0;
-        o.flags[cell] = flags;
+        // the float64 pass keeps the float32 pass's reasons in bits 8..15
+        o.flags[cell] = fast ? flags : (flags | (o.flags[cell] << 8));
         if (fast && (flags & (CF_FAIL_MASK | CF_PREC))) {
             const int slot = atomicAdd(o.fb_count, 1);
             o.fb_list[slot] = (int32_t)cell;
@@ -848,7 +1003,22 @@ __global__ __launch_bounds__(64) void k_cells_fast(CellArgs A) {
     const int gi = (int)(threadIdx.x / G);
     int64_t cell = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * (64 / G) + gi;
     if (cell >= A.n || !selected(A.bt, A.want, A.bt.inst[cell])) cell = -1;
-    cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX>(cell, A, smem[gi], true);
+    cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX, 0>(cell, A, smem[gi]);
+}
+
+// Cells deferred by the fast pass (more candidates than it holds), one per wavefront,
+// with the threshold ladder and clip rounds, in float64: such cells come from crowded
+// regions with large weights, where a site can sit well outside its own cell and the
+// pyramid terms of float32 coordinates cancel. The list length is read on the device
+// and the blocks stride over it.
+__global__ __launch_bounds__(64) void k_cells_overflow(CellArgs A) {
+    __shared__ CellSmem<double, OVF_CMAX, OVF_PMAX, OVF_VMAX> smem[1];
+    const int count = *A.out.ovf_count;
+    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+        const int64_t cell = A.out.ovf_list[k];
+        cell_body<double, 64, OVF_CMAX, OVF_PMAX, OVF_VMAX, 1>(cell, A, smem[0]);
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
@@ -856,15 +1026,18 @@ __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
     const int count = *A.out.fb_count;
     for (int k = blockIdx.x; k < count; k += gridDim.x) {
         const int64_t cell = A.out.fb_list[k];
-        cell_body<double, 64, BIG_CMAX, BIG_PMAX, BIG_VMAX>(cell, A, smem[0], false);
+        cell_body<double, 64, BIG_CMAX, BIG_PMAX, BIG_VMAX, 2>(cell, A, smem[0]);
         __syncthreads();
     }
 }
 
-// Clears the per-evaluation counters: the float64 work list and the failure
-// counts of the selected instances (a kernel, so the sequence can be captured).
+// Clears the per-evaluation counters: the overflow and float64 work lists and the
+// failure counts of the selected instances (a kernel, so the sequence can be captured).
 __global__ __launch_bounds__(1024) void k_eval_begin(Batch bt, int want, EvalOut o) {
-    if (threadIdx.x == 0) *o.fb_count = 0;
+    if (threadIdx.x == 0) {
+        *o.fb_count = 0;
+        *o.ovf_count = 0;
+    }
     for (int b = threadIdx.x; b < bt.B; b += 1024)
         if (selected(bt, want, b)) o.fail_inst[b] = 0;
 }
@@ -889,12 +1062,14 @@ void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const fl
     }
 }
 
-// The float64 path takes the cells listed by the float32 pass (all of them from
-// selected instances); it reads the list length on the device.
+// The overflow pass takes the cells deferred by the fast pass, and the float64 pass
+// the cells listed by both float32 passes (all of them from selected instances); they
+// read the list lengths on the device.
 void launch_cells_fallback(hipStream_t st, const Batch &bt, const float4 *pos_s, const double *psi,
                            const int32_t *perm, const int32_t *cell_start, EvalOut out) {
     CellArgs a{0, pos_s, psi, perm, cell_start, bt, -1, out};
-    hipLaunchKernelGGL(k_cells_big, dim3(512), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_cells_overflow, dim3(4096), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_cells_big, dim3(2048), dim3(64), 0, st, a);
 }
 
 }  // namespace lagot

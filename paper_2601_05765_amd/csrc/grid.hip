@@ -271,31 +271,38 @@ __global__ void k_scatter_walls(int64_t n, const int32_t *__restrict__ perm, con
     for (int a = 0; a < 6; ++a) w[i * 6 + a] = ws[k * 6 + a];
 }
 
-// default start weights of the selected instances: ball radius 1.2 (3 nu / 4 pi)^(1/3)
-__global__ __launch_bounds__(TILE) void k_default_start(Batch bt, int want, const double *__restrict__ nu,
+// Default start weights of the selected instances: one common weight per instance,
+// the square of 1.2 (3 nu_mean / 4 pi)^(1/3). With equal weights the power diagram is
+// the Voronoi diagram, whose cells contain their sites, so no start cell is empty
+// (exactly coincident sites aside); per-site radii from nu_i can swallow a light site
+// next to a heavy one in a crowded region. ev_nu[4b] holds the instance's sum of nu.
+__global__ __launch_bounds__(TILE) void k_default_start(Batch bt, int want, const double *__restrict__ ev_nu,
                                                          double *__restrict__ psi, float4 *__restrict__ pos) {
     const int t = blockIdx.x;
     const int b = bt.tile_inst[t];
     if (!selected(bt, want, b)) return;
     const int i = bt.tile_row[t] + (int)threadIdx.x;
     if (i >= bt.off[b + 1]) return;
-    const double r = 1.2 * cbrt(3.0 * nu[i] / (4.0 * 3.14159265358979323846));
+    const double nu_mean = ev_nu[4 * b] / (double)(bt.off[b + 1] - bt.off[b]);
+    const double r = 1.2 * cbrt(3.0 * nu_mean / (4.0 * 3.14159265358979323846));
     psi[i] = r * r;
     pos[i].w = (float)(r * r);
 }
 
-// A start cell that is empty gets the smallest weight that puts its site inside
-// every power half-space: with psi_i >= psi_j - d_ij^2 for all j, every bisector has
-// t_ij >= 0, so p_i lies in C_i and the cell is not empty; at equality the nearest
-// bisector passes through p_i and the neighbour keeps t_ji = d_ij > 0, so nearly
-// coincident pairs keep both cells. New weight: max(psi_i, max_j (psi_j - d_ij^2))
-// (the default weight if that is not positive), capped at twice the larger of the
-// default weight and the mean weight of the sites searched (a neighbour much heavier
-// than its surroundings is left to the full restart). Only sites within
-// 2 max(r_max, r_i) can matter (farther bisectors miss the ball). The other weights
-// keep the warm start. One thread per row; weights are read from psi and written to
-// psi_out (every row: a copy where nothing changes), so the result does not depend
-// on the order in which rows are repaired.
+// A start cell that is empty gets a weight that puts its site strictly inside every
+// power half-space. Let j* maximise psi_j - d_ij^2 over the other sites (value L).
+// With w = psi_j*, every bisector has t_ij = (d_ij^2 + w - psi_j) / (2 d_ij) > 0
+// (psi_j - d_ij^2 <= L < w), and the bisector with j* is the mid-plane, so the cell
+// gets a share of the space between the two sites, not a sliver. A neighbour k keeps
+// its own site only while w < psi_k + d_ik^2 (minimum U over the sites searched);
+// if psi_j* >= U the weight falls back to (L + U) / 2 when U > L, else to L (the
+// nearest bisector then passes through p_i). The result is at least psi_i, the
+// default weight if not positive, and at most twice the larger of the default weight
+// and the mean weight of the sites searched (a neighbour much heavier than its
+// surroundings is left to the full restart). Only sites within 2 r_max can swallow
+// p_i or be swallowed. The other weights keep the warm start. One thread per row;
+// weights are read from psi and written to psi_out (every row: a copy where nothing
+// changes), so the result does not depend on the order in which rows are repaired.
 __global__ __launch_bounds__(TILE) void k_repair_empty(Batch bt, int want, const double *__restrict__ V,
                                                         const double *__restrict__ nu, const int32_t *__restrict__ cell_start,
                                                         const double *__restrict__ psi, double *__restrict__ psi_out,
@@ -319,7 +326,7 @@ __global__ __launch_bounds__(TILE) void k_repair_empty(Batch bt, int want, const
         lo3[a] = max((int)floorf((pp[a] - reach - g.lo[a]) * g.inv_s), 0);
         hi3[a] = min((int)floorf((pp[a] + reach - g.lo[a]) * g.inv_s), g.dim[a] - 1);
     }
-    double m = -1e300, wsum = 0.0;
+    double m = -1e300, wstar = 0.0, u = 1e300, wsum = 0.0;
     int wn = 0;
     for (int ix = lo3[0]; ix <= hi3[0]; ++ix)
         for (int iy = lo3[1]; iy <= hi3[1]; ++iy) {
@@ -329,13 +336,19 @@ __global__ __launch_bounds__(TILE) void k_repair_empty(Batch bt, int want, const
                 if (j == i) continue;
                 const float4 q = pos[j];  // x, y, z only (.w of repaired rows changes)
                 const double dx = (double)q.x - pi.x, dy = (double)q.y - pi.y, dz = (double)q.z - pi.z;
-                m = fmax(m, psi[j] - (dx * dx + dy * dy + dz * dz));
-                wsum += psi[j];
+                const double pj = psi[j], d2 = dx * dx + dy * dy + dz * dz;
+                if (pj - d2 > m) {
+                    m = pj - d2;
+                    wstar = pj;
+                }
+                u = fmin(u, pj + d2);
+                wsum += pj;
                 ++wn;
             }
         }
     const double cap = fmax(p0, 2.0 * fmax(rd2, wn > 0 ? wsum / wn : 0.0));
-    double w = fmax(p0, m);
+    double w = p0;
+    if (m > p0) w = wstar < u ? wstar : (u > m ? 0.5 * (m + u) : m);
     if (!(w > 0.0)) w = rd2;
     w = fmin(w, cap);
     psi_out[i] = w;
@@ -356,9 +369,9 @@ inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *nu_s, double *psi_s,
+void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *ev_nu, double *psi_s,
                           float4 *pos_s) {
-    hipLaunchKernelGGL(k_default_start, dim3(bt.T), dim3(TILE), 0, st, bt, want, nu_s, psi_s, pos_s);
+    hipLaunchKernelGGL(k_default_start, dim3(bt.T), dim3(TILE), 0, st, bt, want, ev_nu, psi_s, pos_s);
 }
 
 void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu_s,

@@ -24,6 +24,10 @@ constexpr int FAST_VMAX = 64;   // polytope vertices (triangles of the dual)
 constexpr int BIG_CMAX = 256;
 constexpr int BIG_PMAX = 64;
 constexpr int BIG_VMAX = 128;
+constexpr int OVF_CMAX = 96;     // float32 path for cells with more candidates than FAST_CMAX
+constexpr int OVF_PMAX = 64;
+constexpr int OVF_VMAX = 128;
+constexpr int OVERFLOW_ROUNDS = 8;  // clip rounds for cells with more candidates than CMAX
 
 // Per-cell status bits written by the cell kernel.
 enum CellFlag : uint32_t {
@@ -137,6 +141,8 @@ struct EvalOut {
     int32_t *fb_count;// [1] length of fb_list (device counter)
     int32_t *fb_inst; // [B] cells sent to the float64 path, per instance (accumulates over a call)
     int32_t *fail_inst; // [B] cells that failed the float64 path too, per instance (per evaluation)
+    int32_t *ovf_list;  // [n] cells with more candidates than the fast kernel holds
+    int32_t *ovf_count; // [1] length of ovf_list (device counter)
 };
 
 // Conjugate-gradient vectors and scalars (Chronopoulos-Gear form, one kernel per
@@ -181,7 +187,7 @@ void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32
                      const int32_t *fcnt, const int32_t *start, int32_t *col, float *area, int64_t *row_ptr);
 void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const float *wall_s, float *wall);
 void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t *perm, const void *src, void *dst);
-void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *nu_s, double *psi_s,
+void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *ev_nu, double *psi_s,
                           float4 *pos_s);
 // psi_out = psi_s, except that empty cells (V <= 0) of the selected instances get
 // max(psi, default weight, weights of the neighbours whose power region contains the ball)

@@ -106,6 +106,8 @@ def dam_break(n: int = 100_000, seed: int = 0, fill: float = 0.4, total: float =
 
 def _sphere_points(rng, centre, R, count, jitter=0.3):
     """``count`` points of a jittered lattice closest to ``centre`` (spacing fit to the ball)."""
+    if count <= 0:
+        return np.zeros((0, 3))
     vol = 4.0 / 3.0 * math.pi * R ** 3
     s = (vol / count) ** (1.0 / 3.0)
     for _ in range(200):
@@ -153,7 +155,11 @@ def splash(n: int = 2_000_000, seed: int = 0, n_spheres: int = 200, slab_frac: f
     nu = rng.lognormal(0.0, 0.2, size=n)
     nu *= total / nu.sum()
     vel = rng.normal(0.0, 0.5, size=(n, 3))
-    return Scene("splash", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, default_psi0(nu), vel=vel,
+    # start weights: one common weight (a Voronoi start). Per-site radii from the
+    # log-normal nu leave light sites swallowed by heavy neighbours in the crowded
+    # spheres (empty or near-empty start cells, so a KMT floor near zero).
+    psi0 = np.full(n, default_psi0(np.array([nu.mean()]))[0])
+    return Scene("splash", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, psi0, vel=vel,
                  meta={"seed": seed, "n": n, "n_slab": n_slab, "spheres": len(centres)})
 
 

@@ -169,5 +169,5 @@ def test_overpacked_sphere_cells(ctx, oracle_mod, overpacked, tpc):
         ctx.set_threads_per_cell(32)
     _say(f"  oracle candidates per cell: median {int(np.median(c.ncand))} max {int(c.ncand.max())}")
     rep = compare(out, c, psi)
-    _say(f"  {rep} fallback {ctx.last_fallback_cells()}")
+    _say(f"  {rep} fallback {ctx.last_fallback_cells()} flags {ctx.last_flag_counts()}")
     assert_close(rep)
