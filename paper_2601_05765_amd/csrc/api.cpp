@@ -964,9 +964,11 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
                 rc = sync(c);
                 if (rc) return fail_all(rc);
                 fprintf(stderr,
-                        "  inst 0: alpha %.3g |g| %.3e maxrel %.3e minV %.3e evals %d halvings %d cg %d "
-                        "fallback %d failed (last evaluation) %d r_max %.4g cell kernel %.1f ms\n",
-                        q.alpha, q.gnorm, q.maxrel, q.minV, q.evals, q.halvings, q.cg_iters, fb, fl, rm, c->ms_cell);
+                        "  inst 0: alpha %.3g |g| %.3e maxrel %.3e minV %.3e eps0 %.3e evals %d halvings %d cg %d "
+                        "fallback %d failed (last evaluation) %d r_max %.4g cell kernel %.1f ms; last trial: "
+                        "minV %.3e |g| %.3e\n",
+                        q.alpha, q.gnorm, q.maxrel, q.minV, q.eps0, q.evals, q.halvings, q.cg_iters, fb, fl, rm, c->ms_cell,
+                        q.tminV, q.tgnorm);
             }
         }
     }

@@ -116,6 +116,8 @@ struct InstCtl {
     double maxrel;     // max |V - nu| / nu at the accepted iterate
     double minV;       // min V at the accepted iterate
     double sumV;       // sum V at the accepted iterate
+    double tminV;      // min V and ||nu - V||_2 at the last step-size trial (diagnostic)
+    double tgnorm;
     int iters, evals, halvings, hstep, cg_iters, status, default_start, learned;
     int restore;       // the float32 shadow must be reset to the accepted weights
     int repaired;      // empty start cells were given the default weight

@@ -607,6 +607,8 @@ __global__ __launch_bounds__(1024) void k_ctl_decide(Batch bt, CtlOpts o, const 
         InstCtl &c = ctl[b];
         c.evals += 1;
         const double sumV = ev[4 * b + 0], maxrel = ev[4 * b + 1], gnorm = ev[4 * b + 2], minV = ev[4 * b + 3];
+        c.tminV = minV;
+        c.tgnorm = gnorm;
         if (fail_inst[b] == 0 && minV >= c.eps0 && gnorm <= (1.0 - 0.5 * c.alpha) * c.gnorm) {
             c.sumV = sumV;
             c.maxrel = maxrel;
