@@ -196,8 +196,8 @@ def main(argv=None):
     ap.add_argument("--sequence-steps", type=int, default=5)
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded design is described in "
-              f"DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
+              f"built", file=sys.stderr)
         return 2
 
     import torch

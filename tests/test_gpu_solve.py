@@ -162,6 +162,25 @@ def test_solve_overpacked_sphere(ctx, oracle_mod):
     assert _oracle_err(oracle_mod, sc, psi.cpu().numpy()) <= 1e-5
 
 
+def test_solve_splash_200k(ctx, oracle_mod):
+    """The splash recipe at 200,000 sites: 200 droplets packed 1.72x next to a 0.9-full slab,
+    log-normal nu, Voronoi start. Cells with thousands of candidates go through the overflow
+    pass; the FP64 oracle takes 9 Newton iterations and 17 evaluations on this problem."""
+    _say("case: solve splash 200k (over-packed droplets, overflow pass)")
+    import paper_2601_05765_amd as L
+    sc = scenes.splash(200_000, 0)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    _say(f"  {st.as_dict()} flags {ctx.last_flag_counts()}")
+    assert st.status == 0 and st.max_rel_err <= 1e-5
+    assert st.newton_iters <= 12
+    p = psi.cpu().numpy()
+    rng = np.random.default_rng(2)
+    # the most crowded droplet sites (largest weights) and a random sample
+    idx = np.unique(np.concatenate([np.argsort(-p)[:100], rng.choice(sc.n, 200, replace=False)]))
+    assert _oracle_err(oracle_mod, sc, p, idx=idx) <= 1e-5
+
+
 def test_error_codes(ctx):
     _say("case: error codes")
     import torch
