@@ -5,8 +5,9 @@ TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
 with the HIP path.
 
 Contents
-  cells(...)          restricted cell volumes, spherical areas, facet areas
-                      (C routine in lagot_oracle.c; eq. (1), section 3.2, 3.3, Alg. 2)
+  cells(...)          restricted cell volumes, spherical areas, facet areas, centroids
+                      (C routine in lagot_oracle.c; eq. (1), section 3.2, 3.3, Alg. 2;
+                      centroids: the cell centroid of the pressure model, section 5)
   hessian(...)        gradient nu - V and the sparse matrix -Hess K (eq. (2))
   newton_solve(...)   damped Newton with KMT step control (Alg. 1)
 Parity pins for every function live in tests/test_oracle_*.py.
@@ -44,7 +45,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.oracle_cells.argtypes = [ctypes.c_long, P, P, P, P, P, P, ctypes.c_long, P, P, P, P, P, ctypes.c_int,
-                                     P, P, P, ctypes.c_int, P]
+                                     P, P, P, ctypes.c_int, P, P]
         lib.oracle_cells.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -71,6 +72,7 @@ class Cells:
     status: np.ndarray       # [m] 0 ok, 1 empty, 2 facet capacity exceeded
     idx: np.ndarray          # [m] evaluated site indices
     work: np.ndarray | None = None  # [m,6] work units (see lagot_oracle.c) when requested
+    C: np.ndarray | None = None     # [m,3] centroids (the site itself for an empty cell)
 
     def facets(self, c: int) -> dict:
         k = int(self.fcount[c])
@@ -107,12 +109,13 @@ def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, th
     nc = np.zeros(m, np.int32)
     st = np.zeros(m, np.int32)
     wk = np.zeros((m, 6), np.int64) if work else None
+    C = np.zeros((m, 3))
     lib.oracle_cells(n, _ptr(x), _ptr(y), _ptr(z), _ptr(psi), _ptr(b), idx_p, m, _ptr(V), _ptr(K), _ptr(W),
                      _ptr(fj), _ptr(fA), fcap, _ptr(fc), _ptr(nc), _ptr(st), int(threads),
-                     _ptr(wk) if work else None)
+                     _ptr(wk) if work else None, _ptr(C))
     if (st == 2).any():
         raise RuntimeError("oracle facet capacity exceeded; raise fcap")
-    return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr, wk)
+    return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr, wk, C)
 
 
 def hessian(xyz: np.ndarray, psi: np.ndarray, c: Cells):

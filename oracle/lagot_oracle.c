@@ -246,6 +246,7 @@ static void poly_clip(opoly *P, const oplane *pl, int pidx)
 typedef struct {
     double area;  /* planar area of the restricted facet              */
     double omega; /* solid angle it subtends at p_i (sign of orientation only) */
+    double m[3];  /* first moment of the restricted facet about its disk centre q */
 } fanacc;
 
 /* circular sector of the disk between in-plane directions u and v */
@@ -256,6 +257,15 @@ static void fan_sector(const double *u, const double *v, const double *n, double
     double phi = atan2(dot3(n, c), dot3(u, v));
     acc->area += 0.5 * rho2 * phi;
     acc->omega += phi * (1.0 - h / r);
+    /* first moment of the sector: with a the unit direction of u and b = n x a, the
+       integral of (rho' cos s a + rho' sin s b) rho' drho' ds over [0, rho] x [0, phi] */
+    double lu = sqrt(dot3(u, u));
+    if (lu > 0.0) {
+        double a[3] = {u[0] / lu, u[1] / lu, u[2] / lu}, b[3];
+        cross3(n, a, b);
+        double k = rho2 * sqrt(rho2) / 3.0, sp = sin(phi), cp = 1.0 - cos(phi);
+        for (int j = 0; j < 3; ++j) acc->m[j] += k * (a[j] * sp + b[j] * cp);
+    }
 }
 
 /* triangle (q, q+A, q+B) fully inside the disk */
@@ -265,6 +275,8 @@ static void fan_triangle(const double *A, const double *B, const double *n, doub
     cross3(A, B, c);
     double s = dot3(n, c);
     acc->area += 0.5 * s;
+    /* first moment of the triangle (0, A, B): its signed area times its centroid (A + B) / 3 */
+    for (int j = 0; j < 3; ++j) acc->m[j] += 0.5 * s * (A[j] + B[j]) / 3.0;
     double la = sqrt(dot3(A, A) + h * h), lb = sqrt(dot3(B, B) + h * h);
     /* Van Oosterom-Strackee solid angle of the triangle with apex at height h above q */
     acc->omega += 2.0 * atan2(s, la * lb + h * (la + lb) + h * h + dot3(A, B));
@@ -304,7 +316,7 @@ static void fan_piece(const double *u, const double *v, const double *n, double 
 
 static fanacc restrict_face(const oface *f, const oplane *pl, double r)
 {
-    fanacc acc = {0.0, 0.0};
+    fanacc acc = {0.0, 0.0, {0.0, 0.0, 0.0}};
     double t = pl->t, h = fabs(t);
     double rho2 = (r - t) * (r + t);
     if (!(rho2 > 0.0)) return acc;
@@ -334,10 +346,13 @@ static int cmp_plane_t(const void *a, const void *b)
  */
 static int oracle_cell(long i, long n, const double *x, const double *y, const double *z, const double *psi,
                        const double *box, double *V, double *K, double *wall, long *fj, double *fA, int fcap,
-                       int *fcount, int *ncand)
+                       int *fcount, int *ncand, double *cen)
 {
     *V = 0.0;
     *K = 0.0;
+    cen[0] = x[i];
+    cen[1] = y[i];
+    cen[2] = z[i];
     for (int k = 0; k < 6; ++k) wall[k] = 0.0;
     *fcount = 0;
     *ncand = 0;
@@ -432,7 +447,12 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
         if (P.nf == 0) break;
     }
 
-    double sumTA = 0.0, sumOm = 0.0;
+    /* First moment about p_i (the centroid the pressure model of section 5 uses), by the
+       divergence theorem applied to the fields x_k x (divergence 4 x_k):
+       4 * integral of x dV = surface integral of x (x.n) dA. On a facet x.n = t and the
+       facet's moment is q area + m (q = t n); on the sphere x.n = r and x = r n, whose
+       area integral is -sum_f n_f area_f (a closed surface has zero vector area). */
+    double sumTA = 0.0, sumOm = 0.0, mom[3] = {0.0, 0.0, 0.0};
     int nf = 0;
     for (int k = 0; k < P.nf; ++k) {
         const oface *f = &P.f[k];
@@ -442,6 +462,8 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
         fanacc a = restrict_face(f, p, r);
         sumTA += p->t * a.area;
         sumOm += (p->t >= 0.0 ? 1.0 : -1.0) * a.omega;
+        for (int j = 0; j < 3; ++j)
+            mom[j] += p->t * (p->t * p->n[j] * a.area + a.m[j]) - r * r * p->n[j] * a.area;
         if (p->id < 0) {
             wall[-1 - p->id] = a.area;
         } else if (a.area > 0.0) {
@@ -459,6 +481,11 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
     }
     *K = r * r * (4.0 * OR_PI * inside - sumOm);
     *V = (sumTA + r * (*K)) / 3.0;
+    if (*V > 0.0) {
+        cen[0] = pi3[0] + 0.25 * mom[0] / *V;
+        cen[1] = pi3[1] + 0.25 * mom[1] / *V;
+        cen[2] = pi3[2] + 0.25 * mom[2] / *V;
+    }
     *fcount = nf;
     return nf > fcap ? OR_FACET_CAP : OR_OK;
 }
@@ -466,12 +493,13 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
 /*
  * Evaluate m cells (indices idx[0..m), or all n cells when idx == NULL).
  * Per evaluated cell c: V[c], K[c], wall[6c..6c+6), facets fj/fA[c*fcap ..],
- * fcount[c], ncand[c], status[c], and when work != NULL the six work units of
- * each cell at work[6c..6c+6). OpenMP over cells.
+ * fcount[c], ncand[c], status[c], the centroid cen[3c..3c+3) (the site itself for an
+ * empty cell), and when work != NULL the six work units of each cell at
+ * work[6c..6c+6). OpenMP over cells.
  */
 int oracle_cells(long n, const double *x, const double *y, const double *z, const double *psi,
                  const double *box, const long *idx, long m, double *V, double *K, double *wall, long *fj,
-                 double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads, long *work)
+                 double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads, long *work, double *cen)
 {
     long cnt = idx ? m : n;
 #ifdef _OPENMP
@@ -486,7 +514,7 @@ int oracle_cells(long n, const double *x, const double *y, const double *z, cons
         if (g_work)
             for (int k = 0; k < W_N; ++k) g_work[k] = 0;
         status[c] = oracle_cell(i, n, x, y, z, psi, box, &V[c], &K[c], &wall[6 * c], &fj[(size_t)c * fcap],
-                                &fA[(size_t)c * fcap], fcap, &fcount[c], &ncand[c]);
+                                &fA[(size_t)c * fcap], fcap, &fcount[c], &ncand[c], &cen[3 * c]);
     }
     return 0;
 }
