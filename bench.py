@@ -235,18 +235,25 @@ def main(argv=None):
     ms_kernel = sum(s.ms_cell_kernel for s in stats) / max(launches, 1)
     s0 = stats[-1]
 
-    # evaluation alone (lagot_cells at the start weights: validation, grid build, cells, outputs)
-    ev_ms = []
-    k_ms = []
-    for _ in range(3):
-        ctx.cells(x, y, z, psi0, csr=False, walls=False)
-    torch.cuda.synchronize()
-    for _ in range(args.eval_reps):
-        a = time.perf_counter()
-        ctx.cells(x, y, z, psi0, csr=False, walls=False)
+    # evaluation alone (lagot_cells: validation, grid build, cells, outputs), at the start
+    # weights and at the converged ones; and with centroids (lagot_centroids)
+    def eval_times(psi_eval, fn):
+        for _ in range(3):
+            fn(psi_eval)
         torch.cuda.synchronize()
-        ev_ms.append(1000.0 * (time.perf_counter() - a))
-        k_ms.append(ctx.last_cell_kernel_ms())
+        ev, kk = [], []
+        for _ in range(args.eval_reps):
+            a = time.perf_counter()
+            fn(psi_eval)
+            torch.cuda.synchronize()
+            ev.append(1000.0 * (time.perf_counter() - a))
+            kk.append(ctx.last_cell_kernel_ms())
+        return float(np.median(ev)), float(np.median(kk))
+
+    cells_fn = lambda p: ctx.cells(x, y, z, p, csr=False, walls=False)
+    ev0, k0 = eval_times(psi0, cells_fn)
+    ev1, k1 = eval_times(psis[-1], cells_fn)
+    evc, kc = eval_times(psis[-1], lambda p: ctx.centroids(x, y, z, p))
 
     line = {
         "metric": "cells/s (Laguerre∩ball eval); ms per OT solve to 1e-5 vol err, plain vs learned",
@@ -267,9 +274,13 @@ def main(argv=None):
         "solve": {"ms_per_solve_plain": ms_per_step, "newton_iters": s0.newton_iters, "evals": s0.evals,
                   "halvings": s0.halvings, "cg_iters": s0.cg_iters, "max_rel_err": s0.max_rel_err,
                   "fallback_cells": s0.fallback_cells, "ms_eval": s0.ms_eval, "ms_linear": s0.ms_linear},
-        "eval_only": {"cells_per_s_with_grid": args.n / (float(np.median(ev_ms)) / 1000.0),
-                      "cells_per_s_kernel": args.n / (float(np.median(k_ms)) / 1000.0),
-                      "ms_lagot_cells": float(np.median(ev_ms)), "ms_cell_kernel": float(np.median(k_ms))},
+        "eval_only": {"cells_per_s_with_grid": args.n / (ev0 / 1000.0), "cells_per_s_kernel": args.n / (k0 / 1000.0),
+                      "ms_lagot_cells": ev0, "ms_cell_kernel": k0,
+                      "converged": {"cells_per_s_with_grid": args.n / (ev1 / 1000.0),
+                                    "cells_per_s_kernel": args.n / (k1 / 1000.0), "ms_lagot_cells": ev1,
+                                    "ms_cell_kernel": k1},
+                      "centroids_converged": {"ms_lagot_centroids": evc, "ms_cell_kernel": kc,
+                                              "cells_per_s_kernel": args.n / (kc / 1000.0)}},
     }
     if not args.no_batched:
         line["batched"] = batched_section(ctx, L, scenes)
@@ -291,7 +302,7 @@ def main(argv=None):
         achieved = fpc * args.n / (ms_kernel / 1000.0) / 1e12
         line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
-                            "kernel": "k_cells_fast<32> (fused clip + ball integration, float32)",
+                            "kernel": "k_cells_fast<32, false> (fused clip + ball integration, float32)",
                             "flops_per_cell": fpc, "ms_per_launch": ms_kernel,
                             "work_units_per_cell": dict(zip(["cand", "tests", "newv", "faces", "edges", "cross"],
                                                             [float(v) for v in work_mean]))}

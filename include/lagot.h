@@ -142,6 +142,20 @@ int lagot_cells(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const
                 float *facet_area, int64_t nnz_cap, int64_t *nnz_out);
 
 /*
+ * One evaluation of all cells that also returns their centroids c_i = (1/|C_i|)
+ * integral over C_i of x dx, the cell centroid that the paper's pressure model pulls
+ * each site towards (section 5, "Incompressibility"). The first moment comes from the
+ * same facet fans as the volume (divergence theorem: 4 integral of x dV = surface
+ * integral of x (x.n) dA).
+ *   in : as lagot_cells; out: vol [n] float64, centroid [3n] float64 (x, y, z per site,
+ *        site-major; the site itself for an empty cell). Device pointers owned by the
+ *        caller. Synchronises the stream.
+ * Errors: as lagot_cells (LAGOT_EINVAL also for a NULL centroid).
+ */
+int lagot_centroids(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                    lagot_box box, double *vol, double *centroid);
+
+/*
  * One damped Newton iteration of Algorithm 1: evaluate the cells at psi, stop
  * if the tolerance already holds, else solve (-Hess K) u = nu - V by
  * Jacobi-PCG (eq. (2); walls do not enter) and halve the step from alpha = 1

@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_centroids", "lagot_last_cell_kernel_ms",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
@@ -96,6 +96,8 @@ def load():
         lib.lagot_set_threads_per_cell.restype = I
         lib.lagot_set_cg_shape.argtypes = [P, I, I]
         lib.lagot_set_cg_shape.restype = I
+        lib.lagot_centroids.argtypes = [P, I64, P, P, P, P, Box, P, P]
+        lib.lagot_centroids.restype = I
         lib.lagot_last_flag_counts.argtypes = [P, P]
         lib.lagot_last_flag_counts.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
@@ -208,6 +210,20 @@ class Context:
             out["row_ptr"], out["col"], out["area"] = rp, col[: nnz.value], fa[: nnz.value]
         out["nnz"] = int(nnz.value)
         return out
+
+    def centroids(self, x, y, z, psi, box=((0, 0, 0), (1, 1, 1))):
+        """lagot_centroids: (volumes [n], centroids [n, 3]) in caller order, float64."""
+        import torch
+        n = x.shape[0]
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(psi, torch.float64, "psi")]
+        vol = torch.empty(n, dtype=torch.float64, device=x.device)
+        cen = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        rc = load().lagot_centroids(self._h, n, *args, make_box(box), ctypes.c_void_p(vol.data_ptr()),
+                                    ctypes.c_void_p(cen.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_centroids")
+        return vol, cen
 
     def set_cg_shape(self, lanes_per_row: int, rows_per_block: int) -> None:
         rc = load().lagot_set_cg_shape(self._h, int(lanes_per_row), int(rows_per_block))

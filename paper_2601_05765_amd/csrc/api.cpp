@@ -80,6 +80,7 @@ struct lagot_ctx {
     double *V = nullptr, *K = nullptr;
     float *wall = nullptr;
     int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr, *ovf_list = nullptr;
+    double *cen_out = nullptr;  // caller's centroid array during a lagot_centroids call
     float *farea = nullptr;
     uint32_t *flags = nullptr;
     // second set of evaluation outputs (learned guess: evaluated aside, swapped in if kept)
@@ -481,7 +482,7 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
 
 EvalOut eval_out(lagot_ctx *c, bool walls) {
     EvalOut o{c->V, c->K, walls ? c->wall : nullptr, c->fcol, c->farea, c->fcnt, c->flags, c->fb_list, c->misc + 0,
-              c->fb_inst, c->fail_inst, c->ovf_list, c->misc + 4};
+              c->fb_inst, c->fail_inst, c->ovf_list, c->misc + 4, c->cen_out};
     return o;
 }
 
@@ -1088,6 +1089,16 @@ void lagot_destroy(lagot_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_all(ctx);
     delete ctx;
+}
+
+int lagot_centroids(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                    lagot_box box, double *vol, double *centroid) {
+    if (!c || !vol || !centroid || n <= 0) return LAGOT_EINVAL;
+    c->cen_out = centroid;
+    const int rc = lagot_cells(c, n, x, y, z, psi, box, vol, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                               nullptr);
+    c->cen_out = nullptr;
+    return rc;
 }
 
 int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,

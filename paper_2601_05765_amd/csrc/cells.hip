@@ -95,9 +95,24 @@ template <> __device__ inline double rcp_<double>(double v) { return 1.0 / v; }
 //     triangle (q, a, b) inside the disk (Van Oosterom-Strackee with the apex at h).
 //     The two sector angles are parts of one angle below pi, so they are summed as
 //     the argument of the product of their complex numbers (one atan2).
+// With MOM it also adds the piece's first moment about q (an in-plane vector) to
+// (Mx, My, Mz): a sector of radius rho from the unit direction e through the angle phi
+// has the moment rho^3/3 (e sin phi + (n x e)(1 - cos phi)), with sin and cos from the
+// normalised cross and dot products (no angle needed); a triangle (q, q+a, q+b) has its
+// signed area times (a + b)/3.
 template <typename R>
+__device__ inline void sector_moment(R ex, R ey, R ez, R cphi, R sphi, R nx, R ny, R nz, R k, R &Mx, R &My,
+                                     R &Mz) {
+    const R wx = ny * ez - nz * ey, wy = nz * ex - nx * ez, wz = nx * ey - ny * ex;
+    const R oc = R(1) - cphi;
+    Mx += k * (ex * sphi + wx * oc);
+    My += k * (ey * sphi + wy * oc);
+    Mz += k * (ez * sphi + wz * oc);
+}
+
+template <typename R, bool MOM = false>
 __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny, R nz, R rho2, R h, R cone, R &A,
-                                 R &Om) {
+                                 R &Om, R &Mx, R &My, R &Mz) {
     const R wx = vx - ux, wy = vy - uy, wz = vz - uz;
     const R a = dot3(wx, wy, wz, wx, wy, wz);
     if (!(a > R(0))) return;
@@ -114,9 +129,18 @@ __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny,
     const R half_rho2 = R(0.5) * rho2;
     if (!(lo < hi)) {
         const R cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
-        const R phi = atan2_<R>(dot3(nx, ny, nz, cx, cy, cz), dot3(ux, uy, uz, vx, vy, vz));
+        const R sn = dot3(nx, ny, nz, cx, cy, cz), cs = dot3(ux, uy, uz, vx, vy, vz);
+        const R phi = atan2_<R>(sn, cs);
         A += half_rho2 * phi;
         Om += cone * phi;
+        if constexpr (MOM) {
+            const R lu = sqrt(dot3(ux, uy, uz, ux, uy, uz)), luv = lu * sqrt(dot3(vx, vy, vz, vx, vy, vz));
+            if (luv > R(0)) {
+                const R il = rcp_<R>(lu), iuv = rcp_<R>(luv);
+                sector_moment<R>(ux * il, uy * il, uz * il, cs * iuv, sn * iuv, nx, ny, nz,
+                                 rho2 * sqrt(rho2) * R(1.0 / 3.0), Mx, My, Mz);
+            }
+        }
         return;
     }
     const R ax = ux + lo * wx, ay = uy + lo * wy, az = uz + lo * wz;
@@ -128,6 +152,21 @@ __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny,
     R s2 = nx * (by * vz - bz * vy) + ny * (bz * vx - bx * vz) + nz * (bx * vy - by * vx);
     if (c1 == R(0) && s1 == R(0)) c1 = R(1);
     if (c2 == R(0) && s2 == R(0)) c2 = R(1);
+    if constexpr (MOM) {
+        // sector (u, a) from the direction of u and sector (b, v) from the direction of b;
+        // a = u when u is inside the disk (and b = v when v is): angle 0, no moment
+        const R k = rho2 * sqrt(rho2) * R(1.0 / 3.0);
+        const R lu = sqrt(dot3(ux, uy, uz, ux, uy, uz)), la = sqrt(dot3(ax, ay, az, ax, ay, az));
+        const R lb = sqrt(dot3(bx, by, bz, bx, by, bz)), lv = sqrt(dot3(vx, vy, vz, vx, vy, vz));
+        if (lo > R(0) && lu * la > R(0)) {
+            const R il = rcp_<R>(lu), d = rcp_<R>(lu * la);
+            sector_moment<R>(ux * il, uy * il, uz * il, c1 * d, s1 * d, nx, ny, nz, k, Mx, My, Mz);
+        }
+        if (hi < R(1) && lb * lv > R(0)) {
+            const R il = rcp_<R>(lb), d = rcp_<R>(lb * lv);
+            sector_moment<R>(bx * il, by * il, bz * il, c2 * d, s2 * d, nx, ny, nz, k, Mx, My, Mz);
+        }
+    }
     const R phi = atan2_<R>(c1 * s2 + s1 * c2, c1 * c2 - s1 * s2);
     A += half_rho2 * phi;
     Om += cone * phi;
@@ -135,6 +174,12 @@ __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny,
     const R cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
     const R st = dot3(nx, ny, nz, cx, cy, cz);
     A += R(0.5) * st;
+    if constexpr (MOM) {
+        const R w = st * R(1.0 / 6.0);
+        Mx += w * (ax + bx);
+        My += w * (ay + by);
+        Mz += w * (az + bz);
+    }
     const R h2 = h * h;
     const R la = sqrt(dot3(ax, ay, az, ax, ay, az) + h2);
     const R lb = sqrt(dot3(bx, by, bz, bx, by, bz) + h2);
@@ -194,7 +239,7 @@ struct CellArgs {
     EvalOut out;
 };
 
-template <typename R, int G, int CMAX, int PMAX, int VMAX, int MODE>
+template <typename R, int G, int CMAX, int PMAX, int VMAX, int MODE, bool MOM>
 __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMAX, VMAX> &S) {
     // MODE 0: the fast pass (a cell with more than CMAX candidates is deferred to the
     // overflow list); 1: the overflow pass (threshold ladder and clip rounds); 2: the
@@ -840,9 +885,24 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
     }
     __syncthreads();
-    // the pieces, G at a time
+    // a polytope whose vertices all lie in the ball lies in it (both convex): the cell
+    // has no spherical part (K = 0 exactly, not the difference 4 pi - sum of solid
+    // angles) and V is the pyramid sum alone
+    R v2max = R(0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        if (tri[k] != TRI_INVALID) v2max = fmax(v2max, vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v2max = fmax(v2max, __shfl_xor(v2max, o, 64));
+    const bool in_ball = v2max < r * r;
+    // the pieces, G at a time; with MOM each lane also sums its pieces' share of the
+    // first moment: 4 integral of x dV = sum_f [t (t n A + m) - r^2 n A] over the facets
+    // (x.n = t on a facet, whose moment about p_i is t n A + m; on the sphere x.n = r and
+    // the vector area of the spherical part is -sum_f n A). In the ball the r^2 term is
+    // exactly zero (closed polytope) and is left out.
     constexpr int MAXR = 3 * NS;
     R pa[MAXR], po[MAXR];
+    double mom_x = 0.0, mom_y = 0.0, mom_z = 0.0;
     int pc[MAXR];
     bool walk_bad = false;
     const R cone_den = live ? R(1) / r : R(0);
@@ -867,8 +927,16 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 const R cone = R(1) - h * cone_den;
                 const R qx = t * nx, qy = t * ny, qz = t * nz;
                 const VRec<R> P = GT.rec[sv], Q = GT.rec[sn];
-                fan_piece<R>(P.x - qx, P.y - qy, P.z - qz, Q.x - qx, Q.y - qy, Q.z - qz, nx, ny, nz, rho2, h, cone,
-                             pa[rr], po[rr]);
+                R mx = R(0), my = R(0), mz = R(0);
+                fan_piece<R, MOM>(P.x - qx, P.y - qy, P.z - qz, Q.x - qx, Q.y - qy, Q.z - qz, nx, ny, nz, rho2, h,
+                                  cone, pa[rr], po[rr], mx, my, mz);
+                if constexpr (MOM) {
+                    const double td = (double)t, ar = (double)pa[rr];
+                    const double c2 = td * td - (in_ball ? 0.0 : (double)r * (double)r);
+                    mom_x += c2 * (double)nx * ar + td * (double)mx;
+                    mom_y += c2 * (double)ny * ar + td * (double)my;
+                    mom_z += c2 * (double)nz * ar + td * (double)mz;
+                }
             }
         }
     }
@@ -882,16 +950,6 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
     }
     __syncthreads();
-    // a polytope whose vertices all lie in the ball lies in it (both convex): the cell
-    // has no spherical part (K = 0 exactly, not the difference 4 pi - sum of solid
-    // angles) and V is the pyramid sum alone
-    R v2max = R(0);
-#pragma unroll
-    for (int k = 0; k < NS; ++k)
-        if (tri[k] != TRI_INVALID) v2max = fmax(v2max, vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v2max = fmax(v2max, __shfl_xor(v2max, o, 64));
-    const bool in_ball = v2max < r * r;
     // per facet: sum its pieces in walk order from its lowest slot
     double sum_tA = 0.0, sum_om = 0.0, sum_tA_abs = 0.0;
     if (live) {
@@ -932,6 +990,11 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     }
     sum_tA = gsum<G>(sum_tA);
     sum_tA_abs = gsum<G>(sum_tA_abs);
+    if constexpr (MOM) {
+        mom_x = gsum<G>(mom_x);
+        mom_y = gsum<G>(mom_y);
+        mom_z = gsum<G>(mom_z);
+    }
     sum_om = gsum<G>(sum_om);
     __syncthreads();
 
@@ -980,6 +1043,14 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         // a cell much smaller than its terms is a difference of large ones (with a
         // spherical part: of the ball's size; without: pyramids from a site far from its
         // cell): float32 would lose the relative accuracy, so it is redone in float64
+        if (MOM && o.cen) {
+            // centroid in caller order: the site plus the first moment over the volume
+            const int64_t ci = A.perm[cell];
+            const double f = V > 0.0 ? 0.25 / V : 0.0;
+            o.cen[3 * ci + 0] = (double)px + f * mom_x;
+            o.cen[3 * ci + 1] = (double)py + f * mom_y;
+            o.cen[3 * ci + 2] = (double)pz + f * mom_z;
+        }
         const double scale = in_ball ? sum_tA_abs / 3.0 : (4.0 / 3.0) * PI_D * (double)r * (double)r * (double)r;
         if (fast && sizeof(R) == 4 && live && V < 0.05 * scale) flags |= CF_PREC;
         o.V[cell] = V;
@@ -997,13 +1068,13 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     }
 }
 
-template <int G>
+template <int G, bool MOM>
 __global__ __launch_bounds__(64) void k_cells_fast(CellArgs A) {
     __shared__ CellSmem<float, FAST_CMAX, FAST_PMAX, FAST_VMAX> smem[64 / G];
     const int gi = (int)(threadIdx.x / G);
     int64_t cell = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * (64 / G) + gi;
     if (cell >= A.n || !selected(A.bt, A.want, A.bt.inst[cell])) cell = -1;
-    cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX, 0>(cell, A, smem[gi]);
+    cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX, 0, MOM>(cell, A, smem[gi]);
 }
 
 // Cells deferred by the fast pass (more candidates than it holds), one per wavefront,
@@ -1016,7 +1087,7 @@ __global__ __launch_bounds__(64) void k_cells_overflow(CellArgs A) {
     const int count = *A.out.ovf_count;
     for (int k = blockIdx.x; k < count; k += gridDim.x) {
         const int64_t cell = A.out.ovf_list[k];
-        cell_body<double, 64, OVF_CMAX, OVF_PMAX, OVF_VMAX, 1>(cell, A, smem[0]);
+        cell_body<double, 64, OVF_CMAX, OVF_PMAX, OVF_VMAX, 1, true>(cell, A, smem[0]);
         __syncthreads();
     }
 }
@@ -1026,7 +1097,7 @@ __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
     const int count = *A.out.fb_count;
     for (int k = blockIdx.x; k < count; k += gridDim.x) {
         const int64_t cell = A.out.fb_list[k];
-        cell_body<double, 64, BIG_CMAX, BIG_PMAX, BIG_VMAX, 2>(cell, A, smem[0]);
+        cell_body<double, 64, BIG_CMAX, BIG_PMAX, BIG_VMAX, 2, true>(cell, A, smem[0]);
         __syncthreads();
     }
 }
@@ -1051,14 +1122,16 @@ void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out) {
 void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s, const double *psi,
                   const int32_t *perm, const int32_t *cell_start, EvalOut out, int tpc) {
     CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out};
-    if (tpc == 8) {
-        hipLaunchKernelGGL(k_cells_fast<8>, dim3((unsigned)((n + 7) / 8)), dim3(64), 0, st, a);
+    if (out.cen) {  // centroids: one instantiation (32 lanes per cell)
+        hipLaunchKernelGGL((k_cells_fast<32, true>), dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, a);
+    } else if (tpc == 8) {
+        hipLaunchKernelGGL((k_cells_fast<8, false>), dim3((unsigned)((n + 7) / 8)), dim3(64), 0, st, a);
     } else if (tpc == 32) {
-        hipLaunchKernelGGL(k_cells_fast<32>, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_cells_fast<32, false>), dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, a);
     } else if (tpc == 64) {
-        hipLaunchKernelGGL(k_cells_fast<64>, dim3((unsigned)n), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_cells_fast<64, false>), dim3((unsigned)n), dim3(64), 0, st, a);
     } else {
-        hipLaunchKernelGGL(k_cells_fast<16>, dim3((unsigned)((n + 3) / 4)), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_cells_fast<16, false>), dim3((unsigned)((n + 3) / 4)), dim3(64), 0, st, a);
     }
 }
 

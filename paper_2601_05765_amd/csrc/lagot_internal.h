@@ -145,6 +145,7 @@ struct EvalOut {
     int32_t *fail_inst; // [B] cells that failed the float64 path too, per instance (per evaluation)
     int32_t *ovf_list;  // [n] cells with more candidates than the fast kernel holds
     int32_t *ovf_count; // [1] length of ovf_list (device counter)
+    double *cen;        // [3n] centroids in caller order (null: not computed)
 };
 
 // Conjugate-gradient vectors and scalars (Chronopoulos-Gear form, one kernel per

@@ -171,3 +171,70 @@ def test_overpacked_sphere_cells(ctx, oracle_mod, overpacked, tpc):
     rep = compare(out, c, psi)
     _say(f"  {rep} fallback {ctx.last_fallback_cells()} flags {ctx.last_flag_counts()}")
     assert_close(rep)
+
+
+def _centroid_err(ctx, oracle_mod, x, y, z, psi, idx=None, box=((0, 0, 0), (1, 1, 1))):
+    """max over non-empty cells of |c_gpu - c_oracle| / (r_i max(1, 1e-3 |B_i| / V_i)),
+    through lagot_centroids: the first moment V c is held to 1e-5 r max(V, 1e-3 |B_i|),
+    as volumes are to 1e-5 max(V, 1e-3 |B_i|) (a centroid of a vanishing cell is not
+    defined to any accuracy)."""
+    xd, yd, zd, pd = _dev((x, y, z), psi)
+    vol, cen = ctx.centroids(xd, yd, zd, pd, box=box)
+    c = oracle_mod.cells(np.float32(x), np.float32(y), np.float32(z), psi, idx=idx, box=box)
+    sel = c.idx
+    V = vol.cpu().numpy()[sel]
+    C = cen.cpu().numpy()[sel]
+    r = np.sqrt(np.maximum(psi[sel], 0.0))
+    live = c.V > 0
+    assert np.all((V > 0) == live)
+    # empty cells report the site itself
+    site = np.stack([np.float32(x)[sel], np.float32(y)[sel], np.float32(z)[sel]], 1).astype(np.float64)
+    assert np.allclose(C[~live], site[~live], atol=0)
+    if not live.any():
+        return 0.0
+    ball = 4.0 / 3.0 * math.pi * r ** 3
+    scale = r * np.maximum(1.0, 1e-3 * ball / np.maximum(c.V, 1e-300))
+    return float(np.max(np.linalg.norm(C[live] - c.C[live], axis=1) / scale[live]))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_centroids_random_small(ctx, oracle_mod, seed):
+    _say(f"case: centroids, random small seed={seed}")
+    sc = scenes.random_small(40, seed, r_lo=0.05, r_hi=0.2)
+    err = _centroid_err(ctx, oracle_mod, sc.x, sc.y, sc.z, sc.psi0)
+    _say(f"  max |dc|/r = {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_centroids_slab_1k_and_dam_break_sample(ctx, oracle_mod):
+    _say("case: centroids, slab 1k (all cells) and dam_break 100k (3000 sampled)")
+    sc = scenes.slab_uniform(1000, 2)
+    assert _centroid_err(ctx, oracle_mod, sc.x, sc.y, sc.z, sc.psi0) <= 1e-5
+    sc = scenes.dam_break(100_000, 0)
+    idx = np.sort(np.random.default_rng(4).choice(sc.n, 3000, replace=False))
+    err = _centroid_err(ctx, oracle_mod, sc.x, sc.y, sc.z, sc.psi0, idx=idx)
+    _say(f"  dam_break max |dc|/r = {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_centroids_overpacked_sphere(ctx, oracle_mod, overpacked):
+    _say("case: centroids of the over-packed sphere (overflow and float64 passes)")
+    sc, psi = overpacked
+    err = _centroid_err(ctx, oracle_mod, sc.x, sc.y, sc.z, psi)
+    _say(f"  max |dc|/r = {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_centroids_tile_the_box(ctx):
+    """Huge weights: the cells tile the box, so sum_i V_i c_i is its first moment."""
+    _say("case: centroids, box tiling invariant")
+    rng = np.random.default_rng(9)
+    n = 5000
+    P = rng.uniform(0.02, 0.98, size=(n, 3)).astype(np.float32)
+    psi = np.full(n, 0.05)
+    xd, yd, zd, pd = _dev((P[:, 0], P[:, 1], P[:, 2]), psi)
+    vol, cen = ctx.centroids(xd, yd, zd, pd)
+    V = vol.cpu().numpy()
+    C = cen.cpu().numpy()
+    assert V.sum() == pytest.approx(1.0, rel=1e-6)
+    assert np.allclose((V[:, None] * C).sum(0), [0.5, 0.5, 0.5], atol=2e-6)
