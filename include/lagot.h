@@ -63,7 +63,8 @@ typedef struct {
     int threads_per_cell;/* lanes per cell in the cell kernel: 0 = the context's default, else 8, 16,
                             32 or 64                                                             */
     int verbose;         /* 1: one line per Newton iteration to stderr; 2: also the first instance's
-                            step length, residuals, fallback count and r_max                     */
+                            step length, residuals, fallback count and r_max; 3: also every
+                            step-size trial of the first instance                                */
     int use_learned;     /* 1: try the learned warm start (lagot_mlp_set_params) before Newton       */
     int empty_start_fallback; /* 1 (default): if a start cell is empty (KMT needs eps0 > 0), give
                             each empty cell the weight of the neighbour j* that swallows its site
@@ -81,7 +82,9 @@ typedef struct {
                             call and replay them; the call then runs on a private stream of the
                             context, ordered after earlier work on the context's stream. Results
                             are identical to eager launches (default 0)                         */
-    int reserved[1];
+    int residual_test;   /* 1 (default): a step size is kept only if min V >= eps0 and
+                            ||nu - V||_2 drops by the factor (1 - alpha/2) (the KMT method the paper
+                            cites); 0: the min-volume test alone, as Algorithm 1 prints it          */
 } lagot_opts;
 
 typedef struct {

@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_newton", ctypes.c_int), ("max_halvings", ctypes.c_int),
                 ("cg_rtol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("threads_per_cell", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("use_learned", ctypes.c_int), ("empty_start_fallback", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
+                ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("residual_test", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -594,6 +594,7 @@ void fill_defaults(lagot_opts *o) {
     o->use_learned = 0;
     o->empty_start_fallback = 1;
     o->autotune = 0;
+    o->residual_test = 1;
 }
 
 bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
@@ -879,7 +880,8 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     }
     const Batch bt = batch(c);
     hipStream_t st = c->stream;
-    CtlOpts co{o.tol, o.max_newton, o.max_halvings, single ? 1 : 0, o.empty_start_fallback ? 1 : 0};
+    CtlOpts co{o.tol, o.max_newton, o.max_halvings, single ? 1 : 0, o.empty_start_fallback ? 1 : 0,
+               o.residual_test ? 1 : 0};
     CallTimes tm;
     int learned = 0;
     launch_zero_i32(st, c->fb_inst, B);
@@ -947,6 +949,12 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
             }
             rc = read_counts(c);
             if (rc) return fail_all(rc);
+            if (o.verbose > 2) {  // every step-size trial of the first instance
+                InstCtl q;
+                HIP_TRY(hipMemcpy(&q, c->ctl, sizeof(q), hipMemcpyDeviceToHost));
+                fprintf(stderr, "    trial %d: minV %.4e (eps0 %.4e) |g| %.6e (accepted |g| %.6e) -> %s\n", h, q.tminV,
+                        q.eps0, q.tgnorm, q.gnorm, c->h_cnt[PH_TRIAL] == 0 ? "kept" : "halved");
+            }
             if (c->h_cnt[PH_TRIAL] == 0) break;
         }
         tm.eval += now_ms() - te;

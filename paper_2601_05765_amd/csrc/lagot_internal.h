@@ -127,7 +127,7 @@ struct InstCtl {
 // Newton options as the device control kernels see them.
 struct CtlOpts {
     double tol;
-    int max_newton, max_halvings, single, allow_restart;
+    int max_newton, max_halvings, single, allow_restart, residual_test;
 };
 
 // Views of the evaluation outputs (sorted site order).

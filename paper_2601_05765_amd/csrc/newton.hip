@@ -609,7 +609,7 @@ __global__ __launch_bounds__(1024) void k_ctl_decide(Batch bt, CtlOpts o, const 
         const double sumV = ev[4 * b + 0], maxrel = ev[4 * b + 1], gnorm = ev[4 * b + 2], minV = ev[4 * b + 3];
         c.tminV = minV;
         c.tgnorm = gnorm;
-        if (fail_inst[b] == 0 && minV >= c.eps0 && gnorm <= (1.0 - 0.5 * c.alpha) * c.gnorm) {
+        if (fail_inst[b] == 0 && minV >= c.eps0 && (!o.residual_test || gnorm <= (1.0 - 0.5 * c.alpha) * c.gnorm)) {
             c.sumV = sumV;
             c.maxrel = maxrel;
             c.gnorm = gnorm;

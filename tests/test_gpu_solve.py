@@ -220,3 +220,22 @@ def test_error_codes(ctx):
     # bad option -> EINVAL
     x, y, z, nu, psi = _dev(sc)
     assert ctx.solve(x, y, z, nu, psi, opts=L.default_opts(threads_per_cell=7), check=False).status == L.EINVAL
+
+
+def test_solve_min_volume_rule_only(ctx, oracle_mod):
+    """opts.residual_test = 0: the step size is kept on the min-volume test alone (Algorithm 1
+    as printed); the solution is the same unique weight vector."""
+    _say("case: solve with the min-volume step test only")
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 6)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-6, residual_test=0))
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.max_rel_err <= 1e-6
+    x, y, z, nu, psi2 = _dev(sc)
+    st2 = ctx.solve(x, y, z, nu, psi2, opts=L.default_opts(tol=1e-6))
+    assert st2.status == 0
+    # both start from the same psi0, so the additive constant is fixed the same way
+    p1, p2 = psi.cpu().numpy(), psi2.cpu().numpy()
+    assert np.max(np.abs(p1 - p2) / np.abs(p2)) <= 1e-3
+    assert _oracle_err(oracle_mod, sc, p1) <= 1e-5
