@@ -180,6 +180,39 @@ def learned_section(ctx, L, scenes, n_seeds: int, train_steps: int, steps: int):
             "status_plain": [r["status"] for r in a], "status_learned": [r["status"] for r in b]}
 
 
+def splash_section(ctx, L, scenes, n: int, steps: int):
+    """The large-scene recipe (slab + 200 over-packed droplets, log-normal nu, random
+    velocities) at n sites: the first solve from the Voronoi start, then `steps`
+    advect-and-solve steps warm-started from the previous weights. Step sizes use the
+    min-volume test alone (Algorithm 1 as printed), which does not stall on the float32
+    noise floor near the tolerance."""
+    import torch
+    sc = scenes.splash(n, 0)
+    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    nu, psi = t(sc.nu, torch.float64), t(sc.psi0, torch.float64)
+    opts = L.default_opts(tol=1e-5, autotune=1, residual_test=0)
+    out = {"sites": n, "steps": steps, "ms": [], "newton_iters": [], "evals": [], "status": [], "restarted": [],
+           "max_rel_err": []}
+    cur = sc
+    for k in range(steps + 1):
+        if k:
+            cur = scenes.advect(cur, 2e-3)
+        x, y, z = t(cur.x, torch.float32), t(cur.y, torch.float32), t(cur.z, torch.float32)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = ctx.solve(x, y, z, nu, psi, opts=opts, check=False)
+        torch.cuda.synchronize()
+        out["ms"].append(1000.0 * (time.perf_counter() - a))
+        out["newton_iters"].append(st.newton_iters)
+        out["evals"].append(st.evals)
+        out["status"].append(st.status)
+        out["restarted"].append(st.default_start)
+        out["max_rel_err"].append(st.max_rel_err)
+    out["ms_settle"] = out["ms"][0]
+    out["ms_per_step"] = float(np.mean(out["ms"][1:])) if steps else None
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +227,9 @@ def main(argv=None):
     ap.add_argument("--learned-seeds", type=int, default=6, help="training scenes (100k sites each)")
     ap.add_argument("--learned-steps", type=int, default=4, help="advect-and-solve steps per training scene")
     ap.add_argument("--sequence-steps", type=int, default=5)
+    ap.add_argument("--no-splash", action="store_true", help="skip the over-packed splash sequence")
+    ap.add_argument("--splash-n", type=int, default=200_000)
+    ap.add_argument("--splash-steps", type=int, default=5)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
@@ -284,6 +320,8 @@ def main(argv=None):
     }
     if not args.no_batched:
         line["batched"] = batched_section(ctx, L, scenes)
+    if not args.no_splash:
+        line["splash"] = splash_section(ctx, L, scenes, args.splash_n, args.splash_steps)
     if not args.no_learned:
         line["learned"] = learned_section(ctx, L, scenes, args.learned_seeds, args.learned_steps,
                                           args.sequence_steps)

@@ -881,7 +881,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     const Batch bt = batch(c);
     hipStream_t st = c->stream;
     CtlOpts co{o.tol, o.max_newton, o.max_halvings, single ? 1 : 0, o.empty_start_fallback ? 1 : 0,
-               o.residual_test ? 1 : 0};
+               o.residual_test ? 1 : 0, 0};
     CallTimes tm;
     int learned = 0;
     launch_zero_i32(st, c->fb_inst, B);
@@ -898,12 +898,17 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
                      c->counts);
     rc = read_counts(c);
     if (rc) return fail_all(rc);
-    if (c->h_cnt[PH_REPAIR] > 0) {
+    // repair rounds: raising one cell can empty a neighbour's, so a repaired start is
+    // checked and repaired again, up to REPAIR_ROUNDS times, before the full restart
+    constexpr int REPAIR_ROUNDS = 2;
+    for (int round = 0; round < REPAIR_ROUNDS && c->h_cnt[PH_REPAIR] > 0; ++round) {
         launch_repair_empty(st, bt, PH_REPAIR, c->V, c->nu_s, c->cell_start, c->psi_s, c->psi_trial, c->pos_s);
         std::swap(c->psi_s, c->psi_trial);
         launch_rmax(st, bt, PH_REPAIR, c->psi_s, c->rmax);
         evaluate(c, PH_REPAIR, c->psi_s, false, c->ev);
-        launch_ctl_start(st, bt, co, PH_REPAIR, c->ev, c->ev_nu, c->ev, c->fail_inst, c->ctl, c->phase, c->counts);
+        CtlOpts cr = co;
+        cr.repair_more = round + 1 < REPAIR_ROUNDS ? 1 : 0;
+        launch_ctl_start(st, bt, cr, PH_REPAIR, c->ev, c->ev_nu, c->ev, c->fail_inst, c->ctl, c->phase, c->counts);
         rc = read_counts(c);
         if (rc) return fail_all(rc);
     }

@@ -128,6 +128,7 @@ struct InstCtl {
 struct CtlOpts {
     double tol;
     int max_newton, max_halvings, single, allow_restart, residual_test;
+    int repair_more;  // a repaired start that still has an empty cell is repaired again
 };
 
 // Views of the evaluation outputs (sorted site order).

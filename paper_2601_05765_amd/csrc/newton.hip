@@ -558,10 +558,11 @@ __global__ __launch_bounds__(1024) void k_ctl_start(Batch bt, CtlOpts o, int fro
         c.maxrel = ev[4 * b + 1];
         c.gnorm = ev[4 * b + 2];
         c.minV = ev[4 * b + 3];
-        // an empty start cell: first raise the empty cells' weights, then restart from
-        // the default weights, then give up (eps0 would be 0)
+        // an empty start cell: first raise the empty cells' weights (again while the
+        // host allows more rounds), then restart from the default weights, then give up
+        // (eps0 would be 0)
         if (!(c.minV > 0.0) && o.allow_restart && from_phase != PH_RESTART) {
-            phase[b] = from_phase == PH_START ? PH_REPAIR : PH_RESTART;
+            phase[b] = (from_phase == PH_START || o.repair_more) ? PH_REPAIR : PH_RESTART;
             continue;
         }
         c.eps0 = 0.5 * fmin(ev_nu[4 * b + 3], ev_floor[4 * b + 3]);
