@@ -173,11 +173,39 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ keys, int32_t *
     perm[slot] = (int32_t)i;
 }
 
-// Order each grid cell's sites by caller index (insertion sort; cells hold a few sites).
+// Order each grid cell's sites by caller index, so that the grid order does not depend
+// on the order of the scatter's atomics. Cells usually hold a few sites (insertion
+// sort); crowded scenes with large weights get cells of thousands of sites, which are
+// heap-sorted (O(k log k) instead of O(k^2) per thread).
+__device__ inline void sift_down(int32_t *a, int root, int end) {
+    for (;;) {
+        int child = 2 * root + 1;
+        if (child >= end) return;
+        if (child + 1 < end && a[child + 1] > a[child]) ++child;
+        if (a[root] >= a[child]) return;
+        const int32_t t = a[root];
+        a[root] = a[child];
+        a[child] = t;
+        root = child;
+    }
+}
+
 __global__ void k_sort_cells(int ncell, const int32_t *__restrict__ start, int32_t *__restrict__ perm) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     int b = start[c], e = start[c + 1];
+    const int m = e - b;
+    if (m > 32) {
+        int32_t *a = perm + b;
+        for (int r = m / 2 - 1; r >= 0; --r) sift_down(a, r, m);
+        for (int last = m - 1; last > 0; --last) {
+            const int32_t t = a[0];
+            a[0] = a[last];
+            a[last] = t;
+            sift_down(a, 0, last);
+        }
+        return;
+    }
     for (int a = b + 1; a < e; ++a) {
         int v = perm[a];
         int k = a - 1;
