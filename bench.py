@@ -87,6 +87,7 @@ def flops_per_cell(work_mean: np.ndarray) -> float:
 def cpu_baseline(sc, psi, seconds_target: float = 15.0):
     """The oracle (brute-force FP64) on a bounded random sample of cells of the workload."""
     import oracle
+    cores = oracle.num_threads()
     rng = np.random.default_rng(7)
     probe = np.sort(rng.choice(sc.n, 400, replace=False))
     t0 = time.perf_counter()
@@ -101,9 +102,18 @@ def cpu_baseline(sc, psi, seconds_target: float = 15.0):
         c = oracle.cells(sc.x, sc.y, sc.z, psi, idx=idx, work=True)
     dt = time.perf_counter() - t0
     what = f"{reps} passes over all {sc.n} cells" if reps > 1 else f"{m} random cells"
-    return {"value": reps * m / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+    # the same oracle on one core, on a smaller sample (about a quarter of the time budget)
+    m1 = int(min(sc.n, max(200, rate / max(oracle.num_threads(), 1) * seconds_target / 4)))
+    idx1 = np.sort(rng.choice(sc.n, m1, replace=False))
+    t0 = time.perf_counter()
+    oracle.cells(sc.x, sc.y, sc.z, psi, idx=idx1, threads=1)
+    dt1 = time.perf_counter() - t0
+    oracle.cells(sc.x, sc.y, sc.z, psi, idx=idx1[:1], threads=cores)  # back to all threads
+    return {"value": reps * m / dt, "unit": "cells/s", "cores": cores, "kind": "oracle",
             "sample": f"{what} of the {sc.n}-site workload at the start weights, brute-force "
-                      f"neighbours, FP64 ({dt:.1f} s)"}, c.work.mean(axis=0)
+                      f"neighbours, FP64 ({dt:.1f} s)",
+            "single_core": {"value": m1 / dt1, "sample": f"{m1} random cells on 1 thread ({dt1:.1f} s)"}}, \
+        c.work.mean(axis=0)
 
 
 def batched_section(ctx, L, scenes, reps: int = 3):
@@ -216,8 +226,8 @@ def splash_section(ctx, L, scenes, n: int, steps: int):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -259,9 +269,12 @@ def main(argv=None):
     psis = [psi0.clone() for _ in range(args.steps)]
     torch.cuda.synchronize()
     stats = []
+    per_solve = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        stats.append(ctx.solve(x, y, z, nu, psis[k], opts=opts))
+        a = time.perf_counter()
+        stats.append(ctx.solve(x, y, z, nu, psis[k], opts=opts))  # returns after the stream is synchronised
+        per_solve.append(1000.0 * (time.perf_counter() - a))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
@@ -307,7 +320,8 @@ def main(argv=None):
         "config": {"workload": f"dam_break_{args.n}: jittered cubic lattice in the lower 40% of the unit box, "
                                f"nu=0.35/N, one plain OT solve to 1e-5 relative volume error",
                    "n_sites": args.n, "tol": 1e-5},
-        "solve": {"ms_per_solve_plain": ms_per_step, "newton_iters": s0.newton_iters, "evals": s0.evals,
+        "solve": {"ms_per_solve_plain": ms_per_step, "ms_per_solve_median": float(np.median(per_solve)),
+                  "newton_iters": s0.newton_iters, "evals": s0.evals,
                   "halvings": s0.halvings, "cg_iters": s0.cg_iters, "max_rel_err": s0.max_rel_err,
                   "fallback_cells": s0.fallback_cells, "ms_eval": s0.ms_eval, "ms_linear": s0.ms_linear},
         "eval_only": {"cells_per_s_with_grid": args.n / (ev0 / 1000.0), "cells_per_s_kernel": args.n / (k0 / 1000.0),
