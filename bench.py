@@ -53,17 +53,18 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Bytes per launch from the committed counter profile, or None when the kernel
-    sources changed since the counters were taken (or there is no profile)."""
+def counter_record():
+    """The committed counter profile of the fast cell kernel (HBM bytes per launch, VALU
+    issue fraction), or {} when the kernel sources changed since the counters were taken
+    (or there is no profile)."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if rec.get("sources_sha256") != kernel_sources_digest():
-        return None
-    return float(rec["bytes_per_launch"])
+        return {}
+    return rec
 
 # Algorithmic FLOPs of one cell evaluation per work unit (FMA = 2, sqrt/div/rcp/atan2 = 1),
 # counted from the float32 kernel's arithmetic; the units come from the oracle.
@@ -353,7 +354,8 @@ def main(argv=None):
         fpc = flops_per_cell(work_mean)
         achieved = fpc * args.n / (ms_kernel / 1000.0) / 1e12
         line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counter_record().get("bytes_per_launch"),
+                            "valu_issue_frac": counter_record().get("valu_issue_frac"),
                             "kernel": "k_cells_fast<32, false> (fused clip + ball integration, float32)",
                             "flops_per_cell": fpc, "ms_per_launch": ms_kernel,
                             "work_units_per_cell": dict(zip(["cand", "tests", "newv", "faces", "edges", "cross"],
