@@ -142,3 +142,19 @@ def test_batch_256_instances_full_size(ctx, oracle_mod):
         sc = insts[b]
         idx = np.sort(rng.choice(sc.n, min(sc.n, 400), replace=False))
         assert _oracle_err(oracle_mod, sc, out[offs[b]:offs[b + 1]], idx=idx) <= 1e-5
+
+
+def test_batch_with_overpacked_instance(ctx, oracle_mod):
+    """An over-packed droplet (cells through the overflow pass) batched with ordinary
+    instances: each instance converges as it does alone."""
+    _say("case: batch with an over-packed sphere and two slab instances")
+    insts = [scenes.batch_instances(2, base_seed=8000, n_lo=400, n_hi=1200)[0],
+             scenes.overpacked_sphere(1500, 1.72, 2),
+             scenes.batch_instances(2, base_seed=8000, n_lo=400, n_hi=1200)[1]]
+    offs, x, y, z, nu, psi = _concat(insts)
+    sts = ctx.solve_batched(offs, x, y, z, nu, psi)
+    out = psi.cpu().numpy()
+    for b, (sc, st) in enumerate(zip(insts, sts)):
+        _say(f"  inst {b} n={sc.n} status={st.status} it={st.newton_iters} err={st.max_rel_err:.2e}")
+        assert st.status == 0 and st.max_rel_err <= 1e-5
+        assert _oracle_err(oracle_mod, sc, out[offs[b]:offs[b + 1]], box=sc.box) <= 1e-5
