@@ -786,9 +786,9 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o, bool graph) {
             if (rc) return rc;
         }
     }
-    // chunk length for the next direction: this solve's iteration count and a margin
-    // (launches after convergence return at once; a second chunk costs a host round trip)
-    c->cg_chunk = std::min(64, std::max(8, (k + k / 4 + 4 + 3) / 4 * 4));
+    // chunk length for the next direction: about this solve's iteration count (a margin
+    // of a quarter measured slower: the launches after convergence are not free)
+    c->cg_chunk = std::min(64, std::max(8, (k + 3) / 4 * 4));
     launch_cg_finish(st, bt, c->cg_sub, o.cg_rtol * o.cg_rtol, cg_bufs(c), c->herr, c->ctl, c->phase);
     return LAGOT_OK;
 }

@@ -87,35 +87,43 @@ template <> __device__ inline float rcp_<float>(float v) { return __builtin_amdg
 template <> __device__ inline double rcp_<double>(double v) { return 1.0 / v; }
 
 // One fan piece: triangle (q, q+u, q+v) ∩ disk(q, rho), signed by the orientation of
-// (u, v) about n. h = |t|, cone = 1 - h/r. Adds its planar area to A and the solid
-// angle it subtends at p_i (apex at height h above q) to Om.
+// (u, v) about n. h = |t|, cone = 1 - h/r. Returns its planar area A and the solid
+// angle Om it subtends at p_i (apex at height h above q).
 //   - no crossing of the circle: one circular sector of angle phi = angle(u, v):
 //       area rho^2 phi / 2, solid angle phi (1 - h/r)
 //   - crossing at a = u + lo w, b = u + hi w: sectors (u, a) and (b, v) plus the
 //     triangle (q, a, b) inside the disk (Van Oosterom-Strackee with the apex at h).
 //     The two sector angles are parts of one angle below pi, so they are summed as
 //     the argument of the product of their complex numbers (one atan2).
-// With MOM it also adds the piece's first moment about q (an in-plane vector) to
+// With MOM it also returns the piece's first moment about q (an in-plane vector)
 // (Mx, My, Mz): a sector of radius rho from the unit direction e through the angle phi
 // has the moment rho^3/3 (e sin phi + (n x e)(1 - cos phi)), with sin and cos from the
 // normalised cross and dot products (no angle needed); a triangle (q, q+a, q+b) has its
 // signed area times (a + b)/3.
+// One fan piece's planar area A, solid angle Om and (with MOM) first moment (Mx, My, Mz),
+// returned by value: the accumulators stay in registers whatever the optimiser does with
+// the branches.
+template <typename R> struct PieceSum {
+    R A, Om, Mx, My, Mz;
+};
+
 template <typename R>
-__device__ inline void sector_moment(R ex, R ey, R ez, R cphi, R sphi, R nx, R ny, R nz, R k, R &Mx, R &My,
-                                     R &Mz) {
+__device__ __attribute__((always_inline)) inline void sector_moment(R ex, R ey, R ez, R cphi, R sphi, R nx, R ny, R nz, R k,
+                                                                    PieceSum<R> &p) {
     const R wx = ny * ez - nz * ey, wy = nz * ex - nx * ez, wz = nx * ey - ny * ex;
     const R oc = R(1) - cphi;
-    Mx += k * (ex * sphi + wx * oc);
-    My += k * (ey * sphi + wy * oc);
-    Mz += k * (ez * sphi + wz * oc);
+    p.Mx += k * (ex * sphi + wx * oc);
+    p.My += k * (ey * sphi + wy * oc);
+    p.Mz += k * (ez * sphi + wz * oc);
 }
 
 template <typename R, bool MOM = false>
-__device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny, R nz, R rho2, R h, R cone, R &A,
-                                 R &Om, R &Mx, R &My, R &Mz) {
+__device__ __attribute__((always_inline)) inline PieceSum<R> fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny, R nz,
+                                                                        R rho2, R h, R cone) {
+    PieceSum<R> p{R(0), R(0), R(0), R(0), R(0)};
     const R wx = vx - ux, wy = vy - uy, wz = vz - uz;
     const R a = dot3(wx, wy, wz, wx, wy, wz);
-    if (!(a > R(0))) return;
+    if (!(a > R(0))) return p;
     const R b = dot3(ux, uy, uz, wx, wy, wz);
     const R c = dot3(ux, uy, uz, ux, uy, uz) - rho2;
     const R disc = b * b - a * c;
@@ -131,17 +139,17 @@ __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny,
         const R cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
         const R sn = dot3(nx, ny, nz, cx, cy, cz), cs = dot3(ux, uy, uz, vx, vy, vz);
         const R phi = atan2_<R>(sn, cs);
-        A += half_rho2 * phi;
-        Om += cone * phi;
+        p.A += half_rho2 * phi;
+        p.Om += cone * phi;
         if constexpr (MOM) {
             const R lu = sqrt(dot3(ux, uy, uz, ux, uy, uz)), luv = lu * sqrt(dot3(vx, vy, vz, vx, vy, vz));
             if (luv > R(0)) {
                 const R il = rcp_<R>(lu), iuv = rcp_<R>(luv);
                 sector_moment<R>(ux * il, uy * il, uz * il, cs * iuv, sn * iuv, nx, ny, nz,
-                                 rho2 * sqrt(rho2) * R(1.0 / 3.0), Mx, My, Mz);
+                                 rho2 * sqrt(rho2) * R(1.0 / 3.0), p);
             }
         }
-        return;
+        return p;
     }
     const R ax = ux + lo * wx, ay = uy + lo * wy, az = uz + lo * wz;
     const R bx = ux + hi * wx, by = uy + hi * wy, bz = uz + hi * wz;
@@ -160,30 +168,31 @@ __device__ inline void fan_piece(R ux, R uy, R uz, R vx, R vy, R vz, R nx, R ny,
         const R lb = sqrt(dot3(bx, by, bz, bx, by, bz)), lv = sqrt(dot3(vx, vy, vz, vx, vy, vz));
         if (lo > R(0) && lu * la > R(0)) {
             const R il = rcp_<R>(lu), d = rcp_<R>(lu * la);
-            sector_moment<R>(ux * il, uy * il, uz * il, c1 * d, s1 * d, nx, ny, nz, k, Mx, My, Mz);
+            sector_moment<R>(ux * il, uy * il, uz * il, c1 * d, s1 * d, nx, ny, nz, k, p);
         }
         if (hi < R(1) && lb * lv > R(0)) {
             const R il = rcp_<R>(lb), d = rcp_<R>(lb * lv);
-            sector_moment<R>(bx * il, by * il, bz * il, c2 * d, s2 * d, nx, ny, nz, k, Mx, My, Mz);
+            sector_moment<R>(bx * il, by * il, bz * il, c2 * d, s2 * d, nx, ny, nz, k, p);
         }
     }
     const R phi = atan2_<R>(c1 * s2 + s1 * c2, c1 * c2 - s1 * s2);
-    A += half_rho2 * phi;
-    Om += cone * phi;
+    p.A += half_rho2 * phi;
+    p.Om += cone * phi;
     // triangle (q, q+a, q+b) inside the disk: planar area and solid angle
     const R cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
     const R st = dot3(nx, ny, nz, cx, cy, cz);
-    A += R(0.5) * st;
+    p.A += R(0.5) * st;
     if constexpr (MOM) {
         const R w = st * R(1.0 / 6.0);
-        Mx += w * (ax + bx);
-        My += w * (ay + by);
-        Mz += w * (az + bz);
+        p.Mx += w * (ax + bx);
+        p.My += w * (ay + by);
+        p.Mz += w * (az + bz);
     }
     const R h2 = h * h;
     const R la = sqrt(dot3(ax, ay, az, ax, ay, az) + h2);
     const R lb = sqrt(dot3(bx, by, bz, bx, by, bz) + h2);
-    Om += R(2) * atan2_<R>(st, la * lb + h * (la + lb) + h2 + dot3(ax, ay, az, bx, by, bz));
+    p.Om += R(2) * atan2_<R>(st, la * lb + h * (la + lb) + h2 + dot3(ax, ay, az, bx, by, bz));
+    return p;
 }
 
 // Vertex record of the integration phase: position relative to p_i and its three planes.
@@ -927,9 +936,11 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 const R cone = R(1) - h * cone_den;
                 const R qx = t * nx, qy = t * ny, qz = t * nz;
                 const VRec<R> P = GT.rec[sv], Q = GT.rec[sn];
-                R mx = R(0), my = R(0), mz = R(0);
-                fan_piece<R, MOM>(P.x - qx, P.y - qy, P.z - qz, Q.x - qx, Q.y - qy, Q.z - qz, nx, ny, nz, rho2, h,
-                                  cone, pa[rr], po[rr], mx, my, mz);
+                const PieceSum<R> ps = fan_piece<R, MOM>(P.x - qx, P.y - qy, P.z - qz, Q.x - qx, Q.y - qy, Q.z - qz,
+                                                         nx, ny, nz, rho2, h, cone);
+                pa[rr] = ps.A;
+                po[rr] = ps.Om;
+                const R mx = ps.Mx, my = ps.My, mz = ps.Mz;
                 if constexpr (MOM) {
                     const double td = (double)t, ar = (double)pa[rr];
                     const double c2 = td * td - (in_ball ? 0.0 : (double)r * (double)r);
