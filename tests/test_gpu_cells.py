@@ -238,3 +238,30 @@ def test_centroids_tile_the_box(ctx):
     C = cen.cpu().numpy()
     assert V.sum() == pytest.approx(1.0, rel=1e-6)
     assert np.allclose((V[:, None] * C).sum(0), [0.5, 0.5, 0.5], atol=2e-6)
+
+
+def test_centroids_scaled_box_and_edge_cases(ctx, oracle_mod):
+    """Centroids in the box [0, 2]^3 (a similarity of a unit-box scene: centroids scale by
+    2), a single site, and an engulfed (empty) cell."""
+    _say("case: centroids in a scaled box, one site, an empty cell")
+    sc = scenes.random_small(30, 7, r_lo=0.05, r_hi=0.2)
+    f = 2.0
+    xs, ys, zs = [(np.asarray(a, np.float64) * f).astype(np.float32) for a in (sc.x, sc.y, sc.z)]
+    psi = sc.psi0 * f * f
+    box = ((0, 0, 0), (f, f, f))
+    assert _centroid_err(ctx, oracle_mod, xs, ys, zs, psi, box=box) <= 1e-5
+    xd, yd, zd, pd = _dev((xs, ys, zs), psi)
+    _, c2 = ctx.centroids(xd, yd, zd, pd, box=box)
+    xd, yd, zd, pd = _dev((sc.x, sc.y, sc.z), sc.psi0)
+    _, c1 = ctx.centroids(xd, yd, zd, pd)
+    assert np.allclose(c2.cpu().numpy(), f * c1.cpu().numpy(), rtol=0, atol=1e-5)
+    # one site: a ball cut by two walls
+    assert _centroid_err(ctx, oracle_mod, [0.05], [0.93], [0.5], np.array([0.1 ** 2])) <= 1e-5
+    # an engulfed ball reports its site
+    x = np.array([0.4, 0.45], np.float32)
+    y = np.array([0.5, 0.5], np.float32)
+    z = np.array([0.5, 0.5], np.float32)
+    xd, yd, zd, pd = _dev((x, y, z), np.array([0.03 ** 2, 0.12 ** 2]))
+    vol, cen = ctx.centroids(xd, yd, zd, pd)
+    assert float(vol[0]) == 0.0
+    assert np.allclose(cen.cpu().numpy()[0], [x[0], y[0], z[0]], atol=0)
