@@ -45,7 +45,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.oracle_cells.argtypes = [ctypes.c_long, P, P, P, P, P, P, ctypes.c_long, P, P, P, P, P, ctypes.c_int,
-                                     P, P, P, ctypes.c_int, P, P]
+                                     P, P, P, ctypes.c_int, P, P, P, ctypes.c_int]
         lib.oracle_cells.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -64,7 +64,7 @@ def _ptr(a):
 class Cells:
     V: np.ndarray            # [m] volumes
     K: np.ndarray            # [m] spherical (free-surface) areas
-    walls: np.ndarray        # [m,6] wall facet areas (-x,+x,-y,+y,-z,+z)
+    walls: np.ndarray        # [m,6] wall facet areas (-x,+x,-y,+y,-z,+z), or [m,P] per domain plane
     fcount: np.ndarray       # [m] neighbour facet counts
     fj: np.ndarray           # [m,fcap] neighbour ids (valid up to fcount)
     fA: np.ndarray           # [m,fcap] facet areas
@@ -80,8 +80,11 @@ class Cells:
 
 
 def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, threads: int = 0,
-          work: bool = False) -> Cells:
+          work: bool = False, domain=None) -> Cells:
     """Evaluate the restricted Laguerre cells of the sites ``idx`` (default: all).
+
+    ``domain``: optional [P, 4] array of planes (n, c), unit outward normals n, for the
+    convex domain {x : n.x <= c} in place of the box walls.
 
     Positions are promoted to float64 exactly; ``psi`` must be float64.
     Neighbours are found by brute force over all sites (O(N) per cell)."""
@@ -102,7 +105,9 @@ def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, th
         idx_p = _ptr(idx_arr)
     V = np.zeros(m)
     K = np.zeros(m)
-    W = np.zeros((m, 6))
+    dom = None if domain is None else np.ascontiguousarray(domain, np.float64).reshape(-1, 4)
+    nwall = 6 if dom is None else dom.shape[0]
+    W = np.zeros((m, nwall))
     fj = np.full((m, fcap), -1, np.int64)
     fA = np.zeros((m, fcap))
     fc = np.zeros(m, np.int32)
@@ -112,7 +117,8 @@ def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, th
     C = np.zeros((m, 3))
     lib.oracle_cells(n, _ptr(x), _ptr(y), _ptr(z), _ptr(psi), _ptr(b), idx_p, m, _ptr(V), _ptr(K), _ptr(W),
                      _ptr(fj), _ptr(fA), fcap, _ptr(fc), _ptr(nc), _ptr(st), int(threads),
-                     _ptr(wk) if work else None, _ptr(C))
+                     _ptr(wk) if work else None, _ptr(C), _ptr(dom) if dom is not None else None,
+                     0 if dom is None else int(dom.shape[0]))
     if (st == 2).any():
         raise RuntimeError("oracle facet capacity exceeded; raise fcap")
     return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr, wk, C)

@@ -344,16 +344,20 @@ static int cmp_plane_t(const void *a, const void *b)
  * facets (id, area) with area > 0, the facet count (may exceed fcap -> status
  * OR_FACET_CAP), and the number of planes that cut the ball (ncand).
  */
+/* auxiliary cube planes carry ids at or below this (never facets, never walls) */
+#define AUX_ID (-1000000)
+
 static int oracle_cell(long i, long n, const double *x, const double *y, const double *z, const double *psi,
-                       const double *box, double *V, double *K, double *wall, long *fj, double *fA, int fcap,
-                       int *fcount, int *ncand, double *cen)
+                       const double *box, const double *dom, int ndom, double *V, double *K, double *wall, long *fj,
+                       double *fA, int fcap, int *fcount, int *ncand, double *cen)
 {
+    const int nwall = ndom > 0 ? ndom : 6;
     *V = 0.0;
     *K = 0.0;
     cen[0] = x[i];
     cen[1] = y[i];
     cen[2] = z[i];
-    for (int k = 0; k < 6; ++k) wall[k] = 0.0;
+    for (int k = 0; k < nwall; ++k) wall[k] = 0.0;
     *fcount = 0;
     *ncand = 0;
     if (!(psi[i] > 0.0)) return OR_EMPTY;
@@ -395,18 +399,32 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
     }
     *ncand = np;
     if (g_work) g_work[W_CAND] = np;
-    /* box walls: -x,+x,-y,+y,-z,+z with t = distance of p_i to the wall */
-    for (int w = 0; w < 6; ++w) {
-        int ax = w / 2;
-        double t = (w % 2 == 0) ? pi3[ax] - box[ax] : box[3 + ax] - pi3[ax];
+    /* walls: the box -x,+x,-y,+y,-z,+z, or the planes n.x <= c of a convex polyhedral
+       domain (unit outward normals; the paper evaluates cells in polyhedral domains, section
+       6, and a convex one is an intersection of half-spaces); t is the distance of p_i to
+       the wall */
+    for (int w = 0; w < nwall; ++w) {
+        double nw[3] = {0.0, 0.0, 0.0}, t;
+        if (ndom > 0) {
+            const double *q = dom + 4 * w;
+            nw[0] = q[0];
+            nw[1] = q[1];
+            nw[2] = q[2];
+            t = q[3] - dot3(nw, pi3);
+        } else {
+            int ax = w / 2;
+            nw[ax] = (w % 2 == 0) ? -1.0 : 1.0;
+            t = (w % 2 == 0) ? pi3[ax] - box[ax] : box[3 + ax] - pi3[ax];
+        }
         if (t < r) {
             if (np + 1 > pcap) {
                 pcap *= 2;
                 pl = (oplane *)realloc(pl, sizeof(oplane) * (size_t)pcap);
             }
             oplane *p = &pl[np++];
-            p->n[0] = p->n[1] = p->n[2] = 0.0;
-            p->n[ax] = (w % 2 == 0) ? -1.0 : 1.0;
+            p->n[0] = nw[0];
+            p->n[1] = nw[1];
+            p->n[2] = nw[2];
             p->t = t;
             p->id = -1 - w;
         }
@@ -428,7 +446,7 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
         p->n[0] = p->n[1] = p->n[2] = 0.0;
         p->n[ax] = sgn;
         p->t = L;
-        p->id = -7 - w;
+        p->id = AUX_ID - w;
         angpt c4[4];
         int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3, m = 0;
         for (int s1 = -1; s1 <= 1; s1 += 2)
@@ -457,7 +475,7 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
     for (int k = 0; k < P.nf; ++k) {
         const oface *f = &P.f[k];
         const oplane *p = &pl[f->plane];
-        if (p->id <= -7) continue;
+        if (p->id <= AUX_ID) continue;
         if (g_work) g_work[W_FACES]++;
         fanacc a = restrict_face(f, p, r);
         sumTA += p->t * a.area;
@@ -491,15 +509,18 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
 }
 
 /*
- * Evaluate m cells (indices idx[0..m), or all n cells when idx == NULL).
- * Per evaluated cell c: V[c], K[c], wall[6c..6c+6), facets fj/fA[c*fcap ..],
+ * Evaluate m cells (indices idx[0..m), or all n cells when idx == NULL), in the box or,
+ * when ndom > 0, in the convex domain {x : n_w.x <= c_w} given as dom[4w..4w+4) =
+ * (n_w, c_w) with unit outward normals (the box is then not used).
+ * Per evaluated cell c: V[c], K[c], wall[W c..W c+W) with W = 6 or ndom, facets fj/fA[c*fcap ..],
  * fcount[c], ncand[c], status[c], the centroid cen[3c..3c+3) (the site itself for an
  * empty cell), and when work != NULL the six work units of each cell at
  * work[6c..6c+6). OpenMP over cells.
  */
 int oracle_cells(long n, const double *x, const double *y, const double *z, const double *psi,
                  const double *box, const long *idx, long m, double *V, double *K, double *wall, long *fj,
-                 double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads, long *work, double *cen)
+                 double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads, long *work, double *cen,
+                 const double *dom, int ndom)
 {
     long cnt = idx ? m : n;
 #ifdef _OPENMP
@@ -513,8 +534,10 @@ int oracle_cells(long n, const double *x, const double *y, const double *z, cons
         g_work = work ? &work[W_N * c] : NULL;
         if (g_work)
             for (int k = 0; k < W_N; ++k) g_work[k] = 0;
-        status[c] = oracle_cell(i, n, x, y, z, psi, box, &V[c], &K[c], &wall[6 * c], &fj[(size_t)c * fcap],
-                                &fA[(size_t)c * fcap], fcap, &fcount[c], &ncand[c], &cen[3 * c]);
+        const int nwall = ndom > 0 ? ndom : 6;
+        status[c] = oracle_cell(i, n, x, y, z, psi, box, dom, ndom, &V[c], &K[c], &wall[(size_t)nwall * c],
+                                &fj[(size_t)c * fcap], &fA[(size_t)c * fcap], fcap, &fcount[c], &ncand[c],
+                                &cen[3 * c]);
     }
     return 0;
 }
