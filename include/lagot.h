@@ -263,6 +263,22 @@ int lagot_set_threads_per_cell(lagot_ctx *ctx, int threads_per_cell);
  * Returns LAGOT_EINVAL for other shapes. */
 int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block);
 
+/*
+ * Convex polyhedral domain {x : n_w . x <= c_w, w < nplanes} in place of the box walls
+ * for every later call on this context (the paper evaluates its cells in polyhedral
+ * domains, section 6; a convex one is an intersection of half-spaces). The domain's
+ * planes bound the cells, enter V, K and the wall areas, and not the Hessian (they do
+ * not move with psi). The box argument of the calls must still contain the domain (it
+ * bounds the neighbour grid); sites must lie strictly inside both. With a domain,
+ * lagot_cells' wall_area holds nplanes areas per site (site-major, in plane order).
+ *   in : planes [4 nplanes] float64 HOST array (n_x, n_y, n_z, c) per plane, unit outward
+ *        normals (|n| within 1e-6 of 1); 0 <= nplanes <= 32; nplanes = 0 restores the box.
+ * Applies to every instance of a batch. Synchronises the stream.
+ * Errors: LAGOT_EINVAL (NULL ctx or planes, nplanes out of range, normal not unit, c not
+ * finite), LAGOT_EHIP.
+ */
+int lagot_set_domain(lagot_ctx *ctx, int nplanes, const double *planes);
+
 /* Number of cells that the last lagot_cells call on this context redid on the
  * large-capacity float64 path (diagnostic; -1 if ctx is NULL). */
 int lagot_last_fallback_cells(const lagot_ctx *ctx);

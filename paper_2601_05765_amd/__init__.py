@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_centroids", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
@@ -96,6 +96,8 @@ def load():
         lib.lagot_set_threads_per_cell.restype = I
         lib.lagot_set_cg_shape.argtypes = [P, I, I]
         lib.lagot_set_cg_shape.restype = I
+        lib.lagot_set_domain.argtypes = [P, ctypes.c_int, P]
+        lib.lagot_set_domain.restype = I
         lib.lagot_centroids.argtypes = [P, I64, P, P, P, P, Box, P, P]
         lib.lagot_centroids.restype = I
         lib.lagot_last_flag_counts.argtypes = [P, P]
@@ -178,7 +180,8 @@ class Context:
                 _dev(psi, torch.float64, "psi")]
         vol = torch.empty(n, dtype=torch.float64, device=dev)
         K = torch.empty(n, dtype=torch.float64, device=dev) if sph else None
-        W = torch.empty(n * 6, dtype=torch.float32, device=dev) if walls else None
+        nwall = getattr(self, "_nwall", 6)
+        W = torch.empty(n * nwall, dtype=torch.float32, device=dev) if walls else None
         out = {"vol": vol}
         lib = load()
         cap = nnz_per_cell * n
@@ -205,7 +208,7 @@ class Context:
         if K is not None:
             out["sph"] = K
         if W is not None:
-            out["walls"] = W.view(n, 6)
+            out["walls"] = W.view(n, nwall)
         if csr:
             out["row_ptr"], out["col"], out["area"] = rp, col[: nnz.value], fa[: nnz.value]
         out["nnz"] = int(nnz.value)
@@ -224,6 +227,20 @@ class Context:
         if rc != OK:
             raise LagotError(rc, "lagot_centroids")
         return vol, cen
+
+    def set_domain(self, planes=None) -> None:
+        """lagot_set_domain: planes [P, 4] (unit outward normal, c) of the convex domain
+        n.x <= c, or None for the box."""
+        import numpy as np
+        if planes is None:
+            arr, p = None, 0
+        else:
+            arr = np.ascontiguousarray(planes, np.float64).reshape(-1, 4)
+            p = arr.shape[0]
+        rc = load().lagot_set_domain(self._h, p, arr.ctypes.data_as(ctypes.c_void_p) if p else None)
+        if rc != OK:
+            raise LagotError(rc, "lagot_set_domain")
+        self._nwall = max(p, 0) if p else 6
 
     def set_cg_shape(self, lanes_per_row: int, rows_per_block: int) -> None:
         rc = load().lagot_set_cg_shape(self._h, int(lanes_per_row), int(rows_per_block))

@@ -81,6 +81,9 @@ struct lagot_ctx {
     float *wall = nullptr;
     int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr, *ovf_list = nullptr;
     double *cen_out = nullptr;  // caller's centroid array during a lagot_centroids call
+    float4 *dom_d = nullptr;    // [DOM_MAX] convex domain planes (lagot_set_domain)
+    int ndom = 0;
+    int wall_w = 6;             // wall areas per site in the wall buffer (6, or the domain's planes)
     float *farea = nullptr;
     uint32_t *flags = nullptr;
     // second set of evaluation outputs (learned guess: evaluated aside, swapped in if kept)
@@ -197,7 +200,7 @@ void free_all(lagot_ctx *c) {
     free_alt(c);
     free_sites(c);
     free_inst(c);
-    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc);
+    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_rd) (void)hipHostFree(c->h_rd);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
@@ -235,7 +238,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->inst, N));
     HIP_TRY(dalloc(&c->V, N));
     HIP_TRY(dalloc(&c->K, N));
-    HIP_TRY(dalloc(&c->wall, 6 * N));
+    HIP_TRY(dalloc(&c->wall, (size_t)c->wall_w * N));
     HIP_TRY(dalloc(&c->fcol, FCAP * N));
     HIP_TRY(dalloc(&c->farea, FCAP * N));
     HIP_TRY(dalloc(&c->fcnt, N));
@@ -339,6 +342,8 @@ Batch batch(const lagot_ctx *c) {
     b.box = c->box;
     b.rmax = c->rmax;
     b.phase = c->phase;
+    b.dom = c->dom_d;
+    b.ndom = c->ndom;
     return b;
 }
 
@@ -494,7 +499,9 @@ void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double
     const EvalOut o = eval_out(c, walls);
     const bool timed = !c->capturing || c->graph_events;
     launch_eval_begin(c->stream, bt, want, o);
-    if (walls) (void)hipMemsetAsync(c->wall, 0, 6 * sizeof(float) * (size_t)c->n, c->stream);
+    if (walls)
+        (void)hipMemsetAsync(c->wall, 0, (size_t)(c->ndom > 0 ? c->ndom : 6) * sizeof(float) * (size_t)c->n,
+                             c->stream);
     if (timed) (void)hipEventRecord(c->ev0, c->stream);
     launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, c->tpc);
     if (timed) (void)hipEventRecord(c->ev1, c->stream);
@@ -1134,7 +1141,7 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     evaluate(c, -1, c->psi_s, wall_area != nullptr, nullptr);
     launch_scatter_out_f64(st, n, c->perm, c->V, vol);
     if (sph_area) launch_scatter_out_f64(st, n, c->perm, c->K, sph_area);
-    if (wall_area) launch_scatter_walls(st, n, c->perm, c->wall, wall_area);
+    if (wall_area) launch_scatter_walls(st, n, c->ndom > 0 ? c->ndom : 6, c->perm, c->wall, wall_area);
     HIP_TRY(hipMemcpyAsync(c->h_cnt, c->misc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (csr || nnz_out) {
@@ -1310,6 +1317,33 @@ int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block) {
 }
 
 int lagot_last_fallback_cells(const lagot_ctx *ctx) { return ctx ? ctx->last_fb : -1; }
+
+int lagot_set_domain(lagot_ctx *c, int nplanes, const double *planes) {
+    if (!c || nplanes < 0 || nplanes > DOM_MAX || (nplanes > 0 && !planes)) return LAGOT_EINVAL;
+    float4 h[DOM_MAX];
+    for (int w = 0; w < nplanes; ++w) {
+        const double *q = planes + 4 * w;
+        const double len = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        if (!(std::fabs(len - 1.0) <= 1e-6) || !std::isfinite(q[3])) return LAGOT_EINVAL;
+        h[w] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    if (!c->dom_d) HIP_TRY(dalloc(&c->dom_d, DOM_MAX));
+    if (nplanes > 0) {
+        HIP_TRY(hipMemcpyAsync(c->dom_d, h, sizeof(float4) * nplanes, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    const int w = std::max(6, nplanes);
+    if (w > c->wall_w) {  // a wider wall buffer for the next calls
+        if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+        if (c->wall) (void)hipFree(c->wall);
+        c->wall = nullptr;
+        c->wall_w = w;
+        if (c->cap_n > 0) HIP_TRY(dalloc(&c->wall, (size_t)w * (size_t)c->cap_n));
+    }
+    c->ndom = nplanes;
+    return LAGOT_OK;
+}
 
 int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts) {
     if (!ctx || !counts || ctx->n <= 0 || !ctx->flags) return LAGOT_EINVAL;

@@ -382,6 +382,24 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 f(keep, kill, neg, nx, ny, nz, t, j);
             }
         }
+        if (A.bt.ndom > 0) {
+            // walls of a convex polyhedral domain n.x <= c: t = c - n.p_i, G planes at a time
+            for (int w0 = 0; w0 < A.bt.ndom; w0 += G) {
+                const int w = w0 + gl;
+                bool keep = false;
+                R nx = 0, ny = 0, nz = 0, t = 0;
+                if (live && w < A.bt.ndom) {
+                    const float4 q = A.bt.dom[w];
+                    nx = (R)q.x;
+                    ny = (R)q.y;
+                    nz = (R)q.z;
+                    t = (R)q.w - (nx * px + ny * py + nz * pz);
+                    keep = t < r;
+                }
+                f(keep, false, false, nx, ny, nz, t, -1 - w);
+            }
+            return;
+        }
         // box walls -x,+x,-y,+y,-z,+z: t = distance from p_i to the wall; lane gl < 6 reads
         // its own bound (lo[0..2], hi[0..2]) straight from the box array
         bool keep = false;
@@ -503,7 +521,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         S.pl[gl][1] = ax == 1 ? sg : R(0);
         S.pl[gl][2] = ax == 2 ? sg : R(0);
         S.pl[gl][3] = L;
-        S.pid[gl] = -7 - gl;
+        S.pid[gl] = AUX_PLANE_ID - gl;
     }
     // vertex slots in registers; the cube's corners go to slots 0..7
     uint32_t tri[NS];
@@ -1026,7 +1044,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 a = (float)GT.farea[p];
                 id = S.pid[p];
                 isf = id >= 0 && a > 0.f;
-                if (id < 0 && o.wall) o.wall[cell * 6 + (-1 - id)] = a;
+                if (id < 0 && o.wall) o.wall[cell * (A.bt.ndom > 0 ? A.bt.ndom : 6) + (-1 - id)] = a;
             }
             const unsigned long long b = gballot<G>(isf);
             if (isf) {

@@ -252,6 +252,10 @@ __global__ void k_validate(int64_t n, Batch bt, const float *__restrict__ x, con
     float p[3] = {x[i], y[i], z[i]};
     bool ok = true;
     for (int a = 0; a < 3; ++a) ok = ok && (p[a] > box.lo[a]) && (p[a] < box.hi[a]);  // false for NaN
+    for (int w = 0; w < bt.ndom; ++w) {  // strictly inside every domain plane
+        const float4 q = bt.dom[w];
+        ok = ok && (q.x * p[0] + q.y * p[1] + q.z * p[2] < q.w);
+    }
     if (psi) ok = ok && !isnan(psi[i]);
     if (nu) ok = ok && (nu[i] > 0.0);
     if (!ok) atomicAdd(bad + b, 1);
@@ -291,12 +295,12 @@ __global__ void k_csr_fill(int64_t n, const int32_t *__restrict__ perm, const in
     }
 }
 
-__global__ void k_scatter_walls(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ ws,
+__global__ void k_scatter_walls(int64_t n, int nw, const int32_t *__restrict__ perm, const float *__restrict__ ws,
                                 float *__restrict__ w) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int64_t i = perm[k];
-    for (int a = 0; a < 6; ++a) w[i * 6 + a] = ws[k * 6 + a];
+    for (int a = 0; a < nw; ++a) w[i * nw + a] = ws[k * nw + a];
 }
 
 // Default start weights of the selected instances: one common weight per instance,
@@ -441,8 +445,8 @@ void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32
                        area, row_ptr);
 }
 
-void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const float *wall_s, float *wall) {
-    hipLaunchKernelGGL(k_scatter_walls, dim3(nblocks(n, 256)), dim3(256), 0, st, n, perm, wall_s, wall);
+void launch_scatter_walls(hipStream_t st, int64_t n, int nw, const int32_t *perm, const float *wall_s, float *wall) {
+    hipLaunchKernelGGL(k_scatter_walls, dim3(nblocks(n, 256)), dim3(256), 0, st, n, nw, perm, wall_s, wall);
 }
 
 void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float *y, const float *z,

@@ -90,7 +90,12 @@ struct Batch {
     const BoxF *box;             // [B]
     const double *rmax;          // [B] max sqrt(psi) over the instance (weights being evaluated)
     const int32_t *phase;        // [B] Phase
+    const float4 *dom;           // [ndom] convex domain planes (unit outward normal, offset c: n.x <= c)
+    int ndom;                    // 0: the box walls bound the cells
 };
+
+constexpr int DOM_MAX = 32;      // planes of a convex polyhedral domain
+constexpr int AUX_PLANE_ID = -1000000;  // ids of the clipper's auxiliary cube planes (walls: -1-w)
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD w mod 8),
 // and each XCD has its own L2. This maps the hardware workgroup id to a logical one
@@ -189,7 +194,7 @@ void launch_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int n, int
 void launch_csr_count(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcnt, int32_t *cnt_orig);
 void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcol, const float *farea,
                      const int32_t *fcnt, const int32_t *start, int32_t *col, float *area, int64_t *row_ptr);
-void launch_scatter_walls(hipStream_t st, int64_t n, const int32_t *perm, const float *wall_s, float *wall);
+void launch_scatter_walls(hipStream_t st, int64_t n, int nw, const int32_t *perm, const float *wall_s, float *wall);
 void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t *perm, const void *src, void *dst);
 void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *ev_nu, double *psi_s,
                           float4 *pos_s);
