@@ -10,6 +10,10 @@ Contents
                       centroids: the cell centroid of the pressure model, section 5)
   hessian(...)        gradient nu - V and the sparse matrix -Hess K (eq. (2))
   newton_solve(...)   damped Newton with KMT step control (Alg. 1)
+  p1_weights(...)     facet weights w_ij = |V_ij| / (2 |p_j - p_i|) of the P1 Laplacian (eq. (3))
+  p1_laplacian(...)   the P1 (cotan) Laplacian of a per-site field, optional mu_ij (eq. (3))
+  fluid_velocity(...) the semi-implicit velocity update with pressure spring, gravity,
+                      surface tension and viscosity (section 5, eq. (4))
 Parity pins for every function live in tests/test_oracle_*.py.
 """
 from __future__ import annotations
@@ -131,9 +135,25 @@ def hessian(xyz: np.ndarray, psi: np.ndarray, c: Cells):
     the two sides' facet areas (union pattern: a one-sided facet keeps its value).
     Diagonal: sum_j w_ij + K_i / (2 sqrt(psi_i)); box walls do not move with psi and
     do not enter. Empty cells give an empty row and column."""
+    W = p1_weights(xyz, c)
+    r = np.sqrt(np.maximum(psi, 0.0))
+    kterm = np.where(r > 0, c.K / (2.0 * np.where(r > 0, r, 1.0)), 0.0)
+    diag = np.asarray(W.sum(axis=1)).ravel() + kterm
+    import scipy.sparse as sp
+    H = (sp.diags(diag) - W).tocsr()
+    return H, diag
+
+
+def p1_weights(xyz: np.ndarray, c: Cells):
+    """Symmetric sparse matrix of the facet weights w_ij = Abar_ij / (2 |p_j - p_i|)
+    over the restricted Laguerre facets, from a full evaluation ``c``.
+
+    These are the off-diagonal weights of -Hess K (eq. (2)) and the weights of the P1
+    Laplacian of the fluid model (eq. (3)). Abar is the mean of the facet area seen
+    from the two cells; a facet that only one side lists keeps that side's value."""
     import scipy.sparse as sp
     n = xyz.shape[0]
-    assert c.idx.shape[0] == n and (c.idx == np.arange(n)).all(), "hessian needs all cells"
+    assert c.idx.shape[0] == n and (c.idx == np.arange(n)).all(), "weights need all cells"
     rows, cols, vals = [], [], []
     for i in range(n):
         k = int(c.fcount[i])
@@ -154,12 +174,68 @@ def hessian(xyz: np.ndarray, psi: np.ndarray, c: Cells):
     Abar = np.array([v / cnt[(i, j)] for i, j, v in zip(S.row.tolist(), S.col.tolist(), S.data.tolist())])
     d = np.linalg.norm(xyz[S.row] - xyz[S.col], axis=1)
     w = Abar / (2.0 * d)
-    W = sp.coo_matrix((w, (S.row, S.col)), shape=(n, n)).tocsr()
-    r = np.sqrt(np.maximum(psi, 0.0))
-    kterm = np.where(r > 0, c.K / (2.0 * np.where(r > 0, r, 1.0)), 0.0)
-    diag = np.asarray(W.sum(axis=1)).ravel() + kterm
-    H = (sp.diags(diag) - W).tocsr()
-    return H, diag
+    return sp.coo_matrix((w, (S.row, S.col)), shape=(n, n)).tocsr()
+
+
+def _mu_scaled(W, mu):
+    """W with entry (i,j) multiplied by mu_ij = (mu_i + mu_j) / 2 (mu: scalar or [n])."""
+    if np.ndim(mu) == 0:
+        return (W * float(mu)).tocsr()
+    mu = np.asarray(mu, np.float64)
+    C = W.tocoo()
+    import scipy.sparse as sp
+    return sp.coo_matrix((C.data * 0.5 * (mu[C.row] + mu[C.col]), (C.row, C.col)), shape=W.shape).tocsr()
+
+
+def p1_laplacian(W, u: np.ndarray, mu=1.0) -> np.ndarray:
+    """(Lap u)_i = sum_j mu_ij w_ij (u_j - u_i) for every column of u ([n] or [n,k]),
+    the P1 Laplacian of eq. (3); mu_ij = (mu_i + mu_j) / 2."""
+    Wm = _mu_scaled(W, mu)
+    u = np.asarray(u, np.float64)
+    deg = np.asarray(Wm.sum(axis=1)).ravel()
+    if u.ndim == 1:
+        return Wm @ u - deg * u
+    return Wm @ u - deg[:, None] * u
+
+
+@dataclass
+class FluidStep:
+    v: np.ndarray      # [n,3] velocities v^{k+1}
+    Fp: np.ndarray     # [n,3] pressure spring (c_i - p_i) / eps^2
+    Ft: np.ndarray     # [n,3] surface tension gamma Lap p
+    Fg: np.ndarray     # [n,3] gravity m_i g
+    cells: Cells
+    W: object          # P1 weights (scipy CSR)
+
+
+def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.ndarray, mu, dt: float,
+                   eps: float, gamma: float, gravity=(0.0, 0.0, 0.0), box=((0, 0, 0), (1, 1, 1)),
+                   domain=None) -> FluidStep:
+    """Velocity update of the fluid step, section 5: with the cells at the sites ``xyz``
+    and weights ``psi`` (normally the OT solution there),
+
+      F_p = (c_i - p_i) / eps^2        pressure spring to the cell centroid
+      F_g = m_i g                      gravity
+      F_t = gamma Lap p                surface tension, P1 Laplacian of the positions
+      (m_i/dt) v_i - (Lap_mu v)_i = (m_i/dt) v^k_i + F_p + F_g + F_t     (eq. (4))
+
+    solved exactly (sparse direct solve). Lap_mu is the P1 Laplacian with
+    mu_ij = (mu_i + mu_j) / 2. Boundary (wall) terms do not enter."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    xyz = np.asarray(xyz, np.float64)
+    n = xyz.shape[0]
+    c = cells(xyz[:, 0], xyz[:, 1], xyz[:, 2], psi, box, domain=domain)
+    W = p1_weights(xyz, c)
+    m = np.asarray(mass, np.float64)
+    Fp = (c.C - xyz) / (eps * eps)
+    Ft = gamma * p1_laplacian(W, xyz)
+    Fg = m[:, None] * np.asarray(gravity, np.float64)[None, :]
+    Wm = _mu_scaled(W, mu)
+    A = (sp.diags(m / dt + np.asarray(Wm.sum(axis=1)).ravel()) - Wm).tocsc()
+    b = (m / dt)[:, None] * np.asarray(v, np.float64) + Fp + Fg + Ft
+    vn = np.stack([sla.spsolve(A, b[:, k]) for k in range(3)], axis=1)
+    return FluidStep(vn, Fp, Ft, Fg, c, W)
 
 
 @dataclass
