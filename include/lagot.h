@@ -279,6 +279,60 @@ int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block);
  */
 int lagot_set_domain(lagot_ctx *ctx, int nplanes, const double *planes);
 
+/*
+ * The P1 Laplacian over the restricted Laguerre facets (section 5, eq. (3)):
+ *   (Lap u)_i = sum_j mu_ij w_ij (u_j - u_i),  w_ij = |V_ij| / (2 |p_j - p_i|),
+ * mu_ij = (mu_i + mu_j) / 2 (one reading of the paper's per-pair coefficients). |V_ij|
+ * is the facet area seen from the two cells, averaged (a facet that only one side
+ * lists keeps that side's area); wall and spherical facets do not enter.
+ *   in : the cells as lagot_cells (x, y, z [n] float32, psi [n] float64, box); mu [n]
+ *        float64 per-site coefficients or NULL (then mu_ij = mu0); u [3n] float64
+ *        (three values per site, site-major).
+ *   out: lap_u [3n] float64, site-major. Device pointers owned by the caller; u and
+ *        lap_u must not overlap. Synchronises the stream.
+ * Errors: EINVAL (as lagot_cells, or a negative or non-finite mu), ECAPACITY, EHIP.
+ */
+int lagot_p1_laplacian(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                       lagot_box box, const double *mu, double mu0, const double *u, double *lap_u);
+
+typedef struct {
+    double dt;          /* time step (> 0)                                                     */
+    double eps;         /* pressure spring F_p = (c_i - p_i) / eps^2 (> 0; +inf: no spring)    */
+    double gamma;       /* surface tension F_t = gamma Lap p (>= 0)                            */
+    double mu;          /* viscosity of every site when the per-site array is NULL (>= 0)      */
+    double gravity[3];  /* gravity (acceleration): F_g = m_i g                                 */
+    double cg_rtol;     /* PCG stop ||r|| <= cg_rtol ||b|| per coordinate   (default 1e-10)    */
+    int cg_max_iter;    /* PCG iteration limit per coordinate               (default 2000)     */
+    int reserved;
+} lagot_fluid_params;
+
+/* dt 1e-3, eps 1, gamma 0, mu 0, gravity (0, 0, -9.81), cg_rtol 1e-10, cg_max_iter 2000 */
+void lagot_default_fluid_params(lagot_fluid_params *prm);
+
+/*
+ * Velocity update of the fluid step (section 5, "Numerical integration", eq. (4)):
+ * with the cells at the sites p and weights psi (normally the OT solution there) and
+ * their centroids c_i,
+ *   F_p = (c_i - p_i) / eps^2,  F_g = m_i g,  F_t = gamma Lap p  (mu_ij = 1 here),
+ *   (m_i/dt) v_i - (Lap_mu v)_i = (m_i/dt) v_in_i + F_p + F_g + F_t,
+ * solved for v by Jacobi-PCG, one solve per coordinate (Lap_mu as lagot_p1_laplacian;
+ * the system is symmetric positive definite). Positions are not moved: the step's
+ * position update x += dt v is the caller's. Wall terms (fluid-boundary affinities)
+ * do not enter.
+ *   in : x, y, z [n] float32, psi [n] float64, box; mass [n] float64 (> 0); mu [n]
+ *        float64 per-site viscosity or NULL (then prm->mu); v_in [3n] float64
+ *        site-major; prm HOST pointer.
+ *   out: v_out [3n] float64 site-major (may equal v_in); centroid [3n] float64 or NULL;
+ *        cg_iters [3] HOST int32 PCG iterations per coordinate, or NULL. Device
+ *        pointers owned by the caller. Synchronises the stream.
+ * Errors: EINVAL (as lagot_cells, bad parameters, a mass <= 0, a negative mu, a
+ *         non-finite value), ENOCONV (cg_max_iter iterations without the tolerance),
+ *         ESINGULAR (PCG breakdown), ECAPACITY, EHIP.
+ */
+int lagot_fluid_velocity(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                         const double *psi, lagot_box box, const double *mass, const double *mu, const double *v_in,
+                         const lagot_fluid_params *prm, double *v_out, double *centroid, int32_t *cg_iters);
+
 /* Number of cells that the last lagot_cells call on this context redid on the
  * large-capacity float64 path (diagnostic; -1 if ctx is NULL). */
 int lagot_last_fallback_cells(const lagot_ctx *ctx);

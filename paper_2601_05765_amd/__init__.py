@@ -23,6 +23,7 @@ OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
            "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
+           "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
@@ -30,6 +31,24 @@ MLP_NPARAMS = 41473
 
 class Box(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class FluidParams(ctypes.Structure):
+    """lagot_fluid_params: the velocity update of the fluid step (section 5, eq. (4))."""
+    _fields_ = [("dt", ctypes.c_double), ("eps", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("mu", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("cg_rtol", ctypes.c_double),
+                ("cg_max_iter", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+def default_fluid_params(**kw) -> FluidParams:
+    p = FluidParams()
+    load().lagot_default_fluid_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "gravity":
+            p.gravity = (ctypes.c_double * 3)(*[float(a) for a in v])
+        else:
+            setattr(p, k, v)
+    return p
 
 
 class Opts(ctypes.Structure):
@@ -100,6 +119,13 @@ def load():
         lib.lagot_set_domain.restype = I
         lib.lagot_centroids.argtypes = [P, I64, P, P, P, P, Box, P, P]
         lib.lagot_centroids.restype = I
+        lib.lagot_p1_laplacian.argtypes = [P, I64, P, P, P, P, Box, P, ctypes.c_double, P, P]
+        lib.lagot_p1_laplacian.restype = I
+        lib.lagot_default_fluid_params.argtypes = [ctypes.POINTER(FluidParams)]
+        lib.lagot_default_fluid_params.restype = None
+        lib.lagot_fluid_velocity.argtypes = [P, I64, P, P, P, P, Box, P, P, P, ctypes.POINTER(FluidParams), P, P,
+                                             ctypes.POINTER(ctypes.c_int32 * 3)]
+        lib.lagot_fluid_velocity.restype = I
         lib.lagot_last_flag_counts.argtypes = [P, P]
         lib.lagot_last_flag_counts.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
@@ -227,6 +253,47 @@ class Context:
         if rc != OK:
             raise LagotError(rc, "lagot_centroids")
         return vol, cen
+
+    def p1_laplacian(self, x, y, z, psi, u, mu=None, mu0: float = 1.0, box=((0, 0, 0), (1, 1, 1))):
+        """lagot_p1_laplacian: Lap_mu u ([n, 3] float64, caller order) over the restricted
+        Laguerre facets (eq. (3)); mu: per-site coefficients [n] or None (mu0)."""
+        import torch
+        n = x.shape[0]
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(psi, torch.float64, "psi")]
+        if tuple(u.shape) != (n, 3) or (mu is not None and tuple(mu.shape) != (n,)):
+            raise ValueError("u must be [n, 3] and mu [n]")
+        u_p = _dev(u, torch.float64, "u")
+        mu_p = None if mu is None else _dev(mu, torch.float64, "mu")
+        out = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        rc = load().lagot_p1_laplacian(self._h, n, *args, make_box(box), mu_p, float(mu0), u_p,
+                                       ctypes.c_void_p(out.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_p1_laplacian")
+        return out
+
+    def fluid_velocity(self, x, y, z, psi, mass, v, params=None, mu=None, box=((0, 0, 0), (1, 1, 1))):
+        """lagot_fluid_velocity: (v_new [n, 3], centroids [n, 3], PCG iterations per
+        coordinate) of the semi-implicit velocity update (section 5, eq. (4))."""
+        import torch
+        n = x.shape[0]
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(psi, torch.float64, "psi")]
+        if tuple(v.shape) != (n, 3) or tuple(mass.shape) != (n,) or (mu is not None and tuple(mu.shape) != (n,)):
+            raise ValueError("mass and mu must be [n], v [n, 3]")
+        m_p = _dev(mass, torch.float64, "mass")
+        v_p = _dev(v, torch.float64, "v")
+        mu_p = None if mu is None else _dev(mu, torch.float64, "mu")
+        prm = params if params is not None else default_fluid_params()
+        out = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        cen = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        it = (ctypes.c_int32 * 3)()
+        rc = load().lagot_fluid_velocity(self._h, n, *args, make_box(box), m_p, mu_p, v_p, ctypes.byref(prm),
+                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(cen.data_ptr()),
+                                         ctypes.byref(it))
+        if rc != OK:
+            raise LagotError(rc, "lagot_fluid_velocity")
+        return out, cen, list(it)
 
     def set_domain(self, planes=None) -> None:
         """lagot_set_domain: planes [P, 4] (unit outward normal, c) of the convex domain

@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblagot.so")
 ARCH = os.environ.get("LAGOT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["grid.hip", "cells.hip", "newton.hip", "mlp.hip", "api.cpp"]
+SOURCES = ["grid.hip", "cells.hip", "newton.hip", "fluid.hip", "mlp.hip", "api.cpp"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -81,6 +81,8 @@ struct lagot_ctx {
     float *wall = nullptr;
     int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr, *ovf_list = nullptr;
     double *cen_out = nullptr;  // caller's centroid array during a lagot_centroids call
+    double *fl_buf = nullptr;   // fluid step: right-hand sides [3n], zeros [n], centroids [3n]
+    int64_t cap_fl = 0;
     float4 *dom_d = nullptr;    // [DOM_MAX] convex domain planes (lagot_set_domain)
     int ndom = 0;
     int wall_w = 6;             // wall areas per site in the wall buffer (6, or the domain's planes)
@@ -200,7 +202,8 @@ void free_all(lagot_ctx *c) {
     free_alt(c);
     free_sites(c);
     free_inst(c);
-    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d);
+    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf);
+    c->cap_fl = 0;
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_rd) (void)hipHostFree(c->h_rd);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
@@ -1078,6 +1081,36 @@ int single_instance(lagot_ctx *c, int64_t n, const float *x, const float *y, con
 
 }  // namespace
 
+// Cells at (x, psi) with their facet weights: the P1 Laplacian's w_ij in hcol/hval/hcnt
+// (grid order, sorted rows), and the centroids into cen (caller order) when given.
+int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                const lagot_box &box, double *cen) {
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    c->tpc = c->tpc_default;
+    c->ms_cell = 0.0;
+    c->cell_launches = 0;
+    c->ev_pending = false;
+    const int64_t offs[2] = {0, n};
+    int rc = prepare(c, 1, offs, x, y, z, psi, nullptr, &box, nullptr);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    launch_zero_i32(st, c->fb_inst, 1);
+    c->cen_out = cen;
+    evaluate(c, -1, c->psi_s, false, nullptr);
+    c->cen_out = nullptr;
+    const Batch bt = batch(c);
+    launch_hess_assemble(st, n, bt, -1, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval, c->xcnt, c->herr);
+    launch_hess_finish(st, n, bt, -1, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hcol, c->hval, c->diag);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->misc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 2, c->herr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    rc = sync(c);
+    if (rc) return rc;
+    c->last_fb = c->h_cnt[0];
+    if (c->h_cnt[1] != 0 || c->h_cnt[2] != 0) return LAGOT_ECAPACITY;
+    return LAGOT_OK;
+}
+
 extern "C" {
 
 void lagot_default_opts(lagot_opts *opts) {
@@ -1359,6 +1392,92 @@ int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts) {
 }
 
 double lagot_last_cell_kernel_ms(const lagot_ctx *ctx) { return ctx ? ctx->ms_cell : -1.0; }
+
+void lagot_default_fluid_params(lagot_fluid_params *prm) {
+    if (!prm) return;
+    *prm = lagot_fluid_params{};
+    prm->dt = 1e-3;
+    prm->eps = 1.0;
+    prm->gamma = 0.0;
+    prm->mu = 0.0;
+    prm->gravity[2] = -9.81;
+    prm->cg_rtol = 1e-10;
+    prm->cg_max_iter = 2000;
+}
+
+int lagot_p1_laplacian(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                       lagot_box box, const double *mu, double mu0, const double *u, double *lap_u) {
+    if (!c || !u || !lap_u || n <= 0) return LAGOT_EINVAL;
+    if (!mu && !(mu0 >= 0.0 && std::isfinite(mu0))) return LAGOT_EINVAL;
+    int rc = fluid_cells(c, n, x, y, z, psi, box, nullptr);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    launch_zero_i32(st, c->bad_inst, 1);
+    launch_p1_laplacian(st, n, c->perm, c->hcol, c->hval, c->hcnt, mu, mu0, u, lap_u, c->bad_inst);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->bad_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    rc = sync(c);
+    if (rc) return rc;
+    return c->h_cnt[0] ? LAGOT_EINVAL : LAGOT_OK;
+}
+
+int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z,
+                         const double *psi, lagot_box box, const double *mass, const double *mu, const double *v_in,
+                         const lagot_fluid_params *prm, double *v_out, double *centroid, int32_t *cg_iters) {
+    if (!c || !mass || !v_in || !prm || !v_out || n <= 0) return LAGOT_EINVAL;
+    const lagot_fluid_params &p = *prm;
+    bool ok = p.dt > 0.0 && std::isfinite(p.dt) && p.eps > 0.0 && !std::isnan(p.eps) && p.gamma >= 0.0 &&
+              std::isfinite(p.gamma) && p.cg_rtol > 0.0 && p.cg_rtol < 1.0 && p.cg_max_iter >= 1 &&
+              (mu || (p.mu >= 0.0 && std::isfinite(p.mu)));
+    for (int a = 0; a < 3; ++a) ok = ok && std::isfinite(p.gravity[a]);
+    if (!ok) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    if (n > c->cap_fl) {
+        free_ptrs(c->fl_buf);
+        c->cap_fl = 0;
+        HIP_TRY(dalloc(&c->fl_buf, 7 * (size_t)n));
+        c->cap_fl = n;
+    }
+    double *b = c->fl_buf, *zero = c->fl_buf + 3 * n, *cen = centroid ? centroid : c->fl_buf + 4 * n;
+    int rc = fluid_cells(c, n, x, y, z, psi, box, cen);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    FluidPrm fp;
+    fp.dt = p.dt;
+    fp.inv_eps2 = 1.0 / (p.eps * p.eps);
+    fp.gamma = p.gamma;
+    fp.mu = p.mu;
+    for (int a = 0; a < 3; ++a) fp.g[a] = p.gravity[a];
+    launch_zero_i32(st, c->bad_inst, 1);
+    launch_fluid_rows(st, n, c->perm, c->pos_s, c->hcol, c->hval, c->hcnt, mass, mu, fp, v_in, cen, c->diag, b,
+                      c->bad_inst);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt, c->bad_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    rc = sync(c);
+    if (rc) return rc;
+    if (c->h_cnt[0]) return LAGOT_EINVAL;
+    // one Jacobi-PCG solve per coordinate: "V" = 0 and "nu" = b_c give r_0 = b_c, x_0 = 0
+    launch_zero_f64(st, zero, n);
+    launch_fill_i32(st, c->phase, 1, PH_ACTIVE);
+    lagot_opts o;
+    fill_defaults(&o);
+    o.cg_rtol = p.cg_rtol;
+    o.cg_max_iter = p.cg_max_iter;
+    const Batch bt = batch(c);
+    const CgBufs cg = cg_bufs(c);
+    int status = LAGOT_OK;
+    for (int comp = 0; comp < 3; ++comp) {
+        launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, zero, b + comp * n, c->diag, c->hcol, c->hval, c->hcnt, cg);
+        int k = 0;
+        rc = run_cg(c, o, &k, false, false);
+        if (rc) return rc;
+        launch_scatter_comp(st, n, c->perm, cg.x, comp, v_out);
+        HIP_TRY(hipMemcpyAsync(c->h_cnt + 8, c->cg_cgst, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        rc = sync(c);
+        if (rc) return rc;
+        if (cg_iters) cg_iters[comp] = c->h_cnt[8];
+        if (c->h_cnt[10] == 0 && status == LAGOT_OK) status = c->h_cnt[9] ? LAGOT_ESINGULAR : LAGOT_ENOCONV;
+    }
+    return status;
+}
 
 const char *lagot_strerror(int code) {
     switch (code) {

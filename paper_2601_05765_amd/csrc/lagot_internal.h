@@ -173,6 +173,15 @@ struct CgBufs {
     int32_t *remaining;      // [1] instances still iterating after the last chunk
 };
 
+// Parameters of the velocity system of the fluid step (section 5, eq. (4)).
+struct FluidPrm {
+    double dt;        // time step
+    double inv_eps2;  // 1 / eps^2 of the pressure spring
+    double gamma;     // surface tension
+    double mu;        // viscosity of every site when no per-site array is given
+    double g[3];      // gravity (acceleration)
+};
+
 // ---- launch wrappers (defined in the .hip files) ----
 // grid.hip
 void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst);
@@ -243,6 +252,21 @@ void launch_ctl_decide(hipStream_t st, const Batch &bt, CtlOpts o, const double 
 void launch_accept_rows(hipStream_t st, const Batch &bt, const InstCtl *ctl, double *psi_s, const double *psi_trial,
                         float4 *pos_s);
 void launch_ctl_commit(hipStream_t st, const Batch &bt, CtlOpts o, InstCtl *ctl, int32_t *phase, int32_t *counts);
+
+// fluid.hip
+// Rows of the velocity system in grid order: rescales hval from w_ij to mu_ij w_ij,
+// diag = m/dt + row sum, b[c*n + i] = right-hand side of coordinate c; bad counts
+// invalid masses, viscosities and velocities.
+void launch_fluid_rows(hipStream_t st, int64_t n, const int32_t *perm, const float4 *pos_s, const int32_t *hcol,
+                       float *hval, const int32_t *hcnt, const double *mass, const double *mu, const FluidPrm &fp,
+                       const double *v, const double *cen, double *diag, double *b, int32_t *bad);
+// out = Lap_mu u (caller order, [3n]); mu == null: mu_ij = mu0
+void launch_p1_laplacian(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *hcol, const float *hval,
+                         const int32_t *hcnt, const double *mu, double mu0, const double *u, double *out,
+                         int32_t *bad);
+void launch_scatter_comp(hipStream_t st, int64_t n, const int32_t *perm, const double *x, int comp, double *out);
+void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t value);
+void launch_zero_f64(hipStream_t st, double *p, int64_t count);
 
 // mlp.hip
 void launch_knn_features(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm,

@@ -1,0 +1,226 @@
+"""The fluid model's P1 Laplacian (eq. (3)) and semi-implicit velocity update (eq. (4))
+against the FP64 oracle, through the C-ABI (lagot_p1_laplacian, lagot_fluid_velocity).
+
+Tolerances follow from the cell parity bounds (float32 geometry): a facet area is within
+1e-5 pi r^2 of the oracle's and a centroid within 1e-5 r, so a row of the Laplacian is
+within T_i = 2e-5 sum_j mu_ij pi max(r_i, r_j)^2 |u_j - u_i| / (2 d_ij); the velocity
+system is an M-matrix with diagonal excess m_i/dt, so ||dv||_inf <= max(dt/m) times the
+largest row error of the right-hand side and of the matrix applied to v."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_05765_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2601_05765_amd as L
+    assert torch.cuda.is_available()
+    return L.Context()
+
+
+def _t(a, dt):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def _sites(sc):
+    import torch
+    return _t(sc.x, torch.float32), _t(sc.y, torch.float32), _t(sc.z, torch.float32)
+
+
+def _xyz(sc):
+    # the float32 positions are the input of both sides
+    return np.stack([np.float32(sc.x), np.float32(sc.y), np.float32(sc.z)], 1).astype(np.float64)
+
+
+def _row_tol(W, psi, xyz, u, mu, rel=2e-5):
+    """T_i = rel * sum_j mu_ij pi max(r_i, r_j)^2 |u_j - u_i| / (2 d_ij) for every row."""
+    C = W.tocoo()
+    r = np.sqrt(np.maximum(psi, 0))
+    mu = np.broadcast_to(np.asarray(mu, np.float64), (xyz.shape[0],))
+    muij = 0.5 * (mu[C.row] + mu[C.col])
+    d = np.linalg.norm(xyz[C.row] - xyz[C.col], axis=1)
+    rr = np.maximum(r[C.row], r[C.col])
+    du = np.abs(u[C.col] - u[C.row]).max(axis=1) if u.ndim == 2 else np.abs(u[C.col] - u[C.row])
+    t = muij * math.pi * rr * rr * du / (2 * d)
+    return rel * np.bincount(C.row, weights=t, minlength=xyz.shape[0])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_p1_laplacian_parity(ctx, oracle_mod, seed):
+    import torch
+    n = 2500
+    _say(f"case: P1 Laplacian, dam_break {n}, seed {seed}")
+    sc = scenes.dam_break(n, seed)
+    xyz = _xyz(sc)
+    rng = np.random.default_rng(10 + seed)
+    u = rng.normal(size=(n, 3))
+    mu = rng.uniform(0.0, 3.0, n)
+    x, y, z = _sites(sc)
+    psi = _t(sc.psi0, torch.float64)
+    got = ctx.p1_laplacian(x, y, z, psi, _t(u, torch.float64), mu=_t(mu, torch.float64)).cpu().numpy()
+    got_p = ctx.p1_laplacian(x, y, z, psi, _t(xyz, torch.float64)).cpu().numpy()
+    c = oracle_mod.cells(xyz[:, 0], xyz[:, 1], xyz[:, 2], sc.psi0)
+    W = oracle_mod.p1_weights(xyz, c)
+    want = oracle_mod.p1_laplacian(W, u, mu)
+    want_p = oracle_mod.p1_laplacian(W, xyz)
+    tol = _row_tol(W, sc.psi0, xyz, u, mu) + 1e-14
+    tol_p = _row_tol(W, sc.psi0, xyz, xyz, 1.0) + 1e-14
+    e = np.abs(got - want).max(axis=1) / tol
+    e_p = np.abs(got_p - want_p).max(axis=1) / tol_p
+    _say(f"  max err / bound: field {e.max():.3f}, positions {e_p.max():.3f}")
+    assert e.max() <= 1.0 and e_p.max() <= 1.0
+
+
+def test_p1_laplacian_two_balls_closed_form(ctx):
+    import torch
+    r, d = 0.1, 0.12
+    x = _t([0.4, 0.4 + d], torch.float32)
+    y = _t([0.5, 0.5], torch.float32)
+    z = _t([0.5, 0.5], torch.float32)
+    xs = np.array([np.float32(0.4), np.float32(0.4 + d)], np.float64)
+    dd = xs[1] - xs[0]
+    psi = _t([r * r, r * r], torch.float64)
+    P = np.stack([xs, [np.float32(0.5)] * 2, [np.float32(0.5)] * 2], 1)
+    got = ctx.p1_laplacian(x, y, z, psi, _t(P, torch.float64)).cpu().numpy()
+    a2 = r * r - dd * dd / 4
+    assert np.allclose(got[0], [math.pi * a2 / 2, 0, 0], rtol=1e-5, atol=1e-9)
+    assert np.allclose(got[1], -got[0], rtol=0, atol=1e-12)
+
+
+def _fluid_case(n, seed):
+    sc = scenes.dam_break(n, seed)
+    rng = np.random.default_rng(100 + seed)
+    v = rng.normal(size=(n, 3))
+    mu = rng.uniform(0.0, 0.5, n)
+    mass = np.asarray(sc.nu, np.float64)
+    return sc, v, mu, mass
+
+
+@pytest.mark.parametrize("seed,eps,gamma", [(0, 0.2, 0.05), (1, 0.1, 0.0), (2, float("inf"), 0.3)])
+def test_fluid_velocity_parity(ctx, oracle_mod, seed, eps, gamma):
+    import torch
+    import paper_2601_05765_amd as L
+    n = 2500
+    _say(f"case: fluid velocity, dam_break {n}, seed {seed}, eps {eps}, gamma {gamma}")
+    sc, v, mu, mass = _fluid_case(n, seed)
+    xyz = _xyz(sc)
+    dt = 2e-3
+    prm = L.default_fluid_params(dt=dt, eps=eps, gamma=gamma, gravity=(0.0, 0.0, -9.81))
+    x, y, z = _sites(sc)
+    got, cen, its = ctx.fluid_velocity(x, y, z, _t(sc.psi0, torch.float64), _t(mass, torch.float64),
+                                       _t(v, torch.float64), prm, mu=_t(mu, torch.float64))
+    got = got.cpu().numpy()
+    st = oracle_mod.fluid_velocity(xyz, sc.psi0, v, mass, mu, dt=dt, eps=eps, gamma=gamma, gravity=(0, 0, -9.81))
+    r = np.sqrt(sc.psi0)
+    inv_e2 = 0.0 if math.isinf(eps) else 1.0 / (eps * eps)
+    rhs_err = 1e-5 * r * inv_e2 + gamma * _row_tol(st.W, sc.psi0, xyz, xyz, 1.0)
+    mat_err = _row_tol(st.W, sc.psi0, xyz, st.v, mu)
+    bound = 2.0 * (dt / mass.min()) * (rhs_err + mat_err).max() + 1e-8 * np.abs(st.v).max()
+    err = np.abs(got - st.v).max()
+    _say(f"  PCG iterations {its}, max |dv| {err:.3e}, bound {bound:.3e}, max |v| {np.abs(st.v).max():.3f}")
+    assert err <= bound
+    assert np.abs(cen.cpu().numpy() - st.cells.C).max() <= 1e-5 * r.max()
+
+
+def test_fluid_velocity_explicit_when_mu_is_zero(ctx, oracle_mod):
+    import torch
+    import paper_2601_05765_amd as L
+    n = 1500
+    sc, v, _, mass = _fluid_case(n, 3)
+    xyz = _xyz(sc)
+    dt = 1e-3
+    prm = L.default_fluid_params(dt=dt, eps=0.3, gamma=0.2, mu=0.0)
+    x, y, z = _sites(sc)
+    got, _, its = ctx.fluid_velocity(x, y, z, _t(sc.psi0, torch.float64), _t(mass, torch.float64),
+                                     _t(v, torch.float64), prm)
+    st = oracle_mod.fluid_velocity(xyz, sc.psi0, v, mass, 0.0, dt=dt, eps=0.3, gamma=0.2, gravity=(0, 0, -9.81))
+    r = np.sqrt(sc.psi0)
+    bound = 2.0 * (dt / mass) * (1e-5 * r / 0.09 + 0.2 * _row_tol(st.W, sc.psi0, xyz, xyz, 1.0)) + 1e-12
+    err = np.abs(got.cpu().numpy() - st.v).max(axis=1)
+    _say(f"  PCG iterations {its}, max err / bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("per_site", [False, True])
+def test_fluid_velocity_full_size_invariants(ctx, per_site):
+    """100,000-site dam break (the measured workload): a constant velocity field with no
+    forces is kept, and with gravity and surface tension only the total momentum grows by
+    dt g sum m (the P1 Laplacian's rows and columns sum to zero)."""
+    import torch
+    import paper_2601_05765_amd as L
+    n = 100_000
+    _say(f"case: fluid velocity invariants, dam_break {n}, per-site mu {per_site}")
+    sc = scenes.dam_break(n, 0)
+    rng = np.random.default_rng(7)
+    mu = _t(rng.uniform(0.0, 2.0, n), torch.float64) if per_site else None
+    mass = _t(sc.nu, torch.float64)
+    x, y, z = _sites(sc)
+    psi = _t(sc.psi0, torch.float64)
+    U = torch.tensor([0.3, -1.2, 0.45], dtype=torch.float64, device="cuda").repeat(n, 1).contiguous()
+    prm = L.default_fluid_params(dt=2e-3, eps=float("inf"), gamma=0.0, mu=1.0, gravity=(0.0, 0.0, 0.0))
+    v1, _, its = ctx.fluid_velocity(x, y, z, psi, mass, U, prm, mu=mu)
+    e = (v1 - U).abs().max().item()
+    _say(f"  constant field: PCG iterations {its}, max |v - U| {e:.2e}")
+    assert e <= 1e-8
+    v0 = _t(rng.normal(size=(n, 3)), torch.float64)
+    prm = L.default_fluid_params(dt=2e-3, eps=float("inf"), gamma=0.5, mu=1.0, gravity=(0.0, 0.0, -9.81))
+    v2, _, its = ctx.fluid_velocity(x, y, z, psi, mass, v0, prm, mu=mu)
+    m = mass[:, None]
+    got = (m * v2).sum(0).cpu().numpy()
+    want = (m * v0).sum(0).cpu().numpy() + 2e-3 * np.array([0, 0, -9.81]) * float(mass.sum())
+    scale = float((m * v0.abs()).sum())
+    _say(f"  momentum: PCG iterations {its}, error {np.abs(got - want).max() / scale:.2e} (relative)")
+    assert np.abs(got - want).max() <= 1e-8 * scale
+    # kinetic energy of the viscous part does not grow
+    prm0 = L.default_fluid_params(dt=2e-3, eps=float("inf"), gamma=0.0, mu=1.0, gravity=(0.0, 0.0, 0.0))
+    v3, _, _ = ctx.fluid_velocity(x, y, z, psi, mass, v0, prm0, mu=mu)
+    assert float((m * v3 * v3).sum()) < float((m * v0 * v0).sum())
+
+
+def test_fluid_velocity_single_site(ctx):
+    import torch
+    import paper_2601_05765_amd as L
+    x = _t([0.5], torch.float32)
+    y = _t([0.5], torch.float32)
+    z = _t([0.5], torch.float32)
+    psi = _t([0.1 ** 2], torch.float64)
+    mass = _t([2e-3], torch.float64)
+    v = _t([[1.0, 2.0, 3.0]], torch.float64)
+    prm = L.default_fluid_params(dt=0.01, eps=0.1, gamma=1.0, mu=5.0, gravity=(0.0, 0.0, -9.81))
+    out, cen, its = ctx.fluid_velocity(x, y, z, psi, mass, v, prm)
+    # one isolated ball: centroid = site, no facets, so v + dt g
+    assert np.allclose(out.cpu().numpy(), [[1.0, 2.0, 3.0 - 0.0981]], rtol=0, atol=1e-12)
+    assert np.allclose(cen.cpu().numpy(), [[0.5, 0.5, 0.5]], atol=0)
+
+
+def test_fluid_velocity_rejects_bad_input(ctx):
+    import torch
+    import paper_2601_05765_amd as L
+    sc, v, _, mass = _fluid_case(500, 4)
+    x, y, z = _sites(sc)
+    psi = _t(sc.psi0, torch.float64)
+    bad = mass.copy()
+    bad[17] = 0.0
+    with pytest.raises(L.LagotError) as ei:
+        ctx.fluid_velocity(x, y, z, psi, _t(bad, torch.float64), _t(v, torch.float64))
+    assert ei.value.code == L.EINVAL
+    with pytest.raises(L.LagotError) as ei:
+        ctx.fluid_velocity(x, y, z, psi, _t(mass, torch.float64), _t(v, torch.float64),
+                           L.default_fluid_params(dt=0.0))
+    assert ei.value.code == L.EINVAL
+    # the context still works after the rejected calls
+    out, _, _ = ctx.fluid_velocity(x, y, z, psi, _t(mass, torch.float64), _t(v, torch.float64))
+    assert torch.isfinite(out).all()
