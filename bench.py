@@ -191,6 +191,42 @@ def learned_section(ctx, L, scenes, n_seeds: int, train_steps: int, steps: int):
             "status_plain": [r["status"] for r in a], "status_learned": [r["status"] for r in b]}
 
 
+def fluid_section(ctx, L, x, y, z, psi, nu, reps: int = 10, steps: int = 5):
+    """The fluid step's velocity update (lagot_fluid_velocity: cells and centroids at the
+    converged weights, facet weights, right-hand sides, three Jacobi-PCG solves) on the
+    bench workload, per-site viscosity in [0, 2], density 1 (m = nu); then whole fluid
+    steps (lagot_fluid_step) from rest under gravity."""
+    import torch
+    n = x.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(3)
+    v = torch.randn((n, 3), generator=g, dtype=torch.float64, device="cuda")
+    mu = 2.0 * torch.rand(n, generator=g, dtype=torch.float64, device="cuda")
+    prm = L.default_fluid_params(dt=2e-3, eps=0.1, gamma=0.05)
+    for _ in range(2):
+        ctx.fluid_velocity(x, y, z, psi, nu, v, prm, mu=mu)
+    torch.cuda.synchronize()
+    ms, its = [], None
+    for _ in range(reps):
+        a = time.perf_counter()
+        _, _, its = ctx.fluid_velocity(x, y, z, psi, nu, v, prm, mu=mu)
+        torch.cuda.synchronize()
+        ms.append(1000.0 * (time.perf_counter() - a))
+    # whole steps of the dam break from rest (move, re-solve from the last weights, update
+    # the velocities), on copies of the sites
+    xs, ys, zs, ps = x.clone(), y.clone(), z.clone(), psi.clone()
+    vs = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    step_ms, newton = [], []
+    for _ in range(steps):
+        a = time.perf_counter()
+        st, _ = ctx.fluid_step(xs, ys, zs, nu, ps, nu, vs, prm, opts=L.default_opts(tol=1e-5), mu=mu)
+        torch.cuda.synchronize()
+        step_ms.append(1000.0 * (time.perf_counter() - a))
+        newton.append(st.newton_iters)
+    return {"ms_fluid_velocity": float(np.median(ms)), "pcg_iters": its, "dt": prm.dt, "eps": prm.eps,
+            "gamma": prm.gamma, "mu": "per site, uniform in [0, 2]", "ms_per_fluid_step": step_ms,
+            "newton_iters_per_step": newton}
+
+
 def splash_section(ctx, L, scenes, n: int, steps: int):
     """The large-scene recipe (slab + 200 over-packed droplets, log-normal nu, random
     velocities) at n sites: the first solve from the Voronoi start, then `steps`
@@ -239,6 +275,7 @@ def main(argv=None):
     ap.add_argument("--learned-steps", type=int, default=4, help="advect-and-solve steps per training scene")
     ap.add_argument("--sequence-steps", type=int, default=5)
     ap.add_argument("--no-splash", action="store_true", help="skip the over-packed splash sequence")
+    ap.add_argument("--no-fluid", action="store_true", help="skip the fluid-step velocity update")
     ap.add_argument("--splash-n", type=int, default=200_000)
     ap.add_argument("--splash-steps", type=int, default=5)
     args = ap.parse_args(argv)
@@ -333,6 +370,8 @@ def main(argv=None):
                       "centroids_converged": {"ms_lagot_centroids": evc, "ms_cell_kernel": kc,
                                               "cells_per_s_kernel": args.n / (kc / 1000.0)}},
     }
+    if not args.no_fluid:
+        line["fluid"] = fluid_section(ctx, L, x, y, z, psis[-1], nu)
     if not args.no_batched:
         line["batched"] = batched_section(ctx, L, scenes)
     if not args.no_splash:

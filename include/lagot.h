@@ -333,6 +333,28 @@ int lagot_fluid_velocity(lagot_ctx *ctx, int64_t n, const float *x, const float 
                          const double *psi, lagot_box box, const double *mass, const double *mu, const double *v_in,
                          const lagot_fluid_params *prm, double *v_out, double *centroid, int32_t *cg_iters);
 
+/*
+ * One whole fluid step (section 5, "Numerical integration"): the positions move with the
+ * old velocities, x <- x + dt v, the weights are re-solved at the new positions
+ * (Algorithm 1 from psi_inout, as lagot_solve), and the velocities are updated at the
+ * new cells as lagot_fluid_velocity. The moved positions are kept inside the domain:
+ * each coordinate is clamped to [lo + m_a, hi - m_a], m_a = 1e-6 (hi_a - lo_a), and,
+ * with convex domain planes (lagot_set_domain), a site beyond n.x = c - m
+ * (m = 1e-6 times the largest box extent) is moved along -n onto that plane, in two
+ * passes over the planes. The update x + dt v is formed in float64 with separate
+ * roundings and rounded once to float32.
+ *   in/out: x, y, z [n] float32 (device), psi_inout [n] float64, v_inout [3n] float64
+ *           site-major; in: nu [n] float64, mass [n] float64 (> 0), mu [n] or NULL,
+ *           prm, opts (NULL = defaults) HOST; out: stats (the solve's, HOST, may be
+ *           NULL), cg_iters [3] HOST int32 or NULL.
+ * Errors: those of lagot_solve and lagot_fluid_velocity. After a solve error the
+ *         positions have moved, psi_inout holds the solve's last accepted weights and
+ *         v_inout is unchanged. Synchronises the stream.
+ */
+int lagot_fluid_step(lagot_ctx *ctx, int64_t n, float *x, float *y, float *z, const double *nu, lagot_box box,
+                     double *psi_inout, const double *mass, const double *mu, double *v_inout,
+                     const lagot_fluid_params *prm, const lagot_opts *opts, lagot_stats *stats, int32_t *cg_iters);
+
 /* Number of cells that the last lagot_cells call on this context redid on the
  * large-capacity float64 path (diagnostic; -1 if ctx is NULL). */
 int lagot_last_fallback_cells(const lagot_ctx *ctx);

@@ -14,6 +14,7 @@ Contents
   p1_laplacian(...)   the P1 (cotan) Laplacian of a per-site field, optional mu_ij (eq. (3))
   fluid_velocity(...) the semi-implicit velocity update with pressure spring, gravity,
                       surface tension and viscosity (section 5, eq. (4))
+  advect(...)         the position update x + dt v of the fluid step, kept inside the domain
 Parity pins for every function live in tests/test_oracle_*.py.
 """
 from __future__ import annotations
@@ -196,6 +197,37 @@ def p1_laplacian(W, u: np.ndarray, mu=1.0) -> np.ndarray:
     if u.ndim == 1:
         return Wm @ u - deg * u
     return Wm @ u - deg[:, None] * u
+
+
+ADVECT_MARGIN = 1e-6
+
+
+def advect(xyz32: np.ndarray, v: np.ndarray, dt: float, box=((0, 0, 0), (1, 1, 1)), domain=None) -> np.ndarray:
+    """Position update of the fluid step (section 5, numerical integration):
+    x + dt v in float64, kept inside the domain, rounded once to float32.
+
+    Reading (the paper does not say how sites are kept in the domain): each coordinate
+    is clamped to [lo + m_a, hi - m_a] with m_a = 1e-6 (hi_a - lo_a); then, for convex
+    domain planes n.x <= c, a site with n.x - c + m > 0 (m = 1e-6 times the largest box
+    extent) is moved by that amount along -n, in two passes over the planes in order.
+    Every product and sum is rounded separately."""
+    lo = np.asarray(box[0], np.float64)
+    hi = np.asarray(box[1], np.float64)
+    m = ADVECT_MARGIN * (hi - lo)
+    p = np.asarray(xyz32, np.float32).astype(np.float64) + dt * np.asarray(v, np.float64)
+    p = np.minimum(np.maximum(p, lo + m), hi - m)
+    if domain is not None:
+        pm = ADVECT_MARGIN * float(np.max(hi - lo))
+        planes = np.asarray(domain, np.float64).reshape(-1, 4)
+        for _ in range(2):
+            for nx, ny, nz, c in planes:
+                s = ((nx * p[:, 0] + ny * p[:, 1]) + nz * p[:, 2]) - c
+                e = s + pm
+                out = e > 0
+                p[out, 0] -= e[out] * nx
+                p[out, 1] -= e[out] * ny
+                p[out, 2] -= e[out] * nz
+    return p.astype(np.float32)
 
 
 @dataclass

@@ -23,7 +23,7 @@ OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
            "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
-           "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity",
+           "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
@@ -126,6 +126,9 @@ def load():
         lib.lagot_fluid_velocity.argtypes = [P, I64, P, P, P, P, Box, P, P, P, ctypes.POINTER(FluidParams), P, P,
                                              ctypes.POINTER(ctypes.c_int32 * 3)]
         lib.lagot_fluid_velocity.restype = I
+        lib.lagot_fluid_step.argtypes = [P, I64, P, P, P, P, Box, P, P, P, P, ctypes.POINTER(FluidParams),
+                                         ctypes.POINTER(Opts), ctypes.POINTER(Stats), ctypes.POINTER(ctypes.c_int32 * 3)]
+        lib.lagot_fluid_step.restype = I
         lib.lagot_last_flag_counts.argtypes = [P, P]
         lib.lagot_last_flag_counts.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
@@ -294,6 +297,29 @@ class Context:
         if rc != OK:
             raise LagotError(rc, "lagot_fluid_velocity")
         return out, cen, list(it)
+
+    def fluid_step(self, x, y, z, nu, psi, mass, v, params=None, opts=None, mu=None, box=((0, 0, 0), (1, 1, 1))):
+        """lagot_fluid_step, in place on x, y, z, psi and v: move the sites with v, re-solve
+        the weights, update v (section 5). Returns (stats, PCG iterations per coordinate)."""
+        import torch
+        n = x.shape[0]
+        if tuple(v.shape) != (n, 3) or tuple(mass.shape) != (n,) or (mu is not None and tuple(mu.shape) != (n,)):
+            raise ValueError("mass and mu must be [n], v [n, 3]")
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(nu, torch.float64, "nu")]
+        psi_p = _dev(psi, torch.float64, "psi")
+        m_p = _dev(mass, torch.float64, "mass")
+        mu_p = None if mu is None else _dev(mu, torch.float64, "mu")
+        v_p = _dev(v, torch.float64, "v")
+        prm = params if params is not None else default_fluid_params()
+        o = opts if opts is not None else default_opts()
+        st = Stats()
+        it = (ctypes.c_int32 * 3)()
+        rc = load().lagot_fluid_step(self._h, n, *args, make_box(box), psi_p, m_p, mu_p, v_p, ctypes.byref(prm),
+                                     ctypes.byref(o), ctypes.byref(st), ctypes.byref(it))
+        if rc != OK:
+            raise LagotError(rc, "lagot_fluid_step")
+        return st, list(it)
 
     def set_domain(self, planes=None) -> None:
         """lagot_set_domain: planes [P, 4] (unit outward normal, c) of the convex domain

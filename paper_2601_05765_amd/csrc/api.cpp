@@ -666,6 +666,9 @@ int autotune_tpc(lagot_ctx *c) {
     return LAGOT_OK;
 }
 
+// Inward margin of the fluid step's position update, relative to the box extent.
+constexpr double ADVECT_MARGIN = 1e-6;
+
 // ---- graph mode ---------------------------------------------------------------
 void drop_graphs(lagot_ctx *c) {
     if (c->g_dir) (void)hipGraphExecDestroy(c->g_dir);
@@ -1079,8 +1082,6 @@ int single_instance(lagot_ctx *c, int64_t n, const float *x, const float *y, con
     return rc;
 }
 
-}  // namespace
-
 // Cells at (x, psi) with their facet weights: the P1 Laplacian's w_ij in hcol/hval/hcnt
 // (grid order, sorted rows), and the centroids into cen (caller order) when given.
 int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
@@ -1110,6 +1111,8 @@ int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     if (c->h_cnt[1] != 0 || c->h_cnt[2] != 0) return LAGOT_ECAPACITY;
     return LAGOT_OK;
 }
+
+}  // namespace
 
 extern "C" {
 
@@ -1477,6 +1480,27 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
         if (c->h_cnt[10] == 0 && status == LAGOT_OK) status = c->h_cnt[9] ? LAGOT_ESINGULAR : LAGOT_ENOCONV;
     }
     return status;
+}
+
+int lagot_fluid_step(lagot_ctx *c, int64_t n, float *x, float *y, float *z, const double *nu, lagot_box box,
+                     double *psi_inout, const double *mass, const double *mu, double *v_inout,
+                     const lagot_fluid_params *prm, const lagot_opts *opts, lagot_stats *stats, int32_t *cg_iters) {
+    if (!c || !x || !y || !z || !nu || !psi_inout || !mass || !v_inout || !prm || n <= 0) return LAGOT_EINVAL;
+    if (!box_ok(box) || !(prm->dt > 0.0 && std::isfinite(prm->dt))) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    AdvectBounds bd;
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double m = ADVECT_MARGIN * (box.hi[a] - box.lo[a]);
+        bd.lo[a] = box.lo[a] + m;
+        bd.hi[a] = box.hi[a] - m;
+        ext = std::max(ext, box.hi[a] - box.lo[a]);
+    }
+    bd.plane_margin = ADVECT_MARGIN * ext;
+    launch_advect(c->stream, n, x, y, z, v_inout, prm->dt, bd, c->dom_d, c->ndom);
+    int rc = single_instance(c, n, x, y, z, nu, box, psi_inout, opts, stats, false);
+    if (rc) return rc;
+    return lagot_fluid_velocity(c, n, x, y, z, psi_inout, box, mass, mu, v_inout, prm, v_inout, nullptr, cg_iters);
 }
 
 const char *lagot_strerror(int code) {

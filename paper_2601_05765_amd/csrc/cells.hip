@@ -421,11 +421,17 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         }
         f(keep, false, false, nx, ny, nz, t, -1 - gl);
     };
-    // keep the candidates with t < thr
+    // keep the candidates with t < thr. nnear counts the kept planes within 0.1 r of p_i:
+    // where two such planes meet, the cell's shape near p_i is set by offsets far below r,
+    // which float32 coordinates (relative to p_i, absolute error ~6e-8 r) resolve only to
+    // ~6e-8 r / max(|t1|, |t2|); such cells are finished in float64.
+    int nnear = 0;
     auto collect = [&](R thr) {
         ncand = 0;
+        nnear = 0;
         scan([&](bool keep, bool kill, bool neg, R nx, R ny, R nz, R t, int id) {
             const bool k2 = keep && t < thr;
+            if constexpr (sizeof(R) == 4) nnear += popc(gballot<G>(k2 && fabs(t) < R(0.1) * r));
             const unsigned long long b = gballot<G>(k2);
             if (k2) {
                 const int c = ncand + popc(b & below);
@@ -1081,7 +1087,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             o.cen[3 * ci + 2] = (double)pz + f * mom_z;
         }
         const double scale = in_ball ? sum_tA_abs / 3.0 : (4.0 / 3.0) * PI_D * (double)r * (double)r * (double)r;
-        if (fast && sizeof(R) == 4 && live && V < 0.05 * scale) flags |= CF_PREC;
+        if (fast && sizeof(R) == 4 && live && (V < 0.05 * scale || nnear >= 2)) flags |= CF_PREC;
         o.V[cell] = V;
         o.K[cell] = K;
         o.fcnt[cell] = live ? nf : 0;

@@ -114,6 +114,42 @@ __global__ void k_zero_f64(double *p, int64_t count) {
     if (i < count) p[i] = 0.0;
 }
 
+// Position update of the fluid step, x += dt v (section 5), kept inside the domain: each
+// coordinate is clamped to [lo + m_a, hi - m_a] (m_a = margin * (hi_a - lo_a)), then, with
+// convex domain planes n.x <= c, a site with n.x > c - m (m = margin * largest extent)
+// is moved along -n onto n.x = c - m, in two passes over the planes. Every product and
+// sum is rounded separately (no contraction), so the result is reproducible on any
+// IEEE double implementation before the final rounding to float32.
+__global__ __launch_bounds__(FB) void k_advect(int64_t n, float *__restrict__ x, float *__restrict__ y,
+                                               float *__restrict__ z, const double *__restrict__ v, double dt,
+                                               AdvectBounds bd, const float4 *__restrict__ dom, int ndom) {
+    const int64_t i = (int64_t)blockIdx.x * FB + threadIdx.x;
+    if (i >= n) return;
+    double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double q = __dadd_rn(p[a], __dmul_rn(dt, v[3 * i + a]));
+        p[a] = fmin(fmax(q, bd.lo[a]), bd.hi[a]);
+    }
+    for (int pass = 0; pass < 2; ++pass)
+        for (int w = 0; w < ndom; ++w) {
+            const float4 h = dom[w];
+            const double nx = h.x, ny = h.y, nz = h.z;
+            const double s = __dsub_rn(__dadd_rn(__dadd_rn(__dmul_rn(nx, p[0]), __dmul_rn(ny, p[1])),
+                                                 __dmul_rn(nz, p[2])),
+                                       (double)h.w);
+            const double e = __dadd_rn(s, bd.plane_margin);
+            if (e > 0.0) {
+                p[0] = __dsub_rn(p[0], __dmul_rn(e, nx));
+                p[1] = __dsub_rn(p[1], __dmul_rn(e, ny));
+                p[2] = __dsub_rn(p[2], __dmul_rn(e, nz));
+            }
+        }
+    x[i] = (float)p[0];
+    y[i] = (float)p[1];
+    z[i] = (float)p[2];
+}
+
 inline unsigned nb(int64_t n) { return (unsigned)((n + FB - 1) / FB); }
 
 }  // namespace
@@ -137,6 +173,11 @@ void launch_scatter_comp(hipStream_t st, int64_t n, const int32_t *perm, const d
 
 void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t value) {
     hipLaunchKernelGGL(k_fill_i32, dim3(nb(count)), dim3(FB), 0, st, p, count, value);
+}
+
+void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, const double *v, double dt,
+                   const AdvectBounds &bd, const float4 *dom, int ndom) {
+    hipLaunchKernelGGL(k_advect, dim3(nb(n)), dim3(FB), 0, st, n, x, y, z, v, dt, bd, dom, ndom);
 }
 
 void launch_zero_f64(hipStream_t st, double *p, int64_t count) {

@@ -182,6 +182,13 @@ struct FluidPrm {
     double g[3];      // gravity (acceleration)
 };
 
+// Bounds of the position update: per-axis clamp interval, and the inward margin kept
+// from every domain plane.
+struct AdvectBounds {
+    double lo[3], hi[3];
+    double plane_margin;
+};
+
 // ---- launch wrappers (defined in the .hip files) ----
 // grid.hip
 void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst);
@@ -267,6 +274,9 @@ void launch_p1_laplacian(hipStream_t st, int64_t n, const int32_t *perm, const i
 void launch_scatter_comp(hipStream_t st, int64_t n, const int32_t *perm, const double *x, int comp, double *out);
 void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t value);
 void launch_zero_f64(hipStream_t st, double *p, int64_t count);
+// x += dt v, clamped into the box and the domain planes (see k_advect)
+void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, const double *v, double dt,
+                   const AdvectBounds &bd, const float4 *dom, int ndom);
 
 // mlp.hip
 void launch_knn_features(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm,

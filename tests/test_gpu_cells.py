@@ -265,3 +265,29 @@ def test_centroids_scaled_box_and_edge_cases(ctx, oracle_mod):
     vol, cen = ctx.centroids(xd, yd, zd, pd)
     assert float(vol[0]) == 0.0
     assert np.allclose(cen.cpu().numpy()[0], [x[0], y[0], z[0]], atol=0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sites_on_box_edges_and_corners(ctx, oracle_mod, seed):
+    """Sites 1e-6 from two or three walls (the corner edges and corners of the box, where a
+    clamped position update leaves them) among ordinary ones: two planes pass within a
+    tiny distance of p_i, and the cell must still match the oracle."""
+    rng = np.random.default_rng(300 + seed)
+    n = 400
+    p = rng.uniform(0.02, 0.98, (n, 3))
+    e = 1e-6
+    for k in range(60):
+        a, b = rng.choice(3, 2, replace=False)
+        p[k, a] = e if rng.random() < 0.5 else 1 - e
+        p[k, b] = e if rng.random() < 0.5 else 1 - e
+        if k % 4 == 0:
+            c = 3 - a - b
+            p[k, c] = e if rng.random() < 0.5 else 1 - e
+    r = rng.uniform(0.06, 0.12, n)
+    psi = r * r
+    x, y, z = (np.float32(p[:, i]) for i in range(3))
+    _say(f"case: sites on box edges and corners, seed {seed}")
+    out, orc = _run(ctx, oracle_mod, x, y, z, psi)
+    rep = compare(out, orc, psi)
+    _say(f"  {rep}")
+    assert_close(rep)

@@ -6,6 +6,7 @@ Tolerances follow from the cell parity bounds (float32 geometry): a facet area i
 within T_i = 2e-5 sum_j mu_ij pi max(r_i, r_j)^2 |u_j - u_i| / (2 d_ij); the velocity
 system is an M-matrix with diagonal excess m_i/dt, so ||dv||_inf <= max(dt/m) times the
 largest row error of the right-hand side and of the matrix applied to v."""
+import dataclasses
 import math
 import sys
 
@@ -224,3 +225,63 @@ def test_fluid_velocity_rejects_bad_input(ctx):
     # the context still works after the rejected calls
     out, _, _ = ctx.fluid_velocity(x, y, z, psi, _t(mass, torch.float64), _t(v, torch.float64))
     assert torch.isfinite(out).all()
+
+
+@pytest.mark.parametrize("seed,planes", [(0, False), (1, False), (2, True)])
+def test_fluid_step_parity(ctx, oracle_mod, seed, planes):
+    """One whole step: positions bit-exact against the oracle's update (same clamp
+    reading), weights valid under the oracle's own cell evaluation (the stop test holds),
+    velocities within the bound of the velocity test at the new cells."""
+    import torch
+    import paper_2601_05765_amd as L
+    n = 2500
+    _say(f"case: fluid step, dam_break {n}, seed {seed}, domain planes {planes}")
+    sc, v, mu, mass = _fluid_case(n, seed)
+    v[:, 2] -= 1.0  # falling: the bottom layer reaches the floor and is clamped
+    dt, eps, gamma = 0.03, 0.2, 0.05
+    dom = None
+    if planes:
+        nrm = np.array([1.0, 0.0, 1.0]) / math.sqrt(2.0)
+        P = [[-1, 0, 0, 0], [1, 0, 0, 1], [0, -1, 0, 0], [0, 1, 0, 1], [0, 0, -1, 0], [0, 0, 1, 1],
+             [nrm[0], nrm[1], nrm[2], float(nrm @ [0.9, 0, 0.45])]]
+        dom = np.asarray(P, np.float32).astype(np.float64)
+        xyz0 = _xyz(sc)
+        keep = np.all(xyz0 @ dom[:, :3].T < dom[:, 3] - 1e-4, axis=1)
+        sc = dataclasses.replace(sc, x=sc.x[keep], y=sc.y[keep], z=sc.z[keep], nu=sc.nu[keep], psi0=sc.psi0[keep])
+        v, mu, mass = v[keep], mu[keep], mass[keep]
+        n = int(keep.sum())
+        ctx.set_domain(dom)
+    try:
+        xyz0 = _xyz(sc)
+        x, y, z = _sites(sc)
+        psi = _t(sc.psi0, torch.float64)
+        vt = _t(v, torch.float64)
+        prm = L.default_fluid_params(dt=dt, eps=eps, gamma=gamma, gravity=(0.0, 0.0, -9.81))
+        st, its = ctx.fluid_step(x, y, z, _t(sc.nu, torch.float64), psi, _t(mass, torch.float64), vt, prm,
+                                 opts=L.default_opts(tol=1e-5), mu=_t(mu, torch.float64))
+    finally:
+        if planes:
+            ctx.set_domain(None)
+    x1 = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+    want = oracle_mod.advect(xyz0.astype(np.float32), v, dt, domain=dom)
+    moved = np.abs(want.astype(np.float64) - (xyz0 + dt * v)).max(axis=1) > 1e-6
+    _say(f"  {int(moved.sum())} sites clamped; solve status {st.status}, {st.newton_iters} Newton iterations; "
+         f"PCG {its}")
+    assert moved.sum() > 0
+    assert np.array_equal(x1, want)
+    assert st.status == 0
+    xyz1 = x1.astype(np.float64)
+    p1 = psi.cpu().numpy()
+    c = oracle_mod.cells(xyz1[:, 0], xyz1[:, 1], xyz1[:, 2], p1, domain=dom)
+    err = float(np.max(np.abs(c.V - sc.nu) / sc.nu))
+    _say(f"  oracle max rel volume error at the new weights {err:.2e}")
+    assert err <= 1e-5
+    so = oracle_mod.fluid_velocity(xyz1, p1, v, mass, mu, dt=dt, eps=eps, gamma=gamma, gravity=(0, 0, -9.81),
+                                   domain=dom)
+    r = np.sqrt(p1)
+    rhs_err = 1e-5 * r / (eps * eps) + gamma * _row_tol(so.W, p1, xyz1, xyz1, 1.0)
+    mat_err = _row_tol(so.W, p1, xyz1, so.v, mu)
+    bound = 2.0 * (dt / mass.min()) * (rhs_err + mat_err).max() + 1e-8 * np.abs(so.v).max()
+    e = np.abs(vt.cpu().numpy() - so.v).max()
+    _say(f"  max |dv| {e:.3e}, bound {bound:.3e}")
+    assert e <= bound

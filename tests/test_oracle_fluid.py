@@ -143,3 +143,35 @@ def test_surface_tension_pulls_the_pair_together(oracle_mod):
                                    gamma=2.0)
     assert st.Ft[0, 0] > 0 and st.Ft[1, 0] < 0
     assert st.v[0, 0] > 0 and st.v[1, 0] < 0
+
+
+def test_advect_inside_is_the_plain_update(oracle_mod):
+    rng = np.random.default_rng(9)
+    x = rng.uniform(0.3, 0.7, (50, 3)).astype(np.float32)
+    v = rng.normal(size=(50, 3))
+    got = oracle_mod.advect(x, v, 0.01)
+    assert np.array_equal(got, (x.astype(np.float64) + 0.01 * v).astype(np.float32))
+
+
+def test_advect_clamps_to_the_box_margin(oracle_mod):
+    box = ((0.0, -1.0, 2.0), (1.0, 3.0, 2.5))
+    x = np.array([[0.5, 0.0, 2.2], [0.999, 2.9, 2.49]], np.float32)
+    v = np.array([[-100.0, -100.0, -100.0], [100.0, 100.0, 100.0]])
+    got = oracle_mod.advect(x, v, 1.0, box).astype(np.float64)
+    lo, hi = np.array(box[0]), np.array(box[1])
+    m = 1e-6 * (hi - lo)
+    assert np.allclose(got[0], lo + m, rtol=0, atol=1e-7 * 4) and np.all(got[0] > lo)
+    assert np.allclose(got[1], hi - m, rtol=0, atol=1e-7 * 4) and np.all(got[1] < hi)
+
+
+def test_advect_projects_onto_a_domain_plane(oracle_mod):
+    n = np.array([1.0, 1.0, 0.0]) / math.sqrt(2.0)
+    c = float(n @ [0.6, 0.6, 0.0])
+    x = np.array([[0.5, 0.5, 0.5], [0.2, 0.3, 0.5]], np.float32)
+    v = np.array([[0.3, 0.2, 0.1], [0.0, 0.0, 0.0]])
+    got = oracle_mod.advect(x, v, 1.0, domain=[[n[0], n[1], n[2], c]]).astype(np.float64)
+    # the first site crossed the plane: it lands on n.x = c - 1e-6, displaced along -n only
+    assert abs(got[0] @ n - (c - 1e-6)) < 2e-7
+    d = got[0] - (x[0].astype(np.float64) + v[0])
+    assert np.allclose(d - (d @ n) * n, 0, atol=2e-7)
+    assert np.array_equal(got[1], x[1])
