@@ -201,7 +201,7 @@ def fluid_section(ctx, L, x, y, z, psi, nu, reps: int = 10, steps: int = 5):
     g = torch.Generator(device="cuda").manual_seed(3)
     v = torch.randn((n, 3), generator=g, dtype=torch.float64, device="cuda")
     mu = 2.0 * torch.rand(n, generator=g, dtype=torch.float64, device="cuda")
-    prm = L.default_fluid_params(dt=2e-3, eps=0.1, gamma=0.05)
+    prm = L.default_fluid_params(dt=2e-3, eps=0.02, gamma=0.05)
     for _ in range(2):
         ctx.fluid_velocity(x, y, z, psi, nu, v, prm, mu=mu)
     torch.cuda.synchronize()

@@ -297,7 +297,7 @@ int lagot_p1_laplacian(lagot_ctx *ctx, int64_t n, const float *x, const float *y
 
 typedef struct {
     double dt;          /* time step (> 0)                                                     */
-    double eps;         /* pressure spring F_p = (c_i - p_i) / eps^2 (> 0; +inf: no spring)    */
+    double eps;         /* pressure spring F_p = m_i (c_i - p_i) / eps^2 (> 0; +inf: none)     */
     double gamma;       /* surface tension F_t = gamma Lap p (>= 0)                            */
     double mu;          /* viscosity of every site when the per-site array is NULL (>= 0)      */
     double gravity[3];  /* gravity (acceleration): F_g = m_i g                                 */
@@ -313,7 +313,7 @@ void lagot_default_fluid_params(lagot_fluid_params *prm);
  * Velocity update of the fluid step (section 5, "Numerical integration", eq. (4)):
  * with the cells at the sites p and weights psi (normally the OT solution there) and
  * their centroids c_i,
- *   F_p = (c_i - p_i) / eps^2,  F_g = m_i g,  F_t = gamma Lap p  (mu_ij = 1 here),
+ *   F_p = m_i (c_i - p_i) / eps^2,  F_g = m_i g,  F_t = gamma Lap p  (mu_ij = 1 here),
  *   (m_i/dt) v_i - (Lap_mu v)_i = (m_i/dt) v_in_i + F_p + F_g + F_t,
  * solved for v by Jacobi-PCG, one solve per coordinate (Lap_mu as lagot_p1_laplacian;
  * the system is symmetric positive definite). Positions are not moved: the step's

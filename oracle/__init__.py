@@ -246,13 +246,17 @@ def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.nda
     """Velocity update of the fluid step, section 5: with the cells at the sites ``xyz``
     and weights ``psi`` (normally the OT solution there),
 
-      F_p = (c_i - p_i) / eps^2        pressure spring to the cell centroid
+      F_p = m_i (c_i - p_i) / eps^2    pressure spring to the cell centroid
       F_g = m_i g                      gravity
       F_t = gamma Lap p                surface tension, P1 Laplacian of the positions
       (m_i/dt) v_i - (Lap_mu v)_i = (m_i/dt) v^k_i + F_p + F_g + F_t     (eq. (4))
 
     solved exactly (sparse direct solve). Lap_mu is the P1 Laplacian with
-    mu_ij = (mu_i + mu_j) / 2. Boundary (wall) terms do not enter."""
+    mu_ij = (mu_i + mu_j) / 2. Boundary (wall) terms do not enter.
+
+    The spring is read with the particle's mass, as in Gallouet-Merigot's scheme that
+    the paper follows (the pull of the OT distance on site i is m_i (c_i - p_i)); the
+    paper prints it without m_i, for equal masses absorbed in eps."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as sla
     xyz = np.asarray(xyz, np.float64)
@@ -260,7 +264,7 @@ def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.nda
     c = cells(xyz[:, 0], xyz[:, 1], xyz[:, 2], psi, box, domain=domain)
     W = p1_weights(xyz, c)
     m = np.asarray(mass, np.float64)
-    Fp = (c.C - xyz) / (eps * eps)
+    Fp = m[:, None] * (c.C - xyz) / (eps * eps)
     Ft = gamma * p1_laplacian(W, xyz)
     Fg = m[:, None] * np.asarray(gravity, np.float64)[None, :]
     Wm = _mu_scaled(W, mu)

@@ -6,7 +6,7 @@
 // -Hess K, assembled by the Hessian kernels (union pattern, sorted rows, float32
 // values, bit-symmetric). With mu_ij = (mu_i + mu_j) / 2 the velocity system is
 //   (m_i/dt + sum_j mu_ij w_ij) v_i - sum_j mu_ij w_ij v_j = b_i,
-//   b_i = (m_i/dt) v^k_i + (c_i - p_i) / eps^2 + m_i g + gamma (Lap p)_i,
+//   b_i = (m_i/dt) v^k_i + m_i (c_i - p_i) / eps^2 + m_i g + gamma (Lap p)_i,
 // symmetric positive definite, solved per coordinate by the Jacobi-PCG of the Newton
 // direction. The diagonal is the row sum of the stored float32 off-diagonals plus
 // m_i/dt, so every row of the viscous operator sums to zero exactly as stored and the
@@ -62,9 +62,9 @@ __global__ __launch_bounds__(FB) void k_fluid_rows(int64_t n, const int32_t *__r
     const double mdt = m / fp.dt;
     diag[i] = mdt + dsum;
     const double cx = cen[3 * (int64_t)o], cy = cen[3 * (int64_t)o + 1], cz = cen[3 * (int64_t)o + 2];
-    b[i] = mdt * vx + (cx - px) * fp.inv_eps2 + m * fp.g[0] + fp.gamma * lx;
-    b[n + i] = mdt * vy + (cy - py) * fp.inv_eps2 + m * fp.g[1] + fp.gamma * ly;
-    b[2 * n + i] = mdt * vz + (cz - pz) * fp.inv_eps2 + m * fp.g[2] + fp.gamma * lz;
+    b[i] = mdt * vx + m * (cx - px) * fp.inv_eps2 + m * fp.g[0] + fp.gamma * lx;
+    b[n + i] = mdt * vy + m * (cy - py) * fp.inv_eps2 + m * fp.g[1] + fp.gamma * ly;
+    b[2 * n + i] = mdt * vz + m * (cz - pz) * fp.inv_eps2 + m * fp.g[2] + fp.gamma * lz;
 }
 
 // (Lap_mu u)_i = sum_j mu_ij w_ij (u_j - u_i) for a caller-order field u [3n]; the

@@ -176,7 +176,7 @@ struct CgBufs {
 // Parameters of the velocity system of the fluid step (section 5, eq. (4)).
 struct FluidPrm {
     double dt;        // time step
-    double inv_eps2;  // 1 / eps^2 of the pressure spring
+    double inv_eps2;  // 1 / eps^2 of the pressure spring (force m (c - p) / eps^2)
     double gamma;     // surface tension
     double mu;        // viscosity of every site when no per-site array is given
     double g[3];      // gravity (acceleration)

@@ -85,7 +85,7 @@ def test_explicit_update_when_mu_is_zero(oracle_mod):
     want = v + 0.01 / m[:, None] * (st.Fp + st.Fg + st.Ft)
     assert np.allclose(st.v, want, rtol=1e-12, atol=1e-12)
     assert np.allclose(st.Fg[:, 2], -9.81 * m)
-    assert np.allclose(st.Fp, (st.cells.C - xyz) / 0.09)
+    assert np.allclose(st.Fp, m[:, None] * (st.cells.C - xyz) / 0.09)
 
 
 @pytest.mark.parametrize("mu", [0.3, "site"])
@@ -175,3 +175,20 @@ def test_advect_projects_onto_a_domain_plane(oracle_mod):
     d = got[0] - (x[0].astype(np.float64) + v[0])
     assert np.allclose(d - (d @ n) * n, 0, atol=2e-7)
     assert np.array_equal(got[1], x[1])
+
+
+@pytest.mark.parametrize("m", [1e-4, 3.0])
+def test_spring_acceleration_of_a_ball_at_a_wall(oracle_mod, m):
+    """One ball of radius r at distance a from the floor: its cell is the ball minus a cap
+    of height r - a, whose centroid lies V_cap z_cap / (V_ball - V_cap) above the site
+    (closed form). The spring's acceleration (c - p)/eps^2 does not depend on the mass."""
+    r, a, eps, dt = 0.2, 0.07, 0.05, 0.01
+    p = np.array([[0.5, 0.5, a]])
+    h = r - a
+    vcap = math.pi * h * h * (3 * r - h) / 3
+    zc = 3 * (2 * r - h) ** 2 / (4 * (3 * r - h))
+    shift = vcap * zc / (4 / 3 * math.pi * r ** 3 - vcap)
+    v0 = np.array([[0.1, -0.2, 0.3]])
+    st = oracle_mod.fluid_velocity(p, np.array([r * r]), v0, np.array([m]), 2.0, dt=dt, eps=eps, gamma=1.0,
+                                   gravity=(0, 0, -9.81))
+    assert np.allclose(st.v[0], v0[0] + dt * np.array([0, 0, shift / eps ** 2 - 9.81]), rtol=1e-12, atol=1e-12)
