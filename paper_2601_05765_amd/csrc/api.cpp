@@ -81,8 +81,10 @@ struct lagot_ctx {
     float *wall = nullptr;
     int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr, *ovf_list = nullptr;
     double *cen_out = nullptr;  // caller's centroid array during a lagot_centroids call
-    double *fl_buf = nullptr;   // fluid step: right-hand sides [3n], zeros [n], centroids [3n]
+    double *fl_buf = nullptr;   // fluid step: PCG records and vectors, right-hand sides, centroids
+    int32_t *fl_int = nullptr;  // fluid step: PCG status per coordinate, chunk counters
     int64_t cap_fl = 0;
+    int fl_chunk = 32;          // fluid PCG launches between host checks (adapted per call)
     float4 *dom_d = nullptr;    // [DOM_MAX] convex domain planes (lagot_set_domain)
     int ndom = 0;
     int wall_w = 6;             // wall areas per site in the wall buffer (6, or the domain's planes)
@@ -202,7 +204,7 @@ void free_all(lagot_ctx *c) {
     free_alt(c);
     free_sites(c);
     free_inst(c);
-    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf);
+    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int);
     c->cap_fl = 0;
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_rd) (void)hipHostFree(c->h_rd);
@@ -1434,13 +1436,30 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
     for (int a = 0; a < 3; ++a) ok = ok && std::isfinite(p.gravity[a]);
     if (!ok) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    const int nb3 = cg3_blocks(n);
     if (n > c->cap_fl) {
-        free_ptrs(c->fl_buf);
+        free_ptrs(c->fl_buf, c->fl_int);
         c->cap_fl = 0;
-        HIP_TRY(dalloc(&c->fl_buf, 7 * (size_t)n));
+        HIP_TRY(dalloc(&c->fl_buf, 32 * (size_t)n + 21 * (size_t)nb3 + 16));
+        HIP_TRY(dalloc(&c->fl_int, 16));
         c->cap_fl = n;
     }
-    double *b = c->fl_buf, *zero = c->fl_buf + 3 * n, *cen = centroid ? centroid : c->fl_buf + 4 * n;
+    // layout (doubles): records of the two slots [10n each], p [3n], x [3n], b [3n],
+    // centroids [3n], partials [21 nb], scalars [12]; the records come first (16-byte aligned)
+    double *fb = c->fl_buf;
+    Cg3Bufs g;
+    g.rec[0] = reinterpret_cast<Rec3 *>(fb);
+    g.rec[1] = reinterpret_cast<Rec3 *>(fb + 10 * n);
+    g.p = fb + 20 * n;
+    g.x = fb + 23 * n;
+    double *b = fb + 26 * n;
+    double *cen = centroid ? centroid : fb + 29 * n;
+    g.part = fb + 32 * n;
+    g.cgs = fb + 32 * n + 21 * (int64_t)nb3;
+    g.st = c->fl_int;
+    g.kbase = c->fl_int + 12;
+    g.remaining = c->fl_int + 13;
+    g.nb = nb3;
     int rc = fluid_cells(c, n, x, y, z, psi, box, cen);
     if (rc) return rc;
     hipStream_t st = c->stream;
@@ -1457,28 +1476,34 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
     rc = sync(c);
     if (rc) return rc;
     if (c->h_cnt[0]) return LAGOT_EINVAL;
-    // one Jacobi-PCG solve per coordinate: "V" = 0 and "nu" = b_c give r_0 = b_c, x_0 = 0
-    launch_zero_f64(st, zero, n);
-    launch_fill_i32(st, c->phase, 1, PH_ACTIVE);
-    lagot_opts o;
-    fill_defaults(&o);
-    o.cg_rtol = p.cg_rtol;
-    o.cg_max_iter = p.cg_max_iter;
-    const Batch bt = batch(c);
-    const CgBufs cg = cg_bufs(c);
-    int status = LAGOT_OK;
-    for (int comp = 0; comp < 3; ++comp) {
-        launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, zero, b + comp * n, c->diag, c->hcol, c->hval, c->hcnt, cg);
-        int k = 0;
-        rc = run_cg(c, o, &k, false, false);
-        if (rc) return rc;
-        launch_scatter_comp(st, n, c->perm, cg.x, comp, v_out);
-        HIP_TRY(hipMemcpyAsync(c->h_cnt + 8, c->cg_cgst, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    // the three coordinates in one Jacobi-PCG (x_0 = 0, stop at ||r|| <= cg_rtol ||b||
+    // per coordinate), in chunks of launches with a read-back of the count still iterating
+    launch_cg3_init(st, n, c->hcol, c->hval, c->hcnt, c->diag, b, g);
+    const double rtol2 = p.cg_rtol * p.cg_rtol;
+    const int cap = p.cg_max_iter;
+    int k = 0;
+    while (k < cap) {
+        const int m = std::min(c->fl_chunk, cap - k);
+        for (int q = 0; q < m; ++q) launch_cg3_iter(st, n, q, rtol2, cap, c->hcol, c->hval, c->hcnt, g);
+        launch_cg3_advance(st, m, cap, g);
+        k += m;
+        HIP_TRY(hipMemcpyAsync(c->h_cnt, c->fl_int, 14 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         rc = sync(c);
         if (rc) return rc;
-        if (cg_iters) cg_iters[comp] = c->h_cnt[8];
-        if (c->h_cnt[10] == 0 && status == LAGOT_OK) status = c->h_cnt[9] ? LAGOT_ESINGULAR : LAGOT_ENOCONV;
+        if (c->h_cnt[13] == 0) break;
     }
+    launch_scatter3(st, n, c->perm, g.x, v_out);
+    rc = sync(c);
+    if (rc) return rc;
+    int status = LAGOT_OK, most = 0;
+    for (int q = 0; q < 3; ++q) {
+        const int it = c->h_cnt[4 * q], brk = c->h_cnt[4 * q + 1], conv = c->h_cnt[4 * q + 2];
+        if (cg_iters) cg_iters[q] = it;
+        most = std::max(most, it);
+        if (!conv && status == LAGOT_OK) status = brk ? LAGOT_ESINGULAR : LAGOT_ENOCONV;
+    }
+    // next call's chunk: about this solve's iteration count
+    c->fl_chunk = std::min(64, std::max(8, (most + 4 + 3) / 4 * 4));
     return status;
 }
 

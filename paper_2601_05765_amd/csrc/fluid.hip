@@ -7,8 +7,8 @@
 // values, bit-symmetric). With mu_ij = (mu_i + mu_j) / 2 the velocity system is
 //   (m_i/dt + sum_j mu_ij w_ij) v_i - sum_j mu_ij w_ij v_j = b_i,
 //   b_i = (m_i/dt) v^k_i + m_i (c_i - p_i) / eps^2 + m_i g + gamma (Lap p)_i,
-// symmetric positive definite, solved per coordinate by the Jacobi-PCG of the Newton
-// direction. The diagonal is the row sum of the stored float32 off-diagonals plus
+// symmetric positive definite, solved for the three coordinates at once by a
+// Jacobi-PCG of the Newton direction's form (k_cg3_*). The diagonal is the row sum of the stored float32 off-diagonals plus
 // m_i/dt, so every row of the viscous operator sums to zero exactly as stored and the
 // solve conserves momentum up to its residual.
 //
@@ -97,23 +97,6 @@ __global__ __launch_bounds__(FB) void k_p1_laplacian(int64_t n, const int32_t *_
     out[3 * (int64_t)o + 2] = lz;
 }
 
-// out[3 perm[i] + comp] = x[i]
-__global__ __launch_bounds__(FB) void k_scatter_comp(int64_t n, const int32_t *__restrict__ perm,
-                                                     const double *__restrict__ x, int comp, double *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * FB + threadIdx.x;
-    if (i < n) out[3 * (int64_t)perm[i] + comp] = x[i];
-}
-
-__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = value;
-}
-
-__global__ void k_zero_f64(double *p, int64_t count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0.0;
-}
-
 // Position update of the fluid step, x += dt v (section 5), kept inside the domain: each
 // coordinate is clamped to [lo + m_a, hi - m_a] (m_a = margin * (hi_a - lo_a)), then, with
 // convex domain planes n.x <= c, a site with n.x > c - m (m = margin * largest extent)
@@ -150,6 +133,243 @@ __global__ __launch_bounds__(FB) void k_advect(int64_t n, float *__restrict__ x,
     z[i] = (float)p[2];
 }
 
+// ---- three right-hand sides at once: Jacobi-PCG, Chronopoulos-Gear form ----------
+// The three coordinates of the velocity system share the matrix, so one kernel per
+// iteration advances all three (same recurrences as the Newton direction's PCG, with
+// scalars, convergence and breakdown per coordinate): the row's entries and the
+// neighbour indices are loaded once for the three, and the launch count drops by 3x.
+// Per row and slot (iteration parity) one 80-byte record holds r, w = A u, s = A p of
+// the three coordinates and the diagonal D. Every block sums the per-block partials
+// in a fixed order (deterministic, no atomics, no device-scope fences).
+constexpr int C3L = 2;             // lanes per row
+constexpr int C3S = 128;           // rows per block
+constexpr int C3B = C3L * C3S;     // threads per block
+
+__device__ inline void load_rec3(const Rec3 *a, int64_t i, double *r, double *w, double *s, double &d) {
+    const double2 *p = reinterpret_cast<const double2 *>(a + i);
+    const double2 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3], q4 = p[4];
+    r[0] = q0.x; r[1] = q0.y; r[2] = q1.x;
+    w[0] = q1.y; w[1] = q2.x; w[2] = q2.y;
+    s[0] = q3.x; s[1] = q3.y; s[2] = q4.x;
+    d = q4.y;
+}
+
+__device__ inline void store_rec3(Rec3 *a, int64_t i, const double *r, const double *w, const double *s, double d) {
+    double2 *p = reinterpret_cast<double2 *>(a + i);
+    p[0] = make_double2(r[0], r[1]);
+    p[1] = make_double2(r[2], w[0]);
+    p[2] = make_double2(w[1], w[2]);
+    p[3] = make_double2(s[0], s[1]);
+    p[4] = make_double2(s[2], d);
+}
+
+// Block sum of NV values per thread (one row of sh per wave); every thread gets the sums.
+template <int NV> __device__ inline void block_sums(double *v, double (*sh)[NV]) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sh[wv][q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = 0.0;
+        for (int k = 0; k < C3B / 64; ++k) t += sh[k][q];
+        v[q] = t;
+    }
+}
+
+// partial slots: [slot][9][NB] (gamma[3], delta[3], rho[3]) then rho0[3][NB]
+__device__ inline double *P3(const Cg3Bufs &g, int slot, int q) { return g.part + ((int64_t)slot * 9 + q) * g.nb; }
+__device__ inline double *P3_RHO0(const Cg3Bufs &g, int c) { return g.part + ((int64_t)18 + c) * g.nb; }
+
+// r_0 = b, u_0 = r_0 / D, w_0 = A u_0, p_{-1} = s_{-1} = x_0 = 0
+__global__ __launch_bounds__(C3B) void k_cg3_init(int64_t n, const int32_t *__restrict__ hcol,
+                                                  const float *__restrict__ hval, const int32_t *__restrict__ hcnt,
+                                                  const double *__restrict__ diag, const double *__restrict__ b,
+                                                  Cg3Bufs g) {
+    __shared__ double sh[C3B / 64][12];
+    const int blk = (int)blockIdx.x;
+    if (blk == 0 && threadIdx.x < 16) {
+        if (threadIdx.x < 12) g.st[threadIdx.x] = 0;
+        if (threadIdx.x == 12) *g.kbase = 0;
+    }
+    const int64_t row = (int64_t)blk * C3S + (int)(threadIdx.x / C3L);
+    const int l = threadIdx.x & (C3L - 1);
+    const bool has = row < n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (has) {
+        const int c = hcnt[row];
+        const int32_t *cr = hcol + row * FCAP;
+        const float *vr = hval + row * FCAP;
+        for (int f = l; f < c; f += C3L) {
+            const int j = cr[f];
+            const double v = (double)vr[f] / diag[j];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[q] = fma(v, b[q * n + j], acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        for (int o = C3L / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, C3L);
+    double part[12] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (has && l == 0) {
+        const double d = diag[row];
+        double r[3], w[3], z[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            r[q] = b[q * n + row];
+            const double u = r[q] / d;
+            w[q] = d * u - acc[q];
+            part[q] = r[q] * u;          // gamma
+            part[3 + q] = w[q] * u;      // delta
+            part[6 + q] = r[q] * r[q];   // rho
+            g.p[3 * row + q] = 0.0;
+            g.x[3 * row + q] = 0.0;
+        }
+        store_rec3(g.rec[0], row, r, w, z, d);
+    }
+    block_sums<12>(part, sh);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 9; ++q) P3(g, 0, q)[blk] = part[q];
+        for (int q = 0; q < 3; ++q) P3_RHO0(g, q)[blk] = part[6 + q];
+    }
+}
+
+// Iteration k = *kbase + m of the three systems (the host advances kbase per chunk).
+__global__ __launch_bounds__(C3B) void k_cg3_iter(int64_t n, int m, double rtol2, int cap,
+                                                  const int32_t *__restrict__ hcol, const float *__restrict__ hval,
+                                                  const int32_t *__restrict__ hcnt, Cg3Bufs g) {
+    __shared__ double sh[C3B / 64][12];
+    const int blk = (int)blockIdx.x;
+    const int k = *g.kbase + m;
+    if (k >= cap) return;
+    bool act[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) act[q] = g.st[4 * q + 1] == 0 && g.st[4 * q + 2] == 0;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const int cur = k & 1, nxt = cur ^ 1;
+    const int64_t row = (int64_t)blk * C3S + (int)(threadIdx.x / C3L);
+    const int l = threadIdx.x & (C3L - 1);
+    const bool has = row < n;
+    // scalars of iteration k from the partials of every block, in a fixed order
+    double S[12] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = (int)threadIdx.x; t < g.nb; t += C3B) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) S[q] += P3(g, cur, q)[t];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S[9 + q] += P3_RHO0(g, q)[t];
+    }
+    block_sums<12>(S, sh);
+    const bool lead = blk == 0 && threadIdx.x == 0;
+    double alpha[3] = {0.0, 0.0, 0.0}, beta[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (!act[q]) continue;
+        const double gam = S[q], del = S[3 + q], rho = S[6 + q], rho0 = S[9 + q];
+        if (rho <= rtol2 * rho0) {
+            act[q] = false;
+            if (lead) {
+                g.st[4 * q + 2] = 1;
+                g.st[4 * q + 0] = k;
+            }
+            continue;
+        }
+        if (k == 0) {
+            alpha[q] = gam / del;
+        } else {
+            const double pa = g.cgs[6 * nxt + 2 * q], pg = g.cgs[6 * nxt + 2 * q + 1];  // alpha, gamma of k-1
+            beta[q] = gam / pg;
+            alpha[q] = gam / (del - beta[q] * gam / pa);
+        }
+        if (!(alpha[q] > 0.0) || !(alpha[q] < 1e300)) {  // non-positive curvature (or NaN)
+            act[q] = false;
+            if (lead) {
+                g.st[4 * q + 1] = 1;
+                g.st[4 * q + 0] = k;
+            }
+            continue;
+        }
+        if (lead) {
+            g.cgs[6 * cur + 2 * q] = alpha[q];
+            g.cgs[6 * cur + 2 * q + 1] = gam;
+            g.st[4 * q + 0] = k + 1;
+        }
+    }
+    if (!act[0] && !act[1] && !act[2]) return;  // the same decision in every block
+    const Rec3 *crec = g.rec[cur];
+    // u_{k+1} of each neighbour from its stored r_k, w_k, s_{k-1}
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (has) {
+        const int c = hcnt[row];
+        const int32_t *cr = hcol + row * FCAP;
+        const float *vr = hval + row * FCAP;
+        for (int f = l; f < c; f += C3L) {
+            double r[3], w[3], s[3], d;
+            load_rec3(crec, cr[f], r, w, s, d);
+            const double v = (double)vr[f] / d;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[q] = fma(v, fma(-alpha[q], fma(beta[q], s[q], w[q]), r[q]), acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        for (int o = C3L / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, C3L);
+    double part[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (has && l == 0) {
+        double r[3], w[3], s[3], d;
+        load_rec3(crec, row, r, w, s, d);
+        double r1[3], w1[3], s1[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (act[q]) {
+                const double uk = r[q] / d;
+                const double pk = fma(beta[q], g.p[3 * row + q], uk);
+                const double sk = fma(beta[q], s[q], w[q]);
+                g.x[3 * row + q] = fma(alpha[q], pk, g.x[3 * row + q]);
+                g.p[3 * row + q] = pk;
+                r1[q] = fma(-alpha[q], sk, r[q]);
+                const double u1 = r1[q] / d;
+                w1[q] = d * u1 - acc[q];
+                s1[q] = sk;
+                part[q] = r1[q] * u1;
+                part[3 + q] = w1[q] * u1;
+                part[6 + q] = r1[q] * r1[q];
+            } else {
+                r1[q] = r[q];
+                w1[q] = w[q];
+                s1[q] = s[q];
+            }
+        }
+        store_rec3(g.rec[nxt], row, r1, w1, s1, d);
+    }
+    block_sums<9>(part, reinterpret_cast<double (*)[9]>(&sh[0][0]));
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 9; ++q) P3(g, nxt, q)[blk] = part[q];
+}
+
+// After a chunk: advance kbase; count the coordinates still iterating.
+__global__ void k_cg3_advance(int chunk, int cap, Cg3Bufs g) {
+    if (threadIdx.x != 0) return;
+    int cnt = 0;
+    for (int q = 0; q < 3; ++q) cnt += g.st[4 * q + 1] == 0 && g.st[4 * q + 2] == 0 && g.st[4 * q] < cap;
+    *g.kbase += chunk;
+    *g.remaining = cnt;
+}
+
+// out[3 perm[i] + q] = x[3 i + q]
+__global__ __launch_bounds__(FB) void k_scatter3(int64_t n, const int32_t *__restrict__ perm,
+                                                 const double *__restrict__ x, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * FB + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) out[3 * o + q] = x[3 * i + q];
+}
+
 inline unsigned nb(int64_t n) { return (unsigned)((n + FB - 1) / FB); }
 
 }  // namespace
@@ -167,21 +387,29 @@ void launch_p1_laplacian(hipStream_t st, int64_t n, const int32_t *perm, const i
     hipLaunchKernelGGL(k_p1_laplacian, dim3(nb(n)), dim3(FB), 0, st, n, perm, hcol, hval, hcnt, mu, mu0, u, out, bad);
 }
 
-void launch_scatter_comp(hipStream_t st, int64_t n, const int32_t *perm, const double *x, int comp, double *out) {
-    hipLaunchKernelGGL(k_scatter_comp, dim3(nb(n)), dim3(FB), 0, st, n, perm, x, comp, out);
-}
-
-void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t value) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(nb(count)), dim3(FB), 0, st, p, count, value);
-}
-
 void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, const double *v, double dt,
                    const AdvectBounds &bd, const float4 *dom, int ndom) {
     hipLaunchKernelGGL(k_advect, dim3(nb(n)), dim3(FB), 0, st, n, x, y, z, v, dt, bd, dom, ndom);
 }
 
-void launch_zero_f64(hipStream_t st, double *p, int64_t count) {
-    hipLaunchKernelGGL(k_zero_f64, dim3(nb(count)), dim3(FB), 0, st, p, count);
+int cg3_blocks(int64_t n) { return (int)((n + C3S - 1) / C3S); }
+
+void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
+                     const double *diag, const double *b, const Cg3Bufs &g) {
+    hipLaunchKernelGGL(k_cg3_init, dim3(cg3_blocks(n)), dim3(C3B), 0, st, n, hcol, hval, hcnt, diag, b, g);
+}
+
+void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *hcol, const float *hval,
+                     const int32_t *hcnt, const Cg3Bufs &g) {
+    hipLaunchKernelGGL(k_cg3_iter, dim3(cg3_blocks(n)), dim3(C3B), 0, st, n, m, rtol2, cap, hcol, hval, hcnt, g);
+}
+
+void launch_cg3_advance(hipStream_t st, int chunk, int cap, const Cg3Bufs &g) {
+    hipLaunchKernelGGL(k_cg3_advance, dim3(1), dim3(64), 0, st, chunk, cap, g);
+}
+
+void launch_scatter3(hipStream_t st, int64_t n, const int32_t *perm, const double *x, double *out) {
+    hipLaunchKernelGGL(k_scatter3, dim3(nb(n)), dim3(FB), 0, st, n, perm, x, out);
 }
 
 }  // namespace lagot

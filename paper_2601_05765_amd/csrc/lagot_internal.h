@@ -189,6 +189,21 @@ struct AdvectBounds {
     double plane_margin;
 };
 
+// Jacobi-PCG of the three coordinates of the fluid velocity system at once (fluid.hip).
+struct Rec3 {
+    double r[3], w[3], s[3], d;  // per row and slot: r, w = A u, s = A p of 3 coordinates, diagonal
+};
+struct Cg3Bufs {
+    Rec3 *rec[2];        // [n] per slot (iteration parity)
+    double *p, *x;       // [3n] row-major (x: the solution)
+    double *part;        // [21 nb]: per slot gamma[3], delta[3], rho[3] per block, then rho0[3]
+    double *cgs;         // [2][3][2]: alpha and gamma per slot and coordinate
+    int32_t *st;         // [3][4]: iterations, breakdown, converged, unused
+    int32_t *kbase;      // index of the first iteration of the next chunk
+    int32_t *remaining;  // coordinates still iterating after the last chunk
+    int nb;              // blocks (rows / 128, rounded up)
+};
+
 // ---- launch wrappers (defined in the .hip files) ----
 // grid.hip
 void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst);
@@ -271,9 +286,14 @@ void launch_fluid_rows(hipStream_t st, int64_t n, const int32_t *perm, const flo
 void launch_p1_laplacian(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *hcol, const float *hval,
                          const int32_t *hcnt, const double *mu, double mu0, const double *u, double *out,
                          int32_t *bad);
-void launch_scatter_comp(hipStream_t st, int64_t n, const int32_t *perm, const double *x, int comp, double *out);
-void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t value);
-void launch_zero_f64(hipStream_t st, double *p, int64_t count);
+int cg3_blocks(int64_t n);
+void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
+                     const double *diag, const double *b, const Cg3Bufs &g);
+void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *hcol, const float *hval,
+                     const int32_t *hcnt, const Cg3Bufs &g);
+void launch_cg3_advance(hipStream_t st, int chunk, int cap, const Cg3Bufs &g);
+// out[3 perm[i] + q] = x[3 i + q]
+void launch_scatter3(hipStream_t st, int64_t n, const int32_t *perm, const double *x, double *out);
 // x += dt v, clamped into the box and the domain planes (see k_advect)
 void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, const double *v, double dt,
                    const AdvectBounds &bd, const float4 *dom, int ndom);
