@@ -315,8 +315,9 @@ void lagot_default_fluid_params(lagot_fluid_params *prm);
  * their centroids c_i,
  *   F_p = m_i (c_i - p_i) / eps^2,  F_g = m_i g,  F_t = gamma Lap p  (mu_ij = 1 here),
  *   (m_i/dt) v_i - (Lap_mu v)_i = (m_i/dt) v_in_i + F_p + F_g + F_t,
- * solved for v by Jacobi-PCG, one solve per coordinate (Lap_mu as lagot_p1_laplacian;
- * the system is symmetric positive definite). Positions are not moved: the step's
+ * solved for v by Jacobi-PCG, the three coordinates together, each stopping at
+ * ||r|| <= cg_rtol ||b|| (Lap_mu as lagot_p1_laplacian; the system is symmetric
+ * positive definite). Positions are not moved: the step's
  * position update x += dt v is the caller's. Wall terms (fluid-boundary affinities)
  * do not enter.
  *   in : x, y, z [n] float32, psi [n] float64, box; mass [n] float64 (> 0); mu [n]

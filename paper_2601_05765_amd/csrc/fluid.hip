@@ -7,10 +7,10 @@
 // values, bit-symmetric). With mu_ij = (mu_i + mu_j) / 2 the velocity system is
 //   (m_i/dt + sum_j mu_ij w_ij) v_i - sum_j mu_ij w_ij v_j = b_i,
 //   b_i = (m_i/dt) v^k_i + m_i (c_i - p_i) / eps^2 + m_i g + gamma (Lap p)_i,
-// symmetric positive definite, solved for the three coordinates at once by a
-// Jacobi-PCG of the Newton direction's form (k_cg3_*). The diagonal is the row sum of the stored float32 off-diagonals plus
-// m_i/dt, so every row of the viscous operator sums to zero exactly as stored and the
-// solve conserves momentum up to its residual.
+// symmetric positive definite, solved for the three coordinates at once by a Jacobi-PCG
+// of the Newton direction's form (k_cg3_*). The diagonal is the row sum of the stored
+// float32 off-diagonals plus m_i/dt, so every row of the viscous operator sums to zero
+// exactly as stored and the solve conserves momentum up to its residual.
 //
 // Rows are in grid order (the solver's sort); caller-order arrays are read and written
 // through perm (perm[i] = caller index of grid row i).
