@@ -1502,8 +1502,9 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
         most = std::max(most, it);
         if (!conv && status == LAGOT_OK) status = brk ? LAGOT_ESINGULAR : LAGOT_ENOCONV;
     }
-    // next call's chunk: about this solve's iteration count
-    c->fl_chunk = std::min(64, std::max(8, (most + 4 + 3) / 4 * 4));
+    // next call's chunk: this solve's iteration count and a margin, so that a like call
+    // needs one read-back and few launches that find every coordinate done
+    c->fl_chunk = std::min(256, std::max(8, (most + 4 + 3) / 4 * 4));
     return status;
 }
 
