@@ -192,7 +192,7 @@ __global__ __launch_bounds__(C3B) void k_cg3_init(int64_t n, const int32_t *__re
                                                   const double *__restrict__ diag, const double *__restrict__ b,
                                                   Cg3Bufs g) {
     __shared__ double sh[C3B / 64][12];
-    const int blk = (int)blockIdx.x;
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);  // row blocks of one XCD are contiguous
     if (blk == 0 && threadIdx.x < 16) {
         if (threadIdx.x < 12) g.st[threadIdx.x] = 0;
         if (threadIdx.x == 12) *g.kbase = 0;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(C3B) void k_cg3_iter(int64_t n, int m, double rtol2
                                                   const int32_t *__restrict__ hcol, const float *__restrict__ hval,
                                                   const int32_t *__restrict__ hcnt, Cg3Bufs g) {
     __shared__ double sh[C3B / 64][12];
-    const int blk = (int)blockIdx.x;
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);  // row blocks of one XCD are contiguous
     const int k = *g.kbase + m;
     if (k >= cap) return;
     bool act[3];
