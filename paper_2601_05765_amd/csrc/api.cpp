@@ -83,6 +83,8 @@ struct lagot_ctx {
     double *cen_out = nullptr;  // caller's centroid array during a lagot_centroids call
     double *fl_buf = nullptr;   // fluid step: PCG records and vectors, right-hand sides, centroids
     int32_t *fl_int = nullptr;  // fluid step: PCG status per coordinate, chunk counters
+    int2 *fl_ent = nullptr;     // fluid step: matrix rows packed back to back
+    int64_t cap_ent = 0;
     int64_t cap_fl = 0;
     int fl_chunk = 32;          // fluid PCG launches between host checks (adapted per call)
     float4 *dom_d = nullptr;    // [DOM_MAX] convex domain planes (lagot_set_domain)
@@ -204,7 +206,8 @@ void free_all(lagot_ctx *c) {
     free_alt(c);
     free_sites(c);
     free_inst(c);
-    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int);
+    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int, c->fl_ent);
+    c->cap_ent = 0;
     c->cap_fl = 0;
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_rd) (void)hipHostFree(c->h_rd);
@@ -1084,6 +1087,17 @@ int single_instance(lagot_ctx *c, int64_t n, const float *x, const float *y, con
     return rc;
 }
 
+// Parameters of the velocity update: dt > 0, eps > 0 (+inf allowed), gamma >= 0, the
+// scalar viscosity >= 0 when no per-site array is given, finite gravity, a PCG tolerance
+// in (0, 1) and at least one PCG iteration.
+bool fluid_params_ok(const lagot_fluid_params &p, bool per_site_mu) {
+    bool ok = p.dt > 0.0 && std::isfinite(p.dt) && p.eps > 0.0 && !std::isnan(p.eps) && p.gamma >= 0.0 &&
+              std::isfinite(p.gamma) && p.cg_rtol > 0.0 && p.cg_rtol < 1.0 && p.cg_max_iter >= 1 &&
+              (per_site_mu || (p.mu >= 0.0 && std::isfinite(p.mu)));
+    for (int a = 0; a < 3; ++a) ok = ok && std::isfinite(p.gravity[a]);
+    return ok;
+}
+
 // Cells at (x, psi) with their facet weights: the P1 Laplacian's w_ij in hcol/hval/hcnt
 // (grid order, sorted rows), and the centroids into cen (caller order) when given.
 int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
@@ -1430,11 +1444,7 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
                          const lagot_fluid_params *prm, double *v_out, double *centroid, int32_t *cg_iters) {
     if (!c || !mass || !v_in || !prm || !v_out || n <= 0) return LAGOT_EINVAL;
     const lagot_fluid_params &p = *prm;
-    bool ok = p.dt > 0.0 && std::isfinite(p.dt) && p.eps > 0.0 && !std::isnan(p.eps) && p.gamma >= 0.0 &&
-              std::isfinite(p.gamma) && p.cg_rtol > 0.0 && p.cg_rtol < 1.0 && p.cg_max_iter >= 1 &&
-              (mu || (p.mu >= 0.0 && std::isfinite(p.mu)));
-    for (int a = 0; a < 3; ++a) ok = ok && std::isfinite(p.gravity[a]);
-    if (!ok) return LAGOT_EINVAL;
+    if (!fluid_params_ok(p, mu != nullptr)) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     const int nb3 = cg3_blocks(n);
     if (n > c->cap_fl) {
@@ -1472,19 +1482,31 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
     launch_zero_i32(st, c->bad_inst, 1);
     launch_fluid_rows(st, n, c->perm, c->pos_s, c->hcol, c->hval, c->hcnt, mass, mu, fp, v_in, cen, c->diag, b,
                       c->bad_inst);
+    // the scaled rows packed back to back for the PCG (row offsets: scan of the counts)
+    int32_t *rp = c->csr_start;
+    launch_scan_i32(st, c->hcnt, rp, (int)n, c->csr_tmp);
     HIP_TRY(hipMemcpyAsync(c->h_cnt, c->bad_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     rc = sync(c);
     if (rc) return rc;
     if (c->h_cnt[0]) return LAGOT_EINVAL;
+    const int64_t nnz = c->h_cnt[1];
+    if (nnz > c->cap_ent) {
+        free_ptrs(c->fl_ent);
+        c->cap_ent = 0;
+        HIP_TRY(dalloc(&c->fl_ent, (size_t)std::max<int64_t>(nnz, 1)));
+        c->cap_ent = nnz;
+    }
+    launch_pack_rows(st, n, c->hcol, c->hval, c->hcnt, rp, c->fl_ent);
     // the three coordinates in one Jacobi-PCG (x_0 = 0, stop at ||r|| <= cg_rtol ||b||
     // per coordinate), in chunks of launches with a read-back of the count still iterating
-    launch_cg3_init(st, n, c->hcol, c->hval, c->hcnt, c->diag, b, g);
+    launch_cg3_init(st, n, rp, c->fl_ent, c->diag, b, g);
     const double rtol2 = p.cg_rtol * p.cg_rtol;
     const int cap = p.cg_max_iter;
     int k = 0;
     while (k < cap) {
         const int m = std::min(c->fl_chunk, cap - k);
-        for (int q = 0; q < m; ++q) launch_cg3_iter(st, n, q, rtol2, cap, c->hcol, c->hval, c->hcnt, g);
+        for (int q = 0; q < m; ++q) launch_cg3_iter(st, n, q, rtol2, cap, rp, c->fl_ent, g);
         launch_cg3_advance(st, m, cap, g);
         k += m;
         HIP_TRY(hipMemcpyAsync(c->h_cnt, c->fl_int, 14 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1512,7 +1534,7 @@ int lagot_fluid_step(lagot_ctx *c, int64_t n, float *x, float *y, float *z, cons
                      double *psi_inout, const double *mass, const double *mu, double *v_inout,
                      const lagot_fluid_params *prm, const lagot_opts *opts, lagot_stats *stats, int32_t *cg_iters) {
     if (!c || !x || !y || !z || !nu || !psi_inout || !mass || !v_inout || !prm || n <= 0) return LAGOT_EINVAL;
-    if (!box_ok(box) || !(prm->dt > 0.0 && std::isfinite(prm->dt))) return LAGOT_EINVAL;
+    if (!box_ok(box) || !fluid_params_ok(*prm, mu != nullptr)) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     AdvectBounds bd;
     double ext = 0.0;

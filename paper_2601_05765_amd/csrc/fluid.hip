@@ -187,10 +187,9 @@ __device__ inline double *P3(const Cg3Bufs &g, int slot, int q) { return g.part 
 __device__ inline double *P3_RHO0(const Cg3Bufs &g, int c) { return g.part + ((int64_t)18 + c) * g.nb; }
 
 // r_0 = b, u_0 = r_0 / D, w_0 = A u_0, p_{-1} = s_{-1} = x_0 = 0
-__global__ __launch_bounds__(C3B) void k_cg3_init(int64_t n, const int32_t *__restrict__ hcol,
-                                                  const float *__restrict__ hval, const int32_t *__restrict__ hcnt,
-                                                  const double *__restrict__ diag, const double *__restrict__ b,
-                                                  Cg3Bufs g) {
+__global__ __launch_bounds__(C3B) void k_cg3_init(int64_t n, const int32_t *__restrict__ rp,
+                                                  const int2 *__restrict__ ent, const double *__restrict__ diag,
+                                                  const double *__restrict__ b, Cg3Bufs g) {
     __shared__ double sh[C3B / 64][12];
     const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);  // row blocks of one XCD are contiguous
     if (blk == 0 && threadIdx.x < 16) {
@@ -202,12 +201,11 @@ __global__ __launch_bounds__(C3B) void k_cg3_init(int64_t n, const int32_t *__re
     const bool has = row < n;
     double acc[3] = {0.0, 0.0, 0.0};
     if (has) {
-        const int c = hcnt[row];
-        const int32_t *cr = hcol + row * FCAP;
-        const float *vr = hval + row * FCAP;
-        for (int f = l; f < c; f += C3L) {
-            const int j = cr[f];
-            const double v = (double)vr[f] / diag[j];
+        const int e1 = rp[row + 1];
+        for (int f = rp[row] + l; f < e1; f += C3L) {
+            const int2 e = ent[f];
+            const int j = e.x;
+            const double v = (double)__int_as_float(e.y) / diag[j];
 #pragma unroll
             for (int q = 0; q < 3; ++q) acc[q] = fma(v, b[q * n + j], acc[q]);
         }
@@ -241,8 +239,8 @@ __global__ __launch_bounds__(C3B) void k_cg3_init(int64_t n, const int32_t *__re
 
 // Iteration k = *kbase + m of the three systems (the host advances kbase per chunk).
 __global__ __launch_bounds__(C3B) void k_cg3_iter(int64_t n, int m, double rtol2, int cap,
-                                                  const int32_t *__restrict__ hcol, const float *__restrict__ hval,
-                                                  const int32_t *__restrict__ hcnt, Cg3Bufs g) {
+                                                  const int32_t *__restrict__ rp, const int2 *__restrict__ ent,
+                                                  Cg3Bufs g) {
     __shared__ double sh[C3B / 64][12];
     const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);  // row blocks of one XCD are contiguous
     const int k = *g.kbase + m;
@@ -304,13 +302,12 @@ __global__ __launch_bounds__(C3B) void k_cg3_iter(int64_t n, int m, double rtol2
     // u_{k+1} of each neighbour from its stored r_k, w_k, s_{k-1}
     double acc[3] = {0.0, 0.0, 0.0};
     if (has) {
-        const int c = hcnt[row];
-        const int32_t *cr = hcol + row * FCAP;
-        const float *vr = hval + row * FCAP;
-        for (int f = l; f < c; f += C3L) {
+        const int e1 = rp[row + 1];
+        for (int f = rp[row] + l; f < e1; f += C3L) {
+            const int2 e = ent[f];
             double r[3], w[3], s[3], d;
-            load_rec3(crec, cr[f], r, w, s, d);
-            const double v = (double)vr[f] / d;
+            load_rec3(crec, e.x, r, w, s, d);
+            const double v = (double)__int_as_float(e.y) / d;
 #pragma unroll
             for (int q = 0; q < 3; ++q) acc[q] = fma(v, fma(-alpha[q], fma(beta[q], s[q], w[q]), r[q]), acc[q]);
         }
@@ -360,6 +357,17 @@ __global__ void k_cg3_advance(int chunk, int cap, Cg3Bufs g) {
     *g.remaining = cnt;
 }
 
+// The rows of the scaled matrix packed back to back, (column, value bits) per entry:
+// the PCG then reads one contiguous run per row instead of two 64-entry row blocks.
+__global__ __launch_bounds__(FB) void k_pack_rows(int64_t n, const int32_t *__restrict__ hcol,
+                                                  const float *__restrict__ hval, const int32_t *__restrict__ hcnt,
+                                                  const int32_t *__restrict__ rp, int2 *__restrict__ ent) {
+    const int64_t i = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * FB + threadIdx.x;
+    if (i >= n) return;
+    const int c = hcnt[i], o = rp[i];
+    for (int f = 0; f < c; ++f) ent[o + f] = make_int2(hcol[i * FCAP + f], __float_as_int(hval[i * FCAP + f]));
+}
+
 // out[3 perm[i] + q] = x[3 i + q]
 __global__ __launch_bounds__(FB) void k_scatter3(int64_t n, const int32_t *__restrict__ perm,
                                                  const double *__restrict__ x, double *__restrict__ out) {
@@ -394,14 +402,19 @@ void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, cons
 
 int cg3_blocks(int64_t n) { return (int)((n + C3S - 1) / C3S); }
 
-void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
-                     const double *diag, const double *b, const Cg3Bufs &g) {
-    hipLaunchKernelGGL(k_cg3_init, dim3(cg3_blocks(n)), dim3(C3B), 0, st, n, hcol, hval, hcnt, diag, b, g);
+void launch_pack_rows(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
+                      const int32_t *rp, int2 *ent) {
+    hipLaunchKernelGGL(k_pack_rows, dim3(nb(n)), dim3(FB), 0, st, n, hcol, hval, hcnt, rp, ent);
 }
 
-void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *hcol, const float *hval,
-                     const int32_t *hcnt, const Cg3Bufs &g) {
-    hipLaunchKernelGGL(k_cg3_iter, dim3(cg3_blocks(n)), dim3(C3B), 0, st, n, m, rtol2, cap, hcol, hval, hcnt, g);
+void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *rp, const int2 *ent, const double *diag,
+                     const double *b, const Cg3Bufs &g) {
+    hipLaunchKernelGGL(k_cg3_init, dim3(cg3_blocks(n)), dim3(C3B), 0, st, n, rp, ent, diag, b, g);
+}
+
+void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *rp, const int2 *ent,
+                     const Cg3Bufs &g) {
+    hipLaunchKernelGGL(k_cg3_iter, dim3(cg3_blocks(n)), dim3(C3B), 0, st, n, m, rtol2, cap, rp, ent, g);
 }
 
 void launch_cg3_advance(hipStream_t st, int chunk, int cap, const Cg3Bufs &g) {

@@ -287,10 +287,13 @@ void launch_p1_laplacian(hipStream_t st, int64_t n, const int32_t *perm, const i
                          const int32_t *hcnt, const double *mu, double mu0, const double *u, double *out,
                          int32_t *bad);
 int cg3_blocks(int64_t n);
-void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
-                     const double *diag, const double *b, const Cg3Bufs &g);
-void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *hcol, const float *hval,
-                     const int32_t *hcnt, const Cg3Bufs &g);
+// packed rows: rp [n+1] (exclusive scan of hcnt), ent [rp[n]] = (column, float bits of the value)
+void launch_pack_rows(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
+                      const int32_t *rp, int2 *ent);
+void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *rp, const int2 *ent, const double *diag,
+                     const double *b, const Cg3Bufs &g);
+void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *rp, const int2 *ent,
+                     const Cg3Bufs &g);
 void launch_cg3_advance(hipStream_t st, int chunk, int cap, const Cg3Bufs &g);
 // out[3 perm[i] + q] = x[3 i + q]
 void launch_scatter3(hipStream_t st, int64_t n, const int32_t *perm, const double *x, double *out);

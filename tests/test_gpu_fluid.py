@@ -309,3 +309,18 @@ def test_fluid_steps_dam_break_100k(ctx):
     P = torch.stack([x, y, z], 1).double()
     assert float(P.min()) > 0.0 and float(P.max()) < 1.0
     assert float(v[:, 2].mean()) < 0  # the column falls
+
+
+def test_fluid_step_rejects_bad_parameters_before_moving(ctx):
+    import torch
+    import paper_2601_05765_amd as L
+    sc, v, _, mass = _fluid_case(500, 6)
+    x, y, z = _sites(sc)
+    x0 = x.clone()
+    psi = _t(sc.psi0, torch.float64)
+    for bad in (dict(eps=-1.0), dict(dt=0.0), dict(gamma=float("nan")), dict(cg_rtol=2.0)):
+        with pytest.raises(L.LagotError) as ei:
+            ctx.fluid_step(x, y, z, _t(sc.nu, torch.float64), psi, _t(mass, torch.float64), _t(v, torch.float64),
+                           L.default_fluid_params(**bad))
+        assert ei.value.code == L.EINVAL
+        assert torch.equal(x, x0)
