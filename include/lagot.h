@@ -11,7 +11,10 @@
  *
  * (the air object has weight 0). The solver finds the unique weights with
  * |C_i| = nu_i for all i by damped Newton on the Kantorovich functional, whose
- * gradient is nu_i - |C_i| and whose Hessian is eq. (2) (section 3.1).
+ * gradient is nu_i - |C_i| and whose Hessian is eq. (2) (section 3.1). Around the
+ * solve, the fluid model of section 5 (cell centroids, the P1 Laplacian of eq. (3),
+ * the semi-implicit velocity update of eq. (4) and the whole step) reuses the same
+ * cells, facet weights and conjugate gradients.
  *
  * Conventions for every entry point below
  *   - Array arguments are DEVICE pointers (for example torch tensor storage on
@@ -348,9 +351,10 @@ int lagot_fluid_velocity(lagot_ctx *ctx, int64_t n, const float *x, const float 
  *           site-major; in: nu [n] float64, mass [n] float64 (> 0), mu [n] or NULL,
  *           prm, opts (NULL = defaults) HOST; out: stats (the solve's, HOST, may be
  *           NULL), cg_iters [3] HOST int32 or NULL.
- * Errors: those of lagot_solve and lagot_fluid_velocity. After a solve error the
- *         positions have moved, psi_inout holds the solve's last accepted weights and
- *         v_inout is unchanged. Synchronises the stream.
+ * Errors: those of lagot_solve and lagot_fluid_velocity; invalid parameters are
+ *         rejected before anything moves. After a solve error the positions have moved,
+ *         psi_inout holds the solve's last accepted weights and v_inout is unchanged.
+ *         Synchronises the stream.
  */
 int lagot_fluid_step(lagot_ctx *ctx, int64_t n, float *x, float *y, float *z, const double *nu, lagot_box box,
                      double *psi_inout, const double *mass, const double *mu, double *v_inout,
