@@ -11,6 +11,7 @@ Contents
   hessian(...)        gradient nu - V and the sparse matrix -Hess K (eq. (2))
   newton_solve(...)   damped Newton with KMT step control (Alg. 1)
   p1_weights(...)     facet weights w_ij = |V_ij| / (2 |p_j - p_i|) of the P1 Laplacian (eq. (3))
+  p1_rows(...)        the same weights for a few rows only (sampled checks at full size)
   p1_laplacian(...)   the P1 (cotan) Laplacian of a per-site field, optional mu_ij (eq. (3))
   fluid_velocity(...) the semi-implicit velocity update with pressure spring, gravity,
                       surface tension and viscosity (section 5, eq. (4))
@@ -176,6 +177,35 @@ def p1_weights(xyz: np.ndarray, c: Cells):
     d = np.linalg.norm(xyz[S.row] - xyz[S.col], axis=1)
     w = Abar / (2.0 * d)
     return sp.coo_matrix((w, (S.row, S.col)), shape=(n, n)).tocsr()
+
+
+def p1_rows(xyz: np.ndarray, psi: np.ndarray, rows, box=((0, 0, 0), (1, 1, 1)), domain=None) -> dict:
+    """The rows ``rows`` of the facet-weight matrix of p1_weights, without evaluating every
+    cell: the cells of those rows and of all their neighbours are evaluated (brute force),
+    and each weight uses both sides' areas as p1_weights does. Returns {i: {j: w_ij}}."""
+    xyz = np.asarray(xyz, np.float64)
+    psi = np.asarray(psi, np.float64)
+    rows = np.unique(np.asarray(rows, np.int64))
+    r = np.sqrt(np.maximum(psi, 0.0))
+    # a cell can list i only if its ball meets ball i: evaluate the rows and every such site
+    near = set(rows.tolist())
+    for i in rows.tolist():
+        d = np.linalg.norm(xyz - xyz[i], axis=1)
+        near.update(np.nonzero(d < r + r[i])[0].tolist())
+    ev = np.asarray(sorted(near), np.int64)
+    c = cells(xyz[:, 0], xyz[:, 1], xyz[:, 2], psi, box, idx=ev, domain=domain)
+    side = {int(i): c.facets(k) for k, i in enumerate(ev)}
+    out = {}
+    for i in rows.tolist():
+        # row i holds every j that lists i or that i lists (union pattern)
+        js = set(side[i]) | {j for j in side if j != i and i in side[j]}
+        row = {}
+        for j in sorted(js):
+            a, b = side[i].get(j), side[j].get(i)
+            abar = a if b is None else (b if a is None else 0.5 * (a + b))
+            row[j] = abar / (2.0 * float(np.linalg.norm(xyz[j] - xyz[i])))
+        out[i] = row
+    return out
 
 
 def _mu_scaled(W, mu):

@@ -324,3 +324,31 @@ def test_fluid_step_rejects_bad_parameters_before_moving(ctx):
                            L.default_fluid_params(**bad))
         assert ei.value.code == L.EINVAL
         assert torch.equal(x, x0)
+
+
+def test_p1_laplacian_dam_break_100k_sampled(ctx, oracle_mod):
+    """The measured workload at full size: 200 sampled rows of the Laplacian against the
+    oracle's rows (their cells and every overlapping cell evaluated by brute force)."""
+    import scipy.sparse as sp
+    import torch
+    n = 100_000
+    _say(f"case: P1 Laplacian, dam_break {n}, 200 sampled rows")
+    sc = scenes.dam_break(n, 0)
+    xyz = _xyz(sc)
+    rng = np.random.default_rng(21)
+    u = rng.normal(size=(n, 3))
+    mu = rng.uniform(0.0, 3.0, n)
+    x, y, z = _sites(sc)
+    got = ctx.p1_laplacian(x, y, z, _t(sc.psi0, torch.float64), _t(u, torch.float64),
+                           mu=_t(mu, torch.float64)).cpu().numpy()
+    rows = np.sort(rng.choice(n, 200, replace=False))
+    R = oracle_mod.p1_rows(xyz, sc.psi0, rows)
+    ri = [i for i in rows for _ in R[int(i)]]
+    rj = [j for i in rows for j in R[int(i)]]
+    rv = [w for i in rows for w in R[int(i)].values()]
+    W = sp.coo_matrix((rv, (ri, rj)), shape=(n, n)).tocsr()
+    want = oracle_mod.p1_laplacian(W, u, mu)[rows]
+    tol = _row_tol(W, sc.psi0, xyz, u, mu)[rows] + 1e-14
+    e = np.abs(got[rows] - want).max(axis=1) / tol
+    _say(f"  max err / bound {e.max():.3f}")
+    assert e.max() <= 1.0

@@ -192,3 +192,21 @@ def test_spring_acceleration_of_a_ball_at_a_wall(oracle_mod, m):
     st = oracle_mod.fluid_velocity(p, np.array([r * r]), v0, np.array([m]), 2.0, dt=dt, eps=eps, gamma=1.0,
                                    gravity=(0, 0, -9.81))
     assert np.allclose(st.v[0], v0[0] + dt * np.array([0, 0, shift / eps ** 2 - 9.81]), rtol=1e-12, atol=1e-12)
+
+
+def test_p1_rows_match_the_full_matrix(oracle_mod):
+    """The sampled-row form gives the rows of the full assembly (same union pattern)."""
+    rng = np.random.default_rng(11)
+    n = 300
+    xyz = rng.uniform(0.05, 0.95, (n, 3))
+    psi = rng.uniform(0.06, 0.12, n) ** 2
+    c = oracle_mod.cells(xyz[:, 0], xyz[:, 1], xyz[:, 2], psi)
+    W = oracle_mod.p1_weights(xyz, c).tocsr()
+    rows = rng.choice(n, 25, replace=False)
+    got = oracle_mod.p1_rows(xyz, psi, rows)
+    for i in rows:
+        lo, hi = W.indptr[i], W.indptr[i + 1]
+        want = dict(zip(W.indices[lo:hi].tolist(), W.data[lo:hi].tolist()))
+        assert set(got[int(i)]) == set(want)
+        for j, w in want.items():
+            assert got[int(i)][j] == pytest.approx(w, rel=1e-13)
