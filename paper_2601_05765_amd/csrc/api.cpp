@@ -87,6 +87,7 @@ struct lagot_ctx {
     int64_t cap_ent = 0;
     int64_t cap_fl = 0;
     int fl_chunk = 32;          // fluid PCG launches between host checks (adapted per call)
+    bool fl_reuse = false;      // lagot_fluid_step's velocity update: reuse its solve's sorted sites
     float4 *dom_d = nullptr;    // [DOM_MAX] convex domain planes (lagot_set_domain)
     int ndom = 0;
     int wall_w = 6;             // wall areas per site in the wall buffer (6, or the domain's planes)
@@ -1103,14 +1104,22 @@ bool fluid_params_ok(const lagot_fluid_params &p, bool per_site_mu) {
 int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
                 const lagot_box &box, double *cen) {
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
-    c->tpc = c->tpc_default;
     c->ms_cell = 0.0;
     c->cell_launches = 0;
     c->ev_pending = false;
-    const int64_t offs[2] = {0, n};
-    int rc = prepare(c, 1, offs, x, y, z, psi, nullptr, &box, nullptr);
-    if (rc) return rc;
     hipStream_t st = c->stream;
+    int rc = LAGOT_OK;
+    if (c->fl_reuse) {
+        // the solve that just ran on this context sorted these sites and left the final
+        // weights in psi_s (float32 shadow in pos_s.w): only r_max follows the weights
+        if (c->n != n || c->B != 1) return LAGOT_EINVAL;
+        launch_rmax(st, batch(c), -1, c->psi_s, c->rmax);
+    } else {
+        c->tpc = c->tpc_default;
+        const int64_t offs[2] = {0, n};
+        rc = prepare(c, 1, offs, x, y, z, psi, nullptr, &box, nullptr);
+        if (rc) return rc;
+    }
     launch_zero_i32(st, c->fb_inst, 1);
     c->cen_out = cen;
     evaluate(c, -1, c->psi_s, false, nullptr);
@@ -1548,7 +1557,10 @@ int lagot_fluid_step(lagot_ctx *c, int64_t n, float *x, float *y, float *z, cons
     launch_advect(c->stream, n, x, y, z, v_inout, prm->dt, bd, c->dom_d, c->ndom);
     int rc = single_instance(c, n, x, y, z, nu, box, psi_inout, opts, stats, false);
     if (rc) return rc;
-    return lagot_fluid_velocity(c, n, x, y, z, psi_inout, box, mass, mu, v_inout, prm, v_inout, nullptr, cg_iters);
+    c->fl_reuse = true;
+    rc = lagot_fluid_velocity(c, n, x, y, z, psi_inout, box, mass, mu, v_inout, prm, v_inout, nullptr, cg_iters);
+    c->fl_reuse = false;
+    return rc;
 }
 
 const char *lagot_strerror(int code) {
