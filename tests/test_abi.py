@@ -81,3 +81,28 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text and "lagot_oracle" not in text, f
+
+
+def test_fluid_params_defaults_and_layout(lib, tmp_path):
+    """lagot_fluid_params: the binding's structure matches the header, and the library's
+    defaults are the documented ones (host-only call, no GPU needed)."""
+    import ctypes
+    import paper_2601_05765_amd as L
+    p = L.default_fluid_params()
+    assert (p.dt, p.eps, p.gamma, p.mu, list(p.gravity), p.cg_rtol, p.cg_max_iter) == \
+        (1e-3, 1.0, 0.0, 0.0, [0.0, 0.0, -9.81], 1e-10, 2000)
+    src = tmp_path / "fl.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "lagot.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(lagot_fluid_params), offsetof(lagot_fluid_params, gravity),
+         offsetof(lagot_fluid_params, cg_rtol), offsetof(lagot_fluid_params, cg_max_iter));
+  return 0; }
+''')
+    exe = tmp_path / "fl"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).decode().split()]
+    F = L.FluidParams
+    assert got == [ctypes.sizeof(F), F.gravity.offset, F.cg_rtol.offset, F.cg_max_iter.offset]
