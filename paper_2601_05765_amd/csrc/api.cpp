@@ -180,17 +180,21 @@ void free_alt(lagot_ctx *c) {
     c->cap_alt = 0;
 }
 
-int ensure_alt(lagot_ctx *c, int64_t n) {
-    if (n <= c->cap_alt) return LAGOT_OK;
+// The second output set is either not allocated (cap_alt = 0) or exactly as large as
+// the first (cap_alt = cap_n): the two sets are swapped by pointer, so after a kept
+// learned guess either one may serve as the primary set, and both must hold cap_n rows.
+// ensure_sites frees both sets whenever it grows the first.
+int ensure_alt(lagot_ctx *c) {
+    if (c->cap_alt == c->cap_n) return LAGOT_OK;
     free_alt(c);
-    const size_t N = (size_t)n;
+    const size_t N = (size_t)c->cap_n;
     HIP_TRY(dalloc(&c->V2, N));
     HIP_TRY(dalloc(&c->K2, N));
     HIP_TRY(dalloc(&c->fcol2, FCAP * N));
     HIP_TRY(dalloc(&c->farea2, FCAP * N));
     HIP_TRY(dalloc(&c->fcnt2, N));
     HIP_TRY(dalloc(&c->flags2, N));
-    c->cap_alt = n;
+    c->cap_alt = c->cap_n;
     return LAGOT_OK;
 }
 
@@ -235,6 +239,7 @@ void collect_cell_time(lagot_ctx *c) {
 
 int ensure_sites(lagot_ctx *c, int64_t n) {
     if (n <= c->cap_n) return LAGOT_OK;
+    free_alt(c);  // either set may be the primary one (see ensure_alt): both go
     free_sites(c);
     const size_t N = (size_t)n;
     HIP_TRY(dalloc(&c->pos_orig, N));
@@ -835,7 +840,7 @@ int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
     if (hf[0] != 0 || !(eps0 > 0.0)) return LAGOT_OK;  // Newton handles this start itself
     const double t0 = now_ms();
     rc = build_features(c);
-    if (!rc) rc = ensure_alt(c, c->n);
+    if (!rc) rc = ensure_alt(c);
     if (rc) return rc;
     mlp_forward_dev(c, (int)c->n, c->feat_s, c->inf_a, c->inf_b, c->mlp_out);
     launch_apply_guess(st, c->n, c->psi_s, c->nu_s, c->mlp_out, c->psi_trial, c->pos_s);

@@ -58,3 +58,20 @@ def assert_close(rep, tol=TOL):
     assert rep["K"] <= tol, rep
     assert rep["A"] <= tol, rep
     assert rep["W"] <= tol, rep
+
+
+def newton_direction_bound(oracle_mod, P, psi, c, Hd, g, u, cg_rtol, tol=TOL):
+    """Bound on ||u_gpu - u||_2 for a Newton direction u of (-Hess K) u = g (eq. (2)) that the
+    GPU solves with float32 facet areas and a PCG stopped at ||r|| <= cg_rtol ||g||:
+      ||e||_2 <= (cg_rtol ||g||_2 + ||dH||_2 ||u||_2) / lambda_min(-Hess K),
+    first order in dH, where ||dH||_2 <= max row sum of |dH| (symmetric) and the entries of
+    dH are bounded by the cell tolerances (|dA_ij| <= tol pi r_i^2 on both sides' areas of
+    w_ij = Abar_ij / 2d_ij, |dK_i| <= tol 4 pi r_i^2 in K_i / 2r_i)."""
+    r = np.sqrt(np.maximum(psi, 0.0))
+    W = oracle_mod.p1_weights(P, c).tocoo()
+    d = np.linalg.norm(P[W.row] - P[W.col], axis=1)
+    rowb = np.zeros(len(psi))
+    np.add.at(rowb, W.row, tol * math.pi * np.maximum(r[W.row], r[W.col]) ** 2 / (2.0 * d))
+    dH = float((2.0 * rowb + tol * 4.0 * math.pi * r * r / (2.0 * np.maximum(r, 1e-300))).max())
+    lam_min = float(np.linalg.eigvalsh(Hd)[0])
+    return (cg_rtol * float(np.linalg.norm(g)) + dH * float(np.linalg.norm(u))) / lam_min

@@ -135,6 +135,26 @@ def test_dam_break_100k_sampled(ctx, oracle_mod):
     assert float(out["vol"].sum()) < 1.0
 
 
+def test_dam_break_100k_converged_sampled(ctx, oracle_mod):
+    """Cells at the converged weights of the 100k dam break (the state every later Newton
+    evaluation and the fluid step sees): volumes, spherical and wall areas, facet areas and
+    connectivity of 3,000 sampled cells against the oracle."""
+    _say("case: dam_break 100k at its converged weights, 3000 sampled cells")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.dam_break(100_000, 0)
+    x, y, z, psi = _dev(sc)
+    nu = torch.tensor(sc.nu, dtype=torch.float64, device="cuda")
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    assert st.status == 0
+    p = psi.cpu().numpy()
+    idx = np.sort(np.random.default_rng(4).choice(sc.n, 3000, replace=False))
+    out, orc = _run(ctx, oracle_mod, sc.x, sc.y, sc.z, p, idx=idx)
+    rep = compare(out, orc, p, idx=idx)
+    _say(f"  {rep}")
+    assert_close(rep)
+
+
 def test_empty_cells(ctx, oracle_mod):
     _say("case: empty cells (engulfed ball, psi <= 0)")
     x = np.array([0.4, 0.45, 0.7, 0.2], np.float32)

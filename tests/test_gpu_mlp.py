@@ -157,3 +157,35 @@ def test_training_reduces_loss(ctx):
         first = loss if first is None else first
     _say(f"  loss {first:.4f} -> {loss:.4f}")
     assert loss < 0.1 * first
+
+
+def test_adam_three_steps_against_oracle(ctx):
+    """Three GPU training steps on one batch: after each step the GPU's parameters equal the
+    oracle's Adam (bias corrections at t = 1, 2, 3) applied to the GPU's own gradients."""
+    import torch
+    _say("case: three Adam steps against the oracle optimiser")
+    params = mlp.init_params(9)
+    v = flat(params)
+    ctx.mlp_set_params(_t(v, torch.float32))
+    rng = np.random.default_rng(10)
+    m = 1024
+    X = rng.normal(size=(m, 64))
+    X[:, 50:] = 0
+    bits = (np.asarray(bf16_round(X), np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+    y = rng.normal(size=m)
+    lr = 3e-4
+    ref = [v.astype(np.float64)]
+    opt = mlp.Adam(ref, lr=lr)
+    big = np.ones(v.shape[0], bool)
+    for t in range(3):
+        ctx.mlp_train_step(_t(bits, torch.int16), _t(y, torch.float32), _t(np.arange(m), torch.int32), lr)
+        g = ctx.mlp_last_grads().cpu().numpy().astype(np.float64)
+        big &= np.abs(g) > 1e-5
+        opt.step(ref, [g])
+        gpu = ctx.mlp_get_params().cpu().numpy().astype(np.float64)
+        # float32 master weights: |p| * 2^-23 per rounding, a few roundings per step
+        tolp = 4e-7 * np.abs(ref[0]) + 1e-3 * lr
+        bad = np.abs(gpu - ref[0])[big] > tolp[big]
+        _say(f"  step {t + 1}: max |gpu - oracle| {np.abs(gpu - ref[0])[big].max():.3e} over {big.sum()} params")
+        assert not bad.any(), t
+        assert np.all(np.abs(gpu - v) <= (t + 1) * lr * 1.001 + 4e-7 * np.abs(v))

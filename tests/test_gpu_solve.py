@@ -239,3 +239,82 @@ def test_solve_min_volume_rule_only(ctx, oracle_mod):
     p1, p2 = psi.cpu().numpy(), psi2.cpu().numpy()
     assert np.max(np.abs(p1 - p2) / np.abs(p2)) <= 1e-3
     assert _oracle_err(oracle_mod, sc, p1) <= 1e-5
+
+
+def test_newton_step_matches_oracle_direction(ctx, oracle_mod):
+    """One lagot_newton_step against the oracle's Newton step at the same step length:
+    psi_1 - psi_0 = alpha u, u the dense-Cholesky solution of (-Hess K) u = nu - V (eq. (2),
+    Algorithm 1), element by element within the bound of a float32 Hessian (cell
+    tolerances) and a PCG stopped at cg_rtol (tests/parity.py). A wrong diagonal term
+    K_i / (2 r_i) moves u twenty times further than this bound."""
+    _say("case: one Newton step on slab_uniform 1k seed 3 against the oracle direction")
+    import scipy.linalg as sla
+    import paper_2601_05765_amd as L
+    from parity import newton_direction_bound
+    sc = scenes.slab_uniform(1000, 3)
+    P = sc.xyz64()
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, sc.psi0)
+    H, _ = oracle_mod.hessian(P, sc.psi0, c)
+    g = sc.nu - c.V
+    Hd = H.toarray()
+    u = sla.cho_solve(sla.cho_factor(Hd), g)
+    bound = newton_direction_bound(oracle_mod, P, sc.psi0, c, Hd, g, u, cg_rtol=1e-6)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.newton_step(x, y, z, nu, psi, opts=L.default_opts(cg_rtol=1e-6))
+    _say(f"  {st.as_dict()} bound {bound:.3e}")
+    assert st.status == 0 and st.newton_iters == 1
+    alpha = 0.5 ** st.halvings
+    step = psi.cpu().numpy() - sc.psi0
+    err = float(np.linalg.norm(step - alpha * u))
+    _say(f"  alpha {alpha} |step - alpha u|_2 {err:.3e} (|alpha u|_inf {alpha * np.abs(u).max():.3e})")
+    assert err <= alpha * bound
+
+
+def test_step_halving_limit(ctx, oracle_mod):
+    """LAGOT_ELINESEARCH: on slab_uniform(200, 4) from 3 psi0 the full Newton step and its
+    half both empty a cell (the oracle's alpha = 1 and 1/2 trials have min V = 0; alpha = 1/4
+    keeps min V at 3.6 eps0), so max_halvings 0 and 1 end the search with the start
+    weights untouched, and 2 takes the step."""
+    _say("case: step-halving limit (max_halvings 0, 1, 2)")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(200, 4)
+    for mh, want in ((0, L.ELINESEARCH), (1, L.ELINESEARCH), (2, L.OK)):
+        x, y, z, nu, psi = _dev(sc, sc.psi0 * 3.0)
+        start = psi.clone()
+        st = ctx.newton_step(x, y, z, nu, psi, opts=L.default_opts(max_halvings=mh), check=False)
+        _say(f"  max_halvings {mh}: {st.as_dict()}")
+        assert st.status == want
+        if want == L.ELINESEARCH:
+            assert torch.equal(psi, start)
+        else:
+            assert st.halvings == 2 and not torch.equal(psi, start)
+            c1 = oracle_mod.cells(sc.x, sc.y, sc.z, psi.cpu().numpy())
+            c0 = oracle_mod.cells(sc.x, sc.y, sc.z, sc.psi0 * 3.0)
+            assert np.linalg.norm(sc.nu - c1.V) < np.linalg.norm(sc.nu - c0.V)
+
+
+def test_cells_nnz_capacity(ctx):
+    """lagot_cells with a facet capacity below the facet count: LAGOT_ECAPACITY with the
+    needed count in nnz_out; the binding's retry with that capacity gives the same CSR."""
+    _say("case: lagot_cells nnz_cap too small")
+    import ctypes
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 1)
+    x, y, z, nu, psi = _dev(sc)
+    full = ctx.cells(x, y, z, psi)
+    nnz_full = int(full["row_ptr"][-1])
+    lib = L.load()
+    vol = torch.empty(sc.n, dtype=torch.float64, device="cuda")
+    rp = torch.empty(sc.n + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(16, dtype=torch.int32, device="cuda")
+    fa = torch.empty(16, dtype=torch.float32, device="cuda")
+    nnz = ctypes.c_int64(0)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    rc = lib.lagot_cells(ctx._h, sc.n, p(x), p(y), p(z), p(psi), L.make_box(), p(vol), None, None, p(rp), p(col),
+                         p(fa), 16, ctypes.byref(nnz))
+    assert rc == L.ECAPACITY and nnz.value == nnz_full
+    small = ctx.cells(x, y, z, psi, nnz_per_cell=1)
+    for k in ("row_ptr", "col", "area", "vol"):
+        assert torch.equal(small[k], full[k]), k

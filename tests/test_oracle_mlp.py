@@ -110,3 +110,29 @@ def test_adam_first_step_closed_form():
     opt.step(p, g)
     expect = np.array([1.0, -2.0, 0.5]) - 0.1 * g[0] / (np.abs(g[0]) + 1e-8)
     assert np.allclose(p[0], expect, rtol=1e-12)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias corrections make every step exactly
+    lr g / (|g| + eps): m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2 (pins t > 1)."""
+    p = [np.array([0.25, -1.5, 3.0])]
+    g = np.array([0.02, -0.7, 1e-4])
+    opt = mlp.Adam(p, lr=0.05)
+    for t in range(1, 8):
+        opt.step(p, [g.copy()])
+        expect = np.array([0.25, -1.5, 3.0]) - t * 0.05 * g / (np.abs(g) + 1e-8)
+        assert np.allclose(p[0], expect, rtol=1e-12, atol=1e-14), t
+
+
+def test_adam_alternating_gradient_hand_values():
+    """Gradients g, -g, g: the bias-corrected first moments are g, -0.01 g / 0.19 and
+    0.091 g / 0.271 (worked by hand), and sqrt of the corrected second moment is |g|."""
+    g0 = np.array([0.5, -0.2])
+    p = [np.zeros(2)]
+    opt = mlp.Adam(p, lr=1.0, eps=0.0)
+    mhat = [1.0, -0.01 / 0.19, 0.091 / 0.271]
+    total = np.zeros(2)
+    for t, s in enumerate([1.0, -1.0, 1.0]):
+        opt.step(p, [s * g0])
+        total -= mhat[t] * g0 / np.abs(g0)
+        assert np.allclose(p[0], total, rtol=1e-12), t

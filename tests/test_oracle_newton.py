@@ -81,3 +81,58 @@ def test_slab_1k_unique_weights(oracle_mod, slab_solution):
     psi_a, st_a = oracle_mod.newton_solve(P, sc.nu, psi, tol=1e-9)
     assert st_a.status == "ok"
     np.testing.assert_allclose(psi_a, psi_b, rtol=1e-6)
+
+
+def test_pcg_matches_direct_solve_on_a_graph_laplacian(oracle_mod):
+    """The oracle's Jacobi-PCG (used above dense_max sites) against a sparse direct solve of
+    a shifted graph Laplacian with uneven weights (SPD, the structure of -Hess K)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    rng = np.random.default_rng(5)
+    n = 400
+    i = rng.integers(0, n, 3000)
+    j = rng.integers(0, n, 3000)
+    keep = i != j
+    w = rng.uniform(0.1, 3.0, keep.sum())
+    W = sp.coo_matrix((w, (i[keep], j[keep])), shape=(n, n)).tocsr()
+    W = (W + W.T).tocsr()
+    shift = rng.uniform(0.01, 1.0, n)
+    diag = np.asarray(W.sum(axis=1)).ravel() + shift
+    H = (sp.diags(diag) - W).tocsr()
+    b = rng.normal(size=n)
+    x = oracle_mod.pcg(H, b, diag, rtol=1e-13)
+    ref = sla.spsolve(H.tocsc(), b)
+    np.testing.assert_allclose(x, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+
+
+def test_newton_pcg_branch_matches_cholesky(oracle_mod, slab_solution):
+    """newton_solve above dense_max (Jacobi-PCG directions) reaches the same weights as the
+    dense Cholesky directions on the 1,000-site slab (the solution is unique)."""
+    sc, P, psi, st = slab_solution
+    psi_cg, st_cg = oracle_mod.newton_solve(P, sc.nu, sc.psi0, tol=1e-5, dense_max=0)
+    assert st_cg.status == "ok" and st_cg.iters == st.iters
+    np.testing.assert_allclose(psi_cg, psi, rtol=1e-9)
+    # the same trajectory: residuals of every accepted iterate agree
+    for a, b in zip(st.history, st_cg.history):
+        assert a["alpha"] == b["alpha"]
+        assert b["gnorm"] == pytest.approx(a["gnorm"], rel=1e-7)
+
+
+def test_newton_step_bound_separates_a_wrong_diagonal(oracle_mod):
+    """The bound that the GPU Newton-step test uses is tight enough to see a wrong eq. (2)
+    diagonal: a direction with K_i / r_i (or K_i / (4 r_i)) in place of K_i / (2 r_i) lies
+    far outside it (the mistake is planted here, in the oracle's matrix, on the CPU)."""
+    import scipy.linalg as sla
+    from parity import newton_direction_bound
+    sc = scenes.slab_uniform(1000, 3)
+    P = sc.xyz64()
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, sc.psi0)
+    H, diag = oracle_mod.hessian(P, sc.psi0, c)
+    g = sc.nu - c.V
+    Hd = H.toarray()
+    u = sla.cho_solve(sla.cho_factor(Hd), g)
+    bound = newton_direction_bound(oracle_mod, P, sc.psi0, c, Hd, g, u, cg_rtol=1e-6)
+    kterm = c.K / (2.0 * np.sqrt(sc.psi0))
+    for wrong in (Hd + np.diag(kterm), Hd - 0.5 * np.diag(kterm)):
+        u2 = sla.cho_solve(sla.cho_factor(wrong), g)
+        assert np.abs(u2 - u).max() > 20 * bound
