@@ -243,6 +243,20 @@ int lagot_features(lagot_ctx *ctx, int64_t n, const float *x, const float *y, co
  * Synchronises the stream. Errors: EINVAL (no parameters), EHIP. */
 int lagot_mlp_forward(lagot_ctx *ctx, int64_t m, const uint16_t *feats, float *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lagot_mlp_forward without any
+ * allocation. Same arguments, kernels and results. The two bf16 hidden-activation buffers
+ * (2 x m x 128 values) live in one static device array of the library, of
+ * LAGOT_NOALLOC_MAX_ROWS rows (16 MiB; each GPU the library runs on holds its own copy until
+ * the process ends); the parameters are the context's (lagot_mlp_set_params, called before).
+ * The call only enqueues the kernels on the context's stream: out is ready when the stream
+ * reaches that point (it does not synchronise). Every call on one GPU shares that GPU's array,
+ * so calls that overlap on one GPU (two contexts, or streams that run concurrently) race and
+ * must be ordered by the caller. Errors: EINVAL (NULL pointer, m <= 0, no parameters),
+ * ECAPACITY (m > LAGOT_NOALLOC_MAX_ROWS), EHIP. */
+#define LAGOT_NOALLOC_MAX_ROWS 32768
+int lagot_mlp_forward_noalloc(lagot_ctx *ctx, int64_t m, const uint16_t *feats, float *out);
+
 /* One Adam step (lr; beta 0.9, 0.999; eps 1e-8) on the mean squared error of the rows
  * batch_idx[0..batch) (device int32) of feats [nrows x 64] against targets [nrows]
  * (float32, device). *loss (HOST, may be NULL) receives the batch loss before the

@@ -24,9 +24,10 @@ OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
            "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
            "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
-           "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward",
+           "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward", "lagot_mlp_forward_noalloc",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
 MLP_NPARAMS = 41473
+NOALLOC_MAX_ROWS = 32768  # LAGOT_NOALLOC_MAX_ROWS: rows of lagot_mlp_forward_noalloc's static buffers
 
 
 class Box(ctypes.Structure):
@@ -106,10 +107,11 @@ def load():
         lib.lagot_mlp_last_grads.argtypes = [P, P]
         lib.lagot_features.argtypes = [P, I64, P, P, P, P, P, Box, P, P]
         lib.lagot_mlp_forward.argtypes = [P, I64, P, P]
+        lib.lagot_mlp_forward_noalloc.argtypes = [P, I64, P, P]
         lib.lagot_mlp_train_step.argtypes = [P, I64, P, P, P, ctypes.c_int32, ctypes.c_float,
                                              ctypes.POINTER(ctypes.c_float)]
         for f in ("lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_mlp_last_grads", "lagot_features",
-                  "lagot_mlp_forward", "lagot_mlp_train_step"):
+                  "lagot_mlp_forward", "lagot_mlp_forward_noalloc", "lagot_mlp_train_step"):
             getattr(lib, f).restype = I
         lib.lagot_set_threads_per_cell.argtypes = [P, I]
         lib.lagot_set_threads_per_cell.restype = I
@@ -390,6 +392,19 @@ class Context:
                                       ctypes.c_void_p(out.data_ptr()))
         if rc != OK:
             raise LagotError(rc, "lagot_mlp_forward")
+        return out
+
+    def mlp_forward_noalloc(self, feats, out):
+        """lagot_mlp_forward_noalloc: the network output of the rows of feats into the
+        caller's out (float32 [m], device); enqueued on the context's stream, not
+        synchronised."""
+        import torch
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.shape[0] < feats.shape[0]:
+            raise ValueError("out: contiguous float32 with at least one value per row")
+        rc = load().lagot_mlp_forward_noalloc(self._h, feats.shape[0], _dev(feats, torch.int16, "feats"),
+                                              ctypes.c_void_p(out.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_mlp_forward_noalloc")
         return out
 
     def mlp_train_step(self, feats, targets, batch_idx, lr: float, want_loss: bool = True):

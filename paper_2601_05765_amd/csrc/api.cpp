@@ -16,12 +16,19 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "lagot.h"
 #include "lagot_internal.h"
 
 using namespace lagot;
+
+// Device memory of lagot_mlp_forward_noalloc: the two hidden-activation buffers of at most
+// LAGOT_NOALLOC_MAX_ROWS rows, one copy per GPU. Host code never passes this name to a
+// kernel (on the host it is only a stand-in for the symbol); it uses the per-device address
+// that hipGetSymbolAddress returns (noalloc_scratch_ptr).
+static __device__ __align__(256) uint16_t scratch[2 * (size_t)LAGOT_NOALLOC_MAX_ROWS * MLP_HID];
 
 namespace {
 
@@ -144,6 +151,7 @@ struct lagot_ctx {
     bool ev_pending = false;
     double ms_cell = 0.0;
     int cell_launches = 0;
+    uint16_t *noalloc = nullptr;  // this device's copy of the static scratch array
 };
 
 namespace {
@@ -1150,14 +1158,38 @@ void lagot_default_opts(lagot_opts *opts) {
     if (opts) fill_defaults(opts);
 }
 
+// Address of this device's copy of the static scratch array, looked up once per device
+// (with that device current) and kept for the life of the process.
+static int noalloc_scratch_ptr(int device, uint16_t **out) {
+    static std::mutex mu;
+    static std::map<int, uint16_t *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            fprintf(stderr, "lagot: hipGetSymbolAddress(scratch) failed on device %d: %s\n", device,
+                    hipGetErrorString(e));
+            return LAGOT_EHIP;
+        }
+        it = addr.emplace(device, static_cast<uint16_t *>(ptr)).first;
+    }
+    *out = it->second;
+    return LAGOT_OK;
+}
+
 int lagot_create(lagot_ctx **out, int device, void *stream) {
     if (!out) return LAGOT_EINVAL;
     *out = nullptr;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LAGOT_EHIP;
     if (hipSetDevice(device) != hipSuccess) return LAGOT_EHIP;
+    uint16_t *noalloc = nullptr;
+    if (noalloc_scratch_ptr(device, &noalloc) != LAGOT_OK) return LAGOT_EHIP;
     lagot_ctx *c = new lagot_ctx();
     c->device = device;
+    c->noalloc = noalloc;
     c->stream = (hipStream_t)stream;
     if (dalloc(&c->counts, 8) != hipSuccess || dalloc(&c->misc, 8) != hipSuccess ||
         hipHostMalloc((void **)&c->h_cnt, 16 * sizeof(int32_t)) != hipSuccess ||
@@ -1304,6 +1336,22 @@ int lagot_mlp_forward(lagot_ctx *c, int64_t m, const uint16_t *feats, float *out
     if (rc) return rc;
     mlp_forward_dev(c, (int)m, feats, c->inf_a, c->inf_b, out);
     HIP_TRY(hipStreamSynchronize(c->stream));
+    return LAGOT_OK;
+}
+
+int lagot_mlp_forward_noalloc(lagot_ctx *c, int64_t m, const uint16_t *feats, float *out) {
+    if (!c || !feats || !out || m <= 0 || !c->mlp_set) return LAGOT_EINVAL;
+    if (m > LAGOT_NOALLOC_MAX_ROWS) {
+        fprintf(stderr, "lagot: lagot_mlp_forward_noalloc: %lld rows exceed its static buffers (%d rows)\n",
+                (long long)m, LAGOT_NOALLOC_MAX_ROWS);
+        return LAGOT_ECAPACITY;
+    }
+    if (hipSetDevice(c->device) != hipSuccess || !c->noalloc) return LAGOT_EHIP;
+    // the two activation buffers: rows [0, m) of each half of the device's array
+    uint16_t *a = c->noalloc;
+    uint16_t *b = c->noalloc + (size_t)LAGOT_NOALLOC_MAX_ROWS * MLP_HID;
+    mlp_forward_dev(c, (int)m, feats, a, b, out);
+    HIP_TRY(hipGetLastError());
     return LAGOT_OK;
 }
 

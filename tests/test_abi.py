@@ -106,3 +106,13 @@ int main(void) {
     got = [int(v) for v in subprocess.check_output([str(exe)]).decode().split()]
     F = L.FluidParams
     assert got == [ctypes.sizeof(F), F.gravity.offset, F.cg_rtol.offset, F.cg_max_iter.offset]
+
+
+def test_constants_match_header():
+    """The binding's copies of the header's constants (parameter count, row limit of the
+    allocation-free forward)."""
+    import paper_2601_05765_amd as L
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(LAGOT_[A-Z0-9_]+)\s+(-?\d+)\b", text))
+    assert int(defs["LAGOT_MLP_NPARAMS"]) == L.MLP_NPARAMS
+    assert int(defs["LAGOT_NOALLOC_MAX_ROWS"]) == L.NOALLOC_MAX_ROWS
