@@ -88,6 +88,20 @@ typedef struct {
     int residual_test;   /* 1 (default): a step size is kept only if min V >= eps0 and
                             ||nu - V||_2 drops by the factor (1 - alpha/2) (the KMT method the paper
                             cites); 0: the min-volume test alone, as Algorithm 1 prints it          */
+    int continuation;    /* 1: path following on the prescribed volumes for starts far from the
+                            solution (lagot_solve, one instance): with V0 the volumes at the start
+                            weights, the targets nu(s) = (1 - s) V0 + s nu are solved by Algorithm 1
+                            for s rising from 0 to 1, each stage from the previous one's weights:
+                            intermediate stages to stage_tol with at most stage_newton iterations
+                            and 4 step halvings per iteration (PCG tolerance max(cg_rtol, 1e-3)),
+                            the last (s = 1) to tol. The step in s starts at 1/4, doubles after a
+                            stage of at most 3 iterations without halving, and halves after a stage
+                            that fails to converge (or whose step search ends on a cell the kernels
+                            cannot finish), whose weights are discarded; below 2^-12 the call fails
+                            with that stage's error and the last accepted stage's weights.
+                            0 (default): Algorithm 1 from the start weights                       */
+    int stage_newton;    /* Newton iteration limit of an intermediate stage        (default 8)    */
+    double stage_tol;    /* tolerance of the intermediate stages                   (default 1e-2) */
 } lagot_opts;
 
 typedef struct {
@@ -103,7 +117,7 @@ typedef struct {
     int default_start;   /* 1 if an empty start cell forced the default start weights     */
     int repaired_start;  /* 1 if empty start cells were given the default weight (the other
                             weights kept)                                                   */
-    int reserved_i;
+    int stages;          /* continuation stages accepted (opts.continuation), else 0      */
     double max_rel_err;  /* max_i |V_i - nu_i| / nu_i at the returned weights              */
     double grad_norm;    /* || nu - V ||_2 at the returned weights                         */
     double ms_total;     /* wall time of the call (host clock, stream synchronised)       */
@@ -388,6 +402,15 @@ int lagot_last_fallback_cells(const lagot_ctx *ctx);
  *   out: counts [16] HOST array. Synchronises the stream.
  * Errors: EINVAL (null pointer or nothing evaluated yet), EHIP. */
 int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts);
+
+/* Cells of the last evaluation on this context that took the later passes (section 4,
+ * "Finding Contributing Neighbors"): counts[0] the crowded cells the float32 pass
+ * deferred (search block of more than 256 sites, or more than 48 candidate bisectors),
+ * whose candidates came from the overlap of cell boxes; counts[1] the cells redone on the
+ * float64 large-capacity path. Diagnostic.
+ *   out: counts [2] HOST array. Synchronises the stream.
+ * Errors: EINVAL (null pointer or nothing evaluated yet), EHIP. */
+int lagot_last_pass_counts(lagot_ctx *ctx, int64_t *counts);
 
 /* Duration in ms of the float32 cell-kernel launch of the last lagot_cells call
  * (HIP events on the context stream; diagnostic; -1 if ctx is NULL). */

@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
            "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward", "lagot_mlp_forward_noalloc",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
@@ -56,14 +56,15 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_newton", ctypes.c_int), ("max_halvings", ctypes.c_int),
                 ("cg_rtol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("threads_per_cell", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("use_learned", ctypes.c_int), ("empty_start_fallback", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("residual_test", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("residual_test", ctypes.c_int),
+                ("continuation", ctypes.c_int), ("stage_newton", ctypes.c_int), ("stage_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int), ("evals", ctypes.c_int),
                 ("halvings", ctypes.c_int), ("cg_iters", ctypes.c_int), ("fallback_cells", ctypes.c_int),
                 ("failed_cells", ctypes.c_int), ("cell_launches", ctypes.c_int), ("learned_accepted", ctypes.c_int),
-                ("default_start", ctypes.c_int), ("repaired_start", ctypes.c_int), ("reserved_i", ctypes.c_int),
+                ("default_start", ctypes.c_int), ("repaired_start", ctypes.c_int), ("stages", ctypes.c_int),
                 ("max_rel_err", ctypes.c_double), ("grad_norm", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_eval", ctypes.c_double), ("ms_linear", ctypes.c_double),
                 ("ms_cell_kernel", ctypes.c_double), ("ms_learned", ctypes.c_double),
@@ -133,6 +134,8 @@ def load():
         lib.lagot_fluid_step.restype = I
         lib.lagot_last_flag_counts.argtypes = [P, P]
         lib.lagot_last_flag_counts.restype = I
+        lib.lagot_last_pass_counts.argtypes = [P, P]
+        lib.lagot_last_pass_counts.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
         lib.lagot_last_fallback_cells.restype = I
         lib.lagot_last_cell_kernel_ms.argtypes = [P]
@@ -431,6 +434,15 @@ class Context:
             raise LagotError(rc, "lagot_last_flag_counts")
         return {"final": {k: int(buf[i]) for i, k in enumerate(self.FLAG_NAMES)},
                 "float64_reasons": {k: int(buf[8 + i]) for i, k in enumerate(self.FLAG_NAMES)}}
+
+    def last_pass_counts(self) -> dict:
+        """lagot_last_pass_counts: cells of the last evaluation that took the crowded pass
+        and the float64 pass."""
+        buf = (ctypes.c_int64 * 2)()
+        rc = load().lagot_last_pass_counts(self._h, ctypes.cast(buf, ctypes.c_void_p))
+        if rc != OK:
+            raise LagotError(rc, "lagot_last_pass_counts")
+        return {"crowded": int(buf[0]), "float64": int(buf[1])}
 
     def last_cell_kernel_ms(self) -> float:
         return float(load().lagot_last_cell_kernel_ms(self._h))

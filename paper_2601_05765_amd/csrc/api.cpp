@@ -82,12 +82,20 @@ struct lagot_ctx {
     double *ev = nullptr, *ev2 = nullptr, *ev_nu = nullptr, *part_ev = nullptr;
     int32_t *fb_inst = nullptr, *fail_inst = nullptr, *bad_inst = nullptr, *herr = nullptr, *counts = nullptr;
     int32_t *misc = nullptr;  // [0] float64 work-list length [1] feature errors [2] kbase [3] remaining
-                              // [4] overflow work-list length
+                              // [4] overflow work-list length [5] large cell boxes
+    // cell boxes and the box grid of the crowded-cell pass
+    float4 *qbox = nullptr;                 // [2n]
+    int32_t *qent = nullptr, *qlarge = nullptr;  // [QREG_MAX n], [n]
+    int32_t *qcount = nullptr, *qstart = nullptr, *qcursor = nullptr, *qtmp = nullptr;  // bucket arrays
+    GridDesc *qgrid = nullptr;              // [B]
+    int nq = 0, cap_nq = 0;
     // evaluation outputs (grid order)
     double *V = nullptr, *K = nullptr;
     float *wall = nullptr;
     int32_t *fcol = nullptr, *fcnt = nullptr, *fb_list = nullptr, *ovf_list = nullptr;
     double *cen_out = nullptr;  // caller's centroid array during a lagot_centroids call
+    double *cont_buf = nullptr; // continuation: start volumes, prescribed volumes, last accepted weights [3n]
+    int64_t cap_cont = 0;
     double *fl_buf = nullptr;   // fluid step: PCG records and vectors, right-hand sides, centroids
     int32_t *fl_int = nullptr;  // fluid step: PCG status per coordinate, chunk counters
     int2 *fl_ent = nullptr;     // fluid step: matrix rows packed back to back
@@ -110,6 +118,9 @@ struct lagot_ctx {
     int32_t *hcol = nullptr, *hcnt = nullptr, *xcnt = nullptr;
     float *hval = nullptr;
     double *diag = nullptr;
+    int2 *hrow = nullptr;       // packed Hessian rows: (start within the tile's region, length)
+    int2 *hent = nullptr;       // [cap_hent_T * TILE * FCAP] packed entries, one region per tile
+    int cap_hent_T = 0;
     double *cg_vec = nullptr;   // rws[2] (4 doubles per row each), p, x: 10 doubles per row
     double *cg_part = nullptr;  // 7 * 4 * cap_T
     double *cg_cgs = nullptr;   // 4 * cap_B
@@ -173,14 +184,14 @@ template <typename... P> void free_ptrs(P *&...ps) {
 void free_sites(lagot_ctx *c) {
     free_ptrs(c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->inst, c->V, c->K, c->wall,
               c->fcol, c->fcnt, c->fb_list, c->ovf_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
-              c->cg_vec, c->csr_cnt, c->csr_start, c->csr_tmp);
+              c->cg_vec, c->csr_cnt, c->csr_start, c->csr_tmp, c->hrow, c->qbox, c->qent, c->qlarge);
     c->cap_n = 0;
 }
 
 void free_inst(lagot_ctx *c) {
     free_ptrs(c->off, c->tile_inst, c->tile_row, c->first_tile, c->grid, c->box, c->rmax, c->phase, c->ctl, c->ev,
               c->ev2, c->ev_nu, c->part_ev, c->fb_inst, c->fail_inst, c->bad_inst, c->herr, c->cg_part, c->cg_cgs,
-              c->cg_cgst);
+              c->cg_cgst, c->qgrid);
 }
 
 void free_alt(lagot_ctx *c) {
@@ -219,8 +230,12 @@ void free_all(lagot_ctx *c) {
     free_alt(c);
     free_sites(c);
     free_inst(c);
-    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int, c->fl_ent);
+    free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int, c->fl_ent,
+              c->hent, c->qcount, c->qstart, c->qcursor, c->qtmp, c->cont_buf);
+    c->cap_cont = 0;
+    c->cap_nq = 0;
     c->cap_ent = 0;
+    c->cap_hent_T = 0;
     c->cap_fl = 0;
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_rd) (void)hipHostFree(c->h_rd);
@@ -272,6 +287,10 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->hcnt, N));
     HIP_TRY(dalloc(&c->xcnt, N));
     HIP_TRY(dalloc(&c->diag, N));
+    HIP_TRY(dalloc(&c->hrow, N));
+    HIP_TRY(dalloc(&c->qbox, 2 * N));
+    HIP_TRY(dalloc(&c->qent, (size_t)QREG_MAX * N));
+    HIP_TRY(dalloc(&c->qlarge, N));
     HIP_TRY(dalloc(&c->cg_vec, 10 * N));
     HIP_TRY(dalloc(&c->csr_cnt, N + 1));
     HIP_TRY(dalloc(&c->csr_start, N + 1));
@@ -307,6 +326,7 @@ int ensure_inst(lagot_ctx *c, int B, int T) {
     HIP_TRY(dalloc(&c->cg_part, 7 * 4 * t));  // per quarter tile
     HIP_TRY(dalloc(&c->cg_cgs, 4 * b));
     HIP_TRY(dalloc(&c->cg_cgst, 4 * b));
+    HIP_TRY(dalloc(&c->qgrid, (size_t)QLEV * b));
     c->cap_B = B;
     c->cap_T = T;
     return LAGOT_OK;
@@ -321,6 +341,18 @@ int ensure_cells(lagot_ctx *c, int ncell) {
     HIP_TRY(dalloc(&c->cursor, (size_t)ncell + 1));
     HIP_TRY(dalloc(&c->scan_tmp, (size_t)ncell / 1024 + 16));
     c->cap_cells = ncell;
+    return LAGOT_OK;
+}
+
+int ensure_buckets(lagot_ctx *c, int nq) {
+    if (nq <= c->cap_nq) return LAGOT_OK;
+    free_ptrs(c->qcount, c->qstart, c->qcursor, c->qtmp);
+    c->cap_nq = 0;
+    HIP_TRY(dalloc(&c->qcount, (size_t)nq + 1));
+    HIP_TRY(dalloc(&c->qstart, (size_t)nq + 1));
+    HIP_TRY(dalloc(&c->qcursor, (size_t)nq + 1));
+    HIP_TRY(dalloc(&c->qtmp, (size_t)nq / 1024 + 16));
+    c->cap_nq = nq;
     return LAGOT_OK;
 }
 
@@ -406,7 +438,7 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     c->n = n;
     // tile table, boxes and (below) grids, staged in pinned memory
     const size_t stage = sizeof(int32_t) * (2 * (size_t)(B + 1) + 2 * (size_t)T) + sizeof(BoxF) * B +
-                         sizeof(GridDesc) * B + 64;
+                         (1 + QLEV) * sizeof(GridDesc) * B + 64;
     rc = ensure_pinned(&c->h_stage, &c->cap_stage, stage);
     if (rc) return rc;
     int32_t *h_off = (int32_t *)c->h_stage;
@@ -464,47 +496,92 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
         any_bad = any_bad || !ok;
     }
     if (any_bad) return LAGOT_EINVAL;
-    // one grid per instance: cell size 2 r_max (the 3x3x3 neighbourhood then covers
-    // every bisector that can cut a ball), at most 512 cells per axis and 2^24 cells
+    // One grid of sites per instance: cell size 2 r_max (the 3x3x3 neighbourhood then
+    // covers every bisector that can cut a ball), but no coarser than 1.5 times the mean
+    // spacing of the instance's sites in its box: where a few balls are much larger than
+    // the rest (crowded scenes), a grid sized by them would put thousands of sites in
+    // every cell. At most 512 cells per axis and 2^24 cells. The typical site spacing h
+    // (cube root of the mean prescribed volume, else of the box volume per site) sets the
+    // seed radius of crowded cells and the box grids: QLEV levels of buckets 1.2 h 4^l,
+    // at most 1024 buckets per axis and 2^24 per level.
     c->h_grid.resize(B);
-    int64_t total = 0;
+    std::vector<GridDesc> qg((size_t)B * QLEV);
+    int64_t total = 0, qtotal = 0;
+    auto make_grid = [](const lagot_box &bx, double s, int maxdim, int64_t base, GridDesc *g) {
+        int dim[3];
+        for (;;) {
+            int64_t tot = 1;
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                dim[a] = std::max(1, (int)std::ceil((bx.hi[a] - bx.lo[a]) / s));
+                ok = ok && dim[a] <= maxdim;
+                tot *= dim[a];
+            }
+            if (ok && tot <= (1 << 24)) break;
+            s *= 1.25;
+        }
+        for (int a = 0; a < 3; ++a) {
+            g->lo[a] = (float)bx.lo[a];
+            g->dim[a] = dim[a];
+        }
+        g->s = (float)s;
+        g->inv_s = (float)(1.0 / s);
+        g->ncell = dim[0] * dim[1] * dim[2];
+        g->base = (int)base;
+        g->hsp = 0.f;
+        g->pad = 0;
+    };
     for (int b = 0; b < B; ++b) {
         const lagot_box &bx = boxes[b];
         double ext = 0.0;
         for (int a = 0; a < 3; ++a) ext = std::max(ext, bx.hi[a] - bx.lo[a]);
-        double s = std::max(2.0 * r_rmax[b], ext / 512.0);
-        int dim[3];
-        for (;;) {
-            int64_t tot = 1;
-            for (int a = 0; a < 3; ++a) {
-                dim[a] = std::max(1, (int)std::ceil((bx.hi[a] - bx.lo[a]) / s));
-                tot *= dim[a];
-            }
-            if (tot <= (1 << 24)) break;
-            s *= 1.25;
-        }
+        const double nb = (double)(offs[b + 1] - offs[b]);
+        const double hsp = std::cbrt((nu ? r_nu[4 * b] : box_volume(bx)) / nb);
+        double s = std::min(2.0 * r_rmax[b], 1.5 * std::cbrt(box_volume(bx) / nb));
+        s = std::max(s, ext / 512.0);
         GridDesc g;
-        for (int a = 0; a < 3; ++a) {
-            g.lo[a] = (float)bx.lo[a];
-            g.dim[a] = dim[a];
-        }
-        g.s = (float)s;
-        g.inv_s = (float)(1.0 / s);
-        g.ncell = dim[0] * dim[1] * dim[2];
-        g.base = (int)total;
+        make_grid(bx, s, 512, total, &g);
+        g.hsp = (float)hsp;
         total += g.ncell;
         if (total > ((int64_t)1 << 28)) return LAGOT_ECAPACITY;
         c->h_grid[b] = g;
+        double sq = std::max(1.2 * hsp, ext / 1024.0);
+        for (int l = 0; l < QLEV; ++l, sq *= 4.0) {
+            GridDesc &q = qg[(size_t)b * QLEV + l];
+            make_grid(bx, sq, 1024, qtotal, &q);
+            q.hsp = (float)hsp;
+            qtotal += q.ncell;
+        }
+        if (qtotal > ((int64_t)1 << 28)) return LAGOT_ECAPACITY;
     }
     c->ncell_total = (int)total;
+    c->nq = (int)qtotal;
     rc = ensure_cells(c, c->ncell_total);
+    if (!rc) rc = ensure_buckets(c, c->nq);
     if (rc) return rc;
     std::memcpy(h_g, c->h_grid.data(), sizeof(GridDesc) * B);
+    std::memcpy(h_g + B, qg.data(), sizeof(GridDesc) * B * QLEV);
     HIP_TRY(hipMemcpyAsync(c->grid, h_g, sizeof(GridDesc) * B, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->qgrid, h_g + B, sizeof(GridDesc) * B * QLEV, hipMemcpyHostToDevice, st));
     launch_grid_build(st, n, bt, c->ncell_total, c->pos_orig, c->keys, c->cell_count, c->cell_start, c->scan_tmp,
                       c->perm, c->cursor);
     launch_permute_in(st, n, c->perm, c->pos_orig, psi, nu, c->pos_s, c->psi_s, nu ? c->nu_s : nullptr);
     return LAGOT_OK;
+}
+
+QBoxes qboxes(lagot_ctx *c) {
+    QBoxes q;
+    q.box = c->qbox;
+    q.qgrid = c->qgrid;
+    q.count = c->qcount;
+    q.start = c->qstart;
+    q.cursor = c->qcursor;
+    q.ent = c->qent;
+    q.large = c->qlarge;
+    q.nlarge = c->misc + 5;
+    q.tmp = c->qtmp;
+    q.nq = c->nq;
+    return q;
 }
 
 EvalOut eval_out(lagot_ctx *c, bool walls) {
@@ -525,11 +602,25 @@ void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double
         (void)hipMemsetAsync(c->wall, 0, (size_t)(c->ndom > 0 ? c->ndom : 6) * sizeof(float) * (size_t)c->n,
                              c->stream);
     if (timed) (void)hipEventRecord(c->ev0, c->stream);
-    launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, c->tpc);
+    const QBoxes qb = qboxes(c);
+    launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->tpc);
     if (timed) (void)hipEventRecord(c->ev1, c->stream);
     if (!c->capturing) c->ev_pending = true;
-    launch_cells_fallback(c->stream, bt, c->pos_s, psi_eval, c->perm, c->cell_start, o);
+    launch_cells_fallback(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb);
     if (ev_out) launch_eval_reduce(c->stream, bt, want, c->V, c->nu_s, c->part_ev, ev_out);
+}
+
+// Per-bit counts of the cell flags of the last evaluation (bits 0..7: final, 8..15: the
+// reasons that sent cells to the float64 pass).
+int flag_hist(lagot_ctx *c, int64_t *counts) {
+    std::vector<uint32_t> f((size_t)c->n);
+    HIP_TRY(hipMemcpyAsync(f.data(), c->flags, sizeof(uint32_t) * (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
+    const int rc = sync(c);
+    if (rc) return rc;
+    for (int k = 0; k < 16; ++k) counts[k] = 0;
+    for (uint32_t v : f)
+        for (int k = 0; k < 16; ++k) counts[k] += (v >> k) & 1u;
+    return LAGOT_OK;
 }
 
 // Phase histogram written by the last control kernel -> h_cnt[0..7].
@@ -624,6 +715,9 @@ void fill_defaults(lagot_opts *o) {
     o->empty_start_fallback = 1;
     o->autotune = 0;
     o->residual_test = 1;
+    o->continuation = 0;
+    o->stage_newton = 8;
+    o->stage_tol = 1e-2;
 }
 
 bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
@@ -632,6 +726,8 @@ int check_opts(const lagot_opts &o) {
     if (!(o.tol > 0) || o.max_newton < 0 || o.max_halvings < 0 || !(o.cg_rtol > 0) || o.cg_max_iter < 1)
         return LAGOT_EINVAL;
     if (!valid_tpc(o.threads_per_cell) && o.threads_per_cell != 0) return LAGOT_EINVAL;
+    if (o.continuation != 0 && o.continuation != 1) return LAGOT_EINVAL;
+    if (o.continuation && (o.stage_newton < 1 || !(o.stage_tol > 0))) return LAGOT_EINVAL;
     return LAGOT_OK;
 }
 
@@ -725,7 +821,7 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
     const CgBufs cg = cg_bufs(c);
     hipStream_t st = c->stream;
     if (with_init)
-        launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt, cg);
+        launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hrow, c->hent, cg);
     const double rtol2 = o.cg_rtol * o.cg_rtol;
     const int cap = o.cg_max_iter;
     int k = 0;
@@ -733,8 +829,7 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
         const int m = std::min(c->cg_chunk, cap - k);
         auto chunk = [&]() {
             for (int q = 0; q < m; ++q)
-                launch_cg_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hcol, c->hval, c->hcnt,
-                               c->diag, cg);
+                launch_cg_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hrow, c->hent, cg);
             launch_cg_advance(c->stream, bt, m, cap, cg);
         };
         if (graph) {
@@ -763,13 +858,20 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
 int newton_direction(lagot_ctx *c, const lagot_opts &o, bool graph) {
     const Batch bt = batch(c);
     hipStream_t st = c->stream;
+    if (c->cap_hent_T < c->T) {  // one TILE * FCAP region of packed Hessian entries per tile
+        if (graph) drop_graphs(c);   // captured launches hold the old buffer
+        free_ptrs(c->hent);
+        c->cap_hent_T = 0;
+        HIP_TRY(dalloc(&c->hent, (size_t)c->T * TILE * FCAP));
+        c->cap_hent_T = c->T;
+    }
     auto assemble = [&](bool with_init) {
         launch_hess_assemble(c->stream, c->n, bt, PH_ACTIVE, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval,
                              c->xcnt, c->herr);
-        launch_hess_finish(c->stream, c->n, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hcol,
-                           c->hval, c->diag);
+        launch_hess_finish(c->stream, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hcol, c->hval,
+                           c->diag, c->hrow, c->hent);
         if (with_init)
-            launch_cg_init(c->stream, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hcol, c->hval, c->hcnt,
+            launch_cg_init(c->stream, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hrow, c->hent,
                            cg_bufs(c));
     };
     int k = 0, rc;
@@ -876,6 +978,110 @@ int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
     return LAGOT_OK;
 }
 
+// Path following on the prescribed volumes (one instance; opts.continuation). From a
+// start far from the solution, Algorithm 1's global step length can collapse: some cell
+// empties under every long step, and KMT halves the step for all cells. With V0 the
+// volumes at the start iterate, the start solves the problem with targets V0 exactly;
+// the targets nu(s) = (1 - s) V0 + s nu (sum below the box volume for every s, positive)
+// are then solved for s rising to 1, each stage by Algorithm 1 from the weights of the
+// last accepted stage. Stage results are accepted only through Newton's own test, so the
+// final stage is a plain solve of the problem to the caller's tolerance.
+template <typename Loop>
+int continuation(lagot_ctx *c, const lagot_opts &o, const CtlOpts &co, CallTimes &tm, Loop &&newton_loop,
+                 int *stages_out) {
+    const Batch bt = batch(c);
+    hipStream_t st = c->stream;
+    const int64_t n = c->n;
+    if (n > c->cap_cont) {
+        free_ptrs(c->cont_buf);
+        c->cap_cont = 0;
+        HIP_TRY(dalloc(&c->cont_buf, 3 * (size_t)n));
+        c->cap_cont = n;
+    }
+    double *v0 = c->cont_buf, *nu_t = v0 + n, *psi_ok = nu_t + n;
+    HIP_TRY(hipMemcpyAsync(v0, c->V, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(nu_t, c->nu_s, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(psi_ok, c->psi_s, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    lagot_opts os = o;
+    os.cg_rtol = std::max(o.cg_rtol, 1e-3);  // inexact directions suffice for a loose stage
+    os.max_newton = o.stage_newton;
+    CtlOpts cs = co;
+    cs.tol = o.stage_tol;
+    cs.max_newton = o.stage_newton;
+    cs.max_halvings = std::min(o.max_halvings, 4);  // a stage that needs short steps is retried closer
+    double s = 0.0, ds = 0.25;
+    int stages = 0, rc = LAGOT_OK;
+    for (;;) {
+        const double s1 = std::min(1.0, s + ds);
+        const bool last = s1 >= 1.0;
+        const CtlOpts &cc = last ? co : cs;
+        if (o.use_graph) drop_graphs(c);  // captured launches hold the stage's options
+        launch_nu_stage(st, n, s1, v0, nu_t, c->nu_s);
+        launch_eval_reduce(st, bt, -1, c->nu_s, c->nu_s, c->part_ev, c->ev_nu);
+        launch_eval_reduce(st, bt, -1, c->V, c->nu_s, c->part_ev, c->ev);
+        launch_ctl_stage(st, bt, cc, c->ev, c->ev_nu, c->fail_inst, c->ctl, c->phase, c->counts);
+        InstCtl q0, q1;
+        HIP_TRY(hipMemcpyAsync(&q0, c->ctl, sizeof(q0), hipMemcpyDeviceToHost, st));
+        rc = read_counts(c);
+        if (rc) return rc;
+        rc = newton_loop(last ? o : os, cc);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(&q1, c->ctl, sizeof(q1), hipMemcpyDeviceToHost, st));
+        rc = sync(c);
+        if (rc) return rc;
+        const int its = q1.iters - q0.iters, halv = q1.halvings - q0.halvings;
+        if (o.verbose)
+            fprintf(stderr, "lagot continuation s %.5f (step %.5f): status %d, %d Newton iterations, %d halvings\n", s1,
+                    ds, q1.status, its, halv);
+        if (q1.status == LAGOT_OK) {
+            ++stages;
+            s = s1;
+            if (last) break;
+            HIP_TRY(hipMemcpyAsync(psi_ok, c->psi_s, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            if (its <= 3 && halv == 0) ds *= 2.0;
+        } else if (q1.status == LAGOT_ENOCONV || q1.status == LAGOT_ELINESEARCH || q1.status == LAGOT_ECAPACITY) {
+            // back to the last accepted stage, with a shorter step in s
+            ds *= 0.5;
+            if (ds < 1.0 / 4096.0) break;
+            HIP_TRY(hipMemcpyAsync(c->psi_s, psi_ok, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            launch_psi_shadow(st, n, c->psi_s, c->pos_s);
+            launch_rmax(st, bt, -1, c->psi_s, c->rmax);
+            evaluate(c, -1, c->psi_s, false, nullptr);
+            tm.extra_evals++;
+        } else {
+            break;  // empty start cell, capacity, PCG breakdown: the stage's error is the call's
+        }
+    }
+    *stages_out = stages;
+    if (s < 1.0) {
+        // failed: the call returns the last accepted stage's weights with the failing
+        // stage's status and the residuals against the caller's volumes
+        InstCtl q;
+        HIP_TRY(hipMemcpyAsync(&q, c->ctl, sizeof(q), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(c->psi_s, psi_ok, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(c->nu_s, nu_t, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        launch_psi_shadow(st, n, c->psi_s, c->pos_s);
+        launch_rmax(st, bt, -1, c->psi_s, c->rmax);
+        evaluate(c, -1, c->psi_s, false, c->ev);
+        tm.extra_evals++;
+        double e[4];
+        HIP_TRY(hipMemcpyAsync(e, c->ev, sizeof(e), hipMemcpyDeviceToHost, st));
+        rc = sync(c);
+        if (rc) return rc;
+        q.sumV = e[0];
+        q.maxrel = e[1];
+        q.gnorm = e[2];
+        q.minV = e[3];
+        if (q.status == LAGOT_OK) q.status = LAGOT_ENOCONV;
+        const int32_t failed = PH_FAILED;
+        HIP_TRY(hipMemcpyAsync(c->ctl, &q, sizeof(q), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(c->phase, &failed, sizeof(failed), hipMemcpyHostToDevice, st));
+        rc = sync(c);
+        if (rc) return rc;
+    }
+    return LAGOT_OK;
+}
+
 // Damped Newton (Algorithm 1, KMT step control) for every instance of the call;
 // single = true takes at most one Newton iteration per instance.
 int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, const float *y, const float *z,
@@ -895,6 +1101,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     int rc = check_opts(o);
     if (!rc && (!nu || !psi)) rc = LAGOT_EINVAL;
     if (!rc && o.use_learned && B != 1) rc = LAGOT_EINVAL;
+    if (!rc && o.continuation && B != 1) rc = LAGOT_EINVAL;
     if (rc) return fail_all(rc);
     c->tpc = o.threads_per_cell ? o.threads_per_cell : c->tpc_default;
     c->ms_cell = 0.0;
@@ -955,10 +1162,13 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     }
     tm.eval += now_ms() - te - tm.learned;
     int round = 0;
+    // Newton iterations of every ACTIVE instance until none is left (Algorithm 1 with the
+    // step control on the device), with options o and control options co
+    auto newton_loop = [&](const lagot_opts &o, const CtlOpts &co) -> int {
     while (c->h_cnt[PH_ACTIVE] > 0) {
         const double tl = now_ms();
         rc = newton_direction(c, o, graph);
-        if (rc) return fail_all(rc);
+        if (rc) return rc;
         tm.lin += now_ms() - tl;
         te = now_ms();
         // one step-size trial of every instance in the search (Alg. 1, KMT test on the device)
@@ -978,20 +1188,30 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
                         c->graph_events = false;
                         rc = capture(c, trial, &c->g_trial);
                     }
-                    if (rc) return fail_all(rc);
+                    if (rc) return rc;
                 }
-                if (hipGraphLaunch(c->g_trial, st) != hipSuccess) return fail_all(LAGOT_EHIP);
+                if (hipGraphLaunch(c->g_trial, st) != hipSuccess) return LAGOT_EHIP;
                 c->ev_pending = c->graph_events;
             } else {
                 trial();
             }
             rc = read_counts(c);
-            if (rc) return fail_all(rc);
+            if (rc) return rc;
             if (o.verbose > 2) {  // every step-size trial of the first instance
                 InstCtl q;
                 HIP_TRY(hipMemcpy(&q, c->ctl, sizeof(q), hipMemcpyDeviceToHost));
                 fprintf(stderr, "    trial %d: minV %.4e (eps0 %.4e) |g| %.6e (accepted |g| %.6e) -> %s\n", h, q.tminV,
                         q.eps0, q.tgnorm, q.gnorm, c->h_cnt[PH_TRIAL] == 0 ? "kept" : "halved");
+                int32_t fl = 0;
+                HIP_TRY(hipMemcpy(&fl, c->fail_inst, sizeof(fl), hipMemcpyDeviceToHost));
+                if (fl) {  // cells that failed every pass: their flags (final, and first-pass reasons)
+                    int64_t h16[16];
+                    rc = flag_hist(c, h16);
+                    if (rc) return rc;
+                    fprintf(stderr, "      %d failed cells; flag bits:", fl);
+                    for (int k = 0; k < 16; ++k) fprintf(stderr, " %lld", (long long)h16[k]);
+                    fprintf(stderr, "\n");
+                }
             }
             if (c->h_cnt[PH_TRIAL] == 0) break;
         }
@@ -1009,7 +1229,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
                 HIP_TRY(hipMemcpyAsync(&fl, c->fail_inst, sizeof(fl), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&rm, c->rmax, sizeof(rm), hipMemcpyDeviceToHost, st));
                 rc = sync(c);
-                if (rc) return fail_all(rc);
+                if (rc) return rc;
                 fprintf(stderr,
                         "  inst 0: alpha %.3g |g| %.3e maxrel %.3e minV %.3e eps0 %.3e evals %d halvings %d cg %d "
                         "fallback %d failed (last evaluation) %d r_max %.4g cell kernel %.1f ms; last trial: "
@@ -1019,6 +1239,16 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
             }
         }
     }
+    return LAGOT_OK;
+    };
+    int stages = 0;
+    if (o.continuation && !single && c->h_cnt[PH_ACTIVE] > 0) {
+        rc = continuation(c, o, co, tm, newton_loop, &stages);
+    } else {
+        rc = newton_loop(o, co);
+    }
+    if (rc) return fail_all(rc);
+
     // weights back to caller order (every instance holds its last accepted iterate)
     launch_scatter_out_f64(st, c->n, c->perm, c->psi_s, psi);
     std::vector<InstCtl> hc(B);
@@ -1047,6 +1277,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
         S.learned_accepted = learned;
         S.default_start = q.default_start;
         S.repaired_start = q.repaired;
+        S.stages = stages;
         S.max_rel_err = q.maxrel;
         S.grad_norm = q.gnorm;
         S.ms_total = ms_total;
@@ -1139,7 +1370,8 @@ int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     c->cen_out = nullptr;
     const Batch bt = batch(c);
     launch_hess_assemble(st, n, bt, -1, c->pos_s, c->fcol, c->farea, c->fcnt, c->hcol, c->hval, c->xcnt, c->herr);
-    launch_hess_finish(st, n, bt, -1, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hcol, c->hval, c->diag);
+    launch_hess_finish(st, bt, -1, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hcol, c->hval, c->diag, nullptr,
+                       nullptr);
     HIP_TRY(hipMemcpyAsync(c->h_cnt, c->misc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(c->h_cnt + 2, c->herr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1432,6 +1664,17 @@ int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block) {
 
 int lagot_last_fallback_cells(const lagot_ctx *ctx) { return ctx ? ctx->last_fb : -1; }
 
+int lagot_last_pass_counts(lagot_ctx *ctx, int64_t *counts) {
+    if (!ctx || !counts || ctx->n <= 0 || !ctx->misc) return LAGOT_EINVAL;
+    int32_t m[5];
+    HIP_TRY(hipMemcpyAsync(m, ctx->misc, sizeof(m), hipMemcpyDeviceToHost, ctx->stream));
+    const int rc = sync(ctx);
+    if (rc) return rc;
+    counts[0] = m[4];
+    counts[1] = m[0];
+    return LAGOT_OK;
+}
+
 int lagot_set_domain(lagot_ctx *c, int nplanes, const double *planes) {
     if (!c || nplanes < 0 || nplanes > DOM_MAX || (nplanes > 0 && !planes)) return LAGOT_EINVAL;
     float4 h[DOM_MAX];
@@ -1461,15 +1704,7 @@ int lagot_set_domain(lagot_ctx *c, int nplanes, const double *planes) {
 
 int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts) {
     if (!ctx || !counts || ctx->n <= 0 || !ctx->flags) return LAGOT_EINVAL;
-    std::vector<uint32_t> f((size_t)ctx->n);
-    HIP_TRY(hipMemcpyAsync(f.data(), ctx->flags, sizeof(uint32_t) * (size_t)ctx->n, hipMemcpyDeviceToHost,
-                           ctx->stream));
-    const int rc = sync(ctx);
-    if (rc) return rc;
-    for (int k = 0; k < 16; ++k) counts[k] = 0;
-    for (uint32_t v : f)
-        for (int k = 0; k < 16; ++k) counts[k] += (v >> k) & 1u;
-    return LAGOT_OK;
+    return flag_hist(ctx, counts);
 }
 
 double lagot_last_cell_kernel_ms(const lagot_ctx *ctx) { return ctx ? ctx->ms_cell : -1.0; }

@@ -21,6 +21,16 @@
 // T = 2F - 4 checks the combinatorics after every cut; a violation, or any
 // capacity overflow, flags the cell for the float64 large-capacity path.
 //
+// Crowded cells (section 4, "Finding Contributing Neighbors"): where a few balls are
+// much larger than the rest, a cell's search block holds thousands of sites, most of
+// whose bisectors never touch the cell. The fast pass defers such a cell; a seed pass
+// clips it by its nearest sites only (a superset of the cell) and writes its box, every
+// other cell writes the box of its exact cell, the boxes are registered in bucket grids,
+// and the crowded pass (float64) clips each deferred cell by the sites whose boxes
+// overlap its own, starting from its box. This candidate set is exact: a point of the
+// result outside the true cell has a site of lower power whose own cell holds the point,
+// so the two boxes overlap and that site was a candidate.
+//
 // Restriction (section 3.2 "triangles and circular sectors", section 3.3 occlusion
 // identity with the projection centre at p_i, section 3.2 pyramids): each face
 // polygon is walked counter-clockwise; every edge (P,Q) contributes the signed
@@ -246,16 +256,21 @@ struct CellArgs {
     Batch bt;                 // instance of each row, its grid, box and r_max
     int want;                 // evaluate the instances in this phase (< 0: all)
     EvalOut out;
+    QBoxes qb;                // cell boxes and their bucket grid (crowded cells)
 };
 
 template <typename R, int G, int CMAX, int PMAX, int VMAX, int MODE, bool MOM>
 __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMAX, VMAX> &S) {
-    // MODE 0: the fast pass (a cell with more than CMAX candidates is deferred to the
-    // overflow list); 1: the overflow pass (threshold ladder and clip rounds); 2: the
-    // large-capacity pass for the cells that passes 0 and 1 cannot finish (capacity, or
-    // float32 accuracy).
-    constexpr bool fast = MODE < 2;
-    constexpr bool rounds = MODE >= 1;
+    // MODE 0: the fast pass (a crowded cell -- more than CMAX candidates, or a search
+    // block of more than FAST_SCAN_MAX sites -- is deferred to the overflow list; every
+    // other cell writes its box); 3: the seed pass of a deferred cell (clipped by its
+    // nearest sites only: a superset of the cell, whose box it writes); 1: the crowded
+    // pass (candidates are the sites whose boxes overlap the cell's, threshold ladder and
+    // clip rounds when they exceed CMAX); 2: the large-capacity pass for the cells that
+    // passes 0 and 1 cannot finish (capacity, or float32 accuracy).
+    constexpr bool fast = MODE != 2;
+    constexpr bool rounds = MODE == 1 || MODE == 2;
+    constexpr bool seed = MODE == 3;
     bool deferred = false;
     using M = typename MaskType<PMAX>::T;
     constexpr int NS = VMAX / G;  // vertex slots per lane (registers); slot id = k * G + lane
@@ -299,30 +314,134 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     int lo3[3] = {0, 0, 0}, hi3[3] = {-1, -1, -1};
     int nyc = 1, ncol = 0;
     const int gbase = (int)(threadIdx.x & (64 - G));
-    if (live) {
-        gd = A.bt.grid[inst];
-        const float reach = ((float)r + (float)A.bt.rmax[inst]) * 1.0001f;
+    // the crowded pass starts from the cell's box (a superset of the cell written by the
+    // seed pass; an empty box is an empty cell)
+    float qlo[3] = {0.f, 0.f, 0.f}, qhi[3] = {0.f, 0.f, 0.f};
+    if constexpr (MODE == 1) {
+        if (live) {
+            const float4 a = A.qb.box[2 * cell], b = A.qb.box[2 * cell + 1];
+            qlo[0] = a.x;
+            qlo[1] = a.y;
+            qlo[2] = a.z;
+            qhi[0] = b.x;
+            qhi[1] = b.y;
+            qhi[2] = b.z;
+            if (!(a.x <= b.x && a.y <= b.y && a.z <= b.z)) empty = true;
+        }
+    }
+    if (live && !empty) {
         const float pp[3] = {(float)px, (float)py, (float)pz};
+        if constexpr (MODE == 1) {
+            // the buckets are visited level by level (scan sets the block of each level)
+            gd = A.qb.qgrid[inst * QLEV];
+        } else if constexpr (seed) {
+            // the sites within 2.5 spacings
+            gd = A.bt.grid[inst];
+            const float reach = 2.5f * gd.hsp;
+            for (int a = 0; a < 3; ++a) {
+                lo3[a] = max((int)floorf((pp[a] - reach - gd.lo[a]) * gd.inv_s), 0);
+                hi3[a] = min((int)floorf((pp[a] + reach - gd.lo[a]) * gd.inv_s), gd.dim[a] - 1);
+            }
+        } else {
+            // every site whose ball can meet this one: within r + r_max
+            gd = A.bt.grid[inst];
+            const float reach = ((float)r + (float)A.bt.rmax[inst]) * 1.0001f;
+            for (int a = 0; a < 3; ++a) {
+                lo3[a] = max((int)floorf((pp[a] - reach - gd.lo[a]) * gd.inv_s), 0);
+                hi3[a] = min((int)floorf((pp[a] + reach - gd.lo[a]) * gd.inv_s), gd.dim[a] - 1);
+            }
+        }
+        if constexpr (MODE != 1) {
+            nyc = hi3[1] - lo3[1] + 1;
+            ncol = (hi3[0] - lo3[0] + 1) * nyc;
+        }
+    }
+    // bucket block of the cell's box at box-grid level lev (crowded pass)
+    auto bucket_block = [&](int lev) {
+        gd = A.qb.qgrid[inst * QLEV + lev];
         for (int a = 0; a < 3; ++a) {
-            lo3[a] = max((int)floorf((pp[a] - reach - gd.lo[a]) * gd.inv_s), 0);
-            hi3[a] = min((int)floorf((pp[a] + reach - gd.lo[a]) * gd.inv_s), gd.dim[a] - 1);
+            lo3[a] = min(max((int)floorf((qlo[a] - gd.lo[a]) * gd.inv_s), 0), gd.dim[a] - 1);
+            hi3[a] = min(max((int)floorf((qhi[a] - gd.lo[a]) * gd.inv_s), 0), gd.dim[a] - 1);
         }
         nyc = hi3[1] - lo3[1] + 1;
         ncol = (hi3[0] - lo3[0] + 1) * nyc;
-    }
-    // Visit every site of the block, G at a time, then the six box walls. f sees per
-    // lane: keep (a candidate: |t| < r), kill (the site empties the cell), neg (p_i is
-    // behind the bisector), the plane (n, t) and its id (site, or -1-w for wall w).
-    // The sites of up to G grid columns are numbered consecutively (prefix sum over
-    // the lanes); each lane finds its column by a binary search over shuffled sums.
+    };
+    // The bisector of (i, j) as a candidate plane: keep (|t| < r), kill (the site empties
+    // the cell), neg (p_i is behind the bisector), the unit normal and t, and d^2.
+    auto site = [&](bool valid, int j, auto &&f) {
+        bool keep = false, kill = false, neg = false;
+        R nx = 0, ny = 0, nz = 0, t = 0, d2o = 0;
+        if (valid) {
+            const float4 q4 = A.pos_s[j];
+            // the weight difference is formed from the float64 weights: for close
+            // sites t ~ (psi_i - psi_j) / 2d amplifies any rounding of the weights
+            const double psi_j64 = A.psi_s[j];
+            const R dpsi = (R)(psi_i64 - psi_j64);
+            const R dx = (R)q4.x - px, dy = (R)q4.y - py, dz = (R)q4.z - pz;
+            const R d2 = dot3(dx, dy, dz, dx, dy, dz);
+            d2o = d2;
+            if (d2 > R(0)) {
+                const R id = rsqrt_<R>(d2);
+                t = (d2 + dpsi) * (R(0.5) * id);
+                if constexpr (sizeof(R) == 4) {
+                    // d^2 and the weight difference nearly cancel (large weights):
+                    // the float32 offset would carry their rounding, so it is
+                    // formed in float64 (the float32 differences are exact there)
+                    if (fabs(dpsi) > d2 && t > -r && t < r) {
+                        const double ex = (double)q4.x - (double)px, ey = (double)q4.y - (double)py,
+                                     ez = (double)q4.z - (double)pz;
+                        const double e2 = ex * ex + ey * ey + ez * ez;
+                        t = (R)((e2 + (psi_i64 - psi_j64)) / (2.0 * sqrt(e2)));
+                    }
+                }
+                if (t <= -r) {
+                    kill = true;
+                } else if (t < r) {
+                    keep = true;
+                    neg = t < R(0);
+                    nx = dx * id;
+                    ny = dy * id;
+                    nz = dz * id;
+                }
+            } else {
+                // coincident sites: the larger weight, then the lower caller index, owns the point
+                kill = psi_j64 > psi_i64 || (psi_j64 == psi_i64 && A.perm[j] < A.perm[cell]);
+            }
+        }
+        f(keep, kill, neg, nx, ny, nz, t, j, d2o);
+    };
+    // Does the box of cell j overlap this cell's box? With `dedup`, a pair is reported
+    // only in the bucket that holds the low corner of the two boxes' intersection (the
+    // entry e of column (ix, iy), start index col), so a site registered in several
+    // of the buckets visited is a candidate once.
+    auto box_hit = [&](int j, bool dedup, int ix, int iy, int col, int e) -> bool {
+        const float4 a = A.qb.box[2 * (int64_t)j], b = A.qb.box[2 * (int64_t)j + 1];
+        if (!(a.x <= qhi[0] && qlo[0] <= b.x && a.y <= qhi[1] && qlo[1] <= b.y && a.z <= qhi[2] && qlo[2] <= b.z))
+            return false;
+        if (!dedup) return true;
+        const float m[3] = {fmaxf(a.x, qlo[0]), fmaxf(a.y, qlo[1]), fmaxf(a.z, qlo[2])};
+        int mb[3];
+        for (int q = 0; q < 3; ++q)
+            mb[q] = min(max((int)floorf((m[q] - gd.lo[q]) * gd.inv_s), 0), gd.dim[q] - 1);
+        if (mb[0] != ix || mb[1] != iy) return false;
+        return A.qb.start[col + mb[2]] <= e && e < A.qb.start[col + mb[2] + 1];
+    };
+    // Visit every candidate site, G at a time, then the walls. The sites (the entries of
+    // the buckets, in the crowded pass) of up to G grid columns are numbered
+    // consecutively (prefix sum over the lanes); each lane finds its column by a binary
+    // search over shuffled sums.
+    const int32_t *colstart = (MODE == 1) ? A.qb.start : A.cell_start;
     auto scan = [&](auto &&f) {
+      const bool any = ncol > 0 || (MODE == 1 && live && !empty);
+      for (int lev = 0; lev < (MODE == 1 ? QLEV : 1) && any; ++lev) {
+        if constexpr (MODE == 1) bucket_block(lev);
         for (int c0 = 0; c0 < ncol; c0 += G) {
             int cbeg = 0, cnt = 0;
             if (c0 + gl < ncol) {
                 const int ix = lo3[0] + (c0 + gl) / nyc, iy = lo3[1] + (c0 + gl) % nyc;
                 const int col = gd.base + (ix * gd.dim[1] + iy) * gd.dim[2];
-                cbeg = A.cell_start[col + lo3[2]];
-                cnt = A.cell_start[col + hi3[2] + 1] - cbeg;
+                cbeg = colstart[col + lo3[2]];
+                cnt = colstart[col + hi3[2] + 1] - cbeg;
             }
             int incl = cnt;
 #pragma unroll
@@ -340,46 +459,31 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                     const int v = __shfl(incl, gbase + cidx + step - 1, 64);
                     if (v <= idx) cidx += step;
                 }
-                const int j = __shfl(cbeg, gbase + cidx, 64) + (idx - __shfl(excl, gbase + cidx, 64));
-                bool keep = false, kill = false, neg = false;
-                R nx = 0, ny = 0, nz = 0, t = 0;
-                if (idx < total && j != cell) {
-                    const float4 q4 = A.pos_s[j];
-                    // the weight difference is formed from the float64 weights: for close
-                    // sites t ~ (psi_i - psi_j) / 2d amplifies any rounding of the weights
-                    const double psi_j64 = A.psi_s[j];
-                    const R dpsi = (R)(psi_i64 - psi_j64);
-                    const R dx = (R)q4.x - px, dy = (R)q4.y - py, dz = (R)q4.z - pz;
-                    const R d2 = dot3(dx, dy, dz, dx, dy, dz);
-                    if (d2 > R(0)) {
-                        const R id = rsqrt_<R>(d2);
-                        t = (d2 + dpsi) * (R(0.5) * id);
-                        if constexpr (sizeof(R) == 4) {
-                            // d^2 and the weight difference nearly cancel (large weights):
-                            // the float32 offset would carry their rounding, so it is
-                            // formed in float64 (the float32 differences are exact there)
-                            if (fabs(dpsi) > d2 && t > -r && t < r) {
-                                const double ex = (double)q4.x - (double)px, ey = (double)q4.y - (double)py,
-                                             ez = (double)q4.z - (double)pz;
-                                const double e2 = ex * ex + ey * ey + ez * ez;
-                                t = (R)((e2 + (psi_i64 - psi_j64)) / (2.0 * sqrt(e2)));
-                            }
-                        }
-                        if (t <= -r) {
-                            kill = true;
-                        } else if (t < r) {
-                            keep = true;
-                            neg = t < R(0);
-                            nx = dx * id;
-                            ny = dy * id;
-                            nz = dz * id;
-                        }
-                    } else {
-                        // coincident sites: the larger weight, then the lower caller index, owns the point
-                        kill = psi_j64 > psi_i64 || (psi_j64 == psi_i64 && A.perm[j] < A.perm[cell]);
-                    }
+                const int e = __shfl(cbeg, gbase + cidx, 64) + (idx - __shfl(excl, gbase + cidx, 64));
+                bool valid = idx < total;
+                int j = e;
+                if constexpr (MODE == 1) {
+                    j = valid ? A.qb.ent[e] : -1;
+                    const int ix = lo3[0] + (c0 + cidx) / nyc, iy = lo3[1] + (c0 + cidx) % nyc;
+                    valid = valid && j != cell &&
+                            box_hit(j, true, ix, iy, gd.base + (ix * gd.dim[1] + iy) * gd.dim[2], e);
                 }
-                f(keep, kill, neg, nx, ny, nz, t, j);
+                site(valid && j != cell, j, f);
+            }
+        }
+      }
+        if constexpr (MODE == 1) {
+            // cells whose boxes are too large for the buckets: tested one by one
+            const int nl = *A.qb.nlarge;
+            for (int k0 = 0; k0 < nl; k0 += G) {
+                const int k = k0 + gl;
+                int j = -1;
+                bool valid = false;
+                if (k < nl) {
+                    j = A.qb.large[k];
+                    valid = j != cell && A.bt.inst[j] == inst && box_hit(j, false, 0, 0, 0, 0);
+                }
+                site(valid, j, f);
             }
         }
         if (A.bt.ndom > 0) {
@@ -396,7 +500,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                     t = (R)q.w - (nx * px + ny * py + nz * pz);
                     keep = t < r;
                 }
-                f(keep, false, false, nx, ny, nz, t, -1 - w);
+                f(keep, false, false, nx, ny, nz, t, -1 - w, R(0));
             }
             return;
         }
@@ -419,18 +523,21 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             ny = ax == 1 ? sg : R(0);
             nz = ax == 2 ? sg : R(0);
         }
-        f(keep, false, false, nx, ny, nz, t, -1 - gl);
+        f(keep, false, false, nx, ny, nz, t, -1 - gl, R(0));
     };
     // keep the candidates with t < thr. nnear counts the kept planes within 0.1 r of p_i:
     // where two such planes meet, the cell's shape near p_i is set by offsets far below r,
     // which float32 coordinates (relative to p_i, absolute error ~6e-8 r) resolve only to
     // ~6e-8 r / max(|t1|, |t2|); such cells are finished in float64.
     int nnear = 0;
+    // the seed pass keeps the sites within dsel of p_i only (the walls always)
+    R dsel2 = R(0);
     auto collect = [&](R thr) {
         ncand = 0;
         nnear = 0;
-        scan([&](bool keep, bool kill, bool neg, R nx, R ny, R nz, R t, int id) {
-            const bool k2 = keep && t < thr;
+        scan([&](bool keep, bool kill, bool neg, R nx, R ny, R nz, R t, int id, R d2) {
+            bool k2 = keep && t < thr;
+            if constexpr (seed) k2 = k2 && (id < 0 || d2 < dsel2);
             if constexpr (sizeof(R) == 4) nnear += popc(gballot<G>(k2 && fabs(t) < R(0.1) * r));
             const unsigned long long b = gballot<G>(k2);
             if (k2) {
@@ -448,12 +555,71 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             if (gballot<G>(neg)) inside = false;
         });
     };
-    if (live) collect(r);
+    if constexpr (MODE == 0) {
+        // a search block holding more than FAST_SCAN_MAX sites: crowded, deferred
+        if (live) {
+            int tot = 0;
+            for (int c0 = 0; c0 < ncol; c0 += G) {
+                int cnt = 0;
+                if (c0 + gl < ncol) {
+                    const int ix = lo3[0] + (c0 + gl) / nyc, iy = lo3[1] + (c0 + gl) % nyc;
+                    const int col = gd.base + (ix * gd.dim[1] + iy) * gd.dim[2];
+                    cnt = A.cell_start[col + hi3[2] + 1] - A.cell_start[col + lo3[2]];
+                }
+                tot += gsum<G>(cnt);
+            }
+            if (tot > FAST_SCAN_MAX) {
+                deferred = true;
+                live = false;
+            }
+        }
+    }
+    if constexpr (seed) {
+        // the nearest sites: the largest radius 2.5 h 2^(-k/3) (h = site spacing; the sphere
+        // lies in the block) holding at most CMAX candidates. Any subset of the
+        // bisectors gives a superset of the cell, so if even the smallest radius holds
+        // more, the first CMAX found are kept.
+        if (live) {
+            constexpr int ND = 12;
+            int cnt[ND];
+            R d2k[ND];
+            R f = R(2.5) * (R)gd.hsp;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                d2k[k] = f * f;
+                cnt[k] = 0;
+                f *= R(0.79370052598409974);
+            }
+            scan([&](bool keep, bool, bool, R, R, R, R, int id, R d2) {
+#pragma unroll
+                for (int k = 0; k < ND; ++k) cnt[k] += (keep && id >= 0 && d2 < d2k[k]) ? 1 : 0;
+            });
+            int kk = ND - 1;
+#pragma unroll
+            for (int k = ND - 1; k >= 0; --k)
+                if (gsum<G>(cnt[k]) <= CMAX - 6) kk = k;
+#pragma unroll
+            for (int k = 0; k < ND; ++k)
+                if (k == kk) dsel2 = d2k[k];
+        }
+    }
+    if (live && !empty) collect(r);
+    if constexpr (seed) ncand = min(ncand, CMAX);
     if (!rounds && live && !empty && ncand > CMAX) {
         deferred = true;
         live = false;
     }
-    if (rounds && live && !empty && ncand > CMAX) {
+    if (MODE == 1 && live && !empty && ncand > CMAX) {
+        // Crowded pass: the polytope starts from the cell's box, which already holds the
+        // cell tightly, so the first CMAX candidates found are clipped and the clip rounds
+        // then take every candidate that still cuts the polytope (tau = -r: no threshold).
+        // (A threshold on t would assume the site lies near its cell; a crowded site often
+        // lies far outside it, behind many of its bisectors.)
+        tau = -r;
+        overflow = true;
+        ncand = CMAX;
+    }
+    if (MODE == 2 && live && !empty && ncand > CMAX) {
         constexpr int NT = 18;  // tau = r 2^(-k/3), k = 1..18 (down to r / 64)
         R thr[NT];
         int cnt[NT];
@@ -464,7 +630,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             cnt[k] = 0;
             f *= R(0.79370052598409974);
         }
-        scan([&](bool keep, bool, bool, R, R, R, R t, int) {
+        scan([&](bool keep, bool, bool, R, R, R, R t, int, R) {
 #pragma unroll
             for (int k = 0; k < NT; ++k) cnt[k] += (keep && t < thr[k]) ? 1 : 0;
         });
@@ -518,18 +684,32 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             }
         }
     };
-    // auxiliary cube p_i +- L (outside the ball, never a facet); planes 0..5 = -x,+x,-y,+y,-z,+z
+    // auxiliary box (never a facet); planes 0..5 = -x,+x,-y,+y,-z,+z. Normally the cube
+    // p_i +- L, outside the ball. The crowded pass starts from the cell's box instead: it
+    // holds the cell with a margin, so its faces never touch the restricted cell, and the
+    // clipped polytope stays inside the box, where every bisector that can cut the cell
+    // is among the box-overlap candidates.
     const R L = R(1.05) * r;
+    R ax0 = -L, ax1 = L, ay0 = -L, ay1 = L, az0 = -L, az1 = L;
+    if constexpr (MODE == 1) {
+        ax0 = fmax(-L, (R)qlo[0] - px);
+        ax1 = fmin(L, (R)qhi[0] - px);
+        ay0 = fmax(-L, (R)qlo[1] - py);
+        ay1 = fmin(L, (R)qhi[1] - py);
+        az0 = fmax(-L, (R)qlo[2] - pz);
+        az1 = fmin(L, (R)qhi[2] - pz);
+    }
     if (live && gl < 6) {
         const int ax = gl >> 1;
         const R sg = (gl & 1) ? R(1) : R(-1);
+        const R lo = ax == 0 ? ax0 : (ax == 1 ? ay0 : az0), hi = ax == 0 ? ax1 : (ax == 1 ? ay1 : az1);
         S.pl[gl][0] = ax == 0 ? sg : R(0);
         S.pl[gl][1] = ax == 1 ? sg : R(0);
         S.pl[gl][2] = ax == 2 ? sg : R(0);
-        S.pl[gl][3] = L;
+        S.pl[gl][3] = (gl & 1) ? hi : -lo;
         S.pid[gl] = AUX_PLANE_ID - gl;
     }
-    // vertex slots in registers; the cube's corners go to slots 0..7
+    // vertex slots in registers; the box's corners go to slots 0..7
     uint32_t tri[NS];
     R vx[NS], vy[NS], vz[NS];
 #pragma unroll
@@ -541,9 +721,9 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             const int sx = (s & 1) ? 1 : -1, sy = (s & 2) ? 1 : -1, sz = (s & 4) ? 1 : -1;
             const int a = sx < 0 ? 0 : 1, b = sy < 0 ? 2 : 3, c = sz < 0 ? 4 : 5;
             tri[k] = (sx * sy * sz > 0) ? pack3(a, b, c) : pack3(a, c, b);
-            vx[k] = sx * L;
-            vy[k] = sy * L;
-            vz[k] = sz * L;
+            vx[k] = sx < 0 ? ax0 : ax1;
+            vy[k] = sy < 0 ? ay0 : ay1;
+            vz[k] = sz < 0 ? az0 : az1;
         }
     }
     int np = 6, ntri = 8, nface = 6;
@@ -776,7 +956,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         rank_round(count);
         __syncthreads();
         clip_round(nclip);
-        if (!rounds || round >= OVERFLOW_ROUNDS || !__any(more && live)) break;
+        if (!rounds || round >= (MODE == 1 ? CROWD_ROUNDS : OVERFLOW_ROUNDS) || !__any(more && live)) break;
         compact();
         R v2 = R(0);
 #pragma unroll
@@ -790,7 +970,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         __syncthreads();  // the clip tables become the staging list
         if (more && live && reff >= tau) {
             const int npl = np;
-            scan([&](bool keep, bool, bool, R nx, R ny, R nz, R t, int id) {
+            scan([&](bool keep, bool, bool, R nx, R ny, R nz, R t, int id, R) {
                 unsigned long long pm = gballot<G>(keep && t >= tau && t < reff);
                 while (pm) {
                     const int q = __ffsll((long long)pm) - 1;
@@ -856,6 +1036,51 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 vz[k] = (at * bcz + bt * caz + ct * abz) * inv;
             }
         }
+    }
+
+    // ---------------- the cell's box (fast and seed passes) ----------------
+    // The polytope's vertex bounds clamped to the ball's bounds, widened by a margin for
+    // float32 rounding (relative to r, and to the coordinates): a box that holds the
+    // restricted cell (the exact cell in the fast pass, a superset in the seed pass).
+    // Cells that failed get the ball's bounds, empty cells an empty box.
+    if constexpr (MODE == 0 || seed) {
+        R b0x = R(3e38), b0y = R(3e38), b0z = R(3e38), b1x = R(-3e38), b1y = R(-3e38), b1z = R(-3e38);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (tri[k] == TRI_INVALID) continue;
+            b0x = fmin(b0x, vx[k]);
+            b0y = fmin(b0y, vy[k]);
+            b0z = fmin(b0z, vz[k]);
+            b1x = fmax(b1x, vx[k]);
+            b1y = fmax(b1y, vy[k]);
+            b1z = fmax(b1z, vz[k]);
+        }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) {
+            b0x = fmin(b0x, __shfl_xor(b0x, o, 64));
+            b0y = fmin(b0y, __shfl_xor(b0y, o, 64));
+            b0z = fmin(b0z, __shfl_xor(b0z, o, 64));
+            b1x = fmax(b1x, __shfl_xor(b1x, o, 64));
+            b1y = fmax(b1y, __shfl_xor(b1y, o, 64));
+            b1z = fmax(b1z, __shfl_xor(b1z, o, 64));
+        }
+        if (act && !deferred && gl == 0) {
+            const float mg = 2e-5f * (float)r + 2e-7f * (fabsf((float)px) + fabsf((float)py) + fabsf((float)pz));
+            float4 lo = make_float4(3e38f, 3e38f, 3e38f, 0.f), hi = make_float4(-3e38f, -3e38f, -3e38f, 0.f);
+            if (live) {
+                lo = make_float4((float)(px + fmax(b0x, -r)) - mg, (float)(py + fmax(b0y, -r)) - mg,
+                                 (float)(pz + fmax(b0z, -r)) - mg, 0.f);
+                hi = make_float4((float)(px + fmin(b1x, r)) + mg, (float)(py + fmin(b1y, r)) + mg,
+                                 (float)(pz + fmin(b1z, r)) + mg, 0.f);
+            } else if (!(flags & CF_EMPTY) && r > R(0)) {
+                const float rr = (float)r * 1.00002f + mg;
+                lo = make_float4((float)px - rr, (float)py - rr, (float)pz - rr, 0.f);
+                hi = make_float4((float)px + rr, (float)py + rr, (float)pz + rr, 0.f);
+            }
+            A.qb.box[2 * cell] = lo;
+            A.qb.box[2 * cell + 1] = hi;
+        }
+        if constexpr (seed) return;
     }
 
     // ---------------- restriction to the ball and integration ----------------
@@ -1112,11 +1337,111 @@ __global__ __launch_bounds__(64) void k_cells_fast(CellArgs A) {
     cell_body<float, G, FAST_CMAX, FAST_PMAX, FAST_VMAX, 0, MOM>(cell, A, smem[gi]);
 }
 
-// Cells deferred by the fast pass (more candidates than it holds), one per wavefront,
-// with the threshold ladder and clip rounds, in float64: such cells come from crowded
-// regions with large weights, where a site can sit well outside its own cell and the
-// pyramid terms of float32 coordinates cancel. The list length is read on the device
-// and the blocks stride over it.
+// Seed pass of the cells deferred by the fast pass (crowded cells), one per wavefront:
+// each is clipped by its nearest sites only, and writes the box of that superset of
+// its cell. The list length is read on the device and the blocks stride over it.
+__global__ __launch_bounds__(64) void k_cells_seed(CellArgs A) {
+    __shared__ CellSmem<float, SEED_CMAX, SEED_PMAX, SEED_VMAX> smem[1];
+    const int count = *A.out.ovf_count;
+    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+        const int64_t cell = A.out.ovf_list[k];
+        cell_body<float, 64, SEED_CMAX, SEED_PMAX, SEED_VMAX, 3, false>(cell, A, smem[0]);
+        __syncthreads();
+    }
+}
+
+// Registration of the cell boxes in the buckets of the box grid (every cell of the
+// selected instances; nothing to do when no cell was deferred). A box spanning more
+// than QREG_MAX buckets goes to the list of large boxes instead.
+struct BucketRange {
+    int lo[3], hi[3], count;
+};
+__device__ inline BucketRange bucket_range(const GridDesc &g, float4 lo, float4 hi) {
+    BucketRange br;
+    const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+    br.count = 1;
+    for (int a = 0; a < 3; ++a) {
+        br.lo[a] = min(max((int)floorf((l[a] - g.lo[a]) * g.inv_s), 0), g.dim[a] - 1);
+        br.hi[a] = min(max((int)floorf((h[a] - g.lo[a]) * g.inv_s), 0), g.dim[a] - 1);
+        br.count *= br.hi[a] - br.lo[a] + 1;
+    }
+    return br;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_qbox_register(int64_t n, Batch bt, int want, const int32_t *__restrict__ ovf_count,
+                                                       QBoxes qb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || *ovf_count == 0) return;
+    const int b = bt.inst[i];
+    if (!selected(bt, want, b)) return;
+    const float4 lo = qb.box[2 * i], hi = qb.box[2 * i + 1];
+    if (!(lo.x <= hi.x && lo.y <= hi.y && lo.z <= hi.z)) return;  // empty cell
+    GridDesc g;
+    BucketRange br;
+    int lev = 0;
+    for (; lev < QLEV; ++lev) {
+        g = qb.qgrid[b * QLEV + lev];
+        br = bucket_range(g, lo, hi);
+        if (br.count <= QREG_MAX) break;
+    }
+    if (lev == QLEV) {
+        if (!FILL) qb.large[atomicAdd(qb.nlarge, 1)] = (int32_t)i;
+        return;
+    }
+    for (int ix = br.lo[0]; ix <= br.hi[0]; ++ix)
+        for (int iy = br.lo[1]; iy <= br.hi[1]; ++iy)
+            for (int iz = br.lo[2]; iz <= br.hi[2]; ++iz) {
+                const int key = g.base + (ix * g.dim[1] + iy) * g.dim[2] + iz;
+                if (FILL)
+                    qb.ent[qb.start[key] + atomicAdd(qb.cursor + key, 1)] = (int32_t)i;
+                else
+                    atomicAdd(qb.count + key, 1);
+            }
+}
+
+// counts (and the large list) before the count pass, fill cursors before the fill pass
+__global__ __launch_bounds__(256) void k_qbox_zero(QBoxes qb, bool cursors) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cursors) {
+        if (k < qb.nq) qb.cursor[k] = 0;
+        return;
+    }
+    if (k <= qb.nq) qb.count[k] = 0;
+    if (k == 0) *qb.nlarge = 0;
+}
+
+// The list of large boxes in ascending order (its length is small; one thread, heap sort),
+// so that the candidates do not depend on the order of the atomics.
+__global__ __launch_bounds__(64) void k_qbox_sort_large(QBoxes qb) {
+    if (threadIdx.x != 0) return;
+    int32_t *a = qb.large;
+    const int m = *qb.nlarge;
+    auto sift = [&](int root, int end) {
+        for (;;) {
+            int child = 2 * root + 1;
+            if (child >= end) return;
+            if (child + 1 < end && a[child + 1] > a[child]) ++child;
+            if (a[root] >= a[child]) return;
+            const int32_t t = a[root];
+            a[root] = a[child];
+            a[child] = t;
+            root = child;
+        }
+    };
+    for (int r = m / 2 - 1; r >= 0; --r) sift(r, m);
+    for (int last = m - 1; last > 0; --last) {
+        const int32_t t = a[0];
+        a[0] = a[last];
+        a[last] = t;
+        sift(0, last);
+    }
+}
+
+// Crowded pass: the deferred cells, one per wavefront, in float64 (a crowded cell's site
+// often lies well outside its cell, where the pyramid terms of float32 coordinates
+// cancel), with the candidates whose boxes overlap the cell's box, the threshold ladder
+// and clip rounds when they exceed the capacity.
 __global__ __launch_bounds__(64) void k_cells_overflow(CellArgs A) {
     __shared__ CellSmem<double, OVF_CMAX, OVF_PMAX, OVF_VMAX> smem[1];
     const int count = *A.out.ovf_count;
@@ -1155,8 +1480,8 @@ void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out) {
 }
 
 void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s, const double *psi,
-                  const int32_t *perm, const int32_t *cell_start, EvalOut out, int tpc) {
-    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out};
+                  const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb, int tpc) {
+    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb};
     if (out.cen) {  // centroids: one instantiation (32 lanes per cell)
         hipLaunchKernelGGL((k_cells_fast<32, true>), dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, a);
     } else if (tpc == 8) {
@@ -1170,12 +1495,23 @@ void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const fl
     }
 }
 
-// The overflow pass takes the cells deferred by the fast pass, and the float64 pass
-// the cells listed by both float32 passes (all of them from selected instances); they
-// read the list lengths on the device.
-void launch_cells_fallback(hipStream_t st, const Batch &bt, const float4 *pos_s, const double *psi,
-                           const int32_t *perm, const int32_t *cell_start, EvalOut out) {
-    CellArgs a{0, pos_s, psi, perm, cell_start, bt, -1, out};
+// The crowded cells deferred by the fast pass (seed boxes, box grid, box-overlap
+// candidates), then the cells listed for the float64 pass by both; the passes read the
+// list lengths on the device (no host synchronisation).
+void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
+                           const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
+                           const QBoxes &qb) {
+    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb};
+    hipLaunchKernelGGL(k_cells_seed, dim3(4096), dim3(64), 0, st, a);
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    const unsigned nz = (unsigned)((qb.nq + 256) / 256);
+    hipLaunchKernelGGL(k_qbox_zero, dim3(nz), dim3(256), 0, st, qb, false);
+    hipLaunchKernelGGL(k_qbox_register<false>, dim3(nb), dim3(256), 0, st, n, bt, want, out.ovf_count, qb);
+    launch_scan_i32(st, qb.count, qb.start, qb.nq, qb.tmp);
+    hipLaunchKernelGGL(k_qbox_zero, dim3(nz), dim3(256), 0, st, qb, true);
+    hipLaunchKernelGGL(k_qbox_register<true>, dim3(nb), dim3(256), 0, st, n, bt, want, out.ovf_count, qb);
+    launch_sort_segments(st, qb.nq, qb.start, qb.ent);
+    hipLaunchKernelGGL(k_qbox_sort_large, dim3(1), dim3(64), 0, st, qb);
     hipLaunchKernelGGL(k_cells_overflow, dim3(4096), dim3(64), 0, st, a);
     hipLaunchKernelGGL(k_cells_big, dim3(2048), dim3(64), 0, st, a);
 }

@@ -1,11 +1,11 @@
 // grid.hip -- uniform-grid spatial sort of the sites (grid_knn, construction
 // part) and the gathers/scatters between caller order and grid order.
 //
-// The grid cell size s is at least r_i + r_j for every pair the cell kernel
-// may need, so the bisectors that cut ball i come from the grid cells within
-// ceil((r_i + r_max)/s) of site i (section 4 "Finding Contributing Neighbors":
-// the ball bound replaces the security radius and is exact for restricted
-// cells). Sites are counting-sorted by grid cell (z fastest), and within a grid
+// The bisectors that cut ball i come from the grid cells within r_i + r_max of
+// site i (section 4 "Finding Contributing Neighbors": the ball bound replaces the
+// security radius and is exact for restricted cells); cells whose block is crowded
+// take the box-overlap pass of cells.hip instead. Sites are counting-sorted by grid
+// cell (z fastest), and within a grid
 // cell by caller index, so the order is deterministic. In a batched call every
 // instance has its own grid (its own box and r_max); the grids are laid end to
 // end in one cell array, so one sort orders all instances and keeps each one in
@@ -433,6 +433,10 @@ void launch_scatter_rows(hipStream_t st, int64_t n, int row_bytes, const int32_t
 
 void launch_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int n, int32_t *tmp) {
     exclusive_scan(st, in, out, n, tmp);
+}
+
+void launch_sort_segments(hipStream_t st, int nseg, const int32_t *start, int32_t *data) {
+    hipLaunchKernelGGL(k_sort_cells, dim3(nblocks(nseg, 256)), dim3(256), 0, st, nseg, start, data);
 }
 
 void launch_csr_count(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcnt, int32_t *cnt_orig) {

@@ -24,10 +24,24 @@ constexpr int FAST_VMAX = 64;   // polytope vertices (triangles of the dual)
 constexpr int BIG_CMAX = 256;
 constexpr int BIG_PMAX = 64;
 constexpr int BIG_VMAX = 128;
-constexpr int OVF_CMAX = 96;     // float32 path for cells with more candidates than FAST_CMAX
+constexpr int OVF_CMAX = 96;     // float64 pass for the cells the fast pass defers (crowded cells)
 constexpr int OVF_PMAX = 64;
 constexpr int OVF_VMAX = 128;
 constexpr int OVERFLOW_ROUNDS = 8;  // clip rounds for cells with more candidates than CMAX
+constexpr int CROWD_ROUNDS = 32;    // ... in the crowded pass (no threshold on t: rounds end when no
+                                    // candidate cuts the polytope)
+constexpr int SEED_CMAX = 64;    // seed pass of a crowded cell: its nearest sites (float32, 64 lanes)
+constexpr int SEED_PMAX = 64;
+constexpr int SEED_VMAX = 128;
+// The fast pass defers a cell whose search block (sites within r + r_max) holds more
+// sites than this: such a cell is crowded, and its neighbours are found from the
+// geometry of the cells instead (seed pass, cell boxes, box-overlap candidates).
+constexpr int FAST_SCAN_MAX = 256;
+// Box grids: QLEV levels of bucket size h 4^l (h: 1.2 site spacings). A cell box is
+// registered at the finest level where it spans at most QREG_MAX buckets; boxes too
+// large for every level go to a per-call list that every crowded cell tests directly.
+constexpr int QREG_MAX = 27;
+constexpr int QLEV = 3;
 
 // Per-cell status bits written by the cell kernel.
 enum CellFlag : uint32_t {
@@ -49,6 +63,8 @@ struct GridDesc {
     int dim[3];       // cells per axis
     int ncell;        // dim[0]*dim[1]*dim[2]
     int base;         // first entry of this grid in the shared cell_start array
+    float hsp;        // typical site spacing of the instance: cbrt(sum nu / n), else cbrt(|box| / n)
+    int pad;
 };
 
 struct BoxF {
@@ -126,7 +142,8 @@ struct InstCtl {
     int iters, evals, halvings, hstep, cg_iters, status, default_start, learned;
     int restore;       // the float32 shadow must be reset to the accepted weights
     int repaired;      // empty start cells were given the default weight
-    int pad[2];
+    int iter_base;     // iterations before the current continuation stage (the limit counts from here)
+    int pad;
 };
 
 // Newton options as the device control kernels see them.
@@ -152,6 +169,26 @@ struct EvalOut {
     int32_t *ovf_list;  // [n] cells with more candidates than the fast kernel holds
     int32_t *ovf_count; // [1] length of ovf_list (device counter)
     double *cen;        // [3n] centroids in caller order (null: not computed)
+};
+
+// Cell boxes and the box grid of the crowded-cell pass (section 4, "Finding
+// Contributing Neighbors"). Every evaluated cell writes an axis-aligned box that holds
+// its restricted cell: the exact cell for cells finished by the fast pass, a superset
+// (the cell clipped by its nearest sites only) for deferred ones. If sites i and j share
+// a facet, the facet lies in both cells, so their boxes overlap: the candidates of a
+// crowded cell are the sites whose boxes overlap its own. Boxes are registered in the
+// buckets of a uniform grid (one per instance, GridDesc qgrid[b]) they overlap.
+struct QBoxes {
+    float4 *box;        // [2n] grid order: (lo.x, lo.y, lo.z, 0), (hi.x, hi.y, hi.z, 0); empty: lo > hi
+    const GridDesc *qgrid;  // [B * QLEV] bucket grids (instance-major), laid end to end (base) in start/count/cursor
+    int32_t *count;     // [nq + 1] boxes per bucket
+    int32_t *start;     // [nq + 1] exclusive scan of count
+    int32_t *cursor;    // [nq] fill cursors
+    int32_t *ent;       // [QREG_MAX * n] cell ids per bucket
+    int32_t *large;     // [n] cells whose boxes span more than QREG_MAX buckets
+    int32_t *nlarge;    // [1]
+    int32_t *tmp;       // [nq / 1024 + 16] scan workspace
+    int nq;             // buckets over all instances
 };
 
 // Conjugate-gradient vectors and scalars (Chronopoulos-Gear form, one kernel per
@@ -222,6 +259,8 @@ void launch_permute_in(hipStream_t st, int64_t n, const int32_t *perm, const flo
 void launch_psi_shadow(hipStream_t st, int64_t n, const double *psi_s, float4 *pos_s);
 void launch_scatter_out_f64(hipStream_t st, int64_t n, const int32_t *perm, const double *src_s, double *dst);
 void launch_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int n, int32_t *tmp);
+// sorts data[start[c] .. start[c+1]) ascending for every c < nseg
+void launch_sort_segments(hipStream_t st, int nseg, const int32_t *start, int32_t *data);
 void launch_csr_count(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcnt, int32_t *cnt_orig);
 void launch_csr_fill(hipStream_t st, int64_t n, const int32_t *perm, const int32_t *fcol, const float *farea,
                      const int32_t *fcnt, const int32_t *start, int32_t *col, float *area, int64_t *row_ptr);
@@ -238,9 +277,12 @@ void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double
 // Cells of the selected instances at the float64 weights psi (float32 shadow in pos_s.w).
 void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out);
 void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s, const double *psi,
-                  const int32_t *perm, const int32_t *cell_start, EvalOut out, int tpc);
-void launch_cells_fallback(hipStream_t st, const Batch &bt, const float4 *pos_s, const double *psi,
-                           const int32_t *perm, const int32_t *cell_start, EvalOut out);
+                  const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb, int tpc);
+// The passes after the fast one: the crowded cells it deferred (seed boxes, box grid,
+// box-overlap candidates, float64), then the cells flagged for the float64 pass.
+void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
+                           const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
+                           const QBoxes &qb);
 
 // newton.hip
 // ev[4b..4b+3] = sum V, max |V - nu| / nu, ||nu - V||_2, min V of every selected instance
@@ -249,16 +291,19 @@ void launch_eval_reduce(hipStream_t st, const Batch &bt, int want, const double 
 void launch_hess_assemble(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                           const int32_t *fcol, const float *farea, const int32_t *fcnt, int32_t *hcol, float *hval,
                           int32_t *xcnt, int32_t *herr);
-void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, const double *psi_s, const double *K,
+// Row lengths, sorted rows and the diagonal of -Hess K; with ent given (else null), the
+// rows are also packed per tile: row i at ent[tile * TILE * FCAP + hrow[i].x], hrow[i].y
+// entries of (column, float bits of the value)
+void launch_hess_finish(hipStream_t st, const Batch &bt, int want, const double *psi_s, const double *K,
                         const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, int32_t *hcol, float *hval,
-                        double *diag);
+                        double *diag, int2 *hrow, int2 *ent);
 // CG block shape: `lanes` lanes per row (1, 2, 4 or 8), `sub` rows per block (64, 128
 // or 256; 8 lanes with at most 128 rows)
 bool cg_shape_ok(int lanes, int sub);
 void launch_cg_init(hipStream_t st, const Batch &bt, int lanes, int sub, const double *V, const double *nu,
-                    const double *diag, const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg);
+                    const double *diag, const int2 *hrow, const int2 *ent, CgBufs cg);
 void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
-                    const int32_t *hcol, const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg);
+                    const int2 *hrow, const int2 *ent, CgBufs cg);
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg);
 void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, CgBufs cg, const int32_t *herr,
                       InstCtl *ctl, int32_t *phase);
@@ -274,6 +319,14 @@ void launch_ctl_decide(hipStream_t st, const Batch &bt, CtlOpts o, const double 
 void launch_accept_rows(hipStream_t st, const Batch &bt, const InstCtl *ctl, double *psi_s, const double *psi_trial,
                         float4 *pos_s);
 void launch_ctl_commit(hipStream_t st, const Batch &bt, CtlOpts o, InstCtl *ctl, int32_t *phase, int32_t *counts);
+// Start of a continuation stage (every instance): the current iterate, with statistics
+// ev against the stage's prescribed volumes (statistics ev_nu), becomes the stage's
+// start: status cleared, eps0 = 0.5 min(min nu_s, min V), the iteration limit counted
+// from here; DONE if it already meets o.tol.
+void launch_ctl_stage(hipStream_t st, const Batch &bt, CtlOpts o, const double *ev, const double *ev_nu,
+                      const int32_t *fail_inst, InstCtl *ctl, int32_t *phase, int32_t *counts);
+// nu_s = (1 - s) v0 + s nu over n rows
+void launch_nu_stage(hipStream_t st, int64_t n, double s, const double *v0, const double *nu, double *nu_s);
 
 // fluid.hip
 // Rows of the velocity system in grid order: rescales hval from w_ij to mu_ij w_ij,

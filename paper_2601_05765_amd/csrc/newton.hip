@@ -175,35 +175,67 @@ __global__ void k_hess_assemble(int64_t n, Batch bt, int want, const float4 *__r
 
 // Row length, diagonal; the entries appended by the union pattern arrive in atomic
 // order and are sorted by column here, so every later sum over the row is in a fixed
-// order (deterministic results).
-__global__ void k_hess_finish(int64_t n, Batch bt, int want, const double *__restrict__ psi,
-                              const double *__restrict__ K, const int32_t *__restrict__ fcnt,
-                              const int32_t *__restrict__ xcnt, int32_t *__restrict__ hcnt,
-                              int32_t *__restrict__ hcol, float *__restrict__ hval, double *__restrict__ diag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !selected(bt, want, bt.inst[i])) return;
-    const int f0 = fcnt[i];
-    const int c = min(f0 + xcnt[i], FCAP);
-    hcnt[i] = c;
-    int32_t *cr = hcol + i * FCAP;
-    float *vr = hval + i * FCAP;
-    for (int a = f0 + 1; a < c; ++a) {
-        const int32_t key = cr[a];
-        const float v = vr[a];
-        int b = a - 1;
-        while (b >= f0 && cr[b] > key) {
-            cr[b + 1] = cr[b];
-            vr[b + 1] = vr[b];
-            --b;
+// order (deterministic results). One block per tile. With ent given, the tile's rows
+// are also packed back to back as (column, float bits of the value) pairs into the
+// tile's region ent[t * TILE * FCAP ...], row i starting at hrow[i].x within it
+// (hrow[i].y = its length): the conjugate gradients then read every row's entries
+// from consecutive addresses instead of one 64-entry block per row.
+__global__ __launch_bounds__(TILE) void k_hess_finish(Batch bt, int want, const double *__restrict__ psi,
+                                                       const double *__restrict__ K, const int32_t *__restrict__ fcnt,
+                                                       const int32_t *__restrict__ xcnt, int32_t *__restrict__ hcnt,
+                                                       int32_t *__restrict__ hcol, float *__restrict__ hval,
+                                                       double *__restrict__ diag, int2 *__restrict__ hrow,
+                                                       int2 *__restrict__ ent) {
+    __shared__ int wsum[TILE / 64];
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (!selected(bt, want, b)) return;
+    const int64_t i = bt.tile_row[t] + (int)threadIdx.x;
+    const bool has = i < bt.off[b + 1];
+    int c = 0;
+    if (has) {
+        const int f0 = fcnt[i];
+        c = min(f0 + xcnt[i], FCAP);
+        hcnt[i] = c;
+        int32_t *cr = hcol + i * FCAP;
+        float *vr = hval + i * FCAP;
+        for (int a = f0 + 1; a < c; ++a) {
+            const int32_t key = cr[a];
+            const float v = vr[a];
+            int q = a - 1;
+            while (q >= f0 && cr[q] > key) {
+                cr[q + 1] = cr[q];
+                vr[q + 1] = vr[q];
+                --q;
+            }
+            cr[q + 1] = key;
+            vr[q + 1] = v;
         }
-        cr[b + 1] = key;
-        vr[b + 1] = v;
+        double s = 0.0;
+        for (int f = 0; f < c; ++f) s += (double)vr[f];
+        const double p = psi[i];
+        if (p > 0.0) s += K[i] / (2.0 * sqrt(p));
+        diag[i] = s;
     }
-    double s = 0.0;
-    for (int f = 0; f < c; ++f) s += (double)hval[i * FCAP + f];
-    const double p = psi[i];
-    if (p > 0.0) s += K[i] / (2.0 * sqrt(p));
-    diag[i] = s;
+    if (!ent) return;
+    // exclusive scan of the row lengths over the tile
+    int incl = c;
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int excl = incl - c;
+    for (int k = 0; k < w; ++k) excl += wsum[k];
+    if (!has) return;
+    hrow[i] = make_int2(excl, c);
+    const int32_t *cr = hcol + i * FCAP;
+    const float *vr = hval + i * FCAP;
+    int2 *er = ent + (int64_t)t * (TILE * FCAP) + excl;
+    for (int f = 0; f < c; ++f) er[f] = make_int2(cr[f], __float_as_int(vr[f]));
 }
 
 // ---- Jacobi-PCG, one kernel per iteration (Chronopoulos-Gear form) ------------
@@ -294,9 +326,8 @@ __device__ inline double *P_RHO0(const CgBufs &cg, int NS) { return cg.part + 6 
 // r_0 = g = nu - V (0 on empty rows), u_0 = r_0 / D, w_0 = A u_0, s_{-1} = p_{-1} = x_0 = 0
 template <int LANES, int SUB>
 __global__ __launch_bounds__(LANES * SUB) void k_cg_init(Batch bt, const double *__restrict__ V, const double *__restrict__ nu,
-                                                 const double *__restrict__ diag, const int32_t *__restrict__ hcol,
-                                                 const float *__restrict__ hval, const int32_t *__restrict__ hcnt,
-                                                 CgBufs cg) {
+                                                 const double *__restrict__ diag, const int2 *__restrict__ hrow,
+                                                 const int2 *__restrict__ ent, CgBufs cg) {
     constexpr int SPT = TILE / SUB;
     __shared__ double sh[LANES * SUB / 64][4];
     const int q = xcd_block((int)blockIdx.x, (int)gridDim.x);
@@ -310,14 +341,13 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_init(Batch bt, const double 
     const bool has = row < bt.off[b + 1];
     double acc = 0.0;
     if (has) {
-        const int c = hcnt[row];
-        const int32_t *cr = hcol + (int64_t)row * FCAP;
-        const float *vr = hval + (int64_t)row * FCAP;
-        for (int f = l; f < c; f += LANES) {
-            const int j = cr[f];
-            const double dj = diag[j];
-            const double uj = dj > 0.0 ? (nu[j] - V[j]) / dj : 0.0;
-            acc += (double)vr[f] * uj;
+        const int2 hr = hrow[row];
+        const int2 *er = ent + (int64_t)t * (TILE * FCAP) + hr.x;
+        for (int f = l; f < hr.y; f += LANES) {
+            const int2 e = er[f];
+            const double dj = diag[e.x];
+            const double uj = dj > 0.0 ? (nu[e.x] - V[e.x]) / dj : 0.0;
+            acc += (double)__int_as_float(e.y) * uj;
         }
     }
 #pragma unroll
@@ -357,8 +387,7 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_init(Batch bt, const double 
 // are issued before the partial sums that give the scalars, so their latencies overlap.
 template <int LANES, int SUB>
 __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double rtol2, int cap,
-                                                 const int32_t *__restrict__ hcol, const float *__restrict__ hval,
-                                                 const int32_t *__restrict__ hcnt, const double *__restrict__ diag,
+                                                 const int2 *__restrict__ hrow, const int2 *__restrict__ ent,
                                                  CgBufs cg) {
     constexpr int SPT = TILE / SUB;
     __shared__ double sh[LANES * SUB / 64][4];
@@ -382,24 +411,26 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
     int c = 0;
     RWSD own{0.0, 0.0, 0.0, 0.0};
     double pk_1 = 0.0, xk = 0.0;
+    int2 hr = make_int2(0, 0);
     float vv[PF];
     RWSD nb[PF];
     if (has) {
-        c = hcnt[row];
+        hr = hrow[row];
+        c = hr.y;
         own = load_rwsd(cur_rec, row);
         pk_1 = cg.p[row];
         xk = cg.x[row];
     }
-    const int32_t *cr = hcol + (int64_t)row * FCAP;
-    const float *vr = hval + (int64_t)row * FCAP;
+    const int2 *er = ent + (int64_t)t * (TILE * FCAP) + hr.x;
 #pragma unroll
     for (int e = 0; e < PF; ++e) {
         const int f = l + LANES * e;
         vv[e] = 0.f;
         nb[e] = RWSD{0.0, 0.0, 0.0, 0.0};
         if (f < c) {
-            vv[e] = vr[f];
-            nb[e] = load_rwsd(cur_rec, cr[f]);
+            const int2 en = er[f];
+            vv[e] = __int_as_float(en.y);
+            nb[e] = load_rwsd(cur_rec, en.x);
         }
     }
     const double d = own.d, rk = own.r, wk = own.w, sk_1 = own.s;
@@ -442,10 +473,11 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
         acc += (double)vv[e] * uj;
     }
     for (int f = l + LANES * PF; f < c; f += LANES) {
-        const RWSD o = load_rwsd(cur_rec, cr[f]);
+        const int2 en = er[f];
+        const RWSD o = load_rwsd(cur_rec, en.x);
         const double s1 = fma(beta, o.s, o.w);
         const double uj = o.d > 0.0 ? fma(-alpha, s1, o.r) / o.d : 0.0;
-        acc += (double)vr[f] * uj;
+        acc += (double)__int_as_float(en.y) * uj;
     }
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LANES);
@@ -656,7 +688,7 @@ __global__ __launch_bounds__(1024) void k_ctl_commit(Batch bt, CtlOpts o, InstCt
         int ph = PH_ACTIVE;
         if (c.maxrel <= o.tol || o.single) {
             ph = PH_DONE;
-        } else if (c.iters >= o.max_newton) {
+        } else if (c.iters - c.iter_base >= o.max_newton) {
             c.status = -3;  // LAGOT_ENOCONV
             ph = PH_FAILED;
         }
@@ -666,9 +698,55 @@ __global__ __launch_bounds__(1024) void k_ctl_commit(Batch bt, CtlOpts o, InstCt
     count_phases(phase, bt.B, counts);
 }
 
+__global__ __launch_bounds__(1024) void k_ctl_stage(Batch bt, CtlOpts o, const double *__restrict__ ev,
+                                                     const double *__restrict__ ev_nu,
+                                                     const int32_t *__restrict__ fail_inst, InstCtl *__restrict__ ctl,
+                                                     int32_t *__restrict__ phase, int32_t *__restrict__ counts) {
+    for (int b = threadIdx.x; b < bt.B; b += 1024) {
+        InstCtl &c = ctl[b];
+        c.status = 0;
+        c.restore = 0;
+        c.iter_base = c.iters;
+        c.alpha = 1.0;
+        c.sumV = ev[4 * b + 0];
+        c.maxrel = ev[4 * b + 1];
+        c.gnorm = ev[4 * b + 2];
+        c.minV = ev[4 * b + 3];
+        c.eps0 = 0.5 * fmin(ev_nu[4 * b + 3], ev[4 * b + 3]);
+        int ph = PH_ACTIVE;
+        if (!(c.eps0 > 0.0)) {
+            c.status = -2;  // LAGOT_EEMPTY
+            ph = PH_FAILED;
+        } else if (fail_inst[b] != 0) {
+            c.status = -5;  // LAGOT_ECAPACITY
+            ph = PH_FAILED;
+        } else if (c.maxrel <= o.tol) {
+            ph = PH_DONE;
+        }
+        phase[b] = ph;
+    }
+    __syncthreads();
+    count_phases(phase, bt.B, counts);
+}
+
+__global__ __launch_bounds__(256) void k_nu_stage(int64_t n, double s, const double *__restrict__ v0,
+                                                   const double *__restrict__ nu, double *__restrict__ nu_s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) nu_s[i] = (1.0 - s) * v0[i] + s * nu[i];
+}
+
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_ctl_stage(hipStream_t st, const Batch &bt, CtlOpts o, const double *ev, const double *ev_nu,
+                      const int32_t *fail_inst, InstCtl *ctl, int32_t *phase, int32_t *counts) {
+    hipLaunchKernelGGL(k_ctl_stage, dim3(1), dim3(1024), 0, st, bt, o, ev, ev_nu, fail_inst, ctl, phase, counts);
+}
+
+void launch_nu_stage(hipStream_t st, int64_t n, double s, const double *v0, const double *nu, double *nu_s) {
+    hipLaunchKernelGGL(k_nu_stage, dim3(nblocks(n, 256)), dim3(256), 0, st, n, s, v0, nu, nu_s);
+}
 
 void launch_eval_reduce(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu, double *part,
                         double *ev) {
@@ -684,11 +762,11 @@ void launch_hess_assemble(hipStream_t st, int64_t n, const Batch &bt, int want, 
                        fcnt, hcol, hval, xcnt, herr);
 }
 
-void launch_hess_finish(hipStream_t st, int64_t n, const Batch &bt, int want, const double *psi_s, const double *K,
+void launch_hess_finish(hipStream_t st, const Batch &bt, int want, const double *psi_s, const double *K,
                         const int32_t *fcnt, const int32_t *xcnt, int32_t *hcnt, int32_t *hcol, float *hval,
-                        double *diag) {
-    hipLaunchKernelGGL(k_hess_finish, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, psi_s, K, fcnt, xcnt,
-                       hcnt, hcol, hval, diag);
+                        double *diag, int2 *hrow, int2 *ent) {
+    hipLaunchKernelGGL(k_hess_finish, dim3(bt.T), dim3(TILE), 0, st, bt, want, psi_s, K, fcnt, xcnt, hcnt, hcol, hval,
+                       diag, hrow, ent);
 }
 
 // shape = 4 * log2(lanes) + log2(SUB / 64): lanes in {1, 2, 4, 8}, SUB in {64, 128, 256}
@@ -703,19 +781,19 @@ bool cg_shape_ok(int lanes, int sub) {
 }
 
 void launch_cg_init(hipStream_t st, const Batch &bt, int lanes, int sub, const double *V, const double *nu,
-                    const double *diag, const int32_t *hcol, const float *hval, const int32_t *hcnt, CgBufs cg) {
+                    const double *diag, const int2 *hrow, const int2 *ent, CgBufs cg) {
     const dim3 grid((TILE / sub) * bt.T), block(lanes * sub);
 #define X(L, S) \
-    if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_init<L, S>), grid, block, 0, st, bt, V, nu, diag, hcol, hval, hcnt, cg); return; }
+    if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_init<L, S>), grid, block, 0, st, bt, V, nu, diag, hrow, ent, cg); return; }
     LAGOT_CG_SHAPES(X)
 #undef X
 }
 
 void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
-                    const int32_t *hcol, const float *hval, const int32_t *hcnt, const double *diag, CgBufs cg) {
+                    const int2 *hrow, const int2 *ent, CgBufs cg) {
     const dim3 grid((TILE / sub) * bt.T), block(lanes * sub);
 #define X(L, S) \
-    if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_iter<L, S>), grid, block, 0, st, bt, m, rtol2, cap, hcol, hval, hcnt, diag, cg); return; }
+    if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_iter<L, S>), grid, block, 0, st, bt, m, rtol2, cap, hrow, ent, cg); return; }
     LAGOT_CG_SHAPES(X)
 #undef X
 }

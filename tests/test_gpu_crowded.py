@@ -1,0 +1,170 @@
+"""Crowded scenes on the GPU: the box-overlap candidates of section 4 ("Finding
+Contributing Neighbors") and the path following on the prescribed volumes, against
+the FP64 oracle.
+
+Cells whose search block is crowded (a few balls much larger than the rest) are seeded
+with their nearest sites, boxed, and finished with the sites whose boxes overlap their
+own; the results must equal the oracle's brute-force cells element by element (the
+candidate set is exact, not a heuristic). The large-scene recipe (200 droplets packed
+1.72x next to a slab, log-normal prescribed volumes) is solved from its Voronoi start
+with opts.continuation, and then advected and solved again as in the 2M-site sequence,
+at 200,000 sites so that the oracle can check sampled cells."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_05765_amd import scenes
+
+from parity import assert_close, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2601_05765_amd as L
+    assert torch.cuda.is_available()
+    return L.Context()
+
+
+def _t(a, dt):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def _xyz(sc):
+    import torch
+    return _t(sc.x, torch.float32), _t(sc.y, torch.float32), _t(sc.z, torch.float32)
+
+
+def _sample(n, psi, seed, k_top=150, k_rand=250):
+    """The heaviest sites (the most crowded cells) and a random sample."""
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.argsort(-psi)[:k_top], rng.choice(n, k_rand, replace=False)]))
+
+
+@pytest.fixture(scope="module")
+def splash_settled(ctx):
+    """The splash recipe at 200,000 sites solved with path following (continuation)."""
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.splash(200_000, 0)
+    x, y, z = _xyz(sc)
+    nu, psi = _t(sc.nu, torch.float64), _t(sc.psi0, torch.float64)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5, residual_test=0, continuation=1), check=False)
+    _say(f"  settle: {st.as_dict()}")
+    return sc, st, psi.cpu().numpy()
+
+
+def test_continuation_settles_splash_200k(ctx, oracle_mod, splash_settled):
+    _say("case: splash 200k settled by continuation")
+    sc, st, psi = splash_settled
+    assert st.status == 0 and st.max_rel_err <= 1e-5 and st.stages >= 1
+    idx = _sample(sc.n, psi, 1)
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, psi, idx=idx)
+    err = np.abs(c.V - sc.nu[idx]) / sc.nu[idx]
+    _say(f"  oracle on {len(idx)} cells: max {err.max():.2e} p99 {np.percentile(err, 99):.2e}")
+    assert err.max() <= 1e-5
+
+
+def test_crowded_cells_match_oracle(ctx, oracle_mod, splash_settled):
+    """At the settled weights most droplet cells are crowded (balls of many spacings,
+    displaced cells): volumes, spherical areas, facet areas, wall areas and connectivity
+    of sampled cells against the oracle, with the crowded pass in use."""
+    _say("case: crowded cells at the settled splash weights")
+    sc, _, psi = splash_settled
+    x, y, z = _xyz(sc)
+    import torch
+    out = ctx.cells(x, y, z, _t(psi, torch.float64))
+    passes = ctx.last_pass_counts()
+    _say(f"  passes {passes} flags {ctx.last_flag_counts()['final']}")
+    assert passes["crowded"] > 10_000
+    idx = _sample(sc.n, psi, 2)
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, psi, idx=idx)
+    rep = compare(out, c, psi, idx=idx)
+    _say(f"  {rep}")
+    assert_close(rep)
+
+
+def test_overpacked_sphere_takes_crowded_pass(ctx, oracle_mod):
+    """The over-packed sphere at its converged weights: every cell's search block is
+    crowded, so every cell goes through the seed, box and box-overlap passes; all cells
+    match the oracle."""
+    _say("case: over-packed sphere, all cells crowded")
+    import torch
+    sc = scenes.overpacked_sphere(2500, 1.72, 0)
+    psi, st = oracle_mod.newton_solve(sc.xyz64(), sc.nu, sc.psi0, tol=1e-7)
+    assert st.status == "ok"
+    x, y, z = _xyz(sc)
+    out = ctx.cells(x, y, z, _t(psi, torch.float64))
+    passes = ctx.last_pass_counts()
+    _say(f"  passes {passes}")
+    assert passes["crowded"] >= sc.n // 2
+    rep = compare(out, oracle_mod.cells(sc.x, sc.y, sc.z, psi), psi)
+    _say(f"  {rep}")
+    assert_close(rep)
+
+
+def test_advected_steps_200k(ctx, oracle_mod, splash_settled):
+    """Two steps of the large-scene sequence at 200,000 sites: sites advected by dt 2e-3
+    with their random velocities (mirror reflection at the walls), each solve warm-started
+    from the previous weights (with continuation, as the 2M-site sequence runs)."""
+    _say("case: splash 200k, two advect-and-solve steps")
+    import torch
+    import paper_2601_05765_amd as L
+    sc, _, psi = splash_settled
+    cur = sc
+    p = _t(psi, torch.float64)
+    nu = _t(sc.nu, torch.float64)
+    for k in range(1, 3):
+        cur = scenes.advect(cur, 2e-3)
+        x, y, z = _xyz(cur)
+        st = ctx.solve(x, y, z, nu, p, opts=L.default_opts(tol=1e-5, residual_test=0, continuation=1), check=False)
+        _say(f"  step {k}: {st.as_dict()}")
+        assert st.status == 0 and st.max_rel_err <= 1e-5
+        ph = p.cpu().numpy()
+        idx = _sample(cur.n, ph, 10 + k, k_top=80, k_rand=150)
+        c = oracle_mod.cells(cur.x, cur.y, cur.z, ph, idx=idx)
+        err = np.abs(c.V - cur.nu[idx]) / cur.nu[idx]
+        _say(f"  oracle max {err.max():.2e}")
+        assert err.max() <= 1e-5
+
+
+def test_continuation_options_rejected(ctx):
+    """Invalid continuation options, and continuation in a batched call, are EINVAL."""
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(500, 3)
+    x, y, z = _xyz(sc)
+    nu = _t(sc.nu, torch.float64)
+    for kw in ({"continuation": 2}, {"continuation": 1, "stage_newton": 0}, {"continuation": 1, "stage_tol": 0.0}):
+        p = _t(sc.psi0, torch.float64)
+        st = ctx.solve(x, y, z, nu, p, opts=L.default_opts(**kw), check=False)
+        assert st.status == L.EINVAL, kw
+    offs = np.array([0, 250, 500], dtype=np.int64)
+    p = _t(sc.psi0, torch.float64)
+    sts = ctx.solve_batched(offs, x, y, z, nu, p, opts=L.default_opts(continuation=1), check=False)
+    assert all(s.status == L.EINVAL for s in sts)
+
+
+def test_continuation_on_easy_problem_matches_plain(ctx, oracle_mod):
+    """On the 1,000-site slab the path-following solve converges to the same unique
+    weights as the plain one (oracle re-evaluation within tolerance)."""
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 0)
+    x, y, z = _xyz(sc)
+    nu = _t(sc.nu, torch.float64)
+    p = _t(sc.psi0, torch.float64)
+    st = ctx.solve(x, y, z, nu, p, opts=L.default_opts(tol=1e-5, continuation=1), check=False)
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.stages >= 1
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, p.cpu().numpy())
+    assert float(np.max(np.abs(c.V - sc.nu) / sc.nu)) <= 1e-5
