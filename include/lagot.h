@@ -405,10 +405,14 @@ int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts);
 
 /* Cells of the last evaluation on this context that took the later passes (section 4,
  * "Finding Contributing Neighbors"): counts[0] the crowded cells the float32 pass
- * deferred (search block of more than 256 sites, or more than 48 candidate bisectors),
- * whose candidates came from the overlap of cell boxes; counts[1] the cells redone on the
- * float64 large-capacity path. Diagnostic.
- *   out: counts [2] HOST array. Synchronises the stream.
+ * deferred (search block of more than 256 sites, or more than 48 candidate bisectors);
+ * counts[1] the cells listed for the float64 large-capacity path. A deferred cell takes
+ * the crowded pass (candidates from the overlap of cell boxes) when the call expects
+ * crowded cells -- a site grid refined below 2 r_max because a few balls are much larger
+ * than the spacing, or cells deferred earlier in the call or in the context's last call
+ * -- and the float64 pass otherwise (same cells, slower); counts[2] is 1 if the crowded
+ * pass ran. Diagnostic.
+ *   out: counts [3] HOST array. Synchronises the stream.
  * Errors: EINVAL (null pointer or nothing evaluated yet), EHIP. */
 int lagot_last_pass_counts(lagot_ctx *ctx, int64_t *counts);
 

@@ -436,13 +436,13 @@ class Context:
                 "float64_reasons": {k: int(buf[8 + i]) for i, k in enumerate(self.FLAG_NAMES)}}
 
     def last_pass_counts(self) -> dict:
-        """lagot_last_pass_counts: cells of the last evaluation that took the crowded pass
-        and the float64 pass."""
-        buf = (ctypes.c_int64 * 2)()
+        """lagot_last_pass_counts: cells of the last evaluation deferred as crowded, cells
+        listed for the float64 pass, and whether the crowded pass ran."""
+        buf = (ctypes.c_int64 * 3)()
         rc = load().lagot_last_pass_counts(self._h, ctypes.cast(buf, ctypes.c_void_p))
         if rc != OK:
             raise LagotError(rc, "lagot_last_pass_counts")
-        return {"crowded": int(buf[0]), "float64": int(buf[1])}
+        return {"crowded": int(buf[0]), "float64": int(buf[1]), "crowded_pass": bool(buf[2])}
 
     def last_cell_kernel_ms(self) -> float:
         return float(load().lagot_last_cell_kernel_ms(self._h))

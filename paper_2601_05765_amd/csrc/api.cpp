@@ -89,6 +89,10 @@ struct lagot_ctx {
     int32_t *qcount = nullptr, *qstart = nullptr, *qcursor = nullptr, *qtmp = nullptr;  // bucket arrays
     GridDesc *qgrid = nullptr;              // [B]
     int nq = 0, cap_nq = 0;
+    // crowded pass on for this call: some site grid was capped by the spacing (a few large
+    // balls), or an evaluation of this call or of the last one deferred cells
+    bool crowd = false, crowd_seen = false;
+    bool eval_crowd = false;  // the crowded pass ran in the last evaluation
     // evaluation outputs (grid order)
     double *V = nullptr, *K = nullptr;
     float *wall = nullptr;
@@ -124,6 +128,7 @@ struct lagot_ctx {
     double *cg_vec = nullptr;   // rws[2] (4 doubles per row each), p, x: 10 doubles per row
     double *cg_part = nullptr;  // 7 * 4 * cap_T
     double *cg_cgs = nullptr;   // 4 * cap_B
+    double *cg_sc = nullptr;    // 8 * cap_B
     int32_t *cg_cgst = nullptr; // 4 * cap_B
     // pinned host staging (uploads) and read-back
     char *h_stage = nullptr;
@@ -191,7 +196,7 @@ void free_sites(lagot_ctx *c) {
 void free_inst(lagot_ctx *c) {
     free_ptrs(c->off, c->tile_inst, c->tile_row, c->first_tile, c->grid, c->box, c->rmax, c->phase, c->ctl, c->ev,
               c->ev2, c->ev_nu, c->part_ev, c->fb_inst, c->fail_inst, c->bad_inst, c->herr, c->cg_part, c->cg_cgs,
-              c->cg_cgst, c->qgrid);
+              c->cg_cgst, c->qgrid, c->cg_sc);
 }
 
 void free_alt(lagot_ctx *c) {
@@ -325,6 +330,7 @@ int ensure_inst(lagot_ctx *c, int B, int T) {
     HIP_TRY(dalloc(&c->herr, b));
     HIP_TRY(dalloc(&c->cg_part, 7 * 4 * t));  // per quarter tile
     HIP_TRY(dalloc(&c->cg_cgs, 4 * b));
+    HIP_TRY(dalloc(&c->cg_sc, 8 * b));
     HIP_TRY(dalloc(&c->cg_cgst, 4 * b));
     HIP_TRY(dalloc(&c->qgrid, (size_t)QLEV * b));
     c->cap_B = B;
@@ -409,6 +415,7 @@ CgBufs cg_bufs(const lagot_ctx *c) {
     g.x = c->cg_vec + 9 * N;
     g.part = c->cg_part;
     g.cgs = c->cg_cgs;
+    g.sc = c->cg_sc;
     g.cgst = c->cg_cgst;
     g.kbase = c->misc + 2;
     g.remaining = c->misc + 3;
@@ -507,6 +514,7 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     c->h_grid.resize(B);
     std::vector<GridDesc> qg((size_t)B * QLEV);
     int64_t total = 0, qtotal = 0;
+    bool capped = false;
     auto make_grid = [](const lagot_box &bx, double s, int maxdim, int64_t base, GridDesc *g) {
         int dim[3];
         for (;;) {
@@ -539,6 +547,7 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
         const double hsp = std::cbrt((nu ? r_nu[4 * b] : box_volume(bx)) / nb);
         double s = std::min(2.0 * r_rmax[b], 1.5 * std::cbrt(box_volume(bx) / nb));
         s = std::max(s, ext / 512.0);
+        capped = capped || s < 2.0 * r_rmax[b];
         GridDesc g;
         make_grid(bx, s, 512, total, &g);
         g.hsp = (float)hsp;
@@ -556,6 +565,8 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     }
     c->ncell_total = (int)total;
     c->nq = (int)qtotal;
+    c->crowd = c->crowd_seen || capped;
+    c->crowd_seen = false;
     rc = ensure_cells(c, c->ncell_total);
     if (!rc) rc = ensure_buckets(c, c->nq);
     if (rc) return rc;
@@ -603,10 +614,11 @@ void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double
                              c->stream);
     if (timed) (void)hipEventRecord(c->ev0, c->stream);
     const QBoxes qb = qboxes(c);
-    launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->tpc);
+    c->eval_crowd = c->crowd;
+    launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->tpc, c->crowd);
     if (timed) (void)hipEventRecord(c->ev1, c->stream);
     if (!c->capturing) c->ev_pending = true;
-    launch_cells_fallback(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb);
+    launch_cells_fallback(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->crowd);
     if (ev_out) launch_eval_reduce(c->stream, bt, want, c->V, c->nu_s, c->part_ev, ev_out);
 }
 
@@ -623,10 +635,27 @@ int flag_hist(lagot_ctx *c, int64_t *counts) {
     return LAGOT_OK;
 }
 
-// Phase histogram written by the last control kernel -> h_cnt[0..7].
+void drop_graphs(lagot_ctx *c);
+
+// After a synchronisation: cells deferred by the last evaluation turn the crowded pass on
+// for the rest of the call and for the next call (graphs captured without it are dropped).
+void note_deferred(lagot_ctx *c, int32_t deferred) {
+    if (deferred <= 0) return;
+    c->crowd_seen = true;
+    if (!c->crowd) {
+        c->crowd = true;
+        drop_graphs(c);
+    }
+}
+
+// Phase histogram written by the last control kernel -> h_cnt[0..7]; the cells the last
+// evaluation deferred -> h_cnt[9].
 int read_counts(lagot_ctx *c) {
     HIP_TRY(hipMemcpyAsync(c->h_cnt, c->counts, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    return sync(c);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 9, c->misc + 4, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    const int rc = sync(c);
+    if (!rc) note_deferred(c, c->h_cnt[9]);
+    return rc;
 }
 
 // ---- learned warm start ------------------------------------------------------
@@ -821,15 +850,20 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
     const CgBufs cg = cg_bufs(c);
     hipStream_t st = c->stream;
     if (with_init)
+    {
         launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hrow, c->hent, cg);
+        launch_cg_scalars(st, bt, c->cg_sub, -1, o.cg_max_iter, cg);
+    }
     const double rtol2 = o.cg_rtol * o.cg_rtol;
     const int cap = o.cg_max_iter;
     int k = 0;
     while (k < cap) {
         const int m = std::min(c->cg_chunk, cap - k);
         auto chunk = [&]() {
-            for (int q = 0; q < m; ++q)
+            for (int q = 0; q < m; ++q) {
                 launch_cg_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hrow, c->hent, cg);
+                launch_cg_scalars(c->stream, bt, c->cg_sub, q, cap, cg);
+            }
             launch_cg_advance(c->stream, bt, m, cap, cg);
         };
         if (graph) {
@@ -870,9 +904,11 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o, bool graph) {
                              c->xcnt, c->herr);
         launch_hess_finish(c->stream, bt, PH_ACTIVE, c->psi_s, c->K, c->fcnt, c->xcnt, c->hcnt, c->hcol, c->hval,
                            c->diag, c->hrow, c->hent);
-        if (with_init)
+        if (with_init) {
             launch_cg_init(c->stream, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hrow, c->hent,
                            cg_bufs(c));
+            launch_cg_scalars(c->stream, bt, c->cg_sub, -1, o.cg_max_iter, cg_bufs(c));
+        }
     };
     int k = 0, rc;
     if (c->tune_key < 0) {
@@ -1375,8 +1411,10 @@ int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     HIP_TRY(hipMemcpyAsync(c->h_cnt, c->misc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(c->h_cnt + 2, c->herr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 9, c->misc + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     rc = sync(c);
     if (rc) return rc;
+    note_deferred(c, c->h_cnt[9]);
     c->last_fb = c->h_cnt[0];
     if (c->h_cnt[1] != 0 || c->h_cnt[2] != 0) return LAGOT_ECAPACITY;
     return LAGOT_OK;
@@ -1479,8 +1517,10 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
         launch_scan_i32(st, c->csr_cnt, c->csr_start, (int)n, c->csr_tmp);
         HIP_TRY(hipMemcpyAsync(c->h_cnt + 4, c->csr_start + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     }
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 9, c->misc + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     rc = sync(c);
     if (rc) return rc;
+    note_deferred(c, c->h_cnt[9]);
     c->last_fb = c->h_cnt[0];
     if (c->h_cnt[1] != 0) return LAGOT_ECAPACITY;
     if (csr || nnz_out) {
@@ -1672,6 +1712,7 @@ int lagot_last_pass_counts(lagot_ctx *ctx, int64_t *counts) {
     if (rc) return rc;
     counts[0] = m[4];
     counts[1] = m[0];
+    counts[2] = ctx->eval_crowd ? 1 : 0;
     return LAGOT_OK;
 }
 
@@ -1747,12 +1788,13 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
     if (n > c->cap_fl) {
         free_ptrs(c->fl_buf, c->fl_int);
         c->cap_fl = 0;
-        HIP_TRY(dalloc(&c->fl_buf, 32 * (size_t)n + 21 * (size_t)nb3 + 16));
+        HIP_TRY(dalloc(&c->fl_buf, 32 * (size_t)n + 21 * (size_t)nb3 + 40));
         HIP_TRY(dalloc(&c->fl_int, 16));
         c->cap_fl = n;
     }
     // layout (doubles): records of the two slots [10n each], p [3n], x [3n], b [3n],
-    // centroids [3n], partials [21 nb], scalars [12]; the records come first (16-byte aligned)
+    // centroids [3n], partials [21 nb], step scalars [12], summed partials [24]; the records
+    // come first (16-byte aligned)
     double *fb = c->fl_buf;
     Cg3Bufs g;
     g.rec[0] = reinterpret_cast<Rec3 *>(fb);
@@ -1763,6 +1805,7 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
     double *cen = centroid ? centroid : fb + 29 * n;
     g.part = fb + 32 * n;
     g.cgs = fb + 32 * n + 21 * (int64_t)nb3;
+    g.sc = g.cgs + 12;
     g.st = c->fl_int;
     g.kbase = c->fl_int + 12;
     g.remaining = c->fl_int + 13;
@@ -1798,12 +1841,16 @@ int lagot_fluid_velocity(lagot_ctx *c, int64_t n, const float *x, const float *y
     // the three coordinates in one Jacobi-PCG (x_0 = 0, stop at ||r|| <= cg_rtol ||b||
     // per coordinate), in chunks of launches with a read-back of the count still iterating
     launch_cg3_init(st, n, rp, c->fl_ent, c->diag, b, g);
+    launch_cg3_scalars(st, -1, p.cg_max_iter, g);
     const double rtol2 = p.cg_rtol * p.cg_rtol;
     const int cap = p.cg_max_iter;
     int k = 0;
     while (k < cap) {
         const int m = std::min(c->fl_chunk, cap - k);
-        for (int q = 0; q < m; ++q) launch_cg3_iter(st, n, q, rtol2, cap, rp, c->fl_ent, g);
+        for (int q = 0; q < m; ++q) {
+            launch_cg3_iter(st, n, q, rtol2, cap, rp, c->fl_ent, g);
+            launch_cg3_scalars(st, q, cap, g);
+        }
         launch_cg3_advance(st, m, cap, g);
         k += m;
         HIP_TRY(hipMemcpyAsync(c->h_cnt, c->fl_int, 14 * sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -257,6 +257,8 @@ struct CellArgs {
     int want;                 // evaluate the instances in this phase (< 0: all)
     EvalOut out;
     QBoxes qb;                // cell boxes and their bucket grid (crowded cells)
+    int crowd;                // 1: the crowded pass runs (boxes written); 0: deferred cells go to
+                              // the float64 pass
 };
 
 template <typename R, int G, int CMAX, int PMAX, int VMAX, int MODE, bool MOM>
@@ -1043,7 +1045,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     // float32 rounding (relative to r, and to the coordinates): a box that holds the
     // restricted cell (the exact cell in the fast pass, a superset in the seed pass).
     // Cells that failed get the ball's bounds, empty cells an empty box.
-    if constexpr (MODE == 0 || seed) {
+    if ((MODE == 0 && A.crowd) || seed) {
         R b0x = R(3e38), b0y = R(3e38), b0z = R(3e38), b1x = R(-3e38), b1y = R(-3e38), b1z = R(-3e38);
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -1080,7 +1082,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             A.qb.box[2 * cell] = lo;
             A.qb.box[2 * cell + 1] = hi;
         }
-        if constexpr (seed) return;
+        if (seed) return;
     }
 
     // ---------------- restriction to the ball and integration ----------------
@@ -1262,7 +1264,10 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
     if (!act) return;
     const EvalOut &o = A.out;
     if (deferred) {
-        if (gl == 0) o.ovf_list[atomicAdd(o.ovf_count, 1)] = (int32_t)cell;
+        if (gl == 0) {
+            o.ovf_list[atomicAdd(o.ovf_count, 1)] = (int32_t)cell;
+            o.flags[cell] = CF_CAND;  // the reason, kept by a float64 pass
+        }
         return;
     }
     int nf = 0;
@@ -1452,11 +1457,14 @@ __global__ __launch_bounds__(64) void k_cells_overflow(CellArgs A) {
     }
 }
 
+// The float64 large-capacity pass: the cells the earlier passes listed, and, when the
+// crowded pass is off, the cells the fast pass deferred.
 __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
     __shared__ CellSmem<double, BIG_CMAX, BIG_PMAX, BIG_VMAX> smem[1];
     const int count = *A.out.fb_count;
-    for (int k = blockIdx.x; k < count; k += gridDim.x) {
-        const int64_t cell = A.out.fb_list[k];
+    const int total = count + (A.crowd ? 0 : *A.out.ovf_count);
+    for (int k = blockIdx.x; k < total; k += gridDim.x) {
+        const int64_t cell = k < count ? A.out.fb_list[k] : A.out.ovf_list[k - count];
         cell_body<double, 64, BIG_CMAX, BIG_PMAX, BIG_VMAX, 2, true>(cell, A, smem[0]);
         __syncthreads();
     }
@@ -1480,8 +1488,8 @@ void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out) {
 }
 
 void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s, const double *psi,
-                  const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb, int tpc) {
-    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb};
+                  const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb, int tpc, bool crowd) {
+    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb, crowd ? 1 : 0};
     if (out.cen) {  // centroids: one instantiation (32 lanes per cell)
         hipLaunchKernelGGL((k_cells_fast<32, true>), dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, a);
     } else if (tpc == 8) {
@@ -1500,8 +1508,12 @@ void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const fl
 // list lengths on the device (no host synchronisation).
 void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                            const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
-                           const QBoxes &qb) {
-    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb};
+                           const QBoxes &qb, bool crowd) {
+    CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb, crowd ? 1 : 0};
+    if (!crowd) {
+        hipLaunchKernelGGL(k_cells_big, dim3(2048), dim3(64), 0, st, a);
+        return;
+    }
     hipLaunchKernelGGL(k_cells_seed, dim3(4096), dim3(64), 0, st, a);
     const unsigned nb = (unsigned)((n + 255) / 256);
     const unsigned nz = (unsigned)((qb.nq + 256) / 256);

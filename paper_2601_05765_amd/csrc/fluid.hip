@@ -253,15 +253,10 @@ __global__ __launch_bounds__(C3B) void k_cg3_iter(int64_t n, int m, double rtol2
     const int64_t row = (int64_t)blk * C3S + (int)(threadIdx.x / C3L);
     const int l = threadIdx.x & (C3L - 1);
     const bool has = row < n;
-    // scalars of iteration k from the partials of every block, in a fixed order
-    double S[12] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t = (int)threadIdx.x; t < g.nb; t += C3B) {
+    // scalars of iteration k, summed once from every block's partials by k_cg3_scalars
+    double S[12];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) S[q] += P3(g, cur, q)[t];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) S[9 + q] += P3_RHO0(g, q)[t];
-    }
-    block_sums<12>(S, sh);
+    for (int q = 0; q < 12; ++q) S[q] = g.sc[12 * cur + q];
     const bool lead = blk == 0 && threadIdx.x == 0;
     double alpha[3] = {0.0, 0.0, 0.0}, beta[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -348,6 +343,29 @@ __global__ __launch_bounds__(C3B) void k_cg3_iter(int64_t n, int m, double rtol2
         for (int q = 0; q < 9; ++q) P3(g, nxt, q)[blk] = part[q];
 }
 
+// The scalars of the next iteration: the partials of the slot just written, summed once
+// in a fixed order (deterministic) by one block, instead of by every block of the next
+// iteration (quadratic in the number of blocks).
+__global__ __launch_bounds__(C3B) void k_cg3_scalars(int m, int cap, Cg3Bufs g) {
+    __shared__ double sh[C3B / 64][12];
+    int slot = 0;
+    if (m >= 0) {
+        const int k = *g.kbase + m;
+        if (k >= cap) return;
+        slot = (k + 1) & 1;
+    }
+    double S[12] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = (int)threadIdx.x; t < g.nb; t += C3B) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) S[q] += P3(g, slot, q)[t];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S[9 + q] += P3_RHO0(g, q)[t];
+    }
+    block_sums<12>(S, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 12; ++q) g.sc[12 * slot + q] = S[q];
+}
+
 // After a chunk: advance kbase; count the coordinates still iterating.
 __global__ void k_cg3_advance(int chunk, int cap, Cg3Bufs g) {
     if (threadIdx.x != 0) return;
@@ -415,6 +433,10 @@ void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *rp, const int2 *e
 void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *rp, const int2 *ent,
                      const Cg3Bufs &g) {
     hipLaunchKernelGGL(k_cg3_iter, dim3(cg3_blocks(n)), dim3(C3B), 0, st, n, m, rtol2, cap, rp, ent, g);
+}
+
+void launch_cg3_scalars(hipStream_t st, int m, int cap, const Cg3Bufs &g) {
+    hipLaunchKernelGGL(k_cg3_scalars, dim3(1), dim3(C3B), 0, st, m, cap, g);
 }
 
 void launch_cg3_advance(hipStream_t st, int chunk, int cap, const Cg3Bufs &g) {

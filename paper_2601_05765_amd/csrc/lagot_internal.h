@@ -205,6 +205,7 @@ struct CgBufs {
     double *part;            // partials per quarter tile (NS = 4T): gamma[2][NS], delta[2][NS],
                              // rho[2][NS], rho0[NS]
     double *cgs;             // [B][4] alpha and gamma of iterations k%2 = 0, 1
+    double *sc;              // [B][2][4] gamma, delta, rho, rho0 summed from the partials of slot 0, 1
     int32_t *cgst;           // [B][4] iterations done, breakdown, converged, unused
     int32_t *kbase;          // [1] index of the first iteration of the next chunk
     int32_t *remaining;      // [1] instances still iterating after the last chunk
@@ -235,6 +236,7 @@ struct Cg3Bufs {
     double *p, *x;       // [3n] row-major (x: the solution)
     double *part;        // [21 nb]: per slot gamma[3], delta[3], rho[3] per block, then rho0[3]
     double *cgs;         // [2][3][2]: alpha and gamma per slot and coordinate
+    double *sc;          // [2][12]: gamma[3], delta[3], rho[3], rho0[3] summed from the partials of a slot
     int32_t *st;         // [3][4]: iterations, breakdown, converged, unused
     int32_t *kbase;      // index of the first iteration of the next chunk
     int32_t *remaining;  // coordinates still iterating after the last chunk
@@ -277,12 +279,15 @@ void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double
 // Cells of the selected instances at the float64 weights psi (float32 shadow in pos_s.w).
 void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out);
 void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s, const double *psi,
-                  const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb, int tpc);
+                  const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb, int tpc,
+                  bool crowd);
 // The passes after the fast one: the crowded cells it deferred (seed boxes, box grid,
 // box-overlap candidates, float64), then the cells flagged for the float64 pass.
+// crowd = false (no crowded cell expected): the fast pass writes no boxes and the float64
+// pass takes the deferred cells too.
 void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                            const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
-                           const QBoxes &qb);
+                           const QBoxes &qb, bool crowd);
 
 // newton.hip
 // ev[4b..4b+3] = sum V, max |V - nu| / nu, ||nu - V||_2, min V of every selected instance
@@ -305,6 +310,9 @@ void launch_cg_init(hipStream_t st, const Batch &bt, int lanes, int sub, const d
 void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
                     const int2 *hrow, const int2 *ent, CgBufs cg);
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg);
+// The scalars of the next PCG iteration from the partials just written (after launch_cg_init:
+// m = -1; after launch_cg_iter with m: the same m), one block per instance
+void launch_cg_scalars(hipStream_t st, const Batch &bt, int sub, int m, int cap, CgBufs cg);
 void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, CgBufs cg, const int32_t *herr,
                       InstCtl *ctl, int32_t *phase);
 void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase);
@@ -348,6 +356,8 @@ void launch_cg3_init(hipStream_t st, int64_t n, const int32_t *rp, const int2 *e
 void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, const int32_t *rp, const int2 *ent,
                      const Cg3Bufs &g);
 void launch_cg3_advance(hipStream_t st, int chunk, int cap, const Cg3Bufs &g);
+// the scalars of the next iteration from the partials just written (m = -1 after init)
+void launch_cg3_scalars(hipStream_t st, int m, int cap, const Cg3Bufs &g);
 // out[3 perm[i] + q] = x[3 i + q]
 void launch_scatter3(hipStream_t st, int64_t n, const int32_t *perm, const double *x, double *out);
 // x += dt v, clamped into the box and the domain planes (see k_advect)

@@ -400,7 +400,7 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
     const int4 st4 = *reinterpret_cast<const int4 *>(st);
     if (bt.phase[b] != PH_ACTIVE || st4.y != 0 || st4.z != 0 || k >= cap) return;
     const int NS = SPT * bt.T;
-    const int t0 = SPT * bt.first_tile[b], t1 = SPT * bt.first_tile[b + 1];
+    const int t0 = SPT * bt.first_tile[b];
     const int end = bt.off[b + 1];
     const int cur = k & 1, nxt = cur ^ 1;
     const double2 prev = *reinterpret_cast<const double2 *>(cg.cgs + 4 * b + 2 * nxt);  // alpha, gamma of k-1
@@ -434,9 +434,10 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
         }
     }
     const double d = own.d, rk = own.r, wk = own.w, sk_1 = own.s;
-    double S[4];
-    sum_range(P_GAM(cg, NS, cur), P_DEL(cg, NS, cur), P_RHO(cg, NS, cur), P_RHO0(cg, NS), t0, t1, S, sh);
-    const double gam = S[0], del = S[1], rho = S[2], rho0 = S[3];
+    // the iteration's scalars, summed once per iteration by k_cg_scalars
+    const double2 s01 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur);
+    const double2 s23 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur + 2);
+    const double gam = s01.x, del = s01.y, rho = s23.x, rho0 = s23.y;
     const bool lead = q == t0 && threadIdx.x == 0;
     if (rho <= rtol2 * rho0) {
         if (lead) {
@@ -502,6 +503,29 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
         P_DEL(cg, NS, nxt)[q] = dp;
         P_RHO(cg, NS, nxt)[q] = rp;
     }
+}
+
+// The scalars gamma, delta, rho (and rho0) of the next iteration: the instance's sub-tile
+// partials of the slot just written, summed once, in a fixed order (deterministic), by
+// one block per instance, instead of by every block of the next iteration (which made
+// the reduction quadratic in the number of tiles).
+__global__ __launch_bounds__(RB) void k_cg_scalars(Batch bt, int spt, int m, int cap, CgBufs cg) {
+    __shared__ double sh[RB / 64][4];
+    const int b = blockIdx.x;
+    if (bt.phase[b] != PH_ACTIVE) return;
+    int slot = 0;
+    if (m >= 0) {
+        const int32_t *st = cg.cgst + 4 * b;
+        const int k = *cg.kbase + m;
+        if (st[1] != 0 || st[2] != 0 || k >= cap) return;  // iteration k wrote no partials
+        slot = (k + 1) & 1;
+    }
+    const int NS = spt * bt.T;
+    double S[4];
+    sum_range(P_GAM(cg, NS, slot), P_DEL(cg, NS, slot), P_RHO(cg, NS, slot), P_RHO0(cg, NS),
+              spt * bt.first_tile[b], spt * bt.first_tile[b + 1], S, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) cg.sc[8 * b + 4 * slot + q] = S[q];
 }
 
 // After a chunk: advance kbase; count instances still iterating.
@@ -796,6 +820,10 @@ void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, 
     if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_iter<L, S>), grid, block, 0, st, bt, m, rtol2, cap, hrow, ent, cg); return; }
     LAGOT_CG_SHAPES(X)
 #undef X
+}
+
+void launch_cg_scalars(hipStream_t st, const Batch &bt, int sub, int m, int cap, CgBufs cg) {
+    hipLaunchKernelGGL(k_cg_scalars, dim3(bt.B), dim3(RB), 0, st, bt, TILE / sub, m, cap, cg);
 }
 
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg) {
