@@ -92,6 +92,10 @@ struct lagot_ctx {
     // crowded pass on for this call: some site grid was capped by the spacing (a few large
     // balls), or an evaluation of this call or of the last one deferred cells
     bool crowd = false, crowd_seen = false;
+    // local reach (crowded calls): coarse grids, largest radius per coarse cell, spread bound
+    GridDesc *cgrid = nullptr;              // [B]
+    uint32_t *lr_rmc = nullptr, *lr_ir = nullptr;
+    int nc = 0, cap_nc = 0;
     bool eval_crowd = false;  // the crowded pass ran in the last evaluation
     // evaluation outputs (grid order)
     double *V = nullptr, *K = nullptr;
@@ -196,7 +200,7 @@ void free_sites(lagot_ctx *c) {
 void free_inst(lagot_ctx *c) {
     free_ptrs(c->off, c->tile_inst, c->tile_row, c->first_tile, c->grid, c->box, c->rmax, c->phase, c->ctl, c->ev,
               c->ev2, c->ev_nu, c->part_ev, c->fb_inst, c->fail_inst, c->bad_inst, c->herr, c->cg_part, c->cg_cgs,
-              c->cg_cgst, c->qgrid, c->cg_sc);
+              c->cg_cgst, c->qgrid, c->cg_sc, c->cgrid);
 }
 
 void free_alt(lagot_ctx *c) {
@@ -236,8 +240,9 @@ void free_all(lagot_ctx *c) {
     free_sites(c);
     free_inst(c);
     free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int, c->fl_ent,
-              c->hent, c->qcount, c->qstart, c->qcursor, c->qtmp, c->cont_buf);
+              c->hent, c->qcount, c->qstart, c->qcursor, c->qtmp, c->cont_buf, c->lr_rmc, c->lr_ir);
     c->cap_cont = 0;
+    c->cap_nc = 0;
     c->cap_nq = 0;
     c->cap_ent = 0;
     c->cap_hent_T = 0;
@@ -333,6 +338,7 @@ int ensure_inst(lagot_ctx *c, int B, int T) {
     HIP_TRY(dalloc(&c->cg_sc, 8 * b));
     HIP_TRY(dalloc(&c->cg_cgst, 4 * b));
     HIP_TRY(dalloc(&c->qgrid, (size_t)QLEV * b));
+    HIP_TRY(dalloc(&c->cgrid, b));
     c->cap_B = B;
     c->cap_T = T;
     return LAGOT_OK;
@@ -347,6 +353,16 @@ int ensure_cells(lagot_ctx *c, int ncell) {
     HIP_TRY(dalloc(&c->cursor, (size_t)ncell + 1));
     HIP_TRY(dalloc(&c->scan_tmp, (size_t)ncell / 1024 + 16));
     c->cap_cells = ncell;
+    return LAGOT_OK;
+}
+
+int ensure_coarse(lagot_ctx *c, int nc) {
+    if (nc <= c->cap_nc) return LAGOT_OK;
+    free_ptrs(c->lr_rmc, c->lr_ir);
+    c->cap_nc = 0;
+    HIP_TRY(dalloc(&c->lr_rmc, (size_t)nc));
+    HIP_TRY(dalloc(&c->lr_ir, (size_t)nc));
+    c->cap_nc = nc;
     return LAGOT_OK;
 }
 
@@ -404,6 +420,8 @@ Batch batch(const lagot_ctx *c) {
     b.phase = c->phase;
     b.dom = c->dom_d;
     b.ndom = c->ndom;
+    b.cgrid = c->cgrid;
+    b.ir = c->crowd ? reinterpret_cast<const float *>(c->lr_ir) : nullptr;
     return b;
 }
 
@@ -445,7 +463,7 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     c->n = n;
     // tile table, boxes and (below) grids, staged in pinned memory
     const size_t stage = sizeof(int32_t) * (2 * (size_t)(B + 1) + 2 * (size_t)T) + sizeof(BoxF) * B +
-                         (1 + QLEV) * sizeof(GridDesc) * B + 64;
+                         (2 + QLEV) * sizeof(GridDesc) * B + 64;
     rc = ensure_pinned(&c->h_stage, &c->cap_stage, stage);
     if (rc) return rc;
     int32_t *h_off = (int32_t *)c->h_stage;
@@ -512,8 +530,8 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     // seed radius of crowded cells and the box grids: QLEV levels of buckets 1.2 h 4^l,
     // at most 1024 buckets per axis and 2^24 per level.
     c->h_grid.resize(B);
-    std::vector<GridDesc> qg((size_t)B * QLEV);
-    int64_t total = 0, qtotal = 0;
+    std::vector<GridDesc> qg((size_t)B * QLEV), cgv(B);
+    int64_t total = 0, qtotal = 0, ctotal = 0;
     bool capped = false;
     auto make_grid = [](const lagot_box &bx, double s, int maxdim, int64_t base, GridDesc *g) {
         int dim[3];
@@ -554,6 +572,8 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
         total += g.ncell;
         if (total > ((int64_t)1 << 28)) return LAGOT_ECAPACITY;
         c->h_grid[b] = g;
+        make_grid(bx, 4.0 * (double)g.s, 256, ctotal, &cgv[b]);  // coarse grid of the local reach
+        ctotal += cgv[b].ncell;
         double sq = std::max(1.2 * hsp, ext / 1024.0);
         for (int l = 0; l < QLEV; ++l, sq *= 4.0) {
             GridDesc &q = qg[(size_t)b * QLEV + l];
@@ -565,15 +585,19 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     }
     c->ncell_total = (int)total;
     c->nq = (int)qtotal;
+    c->nc = (int)ctotal;
     c->crowd = c->crowd_seen || capped;
     c->crowd_seen = false;
     rc = ensure_cells(c, c->ncell_total);
     if (!rc) rc = ensure_buckets(c, c->nq);
+    if (!rc) rc = ensure_coarse(c, c->nc);
     if (rc) return rc;
     std::memcpy(h_g, c->h_grid.data(), sizeof(GridDesc) * B);
     std::memcpy(h_g + B, qg.data(), sizeof(GridDesc) * B * QLEV);
     HIP_TRY(hipMemcpyAsync(c->grid, h_g, sizeof(GridDesc) * B, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->qgrid, h_g + B, sizeof(GridDesc) * B * QLEV, hipMemcpyHostToDevice, st));
+    std::memcpy(h_g + B + (size_t)B * QLEV, cgv.data(), sizeof(GridDesc) * B);
+    HIP_TRY(hipMemcpyAsync(c->cgrid, h_g + B + (size_t)B * QLEV, sizeof(GridDesc) * B, hipMemcpyHostToDevice, st));
     launch_grid_build(st, n, bt, c->ncell_total, c->pos_orig, c->keys, c->cell_count, c->cell_start, c->scan_tmp,
                       c->perm, c->cursor);
     launch_permute_in(st, n, c->perm, c->pos_orig, psi, nu, c->pos_s, c->psi_s, nu ? c->nu_s : nullptr);
@@ -612,9 +636,10 @@ void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double
     if (walls)
         (void)hipMemsetAsync(c->wall, 0, (size_t)(c->ndom > 0 ? c->ndom : 6) * sizeof(float) * (size_t)c->n,
                              c->stream);
-    if (timed) (void)hipEventRecord(c->ev0, c->stream);
     const QBoxes qb = qboxes(c);
     c->eval_crowd = c->crowd;
+    if (c->crowd) launch_local_reach(c->stream, c->n, bt, want, c->nc, c->pos_s, c->lr_rmc, c->lr_ir);
+    if (timed) (void)hipEventRecord(c->ev0, c->stream);
     launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->tpc, c->crowd);
     if (timed) (void)hipEventRecord(c->ev1, c->stream);
     if (!c->capturing) c->ev_pending = true;

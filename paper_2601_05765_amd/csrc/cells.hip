@@ -345,9 +345,18 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 hi3[a] = min((int)floorf((pp[a] + reach - gd.lo[a]) * gd.inv_s), gd.dim[a] - 1);
             }
         } else {
-            // every site whose ball can meet this one: within r + r_max
+            // every site whose ball can meet this one: within r + r_max, or r + max(r, local
+            // bound of the larger balls) when the local reach is known
             gd = A.bt.grid[inst];
-            const float reach = ((float)r + (float)A.bt.rmax[inst]) * 1.0001f;
+            float rj = (float)A.bt.rmax[inst];
+            if (A.bt.ir) {
+                const GridDesc cg = A.bt.cgrid[inst];
+                int k3[3];
+                for (int a = 0; a < 3; ++a)
+                    k3[a] = min(max((int)floorf((pp[a] - cg.lo[a]) * cg.inv_s), 0), cg.dim[a] - 1);
+                rj = fmaxf((float)r, A.bt.ir[cg.base + (k3[0] * cg.dim[1] + k3[1]) * cg.dim[2] + k3[2]]);
+            }
+            const float reach = ((float)r + rj) * 1.0001f;
             for (int a = 0; a < 3; ++a) {
                 lo3[a] = max((int)floorf((pp[a] - reach - gd.lo[a]) * gd.inv_s), 0);
                 hi3[a] = min((int)floorf((pp[a] + reach - gd.lo[a]) * gd.inv_s), gd.dim[a] - 1);

@@ -397,9 +397,64 @@ __global__ void k_scatter_rows(int64_t n, int chunks, const int32_t *__restrict_
     dst[(int64_t)perm[k] * chunks + c] = src[k * chunks + c];
 }
 
+// Local reach. A bisector of (i, j) cuts ball i only if d_ij < r_i + r_j. For r_j <= r_i
+// that is within 2 r_i; for r_j > r_i the site p_i lies within 2 r_j of p_j, so the coarse
+// cell of p_i is within 2 r_j of the coarse cell of p_j. Each coarse cell c' therefore
+// spreads the largest radius of its sites, rmc[c'], to every coarse cell within 2 rmc[c'],
+// and the search reach of site i is r_i + max(r_i, ir[coarse cell of p_i]): where a few
+// balls are much larger than the rest, only the sites near them search far. Radii are
+// non-negative floats, ordered like their bit patterns (integer atomic max).
+__global__ void k_lr_zero(int nc, uint32_t *__restrict__ rmc, uint32_t *__restrict__ ir) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nc) {
+        rmc[k] = 0u;
+        ir[k] = 0u;
+    }
+}
+
+__global__ void k_lr_rmax(int64_t n, Batch bt, int want, const float4 *__restrict__ pos, uint32_t *__restrict__ rmc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = bt.inst[i];
+    if (!selected(bt, want, b)) return;
+    const float4 p = pos[i];
+    const float r = p.w > 0.f ? sqrtf(p.w) : 0.f;
+    const GridDesc g = bt.cgrid[b];
+    atomicMax(rmc + g.base + grid_key(g, p.x, p.y, p.z), __float_as_uint(r));
+}
+
+// one thread per coarse cell of the selected instances (instance found by the bases)
+__global__ void k_lr_spread(Batch bt, int want, int nc, const uint32_t *__restrict__ rmc, uint32_t *__restrict__ ir) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const uint32_t rb = rmc[k];
+    if (rb == 0u) return;
+    int lo = 0, hi = bt.B - 1;  // the instance whose coarse grid holds k
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (bt.cgrid[mid].base <= k) lo = mid; else hi = mid - 1;
+    }
+    if (!selected(bt, want, lo)) return;
+    const GridDesc g = bt.cgrid[lo];
+    const int c = k - g.base;
+    const int cz = c % g.dim[2], cy = (c / g.dim[2]) % g.dim[1], cx = c / (g.dim[2] * g.dim[1]);
+    const int m = (int)ceilf(2.0f * __uint_as_float(rb) * g.inv_s * 1.0001f);
+    for (int ix = max(cx - m, 0); ix <= min(cx + m, g.dim[0] - 1); ++ix)
+        for (int iy = max(cy - m, 0); iy <= min(cy + m, g.dim[1] - 1); ++iy)
+            for (int iz = max(cz - m, 0); iz <= min(cz + m, g.dim[2] - 1); ++iz)
+                atomicMax(ir + g.base + (ix * g.dim[1] + iy) * g.dim[2] + iz, rb);
+}
+
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_local_reach(hipStream_t st, int64_t n, const Batch &bt, int want, int nc_total, const float4 *pos_s,
+                        uint32_t *rmc, uint32_t *ir) {
+    hipLaunchKernelGGL(k_lr_zero, dim3(nblocks(nc_total, 256)), dim3(256), 0, st, nc_total, rmc, ir);
+    hipLaunchKernelGGL(k_lr_rmax, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, pos_s, rmc);
+    hipLaunchKernelGGL(k_lr_spread, dim3(nblocks(nc_total, 256)), dim3(256), 0, st, bt, want, nc_total, rmc, ir);
+}
 
 void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *ev_nu, double *psi_s,
                           float4 *pos_s) {

@@ -108,6 +108,10 @@ struct Batch {
     const int32_t *phase;        // [B] Phase
     const float4 *dom;           // [ndom] convex domain planes (unit outward normal, offset c: n.x <= c)
     int ndom;                    // 0: the box walls bound the cells
+    // local reach (null: r_max of the instance bounds every ball): ir[cgrid base + c] bounds
+    // the radius of every ball whose site lies within twice its radius of coarse cell c
+    const GridDesc *cgrid;       // [B] coarse grids (laid end to end)
+    const float *ir;
 };
 
 constexpr int DOM_MAX = 32;      // planes of a convex polyhedral domain
@@ -253,6 +257,11 @@ void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float 
                          const double *psi, float4 *pos_orig);
 // rmax[b] = max sqrt(max(psi, 0)) over the rows of every selected instance
 void launch_rmax(hipStream_t st, const Batch &bt, int want, const double *psi, double *rmax);
+// local reach of the selected instances from the float32 weights in pos_s.w: rmc[c] = the
+// largest ball radius of the sites in coarse cell c, ir[c] = the largest rmc[c'] of the coarse
+// cells c' within 2 rmc[c'] of c (work arrays of nc_total entries; ir as bt.ir)
+void launch_local_reach(hipStream_t st, int64_t n, const Batch &bt, int want, int nc_total, const float4 *pos_s,
+                        uint32_t *rmc, uint32_t *ir);
 void launch_grid_build(hipStream_t st, int64_t n, const Batch &bt, int ncell_total, const float4 *pos_orig,
                        int32_t *keys, int32_t *cell_count, int32_t *cell_start, int32_t *scan_tmp, int32_t *perm,
                        int32_t *cursor);
