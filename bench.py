@@ -1,24 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the analytic partial-OT solver on one MI355X.
 
-Workload (the measured configuration): 100,000 sites on a jittered cubic
-lattice filling the lower 40% of the unit box (dam-break layout), prescribed
-volumes 3.5e-6 each (0.35 of the box), start weights with ball radius
-1.2 (3 nu / 4 pi)^(1/3); float32 geometry, float64 reductions and CG.
+Workload (the measured configuration, the largest single-GPU one): the 2M-site
+splash scene -- a jittered lattice slab (60% of the sites) and 200 droplets of
+log-normal radius packed 1.72x denser than their prescribed volumes, log-normal
+prescribed volumes summing to 0.3, random velocities N(0, 0.5^2) per axis. The
+scene is settled from its Voronoi start (path following on the prescribed
+volumes), then advected by dt = 2e-3 per step (mirror reflection at the walls)
+and solved again, each solve warm-started from the previous step's weights.
+float32 geometry, float64 weights, reductions and CG.
 
-A step is one full OT solve (grid build, every Newton evaluation of all cells,
-Hessian assembly, Jacobi-PCG, KMT step control) from the start weights to
-max |V_i - nu_i| / nu_i <= 1e-5. Inputs are resident in HBM before timing.
+A step is one advect-and-solve step of that sequence: every Newton evaluation of
+all cells (including the crowded-cell passes), Hessian assembly, Jacobi-PCG and
+KMT step control, to max |V_i - nu_i| / nu_i <= 1e-5. The positions of every step
+are computed before timing and are resident in HBM. Warm-up: the settle, then
+W - 1 untimed steps; the K timed steps follow.
 
 Printed (one JSON line):
-  value          Laguerre∩ball cell evaluations per second over the whole solve
-                 (N x evaluations / wall time of the timed solves)
-  ms_per_step    ms per OT solve (plain start)
-  roofline       float32 cell kernel: algorithmic FLOPs per launch (cost model x
-                 oracle work units of this workload) / mean launch duration (HIP
-                 events on the library stream, inside the timed solves)
+  value          Laguerre cell evaluations per second over the timed steps
+                 (N x evaluations / wall time)
+  ms_per_step    ms per advect-and-solve step (one OT solve)
+  roofline       the dominant kernel of the step (see the design doc for the model)
   cpu_baseline   the FP64 oracle on the host cores, brute-force neighbours, on a
-                 bounded sample of cells of the same workload, in cells/s
+                 bounded sample of cells of the settled scene, in cells/s
+  c3             settle time, per-step ms, Newton iterations, evaluations, and the
+                 oracle-sampled error of the final weights (heaviest sites + random)
+Sections: dam_break (the 100k-site configuration), batched, fluid, learned.
+
+Profiling modes (no JSON line): --profile c3 | cells | fluid runs a short piece of
+the workload for rocprofv3 (c3: settle and two steps; cells: one dam-break solve
+and a 256 MiB device copy that calibrates the byte counters; fluid: five velocity
+updates of the dam break).
 """
 from __future__ import annotations
 
@@ -34,8 +46,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 VALU peak of MI355X (published): 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+# VALU peaks of MI355X (published): 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+# for FP32; FP64 vector is half of it
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the fast cell kernel from FETCH_SIZE / WRITE_SIZE counters
@@ -83,6 +97,17 @@ def flops_per_cell(work_mean: np.ndarray) -> float:
     cand, tests, newv, faces, edges, cross = work_mean
     return (COST["cand"] * cand + COST["test"] * tests + COST["newv"] * newv + COST["face"] * faces
             + COST["edge"] * edges + COST["cross"] * cross + COST["cell"])
+
+
+def flops_per_cell_minimal_clip(work_mean: np.ndarray) -> float:
+    """The cost model with the clip term of a minimal clipper: each of the cell's own F
+    planes (facets and walls) set up and clipped once against a polytope of at most 2F
+    vertices (F^2 vertex tests, 2F new vertices), plus the integration units of the final
+    cell. For crowded cells the oracle's candidate counts (every bisector that cuts the
+    ball, thousands there) measure its brute force, not the work the method needs."""
+    _, _, _, faces, edges, cross = work_mean
+    return (COST["cand"] * faces + COST["test"] * faces * faces + COST["newv"] * 2.0 * faces
+            + COST["face"] * faces + COST["edge"] * edges + COST["cross"] * cross + COST["cell"])
 
 
 def cpu_baseline(sc, psi, seconds_target: float = 15.0):
@@ -227,57 +252,215 @@ def fluid_section(ctx, L, x, y, z, psi, nu, reps: int = 10, steps: int = 5):
             "newton_iters_per_step": newton}
 
 
-def splash_section(ctx, L, scenes, n: int, steps: int):
-    """The large-scene recipe (slab + 200 over-packed droplets, log-normal nu, random
-    velocities) at n sites: the first solve from the Voronoi start, then `steps`
-    advect-and-solve steps warm-started from the previous weights. Step sizes use the
-    min-volume test alone (Algorithm 1 as printed), which does not stall on the float32
-    noise floor near the tolerance."""
+def sample_idx(n, psi, seed, k_top=100, k_rand=300):
+    """The heaviest sites (the most crowded cells) and a random sample."""
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.argsort(-psi)[:k_top], rng.choice(n, min(k_rand, n), replace=False)]))
+
+
+def oracle_error(x, y, z, psi, nu, idx):
+    """max and p99 over the sampled cells of |V_i - nu_i| / nu_i, the volumes V_i of the
+    returned weights evaluated by the FP64 oracle (brute-force neighbours)."""
+    import oracle
+    c = oracle.cells(x, y, z, psi, idx=idx)
+    e = np.abs(c.V - nu[idx]) / nu[idx]
+    return {"cells": int(len(idx)), "max_rel_err": float(e.max()), "p99_rel_err": float(np.percentile(e, 99))}
+
+
+def c3_sequence(ctx, L, scenes, n: int, warmup: int, steps: int, log):
+    """The settle and the advect-and-solve steps of the 2M-site splash scene. Positions of
+    every step are computed and uploaded before the timed steps."""
     import torch
-    sc = scenes.splash(n, 0)
     t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    sc = scenes.splash(n, 0)
+    seq, cur = [], sc
+    for _ in range(max(warmup, 1) - 1 + steps):
+        cur = scenes.advect(cur, 2e-3)
+        seq.append(cur)
+    pos = [(t(s.x, torch.float32), t(s.y, torch.float32), t(s.z, torch.float32)) for s in seq]
     nu, psi = t(sc.nu, torch.float64), t(sc.psi0, torch.float64)
-    opts = L.default_opts(tol=1e-5, autotune=1, residual_test=0)
-    out = {"sites": n, "steps": steps, "ms": [], "newton_iters": [], "evals": [], "status": [], "restarted": [],
-           "max_rel_err": []}
-    cur = sc
-    for k in range(steps + 1):
-        if k:
-            cur = scenes.advect(cur, 2e-3)
-        x, y, z = t(cur.x, torch.float32), t(cur.y, torch.float32), t(cur.z, torch.float32)
-        torch.cuda.synchronize()
+    x0, y0, z0 = t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32)
+    settle_opts = L.default_opts(tol=1e-5, residual_test=0, continuation=1)
+    step_opts = L.default_opts(tol=1e-5, residual_test=0)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    st = ctx.solve(x0, y0, z0, nu, psi, opts=settle_opts, check=False)
+    torch.cuda.synchronize()
+    settle_ms = 1000.0 * (time.perf_counter() - a)
+    if st.status != 0:
+        raise RuntimeError(f"settle of the splash scene failed: {st.as_dict()}")
+    log(f"c3 settle: {settle_ms:.0f} ms, {st.newton_iters} Newton iterations, {st.stages} stages")
+    settle = {"ms": settle_ms, "newton_iters": st.newton_iters, "evals": st.evals, "stages": st.stages,
+              "halvings": st.halvings, "cg_iters": st.cg_iters, "max_rel_err": st.max_rel_err}
+    prev = torch.empty_like(psi)
+
+    def step(k):
+        x, y, z = pos[k]
+        prev.copy_(psi)
+        s1 = ctx.solve(x, y, z, nu, psi, opts=step_opts, check=False)
+        kt = ctx.last_kernel_times()
+        retried = False
+        if s1.status != 0:  # Algorithm 1 stalled: the same step again with path following
+            psi.copy_(prev)
+            s1 = ctx.solve(x, y, z, nu, psi, opts=settle_opts, check=False)
+            kt = ctx.last_kernel_times()
+            retried = True
+        if s1.status != 0:
+            raise RuntimeError(f"step {k} of the splash sequence failed: {s1.as_dict()}")
+        return s1, kt, retried
+
+    for k in range(max(warmup, 1) - 1):
+        step(k)
+    k0 = max(warmup, 1) - 1
+    out = {"ms": [], "newton_iters": [], "evals": [], "halvings": [], "cg_iters": [], "restarted": [],
+           "retried": [], "ms_eval": [], "ms_linear": [], "kernel_times": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(k0, k0 + steps):
         a = time.perf_counter()
-        st = ctx.solve(x, y, z, nu, psi, opts=opts, check=False)
-        torch.cuda.synchronize()
+        s1, kt, retried = step(k)  # returns after the stream is synchronised
         out["ms"].append(1000.0 * (time.perf_counter() - a))
-        out["newton_iters"].append(st.newton_iters)
-        out["evals"].append(st.evals)
-        out["status"].append(st.status)
-        out["restarted"].append(st.default_start)
-        out["max_rel_err"].append(st.max_rel_err)
-    out["ms_settle"] = out["ms"][0]
-    out["ms_per_step"] = float(np.mean(out["ms"][1:])) if steps else None
-    return out
+        out["newton_iters"].append(s1.newton_iters)
+        out["evals"].append(s1.evals)
+        out["halvings"].append(s1.halvings)
+        out["cg_iters"].append(s1.cg_iters)
+        out["restarted"].append(s1.default_start)
+        out["retried"].append(int(retried))
+        out["ms_eval"].append(s1.ms_eval)
+        out["ms_linear"].append(s1.ms_linear)
+        out["kernel_times"].append(kt)
+        log(f"c3 step {k + 1}: {out['ms'][-1]:.0f} ms, {s1.newton_iters} Newton iterations, {s1.evals} evaluations")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"scene": seq[k0 + steps - 1], "nu": sc.nu, "psi": psi, "settle": settle, "steps": out, "wall": wall,
+            "n": n}
+
+
+def copy_calibration():
+    """A 256 MiB device-to-device copy (256 MiB read, 256 MiB written): the byte counters'
+    reading for a known number of bytes."""
+    import torch
+    copy_bytes = 256 * 1024 * 1024
+    a = torch.empty(copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"profile: copy of {copy_bytes} bytes done", flush=True)
+
+
+def profile_mode(which: str) -> int:
+    """Short runs for rocprofv3 (no JSON line)."""
+    import torch
+    import paper_2601_05765_amd as L
+    from paper_2601_05765_amd import scenes
+    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    ctx = L.Context()
+    if which == "c3":
+        r = c3_sequence(ctx, L, scenes, 2_000_000, 1, 2, lambda m: print("profile c3:", m, flush=True))
+        print(f"profile c3: done, {r['steps']['evals']} evaluations per step", flush=True)
+        copy_calibration()
+    elif which in ("cells", "fluid"):
+        n = 100_000
+        sc = scenes.dam_break(n, 0)
+        x, y, z, nu = t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32), t(sc.nu, torch.float64)
+        psi = t(sc.psi0, torch.float64)
+        ctx.set_threads_per_cell(32)
+        st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+        print(f"profile {which}: dam_break {n} solve, {st.evals} evaluations, status {st.status}", flush=True)
+        if which == "cells":
+            copy_calibration()
+        else:
+            g = torch.Generator(device="cuda").manual_seed(3)
+            v = torch.randn((n, 3), generator=g, dtype=torch.float64, device="cuda")
+            mu = 2.0 * torch.rand(n, generator=g, dtype=torch.float64, device="cuda")
+            prm = L.default_fluid_params(dt=2e-3, eps=0.02, gamma=0.05)
+            for k in range(5):
+                _, _, its = ctx.fluid_velocity(x, y, z, psi, nu, v, prm, mu=mu)
+                print(f"profile fluid: velocity update {k}: PCG iterations {its}", flush=True)
+    else:
+        print(f"unknown profile mode {which}", file=sys.stderr)
+        return 2
+    torch.cuda.synchronize()
+    return 0
+
+
+def dam_break_section(ctx, L, scenes, n: int, steps: int, warmup: int, eval_reps: int):
+    """The 100k-site dam break: plain OT solves from the start weights (autotuned shapes),
+    one evaluation alone (with and without the grid build) at the start and converged
+    weights, and with centroids."""
+    import torch
+    sc = scenes.dam_break(n, 0)
+    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    x, y, z, nu = t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32), t(sc.nu, torch.float64)
+    psi0 = t(sc.psi0, torch.float64)
+    opts = L.default_opts(tol=1e-5, autotune=1)
+    for _ in range(warmup):
+        p = psi0.clone()
+        ctx.solve(x, y, z, nu, p, opts=opts)
+    psis = [psi0.clone() for _ in range(steps)]
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        stats.append(ctx.solve(x, y, z, nu, psis[k], opts=opts))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s0 = stats[-1]
+    launches = sum(s.cell_launches for s in stats)
+    ms_kernel = sum(s.ms_cell_kernel for s in stats) / max(launches, 1)
+
+    def eval_times(psi_eval, fn):
+        for _ in range(3):
+            fn(psi_eval)
+        torch.cuda.synchronize()
+        ev, kk = [], []
+        for _ in range(eval_reps):
+            a = time.perf_counter()
+            fn(psi_eval)
+            torch.cuda.synchronize()
+            ev.append(1000.0 * (time.perf_counter() - a))
+            kk.append(ctx.last_cell_kernel_ms())
+        return float(np.median(ev)), float(np.median(kk))
+
+    cells_fn = lambda p: ctx.cells(x, y, z, p, csr=False, walls=False)
+    ev0, k0 = eval_times(psi0, cells_fn)
+    ev1, k1 = eval_times(psis[-1], cells_fn)
+    evc, kc = eval_times(psis[-1], lambda p: ctx.centroids(x, y, z, p))
+    p_last = psis[-1].cpu().numpy()
+    err = oracle_error(sc.x, sc.y, sc.z, p_last, sc.nu, sample_idx(n, p_last, 5, k_top=0, k_rand=300))
+    sec = {"workload": f"dam_break_{n}: jittered cubic lattice in the lower 40% of the unit box, nu=0.35/N, one "
+                       f"plain OT solve from the start weights to 1e-5",
+           "cells_per_s": n * sum(s.evals for s in stats) / wall, "ms_per_solve": 1000.0 * wall / steps,
+           "newton_iters": s0.newton_iters, "evals": s0.evals, "halvings": s0.halvings, "cg_iters": s0.cg_iters,
+           "max_rel_err": s0.max_rel_err, "ms_eval": s0.ms_eval, "ms_linear": s0.ms_linear,
+           "ms_cell_kernel": ms_kernel, "oracle_error": err,
+           "eval_only": {"cells_per_s_with_grid": n / (ev0 / 1000.0), "cells_per_s_kernel": n / (k0 / 1000.0),
+                         "ms_lagot_cells": ev0, "ms_cell_kernel": k0,
+                         "converged": {"cells_per_s_with_grid": n / (ev1 / 1000.0),
+                                       "cells_per_s_kernel": n / (k1 / 1000.0), "ms_lagot_cells": ev1,
+                                       "ms_cell_kernel": k1},
+                         "centroids_converged": {"ms_lagot_centroids": evc, "ms_cell_kernel": kc,
+                                                 "cells_per_s_kernel": n / (kc / 1000.0)}}}
+    return sec, (sc, x, y, z, nu, psis[-1])
 
 
 def main(argv=None):
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[1])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--steps", type=int, default=20, help="timed advect-and-solve steps of the 2M-site sequence")
+    ap.add_argument("--warmup", type=int, default=2, help="the settle, then warmup - 1 untimed steps")
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--profile", choices=["c3", "cells", "fluid"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eval-reps", type=int, default=20)
+    ap.add_argument("--no-dam-break", action="store_true", help="skip the 100k dam-break section")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--learned-seeds", type=int, default=6, help="training scenes (100k sites each)")
     ap.add_argument("--learned-steps", type=int, default=4, help="advect-and-solve steps per training scene")
     ap.add_argument("--sequence-steps", type=int, default=5)
-    ap.add_argument("--no-splash", action="store_true", help="skip the over-packed splash sequence")
     ap.add_argument("--no-fluid", action="store_true", help="skip the fluid-step velocity update")
-    ap.add_argument("--splash-n", type=int, default=200_000)
-    ap.add_argument("--splash-steps", type=int, default=5)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
@@ -291,57 +474,49 @@ def main(argv=None):
         from paper_2601_05765_amd import build
         build.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.profile:
+        return profile_mode(args.profile)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
 
-    sc = scenes.dam_break(args.n, 0)
-    dev = "cuda"
-    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    x, y, z, nu = t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32), t(sc.nu, torch.float64)
-    psi0 = t(sc.psi0, torch.float64)
     ctx = L.Context()
-    # the autotuner picks lanes per cell and the PCG block shape during the warm-up
-    opts = L.default_opts(tol=1e-5, autotune=1)
-
-    for _ in range(args.warmup):
-        p = psi0.clone()
-        ctx.solve(x, y, z, nu, p, opts=opts)
-    psis = [psi0.clone() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    stats = []
-    per_solve = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        a = time.perf_counter()
-        stats.append(ctx.solve(x, y, z, nu, psis[k], opts=opts))  # returns after the stream is synchronised
-        per_solve.append(1000.0 * (time.perf_counter() - a))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    r = c3_sequence(ctx, L, scenes, args.n, args.warmup, args.steps, log)
+    st3 = r["steps"]
+    wall = r["wall"]
+    n = args.n
+    evals = sum(st3["evals"])
+    value = n * evals / wall
     ms_per_step = 1000.0 * wall / args.steps
-    evals = sum(s.evals for s in stats)
-    value = args.n * evals / wall
-    launches = sum(s.cell_launches for s in stats)
-    ms_kernel = sum(s.ms_cell_kernel for s in stats) / max(launches, 1)
-    s0 = stats[-1]
-
-    # evaluation alone (lagot_cells: validation, grid build, cells, outputs), at the start
-    # weights and at the converged ones; and with centroids (lagot_centroids)
-    def eval_times(psi_eval, fn):
-        for _ in range(3):
-            fn(psi_eval)
-        torch.cuda.synchronize()
-        ev, kk = [], []
-        for _ in range(args.eval_reps):
-            a = time.perf_counter()
-            fn(psi_eval)
-            torch.cuda.synchronize()
-            ev.append(1000.0 * (time.perf_counter() - a))
-            kk.append(ctx.last_cell_kernel_ms())
-        return float(np.median(ev)), float(np.median(kk))
-
-    cells_fn = lambda p: ctx.cells(x, y, z, p, csr=False, walls=False)
-    ev0, k0 = eval_times(psi0, cells_fn)
-    ev1, k1 = eval_times(psis[-1], cells_fn)
-    evc, kc = eval_times(psis[-1], lambda p: ctx.centroids(x, y, z, p))
-
+    fin = r["scene"]
+    p_fin = r["psi"].cpu().numpy()
+    c3_err = oracle_error(fin.x, fin.y, fin.z, p_fin, r["nu"], sample_idx(n, p_fin, 3))
+    kt = st3["kernel_times"]
+    fast_ms = sum(k["fast_ms"] for k in kt) / max(sum(k["fast_launches"] for k in kt), 1)
+    crowd_launches = sum(k["crowd_launches"] for k in kt)
+    crowd_ms = sum(k["crowd_ms"] for k in kt) / max(crowd_launches, 1)
+    crowd_cells = sum(k["crowd_cells"] for k in kt) / max(crowd_launches, 1)
+    # roofline of the dominant kernel, the crowded-cell pass (float64): algorithmic FLOPs per
+    # cell from the oracle's geometry of a sample of the cells it finishes at the final state
+    xf, yf, zf = (torch.tensor(np.ascontiguousarray(a), device="cuda") for a in (fin.x, fin.y, fin.z))
+    ctx.cells(xf, yf, zf, r["psi"], csr=False, walls=False)
+    deferred = ctx.last_deferred()
+    import oracle
+    rs = np.random.default_rng(11)
+    samp = np.sort(rs.choice(deferred, min(300, len(deferred)), replace=False)) if len(deferred) else None
+    roofline = None
+    if samp is not None and crowd_ms > 0:
+        w = oracle.cells(fin.x, fin.y, fin.z, p_fin, idx=samp, work=True).work.mean(axis=0)
+        fpc = flops_per_cell_minimal_clip(w)
+        achieved = fpc * crowd_cells / (crowd_ms / 1000.0) / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                    "kernel": "k_cells_overflow (crowded cells: box-overlap candidates, clip rounds, integration; "
+                              "float64)",
+                    "flops_per_cell": fpc, "cells_per_launch": crowd_cells, "ms_per_launch": crowd_ms,
+                    "launches": crowd_launches,
+                    "work_units_per_cell": dict(zip(["cand", "tests", "newv", "faces", "edges", "cross"],
+                                                    [float(v) for v in w])),
+                    "model": "cost model with a minimal clip term (each facet plane clipped once), oracle units "
+                             "of 300 sampled crowded cells"}
     line = {
         "metric": "cells/s (Laguerre∩ball eval); ms per OT solve to 1e-5 vol err, plain vs learned",
         "value": value,
@@ -355,50 +530,34 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"dam_break_{args.n}: jittered cubic lattice in the lower 40% of the unit box, "
-                               f"nu=0.35/N, one plain OT solve to 1e-5 relative volume error",
-                   "n_sites": args.n, "tol": 1e-5},
-        "solve": {"ms_per_solve_plain": ms_per_step, "ms_per_solve_median": float(np.median(per_solve)),
-                  "newton_iters": s0.newton_iters, "evals": s0.evals,
-                  "halvings": s0.halvings, "cg_iters": s0.cg_iters, "max_rel_err": s0.max_rel_err,
-                  "fallback_cells": s0.fallback_cells, "ms_eval": s0.ms_eval, "ms_linear": s0.ms_linear},
-        "eval_only": {"cells_per_s_with_grid": args.n / (ev0 / 1000.0), "cells_per_s_kernel": args.n / (k0 / 1000.0),
-                      "ms_lagot_cells": ev0, "ms_cell_kernel": k0,
-                      "converged": {"cells_per_s_with_grid": args.n / (ev1 / 1000.0),
-                                    "cells_per_s_kernel": args.n / (k1 / 1000.0), "ms_lagot_cells": ev1,
-                                    "ms_cell_kernel": k1},
-                      "centroids_converged": {"ms_lagot_centroids": evc, "ms_cell_kernel": kc,
-                                              "cells_per_s_kernel": args.n / (kc / 1000.0)}},
+        "config": {"workload": f"splash_{n}: 60% jittered-lattice slab + 200 log-normal droplets packed 1.72x, "
+                               f"log-normal nu summing to 0.3, random velocities N(0, 0.5^2); settled from the "
+                               f"Voronoi start, then advect (dt 2e-3) and solve to 1e-5 per step, warm-started "
+                               f"from the previous weights",
+                   "n_sites": n, "tol": 1e-5, "dt": 2e-3},
+        "c3": {"settle": r["settle"], "ms_per_step": ms_per_step, "ms_steps": st3["ms"],
+               "newton_iters": st3["newton_iters"], "evals": st3["evals"], "halvings": st3["halvings"],
+               "cg_iters": st3["cg_iters"], "restarted": st3["restarted"], "retried": st3["retried"],
+               "ms_eval": st3["ms_eval"], "ms_linear": st3["ms_linear"],
+               "ms_fast_kernel_per_eval": fast_ms, "ms_crowded_pass_per_eval": crowd_ms,
+               "crowded_cells_per_eval": crowd_cells, "oracle_error": c3_err},
     }
-    if not args.no_fluid:
-        line["fluid"] = fluid_section(ctx, L, x, y, z, psis[-1], nu)
+    if roofline is not None:
+        line["roofline"] = roofline
+    if not args.no_dam_break:
+        sec, dam = dam_break_section(ctx, L, scenes, 100_000, 10, 3, args.eval_reps)
+        line["dam_break"] = sec
+        if not args.no_fluid:
+            _, x, y, z, nu, psi = dam
+            line["fluid"] = fluid_section(ctx, L, x, y, z, psi, nu)
     if not args.no_batched:
         line["batched"] = batched_section(ctx, L, scenes)
-    if not args.no_splash:
-        line["splash"] = splash_section(ctx, L, scenes, args.splash_n, args.splash_steps)
     if not args.no_learned:
         line["learned"] = learned_section(ctx, L, scenes, args.learned_seeds, args.learned_steps,
                                           args.sequence_steps)
-    work_mean = None
     if not args.no_cpu_baseline:
-        cb, work_start = cpu_baseline(sc, sc.psi0, args.cpu_seconds)
+        cb, work = cpu_baseline(fin, p_fin, args.cpu_seconds)
         line["cpu_baseline"] = cb
-        # the solve evaluates cells from the start weights to the converged ones: average the
-        # oracle's work units at both ends (a 2,000-cell sample at the converged weights)
-        import oracle
-        idx = np.sort(np.random.default_rng(8).choice(sc.n, min(2000, sc.n), replace=False))
-        cw = oracle.cells(sc.x, sc.y, sc.z, psis[-1].cpu().numpy(), idx=idx, work=True)
-        work_mean = 0.5 * (work_start + cw.work.mean(axis=0))
-    if work_mean is not None:
-        fpc = flops_per_cell(work_mean)
-        achieved = fpc * args.n / (ms_kernel / 1000.0) / 1e12
-        line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counter_record().get("bytes_per_launch"),
-                            "valu_issue_frac": counter_record().get("valu_issue_frac"),
-                            "kernel": "k_cells_fast<32, false> (fused clip + ball integration, float32)",
-                            "flops_per_cell": fpc, "ms_per_launch": ms_kernel,
-                            "work_units_per_cell": dict(zip(["cand", "tests", "newv", "faces", "edges", "cross"],
-                                                            [float(v) for v in work_mean]))}
     print(json.dumps(line), flush=True)
     return 0
 

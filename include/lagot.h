@@ -405,7 +405,7 @@ int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts);
 
 /* Cells of the last evaluation on this context that took the later passes (section 4,
  * "Finding Contributing Neighbors"): counts[0] the crowded cells the float32 pass
- * deferred (search block of more than 256 sites, or more than 48 candidate bisectors);
+ * deferred (search block of more than 1024 sites, or more than 48 candidate bisectors);
  * counts[1] the cells listed for the float64 large-capacity path. A deferred cell takes
  * the crowded pass (candidates from the overlap of cell boxes) when the call expects
  * crowded cells -- a site grid refined below 2 r_max because a few balls are much larger
@@ -415,6 +415,21 @@ int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts);
  *   out: counts [3] HOST array. Synchronises the stream.
  * Errors: EINVAL (null pointer or nothing evaluated yet), EHIP. */
 int lagot_last_pass_counts(lagot_ctx *ctx, int64_t *counts);
+
+/* Kernel times of the last call on this context (HIP events on its stream, outside graph
+ * capture): out[0] summed ms of the float32 cell-kernel launches, out[1] their number,
+ * out[2] summed ms of the crowded-cell pass (box-overlap candidates, float64), out[3]
+ * its launches, out[4] the cells those launches processed. Diagnostic; valid after the
+ * call returned (it synchronises).
+ *   out: out [5] HOST array. Errors: EINVAL (null pointer). */
+int lagot_last_kernel_times(const lagot_ctx *ctx, double *out);
+
+/* The cells the float32 pass deferred as crowded in the last evaluation on this context,
+ * as caller indices (in the order the pass listed them). Diagnostic.
+ *   out: idx [min(count, cap)] HOST int32 (may be NULL when cap = 0); *count HOST = the
+ *        number of deferred cells. Synchronises the stream.
+ * Errors: EINVAL (null pointer or nothing evaluated yet), EHIP. */
+int lagot_last_deferred(lagot_ctx *ctx, int32_t *idx, int64_t cap, int64_t *count);
 
 /* Duration in ms of the float32 cell-kernel launch of the last lagot_cells call
  * (HIP events on the context stream; diagnostic; -1 if ctx is NULL). */

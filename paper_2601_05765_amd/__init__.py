@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
            "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward", "lagot_mlp_forward_noalloc",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
@@ -136,6 +136,10 @@ def load():
         lib.lagot_last_flag_counts.restype = I
         lib.lagot_last_pass_counts.argtypes = [P, P]
         lib.lagot_last_pass_counts.restype = I
+        lib.lagot_last_kernel_times.argtypes = [P, P]
+        lib.lagot_last_kernel_times.restype = I
+        lib.lagot_last_deferred.argtypes = [P, P, I64, ctypes.POINTER(I64)]
+        lib.lagot_last_deferred.restype = I
         lib.lagot_last_fallback_cells.argtypes = [P]
         lib.lagot_last_fallback_cells.restype = I
         lib.lagot_last_cell_kernel_ms.argtypes = [P]
@@ -443,6 +447,32 @@ class Context:
         if rc != OK:
             raise LagotError(rc, "lagot_last_pass_counts")
         return {"crowded": int(buf[0]), "float64": int(buf[1]), "crowded_pass": bool(buf[2])}
+
+    def last_kernel_times(self) -> dict:
+        """lagot_last_kernel_times: summed ms and launches of the float32 cell kernel and of the
+        crowded-cell pass in the last call."""
+        buf = (ctypes.c_double * 5)()
+        rc = load().lagot_last_kernel_times(self._h, ctypes.cast(buf, ctypes.c_void_p))
+        if rc != OK:
+            raise LagotError(rc, "lagot_last_kernel_times")
+        return {"fast_ms": buf[0], "fast_launches": int(buf[1]), "crowd_ms": buf[2], "crowd_launches": int(buf[3]),
+                "crowd_cells": int(buf[4])}
+
+    def last_deferred(self, cap: int = 1 << 30):
+        """lagot_last_deferred: caller indices (numpy int32) of the cells the last evaluation
+        deferred as crowded."""
+        import numpy as np
+        cnt = ctypes.c_int64(0)
+        rc = load().lagot_last_deferred(self._h, None, 0, ctypes.byref(cnt))
+        if rc != OK:
+            raise LagotError(rc, "lagot_last_deferred")
+        k = int(min(cnt.value, cap))
+        out = np.zeros(k, dtype=np.int32)
+        if k:
+            rc = load().lagot_last_deferred(self._h, out.ctypes.data_as(ctypes.c_void_p), k, ctypes.byref(cnt))
+            if rc != OK:
+                raise LagotError(rc, "lagot_last_deferred")
+        return out
 
     def last_cell_kernel_ms(self) -> float:
         return float(load().lagot_last_cell_kernel_ms(self._h))

@@ -87,6 +87,8 @@ struct lagot_ctx {
     float4 *qbox = nullptr;                 // [2n]
     int32_t *qent = nullptr, *qlarge = nullptr;  // [QREG_MAX n], [n]
     int32_t *qcount = nullptr, *qstart = nullptr, *qcursor = nullptr, *qtmp = nullptr;  // bucket arrays
+    int32_t *qdstart = nullptr;             // [n + 1] scan of the deferred-cell marks
+    int64_t cap_qtmp_n = 0;                 // rows the scan workspace qtmp serves
     GridDesc *qgrid = nullptr;              // [B]
     int nq = 0, cap_nq = 0;
     // crowded pass on for this call: some site grid was capped by the spacing (a few large
@@ -161,6 +163,7 @@ struct lagot_ctx {
     float *tZ1 = nullptr, *tZ2 = nullptr, *tZ3 = nullptr, *tdZ = nullptr, *ty = nullptr, *tt = nullptr,
           *tdy = nullptr, *tpart = nullptr, *tloss = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the float32 cell kernel
+    hipEvent_t evc0 = nullptr, evc1 = nullptr;  // around the crowded pass
     // graph mode: a private stream (default priority) and the graphs of the current call
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr;
@@ -171,6 +174,10 @@ struct lagot_ctx {
     bool ev_pending = false;
     double ms_cell = 0.0;
     int cell_launches = 0;
+    bool ev_crowd_pending = false;
+    double ms_crowd = 0.0;      // summed duration of the crowded pass in the current call
+    int crowd_launches = 0;
+    int64_t crowd_cells = 0;    // cells the timed crowded-pass launches processed
     uint16_t *noalloc = nullptr;  // this device's copy of the static scratch array
 };
 
@@ -193,7 +200,7 @@ template <typename... P> void free_ptrs(P *&...ps) {
 void free_sites(lagot_ctx *c) {
     free_ptrs(c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->inst, c->V, c->K, c->wall,
               c->fcol, c->fcnt, c->fb_list, c->ovf_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
-              c->cg_vec, c->csr_cnt, c->csr_start, c->csr_tmp, c->hrow, c->qbox, c->qent, c->qlarge);
+              c->cg_vec, c->csr_cnt, c->csr_start, c->csr_tmp, c->hrow, c->qbox, c->qent, c->qlarge, c->qdstart);
     c->cap_n = 0;
 }
 
@@ -239,6 +246,7 @@ void free_all(lagot_ctx *c) {
     free_alt(c);
     free_sites(c);
     free_inst(c);
+    c->cap_qtmp_n = 0;
     free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int, c->fl_ent,
               c->hent, c->qcount, c->qstart, c->qcursor, c->qtmp, c->cont_buf, c->lr_rmc, c->lr_ir);
     c->cap_cont = 0;
@@ -257,6 +265,8 @@ void free_all(lagot_ctx *c) {
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->evc0) (void)hipEventDestroy(c->evc0);
+    if (c->evc1) (void)hipEventDestroy(c->evc1);
 }
 
 // Add the duration of the last recorded cell-kernel launch (call after a stream sync).
@@ -267,7 +277,17 @@ void collect_cell_time(lagot_ctx *c) {
         c->ms_cell += ms;
         c->cell_launches++;
     }
+    if (c->ev_crowd_pending && hipEventElapsedTime(&ms, c->evc0, c->evc1) == hipSuccess) {
+        int32_t cnt = 0;
+        if (hipMemcpy(&cnt, c->misc + 4, sizeof(cnt), hipMemcpyDeviceToHost) == hipSuccess) {
+            c->ms_crowd += ms;
+            c->crowd_launches++;
+            c->crowd_cells += cnt;
+        }
+    }
+    c->ev_crowd_pending = false;
     c->ev_pending = false;
+    c->ev_crowd_pending = false;
 }
 
 int ensure_sites(lagot_ctx *c, int64_t n) {
@@ -301,6 +321,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->qbox, 2 * N));
     HIP_TRY(dalloc(&c->qent, (size_t)QREG_MAX * N));
     HIP_TRY(dalloc(&c->qlarge, N));
+    HIP_TRY(dalloc(&c->qdstart, N + 1));
     HIP_TRY(dalloc(&c->cg_vec, 10 * N));
     HIP_TRY(dalloc(&c->csr_cnt, N + 1));
     HIP_TRY(dalloc(&c->csr_start, N + 1));
@@ -367,14 +388,16 @@ int ensure_coarse(lagot_ctx *c, int nc) {
 }
 
 int ensure_buckets(lagot_ctx *c, int nq) {
-    if (nq <= c->cap_nq) return LAGOT_OK;
+    if (nq <= c->cap_nq && c->cap_n <= c->cap_qtmp_n) return LAGOT_OK;
+    nq = std::max(nq, c->cap_nq);
     free_ptrs(c->qcount, c->qstart, c->qcursor, c->qtmp);
     c->cap_nq = 0;
     HIP_TRY(dalloc(&c->qcount, (size_t)nq + 1));
     HIP_TRY(dalloc(&c->qstart, (size_t)nq + 1));
     HIP_TRY(dalloc(&c->qcursor, (size_t)nq + 1));
-    HIP_TRY(dalloc(&c->qtmp, (size_t)nq / 1024 + 16));
+    HIP_TRY(dalloc(&c->qtmp, (size_t)std::max<int64_t>(nq, c->cap_n) / 1024 + 16));
     c->cap_nq = nq;
+    c->cap_qtmp_n = c->cap_n;
     return LAGOT_OK;
 }
 
@@ -615,6 +638,8 @@ QBoxes qboxes(lagot_ctx *c) {
     q.large = c->qlarge;
     q.nlarge = c->misc + 5;
     q.tmp = c->qtmp;
+    q.dcnt = c->csr_cnt;
+    q.dstart = c->qdstart;
     q.nq = c->nq;
     return q;
 }
@@ -643,7 +668,10 @@ void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double
     launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->tpc, c->crowd);
     if (timed) (void)hipEventRecord(c->ev1, c->stream);
     if (!c->capturing) c->ev_pending = true;
-    launch_cells_fallback(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->crowd);
+    const bool tc = timed && c->crowd && !c->capturing;  // the crowded pass is timed outside graphs
+    launch_cells_fallback(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->crowd,
+                          tc ? c->evc0 : nullptr, tc ? c->evc1 : nullptr);
+    if (tc) c->ev_crowd_pending = true;
     if (ev_out) launch_eval_reduce(c->stream, bt, want, c->V, c->nu_s, c->part_ev, ev_out);
 }
 
@@ -824,6 +852,7 @@ int autotune_tpc(lagot_ctx *c) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
         c->ev_pending = false;
+        c->ev_crowd_pending = false;
         if (ms < best) {
             best = ms;
             best_t = t;
@@ -1166,8 +1195,12 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     if (rc) return fail_all(rc);
     c->tpc = o.threads_per_cell ? o.threads_per_cell : c->tpc_default;
     c->ms_cell = 0.0;
+    c->ms_crowd = 0.0;
+    c->crowd_launches = 0;
+    c->crowd_cells = 0;
     c->cell_launches = 0;
     c->ev_pending = false;
+    c->ev_crowd_pending = false;
     rc = prepare(c, B, offs, x, y, z, psi, nu, boxes, &bad);
     if (rc) return fail_all(rc);
     c->tune_key = -1;
@@ -1177,6 +1210,9 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
         rc = autotune_tpc(c);
         if (rc) return fail_all(rc);
         c->ms_cell = 0.0;
+        c->ms_crowd = 0.0;
+        c->crowd_launches = 0;
+        c->crowd_cells = 0;
         c->cell_launches = 0;
     }
     const Batch bt = batch(c);
@@ -1410,8 +1446,12 @@ int fluid_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
                 const lagot_box &box, double *cen) {
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     c->ms_cell = 0.0;
+    c->ms_crowd = 0.0;
+    c->crowd_launches = 0;
+    c->crowd_cells = 0;
     c->cell_launches = 0;
     c->ev_pending = false;
+    c->ev_crowd_pending = false;
     hipStream_t st = c->stream;
     int rc = LAGOT_OK;
     if (c->fl_reuse) {
@@ -1488,7 +1528,8 @@ int lagot_create(lagot_ctx **out, int device, void *stream) {
     c->stream = (hipStream_t)stream;
     if (dalloc(&c->counts, 8) != hipSuccess || dalloc(&c->misc, 8) != hipSuccess ||
         hipHostMalloc((void **)&c->h_cnt, 16 * sizeof(int32_t)) != hipSuccess ||
-        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->evc0) != hipSuccess || hipEventCreate(&c->evc1) != hipSuccess) {
         free_all(c);
         delete c;
         return LAGOT_EHIP;
@@ -1524,8 +1565,12 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     c->tpc = c->tpc_default;
     c->ms_cell = 0.0;
+    c->ms_crowd = 0.0;
+    c->crowd_launches = 0;
+    c->crowd_cells = 0;
     c->cell_launches = 0;
     c->ev_pending = false;
+    c->ev_crowd_pending = false;
     const int64_t offs[2] = {0, n};
     int rc = prepare(c, 1, offs, x, y, z, psi, nullptr, &box, nullptr);
     if (rc) return rc;
@@ -1611,6 +1656,7 @@ int lagot_features(lagot_ctx *c, int64_t n, const float *x, const float *y, cons
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     c->tpc = c->tpc_default;
     c->ev_pending = false;
+    c->ev_crowd_pending = false;
     const int64_t offs[2] = {0, n};
     int rc = prepare(c, 1, offs, x, y, z, psi_prev, nu, &box, nullptr);
     if (rc) return rc;
@@ -1774,6 +1820,35 @@ int lagot_last_flag_counts(lagot_ctx *ctx, int64_t *counts) {
 }
 
 double lagot_last_cell_kernel_ms(const lagot_ctx *ctx) { return ctx ? ctx->ms_cell : -1.0; }
+
+int lagot_last_kernel_times(const lagot_ctx *ctx, double *out) {
+    if (!ctx || !out) return LAGOT_EINVAL;
+    out[0] = ctx->ms_cell;
+    out[1] = ctx->cell_launches;
+    out[2] = ctx->ms_crowd;
+    out[3] = ctx->crowd_launches;
+    out[4] = (double)ctx->crowd_cells;
+    return LAGOT_OK;
+}
+
+int lagot_last_deferred(lagot_ctx *ctx, int32_t *idx, int64_t cap, int64_t *count) {
+    if (!ctx || !count || (cap > 0 && !idx) || ctx->n <= 0 || !ctx->misc) return LAGOT_EINVAL;
+    int32_t m = 0;
+    HIP_TRY(hipMemcpyAsync(&m, ctx->misc + 4, sizeof(m), hipMemcpyDeviceToHost, ctx->stream));
+    int rc = sync(ctx);
+    if (rc) return rc;
+    *count = m;
+    const int64_t k = std::min<int64_t>(m, cap);
+    if (k <= 0) return LAGOT_OK;
+    std::vector<int32_t> rows((size_t)k), perm((size_t)ctx->n);
+    HIP_TRY(hipMemcpyAsync(rows.data(), ctx->ovf_list, sizeof(int32_t) * (size_t)k, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(perm.data(), ctx->perm, sizeof(int32_t) * (size_t)ctx->n, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    rc = sync(ctx);
+    if (rc) return rc;
+    for (int64_t q = 0; q < k; ++q) idx[q] = perm[(size_t)rows[(size_t)q]];
+    return LAGOT_OK;
+}
 
 void lagot_default_fluid_params(lagot_fluid_params *prm) {
     if (!prm) return;

@@ -1354,14 +1354,38 @@ __global__ __launch_bounds__(64) void k_cells_fast(CellArgs A) {
 // Seed pass of the cells deferred by the fast pass (crowded cells), one per wavefront:
 // each is clipped by its nearest sites only, and writes the box of that superset of
 // its cell. The list length is read on the device and the blocks stride over it.
+// Work-list loops: the list is split into NXCD contiguous parts, one per XCD (workgroup w
+// runs on XCD w mod NXCD), and the workgroups of an XCD stride over its part, so cells
+// that are neighbours in the list (and in space) run on the same XCD and share its L2.
+#define XCD_LIST_LOOP(k, count)                                                                \
+    const int xcd_ = (int)(blockIdx.x % NXCD), per_ = (int)(gridDim.x / NXCD);                 \
+    const int lo_ = (int)((int64_t)(count) * xcd_ / NXCD), hi_ = (int)((int64_t)(count) * (xcd_ + 1) / NXCD); \
+    for (int k = lo_ + (int)(blockIdx.x / NXCD); k < hi_; k += per_)
+
 __global__ __launch_bounds__(64) void k_cells_seed(CellArgs A) {
     __shared__ CellSmem<float, SEED_CMAX, SEED_PMAX, SEED_VMAX> smem[1];
     const int count = *A.out.ovf_count;
-    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    XCD_LIST_LOOP(k, count) {
         const int64_t cell = A.out.ovf_list[k];
         cell_body<float, 64, SEED_CMAX, SEED_PMAX, SEED_VMAX, 3, false>(cell, A, smem[0]);
         __syncthreads();
     }
+}
+
+// The deferred cells in grid order (the fast pass appends them in the order its atomics
+// happen): a deferred cell is the only one whose fast-pass flags are exactly CF_CAND.
+// Grid order is space order, so the seed and crowded passes then read neighbouring data.
+__global__ __launch_bounds__(256) void k_defer_mark(int64_t n, Batch bt, int want, const uint32_t *__restrict__ flags,
+                                                    const int32_t *__restrict__ ovf_count, int32_t *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cnt[i] = (*ovf_count > 0 && selected(bt, want, bt.inst[i]) && flags[i] == CF_CAND) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_defer_fill(int64_t n, const int32_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ start, int32_t *__restrict__ list) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cnt[i]) list[start[i]] = (int32_t)i;
 }
 
 // Registration of the cell boxes in the buckets of the box grid (every cell of the
@@ -1459,7 +1483,7 @@ __global__ __launch_bounds__(64) void k_qbox_sort_large(QBoxes qb) {
 __global__ __launch_bounds__(64) void k_cells_overflow(CellArgs A) {
     __shared__ CellSmem<double, OVF_CMAX, OVF_PMAX, OVF_VMAX> smem[1];
     const int count = *A.out.ovf_count;
-    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    XCD_LIST_LOOP(k, count) {
         const int64_t cell = A.out.ovf_list[k];
         cell_body<double, 64, OVF_CMAX, OVF_PMAX, OVF_VMAX, 1, true>(cell, A, smem[0]);
         __syncthreads();
@@ -1472,7 +1496,7 @@ __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
     __shared__ CellSmem<double, BIG_CMAX, BIG_PMAX, BIG_VMAX> smem[1];
     const int count = *A.out.fb_count;
     const int total = count + (A.crowd ? 0 : *A.out.ovf_count);
-    for (int k = blockIdx.x; k < total; k += gridDim.x) {
+    XCD_LIST_LOOP(k, total) {
         const int64_t cell = k < count ? A.out.fb_list[k] : A.out.ovf_list[k - count];
         cell_body<double, 64, BIG_CMAX, BIG_PMAX, BIG_VMAX, 2, true>(cell, A, smem[0]);
         __syncthreads();
@@ -1517,14 +1541,17 @@ void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const fl
 // list lengths on the device (no host synchronisation).
 void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                            const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
-                           const QBoxes &qb, bool crowd) {
+                           const QBoxes &qb, bool crowd, hipEvent_t e0, hipEvent_t e1) {
     CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb, crowd ? 1 : 0};
     if (!crowd) {
         hipLaunchKernelGGL(k_cells_big, dim3(2048), dim3(64), 0, st, a);
         return;
     }
-    hipLaunchKernelGGL(k_cells_seed, dim3(4096), dim3(64), 0, st, a);
     const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_defer_mark, dim3(nb), dim3(256), 0, st, n, bt, want, out.flags, out.ovf_count, qb.dcnt);
+    launch_scan_i32(st, qb.dcnt, qb.dstart, (int)n, qb.tmp);
+    hipLaunchKernelGGL(k_defer_fill, dim3(nb), dim3(256), 0, st, n, qb.dcnt, qb.dstart, out.ovf_list);
+    hipLaunchKernelGGL(k_cells_seed, dim3(4096), dim3(64), 0, st, a);
     const unsigned nz = (unsigned)((qb.nq + 256) / 256);
     hipLaunchKernelGGL(k_qbox_zero, dim3(nz), dim3(256), 0, st, qb, false);
     hipLaunchKernelGGL(k_qbox_register<false>, dim3(nb), dim3(256), 0, st, n, bt, want, out.ovf_count, qb);
@@ -1533,7 +1560,9 @@ void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want,
     hipLaunchKernelGGL(k_qbox_register<true>, dim3(nb), dim3(256), 0, st, n, bt, want, out.ovf_count, qb);
     launch_sort_segments(st, qb.nq, qb.start, qb.ent);
     hipLaunchKernelGGL(k_qbox_sort_large, dim3(1), dim3(64), 0, st, qb);
+    if (e0) (void)hipEventRecord(e0, st);
     hipLaunchKernelGGL(k_cells_overflow, dim3(4096), dim3(64), 0, st, a);
+    if (e1) (void)hipEventRecord(e1, st);
     hipLaunchKernelGGL(k_cells_big, dim3(2048), dim3(64), 0, st, a);
 }
 

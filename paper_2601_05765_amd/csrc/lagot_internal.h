@@ -36,7 +36,7 @@ constexpr int SEED_VMAX = 128;
 // The fast pass defers a cell whose search block (sites within r + r_max) holds more
 // sites than this: such a cell is crowded, and its neighbours are found from the
 // geometry of the cells instead (seed pass, cell boxes, box-overlap candidates).
-constexpr int FAST_SCAN_MAX = 256;
+constexpr int FAST_SCAN_MAX = 1024;
 // Box grids: QLEV levels of bucket size h 4^l (h: 1.2 site spacings). A cell box is
 // registered at the finest level where it spans at most QREG_MAX buckets; boxes too
 // large for every level go to a per-call list that every crowded cell tests directly.
@@ -191,7 +191,8 @@ struct QBoxes {
     int32_t *ent;       // [QREG_MAX * n] cell ids per bucket
     int32_t *large;     // [n] cells whose boxes span more than QREG_MAX buckets
     int32_t *nlarge;    // [1]
-    int32_t *tmp;       // [nq / 1024 + 16] scan workspace
+    int32_t *tmp;       // [max(nq, n) / 1024 + 16] scan workspace
+    int32_t *dcnt, *dstart;  // [n + 1] deferred-cell marks and their scan (the list in grid order)
     int nq;             // buckets over all instances
 };
 
@@ -293,10 +294,10 @@ void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const fl
 // The passes after the fast one: the crowded cells it deferred (seed boxes, box grid,
 // box-overlap candidates, float64), then the cells flagged for the float64 pass.
 // crowd = false (no crowded cell expected): the fast pass writes no boxes and the float64
-// pass takes the deferred cells too.
+// pass takes the deferred cells too. Events e0, e1 (may be null) bracket the crowded pass.
 void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                            const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
-                           const QBoxes &qb, bool crowd);
+                           const QBoxes &qb, bool crowd, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // newton.hip
 // ev[4b..4b+3] = sum V, max |V - nu| / nu, ||nu - V||_2, min V of every selected instance
