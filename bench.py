@@ -313,7 +313,7 @@ def c3_sequence(ctx, L, scenes, n: int, warmup: int, steps: int, log):
         step(k)
     k0 = max(warmup, 1) - 1
     out = {"ms": [], "newton_iters": [], "evals": [], "halvings": [], "cg_iters": [], "restarted": [],
-           "retried": [], "ms_eval": [], "ms_linear": [], "kernel_times": []}
+           "retried": [], "parts": [], "ms_eval": [], "ms_linear": [], "kernel_times": []}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(k0, k0 + steps):
@@ -326,6 +326,7 @@ def c3_sequence(ctx, L, scenes, n: int, warmup: int, steps: int, log):
         out["cg_iters"].append(s1.cg_iters)
         out["restarted"].append(s1.default_start)
         out["retried"].append(int(retried))
+        out["parts"].append(s1.stages)  # continuation stages of a retried step
         out["ms_eval"].append(s1.ms_eval)
         out["ms_linear"].append(s1.ms_linear)
         out["kernel_times"].append(kt)
@@ -538,6 +539,7 @@ def main(argv=None):
         "c3": {"settle": r["settle"], "ms_per_step": ms_per_step, "ms_steps": st3["ms"],
                "newton_iters": st3["newton_iters"], "evals": st3["evals"], "halvings": st3["halvings"],
                "cg_iters": st3["cg_iters"], "restarted": st3["restarted"], "retried": st3["retried"],
+               "stages": st3["parts"],
                "ms_eval": st3["ms_eval"], "ms_linear": st3["ms_linear"],
                "ms_fast_kernel_per_eval": fast_ms, "ms_crowded_pass_per_eval": crowd_ms,
                "crowded_cells_per_eval": crowd_cells, "oracle_error": c3_err},

@@ -199,6 +199,31 @@ int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const
                 lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats);
 
 /*
+ * Solve at moved sites from the weights that solved the problem before the move (the
+ * advect-and-solve step of a particle simulation; the warm start is not in the paper).
+ * psi_inout holds the solution at positions p0 = (x0, y0, z0); the sites move to
+ * p1 = (x1, y1, z1). Each weight is carried with its site: with c_i the centroid of cell
+ * i before the move and d_i = p1_i - p0_i, psi_i - 2 d_i.(c_i - p0_i) + |d_i|^2 keeps the
+ * power of the site at its old centroid, so the cell follows its centroid to first order
+ * instead of being swept by the site's motion; Algorithm 1 (lagot_solve, opts) then solves
+ * from these weights. If the carried weights leave a cell empty, or the solve does not
+ * converge, the move is split: the sites go part of the way, float(p0 + t (p1 - p0)), are
+ * solved there to max(tol, stage_tol), and the rest of the move starts from that solution;
+ * the part halves after a failure and doubles after a success, down to 1/64 of the move,
+ * where the empty-start repair of lagot_solve (opts.empty_start_fallback) takes over.
+ *   in : x0, y0, z0, x1, y1, z1 [n] float32 (device; every site strictly inside the box at
+ *        both ends), nu [n] float64, psi_inout [n] float64 (the solution at p0); opts as for
+ *        lagot_solve (use_learned must be 0; continuation applies to each part).
+ *   out: psi_inout (the solution at p1; unchanged on error); *stats (HOST, may be NULL):
+ *        summed over the parts (evals include one centroid evaluation per accepted part),
+ *        stages = parts solved, residuals of the last solve. Synchronises the stream.
+ * Errors: as lagot_solve (the last part's error when even 1/64 of the move fails).
+ */
+int lagot_solve_moved(lagot_ctx *ctx, int64_t n, const float *x0, const float *y0, const float *z0,
+                      const float *x1, const float *y1, const float *z1, const double *nu, lagot_box box,
+                      double *psi_inout, const lagot_opts *opts, lagot_stats *stats);
+
+/*
  * Many independent solves in one call (each instance is a full lagot_solve problem:
  * its own sites, prescribed volumes, box and start weights). Instance b owns the rows
  * [offsets[b], offsets[b+1]) of the concatenated arrays x, y, z, nu, psi_inout.

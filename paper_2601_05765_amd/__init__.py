@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_solve_moved", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
            "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward", "lagot_mlp_forward_noalloc",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
@@ -102,6 +102,9 @@ def load():
             f.restype = I
         lib.lagot_solve_batched.argtypes = [P, ctypes.c_int32, ctypes.POINTER(I64), P, P, P, P, ctypes.POINTER(Box),
                                             P, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+        lib.lagot_solve_moved.argtypes = [P, I64, P, P, P, P, P, P, P, Box, P, ctypes.POINTER(Opts),
+                                          ctypes.POINTER(Stats)]
+        lib.lagot_solve_moved.restype = I
         lib.lagot_solve_batched.restype = I
         lib.lagot_mlp_set_params.argtypes = [P, P]
         lib.lagot_mlp_get_params.argtypes = [P, P]
@@ -497,6 +500,20 @@ class Context:
                     check: bool = True):
         """lagot_newton_step: one damped Newton iteration; psi updated in place."""
         return self._newton(load().lagot_newton_step, x, y, z, nu, psi, box, opts, check)
+
+    def solve_moved(self, x0, y0, z0, x1, y1, z1, nu, psi, box=((0, 0, 0), (1, 1, 1)), opts: Opts | None = None,
+                    check: bool = True):
+        """lagot_solve_moved: psi (the solution at p0) becomes the solution at p1, in place."""
+        import torch
+        f32 = [_dev(a, torch.float32, nm) for a, nm in ((x0, "x0"), (y0, "y0"), (z0, "z0"), (x1, "x1"), (y1, "y1"),
+                                                         (z1, "z1"))]
+        st = Stats()
+        o = opts if opts is not None else default_opts()
+        rc = load().lagot_solve_moved(self._h, x1.shape[0], *f32, _dev(nu, torch.float64, "nu"), make_box(box),
+                                      _dev(psi, torch.float64, "psi"), ctypes.byref(o), ctypes.byref(st))
+        if check and rc != OK:
+            raise LagotError(rc, "lagot_solve_moved")
+        return st
 
     def solve_batched(self, offsets, x, y, z, nu, psi, boxes=None, opts: Opts | None = None, check: bool = True):
         """lagot_solve_batched: instance b owns rows offsets[b]:offsets[b+1] of the concatenated

@@ -106,6 +106,9 @@ struct lagot_ctx {
     double *cen_out = nullptr;  // caller's centroid array during a lagot_centroids call
     double *cont_buf = nullptr; // continuation: start volumes, prescribed volumes, last accepted weights [3n]
     int64_t cap_cont = 0;
+    double *mv_buf = nullptr;   // lagot_solve_moved: centroids [3n], volumes [n], accepted / trial weights [2n]
+    float *mv_pos = nullptr;    // ... positions of the accepted part and of the trial part [6n]
+    int64_t cap_mv = 0;
     double *fl_buf = nullptr;   // fluid step: PCG records and vectors, right-hand sides, centroids
     int32_t *fl_int = nullptr;  // fluid step: PCG status per coordinate, chunk counters
     int2 *fl_ent = nullptr;     // fluid step: matrix rows packed back to back
@@ -248,7 +251,9 @@ void free_all(lagot_ctx *c) {
     free_inst(c);
     c->cap_qtmp_n = 0;
     free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int, c->fl_ent,
-              c->hent, c->qcount, c->qstart, c->qcursor, c->qtmp, c->cont_buf, c->lr_rmc, c->lr_ir);
+              c->hent, c->qcount, c->qstart, c->qcursor, c->qtmp, c->cont_buf, c->lr_rmc, c->lr_ir, c->mv_buf,
+              c->mv_pos);
+    c->cap_mv = 0;
     c->cap_cont = 0;
     c->cap_nc = 0;
     c->cap_nq = 0;
@@ -1617,6 +1622,116 @@ int lagot_solve(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const
     if (!ctx || !psi_inout) return LAGOT_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return LAGOT_EHIP;
     return single_instance(ctx, n, x, y, z, nu, box, psi_inout, opts, stats, false);
+}
+
+int lagot_solve_moved(lagot_ctx *c, int64_t n, const float *x0, const float *y0, const float *z0, const float *x1,
+                      const float *y1, const float *z1, const double *nu, lagot_box box, double *psi_inout,
+                      const lagot_opts *opts, lagot_stats *stats) {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (!c || !x0 || !y0 || !z0 || !x1 || !y1 || !z1 || !nu || !psi_inout || n <= 0) {
+        if (stats) stats->status = LAGOT_EINVAL;
+        return LAGOT_EINVAL;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    const double t_start = now_ms();
+    lagot_opts o;
+    if (opts)
+        o = *opts;
+    else
+        fill_defaults(&o);
+    int rc = check_opts(o);
+    if (!rc && o.use_learned) rc = LAGOT_EINVAL;
+    if (rc) {
+        if (stats) stats->status = rc;
+        return rc;
+    }
+    if (n > c->cap_mv) {
+        free_ptrs(c->mv_buf, c->mv_pos);
+        c->cap_mv = 0;
+        HIP_TRY(dalloc(&c->mv_buf, 6 * (size_t)n));
+        HIP_TRY(dalloc(&c->mv_pos, 6 * (size_t)n));
+        c->cap_mv = n;
+    }
+    double *cen = c->mv_buf, *vol = cen + 3 * n, *psi_a = vol + n, *psi_b = psi_a + n;
+    float *xa = c->mv_pos, *ya = xa + n, *za = ya + n, *xb = za + n, *yb = xb + n, *zb = yb + n;
+    hipStream_t st = c->stream;
+    HIP_TRY(hipMemcpyAsync(xa, x0, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ya, y0, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(za, z0, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(psi_a, psi_inout, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    // Parts of the move: the weights of the last accepted positions are carried to the next
+    // ones (centroids of their cells), and Algorithm 1 solves there, to stage_tol for a part
+    // short of the end. A carried start with an empty cell (EEMPTY: the repair is off while
+    // the move can still be split) or a part that does not converge halves the part.
+    double tau = 0.0, dtau = 1.0;
+    bool have_cen = false;
+    int parts = 0, rc_last = LAGOT_OK;
+    lagot_stats acc, S;
+    std::memset(&acc, 0, sizeof(acc));
+    constexpr double MIN_PART = 1.0 / 64.0;
+    while (tau < 1.0) {
+        const double t1 = std::min(1.0, tau + dtau);
+        const bool last = t1 >= 1.0;
+        if (!have_cen) {
+            rc = lagot_centroids(c, n, xa, ya, za, psi_a, box, vol, cen);
+            if (rc) break;
+            acc.evals += 1;
+            have_cen = true;
+        }
+        launch_lerp_sites(st, n, x0, y0, z0, x1, y1, z1, t1, xb, yb, zb);
+        launch_carry_weights(st, n, xa, ya, za, xb, yb, zb, cen, psi_a, psi_b);
+        lagot_opts op = o;
+        op.empty_start_fallback = dtau <= MIN_PART ? o.empty_start_fallback : 0;
+        if (!last) op.tol = std::max(o.tol, o.stage_tol);
+        rc = single_instance(c, n, xb, yb, zb, nu, box, psi_b, &op, &S, false);
+        acc.newton_iters += S.newton_iters;
+        acc.evals += S.evals;
+        acc.halvings += S.halvings;
+        acc.cg_iters += S.cg_iters;
+        acc.fallback_cells += S.fallback_cells;
+        acc.cell_launches += S.cell_launches;
+        acc.default_start |= S.default_start;
+        acc.repaired_start |= S.repaired_start;
+        acc.ms_eval += S.ms_eval;
+        acc.ms_linear += S.ms_linear;
+        acc.ms_cell_kernel += S.ms_cell_kernel;
+        acc.failed_cells = S.failed_cells;
+        acc.max_rel_err = S.max_rel_err;
+        acc.grad_norm = S.grad_norm;
+        rc_last = rc;
+        if (o.verbose)
+            fprintf(stderr, "lagot moved sites: part to %.4f (step %.4f): status %d, %d Newton iterations\n", t1, dtau,
+                    rc, S.newton_iters);
+        if (rc == LAGOT_OK) {
+            ++parts;
+            tau = t1;
+            HIP_TRY(hipMemcpyAsync(psi_a, psi_b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            std::swap(xa, xb);
+            std::swap(ya, yb);
+            std::swap(za, zb);
+            have_cen = false;
+            dtau = std::min(2.0 * dtau, 1.0);
+        } else if ((rc == LAGOT_EEMPTY || rc == LAGOT_ENOCONV || rc == LAGOT_ELINESEARCH || rc == LAGOT_ECAPACITY) &&
+                   dtau > MIN_PART) {
+            dtau *= 0.5;
+        } else {
+            break;
+        }
+    }
+    if (tau >= 1.0) {
+        rc = LAGOT_OK;
+        HIP_TRY(hipMemcpyAsync(psi_inout, psi_a, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else if (!rc) {
+        rc = rc_last ? rc_last : LAGOT_ENOCONV;
+    }
+    if (stats) {
+        *stats = acc;
+        stats->status = rc;
+        stats->stages = parts;
+        stats->ms_total = now_ms() - t_start;
+    }
+    return rc;
 }
 
 int lagot_solve_batched(lagot_ctx *ctx, int32_t n_inst, const int64_t *offsets, const float *x, const float *y,

@@ -445,9 +445,48 @@ __global__ void k_lr_spread(Batch bt, int want, int nc, const uint32_t *__restri
                 atomicMax(ir + g.base + (ix * g.dim[1] + iy) * g.dim[2] + iz, rb);
 }
 
+__global__ void k_lerp_sites(int64_t n, const float *__restrict__ x0, const float *__restrict__ y0,
+                             const float *__restrict__ z0, const float *__restrict__ x1, const float *__restrict__ y1,
+                             const float *__restrict__ z1, double t, float *__restrict__ x, float *__restrict__ y,
+                             float *__restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // the differences of floats are exact in float64, and p0 + 1 * (p1 - p0) = p1
+    x[i] = (float)((double)x0[i] + t * ((double)x1[i] - (double)x0[i]));
+    y[i] = (float)((double)y0[i] + t * ((double)y1[i] - (double)y0[i]));
+    z[i] = (float)((double)z0[i] + t * ((double)z1[i] - (double)z0[i]));
+}
+
+// The power of a moved site at its old cell's centroid c is kept: |c - pb|^2 - psi' =
+// |c - pa|^2 - psi gives psi' = psi - 2 d.(c - pa) + |d|^2 with d = pb - pa; the cell then
+// moves with its centroid to first order instead of being swept by the site's motion.
+__global__ void k_carry_weights(int64_t n, const float *__restrict__ xa, const float *__restrict__ ya,
+                                const float *__restrict__ za, const float *__restrict__ xb, const float *__restrict__ yb,
+                                const float *__restrict__ zb, const double *__restrict__ cen,
+                                const double *__restrict__ psi, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double ax = xa[i], ay = ya[i], az = za[i];
+    const double dx = (double)xb[i] - ax, dy = (double)yb[i] - ay, dz = (double)zb[i] - az;
+    const double cx = cen[3 * i] - ax, cy = cen[3 * i + 1] - ay, cz = cen[3 * i + 2] - az;
+    out[i] = psi[i] - 2.0 * (dx * cx + dy * cy + dz * cz) + (dx * dx + dy * dy + dz * dz);
+}
+
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_lerp_sites(hipStream_t st, int64_t n, const float *x0, const float *y0, const float *z0, const float *x1,
+                       const float *y1, const float *z1, double t, float *x, float *y, float *z) {
+    hipLaunchKernelGGL(k_lerp_sites, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x0, y0, z0, x1, y1, z1, t, x, y, z);
+}
+
+void launch_carry_weights(hipStream_t st, int64_t n, const float *xa, const float *ya, const float *za,
+                          const float *xb, const float *yb, const float *zb, const double *cen, const double *psi,
+                          double *psi_out) {
+    hipLaunchKernelGGL(k_carry_weights, dim3(nblocks(n, 256)), dim3(256), 0, st, n, xa, ya, za, xb, yb, zb, cen, psi,
+                       psi_out);
+}
 
 void launch_local_reach(hipStream_t st, int64_t n, const Batch &bt, int want, int nc_total, const float4 *pos_s,
                         uint32_t *rmc, uint32_t *ir) {

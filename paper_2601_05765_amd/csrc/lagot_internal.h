@@ -258,6 +258,14 @@ void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float 
                          const double *psi, float4 *pos_orig);
 // rmax[b] = max sqrt(max(psi, 0)) over the rows of every selected instance
 void launch_rmax(hipStream_t st, const Batch &bt, int want, const double *psi, double *rmax);
+// moved sites (lagot_solve_moved): p = float(p0 + t (p1 - p0)) per coordinate (exactly p1 at t = 1)
+void launch_lerp_sites(hipStream_t st, int64_t n, const float *x0, const float *y0, const float *z0, const float *x1,
+                       const float *y1, const float *z1, double t, float *x, float *y, float *z);
+// weights carried with moved sites: psi_out = psi - 2 d.(c - pa) + |d|^2, d = pb - pa (caller order;
+// cen [3n] site-major)
+void launch_carry_weights(hipStream_t st, int64_t n, const float *xa, const float *ya, const float *za,
+                          const float *xb, const float *yb, const float *zb, const double *cen, const double *psi,
+                          double *psi_out);
 // local reach of the selected instances from the float32 weights in pos_s.w: rmc[c] = the
 // largest ball radius of the sites in coarse cell c, ir[c] = the largest rmc[c'] of the coarse
 // cells c' within 2 rmc[c'] of c (work arrays of nc_total entries; ir as bt.ir)

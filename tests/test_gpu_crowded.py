@@ -144,6 +144,58 @@ def test_advected_steps_200k(ctx, oracle_mod, splash_settled):
         assert err.max() <= 1e-5
 
 
+def test_solve_moved_200k(ctx, oracle_mod, splash_settled):
+    """lagot_solve_moved on the large-scene sequence at 200,000 sites: the settled weights
+    carried with the advected sites (dt 2e-3), split into parts while the carried weights
+    leave cells empty; each step converges (oracle re-evaluation of sampled cells), and the
+    two steps take fewer Newton iterations in all than lagot_solve from the previous weights."""
+    _say("case: splash 200k, lagot_solve_moved")
+    import torch
+    import paper_2601_05765_amd as L
+    sc, _, psi = splash_settled
+    nu = _t(sc.nu, torch.float64)
+    opts = L.default_opts(tol=1e-5, residual_test=0)
+    cur, p = sc, _t(psi, torch.float64)
+    its_moved = its_plain = 0
+    for k in range(1, 3):
+        nxt = scenes.advect(cur, 2e-3)
+        x0, y0, z0 = _xyz(cur)
+        x1, y1, z1 = _xyz(nxt)
+        q = p.clone()
+        plain = ctx.solve(x1, y1, z1, nu, q, opts=opts, check=False)
+        st = ctx.solve_moved(x0, y0, z0, x1, y1, z1, nu, p, opts=opts, check=False)
+        _say(f"  step {k}: moved {st.as_dict()}; plain iterations {plain.newton_iters} evals {plain.evals}")
+        assert st.status == 0 and st.max_rel_err <= 1e-5 and st.stages >= 1
+        assert plain.status == 0
+        its_moved += st.newton_iters
+        its_plain += plain.newton_iters
+        ph = p.cpu().numpy()
+        idx = _sample(nxt.n, ph, 20 + k, k_top=80, k_rand=150)
+        c = oracle_mod.cells(nxt.x, nxt.y, nxt.z, ph, idx=idx)
+        err = np.abs(c.V - nxt.nu[idx]) / nxt.nu[idx]
+        _say(f"  oracle max {err.max():.2e}")
+        assert err.max() <= 1e-5
+        cur = nxt
+    assert its_moved < its_plain
+
+
+def test_solve_moved_without_motion_keeps_the_solution(ctx, oracle_mod):
+    """Sites that do not move: the carried weights are the given ones (d = 0), which already
+    solve the problem, so no Newton iteration is taken."""
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(1000, 0)
+    x, y, z = _xyz(sc)
+    nu = _t(sc.nu, torch.float64)
+    p = _t(sc.psi0, torch.float64)
+    st = ctx.solve(x, y, z, nu, p, opts=L.default_opts(tol=1e-6), check=False)
+    assert st.status == 0
+    p0 = p.clone()
+    st = ctx.solve_moved(x, y, z, x, y, z, nu, p, opts=L.default_opts(tol=1e-5), check=False)
+    assert st.status == 0 and st.newton_iters == 0 and st.stages == 1
+    assert torch.equal(p, p0)
+
+
 def test_continuation_options_rejected(ctx):
     """Invalid continuation options, and continuation in a batched call, are EINVAL."""
     import torch
