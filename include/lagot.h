@@ -395,17 +395,20 @@ int lagot_fluid_velocity(lagot_ctx *ctx, int64_t n, const float *x, const float 
  * old velocities, x <- x + dt v, the weights are re-solved at the new positions
  * (Algorithm 1 from psi_inout, as lagot_solve), and the velocities are updated at the
  * new cells as lagot_fluid_velocity. The moved positions are kept inside the domain:
- * each coordinate is clamped to [lo + m_a, hi - m_a], m_a = 1e-6 (hi_a - lo_a), and,
- * with convex domain planes (lagot_set_domain), a site beyond n.x = c - m
- * (m = 1e-6 times the largest box extent) is moved along -n onto that plane, in two
- * passes over the planes. The update x + dt v is formed in float64 with separate
- * roundings and rounded once to float32.
+ * each coordinate is clamped to [lo + m_a, hi - m_a], m_a = max(1e-6 (hi_a - lo_a), u)
+ * with u = 4 float32 spacings at the largest |bound| (so the rounding to float32 keeps a
+ * clamped site strictly inside), and, with convex domain planes (lagot_set_domain), a
+ * site beyond n.x = c - m (m = max(1e-6 times the largest box extent, u)) is moved along
+ * -n onto that plane, in two passes over the planes. The update x + dt v is formed in
+ * float64 with separate roundings and rounded once to float32.
  *   in/out: x, y, z [n] float32 (device), psi_inout [n] float64, v_inout [3n] float64
  *           site-major; in: nu [n] float64, mass [n] float64 (> 0), mu [n] or NULL,
  *           prm, opts (NULL = defaults) HOST; out: stats (the solve's, HOST, may be
  *           NULL), cg_iters [3] HOST int32 or NULL.
- * Errors: those of lagot_solve and lagot_fluid_velocity; invalid parameters are
- *         rejected before anything moves. After a solve error the positions have moved,
+ * Errors: those of lagot_solve and lagot_fluid_velocity; invalid parameters, options,
+ *         prescribed volumes (<= 0), masses (<= 0), velocities (not finite) and
+ *         viscosities (< 0) are rejected (EINVAL) before anything moves; a NaN weight or a
+ *         site outside the box is found by the solve. After a solve error the positions have moved,
  *         psi_inout holds the solve's last accepted weights and v_inout is unchanged.
  *         Synchronises the stream.
  */

@@ -237,17 +237,20 @@ def advect(xyz32: np.ndarray, v: np.ndarray, dt: float, box=((0, 0, 0), (1, 1, 1
     x + dt v in float64, kept inside the domain, rounded once to float32.
 
     Reading (the paper does not say how sites are kept in the domain): each coordinate
-    is clamped to [lo + m_a, hi - m_a] with m_a = 1e-6 (hi_a - lo_a); then, for convex
-    domain planes n.x <= c, a site with n.x - c + m > 0 (m = 1e-6 times the largest box
-    extent) is moved by that amount along -n, in two passes over the planes in order.
-    Every product and sum is rounded separately."""
+    is clamped to [lo + m_a, hi - m_a] with m_a = max(1e-6 (hi_a - lo_a), u), u = 4
+    float32 spacings at the largest |bound| (so that the final rounding to float32 keeps
+    a clamped coordinate strictly inside); then, for convex domain planes n.x <= c, a
+    site with n.x - c + m > 0 (m = max(1e-6 times the largest box extent, u)) is moved
+    by that amount along -n, in two passes over the planes in order. Every product and
+    sum is rounded separately."""
     lo = np.asarray(box[0], np.float64)
     hi = np.asarray(box[1], np.float64)
-    m = ADVECT_MARGIN * (hi - lo)
+    u = 4.0 * float(np.spacing(np.float32(max(np.max(np.abs(lo)), np.max(np.abs(hi))))))
+    m = np.maximum(ADVECT_MARGIN * (hi - lo), u)
     p = np.asarray(xyz32, np.float32).astype(np.float64) + dt * np.asarray(v, np.float64)
     p = np.minimum(np.maximum(p, lo + m), hi - m)
     if domain is not None:
-        pm = ADVECT_MARGIN * float(np.max(hi - lo))
+        pm = max(ADVECT_MARGIN * float(np.max(hi - lo)), u)
         planes = np.asarray(domain, np.float64).reshape(-1, 4)
         for _ in range(2):
             for nx, ny, nz, c in planes:

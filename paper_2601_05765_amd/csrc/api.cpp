@@ -64,6 +64,7 @@ struct lagot_ctx {
     // the current call: B instances, T tiles, n rows
     int B = 0, T = 0;
     int64_t n = 0;
+    int max_inst_tiles = 0;  // tiles of the largest instance of the call
     int ncell_total = 0;
     std::vector<GridDesc> h_grid;
 
@@ -501,9 +502,11 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     BoxF *h_box = (BoxF *)(h_trow + T);
     GridDesc *h_g = (GridDesc *)(h_box + B);
     int t = 0;
+    c->max_inst_tiles = 0;
     for (int b = 0; b < B; ++b) {
         h_off[b] = (int32_t)offs[b];
         h_first[b] = t;
+        c->max_inst_tiles = std::max(c->max_inst_tiles, (int)((offs[b + 1] - offs[b] + TILE - 1) / TILE));
         for (int64_t r = offs[b]; r < offs[b + 1]; r += TILE) {
             h_tinst[t] = b;
             h_trow[t] = (int32_t)r;
@@ -872,6 +875,12 @@ int autotune_tpc(lagot_ctx *c) {
 // Inward margin of the fluid step's position update, relative to the box extent.
 constexpr double ADVECT_MARGIN = 1e-6;
 
+// spacing of float32 numbers at |v|
+double ulp32(double v) {
+    const float f = (float)std::fabs(v);
+    return (double)std::nextafter(f, INFINITY) - (double)f;
+}
+
 // ---- graph mode ---------------------------------------------------------------
 void drop_graphs(lagot_ctx *c) {
     if (c->g_dir) (void)hipGraphExecDestroy(c->g_dir);
@@ -902,6 +911,12 @@ template <typename F> int capture(lagot_ctx *c, F &&enqueue, hipGraphExec_t *out
     return LAGOT_OK;
 }
 
+// The PCG scalars need their own kernel when an instance has more partials (sub-tiles)
+// than the iteration's blocks sum themselves.
+bool cg_scalar_launch(const lagot_ctx *c) {
+    return (int64_t)c->max_inst_tiles * (TILE / c->cg_sub) > cg_sum_in_block_max();
+}
+
 // Jacobi-PCG for every ACTIVE instance with the context's block shape: chunks of
 // launches, then the count of instances still iterating is read back.
 int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, bool graph) {
@@ -911,7 +926,7 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
     if (with_init)
     {
         launch_cg_init(st, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hrow, c->hent, cg);
-        launch_cg_scalars(st, bt, c->cg_sub, -1, o.cg_max_iter, cg);
+        if (cg_scalar_launch(c)) launch_cg_scalars(st, bt, c->cg_sub, -1, o.cg_max_iter, cg);
     }
     const double rtol2 = o.cg_rtol * o.cg_rtol;
     const int cap = o.cg_max_iter;
@@ -921,7 +936,7 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
         auto chunk = [&]() {
             for (int q = 0; q < m; ++q) {
                 launch_cg_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hrow, c->hent, cg);
-                launch_cg_scalars(c->stream, bt, c->cg_sub, q, cap, cg);
+                if (cg_scalar_launch(c)) launch_cg_scalars(c->stream, bt, c->cg_sub, q, cap, cg);
             }
             launch_cg_advance(c->stream, bt, m, cap, cg);
         };
@@ -966,7 +981,7 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o, bool graph) {
         if (with_init) {
             launch_cg_init(c->stream, bt, c->cg_lanes, c->cg_sub, c->V, c->nu_s, c->diag, c->hrow, c->hent,
                            cg_bufs(c));
-            launch_cg_scalars(c->stream, bt, c->cg_sub, -1, o.cg_max_iter, cg_bufs(c));
+            if (cg_scalar_launch(c)) launch_cg_scalars(c->stream, bt, c->cg_sub, -1, o.cg_max_iter, cg_bufs(c));
         }
     };
     int k = 0, rc;
@@ -2095,15 +2110,37 @@ int lagot_fluid_step(lagot_ctx *c, int64_t n, float *x, float *y, float *z, cons
     if (!c || !x || !y || !z || !nu || !psi_inout || !mass || !v_inout || !prm || n <= 0) return LAGOT_EINVAL;
     if (!box_ok(box) || !fluid_params_ok(*prm, mu != nullptr)) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    {
+        // every input is checked before a site moves: options, prescribed volumes,
+        // masses, velocities and viscosities
+        lagot_opts o;
+        if (opts)
+            o = *opts;
+        else
+            fill_defaults(&o);
+        if (check_opts(o) || o.use_learned) return LAGOT_EINVAL;
+        launch_zero_i32(c->stream, c->misc + 6, 1);
+        launch_fluid_check(c->stream, n, nu, mass, mu, v_inout, c->misc + 6);
+        int32_t bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, c->misc + 6, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (bad) return LAGOT_EINVAL;
+    }
     AdvectBounds bd;
-    double ext = 0.0;
+    double ext = 0.0, big = 0.0;
     for (int a = 0; a < 3; ++a) {
-        const double m = ADVECT_MARGIN * (box.hi[a] - box.lo[a]);
+        ext = std::max(ext, box.hi[a] - box.lo[a]);
+        big = std::max(big, std::max(std::fabs(box.lo[a]), std::fabs(box.hi[a])));
+    }
+    // the margin also exceeds a few float32 ulps of the bounds, so that the rounding of a
+    // clamped coordinate to float32 keeps it strictly inside
+    const double ulps = 4.0 * ulp32(big);
+    for (int a = 0; a < 3; ++a) {
+        const double m = std::max(ADVECT_MARGIN * (box.hi[a] - box.lo[a]), ulps);
         bd.lo[a] = box.lo[a] + m;
         bd.hi[a] = box.hi[a] - m;
-        ext = std::max(ext, box.hi[a] - box.lo[a]);
     }
-    bd.plane_margin = ADVECT_MARGIN * ext;
+    bd.plane_margin = std::max(ADVECT_MARGIN * ext, ulps);
     launch_advect(c->stream, n, x, y, z, v_inout, prm->dt, bd, c->dom_d, c->ndom);
     int rc = single_instance(c, n, x, y, z, nu, box, psi_inout, opts, stats, false);
     if (rc) return rc;

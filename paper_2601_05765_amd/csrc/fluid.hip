@@ -103,6 +103,18 @@ __global__ __launch_bounds__(FB) void k_p1_laplacian(int64_t n, const int32_t *_
 // is moved along -n onto n.x = c - m, in two passes over the planes. Every product and
 // sum is rounded separately (no contraction), so the result is reproducible on any
 // IEEE double implementation before the final rounding to float32.
+// Inputs of the fluid step that must be valid before any site moves.
+__global__ __launch_bounds__(FB) void k_fluid_check(int64_t n, const double *__restrict__ nu,
+                                                    const double *__restrict__ mass, const double *__restrict__ mu,
+                                                    const double *__restrict__ v, int32_t *__restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * FB + threadIdx.x;
+    if (i >= n) return;
+    bool ok = nu[i] > 0.0 && isfinite(nu[i]) && mass[i] > 0.0 && isfinite(mass[i]);
+    for (int a = 0; a < 3; ++a) ok = ok && isfinite(v[3 * i + a]);
+    if (mu) ok = ok && mu[i] >= 0.0 && isfinite(mu[i]);
+    if (!ok) atomicAdd(bad, 1);
+}
+
 __global__ __launch_bounds__(FB) void k_advect(int64_t n, float *__restrict__ x, float *__restrict__ y,
                                                float *__restrict__ z, const double *__restrict__ v, double dt,
                                                AdvectBounds bd, const float4 *__restrict__ dom, int ndom) {
@@ -144,6 +156,7 @@ __global__ __launch_bounds__(FB) void k_advect(int64_t n, float *__restrict__ x,
 constexpr int C3L = 2;             // lanes per row
 constexpr int C3S = 128;           // rows per block
 constexpr int C3B = C3L * C3S;     // threads per block
+constexpr int CG3_SUM_IN_BLOCK = 2048;  // up to this many blocks, each block sums the partials itself
 
 __device__ inline void load_rec3(const Rec3 *a, int64_t i, double *r, double *w, double *s, double &d) {
     const double2 *p = reinterpret_cast<const double2 *>(a + i);
@@ -253,10 +266,23 @@ __global__ __launch_bounds__(C3B) void k_cg3_iter(int64_t n, int m, double rtol2
     const int64_t row = (int64_t)blk * C3S + (int)(threadIdx.x / C3L);
     const int l = threadIdx.x & (C3L - 1);
     const bool has = row < n;
-    // scalars of iteration k, summed once from every block's partials by k_cg3_scalars
+    // scalars of iteration k: summed by the block itself from every block's partials when
+    // the blocks are few, else once per iteration by k_cg3_scalars
     double S[12];
+    if (g.nb <= CG3_SUM_IN_BLOCK) {
 #pragma unroll
-    for (int q = 0; q < 12; ++q) S[q] = g.sc[12 * cur + q];
+        for (int q = 0; q < 12; ++q) S[q] = 0.0;
+        for (int t = (int)threadIdx.x; t < g.nb; t += C3B) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) S[q] += P3(g, cur, q)[t];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) S[9 + q] += P3_RHO0(g, q)[t];
+        }
+        block_sums<12>(S, sh);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) S[q] = g.sc[12 * cur + q];
+    }
     const bool lead = blk == 0 && threadIdx.x == 0;
     double alpha[3] = {0.0, 0.0, 0.0}, beta[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -413,6 +439,11 @@ void launch_p1_laplacian(hipStream_t st, int64_t n, const int32_t *perm, const i
     hipLaunchKernelGGL(k_p1_laplacian, dim3(nb(n)), dim3(FB), 0, st, n, perm, hcol, hval, hcnt, mu, mu0, u, out, bad);
 }
 
+void launch_fluid_check(hipStream_t st, int64_t n, const double *nu, const double *mass, const double *mu,
+                        const double *v, int32_t *bad) {
+    hipLaunchKernelGGL(k_fluid_check, dim3(nb(n)), dim3(FB), 0, st, n, nu, mass, mu, v, bad);
+}
+
 void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, const double *v, double dt,
                    const AdvectBounds &bd, const float4 *dom, int ndom) {
     hipLaunchKernelGGL(k_advect, dim3(nb(n)), dim3(FB), 0, st, n, x, y, z, v, dt, bd, dom, ndom);
@@ -436,6 +467,7 @@ void launch_cg3_iter(hipStream_t st, int64_t n, int m, double rtol2, int cap, co
 }
 
 void launch_cg3_scalars(hipStream_t st, int m, int cap, const Cg3Bufs &g) {
+    if (g.nb <= CG3_SUM_IN_BLOCK) return;  // the iteration's blocks sum the partials themselves
     hipLaunchKernelGGL(k_cg3_scalars, dim3(1), dim3(C3B), 0, st, m, cap, g);
 }
 

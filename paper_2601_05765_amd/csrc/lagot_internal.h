@@ -329,8 +329,10 @@ void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, 
                     const int2 *hrow, const int2 *ent, CgBufs cg);
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg);
 // The scalars of the next PCG iteration from the partials just written (after launch_cg_init:
-// m = -1; after launch_cg_iter with m: the same m), one block per instance
+// m = -1; after launch_cg_iter with m: the same m), one block per instance with more than
+// cg_sum_in_block_max() partials (the others are summed inside the iteration's blocks)
 void launch_cg_scalars(hipStream_t st, const Batch &bt, int sub, int m, int cap, CgBufs cg);
+int cg_sum_in_block_max();
 void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, CgBufs cg, const int32_t *herr,
                       InstCtl *ctl, int32_t *phase);
 void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase);
@@ -366,6 +368,9 @@ void launch_p1_laplacian(hipStream_t st, int64_t n, const int32_t *perm, const i
                          const int32_t *hcnt, const double *mu, double mu0, const double *u, double *out,
                          int32_t *bad);
 int cg3_blocks(int64_t n);
+// bad += entries with nu <= 0, mass <= 0, a non-finite velocity, or a viscosity < 0 (mu may be null)
+void launch_fluid_check(hipStream_t st, int64_t n, const double *nu, const double *mass, const double *mu,
+                        const double *v, int32_t *bad);
 // packed rows: rp [n+1] (exclusive scan of hcnt), ent [rp[n]] = (column, float bits of the value)
 void launch_pack_rows(hipStream_t st, int64_t n, const int32_t *hcol, const float *hval, const int32_t *hcnt,
                       const int32_t *rp, int2 *ent);

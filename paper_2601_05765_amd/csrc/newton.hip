@@ -256,6 +256,10 @@ __global__ __launch_bounds__(TILE) void k_hess_finish(Batch bt, int want, const 
 // per sub-tile, so SUB sets how many partials every block sums). Chosen per context
 // (lagot_set_cg_shape / the autotuner); the partial buffers are sized for SUB = 64.
 constexpr int PF = 4;              // row entries per lane fetched before the scalars are known
+// An instance with at most this many partials has every block of an iteration sum them
+// (no extra launch); larger ones get them summed once per iteration by k_cg_scalars.
+constexpr int CG_SUM_IN_BLOCK = 2048;
+constexpr int SCB = 1024;          // threads of k_cg_scalars
 
 // Four fixed-order sums over the partials t0..t1-1 (any block size, multiple of 64;
 // sh holds one row per wave).
@@ -434,10 +438,25 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
         }
     }
     const double d = own.d, rk = own.r, wk = own.w, sk_1 = own.s;
-    // the iteration's scalars, summed once per iteration by k_cg_scalars
-    const double2 s01 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur);
-    const double2 s23 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur + 2);
-    const double gam = s01.x, del = s01.y, rho = s23.x, rho0 = s23.y;
+    // the iteration's scalars: summed by the block itself from the instance's partials when
+    // they are few, else once per iteration by k_cg_scalars
+    double gam, del, rho, rho0;
+    const int t1 = SPT * bt.first_tile[b + 1];
+    if (t1 - t0 <= CG_SUM_IN_BLOCK) {
+        double S[4];
+        sum_range(P_GAM(cg, NS, cur), P_DEL(cg, NS, cur), P_RHO(cg, NS, cur), P_RHO0(cg, NS), t0, t1, S, sh);
+        gam = S[0];
+        del = S[1];
+        rho = S[2];
+        rho0 = S[3];
+    } else {
+        const double2 s01 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur);
+        const double2 s23 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur + 2);
+        gam = s01.x;
+        del = s01.y;
+        rho = s23.x;
+        rho0 = s23.y;
+    }
     const bool lead = q == t0 && threadIdx.x == 0;
     if (rho <= rtol2 * rho0) {
         if (lead) {
@@ -509,10 +528,11 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
 // partials of the slot just written, summed once, in a fixed order (deterministic), by
 // one block per instance, instead of by every block of the next iteration (which made
 // the reduction quadratic in the number of tiles).
-__global__ __launch_bounds__(RB) void k_cg_scalars(Batch bt, int spt, int m, int cap, CgBufs cg) {
-    __shared__ double sh[RB / 64][4];
+__global__ __launch_bounds__(SCB) void k_cg_scalars(Batch bt, int spt, int m, int cap, CgBufs cg) {
+    __shared__ double sh[SCB / 64][4];
     const int b = blockIdx.x;
     if (bt.phase[b] != PH_ACTIVE) return;
+    if (spt * (bt.first_tile[b + 1] - bt.first_tile[b]) <= CG_SUM_IN_BLOCK) return;  // summed in the blocks
     int slot = 0;
     if (m >= 0) {
         const int32_t *st = cg.cgst + 4 * b;
@@ -822,8 +842,10 @@ void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, 
 #undef X
 }
 
+int cg_sum_in_block_max() { return CG_SUM_IN_BLOCK; }
+
 void launch_cg_scalars(hipStream_t st, const Batch &bt, int sub, int m, int cap, CgBufs cg) {
-    hipLaunchKernelGGL(k_cg_scalars, dim3(bt.B), dim3(RB), 0, st, bt, TILE / sub, m, cap, cg);
+    hipLaunchKernelGGL(k_cg_scalars, dim3(bt.B), dim3(SCB), 0, st, bt, TILE / sub, m, cap, cg);
 }
 
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg) {

@@ -94,7 +94,9 @@ def dam_break(n: int = 100_000, seed: int = 0, fill: float = 0.4, total: float =
     """Jittered cubic lattice (jitter +-0.3 spacing) filling the lower ``fill`` of the box."""
     rng = np.random.default_rng(seed)
     h = (fill / n) ** (1.0 / 3.0)
-    nxy = int(math.floor(1.0 / h))
+    # columns at (i + 1/2) h while the jittered lattice stays inside the box:
+    # (nxy - 1/2) h + jitter h < 1 (63 columns at 100,000 sites)
+    nxy = int(math.floor(1.0 / h + 0.5 - jitter - 1e-9))
     nz = int(math.ceil(n / (nxy * nxy))) + 1
     p = _jittered_lattice(rng, h, nxy, nxy, nz, jitter=jitter)
     p = _keep_lowest_z(p, n)

@@ -324,6 +324,22 @@ def test_fluid_step_rejects_bad_parameters_before_moving(ctx):
                            L.default_fluid_params(**bad))
         assert ei.value.code == L.EINVAL
         assert torch.equal(x, x0)
+    # invalid per-site inputs and options are found before the sites move too
+    m_bad = mass.copy()
+    m_bad[7] = 0.0
+    v_bad = v.copy()
+    v_bad[11, 2] = float("inf")
+    nu_bad = sc.nu.copy()
+    nu_bad[3] = -1.0
+    cases = [(sc.nu, m_bad, v, None, None), (sc.nu, mass, v_bad, None, None), (nu_bad, mass, v, None, None),
+             (sc.nu, mass, v, -np.ones(sc.n), None), (sc.nu, mass, v, None, L.default_opts(tol=-1.0))]
+    for nu_c, m_c, v_c, mu_c, opts in cases:
+        with pytest.raises(L.LagotError) as ei:
+            ctx.fluid_step(x, y, z, _t(nu_c, torch.float64), psi, _t(m_c, torch.float64), _t(v_c, torch.float64),
+                           L.default_fluid_params(), opts=opts,
+                           mu=None if mu_c is None else _t(mu_c, torch.float64))
+        assert ei.value.code == L.EINVAL
+        assert torch.equal(x, x0)
 
 
 def test_p1_laplacian_dam_break_100k_sampled(ctx, oracle_mod):

@@ -159,9 +159,23 @@ def test_advect_clamps_to_the_box_margin(oracle_mod):
     v = np.array([[-100.0, -100.0, -100.0], [100.0, 100.0, 100.0]])
     got = oracle_mod.advect(x, v, 1.0, box).astype(np.float64)
     lo, hi = np.array(box[0]), np.array(box[1])
-    m = 1e-6 * (hi - lo)
+    # margin 1e-6 of the extent, at least 4 float32 spacings at the largest bound (3.0)
+    m = np.maximum(1e-6 * (hi - lo), 4.0 * 2.0 ** -22)
     assert np.allclose(got[0], lo + m, rtol=0, atol=1e-7 * 4) and np.all(got[0] > lo)
     assert np.allclose(got[1], hi - m, rtol=0, atol=1e-7 * 4) and np.all(got[1] < hi)
+
+
+def test_advect_margin_survives_float32_rounding_far_from_the_origin(oracle_mod):
+    """A box far from the origin, [100, 101]^3: 1e-6 of the extent is below one float32
+    spacing at 100 (7.6e-6), so the margin is 4 spacings; clamped sites round to float32
+    strictly inside the box (the site validation's strict test passes)."""
+    box = ((100.0, 100.0, 100.0), (101.0, 101.0, 101.0))
+    x = np.array([[100.5, 100.5, 100.5], [100.9, 100.1, 100.5]], np.float32)
+    v = np.array([[-50.0, 50.0, 0.0], [50.0, -50.0, 0.0]])
+    got = oracle_mod.advect(x, v, 1.0, box)
+    assert np.all(got > np.float32(100.0)) and np.all(got < np.float32(101.0))
+    sp = float(np.spacing(np.float32(101.0)))
+    assert abs(float(got[0, 0]) - (100.0 + 4 * sp)) <= sp and abs(float(got[0, 1]) - (101.0 - 4 * sp)) <= sp
 
 
 def test_advect_projects_onto_a_domain_plane(oracle_mod):
