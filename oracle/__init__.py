@@ -51,7 +51,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.oracle_cells.argtypes = [ctypes.c_long, P, P, P, P, P, P, ctypes.c_long, P, P, P, P, P, ctypes.c_int,
-                                     P, P, P, ctypes.c_int, P, P, P, ctypes.c_int]
+                                     P, P, P, ctypes.c_int, P, P, P, ctypes.c_int, P, P]
         lib.oracle_cells.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -79,6 +79,8 @@ class Cells:
     idx: np.ndarray          # [m] evaluated site indices
     work: np.ndarray | None = None  # [m,6] work units (see lagot_oracle.c) when requested
     C: np.ndarray | None = None     # [m,3] centroids (the site itself for an empty cell)
+    Kp: np.ndarray | None = None    # [m] |K| by section 3.3's own route (paper_k=True)
+    cin: np.ndarray | None = None   # [m,3] that route's interior point c (paper_k=True)
 
     def facets(self, c: int) -> dict:
         k = int(self.fcount[c])
@@ -86,8 +88,13 @@ class Cells:
 
 
 def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, threads: int = 0,
-          work: bool = False, domain=None) -> Cells:
+          work: bool = False, domain=None, paper_k: bool = False) -> Cells:
     """Evaluate the restricted Laguerre cells of the sites ``idx`` (default: all).
+
+    ``paper_k``: also compute |K| by section 3.3's own route (interior point c from
+    rays cast from the restricted facets, each facet projected from c onto the sphere,
+    the projected areas by Gauss-Bonnet; Algorithm 2), independently of the signed
+    solid-angle form that gives ``K``.
 
     ``domain``: optional [P, 4] array of planes (n, c), unit outward normals n, for the
     convex domain {x : n.x <= c} in place of the box walls.
@@ -121,13 +128,16 @@ def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, th
     st = np.zeros(m, np.int32)
     wk = np.zeros((m, 6), np.int64) if work else None
     C = np.zeros((m, 3))
+    Kp = np.zeros(m) if paper_k else None
+    cin = np.zeros((m, 3)) if paper_k else None
     lib.oracle_cells(n, _ptr(x), _ptr(y), _ptr(z), _ptr(psi), _ptr(b), idx_p, m, _ptr(V), _ptr(K), _ptr(W),
                      _ptr(fj), _ptr(fA), fcap, _ptr(fc), _ptr(nc), _ptr(st), int(threads),
                      _ptr(wk) if work else None, _ptr(C), _ptr(dom) if dom is not None else None,
-                     0 if dom is None else int(dom.shape[0]))
+                     0 if dom is None else int(dom.shape[0]), _ptr(Kp) if paper_k else None,
+                     _ptr(cin) if paper_k else None)
     if (st == 2).any():
         raise RuntimeError("oracle facet capacity exceeded; raise fcap")
-    return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr, wk, C)
+    return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr, wk, C, Kp, cin)
 
 
 def hessian(xyz: np.ndarray, psi: np.ndarray, c: Cells):
@@ -275,7 +285,7 @@ class FluidStep:
 
 def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.ndarray, mu, dt: float,
                    eps: float, gamma: float, gravity=(0.0, 0.0, 0.0), box=((0, 0, 0), (1, 1, 1)),
-                   domain=None) -> FluidStep:
+                   domain=None, solver: str = "direct") -> FluidStep:
     """Velocity update of the fluid step, section 5: with the cells at the sites ``xyz``
     and weights ``psi`` (normally the OT solution there),
 
@@ -284,8 +294,11 @@ def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.nda
       F_t = gamma Lap p                surface tension, P1 Laplacian of the positions
       (m_i/dt) v_i - (Lap_mu v)_i = (m_i/dt) v^k_i + F_p + F_g + F_t     (eq. (4))
 
-    solved exactly (sparse direct solve). Lap_mu is the P1 Laplacian with
-    mu_ij = (mu_i + mu_j) / 2. Boundary (wall) terms do not enter.
+    solved exactly (sparse direct solve), or with ``solver="cg"`` by Jacobi-PCG to a
+    relative residual of 1e-13 (the matrix is symmetric positive definite: m/dt on the
+    diagonal plus a graph Laplacian; for large scenes, where the direct factorisation
+    fills in). Lap_mu is the P1 Laplacian with mu_ij = (mu_i + mu_j) / 2. Boundary
+    (wall) terms do not enter.
 
     The spring is read with the particle's mass, as in Gallouet-Merigot's scheme that
     the paper follows (the pull of the OT distance on site i is m_i (c_i - p_i)); the
@@ -303,7 +316,13 @@ def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.nda
     Wm = _mu_scaled(W, mu)
     A = (sp.diags(m / dt + np.asarray(Wm.sum(axis=1)).ravel()) - Wm).tocsc()
     b = (m / dt)[:, None] * np.asarray(v, np.float64) + Fp + Fg + Ft
-    vn = np.stack([sla.spsolve(A, b[:, k]) for k in range(3)], axis=1)
+    if solver == "direct":
+        vn = np.stack([sla.spsolve(A, b[:, k]) for k in range(3)], axis=1)
+    elif solver == "cg":
+        A = A.tocsr()
+        vn = np.stack([pcg(A, b[:, k], A.diagonal(), rtol=1e-13) for k in range(3)], axis=1)
+    else:
+        raise ValueError(f"unknown solver {solver!r}")
     return FluidStep(vn, Fp, Ft, Fg, c, W)
 
 

@@ -331,6 +331,238 @@ static fanacc restrict_face(const oface *f, const oplane *pl, double r)
     return acc;
 }
 
+/* auxiliary cube planes carry ids at or below this (never facets, never walls) */
+#define AUX_ID (-1000000)
+
+/* ---- section 3.3's own route to |K_i| (point_in, occluded patches, Gauss-Bonnet) ----
+ *
+ * The restricted cell is convex, so from a point c inside it every ray leaves through
+ * exactly one boundary point: on the spherical part K_i, or on a restricted facet B_f.
+ * The sphere is therefore tiled by K_i and the central projections from c of the B_f:
+ * |K_i| = |Sigma_i| - sum_f |Proj(B_f, Sigma_i, c)|. Each projected facet is a region of
+ * the sphere bounded by circle arcs (a straight boundary piece of B_f projects into the
+ * circle cut from the sphere by the plane through c and the piece; a boundary arc of
+ * B_f, on the facet's own circle, stays where it is); its area follows from
+ * Gauss-Bonnet, |R| / r^2 = 2 pi - sum k_g len - sum turning angles, with the
+ * geodesic curvature of a circle at distance e from the centre k_g = e / (r rho)
+ * (reading of the printed formula, whose radicand is negative), signed positive when
+ * the region is on the circle's smaller cap.
+ */
+typedef struct {
+    int arc;         /* 0: straight piece A->B of an edge; 1: arc of the facet circle A->B (ccw about n) */
+    int full;        /* the whole facet circle */
+    double A[3], B[3];
+} kpiece;
+
+/* end points (parameters lo < hi on a + s (b - a)) of the part of edge ab in the ball |y| < r */
+static int seg_in_ball(const double *a, const double *b, double r, double *lo, double *hi)
+{
+    double w[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double qa = dot3(w, w);
+    if (!(qa > 0.0)) return 0;
+    double qb = dot3(a, w), qc = dot3(a, a) - r * r;
+    double disc = qb * qb - qa * qc;
+    if (!(disc > 0.0)) return 0;
+    double sq = sqrt(disc);
+    double s1 = (-qb - sq) / qa, s2 = (-qb + sq) / qa;
+    *lo = s1 > 0.0 ? s1 : 0.0;
+    *hi = s2 < 1.0 ? s2 : 1.0;
+    return *lo < *hi;
+}
+
+/* boundary of face f restricted to the ball, in order (counter-clockwise about n seen from
+   outside); returns the piece count (0: the restricted facet is empty) */
+static int restricted_boundary(const oface *f, const oplane *pl, double r, kpiece *out, int cap)
+{
+    double t = pl->t;
+    if (!(fabs(t) < r)) return 0;
+    int m = 0, first_entry = -1;
+    for (int e = 0; e < f->nv; ++e) {
+        const double *a = f->v + 3 * e, *b = f->v + 3 * ((e + 1) % f->nv);
+        double lo, hi;
+        if (!seg_in_ball(a, b, r, &lo, &hi)) continue;
+        if (m + 2 > cap) return -1;
+        kpiece sp;
+        sp.arc = 0;
+        sp.full = 0;
+        for (int k = 0; k < 3; ++k) {
+            sp.A[k] = a[k] + lo * (b[k] - a[k]);
+            sp.B[k] = a[k] + hi * (b[k] - a[k]);
+        }
+        /* an entry point: the boundary came along the circle from the last exit */
+        if (lo > 0.0 && m > 0) {
+            kpiece ap = {1, 0, {0, 0, 0}, {0, 0, 0}};
+            memcpy(ap.A, out[m - 1].B, sizeof(ap.A));
+            memcpy(ap.B, sp.A, sizeof(ap.B));
+            out[m++] = ap;
+        }
+        if (m == 0) first_entry = lo > 0.0;
+        out[m++] = sp;
+    }
+    if (m == 0) {
+        /* no edge meets the ball: the facet circle lies wholly inside or outside the polygon;
+           inside iff its centre q = t n is on the inner side of every edge */
+        double q[3] = {t * pl->n[0], t * pl->n[1], t * pl->n[2]};
+        for (int e = 0; e < f->nv; ++e) {
+            const double *a = f->v + 3 * e, *b = f->v + 3 * ((e + 1) % f->nv);
+            double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, v[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]}, c[3];
+            cross3(u, v, c);
+            if (dot3(c, pl->n) < 0.0) return 0;
+        }
+        kpiece fp = {1, 1, {0, 0, 0}, {0, 0, 0}};
+        out[0] = fp;
+        return 1;
+    }
+    /* closing arc from the last exit to the first entry */
+    if (first_entry) {
+        if (m + 1 > cap) return -1;
+        kpiece ap = {1, 0, {0, 0, 0}, {0, 0, 0}};
+        memcpy(ap.A, out[m - 1].B, sizeof(ap.A));
+        memcpy(ap.B, out[0].A, sizeof(ap.B));
+        out[m++] = ap;
+    }
+    return m;
+}
+
+/* point of the ray c + s (x - c), s > 0, on the sphere |y| = r (c inside the ball) */
+static void project_from(const double *c, const double *x, double r, double *out)
+{
+    double e[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    double a = dot3(e, e), b = dot3(c, e), cc = dot3(c, c) - r * r;
+    double s = (-b + sqrt(b * b - a * cc)) / a;
+    for (int k = 0; k < 3; ++k) out[k] = c[k] + s * e[k];
+}
+
+/* positive angle in [0, 2 pi) from x to y about the unit axis u (x, y taken about the
+   circle centre o) */
+static double angle_about(const double *x, const double *y, const double *o, const double *u)
+{
+    double a[3] = {x[0] - o[0], x[1] - o[1], x[2] - o[2]}, b[3] = {y[0] - o[0], y[1] - o[1], y[2] - o[2]}, c[3];
+    cross3(a, b, c);
+    double th = atan2(dot3(c, u), dot3(a, b));
+    return th < 0.0 ? th + 2.0 * OR_PI : th;
+}
+
+/* unit tangent at the sphere point x of a circle traversed positively about the axis u */
+static void tangent_about(const double *u, const double *x, double *T)
+{
+    cross3(u, x, T);
+    double l = sqrt(dot3(T, T));
+    for (int k = 0; k < 3; ++k) T[k] /= l;
+}
+
+/* area of the projection from c of one restricted facet (pieces kp[0..m)) */
+static double projected_patch(const kpiece *kp, int m, const oplane *pl, const double *c, double r)
+{
+    if (m == 1 && kp[0].full) {
+        /* the cap beyond the facet plane: 2 pi r (r - t) */
+        return 2.0 * OR_PI * r * (r - pl->t);
+    }
+    double kl = 0.0, turn = 0.0;
+    double T0[3] = {0.0, 0.0, 0.0}, Tprev[3] = {0.0, 0.0, 0.0}, Pfirst[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < m; ++k) {
+        const kpiece *q = &kp[k];
+        double Ps[3], Pe[3], u[3], e, Ts[3], Te[3];
+        if (q->arc) {
+            memcpy(Ps, q->A, sizeof(Ps));
+            memcpy(Pe, q->B, sizeof(Pe));
+            memcpy(u, pl->n, sizeof(u));
+            e = pl->t;
+        } else {
+            project_from(c, q->A, r, Ps);
+            project_from(c, q->B, r, Pe);
+            double a[3] = {q->A[0] - c[0], q->A[1] - c[1], q->A[2] - c[2]};
+            double b[3] = {q->B[0] - c[0], q->B[1] - c[1], q->B[2] - c[2]};
+            cross3(a, b, u);
+            double l = sqrt(dot3(u, u));
+            for (int j = 0; j < 3; ++j) u[j] /= l;
+            e = dot3(c, u);
+        }
+        double o[3] = {e * u[0], e * u[1], e * u[2]};
+        kl += e * angle_about(Ps, Pe, o, u) / r;
+        tangent_about(u, Ps, Ts);
+        tangent_about(u, Pe, Te);
+        if (k == 0) {
+            memcpy(T0, Ts, sizeof(T0));
+            memcpy(Pfirst, Ps, sizeof(Pfirst));
+        } else {
+            double x[3];
+            cross3(Tprev, Ts, x);
+            turn += atan2(dot3(x, Ps) / r, dot3(Tprev, Ts));
+        }
+        memcpy(Tprev, Te, sizeof(Tprev));
+    }
+    double x[3];
+    cross3(Tprev, T0, x);
+    turn += atan2(dot3(x, Pfirst) / r, dot3(Tprev, T0));
+    return r * r * (2.0 * OR_PI - kl - turn);
+}
+
+/* K_i by the route above, with c = point_in(C_i): from the area centroid of each
+   restricted facet a ray along -n_f to the first of the sphere and the other planes;
+   c = the mean of the chords' midpoints. Returns K; c (local coordinates) in cin. */
+static double paper_k(const opoly *P, const oplane *pl, int nreal, double r, int inside, double *cin)
+{
+    int cap = 8, nb = 0;
+    kpiece *kp = NULL;
+    int *start = (int *)malloc(sizeof(int) * (size_t)(P->nf + 1));
+    int *face = (int *)malloc(sizeof(int) * (size_t)(P->nf + 1));
+    start[0] = 0;
+    int total = 0;
+    for (int k = 0; k < P->nf; ++k) {
+        const oface *f = &P->f[k];
+        const oplane *p = &pl[f->plane];
+        if (p->id <= AUX_ID) continue;
+        int m;
+        for (;;) {
+            kp = (kpiece *)realloc(kp, sizeof(kpiece) * (size_t)(total + cap));
+            m = restricted_boundary(f, p, r, kp + total, cap);
+            if (m >= 0) break;
+            cap *= 2;
+        }
+        if (m == 0) continue;
+        face[nb] = k;
+        total += m;
+        start[++nb] = total;
+    }
+    cin[0] = cin[1] = cin[2] = 0.0;
+    double K;
+    if (nb == 0) {
+        K = 4.0 * OR_PI * r * r * inside;
+    } else {
+        for (int b = 0; b < nb; ++b) {
+            const oplane *p = &pl[P->f[face[b]].plane];
+            /* the restricted facet's area centroid q + m / area (a point of its relative
+               interior, so the ray below has a chord of positive length) */
+            fanacc a = restrict_face(&P->f[face[b]], p, r);
+            double g[3];
+            for (int j = 0; j < 3; ++j) g[j] = p->t * p->n[j] + (a.area > 0.0 ? a.m[j] / a.area : 0.0);
+            double d[3] = {-p->n[0], -p->n[1], -p->n[2]};
+            double gd = dot3(g, d);
+            double lam = -gd + sqrt(gd * gd - (dot3(g, g) - r * r));
+            for (int k = 0; k < nreal; ++k) {
+                if (&pl[k] == p) continue;
+                double den = dot3(pl[k].n, d);
+                if (den > 0.0) {
+                    double l = (pl[k].t - dot3(pl[k].n, g)) / den;
+                    if (l < lam) lam = l;
+                }
+            }
+            if (lam < 0.0) lam = 0.0;
+            for (int j = 0; j < 3; ++j) cin[j] += g[j] + 0.5 * lam * d[j];
+        }
+        for (int j = 0; j < 3; ++j) cin[j] /= nb;
+        double occluded = 0.0;
+        for (int b = 0; b < nb; ++b)
+            occluded += projected_patch(kp + start[b], start[b + 1] - start[b], &pl[P->f[face[b]].plane], cin, r);
+        K = 4.0 * OR_PI * r * r - occluded;
+    }
+    free(kp);
+    free(start);
+    free(face);
+    return K;
+}
+
 static int cmp_plane_t(const void *a, const void *b)
 {
     const oplane *u = (const oplane *)a, *v = (const oplane *)b;
@@ -344,12 +576,10 @@ static int cmp_plane_t(const void *a, const void *b)
  * facets (id, area) with area > 0, the facet count (may exceed fcap -> status
  * OR_FACET_CAP), and the number of planes that cut the ball (ncand).
  */
-/* auxiliary cube planes carry ids at or below this (never facets, never walls) */
-#define AUX_ID (-1000000)
 
 static int oracle_cell(long i, long n, const double *x, const double *y, const double *z, const double *psi,
                        const double *box, const double *dom, int ndom, double *V, double *K, double *wall, long *fj,
-                       double *fA, int fcap, int *fcount, int *ncand, double *cen)
+                       double *fA, int fcap, int *fcount, int *ncand, double *cen, double *Kp, double *cin)
 {
     const int nwall = ndom > 0 ? ndom : 6;
     *V = 0.0;
@@ -357,6 +587,12 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
     cen[0] = x[i];
     cen[1] = y[i];
     cen[2] = z[i];
+    if (Kp) {
+        *Kp = 0.0;
+        cin[0] = x[i];
+        cin[1] = y[i];
+        cin[2] = z[i];
+    }
     for (int k = 0; k < nwall; ++k) wall[k] = 0.0;
     *fcount = 0;
     *ncand = 0;
@@ -492,6 +728,11 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
             nf++;
         }
     }
+    if (Kp) {
+        double cl[3];
+        *Kp = paper_k(&P, pl, nreal, r, inside, cl);
+        for (int j = 0; j < 3; ++j) cin[j] = pi3[j] + cl[j];
+    }
     poly_free(&P);
     free(pl);
     if (P.nf == 0 && !inside) {
@@ -515,12 +756,14 @@ static int oracle_cell(long i, long n, const double *x, const double *y, const d
  * Per evaluated cell c: V[c], K[c], wall[W c..W c+W) with W = 6 or ndom, facets fj/fA[c*fcap ..],
  * fcount[c], ncand[c], status[c], the centroid cen[3c..3c+3) (the site itself for an
  * empty cell), and when work != NULL the six work units of each cell at
- * work[6c..6c+6). OpenMP over cells.
+ * work[6c..6c+6). With Kp != NULL also |K| by section 3.3's own route (point_in and the
+ * projected facets, paper_k above) at Kp[c] and its interior point at cin[3c..3c+3).
+ * OpenMP over cells.
  */
 int oracle_cells(long n, const double *x, const double *y, const double *z, const double *psi,
                  const double *box, const long *idx, long m, double *V, double *K, double *wall, long *fj,
                  double *fA, int fcap, int *fcount, int *ncand, int *status, int nthreads, long *work, double *cen,
-                 const double *dom, int ndom)
+                 const double *dom, int ndom, double *Kp, double *cin)
 {
     long cnt = idx ? m : n;
 #ifdef _OPENMP
@@ -537,7 +780,7 @@ int oracle_cells(long n, const double *x, const double *y, const double *z, cons
         const int nwall = ndom > 0 ? ndom : 6;
         status[c] = oracle_cell(i, n, x, y, z, psi, box, dom, ndom, &V[c], &K[c], &wall[(size_t)nwall * c],
                                 &fj[(size_t)c * fcap], &fA[(size_t)c * fcap], fcap, &fcount[c], &ncand[c],
-                                &cen[3 * c]);
+                                &cen[3 * c], Kp ? &Kp[c] : NULL, cin ? &cin[3 * c] : NULL);
     }
     return 0;
 }

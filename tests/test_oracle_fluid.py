@@ -119,6 +119,25 @@ def test_momentum_and_energy(oracle_mod):
     assert np.abs(st0.v - st0.v.mean(0)).max() < np.abs(v - v.mean(0)).max()
 
 
+def test_cg_solver_matches_the_direct_solve(oracle_mod):
+    """The iterative solve of eq. (4) (Jacobi-PCG, for scenes too large to factorise)
+    reaches the sparse direct solution; it also keeps the momentum balance, which the
+    direct solve satisfies exactly."""
+    xyz, psi, rng = _blob(180, 5)
+    m = rng.uniform(0.5, 2.0, 180) * 1e-3
+    muv = rng.uniform(0.0, 3.0, 180)
+    v = rng.normal(size=(180, 3))
+    dt = 0.01
+    kw = dict(dt=dt, eps=0.2, gamma=0.4, gravity=(0, 0, -9.81))
+    a = oracle_mod.fluid_velocity(xyz, psi, v, m, muv, **kw)
+    b = oracle_mod.fluid_velocity(xyz, psi, v, m, muv, solver="cg", **kw)
+    assert np.abs(b.v - a.v).max() <= 1e-10 * np.abs(a.v).max()
+    F = b.Fp + b.Fg + b.Ft
+    assert np.allclose((m[:, None] * b.v).sum(0), (m[:, None] * v).sum(0) + dt * F.sum(0), rtol=0, atol=1e-10)
+    with pytest.raises(ValueError):
+        oracle_mod.fluid_velocity(xyz, psi, v, m, muv, solver="lu", **kw)
+
+
 @pytest.mark.parametrize("mu1,mu2,m1,m2", [(1.0, 1.0, 1e-3, 1e-3), (0.2, 3.0, 1e-3, 4e-3)])
 def test_two_particle_system_by_hand(oracle_mod, mu1, mu2, m1, m2):
     """Two cells sharing one facet: with k = mu_12 w_12 dt, mu_12 = (mu1 + mu2)/2,
