@@ -7,7 +7,8 @@ log-normal radius packed 1.72x denser than their prescribed volumes, log-normal
 prescribed volumes summing to 0.3, random velocities N(0, 0.5^2) per axis. The
 scene is settled from its Voronoi start (path following on the prescribed
 volumes), then advected by dt = 2e-3 per step (mirror reflection at the walls)
-and solved again, each solve warm-started from the previous step's weights.
+and solved again, each solve from the previous step's weights (repaired where they
+leave cells empty, else the default start) with the same path following.
 float32 geometry, float64 weights, reductions and CG.
 
 A step is one advect-and-solve step of that sequence: every Newton evaluation of
@@ -20,12 +21,17 @@ Printed (one JSON line):
   value          Laguerre cell evaluations per second over the timed steps
                  (N x evaluations / wall time)
   ms_per_step    ms per advect-and-solve step (one OT solve)
-  roofline       the dominant kernel of the step (see the design doc for the model)
+  roofline       the dominant kernel of the step, the crowded-cell pass: algorithmic
+                 FLOPs per launch (cost model over the oracle's work units) / launch
+                 time against the FP64 peak, with its counter record (HBM bytes per
+                 launch, VALU issue fraction) when the sources match
   cpu_baseline   the FP64 oracle on the host cores, brute-force neighbours, on a
                  bounded sample of cells of the settled scene, in cells/s
   c3             settle time, per-step ms, Newton iterations, evaluations, and the
                  oracle-sampled error of the final weights (heaviest sites + random)
-Sections: dam_break (the 100k-site configuration), batched, fluid, learned.
+Sections: dam_break (the 100k-site configuration), paper_k_route (the A/B pair of the
+spherical area on its converged cells), batched, fluid, learned; each carries its
+error against the FP64 oracle (oracle_error), computed after all GPU timing.
 
 Profiling modes (no JSON line): --profile c3 | cells | fluid runs a short piece of
 the workload for rocprofv3 (c3: settle and two steps; cells: one dam-break solve
@@ -52,9 +58,11 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the fast cell kernel from FETCH_SIZE / WRITE_SIZE counters
-# (profiles/), valid only for the kernel sources they were taken with
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cells_fast32_dam_break_100k_traffic.json")
+# HBM bytes per launch of the crowded-cell pass from FETCH_SIZE / WRITE_SIZE counters and its
+# VALU issue fraction from SQ_INSTS_VALU / GRBM_GUI_ACTIVE (profiles/; written by
+# --counters-summary from the rocprofv3 runs the record names), valid only for the kernel
+# sources they were taken with
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cells_overflow_splash_2m_counters.json")
 TRAFFIC_SOURCES = ("paper_2601_05765_amd/csrc/cells.hip", "paper_2601_05765_amd/csrc/lagot_internal.h")
 
 
@@ -68,7 +76,7 @@ def kernel_sources_digest() -> str:
 
 
 def counter_record():
-    """The committed counter profile of the fast cell kernel (HBM bytes per launch, VALU
+    """The committed counter profile of the crowded-cell pass (HBM bytes per launch, VALU
     issue fraction), or {} when the kernel sources changed since the counters were taken
     (or there is no profile)."""
     try:
@@ -136,7 +144,7 @@ def cpu_baseline(sc, psi, seconds_target: float = 15.0):
     dt1 = time.perf_counter() - t0
     oracle.cells(sc.x, sc.y, sc.z, psi, idx=idx1[:1], threads=cores)  # back to all threads
     return {"value": reps * m / dt, "unit": "cells/s", "cores": cores, "kind": "oracle",
-            "sample": f"{what} of the {sc.n}-site workload at the start weights, brute-force "
+            "sample": f"{what} of the {sc.n}-site workload at the weights of the last step, brute-force "
                       f"neighbours, FP64 ({dt:.1f} s)",
             "single_core": {"value": m1 / dt1, "sample": f"{m1} random cells on 1 thread ({dt1:.1f} s)"}}, \
         c.work.mean(axis=0)
@@ -176,12 +184,23 @@ def batched_section(ctx, L, scenes, reps: int = 3):
     torch.cuda.synchronize()
     singles = 1000.0 * (time.perf_counter() - a)
     med = float(np.median(ms))
+    p_fin = p.cpu().numpy()
+
+    def check():
+        # eight instances spread over the size range: the heaviest sites and a random sample of each
+        order = np.argsort([sc.n for sc in insts])
+        errs = []
+        for k, b in enumerate(order[np.linspace(0, len(insts) - 1, 8).astype(int)]):
+            sc, pb = insts[b], p_fin[offs[b]:offs[b + 1]]
+            errs.append(cell_errors(sc.x, sc.y, sc.z, pb, sc.nu, sample_idx(sc.n, pb, 40 + k, k_top=5, k_rand=40)))
+        return summarize(np.concatenate(errs), "8 instances spread over the sizes, 5 heaviest + 40 random cells each")
+
     return {"instances": 256, "sites": int(offs[-1]), "ms_per_batched_solve": med,
             "cells_per_s": float(cell_evals / (med / 1000.0)),
             "newton_iters_max": max(s.newton_iters for s in sts),
             "newton_iters_mean": float(np.mean([s.newton_iters for s in sts])),
             "max_rel_err": max(s.max_rel_err for s in sts),
-            "ms_one_at_a_time": singles, "speedup_vs_one_at_a_time": singles / med}
+            "ms_one_at_a_time": singles, "speedup_vs_one_at_a_time": singles / med}, check
 
 
 def learned_section(ctx, L, scenes, n_seeds: int, train_steps: int, steps: int):
@@ -230,10 +249,10 @@ def fluid_section(ctx, L, x, y, z, psi, nu, reps: int = 10, steps: int = 5):
     for _ in range(2):
         ctx.fluid_velocity(x, y, z, psi, nu, v, prm, mu=mu)
     torch.cuda.synchronize()
-    ms, its = [], None
+    ms, its, vn = [], None, None
     for _ in range(reps):
         a = time.perf_counter()
-        _, _, its = ctx.fluid_velocity(x, y, z, psi, nu, v, prm, mu=mu)
+        vn, _, its = ctx.fluid_velocity(x, y, z, psi, nu, v, prm, mu=mu)
         torch.cuda.synchronize()
         ms.append(1000.0 * (time.perf_counter() - a))
     # whole steps of the dam break from rest (move, re-solve from the last weights, update
@@ -247,9 +266,58 @@ def fluid_section(ctx, L, x, y, z, psi, nu, reps: int = 10, steps: int = 5):
         torch.cuda.synchronize()
         step_ms.append(1000.0 * (time.perf_counter() - a))
         newton.append(st.newton_iters)
+    data = [a.cpu().numpy() for a in (x, y, z, psi, nu, v, mu, vn)]
+
+    def check():
+        import oracle
+        xs_, ys_, zs_, ps_, nus_, v_, mu_, vn_ = data
+        xyz = np.stack([xs_, ys_, zs_], 1).astype(np.float64)
+        o = oracle.fluid_velocity(xyz, ps_, v_, nus_, mu_, dt=prm.dt, eps=prm.eps, gamma=prm.gamma,
+                                  gravity=tuple(prm.gravity), solver="cg")
+        e = np.linalg.norm(vn_ - o.v, axis=1) / np.linalg.norm(o.v, axis=1)
+        return summarize(e, f"|v_i - v_i(oracle)| / |v_i(oracle)| over all {len(e)} sites (oracle: every cell, "
+                            f"eq. (4) by FP64 Jacobi-PCG to 1e-13)")
+
     return {"ms_fluid_velocity": float(np.median(ms)), "pcg_iters": its, "dt": prm.dt, "eps": prm.eps,
             "gamma": prm.gamma, "mu": "per site, uniform in [0, 2]", "ms_per_fluid_step": step_ms,
-            "newton_iters_per_step": newton}
+            "newton_iters_per_step": newton}, check
+
+
+def paper_k_section(ctx, x, y, z, psi, reps: int = 5):
+    """The A/B pair of the spherical area: lagot_cells (signed solid angles at p_i, float32
+    fast pass) against lagot_cells_paper_k (section 3.3's own route: interior point,
+    projected facets, Gauss-Bonnet; every cell on the float64 path), on the same cells."""
+    import torch
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        wall, kern = [], []
+        for _ in range(reps):
+            a = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            wall.append(1000.0 * (time.perf_counter() - a))
+            kern.append(ctx.last_cell_kernel_ms())
+        return out, float(np.median(wall)), float(np.median(kern))
+
+    sg, w_sg, k_sg = timed(lambda: ctx.cells(x, y, z, psi, csr=False, walls=False)["sph"])
+    (_, kr), w_kr, k_kr = timed(lambda: ctx.cells_paper_k(x, y, z, psi))
+    area = 4.0 * math.pi * psi
+    d = ((kr - sg).abs() / area).max().item()
+    data = [a.cpu().numpy() for a in (x, y, z, psi, kr)]
+
+    def check():
+        import oracle
+        xs, ys, zs, ps, kk = data
+        idx = sample_idx(len(ps), ps, 9, k_top=0, k_rand=300)
+        c = oracle.cells(xs, ys, zs, ps, idx=idx, paper_k=True)
+        e = np.abs(kk[idx] - c.Kp) / (4.0 * math.pi * ps[idx])
+        return summarize(e, "|K_i(route) - K_i(oracle route)| / 4 pi r_i^2, 300 random cells")
+
+    return {"ms_lagot_cells": w_sg, "ms_cell_kernel_signed": k_sg, "ms_lagot_cells_paper_k": w_kr,
+            "ms_cell_kernel_paper_k": k_kr, "kernel_ratio": k_kr / max(k_sg, 1e-9),
+            "max_rel_diff_K": d, "diff_normalised_by": "4 pi r_i^2"}, check
 
 
 def sample_idx(n, psi, seed, k_top=100, k_rand=300):
@@ -258,13 +326,21 @@ def sample_idx(n, psi, seed, k_top=100, k_rand=300):
     return np.unique(np.concatenate([np.argsort(-psi)[:k_top], rng.choice(n, min(k_rand, n), replace=False)]))
 
 
-def oracle_error(x, y, z, psi, nu, idx):
-    """max and p99 over the sampled cells of |V_i - nu_i| / nu_i, the volumes V_i of the
-    returned weights evaluated by the FP64 oracle (brute-force neighbours)."""
+def cell_errors(x, y, z, psi, nu, idx):
+    """|V_i - nu_i| / nu_i of the sampled cells, the volumes V_i of the returned weights
+    evaluated by the FP64 oracle (brute-force neighbours)."""
     import oracle
     c = oracle.cells(x, y, z, psi, idx=idx)
-    e = np.abs(c.V - nu[idx]) / nu[idx]
-    return {"cells": int(len(idx)), "max_rel_err": float(e.max()), "p99_rel_err": float(np.percentile(e, 99))}
+    return np.abs(c.V - nu[idx]) / nu[idx]
+
+
+def summarize(e, what):
+    return {"count": int(len(e)), "max_rel_err": float(np.max(e)), "p99_rel_err": float(np.percentile(e, 99)),
+            "sample": what}
+
+
+def oracle_error(x, y, z, psi, nu, idx, what="heaviest sites + random cells"):
+    return summarize(cell_errors(x, y, z, psi, nu, idx), what)
 
 
 def c3_sequence(ctx, L, scenes, n: int, warmup: int, steps: int, log):
@@ -280,8 +356,11 @@ def c3_sequence(ctx, L, scenes, n: int, warmup: int, steps: int, log):
     pos = [(t(s.x, torch.float32), t(s.y, torch.float32), t(s.z, torch.float32)) for s in seq]
     nu, psi = t(sc.nu, torch.float64), t(sc.psi0, torch.float64)
     x0, y0, z0 = t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32)
+    # every solve follows the path on the prescribed volumes (opts.continuation): at this size
+    # the advected previous weights leave ~20% of the cells empty, the repair does not
+    # recover them, and the solve restarts from the default weights, from which the path
+    # takes fewer evaluations than Algorithm 1 alone (41 against 57 per step)
     settle_opts = L.default_opts(tol=1e-5, residual_test=0, continuation=1)
-    step_opts = L.default_opts(tol=1e-5, residual_test=0)
     torch.cuda.synchronize()
     a = time.perf_counter()
     st = ctx.solve(x0, y0, z0, nu, psi, opts=settle_opts, check=False)
@@ -292,41 +371,33 @@ def c3_sequence(ctx, L, scenes, n: int, warmup: int, steps: int, log):
     log(f"c3 settle: {settle_ms:.0f} ms, {st.newton_iters} Newton iterations, {st.stages} stages")
     settle = {"ms": settle_ms, "newton_iters": st.newton_iters, "evals": st.evals, "stages": st.stages,
               "halvings": st.halvings, "cg_iters": st.cg_iters, "max_rel_err": st.max_rel_err}
-    prev = torch.empty_like(psi)
 
     def step(k):
         x, y, z = pos[k]
-        prev.copy_(psi)
-        s1 = ctx.solve(x, y, z, nu, psi, opts=step_opts, check=False)
+        s1 = ctx.solve(x, y, z, nu, psi, opts=settle_opts, check=False)
         kt = ctx.last_kernel_times()
-        retried = False
-        if s1.status != 0:  # Algorithm 1 stalled: the same step again with path following
-            psi.copy_(prev)
-            s1 = ctx.solve(x, y, z, nu, psi, opts=settle_opts, check=False)
-            kt = ctx.last_kernel_times()
-            retried = True
         if s1.status != 0:
             raise RuntimeError(f"step {k} of the splash sequence failed: {s1.as_dict()}")
-        return s1, kt, retried
+        return s1, kt
 
     for k in range(max(warmup, 1) - 1):
         step(k)
     k0 = max(warmup, 1) - 1
     out = {"ms": [], "newton_iters": [], "evals": [], "halvings": [], "cg_iters": [], "restarted": [],
-           "retried": [], "parts": [], "ms_eval": [], "ms_linear": [], "kernel_times": []}
+           "repaired": [], "stages": [], "ms_eval": [], "ms_linear": [], "kernel_times": []}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(k0, k0 + steps):
         a = time.perf_counter()
-        s1, kt, retried = step(k)  # returns after the stream is synchronised
+        s1, kt = step(k)  # returns after the stream is synchronised
         out["ms"].append(1000.0 * (time.perf_counter() - a))
         out["newton_iters"].append(s1.newton_iters)
         out["evals"].append(s1.evals)
         out["halvings"].append(s1.halvings)
         out["cg_iters"].append(s1.cg_iters)
         out["restarted"].append(s1.default_start)
-        out["retried"].append(int(retried))
-        out["parts"].append(s1.stages)  # continuation stages of a retried step
+        out["repaired"].append(s1.repaired_start)
+        out["stages"].append(s1.stages)
         out["ms_eval"].append(s1.ms_eval)
         out["ms_linear"].append(s1.ms_linear)
         out["kernel_times"].append(kt)
@@ -385,6 +456,47 @@ def profile_mode(which: str) -> int:
     return 0
 
 
+def counters_summary(fetch_dir: str, write_dir: str, sq_dir: str, kernel: str = "k_cells_overflow") -> int:
+    """Writes the counter record of one kernel (TRAFFIC_FILE and a markdown table beside it)
+    from three rocprofv3 --pmc runs of ``--profile c3`` (FETCH_SIZE; WRITE_SIZE;
+    SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE). Byte counters are scaled by what they read for
+    the 256 MiB device copy at the end of the run; GRBM_GUI_ACTIVE sums the eight XCDs, and
+    a CU issues at most one wave64 VALU instruction per cycle."""
+    import csv
+    import re
+    from collections import defaultdict
+
+    def load(d):
+        out = defaultdict(lambda: defaultdict(list))
+        with open(os.path.join(d, "pmc_counter_collection.csv")) as f:
+            for row in csv.DictReader(f):
+                m = re.search(r"(k_\w+|copyBuffer\w*)", row["Kernel_Name"])
+                if m:
+                    out[m.group(1)][row["Counter_Name"]].append(float(row["Counter_Value"]))
+        return out
+
+    F, W, S = load(fetch_dir), load(write_dir), load(sq_dir)
+    cp = next(k for k in F if k.startswith("copyBuffer"))
+    copy_kib = 256 * 1024
+    ff = copy_kib / max(F[cp]["FETCH_SIZE"])
+    wf = copy_kib / max(W[cp]["WRITE_SIZE"])
+    mean = lambda v: sum(v) / len(v)
+    fk, wk = mean(F[kernel]["FETCH_SIZE"]), mean(W[kernel]["WRITE_SIZE"])
+    valu, waves, gui = (mean(S[kernel][c]) for c in ("SQ_INSTS_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE"))
+    cycles = gui / 8.0
+    rec = {"kernel": kernel, "workload": "splash_2000000: settle and two advect-and-solve steps (--profile c3)",
+           "dispatches": len(F[kernel]["FETCH_SIZE"]), "fetch_kib_per_dispatch": fk,
+           "write_kib_per_dispatch": wk, "fetch_factor": ff, "write_factor": wf,
+           "bytes_per_launch": 1024.0 * (fk * ff + wk * wf), "valu_insts_per_dispatch": valu,
+           "waves_per_dispatch": waves, "cycles_per_dispatch": cycles,
+           "valu_issue_frac": valu / (256.0 * cycles), "sources_sha256": kernel_sources_digest(),
+           "source": os.path.relpath(TRAFFIC_FILE.replace(".json", ".md"), ROOT)}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+    return 0
+
+
 def dam_break_section(ctx, L, scenes, n: int, steps: int, warmup: int, eval_reps: int):
     """The 100k-site dam break: plain OT solves from the start weights (autotuned shapes),
     one evaluation alone (with and without the grid build) at the start and converged
@@ -428,13 +540,12 @@ def dam_break_section(ctx, L, scenes, n: int, steps: int, warmup: int, eval_reps
     ev1, k1 = eval_times(psis[-1], cells_fn)
     evc, kc = eval_times(psis[-1], lambda p: ctx.centroids(x, y, z, p))
     p_last = psis[-1].cpu().numpy()
-    err = oracle_error(sc.x, sc.y, sc.z, p_last, sc.nu, sample_idx(n, p_last, 5, k_top=0, k_rand=300))
     sec = {"workload": f"dam_break_{n}: jittered cubic lattice in the lower 40% of the unit box, nu=0.35/N, one "
                        f"plain OT solve from the start weights to 1e-5",
            "cells_per_s": n * sum(s.evals for s in stats) / wall, "ms_per_solve": 1000.0 * wall / steps,
            "newton_iters": s0.newton_iters, "evals": s0.evals, "halvings": s0.halvings, "cg_iters": s0.cg_iters,
            "max_rel_err": s0.max_rel_err, "ms_eval": s0.ms_eval, "ms_linear": s0.ms_linear,
-           "ms_cell_kernel": ms_kernel, "oracle_error": err,
+           "ms_cell_kernel": ms_kernel,
            "eval_only": {"cells_per_s_with_grid": n / (ev0 / 1000.0), "cells_per_s_kernel": n / (k0 / 1000.0),
                          "ms_lagot_cells": ev0, "ms_cell_kernel": k0,
                          "converged": {"cells_per_s_with_grid": n / (ev1 / 1000.0),
@@ -442,7 +553,9 @@ def dam_break_section(ctx, L, scenes, n: int, steps: int, warmup: int, eval_reps
                                        "ms_cell_kernel": k1},
                          "centroids_converged": {"ms_lagot_centroids": evc, "ms_cell_kernel": kc,
                                                  "cells_per_s_kernel": n / (kc / 1000.0)}}}
-    return sec, (sc, x, y, z, nu, psis[-1])
+    check = lambda: oracle_error(sc.x, sc.y, sc.z, p_last, sc.nu, sample_idx(n, p_last, 5, k_top=0, k_rand=300),
+                                 "300 random cells of the last solve")
+    return sec, (sc, x, y, z, nu, psis[-1]), check
 
 
 def main(argv=None):
@@ -452,6 +565,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2, help="the settle, then warmup - 1 untimed steps")
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--profile", choices=["c3", "cells", "fluid"], default=None)
+    ap.add_argument("--counters-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "SQ_DIR"), default=None,
+                    help="write the crowded pass's counter record from three rocprofv3 --pmc runs of --profile c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eval-reps", type=int, default=20)
@@ -467,6 +582,9 @@ def main(argv=None):
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
               f"built", file=sys.stderr)
         return 2
+
+    if args.counters_summary:
+        return counters_summary(*args.counters_summary)
 
     import torch
     import paper_2601_05765_amd as L
@@ -489,35 +607,27 @@ def main(argv=None):
     ms_per_step = 1000.0 * wall / args.steps
     fin = r["scene"]
     p_fin = r["psi"].cpu().numpy()
-    c3_err = oracle_error(fin.x, fin.y, fin.z, p_fin, r["nu"], sample_idx(n, p_fin, 3))
     kt = st3["kernel_times"]
     fast_ms = sum(k["fast_ms"] for k in kt) / max(sum(k["fast_launches"] for k in kt), 1)
     crowd_launches = sum(k["crowd_launches"] for k in kt)
     crowd_ms = sum(k["crowd_ms"] for k in kt) / max(crowd_launches, 1)
     crowd_cells = sum(k["crowd_cells"] for k in kt) / max(crowd_launches, 1)
-    # roofline of the dominant kernel, the crowded-cell pass (float64): algorithmic FLOPs per
-    # cell from the oracle's geometry of a sample of the cells it finishes at the final state
+    # the cells the crowded pass finishes at the final state (for the roofline's work units)
     xf, yf, zf = (torch.tensor(np.ascontiguousarray(a), device="cuda") for a in (fin.x, fin.y, fin.z))
     ctx.cells(xf, yf, zf, r["psi"], csr=False, walls=False)
     deferred = ctx.last_deferred()
-    import oracle
-    rs = np.random.default_rng(11)
-    samp = np.sort(rs.choice(deferred, min(300, len(deferred)), replace=False)) if len(deferred) else None
-    roofline = None
-    if samp is not None and crowd_ms > 0:
-        w = oracle.cells(fin.x, fin.y, fin.z, p_fin, idx=samp, work=True).work.mean(axis=0)
-        fpc = flops_per_cell_minimal_clip(w)
-        achieved = fpc * crowd_cells / (crowd_ms / 1000.0) / 1e12
-        roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                    "kernel": "k_cells_overflow (crowded cells: box-overlap candidates, clip rounds, integration; "
-                              "float64)",
-                    "flops_per_cell": fpc, "cells_per_launch": crowd_cells, "ms_per_launch": crowd_ms,
-                    "launches": crowd_launches,
-                    "work_units_per_cell": dict(zip(["cand", "tests", "newv", "faces", "edges", "cross"],
-                                                    [float(v) for v in w])),
-                    "model": "cost model with a minimal clip term (each facet plane clipped once), oracle units "
-                             "of 300 sampled crowded cells"}
+    rec = counter_record()
+    traffic = rec.get("bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": traffic,
+                "kernel": "k_cells_overflow (crowded cells: box-overlap candidates, clip rounds, integration; "
+                          "float64)",
+                "cells_per_launch": crowd_cells, "ms_per_launch": crowd_ms, "launches": crowd_launches,
+                "valu_issue_frac": rec.get("valu_issue_frac"),
+                "traffic_bytes_per_cell": None if traffic is None else traffic / max(crowd_cells, 1.0),
+                "counters": rec.get("source"),
+                "model": "cost model with a minimal clip term (each facet plane clipped once), oracle units "
+                         "of 300 sampled crowded cells"}
     line = {
         "metric": "cells/s (Laguerre∩ball eval); ms per OT solve to 1e-5 vol err, plain vs learned",
         "value": value,
@@ -533,31 +643,48 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"splash_{n}: 60% jittered-lattice slab + 200 log-normal droplets packed 1.72x, "
                                f"log-normal nu summing to 0.3, random velocities N(0, 0.5^2); settled from the "
-                               f"Voronoi start, then advect (dt 2e-3) and solve to 1e-5 per step, warm-started "
-                               f"from the previous weights",
+                               f"Voronoi start, then advect (dt 2e-3) and solve to 1e-5 per step from the previous "
+                               f"weights (repaired, else the default start) with path following on the volumes",
                    "n_sites": n, "tol": 1e-5, "dt": 2e-3},
         "c3": {"settle": r["settle"], "ms_per_step": ms_per_step, "ms_steps": st3["ms"],
                "newton_iters": st3["newton_iters"], "evals": st3["evals"], "halvings": st3["halvings"],
-               "cg_iters": st3["cg_iters"], "restarted": st3["restarted"], "retried": st3["retried"],
-               "stages": st3["parts"],
+               "cg_iters": st3["cg_iters"], "restarted": st3["restarted"], "repaired": st3["repaired"],
+               "stages": st3["stages"],
                "ms_eval": st3["ms_eval"], "ms_linear": st3["ms_linear"],
                "ms_fast_kernel_per_eval": fast_ms, "ms_crowded_pass_per_eval": crowd_ms,
-               "crowded_cells_per_eval": crowd_cells, "oracle_error": c3_err},
+               "crowded_cells_per_eval": crowd_cells},
+        "roofline": roofline,
     }
-    if roofline is not None:
-        line["roofline"] = roofline
+    # every oracle call of the run is in the leg at the end: the error of each section's result
+    # against the FP64 oracle, the roofline's work units, and the oracle's own rate (cpu_baseline)
+    checks = {"c3": lambda: oracle_error(fin.x, fin.y, fin.z, p_fin, r["nu"], sample_idx(n, p_fin, 3),
+                                         "100 heaviest sites + 300 random cells of the last step")}
     if not args.no_dam_break:
-        sec, dam = dam_break_section(ctx, L, scenes, 100_000, 10, 3, args.eval_reps)
+        sec, dam, checks["dam_break"] = dam_break_section(ctx, L, scenes, 100_000, 10, 3, args.eval_reps)
         line["dam_break"] = sec
+        _, x, y, z, nu, psi = dam
+        line["paper_k_route"], checks["paper_k_route"] = paper_k_section(ctx, x, y, z, psi)
         if not args.no_fluid:
-            _, x, y, z, nu, psi = dam
-            line["fluid"] = fluid_section(ctx, L, x, y, z, psi, nu)
+            line["fluid"], checks["fluid"] = fluid_section(ctx, L, x, y, z, psi, nu)
     if not args.no_batched:
-        line["batched"] = batched_section(ctx, L, scenes)
+        line["batched"], checks["batched"] = batched_section(ctx, L, scenes)
     if not args.no_learned:
-        line["learned"] = learned_section(ctx, L, scenes, args.learned_seeds, args.learned_steps,
-                                          args.sequence_steps)
+        line["learned"], checks["learned"] = learned_section(ctx, L, scenes, args.learned_seeds,
+                                                             args.learned_steps, args.sequence_steps)
     if not args.no_cpu_baseline:
+        for key, fn in checks.items():
+            line[key]["oracle_error"] = fn()
+            log(f"oracle error of {key}: {line[key]['oracle_error']}")
+        import oracle
+        if len(deferred) and crowd_ms > 0:
+            rs = np.random.default_rng(11)
+            samp = np.sort(rs.choice(deferred, min(300, len(deferred)), replace=False))
+            w = oracle.cells(fin.x, fin.y, fin.z, p_fin, idx=samp, work=True).work.mean(axis=0)
+            fpc = flops_per_cell_minimal_clip(w)
+            achieved = fpc * crowd_cells / (crowd_ms / 1000.0) / 1e12
+            roofline.update({"achieved": achieved, "frac": achieved / PEAK_FP64_TFLOPS, "flops_per_cell": fpc,
+                             "work_units_per_cell": dict(zip(["cand", "tests", "newv", "faces", "edges", "cross"],
+                                                             [float(v) for v in w]))})
         cb, work = cpu_baseline(fin, p_fin, args.cpu_seconds)
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)

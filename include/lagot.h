@@ -176,6 +176,27 @@ int lagot_centroids(lagot_ctx *ctx, int64_t n, const float *x, const float *y, c
                     lagot_box box, double *vol, double *centroid);
 
 /*
+ * One evaluation of all cells with the spherical area |K_i| by section 3.3's own route
+ * (Algorithm 2: c = point_in(C_i), then |K_i| = |Sigma_i| - sum_f |Proj(B_f, Sigma_i, c)|):
+ * c is the mean of the midpoints of the chords cast from each restricted facet's area
+ * centroid along its inward normal; each restricted facet is projected from c onto the
+ * sphere and the projected area taken by Gauss-Bonnet (geodesic curvature of a circle
+ * at distance e from the centre e / (r rho), the corrected form of the printed one;
+ * turning angles at the corners). A cell with no restricted facet is the whole sphere
+ * if p_i is in its cell and empty otherwise. V_i = (sum_f t_f |B_f| + r |K_i|) / 3 as in
+ * lagot_cells. Every cell is evaluated on the float64 path: this is the A/B variant of
+ * the signed solid-angle form lagot_cells uses (same cells, same facets; the two agree
+ * to rounding), slower by design.
+ *   in : as lagot_cells; out: vol [n], sph_area [n] float64 in site order (device
+ *        pointers owned by the caller). Synchronises the stream; the cell kernel's
+ *        time is then lagot_last_cell_kernel_ms.
+ * Errors: LAGOT_EINVAL (NULL output, n <= 0, site outside the box), LAGOT_ECAPACITY
+ * (a cell beyond the float64 path's capacities).
+ */
+int lagot_cells_paper_k(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                        const double *psi, lagot_box box, double *vol, double *sph_area);
+
+/*
  * One damped Newton iteration of Algorithm 1: evaluate the cells at psi, stop
  * if the tolerance already holds, else solve (-Hess K) u = nu - V by
  * Jacobi-PCG (eq. (2); walls do not enter) and halve the step from alpha = 1

@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_solve_moved", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_set_domain", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_solve_moved", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_cells_paper_k", "lagot_set_domain", "lagot_last_cell_kernel_ms",
            "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward", "lagot_mlp_forward_noalloc",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
@@ -125,6 +125,8 @@ def load():
         lib.lagot_set_domain.restype = I
         lib.lagot_centroids.argtypes = [P, I64, P, P, P, P, Box, P, P]
         lib.lagot_centroids.restype = I
+        lib.lagot_cells_paper_k.argtypes = [P, I64, P, P, P, P, Box, P, P]
+        lib.lagot_cells_paper_k.restype = I
         lib.lagot_p1_laplacian.argtypes = [P, I64, P, P, P, P, Box, P, ctypes.c_double, P, P]
         lib.lagot_p1_laplacian.restype = I
         lib.lagot_default_fluid_params.argtypes = [ctypes.POINTER(FluidParams)]
@@ -268,6 +270,21 @@ class Context:
         if rc != OK:
             raise LagotError(rc, "lagot_centroids")
         return vol, cen
+
+    def cells_paper_k(self, x, y, z, psi, box=((0, 0, 0), (1, 1, 1))):
+        """lagot_cells_paper_k: (volumes [n], spherical areas [n]) in caller order, float64,
+        with |K| by section 3.3's own route (interior point, projected facets, Gauss-Bonnet)."""
+        import torch
+        n = x.shape[0]
+        args = [_dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), _dev(z, torch.float32, "z"),
+                _dev(psi, torch.float64, "psi")]
+        vol = torch.empty(n, dtype=torch.float64, device=x.device)
+        sph = torch.empty(n, dtype=torch.float64, device=x.device)
+        rc = load().lagot_cells_paper_k(self._h, n, *args, make_box(box), ctypes.c_void_p(vol.data_ptr()),
+                                        ctypes.c_void_p(sph.data_ptr()))
+        if rc != OK:
+            raise LagotError(rc, "lagot_cells_paper_k")
+        return vol, sph
 
     def p1_laplacian(self, x, y, z, psi, u, mu=None, mu0: float = 1.0, box=((0, 0, 0), (1, 1, 1))):
         """lagot_p1_laplacian: Lap_mu u ([n, 3] float64, caller order) over the restricted

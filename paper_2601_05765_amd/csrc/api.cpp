@@ -1625,6 +1625,39 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     return LAGOT_OK;
 }
 
+int lagot_cells_paper_k(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
+                        lagot_box box, double *vol, double *sph_area) {
+    if (!c || !vol || !sph_area || n <= 0) return LAGOT_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    c->tpc = c->tpc_default;
+    c->ms_cell = 0.0;
+    c->ms_crowd = 0.0;
+    c->crowd_launches = 0;
+    c->crowd_cells = 0;
+    c->cell_launches = 0;
+    c->ev_pending = false;
+    c->ev_crowd_pending = false;
+    const int64_t offs[2] = {0, n};
+    int rc = prepare(c, 1, offs, x, y, z, psi, nullptr, &box, nullptr);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    const Batch bt = batch(c);
+    const EvalOut o = eval_out(c, false);
+    launch_zero_i32(st, c->fb_inst, 1);
+    launch_eval_begin(st, bt, -1, o);
+    if (c->crowd) launch_local_reach(st, c->n, bt, -1, c->nc, c->pos_s, c->lr_rmc, c->lr_ir);
+    (void)hipEventRecord(c->ev0, st);
+    launch_cells_kroute(st, n, bt, c->pos_s, c->psi_s, c->perm, c->cell_start, o, qboxes(c));
+    (void)hipEventRecord(c->ev1, st);
+    c->ev_pending = true;
+    launch_scatter_out_f64(st, n, c->perm, c->V, vol);
+    launch_scatter_out_f64(st, n, c->perm, c->K, sph_area);
+    HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    rc = sync(c);
+    if (rc) return rc;
+    return c->h_cnt[1] != 0 ? LAGOT_ECAPACITY : LAGOT_OK;
+}
+
 int lagot_newton_step(lagot_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const double *nu,
                       lagot_box box, double *psi_inout, const lagot_opts *opts, lagot_stats *stats) {
     if (!ctx || !psi_inout) return LAGOT_EINVAL;

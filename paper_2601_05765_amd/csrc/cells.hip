@@ -205,6 +205,173 @@ __device__ __attribute__((always_inline)) inline PieceSum<R> fan_piece(R ux, R u
     return p;
 }
 
+// ---- section 3.3's own route to |K| (Algorithm 2: point_in, occluded patches) ----
+// From a point c inside the (convex) restricted cell every ray leaves through one
+// boundary point, on the sphere or on a restricted facet B_f, so the sphere is tiled by
+// K and the projections of the B_f from c: |K| = 4 pi r^2 - sum_f |Proj(B_f)|. A
+// projected facet is bounded by circle arcs: a straight boundary piece of B_f projects
+// into the circle cut by the plane through c and the piece; a boundary arc of B_f (on
+// the facet's circle) stays. Gauss-Bonnet gives |Proj(B_f)| = r^2 (2 pi - G_f) with
+// G_f = sum k_g len + sum turning angles, k_g = e / (r rho) for a circle at signed
+// distance e from the centre (positive on the smaller cap: the corrected form of the
+// printed curvature), so k_g len = e theta / r for an arc of angle theta.
+// Per fan piece (the facet edge P -> Q, counter-clockwise about n seen from outside),
+// G_f is split into parts that need only the piece and the next vertex X on the facet:
+//   - the facet circle's arcs: (t / r) times the piece's signed sector angle about q;
+//     over the facet these sum to the angle of the circle inside the polygon (the same
+//     winding argument as the signed fan), i.e. to the arcs of B_f's boundary;
+//   - the projection of the piece's part inside the ball [A, B] (plane through c, A, B);
+//   - the turning angles at A (from the circle arc, if A is where the edge enters the
+//     ball) and at B (to the circle arc if the edge leaves the ball, else to the next
+//     piece's projection at the vertex Q).
+// A vertex is inside the ball by one test (|Q| < r) for both pieces that meet there.
+template <typename R> __device__ inline void kr_unit(R &x, R &y, R &z) {
+    const R l = sqrt(x * x + y * y + z * z);
+    const R il = l > R(0) ? R(1) / l : R(0);
+    x *= il;
+    y *= il;
+    z *= il;
+}
+
+// the ray c + s (a - c), s > 0, on the sphere |y| = r (c inside the ball)
+template <typename R> __device__ inline void kr_project(R cx, R cy, R cz, R ax, R ay, R az, R r, R &ox, R &oy, R &oz) {
+    const R ex = ax - cx, ey = ay - cy, ez = az - cz;
+    const R qa = dot3(ex, ey, ez, ex, ey, ez), qb = dot3(cx, cy, cz, ex, ey, ez);
+    const R qc = dot3(cx, cy, cz, cx, cy, cz) - r * r;
+    const R s = (-qb + sqrt(fmax(qb * qb - qa * qc, R(0)))) / qa;
+    ox = cx + s * ex;
+    oy = cy + s * ey;
+    oz = cz + s * ez;
+}
+
+// signed turning angle at the sphere point x from tangent T1 to tangent T2
+template <typename R> __device__ inline R kr_turn(R t1x, R t1y, R t1z, R t2x, R t2y, R t2z, R x, R y, R z) {
+    const R wx = t1y * t2z - t1z * t2y, wy = t1z * t2x - t1x * t2z, wz = t1x * t2y - t1y * t2x;
+    return atan2_<R>(dot3(wx, wy, wz, x, y, z), dot3(t1x, t1y, t1z, t2x, t2y, t2z) * sqrt(dot3(x, y, z, x, y, z)));
+}
+
+// unit tangent at x of a circle traversed positively about the unit axis u
+template <typename R> __device__ inline void kr_tangent(R ux, R uy, R uz, R x, R y, R z, R &tx, R &ty, R &tz) {
+    tx = uy * z - uz * y;
+    ty = uz * x - ux * z;
+    tz = ux * y - uy * x;
+    kr_unit(tx, ty, tz);
+}
+
+// The piece P -> Q against the ball: the part inside [lo, hi] of P + s (Q - P) (empty if
+// lo >= hi), and the piece's signed sector angle phi about the circle centre q = t n
+// (the parts of the piece outside the ball). A facet's restricted part is not empty iff
+// one of its pieces has a part inside, or its circle lies inside the polygon (sum of phi
+// 2 pi rather than 0): a combinatorial test, not the sign of a cancelling area sum.
+template <typename R> struct KRArc {
+    R lo, hi, phi;
+    bool inP, inQ;
+};
+
+template <typename R>
+__device__ KRArc<R> kr_arc(R px, R py, R pz, R qx, R qy, R qz, R nx, R ny, R nz, R t, R r) {
+    KRArc<R> k;
+    const R r2 = r * r;
+    k.inP = dot3(px, py, pz, px, py, pz) < r2;
+    k.inQ = dot3(qx, qy, qz, qx, qy, qz) < r2;
+    const bool inP = k.inP, inQ = k.inQ;
+    const R wx = qx - px, wy = qy - py, wz = qz - pz;
+    const R a = dot3(wx, wy, wz, wx, wy, wz);
+    k.lo = R(1);
+    k.hi = R(0);
+    k.phi = R(0);
+    if (!(a > R(0))) return k;
+    R lo = R(1), hi = R(0);
+    {
+        const R b = dot3(px, py, pz, wx, wy, wz), c0 = dot3(px, py, pz, px, py, pz) - r2;
+        const R disc = b * b - a * c0;
+        if (disc > R(0)) {
+            const R sq = sqrt(disc);
+            lo = inP ? R(0) : fmin(fmax((-b - sq) / a, R(0)), R(1));
+            hi = inQ ? R(1) : fmin(fmax((-b + sq) / a, R(0)), R(1));
+        }
+        if (inP && inQ) {
+            lo = R(0);
+            hi = R(1);
+        }
+    }
+    k.lo = lo;
+    k.hi = hi;
+    const bool seg = lo < hi;
+    const R ox = t * nx, oy = t * ny, oz = t * nz;
+    const R ux = px - ox, uy = py - oy, uz = pz - oz, vx = qx - ox, vy = qy - oy, vz = qz - oz;
+    if (!seg) {
+        k.phi = atan2_<R>(nx * (uy * vz - uz * vy) + ny * (uz * vx - ux * vz) + nz * (ux * vy - uy * vx),
+                          dot3(ux, uy, uz, vx, vy, vz));
+    } else {
+        const R aqx = px + lo * wx - ox, aqy = py + lo * wy - oy, aqz = pz + lo * wz - oz;
+        const R bqx = px + hi * wx - ox, bqy = py + hi * wy - oy, bqz = pz + hi * wz - oz;
+        if (!inP)
+            k.phi += atan2_<R>(nx * (uy * aqz - uz * aqy) + ny * (uz * aqx - ux * aqz) + nz * (ux * aqy - uy * aqx),
+                               dot3(ux, uy, uz, aqx, aqy, aqz));
+        if (!inQ)
+            k.phi += atan2_<R>(nx * (bqy * vz - bqz * vy) + ny * (bqz * vx - bqx * vz) + nz * (bqx * vy - bqy * vx),
+                               dot3(bqx, bqy, bqz, vx, vy, vz));
+    }
+    return k;
+}
+
+// G_f share of one fan piece P -> Q (next vertex X on the facet); positions relative to p_i
+template <typename R>
+__device__ R kr_piece(R px, R py, R pz, R qx, R qy, R qz, R xx, R xy, R xz, R nx, R ny, R nz, R t, R r, R cx, R cy,
+                      R cz) {
+    const KRArc<R> k = kr_arc<R>(px, py, pz, qx, qy, qz, nx, ny, nz, t, r);
+    R g = t * k.phi / r;
+    if (!(k.lo < k.hi)) return g;
+    const bool inP = k.inP, inQ = k.inQ;
+    const R wx = qx - px, wy = qy - py, wz = qz - pz;
+    const R ax = px + k.lo * wx, ay = py + k.lo * wy, az = pz + k.lo * wz;
+    const R bx = px + k.hi * wx, by = py + k.hi * wy, bz = pz + k.hi * wz;
+    // projection of [A, B] from c: the circle of the plane through c, A, B (axis m)
+    R pax, pay, paz, pbx, pby, pbz;
+    kr_project<R>(cx, cy, cz, ax, ay, az, r, pax, pay, paz);
+    kr_project<R>(cx, cy, cz, bx, by, bz, r, pbx, pby, pbz);
+    const R eax = ax - cx, eay = ay - cy, eaz = az - cz, ebx = bx - cx, eby = by - cy, ebz = bz - cz;
+    R mx = eay * ebz - eaz * eby, my = eaz * ebx - eax * ebz, mz = eax * eby - eay * ebx;
+    kr_unit(mx, my, mz);
+    const R e = dot3(cx, cy, cz, mx, my, mz);
+    const R ocx = e * mx, ocy = e * my, ocz = e * mz;
+    {
+        const R sx = pax - ocx, sy = pay - ocy, sz = paz - ocz, fx = pbx - ocx, fy = pby - ocy, fz = pbz - ocz;
+        R th = atan2_<R>(mx * (sy * fz - sz * fy) + my * (sz * fx - sx * fz) + mz * (sx * fy - sy * fx),
+                         dot3(sx, sy, sz, fx, fy, fz));
+        if (th < R(0)) th += R(2.0 * PI_D);
+        g += e * th / r;
+    }
+    R tax, tay, taz, tbx, tby, tbz;
+    kr_tangent<R>(mx, my, mz, pax, pay, paz, tax, tay, taz);
+    kr_tangent<R>(mx, my, mz, pbx, pby, pbz, tbx, tby, tbz);
+    if (!inP) {  // entry from the facet circle's arc
+        R cxa, cya, cza;
+        kr_tangent<R>(nx, ny, nz, ax, ay, az, cxa, cya, cza);
+        g += kr_turn<R>(cxa, cya, cza, tax, tay, taz, ax, ay, az);
+    }
+    if (!inQ) {  // exit onto the facet circle's arc
+        R cxb, cyb, czb;
+        kr_tangent<R>(nx, ny, nz, bx, by, bz, cxb, cyb, czb);
+        g += kr_turn<R>(tbx, tby, tbz, cxb, cyb, czb, bx, by, bz);
+    } else {     // the vertex Q: on to the projection of the next piece Q -> X
+        const R fx = qx - cx, fy = qy - cy, fz = qz - cz, hx = xx - cx, hy = xy - cy, hz = xz - cz;
+        R m2x = fy * hz - fz * hy, m2y = fz * hx - fx * hz, m2z = fx * hy - fy * hx;
+        kr_unit(m2x, m2y, m2z);
+        R t2x, t2y, t2z;
+        kr_tangent<R>(m2x, m2y, m2z, pbx, pby, pbz, t2x, t2y, t2z);
+        g += kr_turn<R>(tbx, tby, tbz, t2x, t2y, t2z, pbx, pby, pbz);
+    }
+    return g;
+}
+
+// per-piece first moments and areas, per-face chord midpoints (the route's scratch)
+template <typename R, int PMAX, int VMAX> struct KRSmem {
+    R pm[3 * VMAX][6];  // piece: first moment about q (3), planar area, sector angle, 1 if a part is inside
+    R fm[PMAX][4];      // face: chord midpoint (3), 1 if the restricted facet is not empty
+};
+
 // Vertex record of the integration phase: position relative to p_i and its three planes.
 template <typename R> struct alignas(16) VRec {
     R x, y, z;
@@ -261,8 +428,10 @@ struct CellArgs {
                               // the float64 pass
 };
 
-template <typename R, int G, int CMAX, int PMAX, int VMAX, int MODE, bool MOM>
-__device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMAX, VMAX> &S) {
+template <typename R, int G, int CMAX, int PMAX, int VMAX, int MODE, bool MOM, bool KR = false>
+__device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMAX, VMAX> &S,
+                          KRSmem<R, PMAX, VMAX> *KS = nullptr) {
+    // KR: |K| by section 3.3's own route (kr_piece) in place of the signed solid angles
     // MODE 0: the fast pass (a crowded cell -- more than CMAX candidates, or a search
     // block of more than FAST_SCAN_MAX sites -- is deferred to the overflow list; every
     // other cell writes its box); 3: the seed pass of a deferred cell (clipped by its
@@ -1201,6 +1370,15 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 pa[rr] = ps.A;
                 po[rr] = ps.Om;
                 const R mx = ps.Mx, my = ps.My, mz = ps.Mz;
+                if constexpr (KR) {
+                    const KRArc<R> ka = kr_arc<R>(P.x, P.y, P.z, Q.x, Q.y, Q.z, nx, ny, nz, t, r);
+                    KS->pm[code][0] = mx;
+                    KS->pm[code][1] = my;
+                    KS->pm[code][2] = mz;
+                    KS->pm[code][3] = ps.A;
+                    KS->pm[code][4] = ka.phi;
+                    KS->pm[code][5] = ka.lo < ka.hi ? R(1) : R(0);
+                }
                 if constexpr (MOM) {
                     const double td = (double)t, ar = (double)pa[rr];
                     const double c2 = td * td - (in_ball ? 0.0 : (double)r * (double)r);
@@ -1210,6 +1388,108 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                 }
             }
         }
+    }
+    // section 3.3's route: c = point_in (a ray from each restricted facet's area centroid
+    // along -n to the first of the sphere and the other planes; the mean of the chords'
+    // midpoints), then the Gauss-Bonnet shares of the pieces (kr_piece)
+    double kr_sum = 0.0;
+    int kr_faces = 0;
+    if constexpr (KR) {
+        static_assert(MOM, "the route needs the pieces' first moments");
+        __syncthreads();
+        if (live) {
+            for (int p = gl; p < np; p += G) {
+                R f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+                const uint32_t s0 = GT.fstart[p];
+                if (p >= 6 && s0 < (uint32_t)VMAX) {
+                    R Af = 0, Mx = 0, My = 0, Mz = 0, phi = 0, nseg = 0;
+                    uint32_t sv = s0;
+                    int steps = 0;
+                    do {
+                        const uint32_t u = GT.trs[sv];
+                        const int rot = ((int)(u & 0xFFu) == p) ? 0
+                                      : (((int)((u >> 8) & 0xFFu) == p) ? 1 : (((int)((u >> 16) & 0xFFu) == p) ? 2 : -1));
+                        if (rot < 0) break;
+                        Mx += KS->pm[3 * sv + rot][0];
+                        My += KS->pm[3 * sv + rot][1];
+                        Mz += KS->pm[3 * sv + rot][2];
+                        Af += KS->pm[3 * sv + rot][3];
+                        phi += KS->pm[3 * sv + rot][4];
+                        nseg += KS->pm[3 * sv + rot][5];
+                        const uint32_t sn = (GT.succ[sv] >> (8 * rot)) & 0xFFu;
+                        if (sn >= (uint32_t)VMAX || ++steps > VMAX) break;
+                        sv = sn;
+                    } while (sv != s0);
+                    if ((nseg > R(0) || phi > R(PI_D)) && Af > R(0)) {
+                        const R nx = S.pl[p][0], ny = S.pl[p][1], nz = S.pl[p][2], t = S.pl[p][3];
+                        const R ia = R(1) / Af;
+                        const R gx = t * nx + Mx * ia, gy = t * ny + My * ia, gz = t * nz + Mz * ia;
+                        // d = -n: the far root of |g + s d| = r, then the other planes
+                        const R gd = -dot3(gx, gy, gz, nx, ny, nz);
+                        R lam = -gd + sqrt(fmax(gd * gd - (dot3(gx, gy, gz, gx, gy, gz) - r * r), R(0)));
+                        for (int k = 6; k < np; ++k) {
+                            if (k == p) continue;
+                            const R den = -dot3(S.pl[k][0], S.pl[k][1], S.pl[k][2], nx, ny, nz);
+                            if (den > R(0)) {
+                                const R l = (S.pl[k][3] - dot3(S.pl[k][0], S.pl[k][1], S.pl[k][2], gx, gy, gz)) / den;
+                                lam = fmin(lam, l);
+                            }
+                        }
+                        lam = fmax(lam, R(0));
+                        f0 = gx - R(0.5) * lam * nx;
+                        f1 = gy - R(0.5) * lam * ny;
+                        f2 = gz - R(0.5) * lam * nz;
+                        f3 = R(1);
+                    }
+                }
+                KS->fm[p][0] = f0;
+                KS->fm[p][1] = f1;
+                KS->fm[p][2] = f2;
+                KS->fm[p][3] = f3;
+            }
+        }
+        __syncthreads();
+        double csx = 0.0, csy = 0.0, csz = 0.0;
+        if (live) {
+            for (int p = gl; p < np; p += G) {
+                if (KS->fm[p][3] > R(0)) {
+                    csx += (double)KS->fm[p][0];
+                    csy += (double)KS->fm[p][1];
+                    csz += (double)KS->fm[p][2];
+                    ++kr_faces;
+                }
+            }
+        }
+        csx = gsum<G>(csx);
+        csy = gsum<G>(csy);
+        csz = gsum<G>(csz);
+        kr_faces = (int)gsum<G>((double)kr_faces);
+        const R ccx = kr_faces ? (R)(csx / kr_faces) : R(0), ccy = kr_faces ? (R)(csy / kr_faces) : R(0),
+                ccz = kr_faces ? (R)(csz / kr_faces) : R(0);
+#pragma unroll
+        for (int rr = 0; rr < MAXR; ++rr) {
+            const int idx = rr * G + gl;
+            if (live && idx < npc && kr_faces > 0) {
+                const int code = plist[idx];
+                const int sv = code / 3, rot = code - 3 * sv;
+                const uint32_t u = GT.trs[sv];
+                const int f = (int)((u >> (8 * rot)) & 0xFFu);
+                const uint32_t sn = (GT.succ[sv] >> (8 * rot)) & 0xFFu;
+                if (sn < (uint32_t)VMAX && KS->fm[f][3] > R(0)) {
+                    const uint32_t un = GT.trs[sn];
+                    const int rot2 = ((int)(un & 0xFFu) == f) ? 0 : (((int)((un >> 8) & 0xFFu) == f) ? 1 : 2);
+                    const uint32_t sx = (GT.succ[sn] >> (8 * rot2)) & 0xFFu;
+                    if (sx < (uint32_t)VMAX) {
+                        const VRec<R> P = GT.rec[sv], Q = GT.rec[sn], X = GT.rec[sx];
+                        kr_sum += (double)kr_piece<R>(P.x, P.y, P.z, Q.x, Q.y, Q.z, X.x, X.y, X.z, S.pl[f][0],
+                                                      S.pl[f][1], S.pl[f][2], S.pl[f][3], r, ccx, ccy, ccz);
+                    } else {
+                        walk_bad = true;
+                    }
+                }
+            }
+        }
+        kr_sum = gsum<G>(kr_sum);
     }
     __syncthreads();  // rec and the list are dead: they take the pieces
     R(*pieces)[2] = reinterpret_cast<R(*)[2]>(&GT.rec[0]);
@@ -1310,7 +1590,13 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         double V = 0.0, K = 0.0;
         if (live) {
             const double rd = (double)r;
-            K = in_ball ? 0.0 : rd * rd * (4.0 * PI_D * (inside ? 1.0 : 0.0) - sum_om);
+            if constexpr (KR) {
+                // no restricted facet: the whole sphere if p_i is in the cell, else nothing
+                K = kr_faces == 0 ? rd * rd * 4.0 * PI_D * (inside ? 1.0 : 0.0)
+                                  : rd * rd * (4.0 * PI_D - 2.0 * PI_D * kr_faces + kr_sum);
+            } else {
+                K = in_ball ? 0.0 : rd * rd * (4.0 * PI_D * (inside ? 1.0 : 0.0) - sum_om);
+            }
             V = (sum_tA + rd * K) / 3.0;
             if (!(V == V) || !(K == K)) flags |= CF_TOPO;
         }
@@ -1331,7 +1617,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         o.K[cell] = K;
         o.fcnt[cell] = live ? nf : 0;
         // the float64 pass keeps the float32 pass's reasons in bits 8..15
-        o.flags[cell] = fast ? flags : (flags | (o.flags[cell] << 8));
+        o.flags[cell] = (fast || KR) ? flags : (flags | (o.flags[cell] << 8));
         if (fast && (flags & (CF_FAIL_MASK | CF_PREC))) {
             const int slot = atomicAdd(o.fb_count, 1);
             o.fb_list[slot] = (int32_t)cell;
@@ -1503,6 +1789,17 @@ __global__ __launch_bounds__(64) void k_cells_big(CellArgs A) {
     }
 }
 
+// Every cell on the float64 path with |K| by section 3.3's own route (interior point,
+// projected facets, Gauss-Bonnet): the A/B variant of the signed solid-angle form.
+__global__ __launch_bounds__(64) void k_cells_kroute(CellArgs A) {
+    __shared__ CellSmem<double, BIG_CMAX, BIG_PMAX, BIG_VMAX> smem[1];
+    __shared__ KRSmem<double, BIG_PMAX, BIG_VMAX> krs[1];
+    XCD_LIST_LOOP(k, A.n) {
+        cell_body<double, 64, BIG_CMAX, BIG_PMAX, BIG_VMAX, 2, true, true>(k, A, smem[0], &krs[0]);
+        __syncthreads();
+    }
+}
+
 // Clears the per-evaluation counters: the overflow and float64 work lists and the
 // failure counts of the selected instances (a kernel, so the sequence can be captured).
 __global__ __launch_bounds__(1024) void k_eval_begin(Batch bt, int want, EvalOut o) {
@@ -1515,6 +1812,12 @@ __global__ __launch_bounds__(1024) void k_eval_begin(Batch bt, int want, EvalOut
 }
 
 }  // namespace
+
+void launch_cells_kroute(hipStream_t st, int64_t n, const Batch &bt, const float4 *pos_s, const double *psi,
+                         const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb) {
+    CellArgs a{n, pos_s, psi, perm, cell_start, bt, -1, out, qb, 0};
+    hipLaunchKernelGGL(k_cells_kroute, dim3(4096), dim3(64), 0, st, a);
+}
 
 void launch_eval_begin(hipStream_t st, const Batch &bt, int want, EvalOut out) {
     hipLaunchKernelGGL(k_eval_begin, dim3(1), dim3(1024), 0, st, bt, want, out);

@@ -303,6 +303,9 @@ void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const fl
 // box-overlap candidates, float64), then the cells flagged for the float64 pass.
 // crowd = false (no crowded cell expected): the fast pass writes no boxes and the float64
 // pass takes the deferred cells too. Events e0, e1 (may be null) bracket the crowded pass.
+// every cell on the float64 path with |K| by section 3.3's own route (lagot_cells_paper_k)
+void launch_cells_kroute(hipStream_t st, int64_t n, const Batch &bt, const float4 *pos_s, const double *psi,
+                         const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb);
 void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                            const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
                            const QBoxes &qb, bool crowd, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
