@@ -113,7 +113,8 @@ typedef struct {
     int fallback_cells;  /* cells redone on the large-capacity float64 path (all evals)    */
     int failed_cells;    /* cells that exceeded even the large-capacity path (last eval)   */
     int cell_launches;   /* launches of the float32 cell kernel (one per evaluation)      */
-    int learned_accepted;/* 1 if the learned guess replaced the start weights             */
+    int learned_accepted;/* 0, or 1 + the halvings of the network's correction when the
+                            learned guess replaced the start weights                   */
     int default_start;   /* 1 if an empty start cell forced the default start weights     */
     int repaired_start;  /* 1 if empty start cells were given the default weight (the other
                             weights kept)                                                   */
@@ -269,11 +270,14 @@ int lagot_solve_batched(lagot_ctx *ctx, int32_t n_inst, const int64_t *offsets, 
 
 /*
  * Learned warm start (not part of the paper's method). With opts->use_learned set,
- * lagot_solve evaluates the network's guess like a Newton trial step from the given
- * start weights: it replaces them only if every cell of the guess keeps at least the
- * KMT floor eps0 = 1/2 min(min nu, min V(psi_start)) and both ||nu - V||_2 and
- * max_i |V_i - nu_i| / nu_i are smaller than at the start; eps0 stays that of the
- * given start, and Newton then runs to the tolerance as usual.
+ * lagot_solve takes the network's correction like a Newton step from the given start
+ * weights: psi_start + beta s^2 out for beta = 1, 1/2, 1/4 (Algorithm 1's step halving),
+ * the first trial that keeps every cell at least at the KMT floor
+ * eps0 = 1/2 min(min nu, min V(psi_start)) and makes both ||nu - V||_2 and
+ * max_i |V_i - nu_i| / nu_i smaller than at the start replaces the start (stats
+ * learned_accepted = 1 + the halvings); eps0 stays that of the given start, and Newton
+ * then runs to the tolerance as usual. A start with an empty cell is left to the repair
+ * and restart of empty_start_fallback (no guess is tried).
  * Inputs of site i (64 bf16, row-major n x 64): offsets (p_j - p_i)/s_i of its 16 nearest
  * sites in ascending (distance, index), psi_prev_i / s_i^2, nu_i / mean(nu), and the
  * relative volume mismatch (nu - V)/nu under the previous weights of site i and of its

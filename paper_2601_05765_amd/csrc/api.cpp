@@ -466,6 +466,7 @@ CgBufs cg_bufs(const lagot_ctx *c) {
     g.cgst = c->cg_cgst;
     g.kbase = c->misc + 2;
     g.remaining = c->misc + 3;
+    g.maxit = c->misc + 7;
     return g;
 }
 
@@ -952,6 +953,7 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
         }
         k += m;
         HIP_TRY(hipMemcpyAsync(c->h_cnt + 8, c->misc + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(c->h_cnt + 10, c->misc + 7, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         int rc = sync(c);
         if (rc) return rc;
         if (c->h_cnt[8] == 0) break;
@@ -1030,9 +1032,10 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o, bool graph) {
             if (rc) return rc;
         }
     }
-    // chunk length for the next direction: about this solve's iteration count (a margin
-    // of a quarter measured slower: the launches after convergence are not free)
-    c->cg_chunk = std::min(64, std::max(8, (k + 3) / 4 * 4));
+    // chunk length for the next direction: this solve's iteration count (the iterations
+    // it ran, not the launches: a launch after convergence returns at once but is not
+    // free) plus two, in steps of four (graph mode captures one chunk per length)
+    c->cg_chunk = std::min(64, std::max(4, (c->h_cnt[10] + 2 + 3) / 4 * 4));
     launch_cg_finish(st, bt, c->cg_sub, o.cg_rtol * o.cg_rtol, cg_bufs(c), c->herr, c->ctl, c->phase);
     return LAGOT_OK;
 }
@@ -1042,9 +1045,12 @@ struct CallTimes {
     int extra_evals = 0;
 };
 
-// Learned guess for a single instance, evaluated like a trial step from the start
-// weights into the second set of outputs: kept if every cell keeps eps0 and both the
-// residual norm and the largest relative volume error (the stop test) drop.
+// Learned guess for a single instance, taken like a Newton step from the start weights:
+// psi + beta s^2 out for beta = 1, 1/2, 1/4 (Algorithm 1's step halving applied to the
+// network's correction, so that a few outlying weights that empty cells at the full step
+// do not throw the whole guess away), each evaluated into the second set of outputs; the
+// first that keeps every cell above eps0 and lowers both the residual norm and the largest
+// relative volume error (the stop test) is kept. *accepted = 1 + the halvings taken, or 0.
 int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
     *accepted = 0;
     const Batch bt = batch(c);
@@ -1063,21 +1069,24 @@ int learned_guess(lagot_ctx *c, CallTimes &tm, int *accepted) {
     if (!rc) rc = ensure_alt(c);
     if (rc) return rc;
     mlp_forward_dev(c, (int)c->n, c->feat_s, c->inf_a, c->inf_b, c->mlp_out);
-    launch_apply_guess(st, c->n, c->psi_s, c->nu_s, c->mlp_out, c->psi_trial, c->pos_s);
-    launch_rmax(st, bt, -1, c->psi_trial, c->rmax);
-    swap_alt(c);  // the guess's cells go to the second output set
-    evaluate(c, -1, c->psi_trial, false, c->ev2);
-    swap_alt(c);
-    tm.extra_evals++;
-    HIP_TRY(hipMemcpyAsync(h + 4, c->ev2, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hf + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hf + 2, c->misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    rc = sync(c);
-    if (rc) return rc;
-    if (hf[2] == 0 && hf[1] == 0 && h[7] >= eps0 && h[6] < h[2] && h[5] < h[1]) {
+    constexpr int GUESS_HALVINGS = 2;
+    for (int k = 0; k <= GUESS_HALVINGS && !*accepted; ++k) {
+        launch_apply_guess(st, c->n, c->psi_s, c->nu_s, c->mlp_out, std::ldexp(1.0, -k), c->psi_trial, c->pos_s);
+        launch_rmax(st, bt, -1, c->psi_trial, c->rmax);
+        swap_alt(c);  // the guess's cells go to the second output set
+        evaluate(c, -1, c->psi_trial, false, c->ev2);
+        swap_alt(c);
+        tm.extra_evals++;
+        HIP_TRY(hipMemcpyAsync(h + 4, c->ev2, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hf + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hf + 2, c->misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        rc = sync(c);
+        if (rc) return rc;
+        if (hf[2] == 0 && hf[1] == 0 && h[7] >= eps0 && h[6] < h[2] && h[5] < h[1]) *accepted = 1 + k;
+    }
+    if (*accepted) {
         HIP_TRY(hipMemcpyAsync(c->psi_s, c->psi_trial, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st));
         swap_alt(c);
-        *accepted = 1;
     } else {
         // back to the start weights, whose cells are still in the first output set
         launch_psi_shadow(st, c->n, c->psi_s, c->pos_s);

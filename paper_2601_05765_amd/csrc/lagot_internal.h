@@ -214,6 +214,7 @@ struct CgBufs {
     int32_t *cgst;           // [B][4] iterations done, breakdown, converged, unused
     int32_t *kbase;          // [1] index of the first iteration of the next chunk
     int32_t *remaining;      // [1] instances still iterating after the last chunk
+    int32_t *maxit;          // [1] most iterations any instance has done in this solve
 };
 
 // Parameters of the velocity system of the fluid step (section 5, eq. (4)).
@@ -407,7 +408,7 @@ void launch_adam(hipStream_t st, int64_t np, float *p, const float *g, float *m1
 void launch_to_bf16(hipStream_t st, int64_t n, const float *x, uint16_t *y);
 void launch_gather_rows(hipStream_t st, int m, const int32_t *idx, const uint16_t *F, const float *T, uint16_t *Fb,
                         float *Tb);
-void launch_apply_guess(hipStream_t st, int64_t n, const double *psi_prev, const double *nu, const float *out,
+void launch_apply_guess(hipStream_t st, int64_t n, const double *psi_prev, const double *nu, const float *out, double beta,
                         double *psi_new, float4 *pos_s);
 enum { MLP_EPI_STORE = 0, MLP_EPI_BIAS_GELU = 1, MLP_EPI_GELU_BACK = 2 };
 

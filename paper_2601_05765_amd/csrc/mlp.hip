@@ -330,13 +330,15 @@ __global__ void k_gather_rows(int m, const int32_t *__restrict__ idx, const uint
     if (v == 0 && T) Tb[r] = T[src];
 }
 
-// psi_guess = psi_prev + s^2 * out, s = nu^(1/3) (grid order)
+// psi_guess = psi_prev + beta s^2 out, s = nu^(1/3) (grid order; beta: the step along the
+// network's correction)
 __global__ void k_apply_guess(int64_t n, const double *__restrict__ psi_prev, const double *__restrict__ nu,
-                              const float *__restrict__ out, double *__restrict__ psi_new, float4 *__restrict__ pos_s) {
+                              const float *__restrict__ out, double beta, double *__restrict__ psi_new,
+                              float4 *__restrict__ pos_s) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double s = cbrt(nu[i]);
-    const double v = psi_prev[i] + s * s * (double)out[i];
+    const double v = psi_prev[i] + beta * s * s * (double)out[i];
     psi_new[i] = v;
     pos_s[i].w = (float)v;
 }
@@ -397,8 +399,9 @@ void launch_gather_rows(hipStream_t st, int m, const int32_t *idx, const uint16_
 }
 
 void launch_apply_guess(hipStream_t st, int64_t n, const double *psi_prev, const double *nu, const float *out,
-                        double *psi_new, float4 *pos_s) {
-    hipLaunchKernelGGL(k_apply_guess, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi_prev, nu, out, psi_new, pos_s);
+                        double beta, double *psi_new, float4 *pos_s) {
+    hipLaunchKernelGGL(k_apply_guess, dim3(nblocks(n, 256)), dim3(256), 0, st, n, psi_prev, nu, out, beta, psi_new,
+                       pos_s);
 }
 
 }  // namespace lagot

@@ -548,21 +548,26 @@ __global__ __launch_bounds__(SCB) void k_cg_scalars(Batch bt, int spt, int m, in
         for (int q = 0; q < 4; ++q) cg.sc[8 * b + 4 * slot + q] = S[q];
 }
 
-// After a chunk: advance kbase; count instances still iterating.
+// After a chunk: advance kbase; count instances still iterating; the most iterations
+// any active instance has done (sizes the next solve's chunks).
 __global__ __launch_bounds__(1024) void k_cg_advance(Batch bt, int chunk, int cap, CgBufs cg) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
+    __shared__ int cnt, mx;
+    if (threadIdx.x == 0) cnt = mx = 0;
     __syncthreads();
-    int mine = 0;
+    int mine = 0, most = 0;
     for (int b = threadIdx.x; b < bt.B; b += 1024) {
         const int32_t *st = cg.cgst + 4 * b;
-        mine += bt.phase[b] == PH_ACTIVE && st[1] == 0 && st[2] == 0 && st[0] < cap;
+        if (bt.phase[b] != PH_ACTIVE) continue;
+        mine += st[1] == 0 && st[2] == 0 && st[0] < cap;
+        most = max(most, st[0]);
     }
     if (mine) atomicAdd(&cnt, mine);
+    if (most) atomicMax(&mx, most);
     __syncthreads();
     if (threadIdx.x == 0) {
         *cg.kbase += chunk;
         *cg.remaining = cnt;
+        *cg.maxit = mx;
     }
 }
 

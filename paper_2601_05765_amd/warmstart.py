@@ -93,9 +93,10 @@ def train(ctx, feats, targets, epochs: int = 6, batch: int = 4096, lr: float = 1
 
 
 def sequence(ctx, sc, steps: int, dt: float = 2e-3, use_learned: bool = False, tol: float = 1e-5, psi_start=None,
-             log=print):
+             log=print, cg_rtol: float = 1e-6, state: dict | None = None):
     """Advect-and-solve sequence from converged weights; per-step solve statistics (a failed
-    solve is recorded and the sequence goes on from its last accepted weights)."""
+    solve is recorded and the sequence goes on from its last accepted weights). ``state``
+    receives the last scene and weights."""
     import torch
     import paper_2601_05765_amd as L
     nu = _t(sc.nu, torch.float64)
@@ -107,7 +108,8 @@ def sequence(ctx, sc, steps: int, dt: float = 2e-3, use_learned: bool = False, t
         x, y, z = _t(cur.x, torch.float32), _t(cur.y, torch.float32), _t(cur.z, torch.float32)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=tol, use_learned=int(use_learned)), check=False)
+        st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=tol, use_learned=int(use_learned), cg_rtol=cg_rtol),
+                       check=False)
         torch.cuda.synchronize()
         ms = 1000 * (time.perf_counter() - t0)
         out.append({"step": k + 1, "ms": ms, "status": st.status, "newton_iters": st.newton_iters,
@@ -115,4 +117,7 @@ def sequence(ctx, sc, steps: int, dt: float = 2e-3, use_learned: bool = False, t
                     "max_rel_err": st.max_rel_err})
         log(f"step {k + 1}: {'learned' if use_learned else 'plain'} {ms:.1f} ms, {st.newton_iters} it, "
             f"accepted={st.learned_accepted}")
+    if state is not None:
+        state["scene"] = cur
+        state["psi"] = psi
     return out

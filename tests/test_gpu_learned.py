@@ -1,18 +1,21 @@
 """The learned warm start inside lagot_solve (opts.use_learned = 1) against the FP64 oracle.
 
-The network's guess is a trial start: it is kept only when every cell keeps the KMT floor
-eps0 of the start weights and both the residual norm and the largest relative volume error
-drop; Newton then runs to the tolerance from whichever start was kept (Algorithm 1 with
-the guess as its first iterate). Two networks with a known outcome are used:
+The network's correction is taken like a Newton step from the start weights, halved up to
+twice: psi + beta s^2 out for beta = 1, 1/2, 1/4; the first trial that keeps every cell at
+the KMT floor eps0 of the start weights and lowers both the residual norm and the largest
+relative volume error is kept (learned_accepted = 1 + the halvings); Newton then runs to
+the tolerance from whichever start was kept. The networks have known outcomes:
 
-  * a hand-built network that outputs a damped Jacobi step from its input (nu - V)/nu:
-    hidden unit 0 carries 16 f + 8 through three GELU layers (GELU is the identity to
-    3e-7 there), the output layer maps it back to 0.1 f, so the guess is
-    psi + 0.1 nu^(2/3) (nu - V)/nu. On slab_uniform(1000, 0) from psi0 the oracle finds
-    that guess keeps min V >= 3.2 eps0 and lowers ||g|| by 22% and the largest relative
-    error by 10%: it must be kept;
-  * the He-normal initialisation (seed 11): its guess empties cells (oracle: min V = 0)
-    and must be rejected, after which the solve is the plain solve, bit for bit.
+  * hand-built networks that output a damped Jacobi step k f from their input
+    f = (nu - V)/nu: hidden unit 0 carries 16 f + 8 through three GELU layers (GELU is the
+    identity to 3e-7 there), the output layer maps it back to k f, so the trial is
+    psi + beta k nu^(2/3) (nu - V)/nu. On slab_uniform(1000, 0) from psi0 the oracle gives
+    (min V / eps0, ||g|| ratio, max rel err ratio) at beta = 1, 1/2, 1/4:
+      k = 0.1: (3.21, 0.77, 0.90) kept at the full step;
+      k = 0.4: (0.00, 0.68, 1.16), then (3.37, 0.61, 0.89): kept at beta = 1/2;
+      k = 0.8: empty, empty, then (3.37, 0.61, 0.89): kept at beta = 1/4;
+      k = 1.6: a cell empties at every beta; k = -0.1: ||g|| grows at every beta (1.24,
+      1.12, 1.06): both rejected, after which the solve is the plain solve, bit for bit.
 """
 import sys
 
@@ -78,13 +81,27 @@ def test_learned_guess_kept(oracle_mod):
     assert err <= 1e-5
 
 
-def test_learned_guess_rejected_is_plain_solve(oracle_mod):
-    _say("case: learned solve, random network (guess must be rejected), bit-identical to the plain solve")
+@pytest.mark.parametrize("k,kept", [(0.4, 2), (0.8, 3)])
+def test_learned_guess_kept_after_halving(oracle_mod, k, kept):
+    _say(f"case: learned solve, damped-Jacobi network k={k}, slab_uniform 1k (guess kept after {kept - 1} halvings)")
+    import paper_2601_05765_amd as L
+    ctx = L.Context()
+    _set(ctx, jacobi_params(k=k))
+    sc = scenes.slab_uniform(1000, 0)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5, use_learned=1))
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.learned_accepted == kept
+    assert _oracle_err(oracle_mod, sc, psi.cpu().numpy()) <= 1e-5
+
+
+@pytest.mark.parametrize("k", [1.6, -0.1])
+def test_learned_guess_rejected_is_plain_solve(oracle_mod, k):
+    _say(f"case: learned solve, damped-Jacobi network k={k} (guess must be rejected), bit-identical to the plain solve")
     import torch
     import paper_2601_05765_amd as L
-    from paper_2601_05765_amd import warmstart
     ctx = L.Context()
-    _set(ctx, warmstart.init_params(11))
+    _set(ctx, jacobi_params(k=k))
     sc = scenes.slab_uniform(1000, 0)
     x, y, z, nu, psi = _dev(sc)
     st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5, use_learned=1))
