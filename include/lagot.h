@@ -75,7 +75,9 @@ typedef struct {
                             (bounded so no other neighbour loses its site, and by twice the
                             local mean weight), and if a cell is still empty restart from the
                             default start: the common weight (1.2 (3 nu_mean / 4 pi)^(1/3))^2 of
-                            the instance (a Voronoi start, no empty cell); 0: LAGOT_EEMPTY      */
+                            the instance (a Voronoi start, no empty cell). An instance with more
+                            than 64 empty start cells, and more than 1% of its cells, restarts
+                            at once (no repair); 0: LAGOT_EEMPTY                                 */
     int autotune;        /* 1: when threads_per_cell is 0, time the cell kernel with 16, 32 and 64
                             lanes per cell, and the PCG kernels with four block shapes, on the
                             first solve of each size and density class, and keep the fastest in
@@ -102,6 +104,12 @@ typedef struct {
                             0 (default): Algorithm 1 from the start weights                       */
     int stage_newton;    /* Newton iteration limit of an intermediate stage        (default 8)    */
     double stage_tol;    /* tolerance of the intermediate stages                   (default 1e-2) */
+    int step_start;      /* 0 (default): each Newton iteration's step search starts at alpha = 1;
+                            1: at min(1, 2 x the step length accepted by the previous iteration
+                            of the call or continuation stage) -- Algorithm 1 does not say where
+                            the search restarts; after short accepted steps this saves the
+                            evaluations of trials that would be halved again                   */
+    int reserved;        /* must be 0                                                            */
 } lagot_opts;
 
 typedef struct {
@@ -343,6 +351,16 @@ int lagot_set_threads_per_cell(lagot_ctx *ctx, int threads_per_cell);
  * 2x128, 4x128, 2x64 and 4x64 and keeps the fastest. Affects speed only.
  * Returns LAGOT_EINVAL for other shapes. */
 int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block);
+
+/* How a Jacobi-PCG iteration of the Newton direction is launched. One kernel per iteration
+ * forms each neighbour's direction entry from its whole 32-byte record (one global
+ * synchronisation per iteration, but 32 bytes gathered per matrix entry); two kernels
+ * write every row's entry first (8 bytes per row) and then take the product from those
+ * (8 bytes gathered per entry, one more launch). mode 0 (default): two kernels when an
+ * instance of the call has more than 2048 partial sums (about 131,000 rows), else one;
+ * 1: always one; 2: always two. The same arithmetic per row: the directions agree to the
+ * rounding of the partial sums. Affects speed only. Errors: LAGOT_EINVAL. */
+int lagot_set_cg_split(lagot_ctx *ctx, int mode);
 
 /*
  * Convex polyhedral domain {x : n_w . x <= c_w, w < nplanes} in place of the box walls

@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_solve_moved", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_cells_paper_k", "lagot_set_domain", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_solve_moved", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_set_cg_split", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_cells_paper_k", "lagot_set_domain", "lagot_last_cell_kernel_ms",
            "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward", "lagot_mlp_forward_noalloc",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
@@ -57,7 +57,8 @@ class Opts(ctypes.Structure):
                 ("cg_rtol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("threads_per_cell", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("use_learned", ctypes.c_int), ("empty_start_fallback", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("residual_test", ctypes.c_int),
-                ("continuation", ctypes.c_int), ("stage_newton", ctypes.c_int), ("stage_tol", ctypes.c_double)]
+                ("continuation", ctypes.c_int), ("stage_newton", ctypes.c_int), ("stage_tol", ctypes.c_double),
+                ("step_start", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -121,6 +122,8 @@ def load():
         lib.lagot_set_threads_per_cell.restype = I
         lib.lagot_set_cg_shape.argtypes = [P, I, I]
         lib.lagot_set_cg_shape.restype = I
+        lib.lagot_set_cg_split.argtypes = [P, I]
+        lib.lagot_set_cg_split.restype = I
         lib.lagot_set_domain.argtypes = [P, ctypes.c_int, P]
         lib.lagot_set_domain.restype = I
         lib.lagot_centroids.argtypes = [P, I64, P, P, P, P, Box, P, P]
@@ -368,6 +371,13 @@ class Context:
         rc = load().lagot_set_cg_shape(self._h, int(lanes_per_row), int(rows_per_block))
         if rc != OK:
             raise LagotError(rc, "lagot_set_cg_shape")
+
+    def set_cg_split(self, mode: int) -> None:
+        """lagot_set_cg_split: 0 auto (two launches per PCG iteration for large instances),
+        1 always one launch, 2 always two."""
+        rc = load().lagot_set_cg_split(self._h, int(mode))
+        if rc != OK:
+            raise LagotError(rc, "lagot_set_cg_split")
 
     def set_threads_per_cell(self, tpc: int) -> None:
         rc = load().lagot_set_threads_per_cell(self._h, int(tpc))

@@ -82,6 +82,7 @@ struct lagot_ctx {
     InstCtl *ctl = nullptr;
     double *ev = nullptr, *ev2 = nullptr, *ev_nu = nullptr, *part_ev = nullptr;
     int32_t *fb_inst = nullptr, *fail_inst = nullptr, *bad_inst = nullptr, *herr = nullptr, *counts = nullptr;
+    int32_t *nempty = nullptr;  // [cap_B] empty start cells per instance
     int32_t *misc = nullptr;  // [0] float64 work-list length [1] feature errors [2] kbase [3] remaining
                               // [4] overflow work-list length [5] large cell boxes
     // cell boxes and the box grid of the crowded-cell pass
@@ -135,7 +136,8 @@ struct lagot_ctx {
     int2 *hrow = nullptr;       // packed Hessian rows: (start within the tile's region, length)
     int2 *hent = nullptr;       // [cap_hent_T * TILE * FCAP] packed entries, one region per tile
     int cap_hent_T = 0;
-    double *cg_vec = nullptr;   // rws[2] (4 doubles per row each), p, x: 10 doubles per row
+    double *cg_vec = nullptr;   // rws[2] (4 doubles per row each), p, x, u: 11 doubles per row
+    int cg_split = 0;           // PCG iteration: 0 two launches for large instances, 1 always one, 2 always two
     double *cg_part = nullptr;  // 7 * 4 * cap_T
     double *cg_cgs = nullptr;   // 4 * cap_B
     double *cg_sc = nullptr;    // 8 * cap_B
@@ -211,7 +213,7 @@ void free_sites(lagot_ctx *c) {
 void free_inst(lagot_ctx *c) {
     free_ptrs(c->off, c->tile_inst, c->tile_row, c->first_tile, c->grid, c->box, c->rmax, c->phase, c->ctl, c->ev,
               c->ev2, c->ev_nu, c->part_ev, c->fb_inst, c->fail_inst, c->bad_inst, c->herr, c->cg_part, c->cg_cgs,
-              c->cg_cgst, c->qgrid, c->cg_sc, c->cgrid);
+              c->cg_cgst, c->qgrid, c->cg_sc, c->cgrid, c->nempty);
 }
 
 void free_alt(lagot_ctx *c) {
@@ -328,7 +330,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->qent, (size_t)QREG_MAX * N));
     HIP_TRY(dalloc(&c->qlarge, N));
     HIP_TRY(dalloc(&c->qdstart, N + 1));
-    HIP_TRY(dalloc(&c->cg_vec, 10 * N));
+    HIP_TRY(dalloc(&c->cg_vec, 11 * N));
     HIP_TRY(dalloc(&c->csr_cnt, N + 1));
     HIP_TRY(dalloc(&c->csr_start, N + 1));
     HIP_TRY(dalloc(&c->csr_tmp, N / 1024 + 16));
@@ -366,6 +368,7 @@ int ensure_inst(lagot_ctx *c, int B, int T) {
     HIP_TRY(dalloc(&c->cg_cgst, 4 * b));
     HIP_TRY(dalloc(&c->qgrid, (size_t)QLEV * b));
     HIP_TRY(dalloc(&c->cgrid, b));
+    HIP_TRY(dalloc(&c->nempty, b));
     c->cap_B = B;
     c->cap_T = T;
     return LAGOT_OK;
@@ -460,6 +463,7 @@ CgBufs cg_bufs(const lagot_ctx *c) {
     for (int q = 0; q < 2; ++q) g.rws[q] = reinterpret_cast<RWSD *>(c->cg_vec + 4 * q * N);
     g.p = c->cg_vec + 8 * N;
     g.x = c->cg_vec + 9 * N;
+    g.u = c->cg_vec + 10 * N;
     g.part = c->cg_part;
     g.cgs = c->cg_cgs;
     g.sc = c->cg_sc;
@@ -809,6 +813,8 @@ void fill_defaults(lagot_opts *o) {
     o->continuation = 0;
     o->stage_newton = 8;
     o->stage_tol = 1e-2;
+    o->step_start = 0;
+    o->reserved = 0;
 }
 
 bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
@@ -819,6 +825,7 @@ int check_opts(const lagot_opts &o) {
     if (!valid_tpc(o.threads_per_cell) && o.threads_per_cell != 0) return LAGOT_EINVAL;
     if (o.continuation != 0 && o.continuation != 1) return LAGOT_EINVAL;
     if (o.continuation && (o.stage_newton < 1 || !(o.stage_tol > 0))) return LAGOT_EINVAL;
+    if ((o.step_start != 0 && o.step_start != 1) || o.reserved != 0) return LAGOT_EINVAL;
     return LAGOT_OK;
 }
 
@@ -934,9 +941,13 @@ int run_cg(lagot_ctx *c, const lagot_opts &o, int *launched, bool with_init, boo
     int k = 0;
     while (k < cap) {
         const int m = std::min(c->cg_chunk, cap - k);
+        const bool split = c->cg_split == 2 || (c->cg_split == 0 && cg_scalar_launch(c));
         auto chunk = [&]() {
             for (int q = 0; q < m; ++q) {
-                launch_cg_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hrow, c->hent, cg);
+                if (split)
+                    launch_cg_split_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hrow, c->hent, cg);
+                else
+                    launch_cg_iter(c->stream, bt, c->cg_lanes, c->cg_sub, q, rtol2, cap, c->hrow, c->hent, cg);
                 if (cg_scalar_launch(c)) launch_cg_scalars(c->stream, bt, c->cg_sub, q, cap, cg);
             }
             launch_cg_advance(c->stream, bt, m, cap, cg);
@@ -1036,7 +1047,7 @@ int newton_direction(lagot_ctx *c, const lagot_opts &o, bool graph) {
     // it ran, not the launches: a launch after convergence returns at once but is not
     // free) plus two, in steps of four (graph mode captures one chunk per length)
     c->cg_chunk = std::min(64, std::max(4, (c->h_cnt[10] + 2 + 3) / 4 * 4));
-    launch_cg_finish(st, bt, c->cg_sub, o.cg_rtol * o.cg_rtol, cg_bufs(c), c->herr, c->ctl, c->phase);
+    launch_cg_finish(st, bt, c->cg_sub, o.cg_rtol * o.cg_rtol, o.step_start, cg_bufs(c), c->herr, c->ctl, c->phase);
     return LAGOT_OK;
 }
 
@@ -1264,6 +1275,14 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
                      c->counts);
     rc = read_counts(c);
     if (rc) return fail_all(rc);
+    // the repair is for a few empty start cells: an instance with more than 64 empty cells,
+    // and more than 1% of its cells (a warm start from weights of much moved sites), goes to
+    // the restart at once
+    if (c->h_cnt[PH_REPAIR] > 0) {
+        launch_repair_gate(st, bt, PH_REPAIR, c->V, c->nempty, c->phase, c->counts);
+        rc = read_counts(c);
+        if (rc) return fail_all(rc);
+    }
     // repair rounds: raising one cell can empty a neighbour's, so a repaired start is
     // checked and repaired again, up to REPAIR_ROUNDS times, before the full restart
     constexpr int REPAIR_ROUNDS = 2;
@@ -1942,6 +1961,13 @@ int lagot_set_cg_shape(lagot_ctx *ctx, int lanes_per_row, int rows_per_block) {
     if (!ctx || !cg_shape_ok(lanes_per_row, rows_per_block)) return LAGOT_EINVAL;
     ctx->cg_lanes = ctx->cg_lanes_def = lanes_per_row;
     ctx->cg_sub = ctx->cg_sub_def = rows_per_block;
+    return LAGOT_OK;
+}
+
+int lagot_set_cg_split(lagot_ctx *ctx, int mode) {
+    if (!ctx || mode < 0 || mode > 2) return LAGOT_EINVAL;
+    if (mode != ctx->cg_split) drop_graphs(ctx);  // captured chunks hold the other kernels
+    ctx->cg_split = mode;
     return LAGOT_OK;
 }
 

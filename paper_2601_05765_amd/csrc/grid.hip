@@ -321,6 +321,36 @@ __global__ __launch_bounds__(TILE) void k_default_start(Batch bt, int want, cons
     pos[i].w = (float)(r * r);
 }
 
+__global__ void k_zero_n(int n, int32_t *__restrict__ a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+// empty cells (V <= 0) of the instances in phase `want`, per instance
+__global__ __launch_bounds__(TILE) void k_count_empty(Batch bt, int want, const double *__restrict__ V,
+                                                       int32_t *__restrict__ nempty) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (!selected(bt, want, b)) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    const int e = __syncthreads_count(i < bt.off[b + 1] && !(V[i] > 0.0));
+    if (threadIdx.x == 0 && e > 0) atomicAdd(&nempty[b], e);
+}
+
+// the repair is meant for a few empty cells: more than 64 and more than 1% of the
+// instance's cells send it to the restart
+__global__ void k_repair_gate(Batch bt, int want, const int32_t *__restrict__ nempty, int32_t *__restrict__ phase,
+                              int32_t *__restrict__ counts) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bt.B || phase[b] != want) return;
+    const int64_t nb = bt.off[b + 1] - bt.off[b];
+    if (nempty[b] > 64 && 100 * (int64_t)nempty[b] > nb) {
+        phase[b] = PH_RESTART;
+        atomicSub(&counts[want], 1);
+        atomicAdd(&counts[PH_RESTART], 1);
+    }
+}
+
 // A start cell that is empty gets a weight that puts its site strictly inside every
 // power half-space. Let j* maximise psi_j - d_ij^2 over the other sites (value L).
 // With w = psi_j*, every bisector has t_ij = (d_ij^2 + w - psi_j) / (2 d_ij) > 0
@@ -498,6 +528,13 @@ void launch_local_reach(hipStream_t st, int64_t n, const Batch &bt, int want, in
 void launch_default_start(hipStream_t st, const Batch &bt, int want, const double *ev_nu, double *psi_s,
                           float4 *pos_s) {
     hipLaunchKernelGGL(k_default_start, dim3(bt.T), dim3(TILE), 0, st, bt, want, ev_nu, psi_s, pos_s);
+}
+
+void launch_repair_gate(hipStream_t st, const Batch &bt, int want, const double *V, int32_t *nempty, int32_t *phase,
+                        int32_t *counts) {
+    hipLaunchKernelGGL(k_zero_n, dim3(nblocks(bt.B, 256)), dim3(256), 0, st, bt.B, nempty);
+    hipLaunchKernelGGL(k_count_empty, dim3(bt.T), dim3(TILE), 0, st, bt, want, V, nempty);
+    hipLaunchKernelGGL(k_repair_gate, dim3(nblocks(bt.B, 256)), dim3(256), 0, st, bt, want, nempty, phase, counts);
 }
 
 void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu_s,

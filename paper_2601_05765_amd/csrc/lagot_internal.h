@@ -148,6 +148,7 @@ struct InstCtl {
     int repaired;      // empty start cells were given the default weight
     int iter_base;     // iterations before the current continuation stage (the limit counts from here)
     int pad;
+    double alpha_acc;  // last accepted step length (1 at a start or a stage start)
 };
 
 // Newton options as the device control kernels see them.
@@ -215,6 +216,7 @@ struct CgBufs {
     int32_t *kbase;          // [1] index of the first iteration of the next chunk
     int32_t *remaining;      // [1] instances still iterating after the last chunk
     int32_t *maxit;          // [1] most iterations any instance has done in this solve
+    double *u;               // [n] u_{k+1} of every row (the split iteration's product input)
 };
 
 // Parameters of the velocity system of the fluid step (section 5, eq. (4)).
@@ -291,6 +293,11 @@ void launch_default_start(hipStream_t st, const Batch &bt, int want, const doubl
                           float4 *pos_s);
 // psi_out = psi_s, except that empty cells (V <= 0) of the selected instances get
 // max(psi, default weight, weights of the neighbours whose power region contains the ball)
+// instances of phase `want` with more than 64, and more than 1%, of their cells empty
+// (V <= 0) -> PH_RESTART,
+// the phase histogram counts updated (nempty: [B] scratch)
+void launch_repair_gate(hipStream_t st, const Batch &bt, int want, const double *V, int32_t *nempty, int32_t *phase,
+                        int32_t *counts);
 void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu_s,
                          const int32_t *cell_start, const double *psi_s, double *psi_out, float4 *pos_s);
 
@@ -329,6 +336,9 @@ void launch_hess_finish(hipStream_t st, const Batch &bt, int want, const double 
 bool cg_shape_ok(int lanes, int sub);
 void launch_cg_init(hipStream_t st, const Batch &bt, int lanes, int sub, const double *V, const double *nu,
                     const double *diag, const int2 *hrow, const int2 *ent, CgBufs cg);
+// one PCG iteration in two launches (own update, then the product on u_{k+1})
+void launch_cg_split_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
+                          const int2 *hrow, const int2 *ent, CgBufs cg);
 void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
                     const int2 *hrow, const int2 *ent, CgBufs cg);
 void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBufs cg);
@@ -337,8 +347,9 @@ void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBu
 // cg_sum_in_block_max() partials (the others are summed inside the iteration's blocks)
 void launch_cg_scalars(hipStream_t st, const Batch &bt, int sub, int m, int cap, CgBufs cg);
 int cg_sum_in_block_max();
-void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, CgBufs cg, const int32_t *herr,
-                      InstCtl *ctl, int32_t *phase);
+// step_start 1: the step search starts at min(1, 2 alpha_acc) instead of 1
+void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, int step_start, CgBufs cg,
+                      const int32_t *herr, InstCtl *ctl, int32_t *phase);
 void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase);
 // ev: statistics of the first iterate; ev_floor: of the given start weights (eps0)
 void launch_ctl_start(hipStream_t st, const Batch &bt, CtlOpts o, int from_phase, const double *ev,

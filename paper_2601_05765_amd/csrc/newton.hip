@@ -524,6 +524,146 @@ __global__ __launch_bounds__(LANES * SUB) void k_cg_iter(Batch bt, int m, double
     }
 }
 
+// ---- the same iteration in two launches (large instances) ----------------------------
+// k_cg_iter forms a neighbour's u_{k+1} from its whole (r, w, s, D) record: one launch per
+// iteration, but 32 bytes gathered per matrix entry, which at millions of rows no longer
+// stay in L2. Split, the first launch does the scalars and every row's own update and
+// writes u_{k+1} (8 bytes per row), the second the product w_{k+1} = A u_{k+1} from those
+// values. Same arithmetic per row (u_{k+1} bit for bit); the partial sums are taken in
+// other block shapes, so the scalars differ from k_cg_iter's in the last bits.
+template <int SUB>
+__global__ __launch_bounds__(SUB) void k_cg_update(Batch bt, int m, double rtol2, int cap, CgBufs cg) {
+    constexpr int SPT = TILE / SUB;
+    __shared__ double sh[SUB / 64][4];
+    const int q = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int t = q / SPT;
+    const int b = bt.tile_inst[t];
+    const int row = bt.tile_row[t] + (q % SPT) * SUB + (int)threadIdx.x;
+    const int k = *cg.kbase + m;
+    int32_t *st = cg.cgst + 4 * b;
+    const int4 st4 = *reinterpret_cast<const int4 *>(st);
+    if (bt.phase[b] != PH_ACTIVE || st4.y != 0 || st4.z != 0 || k >= cap) return;
+    const int NS = SPT * bt.T;
+    const int t0 = SPT * bt.first_tile[b], t1 = SPT * bt.first_tile[b + 1];
+    const int end = bt.off[b + 1];
+    const int cur = k & 1, nxt = cur ^ 1;
+    const double2 prev = *reinterpret_cast<const double2 *>(cg.cgs + 4 * b + 2 * nxt);  // alpha, gamma of k-1
+    const bool has = row < end;
+    RWSD own{0.0, 0.0, 0.0, 0.0};
+    double pk_1 = 0.0, xk = 0.0;
+    if (has) {
+        own = load_rwsd(cg.rws[cur], row);
+        pk_1 = cg.p[row];
+        xk = cg.x[row];
+    }
+    double gam, del, rho, rho0;
+    if (t1 - t0 <= CG_SUM_IN_BLOCK) {
+        double S[4];
+        sum_range(P_GAM(cg, NS, cur), P_DEL(cg, NS, cur), P_RHO(cg, NS, cur), P_RHO0(cg, NS), t0, t1, S, sh);
+        gam = S[0];
+        del = S[1];
+        rho = S[2];
+        rho0 = S[3];
+    } else {
+        const double2 s01 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur);
+        const double2 s23 = *reinterpret_cast<const double2 *>(cg.sc + 8 * b + 4 * cur + 2);
+        gam = s01.x;
+        del = s01.y;
+        rho = s23.x;
+        rho0 = s23.y;
+    }
+    const bool lead = q == t0 && threadIdx.x == 0;
+    if (rho <= rtol2 * rho0) {
+        if (lead) {
+            st[2] = 1;
+            st[0] = k;
+        }
+        return;
+    }
+    double alpha, beta = 0.0;
+    if (k == 0) {
+        alpha = gam / del;
+    } else {
+        beta = gam / prev.y;
+        alpha = gam / (del - beta * gam / prev.x);
+    }
+    if (!(alpha > 0.0) || !(alpha < 1e300)) {  // non-positive curvature (or NaN)
+        if (lead) {
+            st[1] = 1;
+            st[0] = k;
+        }
+        return;
+    }
+    if (lead) {
+        cg.cgs[4 * b + 2 * cur] = alpha;
+        cg.cgs[4 * b + 2 * cur + 1] = gam;
+        st[0] = k + 1;
+    }
+    double gp = 0.0, rp = 0.0, unused = 0.0;
+    if (has) {
+        const double d = own.d;
+        const double uk = d > 0.0 ? own.r / d : 0.0;
+        const double pk = fma(beta, pk_1, uk);
+        const double sk = fma(beta, own.s, own.w);
+        cg.x[row] = fma(alpha, pk, xk);
+        const double r1 = fma(-alpha, sk, own.r);
+        const double u1 = d > 0.0 ? r1 / d : 0.0;
+        cg.p[row] = pk;
+        cg.u[row] = u1;
+        // r, s and D of the new record; its w comes from the product
+        double *rec = reinterpret_cast<double *>(cg.rws[nxt] + row);
+        rec[0] = r1;
+        *reinterpret_cast<double2 *>(rec + 2) = make_double2(sk, d);
+        gp = r1 * u1;
+        rp = r1 * r1;
+    }
+    block_sum3(gp, rp, unused, sh);
+    if (threadIdx.x == 0) {
+        P_GAM(cg, NS, nxt)[q] = gp;
+        P_RHO(cg, NS, nxt)[q] = rp;
+    }
+}
+
+// second launch of the split iteration: w_{k+1} = D u_{k+1} - sum_j v_ij u_{k+1,j} and the
+// delta partials, for the instances whose update ran (iteration count advanced to k + 1)
+template <int LANES, int SUB>
+__global__ __launch_bounds__(LANES * SUB) void k_cg_product(Batch bt, int m, int cap, const int2 *__restrict__ hrow,
+                                                    const int2 *__restrict__ ent, CgBufs cg) {
+    constexpr int SPT = TILE / SUB;
+    __shared__ double sh[LANES * SUB / 64][4];
+    const int q = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int t = q / SPT;
+    const int b = bt.tile_inst[t];
+    const int row = bt.tile_row[t] + (q % SPT) * SUB + (int)(threadIdx.x / LANES);
+    const int k = *cg.kbase + m;
+    const int4 st4 = *reinterpret_cast<const int4 *>(cg.cgst + 4 * b);
+    if (bt.phase[b] != PH_ACTIVE || st4.y != 0 || st4.z != 0 || st4.x != k + 1 || k >= cap) return;
+    const int NS = SPT * bt.T;
+    const int nxt = (k & 1) ^ 1;
+    const int l = threadIdx.x & (LANES - 1);
+    const bool has = row < bt.off[b + 1];
+    int2 hr = make_int2(0, 0);
+    if (has) hr = hrow[row];
+    const int2 *er = ent + (int64_t)t * (TILE * FCAP) + hr.x;
+    double acc = 0.0;
+    for (int f = l; f < hr.y; f += LANES) {
+        const int2 en = er[f];
+        acc += (double)__int_as_float(en.y) * cg.u[en.x];
+    }
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LANES);
+    double dp = 0.0, u1 = 0.0, z1 = 0.0;
+    if (has && l == 0) {
+        double *rec = reinterpret_cast<double *>(cg.rws[nxt] + row);
+        u1 = cg.u[row];
+        const double w1 = rec[3] * u1 - acc;
+        rec[1] = w1;
+        dp = w1 * u1;
+    }
+    block_sum3(dp, u1, z1, sh);
+    if (threadIdx.x == 0) P_DEL(cg, NS, nxt)[q] = dp;
+}
+
 // The scalars gamma, delta, rho (and rho0) of the next iteration: the instance's sub-tile
 // partials of the slot just written, summed once, in a fixed order (deterministic), by
 // one block per instance, instead of by every block of the next iteration (which made
@@ -571,8 +711,9 @@ __global__ __launch_bounds__(1024) void k_cg_advance(Batch bt, int chunk, int ca
     }
 }
 
-// End of the direction solve: ACTIVE -> TRIAL with alpha = 1, or FAILED.
-__global__ __launch_bounds__(RB) void k_cg_finish(Batch bt, int SPT, double rtol2, CgBufs cg,
+// End of the direction solve: ACTIVE -> TRIAL with alpha = 1 (with step_start:
+// min(1, 2 x the last accepted step length)), or FAILED.
+__global__ __launch_bounds__(RB) void k_cg_finish(Batch bt, int SPT, double rtol2, int step_start, CgBufs cg,
                                                    const int32_t *__restrict__ herr, InstCtl *__restrict__ ctl,
                                                    int32_t *__restrict__ phase) {
     __shared__ double sh[RB / 64][4];
@@ -596,7 +737,7 @@ __global__ __launch_bounds__(RB) void k_cg_finish(Batch bt, int SPT, double rtol
         c.status = -6;  // LAGOT_ESINGULAR
         phase[b] = PH_FAILED;
     } else {
-        c.alpha = 1.0;
+        c.alpha = step_start ? fmin(1.0, 2.0 * c.alpha_acc) : 1.0;
         c.hstep = 0;
         phase[b] = PH_TRIAL;
     }
@@ -616,6 +757,7 @@ __global__ __launch_bounds__(1024) void k_ctl_init(Batch bt, InstCtl *__restrict
     for (int b = threadIdx.x; b < bt.B; b += 1024) {
         InstCtl c{};
         c.alpha = 1.0;
+        c.alpha_acc = 1.0;
         ctl[b] = c;
         phase[b] = PH_START;
     }
@@ -696,6 +838,7 @@ __global__ __launch_bounds__(1024) void k_ctl_decide(Batch bt, CtlOpts o, const 
             c.maxrel = maxrel;
             c.gnorm = gnorm;
             c.minV = minV;
+            c.alpha_acc = c.alpha;
             phase[b] = PH_ACCEPT;
         } else {
             c.alpha *= 0.5;
@@ -757,6 +900,7 @@ __global__ __launch_bounds__(1024) void k_ctl_stage(Batch bt, CtlOpts o, const d
         c.restore = 0;
         c.iter_base = c.iters;
         c.alpha = 1.0;
+        c.alpha_acc = 1.0;
         c.sumV = ev[4 * b + 0];
         c.maxrel = ev[4 * b + 1];
         c.gnorm = ev[4 * b + 2];
@@ -849,6 +993,22 @@ void launch_cg_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, 
 
 int cg_sum_in_block_max() { return CG_SUM_IN_BLOCK; }
 
+void launch_cg_split_iter(hipStream_t st, const Batch &bt, int lanes, int sub, int m, double rtol2, int cap,
+                          const int2 *hrow, const int2 *ent, CgBufs cg) {
+    const dim3 grid((TILE / sub) * bt.T);
+    if (sub == 64)
+        hipLaunchKernelGGL((k_cg_update<64>), grid, dim3(64), 0, st, bt, m, rtol2, cap, cg);
+    else if (sub == 128)
+        hipLaunchKernelGGL((k_cg_update<128>), grid, dim3(128), 0, st, bt, m, rtol2, cap, cg);
+    else
+        hipLaunchKernelGGL((k_cg_update<256>), grid, dim3(256), 0, st, bt, m, rtol2, cap, cg);
+    const dim3 block(lanes * sub);
+#define X(L, S) \
+    if (lanes == L && sub == S) { hipLaunchKernelGGL((k_cg_product<L, S>), grid, block, 0, st, bt, m, cap, hrow, ent, cg); return; }
+    LAGOT_CG_SHAPES(X)
+#undef X
+}
+
 void launch_cg_scalars(hipStream_t st, const Batch &bt, int sub, int m, int cap, CgBufs cg) {
     hipLaunchKernelGGL(k_cg_scalars, dim3(bt.B), dim3(SCB), 0, st, bt, TILE / sub, m, cap, cg);
 }
@@ -857,9 +1017,10 @@ void launch_cg_advance(hipStream_t st, const Batch &bt, int chunk, int cap, CgBu
     hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(1024), 0, st, bt, chunk, cap, cg);
 }
 
-void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, CgBufs cg, const int32_t *herr,
-                      InstCtl *ctl, int32_t *phase) {
-    hipLaunchKernelGGL(k_cg_finish, dim3(bt.B), dim3(RB), 0, st, bt, TILE / sub, rtol2, cg, herr, ctl, phase);
+void launch_cg_finish(hipStream_t st, const Batch &bt, int sub, double rtol2, int step_start, CgBufs cg,
+                      const int32_t *herr, InstCtl *ctl, int32_t *phase) {
+    hipLaunchKernelGGL(k_cg_finish, dim3(bt.B), dim3(RB), 0, st, bt, TILE / sub, rtol2, step_start, cg, herr, ctl,
+                       phase);
 }
 
 void launch_ctl_init(hipStream_t st, const Batch &bt, InstCtl *ctl, int32_t *phase) {

@@ -207,11 +207,18 @@ def test_error_codes(ctx):
     st = ctx.solve(x, y, z, nu, psi, check=False)
     # the empty cell gets the default weight, the other start weights are kept
     assert st.status == 0 and st.repaired_start == 1 and st.default_start == 0
-    # a cell swallowed by a heavy neighbour stays empty after the repair: full default start
+    # a neighbour 5x heavier swallows a few cells: they are repaired (a cell that stays
+    # swallowed then sends the solve to the default start)
+    x, y, z, nu, psi = _dev(sc)
+    psi[11] = 5.0 * float(psi[11])
+    st = ctx.solve(x, y, z, nu, psi, check=False)
+    assert st.status == 0 and st.repaired_start == 1
+    # a neighbour 400x heavier swallows most of the 200 cells (more than 64, more than 1%):
+    # the default start at once, no repair
     x, y, z, nu, psi = _dev(sc)
     psi[11] = 400.0 * float(psi[11])
     st = ctx.solve(x, y, z, nu, psi, check=False)
-    assert st.status == 0 and st.repaired_start == 1 and st.default_start == 1
+    assert st.status == 0 and st.repaired_start == 0 and st.default_start == 1
     # iteration limit -> ENOCONV, psi holds an accepted iterate
     x, y, z, nu, psi = _dev(sc)
     st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(max_newton=1), check=False)
@@ -318,3 +325,84 @@ def test_cells_nnz_capacity(ctx):
     small = ctx.cells(x, y, z, psi, nnz_per_cell=1)
     for k in ("row_ptr", "col", "area", "vol"):
         assert torch.equal(small[k], full[k]), k
+
+
+def test_step_start_option(ctx, oracle_mod):
+    """opts.step_start = 1 (the step search of each Newton iteration starts at
+    min(1, 2 x the last accepted step) instead of 1): the splash solve at 200,000 sites,
+    whose first iterations take short steps, converges to the same unique weights (oracle
+    re-evaluation of the heaviest and random cells) in at most as many evaluations as with
+    the reset to 1; invalid values and a non-zero reserved field are EINVAL."""
+    _say("case: step_start on splash 200k")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.splash(200_000, 0)
+    x, y, z, nu, psi0 = _dev(sc)
+    p0, p1 = psi0.clone(), psi0.clone()
+    s0 = ctx.solve(x, y, z, nu, p0, opts=L.default_opts(tol=1e-5, residual_test=0), check=False)
+    s1 = ctx.solve(x, y, z, nu, p1, opts=L.default_opts(tol=1e-5, residual_test=0, step_start=1), check=False)
+    _say(f"  reset to 1: {s0.as_dict()}\n  carried:    {s1.as_dict()}")
+    assert s0.status == 0 and s1.status == 0
+    assert s1.evals <= s0.evals
+    p = p1.cpu().numpy()
+    rng = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([np.argsort(-p)[:100], rng.choice(sc.n, 200, replace=False)]))
+    assert _oracle_err(oracle_mod, sc, p, idx=idx) <= 1e-5
+    small = scenes.slab_uniform(300, 1)
+    x, y, z, nu, psi = _dev(small)
+    for kw in ({"step_start": 2}, {"step_start": -1}, {"reserved": 1}):
+        assert ctx.solve(x, y, z, nu, psi.clone(), opts=L.default_opts(**kw), check=False).status == L.EINVAL
+
+
+@pytest.mark.parametrize("n_empty,repaired", [(40, 1), (300, 0)])
+def test_repair_only_for_a_few_empty_start_cells(ctx, oracle_mod, n_empty, repaired):
+    """Start weights with n_empty cells emptied (psi = -1) out of 10,000: 40 empty cells are
+    repaired (each gets a weight that puts its site inside its cell, the other weights are
+    kept); 300 (more than 64 and more than 1% of the cells) send the solve to the default
+    start at once. Both converge (oracle re-evaluation)."""
+    _say(f"case: {n_empty} empty start cells of 10,000")
+    import paper_2601_05765_amd as L
+    sc = scenes.slab_uniform(10_000, 8)
+    p = sc.psi0.copy()
+    p[np.random.default_rng(9).choice(sc.n, n_empty, replace=False)] = -1.0
+    x, y, z, nu, psi = _dev(sc, p)
+    st = ctx.solve(x, y, z, nu, psi, check=False)
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.repaired_start == repaired
+    if not repaired:
+        assert st.default_start == 1
+    rng = np.random.default_rng(10)
+    assert _oracle_err(oracle_mod, sc, psi.cpu().numpy(), idx=np.sort(rng.choice(sc.n, 400, replace=False))) <= 1e-5
+
+
+def test_cg_split_iteration_matches_one_kernel(oracle_mod):
+    """The PCG iteration in two launches (own update, then the product on u_{k+1}) against
+    the one-launch iteration on the 100,000-site dam break: one Newton step from the same
+    start gives the same weights to the rounding of the partial sums, and a full solve with
+    the split iteration converges to the oracle's volumes."""
+    _say("case: split PCG iteration vs one kernel, dam_break 100k")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.dam_break(100_000, 0)
+    out = []
+    for mode in (1, 2):
+        ctx = L.Context()
+        ctx.set_cg_split(mode)
+        x, y, z, nu, psi = _dev(sc)
+        st = ctx.newton_step(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+        _say(f"  mode {mode}: {st.as_dict()}")
+        assert st.status == 0 and st.newton_iters == 1
+        out.append((psi.cpu().numpy(), st.cg_iters))
+    step = np.abs(out[0][0] - sc.psi0).max()
+    diff = np.abs(out[0][0] - out[1][0]).max()
+    _say(f"  max |dpsi| {step:.3e}, max difference of the two {diff:.3e}, cg {out[0][1]} / {out[1][1]}")
+    assert diff <= 1e-9 * step and abs(out[0][1] - out[1][1]) <= 1
+    ctx = L.Context()
+    ctx.set_cg_split(2)
+    x, y, z, nu, psi = _dev(sc)
+    st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5))
+    assert st.status == 0
+    idx = np.sort(np.random.default_rng(12).choice(sc.n, 500, replace=False))
+    assert _oracle_err(oracle_mod, sc, psi.cpu().numpy(), idx=idx) <= 1e-5
+    with pytest.raises(L.LagotError):
+        ctx.set_cg_split(3)
