@@ -255,6 +255,7 @@ def learned_section(ctx, L, scenes, n_seeds: int, train_steps: int, steps: int):
             "newton_iters_plain": [r["newton_iters"] for r in a],
             "newton_iters_learned": [r["newton_iters"] for r in b],
             "guess_accepted": [r["learned_accepted"] for r in b],
+            "ms_guess": [r["ms_learned"] for r in b],  # inputs, network and trial evaluations per solve
             "status_plain": [r["status"] for r in a], "status_learned": [r["status"] for r in b]}, check
 
 

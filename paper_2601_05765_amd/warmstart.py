@@ -114,7 +114,7 @@ def sequence(ctx, sc, steps: int, dt: float = 2e-3, use_learned: bool = False, t
         ms = 1000 * (time.perf_counter() - t0)
         out.append({"step": k + 1, "ms": ms, "status": st.status, "newton_iters": st.newton_iters,
                     "evals": st.evals, "cg_iters": st.cg_iters, "learned_accepted": st.learned_accepted,
-                    "max_rel_err": st.max_rel_err})
+                    "max_rel_err": st.max_rel_err, "ms_learned": st.ms_learned})
         log(f"step {k + 1}: {'learned' if use_learned else 'plain'} {ms:.1f} ms, {st.newton_iters} it, "
             f"accepted={st.learned_accepted}")
     if state is not None:

@@ -71,6 +71,32 @@ def test_domain_cells_parity(ctx, oracle_mod, seed):
     assert_close(rep)
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_domain_paper_k_route(ctx, oracle_mod, seed):
+    """lagot_cells_paper_k in the cut box: the domain planes are facets of the restricted
+    cells like the box walls; K and V against the oracle's route and its signed form. The
+    planes are the float32 values both sides are given, whose normals are unit only to
+    1.7e-8; the two forms of K read a non-unit normal differently at that level (with the
+    normals renormalised in float64 the oracle's two forms agree to 3e-16), hence 1e-7."""
+    _say(f"case: paper K route in a cut box (9 planes), seed {seed}")
+    sc = scenes.random_small(60, seed, r_lo=0.05, r_hi=0.2)
+    P = np.stack([sc.x, sc.y, sc.z], 1).astype(np.float64)
+    keep = _inside(P, CUT)
+    x, y, z, psi = sc.x[keep], sc.y[keep], sc.z[keep], sc.psi0[keep]
+    ctx.set_domain(CUT)
+    try:
+        V, K = ctx.cells_paper_k(*_dev(x, y, z, psi))
+    finally:
+        ctx.set_domain(None)
+    orc = oracle_mod.cells(x, y, z, psi, domain=CUT, paper_k=True)
+    area = 4.0 * math.pi * psi
+    eK = np.abs(K.cpu().numpy() - orc.Kp) / area
+    eK2 = np.abs(orc.Kp - orc.K) / area
+    eV = np.abs(V.cpu().numpy() - orc.V) / (area * np.sqrt(psi) / 3.0)
+    _say(f"  {keep.sum()} sites: K vs oracle route {eK.max():.2e}, oracle routes {eK2.max():.2e}, V {eV.max():.2e}")
+    assert eK.max() <= 1e-7 and eK2.max() <= 1e-7 and eV.max() <= 1e-7
+
+
 def _tetra():
     v = np.array([[0.1, 0.1, 0.1], [0.9, 0.15, 0.1], [0.2, 0.85, 0.15], [0.3, 0.3, 0.9]])
     planes, areas = [], []
