@@ -383,7 +383,8 @@ def c3_sequence(ctx, L, scenes, n: int, warmup: int, steps: int, log):
     # every solve follows the path on the prescribed volumes (opts.continuation), with loose
     # intermediate stages (stage_tol 0.1: 38 evaluations per step against 41 at 1e-2) and the
     # step search of each iteration started at twice the last accepted step (step_start: 33
-    # evaluations per step against 36, the same Newton iterations): at this size
+    # evaluations per step against 36, the same Newton iterations); the first step in s stays at
+    # 1/4 (1/3 saves evaluations on most steps but over 20 steps averages the same): at this size
     # the advected previous weights leave ~20% of the cells empty, the repair does not
     # recover them, and the solve restarts from the default weights, from which the path
     # takes fewer evaluations than Algorithm 1 alone (41 against 57 per step)

@@ -96,8 +96,8 @@ typedef struct {
                             for s rising from 0 to 1, each stage from the previous one's weights:
                             intermediate stages to stage_tol with at most stage_newton iterations
                             and 4 step halvings per iteration (PCG tolerance max(cg_rtol, 1e-3)),
-                            the last (s = 1) to tol. The step in s starts at 1/4, doubles after a
-                            stage of at most 3 iterations without halving, and halves after a stage
+                            the last (s = 1) to tol. The step in s starts at stage_step, doubles after
+                            a stage of at most 3 iterations without halving, and halves after a stage
                             that fails to converge (or whose step search ends on a cell the kernels
                             cannot finish), whose weights are discarded; below 2^-12 the call fails
                             with that stage's error and the last accepted stage's weights.
@@ -110,6 +110,7 @@ typedef struct {
                             the search restarts; after short accepted steps this saves the
                             evaluations of trials that would be halved again                   */
     int reserved;        /* must be 0                                                            */
+    double stage_step;   /* first step in s of the path following, in (0, 1]      (default 0.25) */
 } lagot_opts;
 
 typedef struct {

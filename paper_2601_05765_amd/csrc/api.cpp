@@ -815,6 +815,7 @@ void fill_defaults(lagot_opts *o) {
     o->stage_tol = 1e-2;
     o->step_start = 0;
     o->reserved = 0;
+    o->stage_step = 0.25;
 }
 
 bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
@@ -826,6 +827,7 @@ int check_opts(const lagot_opts &o) {
     if (o.continuation != 0 && o.continuation != 1) return LAGOT_EINVAL;
     if (o.continuation && (o.stage_newton < 1 || !(o.stage_tol > 0))) return LAGOT_EINVAL;
     if ((o.step_start != 0 && o.step_start != 1) || o.reserved != 0) return LAGOT_EINVAL;
+    if (o.continuation && !(o.stage_step > 0.0 && o.stage_step <= 1.0)) return LAGOT_EINVAL;
     return LAGOT_OK;
 }
 
@@ -1139,7 +1141,7 @@ int continuation(lagot_ctx *c, const lagot_opts &o, const CtlOpts &co, CallTimes
     cs.tol = o.stage_tol;
     cs.max_newton = o.stage_newton;
     cs.max_halvings = std::min(o.max_halvings, 4);  // a stage that needs short steps is retried closer
-    double s = 0.0, ds = 0.25;
+    double s = 0.0, ds = o.stage_step;
     int stages = 0, rc = LAGOT_OK;
     for (;;) {
         const double s1 = std::min(1.0, s + ds);

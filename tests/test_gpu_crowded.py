@@ -203,7 +203,8 @@ def test_continuation_options_rejected(ctx):
     sc = scenes.slab_uniform(500, 3)
     x, y, z = _xyz(sc)
     nu = _t(sc.nu, torch.float64)
-    for kw in ({"continuation": 2}, {"continuation": 1, "stage_newton": 0}, {"continuation": 1, "stage_tol": 0.0}):
+    for kw in ({"continuation": 2}, {"continuation": 1, "stage_newton": 0}, {"continuation": 1, "stage_tol": 0.0},
+               {"continuation": 1, "stage_step": 0.0}, {"continuation": 1, "stage_step": 1.5}):
         p = _t(sc.psi0, torch.float64)
         st = ctx.solve(x, y, z, nu, p, opts=L.default_opts(**kw), check=False)
         assert st.status == L.EINVAL, kw
@@ -227,3 +228,24 @@ def test_continuation_on_easy_problem_matches_plain(ctx, oracle_mod):
     assert st.status == 0 and st.stages >= 1
     c = oracle_mod.cells(sc.x, sc.y, sc.z, p.cpu().numpy())
     assert float(np.max(np.abs(c.V - sc.nu) / sc.nu)) <= 1e-5
+
+
+def test_continuation_first_step_one_third(ctx, oracle_mod):
+    """Path following with a first step of 1/3 in s (the bench's setting, with loose
+    intermediate stages and the step search started at twice the last step) on the
+    200,000-site splash scene from its Voronoi start: converges to the oracle's volumes."""
+    _say("case: splash 200k, continuation with stage_step 1/3")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.splash(200_000, 0)
+    x, y, z = _xyz(sc)
+    nu, psi = _t(sc.nu, torch.float64), _t(sc.psi0, torch.float64)
+    opts = L.default_opts(tol=1e-5, residual_test=0, continuation=1, stage_step=1.0 / 3.0, stage_tol=0.1,
+                          step_start=1, cg_rtol=1e-3)
+    st = ctx.solve(x, y, z, nu, psi, opts=opts, check=False)
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.stages >= 1 and st.max_rel_err <= 1e-5
+    ph = psi.cpu().numpy()
+    idx = _sample(sc.n, ph, 31, k_top=100, k_rand=200)
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, ph, idx=idx)
+    assert float(np.max(np.abs(c.V - sc.nu[idx]) / sc.nu[idx])) <= 1e-5
