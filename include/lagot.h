@@ -380,6 +380,36 @@ int lagot_set_cg_split(lagot_ctx *ctx, int mode);
 int lagot_set_domain(lagot_ctx *ctx, int nplanes, const double *planes);
 
 /*
+ * Non-convex polyhedral domain (section 6: cells in polyhedral domains, e.g. a pipe) as
+ * the union of npieces convex pieces with disjoint interiors, for every later call on
+ * this context. Piece k is {x : n_w . x <= c_w, piece_off[k] <= w < piece_off[k+1]}.
+ * Each plane is either a wall of the domain (wall_id[w] in [0, nwalls): its facet areas
+ * go to that wall; a wall may span several pieces) or a plane between two pieces
+ * (wall_id[w] = -1: no wall area). The restricted cell is the union of its parts in the
+ * pieces, so V, K, the facet areas (and with them the Hessian) and the centroids are the
+ * sums over the pieces; each piece is evaluated like a convex domain, so a call costs up
+ * to npieces evaluations. With pieces, lagot_cells' wall_area holds nwalls areas per site
+ * (site-major, by wall id). Sites must lie strictly inside some piece: not on a plane
+ * between pieces either (the solid angle of a facet seen from a site on its plane depends
+ * on the side it is approached from), so the cuts between pieces should avoid the sites.
+ * Every plane of a piece must lie wholly on the domain's boundary or wholly between two
+ * pieces. The box argument must contain the domain. lagot_set_domain (any nplanes, 0
+ * included) goes back to a convex domain.
+ *   in : piece_off [npieces + 1] int32 HOST (piece_off[0] = 0, 1 to 32 planes per piece,
+ *        at most 64 planes in all); planes [4 piece_off[npieces]] float64 HOST, (n_x, n_y,
+ *        n_z, c) per plane, unit outward normals (|n| within 1e-6 of 1); wall_id
+ *        [piece_off[npieces]] int32 HOST; 1 <= npieces <= 16, 1 <= nwalls <= 64.
+ * Not with lagot_cells_paper_k or lagot_fluid_step (they return LAGOT_EINVAL while a
+ * non-convex domain is set). The crowded pass is not timed per piece (lagot_last_kernel_times
+ * reports no crowded-pass time) and lagot_last_pass_counts gives the last piece's counts.
+ * Synchronises the stream.
+ * Errors: LAGOT_EINVAL (NULL pointers, counts out of range, a normal not unit, c not
+ * finite, a wall id out of range), LAGOT_EHIP.
+ */
+int lagot_set_domain_pieces(lagot_ctx *ctx, int npieces, const int32_t *piece_off, const double *planes,
+                            const int32_t *wall_id, int nwalls);
+
+/*
  * The P1 Laplacian over the restricted Laguerre facets (section 5, eq. (3)):
  *   (Lap u)_i = sum_j mu_ij w_ij (u_j - u_i),  w_ij = |V_ij| / (2 |p_j - p_i|),
  * mu_ij = (mu_i + mu_j) / 2 (one reading of the paper's per-pair coefficients). |V_ij|

@@ -8,6 +8,8 @@ Contents
   cells(...)          restricted cell volumes, spherical areas, facet areas, centroids
                       (C routine in lagot_oracle.c; eq. (1), section 3.2, 3.3, Alg. 2;
                       centroids: the cell centroid of the pressure model, section 5)
+  cells_pieces(...)   the same in a non-convex domain given as a union of convex pieces
+                      (section 6: cells in polyhedral domains; sums of the per-piece parts)
   hessian(...)        gradient nu - V and the sparse matrix -Hess K (eq. (2))
   newton_solve(...)   damped Newton with KMT step control (Alg. 1)
   p1_weights(...)     facet weights w_ij = |V_ij| / (2 |p_j - p_i|) of the P1 Laplacian (eq. (3))
@@ -138,6 +140,54 @@ def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, th
     if (st == 2).any():
         raise RuntimeError("oracle facet capacity exceeded; raise fcap")
     return Cells(V, K, W, fc, fj, fA, nc, st, idx_arr, wk, C, Kp, cin)
+
+
+def cells_pieces(x, y, z, psi, pieces, nwalls: int, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96,
+                 threads: int = 0) -> Cells:
+    """Restricted cells in a non-convex domain, the union of convex pieces with disjoint
+    interiors (section 6 evaluates cells in polyhedral domains). ``pieces`` is a list of
+    (planes [P_k, 4] (unit outward normal n, c: piece {x : n.x <= c}), wall_id [P_k]) with
+    wall_id the wall a plane belongs to, or -1 for a plane between two pieces.
+
+    The restricted cell L_i ∩ B_i ∩ Ω is the disjoint union of L_i ∩ B_i ∩ Ω_k over the
+    pieces Ω_k, so every measure of it is the sum of the pieces' measures: volume,
+    spherical area, the area of each facet (by neighbour), the area on each wall (by wall
+    id; a plane between pieces bounds no wall), and the first moment (the centroid is
+    their sum over the total volume; an empty cell keeps the site)."""
+    parts = [cells(x, y, z, psi, box=box, idx=idx, fcap=fcap, threads=threads, domain=np.asarray(pl, np.float64))
+             for pl, _ in pieces]
+    m = parts[0].V.shape[0]
+    V = np.zeros(m)
+    K = np.zeros(m)
+    W = np.zeros((m, nwalls))
+    mom = np.zeros((m, 3))
+    fac = [dict() for _ in range(m)]
+    nc = np.zeros(m, np.int32)
+    for (pl, wid), c in zip(pieces, parts):
+        V += c.V
+        K += c.K
+        mom += c.V[:, None] * c.C
+        nc = np.maximum(nc, c.ncand)
+        for w, wi in enumerate(np.asarray(wid).reshape(-1)):
+            if wi >= 0:
+                W[:, wi] += c.walls[:, w]
+        for i in range(m):
+            for j, a in c.facets(i).items():
+                fac[i][j] = fac[i].get(j, 0.0) + a
+    fc = np.array([len(f) for f in fac], np.int32)
+    if (fc > fcap).any():
+        raise RuntimeError("oracle facet capacity exceeded; raise fcap")
+    fj = np.full((m, fcap), -1, np.int64)
+    fA = np.zeros((m, fcap))
+    for i, f in enumerate(fac):
+        for s, j in enumerate(sorted(f)):
+            fj[i, s] = j
+            fA[i, s] = f[j]
+    site = np.stack([np.asarray(x, np.float64), np.asarray(y, np.float64), np.asarray(z, np.float64)], 1)
+    site = site[parts[0].idx]
+    C = np.where(V[:, None] > 0, mom / np.where(V > 0, V, 1.0)[:, None], site)
+    st = np.where(V > 0, 0, 1).astype(np.int32)
+    return Cells(V, K, W, fc, fj, fA, nc, st, parts[0].idx, None, C)
 
 
 def hessian(xyz: np.ndarray, psi: np.ndarray, c: Cells):

@@ -22,7 +22,7 @@ _lib = None
 OK, EINVAL, EEMPTY, ENOCONV, ELINESEARCH, ECAPACITY, ESINGULAR, EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["lagot_default_opts", "lagot_create", "lagot_destroy", "lagot_cells", "lagot_newton_step", "lagot_solve",
-           "lagot_solve_batched", "lagot_solve_moved", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_set_cg_split", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_cells_paper_k", "lagot_set_domain", "lagot_last_cell_kernel_ms",
+           "lagot_solve_batched", "lagot_solve_moved", "lagot_set_threads_per_cell", "lagot_set_cg_shape", "lagot_set_cg_split", "lagot_last_fallback_cells", "lagot_last_flag_counts", "lagot_last_pass_counts", "lagot_last_kernel_times", "lagot_last_deferred", "lagot_centroids", "lagot_cells_paper_k", "lagot_set_domain", "lagot_set_domain_pieces", "lagot_last_cell_kernel_ms",
            "lagot_p1_laplacian", "lagot_default_fluid_params", "lagot_fluid_velocity", "lagot_fluid_step",
            "lagot_mlp_set_params", "lagot_mlp_get_params", "lagot_features", "lagot_mlp_forward", "lagot_mlp_forward_noalloc",
            "lagot_mlp_train_step", "lagot_mlp_last_grads", "lagot_strerror"]
@@ -126,6 +126,8 @@ def load():
         lib.lagot_set_cg_split.restype = I
         lib.lagot_set_domain.argtypes = [P, ctypes.c_int, P]
         lib.lagot_set_domain.restype = I
+        lib.lagot_set_domain_pieces.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_int]
+        lib.lagot_set_domain_pieces.restype = I
         lib.lagot_centroids.argtypes = [P, I64, P, P, P, P, Box, P, P]
         lib.lagot_centroids.restype = I
         lib.lagot_cells_paper_k.argtypes = [P, I64, P, P, P, P, Box, P, P]
@@ -366,6 +368,22 @@ class Context:
         if rc != OK:
             raise LagotError(rc, "lagot_set_domain")
         self._nwall = max(p, 0) if p else 6
+
+    def set_domain_pieces(self, pieces, nwalls: int) -> None:
+        """lagot_set_domain_pieces: a non-convex domain as the union of convex pieces.
+        ``pieces`` is a list of (planes [P_k, 4] (unit outward normal, c), wall_id [P_k]
+        (wall index, or -1 for a plane between pieces)); ``nwalls`` walls in all."""
+        import numpy as np
+        planes = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64).reshape(-1, 4) for p, _ in pieces]))
+        wid = np.ascontiguousarray(np.concatenate([np.asarray(w, np.int32).reshape(-1) for _, w in pieces]), np.int32)
+        off = np.ascontiguousarray(np.cumsum([0] + [np.asarray(p).reshape(-1, 4).shape[0] for p, _ in pieces]),
+                                   np.int32)
+        rc = load().lagot_set_domain_pieces(self._h, len(pieces), off.ctypes.data_as(ctypes.c_void_p),
+                                            planes.ctypes.data_as(ctypes.c_void_p),
+                                            wid.ctypes.data_as(ctypes.c_void_p), int(nwalls))
+        if rc != OK:
+            raise LagotError(rc, "lagot_set_domain_pieces")
+        self._nwall = int(nwalls)
 
     def set_cg_shape(self, lanes_per_row: int, rows_per_block: int) -> None:
         rc = load().lagot_set_cg_shape(self._h, int(lanes_per_row), int(rows_per_block))

@@ -118,8 +118,19 @@ struct lagot_ctx {
     int64_t cap_fl = 0;
     int fl_chunk = 32;          // fluid PCG launches between host checks (adapted per call)
     bool fl_reuse = false;      // lagot_fluid_step's velocity update: reuse its solve's sorted sites
-    float4 *dom_d = nullptr;    // [DOM_MAX] convex domain planes (lagot_set_domain)
+    float4 *dom_d = nullptr;    // [PIECE_PLANES_MAX] domain planes (lagot_set_domain, lagot_set_domain_pieces)
     int ndom = 0;
+    // a non-convex domain as a union of convex pieces (lagot_set_domain_pieces; 0: convex)
+    int npieces = 0, nwalls = 0;
+    int32_t h_dom_off[PIECE_MAX + 1] = {0};
+    int32_t *dom_off_d = nullptr, *dom_wid_d = nullptr;  // [PIECE_MAX + 1], [PIECE_PLANES_MAX]
+    // per-piece accumulators of an evaluation (allocated with the sites when pieces are set)
+    double *pa_V = nullptr, *pa_K = nullptr, *pa_mom = nullptr, *pa_cen = nullptr;
+    int32_t *pa_fcol = nullptr, *pa_fcnt = nullptr;
+    float *pa_farea = nullptr, *pa_wall = nullptr;
+    uint32_t *pa_flags = nullptr;
+    int64_t cap_piece = 0;
+    int cap_piece_w = 0;
     int wall_w = 6;             // wall areas per site in the wall buffer (6, or the domain's planes)
     float *farea = nullptr;
     uint32_t *flags = nullptr;
@@ -210,6 +221,12 @@ void free_sites(lagot_ctx *c) {
     c->cap_n = 0;
 }
 
+void free_pieces(lagot_ctx *c) {
+    free_ptrs(c->pa_V, c->pa_K, c->pa_mom, c->pa_cen, c->pa_fcol, c->pa_fcnt, c->pa_farea, c->pa_wall, c->pa_flags);
+    c->cap_piece = 0;
+    c->cap_piece_w = 0;
+}
+
 void free_inst(lagot_ctx *c) {
     free_ptrs(c->off, c->tile_inst, c->tile_row, c->first_tile, c->grid, c->box, c->rmax, c->phase, c->ctl, c->ev,
               c->ev2, c->ev_nu, c->part_ev, c->fb_inst, c->fail_inst, c->bad_inst, c->herr, c->cg_part, c->cg_cgs,
@@ -253,6 +270,8 @@ void free_all(lagot_ctx *c) {
     free_sites(c);
     free_inst(c);
     c->cap_qtmp_n = 0;
+    free_pieces(c);
+    free_ptrs(c->dom_off_d, c->dom_wid_d);
     free_ptrs(c->cell_count, c->cell_start, c->cursor, c->scan_tmp, c->counts, c->misc, c->dom_d, c->fl_buf, c->fl_int, c->fl_ent,
               c->hent, c->qcount, c->qstart, c->qcursor, c->qtmp, c->cont_buf, c->lr_rmc, c->lr_ir, c->mv_buf,
               c->mv_pos);
@@ -335,6 +354,26 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->csr_start, N + 1));
     HIP_TRY(dalloc(&c->csr_tmp, N / 1024 + 16));
     c->cap_n = n;
+    return LAGOT_OK;
+}
+
+// accumulators of the per-piece evaluations of a non-convex domain
+int ensure_pieces(lagot_ctx *c, int64_t n) {
+    if (c->npieces == 0 || (n <= c->cap_piece && c->nwalls <= c->cap_piece_w)) return LAGOT_OK;
+    free_pieces(c);
+    const size_t N = (size_t)std::max(n, c->cap_n);
+    const int w = std::max(c->nwalls, 1);
+    HIP_TRY(dalloc(&c->pa_V, N));
+    HIP_TRY(dalloc(&c->pa_K, N));
+    HIP_TRY(dalloc(&c->pa_mom, 3 * N));
+    HIP_TRY(dalloc(&c->pa_cen, 3 * N));
+    HIP_TRY(dalloc(&c->pa_fcol, FCAP * N));
+    HIP_TRY(dalloc(&c->pa_farea, FCAP * N));
+    HIP_TRY(dalloc(&c->pa_fcnt, N));
+    HIP_TRY(dalloc(&c->pa_flags, N));
+    HIP_TRY(dalloc(&c->pa_wall, (size_t)w * N));
+    c->cap_piece = (int64_t)N;
+    c->cap_piece_w = w;
     return LAGOT_OK;
 }
 
@@ -452,6 +491,9 @@ Batch batch(const lagot_ctx *c) {
     b.phase = c->phase;
     b.dom = c->dom_d;
     b.ndom = c->ndom;
+    b.npieces = c->npieces;
+    b.dom_off = c->dom_off_d;
+    b.dom_wid = c->dom_wid_d;
     b.cgrid = c->cgrid;
     b.ir = c->crowd ? reinterpret_cast<const float *>(c->lr_ir) : nullptr;
     return b;
@@ -490,6 +532,7 @@ int prepare(lagot_ctx *c, int B, const int64_t *offs, const float *x, const floa
     for (int b = 0; b < B; ++b) T64 += (offs[b + 1] - offs[b] + TILE - 1) / TILE;
     const int T = (int)T64;
     int rc = ensure_sites(c, n);
+    if (!rc) rc = ensure_pieces(c, n);
     if (!rc) rc = ensure_inst(c, B, T);
     if (rc) return rc;
     c->B = B;
@@ -666,11 +709,66 @@ EvalOut eval_out(lagot_ctx *c, bool walls) {
 // Cells of the instances in phase `want` (< 0: all) at the float64 weights psi_eval
 // (grid order; float32 shadow in pos_s.w, r_max per instance on the device); the
 // per-instance statistics go to ev_out when it is given.
+// wall areas per site: 6 box walls, a convex domain's planes, or a non-convex domain's walls
+int wall_count(const lagot_ctx *c) { return c->npieces > 0 ? c->nwalls : (c->ndom > 0 ? c->ndom : 6); }
+
+PieceAcc piece_acc(const lagot_ctx *c) {
+    PieceAcc a;
+    a.V = c->pa_V;
+    a.K = c->pa_K;
+    a.mom = c->pa_mom;
+    a.fcol = c->pa_fcol;
+    a.farea = c->pa_farea;
+    a.fcnt = c->pa_fcnt;
+    a.flags = c->pa_flags;
+    a.wall = c->pa_wall;
+    a.cen = c->pa_cen;
+    return a;
+}
+
+// A non-convex domain (a union of convex pieces with disjoint interiors): the restricted
+// cell is the union of its parts in the pieces, so volume, spherical area, facet areas,
+// wall areas and first moments are sums over the pieces. Each piece is evaluated as a
+// convex domain (all passes), and its outputs are added to the accumulators; the sums are
+// then written back as the evaluation's outputs (section 6: cells in polyhedral domains).
+void evaluate_pieces(lagot_ctx *c, int want, const double *psi_eval, bool walls, const Batch &bt, const EvalOut &o,
+                     bool timed) {
+    hipStream_t st = c->stream;
+    const QBoxes qb = qboxes(c);
+    const PieceAcc acc = piece_acc(c);
+    c->eval_crowd = c->crowd;
+    if (c->crowd) launch_local_reach(st, c->n, bt, want, c->nc, c->pos_s, c->lr_rmc, c->lr_ir);
+    if (timed) (void)hipEventRecord(c->ev0, st);
+    for (int k = 0; k < c->npieces; ++k) {
+        Batch bk = bt;
+        bk.dom = c->dom_d + c->h_dom_off[k];
+        bk.ndom = c->h_dom_off[k + 1] - c->h_dom_off[k];
+        bk.npieces = 0;
+        EvalOut ok = o;
+        ok.cen = o.cen ? acc.cen : nullptr;
+        launch_piece_begin(st, o.fb_count, o.ovf_count);
+        if (walls) launch_zero_f32(st, c->wall, (int64_t)bk.ndom * c->n);
+        launch_cells(st, c->n, bk, want, c->pos_s, psi_eval, c->perm, c->cell_start, ok, qb, c->tpc, c->crowd);
+        launch_cells_fallback(st, c->n, bk, want, c->pos_s, psi_eval, c->perm, c->cell_start, ok, qb, c->crowd,
+                              nullptr, nullptr);
+        launch_piece_accum(st, c->n, bt, want, k == 0, ok, bk.ndom, c->dom_wid_d + c->h_dom_off[k], c->nwalls, c->perm,
+                           acc);
+    }
+    launch_piece_final(st, c->n, bt, want, o, c->nwalls, c->perm, c->pos_s, o.cen, acc);
+    if (timed) (void)hipEventRecord(c->ev1, st);
+    if (!c->capturing) c->ev_pending = true;
+}
+
 void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double *ev_out) {
     const Batch bt = batch(c);
     const EvalOut o = eval_out(c, walls);
     const bool timed = !c->capturing || c->graph_events;
     launch_eval_begin(c->stream, bt, want, o);
+    if (c->npieces > 0) {
+        evaluate_pieces(c, want, psi_eval, walls, bt, o, timed);
+        if (ev_out) launch_eval_reduce(c->stream, bt, want, c->V, c->nu_s, c->part_ev, ev_out);
+        return;
+    }
     if (walls)
         (void)hipMemsetAsync(c->wall, 0, (size_t)(c->ndom > 0 ? c->ndom : 6) * sizeof(float) * (size_t)c->n,
                              c->stream);
@@ -1629,7 +1727,7 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
     evaluate(c, -1, c->psi_s, wall_area != nullptr, nullptr);
     launch_scatter_out_f64(st, n, c->perm, c->V, vol);
     if (sph_area) launch_scatter_out_f64(st, n, c->perm, c->K, sph_area);
-    if (wall_area) launch_scatter_walls(st, n, c->ndom > 0 ? c->ndom : 6, c->perm, c->wall, wall_area);
+    if (wall_area) launch_scatter_walls(st, n, wall_count(c), c->perm, c->wall, wall_area);
     HIP_TRY(hipMemcpyAsync(c->h_cnt, c->misc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(c->h_cnt + 1, c->fail_inst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (csr || nnz_out) {
@@ -1657,7 +1755,7 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
 
 int lagot_cells_paper_k(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
                         lagot_box box, double *vol, double *sph_area) {
-    if (!c || !vol || !sph_area || n <= 0) return LAGOT_EINVAL;
+    if (!c || !vol || !sph_area || n <= 0 || c->npieces > 0) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     c->tpc = c->tpc_default;
     c->ms_cell = 0.0;
@@ -1987,6 +2085,17 @@ int lagot_last_pass_counts(lagot_ctx *ctx, int64_t *counts) {
     return LAGOT_OK;
 }
 
+// a wall buffer of at least w areas per site for the next calls
+static int widen_walls(lagot_ctx *c, int w) {
+    if (w <= c->wall_w) return LAGOT_OK;
+    if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->wall) (void)hipFree(c->wall);
+    c->wall = nullptr;
+    c->wall_w = w;
+    if (c->cap_n > 0) HIP_TRY(dalloc(&c->wall, (size_t)w * (size_t)c->cap_n));
+    return LAGOT_OK;
+}
+
 int lagot_set_domain(lagot_ctx *c, int nplanes, const double *planes) {
     if (!c || nplanes < 0 || nplanes > DOM_MAX || (nplanes > 0 && !planes)) return LAGOT_EINVAL;
     float4 h[DOM_MAX];
@@ -1997,20 +2106,54 @@ int lagot_set_domain(lagot_ctx *c, int nplanes, const double *planes) {
         h[w] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
     }
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
-    if (!c->dom_d) HIP_TRY(dalloc(&c->dom_d, DOM_MAX));
+    if (!c->dom_d) HIP_TRY(dalloc(&c->dom_d, PIECE_PLANES_MAX));
     if (nplanes > 0) {
         HIP_TRY(hipMemcpyAsync(c->dom_d, h, sizeof(float4) * nplanes, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
     }
-    const int w = std::max(6, nplanes);
-    if (w > c->wall_w) {  // a wider wall buffer for the next calls
-        if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
-        if (c->wall) (void)hipFree(c->wall);
-        c->wall = nullptr;
-        c->wall_w = w;
-        if (c->cap_n > 0) HIP_TRY(dalloc(&c->wall, (size_t)w * (size_t)c->cap_n));
-    }
+    const int rc = widen_walls(c, std::max(6, nplanes));
+    if (rc) return rc;
     c->ndom = nplanes;
+    c->npieces = 0;
+    c->nwalls = 0;
+    return LAGOT_OK;
+}
+
+int lagot_set_domain_pieces(lagot_ctx *c, int npieces, const int32_t *piece_off, const double *planes,
+                            const int32_t *wall_id, int nwalls) {
+    if (!c || npieces < 1 || npieces > PIECE_MAX || !piece_off || !planes || !wall_id) return LAGOT_EINVAL;
+    if (nwalls < 1 || nwalls > PIECE_PLANES_MAX || piece_off[0] != 0) return LAGOT_EINVAL;
+    int widest = 0;
+    for (int k = 0; k < npieces; ++k) {
+        const int m = piece_off[k + 1] - piece_off[k];
+        if (m < 1 || m > DOM_MAX) return LAGOT_EINVAL;
+        widest = std::max(widest, m);
+    }
+    const int total = piece_off[npieces];
+    if (total > PIECE_PLANES_MAX) return LAGOT_EINVAL;
+    float4 h[PIECE_PLANES_MAX];
+    for (int w = 0; w < total; ++w) {
+        const double *q = planes + 4 * w;
+        const double len = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        if (!(std::fabs(len - 1.0) <= 1e-6) || !std::isfinite(q[3])) return LAGOT_EINVAL;
+        if (wall_id[w] < -1 || wall_id[w] >= nwalls) return LAGOT_EINVAL;
+        h[w] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
+    if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!c->dom_d) HIP_TRY(dalloc(&c->dom_d, PIECE_PLANES_MAX));
+    if (!c->dom_off_d) HIP_TRY(dalloc(&c->dom_off_d, PIECE_MAX + 1));
+    if (!c->dom_wid_d) HIP_TRY(dalloc(&c->dom_wid_d, PIECE_PLANES_MAX));
+    HIP_TRY(hipMemcpyAsync(c->dom_d, h, sizeof(float4) * total, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->dom_off_d, piece_off, sizeof(int32_t) * (npieces + 1), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->dom_wid_d, wall_id, sizeof(int32_t) * total, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int rc = widen_walls(c, std::max(6, std::max(widest, nwalls)));
+    if (rc) return rc;
+    for (int k = 0; k <= npieces; ++k) c->h_dom_off[k] = piece_off[k];
+    c->ndom = total;
+    c->npieces = npieces;
+    c->nwalls = nwalls;
     return LAGOT_OK;
 }
 
@@ -2179,6 +2322,7 @@ int lagot_fluid_step(lagot_ctx *c, int64_t n, float *x, float *y, float *z, cons
                      const lagot_fluid_params *prm, const lagot_opts *opts, lagot_stats *stats, int32_t *cg_iters) {
     if (!c || !x || !y || !z || !nu || !psi_inout || !mass || !v_inout || !prm || n <= 0) return LAGOT_EINVAL;
     if (!box_ok(box) || !fluid_params_ok(*prm, mu != nullptr)) return LAGOT_EINVAL;
+    if (c->npieces > 0) return LAGOT_EINVAL;  // the advection keeps sites in a convex domain only
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     {
         // every input is checked before a site moves: options, prescribed volumes,

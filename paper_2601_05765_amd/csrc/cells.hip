@@ -680,7 +680,9 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
                     t = (R)q.w - (nx * px + ny * py + nz * pz);
                     keep = t < r;
                 }
-                f(keep, false, false, nx, ny, nz, t, -1 - w, R(0));
+                // the site may lie outside the domain's convex piece: behind the plane (t < 0),
+                // and beyond the ball's reach (t <= -r: the cell has no part in the piece)
+                f(keep, live && w < A.bt.ndom && t <= -r, keep && t < R(0), nx, ny, nz, t, -1 - w, R(0));
             }
             return;
         }

@@ -252,13 +252,123 @@ __global__ void k_validate(int64_t n, Batch bt, const float *__restrict__ x, con
     float p[3] = {x[i], y[i], z[i]};
     bool ok = true;
     for (int a = 0; a < 3; ++a) ok = ok && (p[a] > box.lo[a]) && (p[a] < box.hi[a]);  // false for NaN
-    for (int w = 0; w < bt.ndom; ++w) {  // strictly inside every domain plane
-        const float4 q = bt.dom[w];
-        ok = ok && (q.x * p[0] + q.y * p[1] + q.z * p[2] < q.w);
+    if (bt.npieces > 0) {
+        // strictly inside some piece (a site on a plane of a piece would see that plane's
+        // facet at a solid angle that depends on the side it is approached from)
+        bool in_any = false;
+        for (int k = 0; k < bt.npieces; ++k) {
+            bool in = true;
+            for (int w = bt.dom_off[k]; w < bt.dom_off[k + 1]; ++w) {
+                const float4 q = bt.dom[w];
+                in = in && (q.x * p[0] + q.y * p[1] + q.z * p[2] < q.w);
+            }
+            in_any = in_any || in;
+        }
+        ok = ok && in_any;
+    } else {
+        for (int w = 0; w < bt.ndom; ++w) {  // strictly inside every domain plane
+            const float4 q = bt.dom[w];
+            ok = ok && (q.x * p[0] + q.y * p[1] + q.z * p[2] < q.w);
+        }
     }
     if (psi) ok = ok && !isnan(psi[i]);
     if (nu) ok = ok && (nu[i] > 0.0);
     if (!ok) atomicAdd(bad + b, 1);
+}
+
+__global__ void k_zero_f32(float *p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.f;
+}
+
+__global__ void k_piece_begin(int32_t *fb_count, int32_t *ovf_count) {
+    *fb_count = 0;
+    *ovf_count = 0;
+}
+
+// One piece's outputs into the accumulators (grid row k; the rows of the selected
+// instances): volume, spherical area and first moment added, facets merged by neighbour
+// (areas of the same neighbour summed), wall areas added by wall id (planes between
+// pieces dropped), flags or-ed. A merged list longer than FCAP is a capacity failure.
+__global__ void k_piece_accum(int64_t n, Batch bt, int want, int first, EvalOut o, int nwp,
+                              const int32_t *__restrict__ wid, int nwalls, const int32_t *__restrict__ perm,
+                              PieceAcc a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int b = bt.inst[k];
+    if (!selected(bt, want, b)) return;
+    const double V = o.V[k];
+    const int64_t ci = perm[k];
+    const int cnt = o.fcnt[k];
+    if (first) {
+        a.V[k] = V;
+        a.K[k] = o.K[k];
+        a.flags[k] = o.flags[k];
+        for (int f = 0; f < cnt; ++f) {
+            a.fcol[k * FCAP + f] = o.fcol[k * FCAP + f];
+            a.farea[k * FCAP + f] = o.farea[k * FCAP + f];
+        }
+        a.fcnt[k] = cnt;
+        if (o.cen)
+            for (int q = 0; q < 3; ++q) a.mom[3 * ci + q] = V * o.cen[3 * ci + q];
+        if (o.wall)
+            for (int w = 0; w < nwalls; ++w) a.wall[k * nwalls + w] = 0.f;
+    } else {
+        a.V[k] += V;
+        a.K[k] += o.K[k];
+        uint32_t fl = a.flags[k] | o.flags[k];
+        int m = a.fcnt[k];
+        const int m0 = m;
+        for (int f = 0; f < cnt; ++f) {
+            const int j = o.fcol[k * FCAP + f];
+            const float ar = o.farea[k * FCAP + f];
+            int g = 0;
+            while (g < m0 && a.fcol[k * FCAP + g] != j) ++g;
+            if (g < m0) {
+                a.farea[k * FCAP + g] += ar;
+            } else if (m < FCAP) {
+                a.fcol[k * FCAP + m] = j;
+                a.farea[k * FCAP + m] = ar;
+                ++m;
+            } else if (!(fl & CF_FACETS)) {
+                fl |= CF_FACETS;
+                atomicAdd(o.fail_inst + b, 1);
+            }
+        }
+        a.fcnt[k] = m;
+        a.flags[k] = fl;
+        if (o.cen)
+            for (int q = 0; q < 3; ++q) a.mom[3 * ci + q] += V * o.cen[3 * ci + q];
+    }
+    if (o.wall)
+        for (int p = 0; p < nwp; ++p)
+            if (wid[p] >= 0) a.wall[k * nwalls + wid[p]] += o.wall[k * nwp + p];
+}
+
+// The accumulated sums as the evaluation's outputs; a cell is empty when its parts are.
+__global__ void k_piece_final(int64_t n, Batch bt, int want, EvalOut o, int nwalls, const int32_t *__restrict__ perm,
+                              const float4 *__restrict__ pos_s, double *__restrict__ cen_out, PieceAcc a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (!selected(bt, want, bt.inst[k])) return;
+    const double V = a.V[k];
+    o.V[k] = V;
+    o.K[k] = a.K[k];
+    const int cnt = a.fcnt[k];
+    for (int f = 0; f < cnt; ++f) {
+        o.fcol[k * FCAP + f] = a.fcol[k * FCAP + f];
+        o.farea[k * FCAP + f] = a.farea[k * FCAP + f];
+    }
+    o.fcnt[k] = cnt;
+    o.flags[k] = (a.flags[k] & ~(uint32_t)CF_EMPTY) | (V > 0.0 ? 0u : (uint32_t)CF_EMPTY);
+    if (o.wall)
+        for (int w = 0; w < nwalls; ++w) o.wall[k * nwalls + w] = a.wall[k * nwalls + w];
+    if (cen_out) {
+        const int64_t ci = perm[k];
+        const float4 p = pos_s[k];
+        const double ps[3] = {(double)p.x, (double)p.y, (double)p.z};
+        for (int q = 0; q < 3; ++q) cen_out[3 * ci + q] = V > 0.0 ? a.mom[3 * ci + q] / V : ps[q];
+    }
 }
 
 // facet counts per caller row
@@ -549,6 +659,26 @@ void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst) {
 
 void launch_zero_i32(hipStream_t st, int32_t *p, int64_t count) {
     hipLaunchKernelGGL(k_zero_i32, dim3(nblocks(count, 256)), dim3(256), 0, st, p, count);
+}
+
+void launch_zero_f32(hipStream_t st, float *p, int64_t count) {
+    hipLaunchKernelGGL(k_zero_f32, dim3(nblocks(count, 256)), dim3(256), 0, st, p, count);
+}
+
+void launch_piece_begin(hipStream_t st, int32_t *fb_count, int32_t *ovf_count) {
+    hipLaunchKernelGGL(k_piece_begin, dim3(1), dim3(1), 0, st, fb_count, ovf_count);
+}
+
+void launch_piece_accum(hipStream_t st, int64_t n, const Batch &bt, int want, bool first, const EvalOut &o,
+                        int nw_piece, const int32_t *wid_piece, int nwalls, const int32_t *perm, PieceAcc acc) {
+    hipLaunchKernelGGL(k_piece_accum, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, first ? 1 : 0, o,
+                       nw_piece, wid_piece, nwalls, perm, acc);
+}
+
+void launch_piece_final(hipStream_t st, int64_t n, const Batch &bt, int want, const EvalOut &o, int nwalls,
+                        const int32_t *perm, const float4 *pos_s, double *cen_out, PieceAcc acc) {
+    hipLaunchKernelGGL(k_piece_final, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, o, nwalls, perm, pos_s,
+                       cen_out, acc);
 }
 
 void launch_rmax(hipStream_t st, const Batch &bt, int want, const double *psi, double *rmax) {

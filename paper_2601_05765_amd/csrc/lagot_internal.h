@@ -108,6 +108,12 @@ struct Batch {
     const int32_t *phase;        // [B] Phase
     const float4 *dom;           // [ndom] convex domain planes (unit outward normal, offset c: n.x <= c)
     int ndom;                    // 0: the box walls bound the cells
+    // a union of convex pieces (npieces > 0): piece k holds planes dom[dom_off[k] .. dom_off[k+1]),
+    // dom_wid[w] is plane w's wall (-1: a plane between pieces); the cell passes see one piece
+    // at a time (npieces 0, dom and ndom of that piece)
+    int npieces;
+    const int32_t *dom_off;
+    const int32_t *dom_wid;
     // local reach (null: r_max of the instance bounds every ball): ir[cgrid base + c] bounds
     // the radius of every ball whose site lies within twice its radius of coarse cell c
     const GridDesc *cgrid;       // [B] coarse grids (laid end to end)
@@ -115,6 +121,8 @@ struct Batch {
 };
 
 constexpr int DOM_MAX = 32;      // planes of a convex polyhedral domain
+constexpr int PIECE_MAX = 16;    // convex pieces of a non-convex domain
+constexpr int PIECE_PLANES_MAX = 64;  // planes of all its pieces together
 constexpr int AUX_PLANE_ID = -1000000;  // ids of the clipper's auxiliary cube planes (walls: -1-w)
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD w mod 8),
@@ -255,6 +263,24 @@ struct Cg3Bufs {
 // grid.hip
 void launch_fill_inst(hipStream_t st, const Batch &bt, int32_t *inst);
 void launch_zero_i32(hipStream_t st, int32_t *p, int64_t count);
+// Non-convex domains (a union of convex pieces): the per-piece evaluation outputs are
+// summed into accumulators (volume, area, facet lists merged by neighbour, walls by wall
+// id, first moments), which the last call writes back as the evaluation's outputs.
+struct PieceAcc {
+    double *V, *K, *mom;   // [n], [n], [3n] (caller order: the first moments sum V_k c_k)
+    int32_t *fcol;         // [n*FCAP]
+    float *farea;          // [n*FCAP]
+    int32_t *fcnt;         // [n]
+    uint32_t *flags;       // [n]
+    float *wall;           // [nwalls*n]
+    double *cen;           // [3n] the piece pass's centroids (caller order)
+};
+void launch_piece_begin(hipStream_t st, int32_t *fb_count, int32_t *ovf_count);
+void launch_zero_f32(hipStream_t st, float *p, int64_t count);
+void launch_piece_accum(hipStream_t st, int64_t n, const Batch &bt, int want, bool first, const EvalOut &o,
+                        int nw_piece, const int32_t *wid_piece, int nwalls, const int32_t *perm, PieceAcc acc);
+void launch_piece_final(hipStream_t st, int64_t n, const Batch &bt, int want, const EvalOut &o, int nwalls,
+                        const int32_t *perm, const float4 *pos_s, double *cen_out, PieceAcc acc);
 void launch_validate(hipStream_t st, int64_t n, const Batch &bt, const float *x, const float *y, const float *z,
                      const double *psi, const double *nu, int32_t *bad_inst);
 void launch_gather_sites(hipStream_t st, int64_t n, const float *x, const float *y, const float *z,

@@ -259,3 +259,71 @@ CONFIGS = {
     "c2_dam_100k": lambda seed=0: dam_break(100_000, seed),
     "c3_splash_2m": lambda seed=0: splash(2_000_000, seed),
 }
+
+
+# An L-shaped prism, the unit box without the quarter x > 1/2, y > 1/2: a non-convex
+# polyhedral domain given as convex pieces (each a list of planes (n, c), n.x <= c, with
+# the wall each plane bounds, or -1 for a plane between two pieces). Walls: 0 x = 0,
+# 1 y = 0, 2 z = 0, 3 z = 1, 4 x = 1, 5 y = 1, 6 x = 1/2 (for y > 1/2), 7 y = 1/2 (for
+# x > 1/2). Every plane of a piece lies wholly on a wall or wholly between two pieces.
+L_WALLS = 8
+L_VOLUME = 0.75
+L_WALL_AREAS = (1.0, 1.0, 0.75, 0.75, 0.5, 0.5, 0.5, 0.5)
+
+
+def _slab_planes(x0, x1, y0, y1, z0, z1, ids):
+    """The six planes of the box [x0,x1] x [y0,y1] x [z0,z1] (-x, +x, -y, +y, -z, +z) and
+    their wall ids."""
+    planes = [[-1.0, 0.0, 0.0, -x0], [1.0, 0.0, 0.0, x1], [0.0, -1.0, 0.0, -y0], [0.0, 1.0, 0.0, y1],
+              [0.0, 0.0, -1.0, -z0], [0.0, 0.0, 1.0, z1]]
+    return np.array(planes), np.array(ids, np.int32)
+
+
+def l_shape_pieces(split_z: bool = False):
+    """The L-shaped prism as 3 convex pieces (2 x 2 x 1 quarters less one), or 6 with each
+    also cut at z = 1/2. Returns the list of (planes [6, 4], wall ids [6])."""
+    quarters = [((0.0, 0.5), (0.0, 0.5), (0, -1, 1, -1)),
+                ((0.5, 1.0), (0.0, 0.5), (-1, 4, 1, 7)),
+                ((0.0, 0.5), (0.5, 1.0), (0, 6, -1, 5))]
+    zs = [((0.0, 0.5), (2, -1)), ((0.5, 1.0), (-1, 3))] if split_z else [((0.0, 1.0), (2, 3))]
+    pieces = []
+    for (x0, x1), (y0, y1), wxy in quarters:
+        for (z0, z1), wz in zs:
+            pieces.append(_slab_planes(x0, x1, y0, y1, z0, z1, list(wxy) + list(wz)))
+    return pieces
+
+
+def in_l_shape(p: np.ndarray, eps: float = 1e-6) -> np.ndarray:
+    """Points strictly inside the L-shaped prism (by eps)."""
+    inside_box = np.all((p > eps) & (p < 1.0 - eps), axis=1)
+    cut = (p[:, 0] > 0.5 - eps) & (p[:, 1] > 0.5 - eps)
+    return inside_box & ~cut
+
+
+def l_shape_sites(n: int, seed: int, spread: float = 0.15) -> Scene:
+    """n sites uniform in the L-shaped prism, nu = 0.5 |L| / n, start radii the default
+    start's times a log-normal factor (sigma `spread`)."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    while sum(len(q) for q in pts) < n:
+        q = rng.uniform(0.0, 1.0, (2 * n, 3))
+        pts.append(q[in_l_shape(q, 1e-4)])
+    p = np.concatenate(pts)[:n]
+    nu = np.full(n, 0.5 * L_VOLUME / n)
+    psi = default_psi0(nu) * np.exp(2.0 * spread * rng.standard_normal(n))
+    return Scene(f"l_shape_{n}", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, psi)
+
+
+def l_shape_crowded(n: int = 2500, seed: int = 0, over: float = 1.72, R: float = 0.15,
+                    radius_factor: float = 3.0) -> Scene:
+    """The over-packed sphere (jittered lattice, volumes `over` times the sphere's) centred
+    at (0.36, 0.36, 0.5) in the L-shaped prism, next to the planes between its pieces and
+    the re-entrant edge; the few sites outside the prism are dropped. The start radii are
+    radius_factor (3 nu / 4 pi)^(1/3): equal weights (the Voronoi cells) with balls that
+    reach hundreds of neighbours, so that the cells are crowded."""
+    sc = overpacked_sphere(n, over, seed, R)
+    p = np.stack([sc.x, sc.y, sc.z], 1).astype(np.float64) + np.array([-0.14, -0.14, 0.0])
+    keep = in_l_shape(p, 1e-4)
+    p = p[keep]
+    nu = sc.nu[keep]
+    return Scene("l_shape_crowded", _f32(p[:, 0]), _f32(p[:, 1]), _f32(p[:, 2]), nu, default_psi0(nu, radius_factor))

@@ -185,3 +185,124 @@ def test_domain_errors_and_reset(ctx):
     finally:
         ctx.set_domain(None)
     assert np.array_equal(ref, six)
+
+
+# ---- non-convex domains: unions of convex pieces (lagot_set_domain_pieces) ----
+
+def _halves():
+    """The unit box as two pieces split at x = 0.6 (walls 0..5 = -x, +x, -y, +y, -z, +z)."""
+    left = (np.array([[-1, 0, 0, 0], [1, 0, 0, 0.6], [0, -1, 0, 0], [0, 1, 0, 1], [0, 0, -1, 0], [0, 0, 1, 1]],
+                     np.float64), [0, -1, 2, 3, 4, 5])
+    right = (np.array([[-1, 0, 0, -0.6], [1, 0, 0, 1], [0, -1, 0, 0], [0, 1, 0, 1], [0, 0, -1, 0], [0, 0, 1, 1]],
+                      np.float64), [-1, 1, 2, 3, 4, 5])
+    return [(_f32_planes(p), w) for p, w in (left, right)]
+
+
+@pytest.mark.parametrize("case,split_z", [("uniform", False), ("uniform", True), ("crowded", False)])
+def test_l_prism_cells_parity(ctx, oracle_mod, case, split_z):
+    """Every cell in the L-shaped prism (3 or 6 pieces) against the oracle: V, K, facet
+    areas and connectivity, the 8 walls (re-entrant ones included) and the first moments
+    about the sites (on the ball's scale, r times its volume, like the volumes: the
+    centroid of a cell empty up to rounding is 0/0). 'crowded' is the over-packed sphere
+    next to the planes between pieces, whose cells go through the crowded pass."""
+    _say(f"case: cells in the L prism, {6 if split_z else 3} pieces, {case} sites")
+    sc = scenes.l_shape_sites(1500, 11) if case == "uniform" else scenes.l_shape_crowded(2500, 0)
+    pieces = scenes.l_shape_pieces(split_z)
+    args = _dev(sc.x, sc.y, sc.z, sc.psi0)
+    ctx.set_domain_pieces(pieces, scenes.L_WALLS)
+    try:
+        # the first evaluation with crowded cells announces them (they finish on the
+        # float64 pass); the later ones take the crowded pass
+        first = ctx.cells(*args)
+        out = ctx.cells(*args)
+        crowd = ctx.last_pass_counts()["crowded_pass"]
+        vol, cen = ctx.centroids(*args)
+    finally:
+        ctx.set_domain(None)
+    orc = oracle_mod.cells_pieces(sc.x, sc.y, sc.z, sc.psi0, pieces, scenes.L_WALLS)
+    assert_close(compare(first, orc, sc.psi0))
+    rep = compare(out, orc, sc.psi0)
+    r = np.sqrt(sc.psi0)
+    ball = 4.0 / 3.0 * math.pi * r ** 3
+    site = np.stack([sc.x, sc.y, sc.z], 1).astype(np.float64)
+    V = vol.cpu().numpy()
+    eM = np.abs(V[:, None] * (cen.cpu().numpy() - site) - orc.V[:, None] * (orc.C - site)).max(1) / (ball * r)
+    _say(f"  {sc.n} sites: {rep}; first moments {eM.max():.2e}; crowded pass {crowd}; "
+         f"empty {(orc.V == 0).sum()}")
+    assert out["walls"].shape[1] == scenes.L_WALLS
+    assert_close(rep)
+    assert eM.max() <= 1e-5
+    assert np.array_equal(V, out["vol"].cpu().numpy())
+    assert (orc.walls[:, 6] > 0).any() and (orc.walls[:, 7] > 0).any() or case == "crowded"
+    if case == "crowded":
+        assert crowd
+
+
+def test_box_split_in_two_pieces(ctx, oracle_mod):
+    """The unit box given as two pieces (cut at x = 0.6): the cells against the oracle's
+    box cells; sites lie on both sides of the cut and many balls cross it."""
+    _say("case: the unit box as two pieces")
+    sc = scenes.random_small(400, 2, lo=0.05, hi=0.95, r_lo=0.05, r_hi=0.25)
+    ctx.set_domain_pieces(_halves(), 6)
+    try:
+        out = ctx.cells(*_dev(sc.x, sc.y, sc.z, sc.psi0))
+    finally:
+        ctx.set_domain(None)
+    orc = oracle_mod.cells(sc.x, sc.y, sc.z, sc.psi0)
+    rep = compare(out, orc, sc.psi0)
+    _say(f"  {rep}")
+    assert_close(rep)
+
+
+def test_l_prism_solve(ctx, oracle_mod):
+    """Algorithm 1 in the L-shaped prism (3 pieces): the solve converges and the oracle
+    confirms 300 sampled volumes."""
+    _say("case: solve in the L prism")
+    import paper_2601_05765_amd as L
+    import torch
+    sc = scenes.l_shape_sites(2000, 4)
+    psi0 = scenes.default_psi0(sc.nu)  # the Voronoi start
+    xd, yd, zd, pd = _dev(sc.x, sc.y, sc.z, psi0)
+    nud = torch.tensor(sc.nu, device="cuda")
+    pieces = scenes.l_shape_pieces()
+    ctx.set_domain_pieces(pieces, scenes.L_WALLS)
+    try:
+        st = ctx.solve(xd, yd, zd, nud, pd, opts=L.default_opts(tol=1e-6))
+    finally:
+        ctx.set_domain(None)
+    _say(f"  {sc.n} sites: {st.as_dict()}")
+    assert st.status == 0 and st.max_rel_err <= 1e-6
+    idx = np.sort(np.random.default_rng(3).choice(sc.n, 300, replace=False))
+    c = oracle_mod.cells_pieces(sc.x, sc.y, sc.z, pd.cpu().numpy(), pieces, scenes.L_WALLS, idx=idx)
+    err = float(np.max(np.abs(c.V - sc.nu[idx]) / sc.nu[idx]))
+    _say(f"  oracle: max rel volume error {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_pieces_errors_and_reset(ctx):
+    _say("case: non-convex domain errors, reset to the box")
+    import paper_2601_05765_amd as L
+    pieces = scenes.l_shape_pieces()
+    with pytest.raises(L.LagotError):
+        ctx.set_domain_pieces(pieces, 6)  # wall ids 6 and 7 out of range
+    with pytest.raises(L.LagotError):
+        ctx.set_domain_pieces([(np.array([[1.0, 1.0, 0.0, 0.5]]), [0])], 1)  # normal not unit
+    sc = scenes.l_shape_sites(50, 2)
+    args = _dev(sc.x, sc.y, sc.z, sc.psi0)
+    ref = ctx.cells(*args, csr=False)["vol"].cpu().numpy()
+    ctx.set_domain_pieces(pieces, scenes.L_WALLS)
+    try:
+        # a site in the removed quarter lies in no piece; a site on a plane between pieces
+        # lies strictly inside none
+        for p in ([0.75, 0.75, 0.5], [0.5, 0.25, 0.5]):
+            x, y, z = sc.x.copy(), sc.y.copy(), sc.z.copy()
+            x[0], y[0], z[0] = p
+            with pytest.raises(L.LagotError):
+                ctx.cells(*_dev(x, y, z, sc.psi0), csr=False)
+        with pytest.raises(L.LagotError):
+            ctx.cells_paper_k(*args)
+        ctx.cells(*args, csr=False)
+    finally:
+        ctx.set_domain(None)
+    again = ctx.cells(*args, csr=False)["vol"].cpu().numpy()
+    assert np.array_equal(ref, again)
