@@ -344,6 +344,60 @@ def paper_k_section(ctx, x, y, z, psi, reps: int = 5):
             "max_rel_diff_K": d, "diff_normalised_by": "4 pi r_i^2"}, check
 
 
+def domain_section(ctx, L, scenes, n: int = 100_000, reps: int = 3):
+    """A non-convex domain: n sites in the L-shaped prism (the unit box less the quarter
+    x, y > 1/2) given as 3 convex pieces. Evaluation time against the same sites in the
+    unit box (one convex domain), and a solve from the default start to 1e-5."""
+    import torch
+    t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    sc = scenes.l_shape_sites(n, 0)
+    pieces = scenes.l_shape_pieces()
+    x, y, z = t(sc.x, torch.float32), t(sc.y, torch.float32), t(sc.z, torch.float32)
+    psi0 = scenes.default_psi0(sc.nu)
+    nu = t(sc.nu, torch.float64)
+
+    def eval_ms():
+        p = t(psi0, torch.float64)
+        ctx.cells(x, y, z, p, csr=False, walls=False)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a = time.perf_counter()
+            ctx.cells(x, y, z, p, csr=False, walls=False)
+            torch.cuda.synchronize()
+            ms.append(1000.0 * (time.perf_counter() - a))
+        return float(np.median(ms))
+
+    ms_box = eval_ms()
+    ctx.set_domain_pieces(pieces, scenes.L_WALLS)
+    try:
+        ms_l = eval_ms()
+        psi = t(psi0, torch.float64)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = ctx.solve(x, y, z, nu, psi, opts=L.default_opts(tol=1e-5), check=False)
+        torch.cuda.synchronize()
+        ms_solve = 1000.0 * (time.perf_counter() - a)
+    finally:
+        ctx.set_domain(None)
+    if st.status != 0:
+        raise RuntimeError(f"solve in the L prism failed: {st.as_dict()}")
+    data = (sc.x, sc.y, sc.z, psi.cpu().numpy(), sc.nu)
+
+    def check():
+        import oracle
+        xs, ys, zs, ps, nus = data
+        idx = np.sort(np.random.default_rng(13).choice(len(ps), 300, replace=False))
+        c = oracle.cells_pieces(xs, ys, zs, ps, pieces, scenes.L_WALLS, idx=idx)
+        return summarize(np.abs(c.V - nus[idx]) / nus[idx], "|V_i - nu_i| / nu_i of 300 random cells")
+
+    return {"workload": f"{n} sites uniform in the L-shaped prism [0,1]^3 less x, y > 1/2, 3 convex pieces, "
+                        f"nu = 0.375 / n, default start", "n_sites": n, "pieces": len(pieces),
+            "ms_lagot_cells_l_prism": ms_l, "ms_lagot_cells_unit_box": ms_box, "eval_ratio": ms_l / ms_box,
+            "solve": {"ms": ms_solve, "newton_iters": st.newton_iters, "evals": st.evals,
+                      "halvings": st.halvings, "max_rel_err": st.max_rel_err}}, check
+
+
 def sample_idx(n, psi, seed, k_top=100, k_rand=300):
     """The heaviest sites (the most crowded cells) and a random sample."""
     rng = np.random.default_rng(seed)
@@ -601,6 +655,7 @@ def main(argv=None):
     ap.add_argument("--eval-reps", type=int, default=20)
     ap.add_argument("--no-dam-break", action="store_true", help="skip the 100k dam-break section")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched solve")
+    ap.add_argument("--no-domain", action="store_true", help="skip the non-convex (L-shaped) domain section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--learned-seeds", type=int, default=6, help="training scenes (100k sites each)")
     ap.add_argument("--learned-steps", type=int, default=4, help="advect-and-solve steps per training scene")
@@ -697,6 +752,8 @@ def main(argv=None):
             line["fluid"], checks["fluid"] = fluid_section(ctx, L, x, y, z, psi, nu)
     if not args.no_batched:
         line["batched"], checks["batched"] = batched_section(ctx, L, scenes)
+    if not args.no_domain:
+        line["domain_pieces"], checks["domain_pieces"] = domain_section(ctx, L, scenes)
     if not args.no_learned:
         line["learned"], checks["learned"] = learned_section(ctx, L, scenes, args.learned_seeds,
                                                              args.learned_steps, args.sequence_steps)

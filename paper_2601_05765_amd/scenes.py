@@ -302,12 +302,14 @@ def in_l_shape(p: np.ndarray, eps: float = 1e-6) -> np.ndarray:
 
 def l_shape_sites(n: int, seed: int, spread: float = 0.15) -> Scene:
     """n sites uniform in the L-shaped prism, nu = 0.5 |L| / n, start radii the default
-    start's times a log-normal factor (sigma `spread`)."""
+    start's times a log-normal factor (sigma `spread`). The sites keep 1e-4 off the planes
+    x, y, z = 1/2 between the pieces of l_shape_pieces (a site must not lie on one)."""
     rng = np.random.default_rng(seed)
     pts = []
     while sum(len(q) for q in pts) < n:
         q = rng.uniform(0.0, 1.0, (2 * n, 3))
-        pts.append(q[in_l_shape(q, 1e-4)])
+        off = np.all(np.abs(q - 0.5) > 1e-4, axis=1)
+        pts.append(q[in_l_shape(q, 1e-4) & off])
     p = np.concatenate(pts)[:n]
     nu = np.full(n, 0.5 * L_VOLUME / n)
     psi = default_psi0(nu) * np.exp(2.0 * spread * rng.standard_normal(n))
