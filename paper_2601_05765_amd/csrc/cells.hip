@@ -737,9 +737,20 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
             if (gballot<G>(neg)) inside = false;
         });
     };
+    // a convex piece of the domain that the ball cannot reach (t <= -r for one of its
+    // planes): the cell has no part in it, and no candidate needs to be scanned
+    if (A.bt.ndom > 0 && live && !empty) {
+        bool out = false;
+        for (int w = gl; w < A.bt.ndom; w += G) {
+            const float4 q = A.bt.dom[w];
+            const R nx = (R)q.x, ny = (R)q.y, nz = (R)q.z;
+            out = out || (R)q.w - (nx * px + ny * py + nz * pz) <= -r;
+        }
+        if (gballot<G>(out)) empty = true;
+    }
     if constexpr (MODE == 0) {
         // a search block holding more than FAST_SCAN_MAX sites: crowded, deferred
-        if (live) {
+        if (live && !empty) {
             int tot = 0;
             for (int c0 = 0; c0 < ncol; c0 += G) {
                 int cnt = 0;
@@ -761,7 +772,7 @@ __device__ void cell_body(int64_t cell, const CellArgs &A, CellSmem<R, CMAX, PMA
         // lies in the block) holding at most CMAX candidates. Any subset of the
         // bisectors gives a superset of the cell, so if even the smallest radius holds
         // more, the first CMAX found are kept.
-        if (live) {
+        if (live && !empty) {
             constexpr int ND = 12;
             int cnt[ND];
             R d2k[ND];
