@@ -399,8 +399,7 @@ int lagot_set_domain(lagot_ctx *ctx, int nplanes, const double *planes);
  *        at most 64 planes in all); planes [4 piece_off[npieces]] float64 HOST, (n_x, n_y,
  *        n_z, c) per plane, unit outward normals (|n| within 1e-6 of 1); wall_id
  *        [piece_off[npieces]] int32 HOST; 1 <= npieces <= 16, 1 <= nwalls <= 64.
- * Not with lagot_cells_paper_k or lagot_fluid_step (they return LAGOT_EINVAL while a
- * non-convex domain is set). The crowded pass is not timed per piece (lagot_last_kernel_times
+ * Not with lagot_cells_paper_k (it returns LAGOT_EINVAL while a non-convex domain is set). The crowded pass is not timed per piece (lagot_last_kernel_times
  * reports no crowded-pass time) and lagot_last_pass_counts gives the last piece's counts.
  * Synchronises the stream.
  * Errors: LAGOT_EINVAL (NULL pointers, counts out of range, a normal not unit, c not
@@ -473,8 +472,11 @@ int lagot_fluid_velocity(lagot_ctx *ctx, int64_t n, const float *x, const float 
  * with u = 4 float32 spacings at the largest |bound| (so the rounding to float32 keeps a
  * clamped site strictly inside), and, with convex domain planes (lagot_set_domain), a
  * site beyond n.x = c - m (m = max(1e-6 times the largest box extent, u)) is moved along
- * -n onto that plane, in two passes over the planes. The update x + dt v is formed in
- * float64 with separate roundings and rounded once to float32.
+ * -n onto that plane, in two passes over the planes. With a non-convex domain
+ * (lagot_set_domain_pieces) a site stays where it is if that rule, applied with the planes
+ * of some piece, leaves it in place; else it moves to the nearest of the places the rule
+ * gives with each piece's planes (ties to the first piece). The update x + dt v is formed
+ * in float64 with separate roundings and rounded once to float32.
  *   in/out: x, y, z [n] float32 (device), psi_inout [n] float64, v_inout [3n] float64
  *           site-major; in: nu [n] float64, mass [n] float64 (> 0), mu [n] or NULL,
  *           prm, opts (NULL = defaults) HOST; out: stats (the solve's, HOST, may be

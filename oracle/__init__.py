@@ -292,7 +292,22 @@ def p1_laplacian(W, u: np.ndarray, mu=1.0) -> np.ndarray:
 ADVECT_MARGIN = 1e-6
 
 
-def advect(xyz32: np.ndarray, v: np.ndarray, dt: float, box=((0, 0, 0), (1, 1, 1)), domain=None) -> np.ndarray:
+def _keep_in_planes(p, planes, pm):
+    """The convex rule: a site with n.x - c + pm > 0 is moved by that amount along -n, in
+    two passes over the planes in order (every product and sum rounded separately)."""
+    for _ in range(2):
+        for nx, ny, nz, c in planes:
+            s = ((nx * p[:, 0] + ny * p[:, 1]) + nz * p[:, 2]) - c
+            e = s + pm
+            out = e > 0
+            p[out, 0] -= e[out] * nx
+            p[out, 1] -= e[out] * ny
+            p[out, 2] -= e[out] * nz
+    return p
+
+
+def advect(xyz32: np.ndarray, v: np.ndarray, dt: float, box=((0, 0, 0), (1, 1, 1)), domain=None,
+           pieces=None) -> np.ndarray:
     """Position update of the fluid step (section 5, numerical integration):
     x + dt v in float64, kept inside the domain, rounded once to float32.
 
@@ -302,24 +317,35 @@ def advect(xyz32: np.ndarray, v: np.ndarray, dt: float, box=((0, 0, 0), (1, 1, 1
     a clamped coordinate strictly inside); then, for convex domain planes n.x <= c, a
     site with n.x - c + m > 0 (m = max(1e-6 times the largest box extent, u)) is moved
     by that amount along -n, in two passes over the planes in order. Every product and
-    sum is rounded separately."""
+    sum is rounded separately.
+
+    With ``pieces`` (a non-convex domain, the union of convex pieces given as in
+    ``cells_pieces``): a site stays where it is if the plane rule with the planes of some
+    piece leaves it in place (it lies inside that piece by the margin); else it takes the
+    nearest, in squared distance ((dx^2 + dy^2) + dz^2), of the places the rule gives with
+    each piece's planes, ties to the first piece."""
     lo = np.asarray(box[0], np.float64)
     hi = np.asarray(box[1], np.float64)
     u = 4.0 * float(np.spacing(np.float32(max(np.max(np.abs(lo)), np.max(np.abs(hi))))))
     m = np.maximum(ADVECT_MARGIN * (hi - lo), u)
     p = np.asarray(xyz32, np.float32).astype(np.float64) + dt * np.asarray(v, np.float64)
     p = np.minimum(np.maximum(p, lo + m), hi - m)
-    if domain is not None:
-        pm = max(ADVECT_MARGIN * float(np.max(hi - lo)), u)
-        planes = np.asarray(domain, np.float64).reshape(-1, 4)
-        for _ in range(2):
-            for nx, ny, nz, c in planes:
-                s = ((nx * p[:, 0] + ny * p[:, 1]) + nz * p[:, 2]) - c
-                e = s + pm
-                out = e > 0
-                p[out, 0] -= e[out] * nx
-                p[out, 1] -= e[out] * ny
-                p[out, 2] -= e[out] * nz
+    pm = max(ADVECT_MARGIN * float(np.max(hi - lo)), u)
+    if pieces is not None:
+        best = p.copy()
+        bestd = np.full(p.shape[0], np.inf)
+        done = np.zeros(p.shape[0], bool)
+        for planes, _ in pieces:
+            q = _keep_in_planes(p.copy(), np.asarray(planes, np.float64).reshape(-1, 4), pm)
+            dq = q - p
+            d = (dq[:, 0] * dq[:, 0] + dq[:, 1] * dq[:, 1]) + dq[:, 2] * dq[:, 2]
+            take = ~done & (d < bestd)
+            best[take] = q[take]
+            bestd[take] = d[take]
+            done |= d == 0.0
+        p = best
+    elif domain is not None:
+        p = _keep_in_planes(p, np.asarray(domain, np.float64).reshape(-1, 4), pm)
     return p.astype(np.float32)
 
 
@@ -335,7 +361,7 @@ class FluidStep:
 
 def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.ndarray, mu, dt: float,
                    eps: float, gamma: float, gravity=(0.0, 0.0, 0.0), box=((0, 0, 0), (1, 1, 1)),
-                   domain=None, solver: str = "direct") -> FluidStep:
+                   domain=None, solver: str = "direct", pieces=None, nwalls: int = 0) -> FluidStep:
     """Velocity update of the fluid step, section 5: with the cells at the sites ``xyz``
     and weights ``psi`` (normally the OT solution there),
 
@@ -357,7 +383,10 @@ def fluid_velocity(xyz: np.ndarray, psi: np.ndarray, v: np.ndarray, mass: np.nda
     import scipy.sparse.linalg as sla
     xyz = np.asarray(xyz, np.float64)
     n = xyz.shape[0]
-    c = cells(xyz[:, 0], xyz[:, 1], xyz[:, 2], psi, box, domain=domain)
+    if pieces is not None:  # a non-convex domain (cells_pieces)
+        c = cells_pieces(xyz[:, 0], xyz[:, 1], xyz[:, 2], psi, pieces, nwalls, box)
+    else:
+        c = cells(xyz[:, 0], xyz[:, 1], xyz[:, 2], psi, box, domain=domain)
     W = p1_weights(xyz, c)
     m = np.asarray(mass, np.float64)
     Fp = m[:, None] * (c.C - xyz) / (eps * eps)

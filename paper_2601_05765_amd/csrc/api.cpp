@@ -2322,7 +2322,6 @@ int lagot_fluid_step(lagot_ctx *c, int64_t n, float *x, float *y, float *z, cons
                      const lagot_fluid_params *prm, const lagot_opts *opts, lagot_stats *stats, int32_t *cg_iters) {
     if (!c || !x || !y || !z || !nu || !psi_inout || !mass || !v_inout || !prm || n <= 0) return LAGOT_EINVAL;
     if (!box_ok(box) || !fluid_params_ok(*prm, mu != nullptr)) return LAGOT_EINVAL;
-    if (c->npieces > 0) return LAGOT_EINVAL;  // the advection keeps sites in a convex domain only
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     {
         // every input is checked before a site moves: options, prescribed volumes,
@@ -2355,7 +2354,7 @@ int lagot_fluid_step(lagot_ctx *c, int64_t n, float *x, float *y, float *z, cons
         bd.hi[a] = box.hi[a] - m;
     }
     bd.plane_margin = std::max(ADVECT_MARGIN * ext, ulps);
-    launch_advect(c->stream, n, x, y, z, v_inout, prm->dt, bd, c->dom_d, c->ndom);
+    launch_advect(c->stream, n, x, y, z, v_inout, prm->dt, bd, c->dom_d, c->ndom, c->dom_off_d, c->npieces);
     int rc = single_instance(c, n, x, y, z, nu, box, psi_inout, opts, stats, false);
     if (rc) return rc;
     c->fl_reuse = true;

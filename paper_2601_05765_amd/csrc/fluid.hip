@@ -115,9 +115,29 @@ __global__ __launch_bounds__(FB) void k_fluid_check(int64_t n, const double *__r
     if (!ok) atomicAdd(bad, 1);
 }
 
+// The convex rule: a site beyond n.x = c - margin is moved along -n onto that plane, in
+// two passes over the planes in order (every product and sum rounded separately).
+__device__ inline void keep_in_planes(double p[3], const float4 *__restrict__ dom, int m, double margin) {
+    for (int pass = 0; pass < 2; ++pass)
+        for (int w = 0; w < m; ++w) {
+            const float4 h = dom[w];
+            const double nx = h.x, ny = h.y, nz = h.z;
+            const double s = __dsub_rn(__dadd_rn(__dadd_rn(__dmul_rn(nx, p[0]), __dmul_rn(ny, p[1])),
+                                                 __dmul_rn(nz, p[2])),
+                                       (double)h.w);
+            const double e = __dadd_rn(s, margin);
+            if (e > 0.0) {
+                p[0] = __dsub_rn(p[0], __dmul_rn(e, nx));
+                p[1] = __dsub_rn(p[1], __dmul_rn(e, ny));
+                p[2] = __dsub_rn(p[2], __dmul_rn(e, nz));
+            }
+        }
+}
+
 __global__ __launch_bounds__(FB) void k_advect(int64_t n, float *__restrict__ x, float *__restrict__ y,
                                                float *__restrict__ z, const double *__restrict__ v, double dt,
-                                               AdvectBounds bd, const float4 *__restrict__ dom, int ndom) {
+                                               AdvectBounds bd, const float4 *__restrict__ dom, int ndom,
+                                               const int32_t *__restrict__ dom_off, int npieces) {
     const int64_t i = (int64_t)blockIdx.x * FB + threadIdx.x;
     if (i >= n) return;
     double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
@@ -126,20 +146,32 @@ __global__ __launch_bounds__(FB) void k_advect(int64_t n, float *__restrict__ x,
         const double q = __dadd_rn(p[a], __dmul_rn(dt, v[3 * i + a]));
         p[a] = fmin(fmax(q, bd.lo[a]), bd.hi[a]);
     }
-    for (int pass = 0; pass < 2; ++pass)
-        for (int w = 0; w < ndom; ++w) {
-            const float4 h = dom[w];
-            const double nx = h.x, ny = h.y, nz = h.z;
-            const double s = __dsub_rn(__dadd_rn(__dadd_rn(__dmul_rn(nx, p[0]), __dmul_rn(ny, p[1])),
-                                                 __dmul_rn(nz, p[2])),
-                                       (double)h.w);
-            const double e = __dadd_rn(s, bd.plane_margin);
-            if (e > 0.0) {
-                p[0] = __dsub_rn(p[0], __dmul_rn(e, nx));
-                p[1] = __dsub_rn(p[1], __dmul_rn(e, ny));
-                p[2] = __dsub_rn(p[2], __dmul_rn(e, nz));
+    if (npieces > 0) {
+        // a union of convex pieces: the site stays if the convex rule of some piece leaves
+        // it in place (it lies inside that piece by the margin), else it takes the nearest
+        // of its places under the pieces' rules (ties to the first piece)
+        double best[3] = {p[0], p[1], p[2]};
+        double bestd = INFINITY;
+        bool done = false;
+        for (int k = 0; k < npieces && !done; ++k) {
+            double q[3] = {p[0], p[1], p[2]};
+            keep_in_planes(q, dom + dom_off[k], dom_off[k + 1] - dom_off[k], bd.plane_margin);
+            const double dx = __dsub_rn(q[0], p[0]), dy = __dsub_rn(q[1], p[1]), dz = __dsub_rn(q[2], p[2]);
+            const double d = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            if (d < bestd) {
+                best[0] = q[0];
+                best[1] = q[1];
+                best[2] = q[2];
+                bestd = d;
             }
+            done = d == 0.0;
         }
+        p[0] = best[0];
+        p[1] = best[1];
+        p[2] = best[2];
+    } else {
+        keep_in_planes(p, dom, ndom, bd.plane_margin);
+    }
     x[i] = (float)p[0];
     y[i] = (float)p[1];
     z[i] = (float)p[2];
@@ -445,8 +477,8 @@ void launch_fluid_check(hipStream_t st, int64_t n, const double *nu, const doubl
 }
 
 void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, const double *v, double dt,
-                   const AdvectBounds &bd, const float4 *dom, int ndom) {
-    hipLaunchKernelGGL(k_advect, dim3(nb(n)), dim3(FB), 0, st, n, x, y, z, v, dt, bd, dom, ndom);
+                   const AdvectBounds &bd, const float4 *dom, int ndom, const int32_t *dom_off, int npieces) {
+    hipLaunchKernelGGL(k_advect, dim3(nb(n)), dim3(FB), 0, st, n, x, y, z, v, dt, bd, dom, ndom, dom_off, npieces);
 }
 
 int cg3_blocks(int64_t n) { return (int)((n + C3S - 1) / C3S); }

@@ -426,7 +426,7 @@ void launch_cg3_scalars(hipStream_t st, int m, int cap, const Cg3Bufs &g);
 void launch_scatter3(hipStream_t st, int64_t n, const int32_t *perm, const double *x, double *out);
 // x += dt v, clamped into the box and the domain planes (see k_advect)
 void launch_advect(hipStream_t st, int64_t n, float *x, float *y, float *z, const double *v, double dt,
-                   const AdvectBounds &bd, const float4 *dom, int ndom);
+                   const AdvectBounds &bd, const float4 *dom, int ndom, const int32_t *dom_off, int npieces);
 
 // mlp.hip
 void launch_knn_features(hipStream_t st, int64_t n, const float4 *pos_s, const int32_t *perm,

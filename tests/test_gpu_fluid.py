@@ -368,3 +368,57 @@ def test_p1_laplacian_dam_break_100k_sampled(ctx, oracle_mod):
     e = np.abs(got[rows] - want).max(axis=1) / tol
     _say(f"  max err / bound {e.max():.3f}")
     assert e.max() <= 1.0
+
+
+def test_fluid_step_in_the_l_prism(ctx, oracle_mod):
+    """One whole step in a non-convex domain (the L-shaped prism, 3 convex pieces): sites
+    pushed towards the removed quarter; positions bit-exact against the oracle's update
+    (sites that enter the quarter go to the nearest piece), the new weights valid under
+    the oracle's cells in the pieces, velocities within the bound of the velocity test."""
+    import torch
+    import paper_2601_05765_amd as L
+    n = 2500
+    _say(f"case: fluid step in the L prism, {n} sites")
+    sc = scenes.l_shape_sites(n, 6)
+    rng = np.random.default_rng(7)
+    v = rng.normal(size=(n, 3)) + np.array([1.5, 1.5, 0.0])
+    mu = rng.uniform(0.0, 0.5, n)
+    mass = np.asarray(sc.nu, np.float64)
+    dt, eps, gamma = 0.03, 0.05, 0.05
+    pieces = scenes.l_shape_pieces()
+    xyz0 = _xyz(sc)
+    x, y, z = _sites(sc)
+    psi = _t(sc.psi0, torch.float64)
+    vt = _t(v, torch.float64)
+    prm = L.default_fluid_params(dt=dt, eps=eps, gamma=gamma, gravity=(0.0, 0.0, -9.81))
+    ctx.set_domain_pieces(pieces, scenes.L_WALLS)
+    try:
+        st, its = ctx.fluid_step(x, y, z, _t(sc.nu, torch.float64), psi, _t(mass, torch.float64), vt, prm,
+                                 opts=L.default_opts(tol=1e-5), mu=_t(mu, torch.float64))
+    finally:
+        ctx.set_domain(None)
+    x1 = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+    want = oracle_mod.advect(xyz0.astype(np.float32), v, dt, pieces=pieces)
+    free = xyz0 + dt * v
+    moved = np.abs(want.astype(np.float64) - free).max(axis=1) > 1e-6
+    quarter = (free[:, 0] > 0.5) & (free[:, 1] > 0.5)
+    _say(f"  {int(moved.sum())} sites kept in the domain ({int(quarter.sum())} from the removed quarter); "
+         f"solve status {st.status}, {st.newton_iters} Newton iterations; PCG {its}")
+    assert quarter.sum() > 20
+    assert np.array_equal(x1, want)
+    assert st.status == 0
+    xyz1 = x1.astype(np.float64)
+    p1 = psi.cpu().numpy()
+    c = oracle_mod.cells_pieces(xyz1[:, 0], xyz1[:, 1], xyz1[:, 2], p1, pieces, scenes.L_WALLS)
+    err = float(np.max(np.abs(c.V - sc.nu) / sc.nu))
+    _say(f"  oracle max rel volume error at the new weights {err:.2e}")
+    assert err <= 1e-5
+    so = oracle_mod.fluid_velocity(xyz1, p1, v, mass, mu, dt=dt, eps=eps, gamma=gamma, gravity=(0, 0, -9.81),
+                                   pieces=pieces, nwalls=scenes.L_WALLS)
+    r = np.sqrt(p1)
+    rhs_err = 1e-5 * r * mass / (eps * eps) + gamma * _row_tol(so.W, p1, xyz1, xyz1, 1.0)
+    mat_err = _row_tol(so.W, p1, xyz1, so.v, mu)
+    bound = 2.0 * (dt / mass.min()) * (rhs_err + mat_err).max() + 1e-8 * np.abs(so.v).max()
+    e = np.abs(vt.cpu().numpy() - so.v).max()
+    _say(f"  max |dv| {e:.3e}, bound {bound:.3e}")
+    assert e <= bound

@@ -141,3 +141,46 @@ def test_l_prism_tiling(oracle_mod):
     # first moment of the prism: the unit box's less the removed quarter's
     m = (c.V[:, None] * c.C).sum(0)
     assert np.allclose(m, 1.0 * np.array([0.5, 0.5, 0.5]) - 0.25 * np.array([0.75, 0.75, 0.5]), atol=1e-12)
+
+
+# ---- the position update in a non-convex domain (fluid step) ----
+
+M = 1e-6  # the plane margin of the unit box: max(1e-6 x extent, 4 float32 spacings at 1)
+
+
+def _adv(p, pieces=None, domain=None):
+    import oracle
+    p = np.asarray(p, np.float32).reshape(-1, 3)
+    return oracle.advect(p, np.zeros((len(p), 3)), 0.0, pieces=pieces, domain=domain).astype(np.float64)
+
+
+def test_advect_one_piece_is_the_convex_rule(oracle_mod):
+    planes = np.array([[-1, 0, 0, 0], [1, 0, 0, 1], [0, -1, 0, 0], [0, 1, 0, 1], [0, 0, -1, 0],
+                       [0, 0, 1, 1], [0.6, 0.0, 0.8, 0.7]], np.float64)
+    rng = np.random.default_rng(2)
+    p = rng.uniform(0.0, 1.0, (500, 3)).astype(np.float32)
+    v = rng.normal(size=(500, 3))
+    a = oracle_mod.advect(p, v, 0.05, domain=planes)
+    b = oracle_mod.advect(p, v, 0.05, pieces=[(planes, list(range(7)))])
+    assert np.array_equal(a, b)
+    assert (np.abs(a.astype(np.float64) - (p + 0.05 * v)).max(axis=1) > 1e-6).sum() > 50
+
+
+def test_advect_sites_inside_pieces_stay(oracle_mod):
+    sc = scenes.l_shape_sites(400, 5)
+    p = np.stack([sc.x, sc.y, sc.z], 1)
+    inner = np.all(np.abs(p.astype(np.float64) - 0.5) > 1e-3, axis=1) & np.all((p > 1e-3) & (p < 1 - 1e-3), axis=1)
+    out = _adv(p[inner], pieces=scenes.l_shape_pieces(True))
+    assert np.array_equal(out, p[inner].astype(np.float64))
+
+
+@pytest.mark.parametrize("site,axis", [((0.6, 0.55, 0.45), 1), ((0.52, 0.7, 0.45), 0), ((0.6, 0.6, 0.45), 1)])
+def test_advect_into_the_nearest_piece(oracle_mod, site, axis):
+    """A site in the removed quarter of the L prism moves onto the nearer re-entrant wall,
+    the margin inside: (0.6, 0.55) to y = 1/2 - m (piece 1), (0.52, 0.7) to x = 1/2 - m
+    (piece 2), and (0.6, 0.6), as near to both, to the first of them (piece 1)."""
+    for split in (False, True):
+        q = _adv(site, pieces=scenes.l_shape_pieces(split))[0]
+        want = np.array(site, np.float32).astype(np.float64)
+        want[axis] = 0.5 - M
+        assert np.all(np.abs(q - want) <= 6e-8), (split, q, want)
