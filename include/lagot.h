@@ -108,7 +108,9 @@ typedef struct {
                             1: at min(1, 2 x the step length accepted by the previous iteration
                             of the call or continuation stage) -- Algorithm 1 does not say where
                             the search restarts; after short accepted steps this saves the
-                            evaluations of trials that would be halved again                   */
+                            evaluations of trials that would be halved again; 2: as 1, and the
+                            first iteration of each continuation stage after the first starts at
+                            the first step length accepted in the stage before (not at 1)        */
     int reserved;        /* must be 0                                                            */
     double stage_step;   /* first step in s of the path following, in (0, 1]      (default 0.25) */
 } lagot_opts;

@@ -924,7 +924,7 @@ int check_opts(const lagot_opts &o) {
     if (!valid_tpc(o.threads_per_cell) && o.threads_per_cell != 0) return LAGOT_EINVAL;
     if (o.continuation != 0 && o.continuation != 1) return LAGOT_EINVAL;
     if (o.continuation && (o.stage_newton < 1 || !(o.stage_tol > 0))) return LAGOT_EINVAL;
-    if ((o.step_start != 0 && o.step_start != 1) || o.reserved != 0) return LAGOT_EINVAL;
+    if (o.step_start < 0 || o.step_start > 2 || o.reserved != 0) return LAGOT_EINVAL;
     if (o.continuation && !(o.stage_step > 0.0 && o.stage_step <= 1.0)) return LAGOT_EINVAL;
     return LAGOT_OK;
 }
@@ -1358,7 +1358,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     const Batch bt = batch(c);
     hipStream_t st = c->stream;
     CtlOpts co{o.tol, o.max_newton, o.max_halvings, single ? 1 : 0, o.empty_start_fallback ? 1 : 0,
-               o.residual_test ? 1 : 0, 0};
+               o.residual_test ? 1 : 0, 0, o.step_start == 2 ? 1 : 0};
     CallTimes tm;
     int learned = 0;
     launch_zero_i32(st, c->fb_inst, B);

@@ -157,6 +157,7 @@ struct InstCtl {
     int iter_base;     // iterations before the current continuation stage (the limit counts from here)
     int pad;
     double alpha_acc;  // last accepted step length (1 at a start or a stage start)
+    double alpha_first;  // the first accepted step length of the current continuation stage (0: none)
 };
 
 // Newton options as the device control kernels see them.
@@ -164,6 +165,7 @@ struct CtlOpts {
     double tol;
     int max_newton, max_halvings, single, allow_restart, residual_test;
     int repair_more;  // a repaired start that still has an empty cell is repaired again
+    int stage_carry;  // a continuation stage's step search starts at the last stage's first accepted step
 };
 
 // Views of the evaluation outputs (sorted site order).

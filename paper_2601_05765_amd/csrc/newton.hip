@@ -839,6 +839,7 @@ __global__ __launch_bounds__(1024) void k_ctl_decide(Batch bt, CtlOpts o, const 
             c.gnorm = gnorm;
             c.minV = minV;
             c.alpha_acc = c.alpha;
+            if (c.iters == c.iter_base) c.alpha_first = c.alpha;
             phase[b] = PH_ACCEPT;
         } else {
             c.alpha *= 0.5;
@@ -900,7 +901,8 @@ __global__ __launch_bounds__(1024) void k_ctl_stage(Batch bt, CtlOpts o, const d
         c.restore = 0;
         c.iter_base = c.iters;
         c.alpha = 1.0;
-        c.alpha_acc = 1.0;
+        // the search of the stage's first iteration starts at min(1, 2 alpha_acc)
+        c.alpha_acc = (o.stage_carry && c.alpha_first > 0.0) ? 0.5 * c.alpha_first : 1.0;
         c.sumV = ev[4 * b + 0];
         c.maxrel = ev[4 * b + 1];
         c.gnorm = ev[4 * b + 2];

@@ -231,9 +231,9 @@ def test_continuation_on_easy_problem_matches_plain(ctx, oracle_mod):
 
 
 def test_continuation_first_step_one_third(ctx, oracle_mod):
-    """Path following with a first step of 1/3 in s (the bench's setting, with loose
-    intermediate stages and the step search started at twice the last step) on the
-    200,000-site splash scene from its Voronoi start: converges to the oracle's volumes."""
+    """Path following with a first step of 1/3 in s (with loose intermediate stages and
+    the step search started at twice the last step) on the 200,000-site splash scene from
+    its Voronoi start: converges to the oracle's volumes."""
     _say("case: splash 200k, continuation with stage_step 1/3")
     import torch
     import paper_2601_05765_amd as L
@@ -247,5 +247,31 @@ def test_continuation_first_step_one_third(ctx, oracle_mod):
     assert st.status == 0 and st.stages >= 1 and st.max_rel_err <= 1e-5
     ph = psi.cpu().numpy()
     idx = _sample(sc.n, ph, 31, k_top=100, k_rand=200)
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, ph, idx=idx)
+    assert float(np.max(np.abs(c.V - sc.nu[idx]) / sc.nu[idx])) <= 1e-5
+
+
+def test_continuation_stage_carry(ctx, oracle_mod):
+    """opts.step_start = 2 (the bench's setting: each continuation stage after the first
+    starts its step search at the first step length accepted in the stage before) on the
+    200,000-site splash scene from its Voronoi start: the same unique weights (oracle
+    re-evaluation of the heaviest and random cells) as with step_start = 1."""
+    _say("case: splash 200k, continuation with the stages' first steps carried")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.splash(200_000, 0)
+    x, y, z = _xyz(sc)
+    nu = _t(sc.nu, torch.float64)
+    res = {}
+    for ss in (1, 2):
+        psi = _t(sc.psi0, torch.float64)
+        opts = L.default_opts(tol=1e-5, residual_test=0, continuation=1, stage_tol=0.1, step_start=ss,
+                              cg_rtol=1e-3)
+        st = ctx.solve(x, y, z, nu, psi, opts=opts, check=False)
+        _say(f"  step_start {ss}: {st.as_dict()}")
+        assert st.status == 0 and st.stages >= 2 and st.max_rel_err <= 1e-5
+        res[ss] = psi.cpu().numpy()
+    ph = res[2]
+    idx = _sample(sc.n, ph, 37, k_top=100, k_rand=200)
     c = oracle_mod.cells(sc.x, sc.y, sc.z, ph, idx=idx)
     assert float(np.max(np.abs(c.V - sc.nu[idx]) / sc.nu[idx])) <= 1e-5

@@ -350,7 +350,7 @@ def test_step_start_option(ctx, oracle_mod):
     assert _oracle_err(oracle_mod, sc, p, idx=idx) <= 1e-5
     small = scenes.slab_uniform(300, 1)
     x, y, z, nu, psi = _dev(small)
-    for kw in ({"step_start": 2}, {"step_start": -1}, {"reserved": 1}):
+    for kw in ({"step_start": 3}, {"step_start": -1}, {"reserved": 1}):
         assert ctx.solve(x, y, z, nu, psi.clone(), opts=L.default_opts(**kw), check=False).status == L.EINVAL
 
 
