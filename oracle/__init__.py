@@ -143,7 +143,7 @@ def cells(x, y, z, psi, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96, th
 
 
 def cells_pieces(x, y, z, psi, pieces, nwalls: int, box=((0, 0, 0), (1, 1, 1)), idx=None, fcap: int = 96,
-                 threads: int = 0) -> Cells:
+                 threads: int = 0, paper_k: bool = False) -> Cells:
     """Restricted cells in a non-convex domain, the union of convex pieces with disjoint
     interiors (section 6 evaluates cells in polyhedral domains). ``pieces`` is a list of
     (planes [P_k, 4] (unit outward normal n, c: piece {x : n.x <= c}), wall_id [P_k]) with
@@ -153,9 +153,10 @@ def cells_pieces(x, y, z, psi, pieces, nwalls: int, box=((0, 0, 0), (1, 1, 1)), 
     pieces Ω_k, so every measure of it is the sum of the pieces' measures: volume,
     spherical area, the area of each facet (by neighbour), the area on each wall (by wall
     id; a plane between pieces bounds no wall), and the first moment (the centroid is
-    their sum over the total volume; an empty cell keeps the site)."""
-    parts = [cells(x, y, z, psi, box=box, idx=idx, fcap=fcap, threads=threads, domain=np.asarray(pl, np.float64))
-             for pl, _ in pieces]
+    their sum over the total volume; an empty cell keeps the site). With ``paper_k`` the
+    second route's |K| (section 3.3) is summed over the pieces too (``Kp``)."""
+    parts = [cells(x, y, z, psi, box=box, idx=idx, fcap=fcap, threads=threads, domain=np.asarray(pl, np.float64),
+                   paper_k=paper_k) for pl, _ in pieces]
     m = parts[0].V.shape[0]
     V = np.zeros(m)
     K = np.zeros(m)
@@ -187,7 +188,8 @@ def cells_pieces(x, y, z, psi, pieces, nwalls: int, box=((0, 0, 0), (1, 1, 1)), 
     site = site[parts[0].idx]
     C = np.where(V[:, None] > 0, mom / np.where(V > 0, V, 1.0)[:, None], site)
     st = np.where(V > 0, 0, 1).astype(np.int32)
-    return Cells(V, K, W, fc, fj, fA, nc, st, parts[0].idx, None, C)
+    Kp = sum(c.Kp for c in parts) if paper_k else None
+    return Cells(V, K, W, fc, fj, fA, nc, st, parts[0].idx, None, C, Kp)
 
 
 def hessian(xyz: np.ndarray, psi: np.ndarray, c: Cells):

@@ -1755,7 +1755,7 @@ int lagot_cells(lagot_ctx *c, int64_t n, const float *x, const float *y, const f
 
 int lagot_cells_paper_k(lagot_ctx *c, int64_t n, const float *x, const float *y, const float *z, const double *psi,
                         lagot_box box, double *vol, double *sph_area) {
-    if (!c || !vol || !sph_area || n <= 0 || c->npieces > 0) return LAGOT_EINVAL;
+    if (!c || !vol || !sph_area || n <= 0) return LAGOT_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LAGOT_EHIP;
     c->tpc = c->tpc_default;
     c->ms_cell = 0.0;
@@ -1775,7 +1775,22 @@ int lagot_cells_paper_k(lagot_ctx *c, int64_t n, const float *x, const float *y,
     launch_eval_begin(st, bt, -1, o);
     if (c->crowd) launch_local_reach(st, c->n, bt, -1, c->nc, c->pos_s, c->lr_rmc, c->lr_ir);
     (void)hipEventRecord(c->ev0, st);
-    launch_cells_kroute(st, n, bt, c->pos_s, c->psi_s, c->perm, c->cell_start, o, qboxes(c));
+    if (c->npieces > 0) {
+        // a non-convex domain: the route in each convex piece, V and K summed over the pieces
+        const PieceAcc acc = piece_acc(c);
+        for (int k = 0; k < c->npieces; ++k) {
+            Batch bk = bt;
+            bk.dom = c->dom_d + c->h_dom_off[k];
+            bk.ndom = c->h_dom_off[k + 1] - c->h_dom_off[k];
+            bk.npieces = 0;
+            launch_cells_kroute(st, n, bk, c->pos_s, c->psi_s, c->perm, c->cell_start, o, qboxes(c));
+            launch_piece_accum(st, n, bt, -1, k == 0, o, bk.ndom, c->dom_wid_d + c->h_dom_off[k], c->nwalls,
+                               c->perm, acc);
+        }
+        launch_piece_final(st, n, bt, -1, o, c->nwalls, c->perm, c->pos_s, nullptr, acc);
+    } else {
+        launch_cells_kroute(st, n, bt, c->pos_s, c->psi_s, c->perm, c->cell_start, o, qboxes(c));
+    }
     (void)hipEventRecord(c->ev1, st);
     c->ev_pending = true;
     launch_scatter_out_f64(st, n, c->perm, c->V, vol);

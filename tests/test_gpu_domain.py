@@ -299,8 +299,6 @@ def test_pieces_errors_and_reset(ctx):
             x[0], y[0], z[0] = p
             with pytest.raises(L.LagotError):
                 ctx.cells(*_dev(x, y, z, sc.psi0), csr=False)
-        with pytest.raises(L.LagotError):
-            ctx.cells_paper_k(*args)
         ctx.cells(*args, csr=False)
     finally:
         ctx.set_domain(None)
@@ -341,3 +339,24 @@ def test_l_prism_batched_solve(ctx, oracle_mod):
         err = float(np.max(np.abs(c.V - nu[a:b][idx]) / nu[a:b][idx]))
         _say(f"    oracle max rel volume error {err:.2e}")
         assert err <= 1e-5
+
+
+def test_l_prism_paper_k_route(ctx, oracle_mod):
+    """lagot_cells_paper_k in the L-shaped prism (6 pieces): the paper's |K| route run in
+    every piece and summed, against the oracle's route summed the same way and its signed
+    form (every cell on the float64 path; axis-aligned planes, exact in float32)."""
+    _say("case: paper K route in the L prism, 6 pieces")
+    sc = scenes.l_shape_sites(1500, 12)
+    pieces = scenes.l_shape_pieces(True)
+    ctx.set_domain_pieces(pieces, scenes.L_WALLS)
+    try:
+        V, K = ctx.cells_paper_k(*_dev(sc.x, sc.y, sc.z, sc.psi0))
+    finally:
+        ctx.set_domain(None)
+    orc = oracle_mod.cells_pieces(sc.x, sc.y, sc.z, sc.psi0, pieces, scenes.L_WALLS, paper_k=True)
+    area = 4.0 * math.pi * sc.psi0
+    eK = np.abs(K.cpu().numpy() - orc.Kp) / area
+    eK2 = np.abs(K.cpu().numpy() - orc.K) / area
+    eV = np.abs(V.cpu().numpy() - orc.V) / (area * np.sqrt(sc.psi0) / 3.0)
+    _say(f"  K vs oracle route {eK.max():.2e}, vs signed form {eK2.max():.2e}, V {eV.max():.2e}")
+    assert eK.max() <= 1e-9 and eK2.max() <= 1e-9 and eV.max() <= 1e-9

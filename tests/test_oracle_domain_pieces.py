@@ -184,3 +184,17 @@ def test_advect_into_the_nearest_piece(oracle_mod, site, axis):
         want = np.array(site, np.float32).astype(np.float64)
         want[axis] = 0.5 - M
         assert np.all(np.abs(q - want) <= 6e-8), (split, q, want)
+
+
+def test_paper_k_route_summed_over_pieces(oracle_mod):
+    """The second |K| route (section 3.3), run in each piece and summed, agrees with the
+    signed solid-angle form summed the same way (1e-10 of 4 pi r^2), in the L prism and
+    for the box split in two (where it also equals the box's own route)."""
+    sc = scenes.l_shape_sites(300, 9, spread=0.3)
+    c = oracle_mod.cells_pieces(sc.x, sc.y, sc.z, sc.psi0, scenes.l_shape_pieces(True), scenes.L_WALLS,
+                                paper_k=True)
+    assert np.max(np.abs(c.Kp - c.K) / (4 * math.pi * sc.psi0)) <= 1e-10
+    sb = scenes.random_small(120, 4, lo=0.05, hi=0.95, r_lo=0.05, r_hi=0.25)
+    h = oracle_mod.cells_pieces(sb.x, sb.y, sb.z, sb.psi0, _halves(), 6, paper_k=True)
+    w = oracle_mod.cells(sb.x, sb.y, sb.z, sb.psi0, paper_k=True)
+    assert np.max(np.abs(h.Kp - w.Kp) / (4 * math.pi * sb.psi0)) <= 1e-10
