@@ -402,8 +402,9 @@ int lagot_set_domain(lagot_ctx *ctx, int nplanes, const double *planes);
  *        n_z, c) per plane, unit outward normals (|n| within 1e-6 of 1); wall_id
  *        [piece_off[npieces]] int32 HOST; 1 <= npieces <= 16, 1 <= nwalls <= 64.
  * lagot_cells_paper_k runs its route in each piece and sums. The crowded pass is not timed
- * per piece (lagot_last_kernel_times reports no crowded-pass time), and
- * lagot_last_pass_counts gives the last piece's counts. Synchronises the stream.
+ * per piece (lagot_last_kernel_times reports no crowded-pass time); lagot_last_pass_counts
+ * gives the crowded cells summed over the pieces and the last piece's float64 count.
+ * Synchronises the stream.
  * Errors: LAGOT_EINVAL (NULL pointers, counts out of range, a normal not unit, c not
  * finite, a wall id out of range), LAGOT_EHIP.
  */

@@ -746,7 +746,7 @@ void evaluate_pieces(lagot_ctx *c, int want, const double *psi_eval, bool walls,
         bk.npieces = 0;
         EvalOut ok = o;
         ok.cen = o.cen ? acc.cen : nullptr;
-        launch_piece_begin(st, o.fb_count, o.ovf_count);
+        launch_piece_begin(st, k == 0, o.fb_count, o.ovf_count, c->misc + 8);
         if (walls) launch_zero_f32(st, c->wall, (int64_t)bk.ndom * c->n);
         launch_cells(st, c->n, bk, want, c->pos_s, psi_eval, c->perm, c->cell_start, ok, qb, c->tpc, c->crowd);
         launch_cells_fallback(st, c->n, bk, want, c->pos_s, psi_eval, c->perm, c->cell_start, ok, qb, c->crowd,
@@ -755,6 +755,8 @@ void evaluate_pieces(lagot_ctx *c, int want, const double *psi_eval, bool walls,
                            acc);
     }
     launch_piece_final(st, c->n, bt, want, o, c->nwalls, c->perm, c->pos_s, o.cen, acc);
+    // the deferred cells of all pieces as the evaluation's count (it turns the crowded pass on)
+    launch_piece_begin(st, false, nullptr, o.ovf_count, c->misc + 8);
     if (timed) (void)hipEventRecord(c->ev1, st);
     if (!c->capturing) c->ev_pending = true;
 }
@@ -1674,7 +1676,7 @@ int lagot_create(lagot_ctx **out, int device, void *stream) {
     c->device = device;
     c->noalloc = noalloc;
     c->stream = (hipStream_t)stream;
-    if (dalloc(&c->counts, 8) != hipSuccess || dalloc(&c->misc, 8) != hipSuccess ||
+    if (dalloc(&c->counts, 8) != hipSuccess || dalloc(&c->misc, 16) != hipSuccess ||
         hipHostMalloc((void **)&c->h_cnt, 16 * sizeof(int32_t)) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipEventCreate(&c->evc0) != hipSuccess || hipEventCreate(&c->evc1) != hipSuccess) {

@@ -281,9 +281,18 @@ __global__ void k_zero_f32(float *p, int64_t count) {
     if (i < count) p[i] = 0.f;
 }
 
-__global__ void k_piece_begin(int32_t *fb_count, int32_t *ovf_count) {
-    *fb_count = 0;
-    *ovf_count = 0;
+// Before each piece's passes: the last piece's deferred cells are added to the sum (which
+// the first piece starts at 0) and the list counters are cleared. Called once more after
+// the last piece without fb_count: the count then holds the sum over all pieces.
+__global__ void k_piece_begin(int first, int32_t *fb_count, int32_t *ovf_count, int32_t *ovf_sum) {
+    const int32_t s = first ? 0 : *ovf_sum + *ovf_count;
+    *ovf_sum = s;
+    if (fb_count) {
+        *fb_count = 0;
+        *ovf_count = 0;
+    } else {
+        *ovf_count = s;
+    }
 }
 
 // One piece's outputs into the accumulators (grid row k; the rows of the selected
@@ -665,8 +674,8 @@ void launch_zero_f32(hipStream_t st, float *p, int64_t count) {
     hipLaunchKernelGGL(k_zero_f32, dim3(nblocks(count, 256)), dim3(256), 0, st, p, count);
 }
 
-void launch_piece_begin(hipStream_t st, int32_t *fb_count, int32_t *ovf_count) {
-    hipLaunchKernelGGL(k_piece_begin, dim3(1), dim3(1), 0, st, fb_count, ovf_count);
+void launch_piece_begin(hipStream_t st, bool first, int32_t *fb_count, int32_t *ovf_count, int32_t *ovf_sum) {
+    hipLaunchKernelGGL(k_piece_begin, dim3(1), dim3(1), 0, st, first ? 1 : 0, fb_count, ovf_count, ovf_sum);
 }
 
 void launch_piece_accum(hipStream_t st, int64_t n, const Batch &bt, int want, bool first, const EvalOut &o,

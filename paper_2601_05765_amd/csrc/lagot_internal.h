@@ -277,7 +277,7 @@ struct PieceAcc {
     float *wall;           // [nwalls*n]
     double *cen;           // [3n] the piece pass's centroids (caller order)
 };
-void launch_piece_begin(hipStream_t st, int32_t *fb_count, int32_t *ovf_count);
+void launch_piece_begin(hipStream_t st, bool first, int32_t *fb_count, int32_t *ovf_count, int32_t *ovf_sum);
 void launch_zero_f32(hipStream_t st, float *p, int64_t count);
 void launch_piece_accum(hipStream_t st, int64_t n, const Batch &bt, int want, bool first, const EvalOut &o,
                         int nw_piece, const int32_t *wid_piece, int nwalls, const int32_t *perm, PieceAcc acc);
