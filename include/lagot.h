@@ -94,7 +94,7 @@ typedef struct {
                             solution (lagot_solve, one instance): with V0 the volumes at the start
                             weights, the targets nu(s) = (1 - s) V0 + s nu are solved by Algorithm 1
                             for s rising from 0 to 1, each stage from the previous one's weights:
-                            intermediate stages to stage_tol with at most stage_newton iterations
+                            intermediate stages to stage_tol (or stage_gtol) with at most stage_newton iterations
                             and 4 step halvings per iteration (PCG tolerance max(cg_rtol, 1e-3)),
                             the last (s = 1) to tol. The step in s starts at stage_step, doubles after
                             a stage of at most 3 iterations without halving, and halves after a stage
@@ -113,6 +113,10 @@ typedef struct {
                             the first step length accepted in the stage before (not at 1)        */
     int reserved;        /* must be 0                                                            */
     double stage_step;   /* first step in s of the path following, in (0, 1]      (default 0.25) */
+    double stage_gtol;   /* an intermediate stage also ends when ||nu(s) - V||_2 falls to stage_gtol
+                            times its value at the stage's start (the largest relative error is set
+                            by a few small cells; the bulk of the path is tracked by the norm);
+                            0 (default): stage_tol alone; else in (0, 1)                         */
 } lagot_opts;
 
 typedef struct {

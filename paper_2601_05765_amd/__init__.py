@@ -58,7 +58,8 @@ class Opts(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("use_learned", ctypes.c_int), ("empty_start_fallback", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("residual_test", ctypes.c_int),
                 ("continuation", ctypes.c_int), ("stage_newton", ctypes.c_int), ("stage_tol", ctypes.c_double),
-                ("step_start", ctypes.c_int), ("reserved", ctypes.c_int), ("stage_step", ctypes.c_double)]
+                ("step_start", ctypes.c_int), ("reserved", ctypes.c_int), ("stage_step", ctypes.c_double),
+                ("stage_gtol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

@@ -916,6 +916,7 @@ void fill_defaults(lagot_opts *o) {
     o->step_start = 0;
     o->reserved = 0;
     o->stage_step = 0.25;
+    o->stage_gtol = 0.0;
 }
 
 bool valid_tpc(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
@@ -928,6 +929,7 @@ int check_opts(const lagot_opts &o) {
     if (o.continuation && (o.stage_newton < 1 || !(o.stage_tol > 0))) return LAGOT_EINVAL;
     if (o.step_start < 0 || o.step_start > 2 || o.reserved != 0) return LAGOT_EINVAL;
     if (o.continuation && !(o.stage_step > 0.0 && o.stage_step <= 1.0)) return LAGOT_EINVAL;
+    if (!(o.stage_gtol >= 0.0 && o.stage_gtol < 1.0)) return LAGOT_EINVAL;
     return LAGOT_OK;
 }
 
@@ -1241,6 +1243,7 @@ int continuation(lagot_ctx *c, const lagot_opts &o, const CtlOpts &co, CallTimes
     cs.tol = o.stage_tol;
     cs.max_newton = o.stage_newton;
     cs.max_halvings = std::min(o.max_halvings, 4);  // a stage that needs short steps is retried closer
+    cs.gtol = o.stage_gtol;
     double s = 0.0, ds = o.stage_step;
     int stages = 0, rc = LAGOT_OK;
     for (;;) {
@@ -1360,7 +1363,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     const Batch bt = batch(c);
     hipStream_t st = c->stream;
     CtlOpts co{o.tol, o.max_newton, o.max_halvings, single ? 1 : 0, o.empty_start_fallback ? 1 : 0,
-               o.residual_test ? 1 : 0, 0, o.step_start == 2 ? 1 : 0};
+               o.residual_test ? 1 : 0, 0, o.step_start == 2 ? 1 : 0, 0.0};
     CallTimes tm;
     int learned = 0;
     launch_zero_i32(st, c->fb_inst, B);

@@ -158,6 +158,7 @@ struct InstCtl {
     int pad;
     double alpha_acc;  // last accepted step length (1 at a start or a stage start)
     double alpha_first;  // the first accepted step length of the current continuation stage (0: none)
+    double gnorm0;       // ||nu - V||_2 at the start of the current continuation stage
 };
 
 // Newton options as the device control kernels see them.
@@ -166,6 +167,7 @@ struct CtlOpts {
     int max_newton, max_halvings, single, allow_restart, residual_test;
     int repair_more;  // a repaired start that still has an empty cell is repaired again
     int stage_carry;  // a continuation stage's step search starts at the last stage's first accepted step
+    double gtol;      // > 0: an intermediate stage also ends when ||nu - V||_2 <= gtol x its start value
 };
 
 // Views of the evaluation outputs (sorted site order).

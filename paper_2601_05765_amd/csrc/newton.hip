@@ -879,7 +879,7 @@ __global__ __launch_bounds__(1024) void k_ctl_commit(Batch bt, CtlOpts o, InstCt
         if (phase[b] != PH_ACCEPT) continue;
         c.iters += 1;
         int ph = PH_ACTIVE;
-        if (c.maxrel <= o.tol || o.single) {
+        if (c.maxrel <= o.tol || o.single || (o.gtol > 0.0 && c.gnorm <= o.gtol * c.gnorm0)) {
             ph = PH_DONE;
         } else if (c.iters - c.iter_base >= o.max_newton) {
             c.status = -3;  // LAGOT_ENOCONV
@@ -907,6 +907,7 @@ __global__ __launch_bounds__(1024) void k_ctl_stage(Batch bt, CtlOpts o, const d
         c.maxrel = ev[4 * b + 1];
         c.gnorm = ev[4 * b + 2];
         c.minV = ev[4 * b + 3];
+        c.gnorm0 = c.gnorm;
         c.eps0 = 0.5 * fmin(ev_nu[4 * b + 3], ev[4 * b + 3]);
         int ph = PH_ACTIVE;
         if (!(c.eps0 > 0.0)) {

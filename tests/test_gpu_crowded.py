@@ -275,3 +275,36 @@ def test_continuation_stage_carry(ctx, oracle_mod):
     idx = _sample(sc.n, ph, 37, k_top=100, k_rand=200)
     c = oracle_mod.cells(sc.x, sc.y, sc.z, ph, idx=idx)
     assert float(np.max(np.abs(c.V - sc.nu[idx]) / sc.nu[idx])) <= 1e-5
+
+
+def test_continuation_stage_norm_stop(ctx, oracle_mod):
+    """opts.stage_gtol = 0.01 (the bench's setting: an intermediate stage also ends when
+    ||nu(s) - V||_2 has fallen to 1% of its value at the stage's start) on the 200,000-site
+    splash scene from its Voronoi start: converges to the oracle's volumes in no more
+    Newton iterations than with stage_tol alone; out-of-range values are EINVAL."""
+    _say("case: splash 200k, continuation with the stages' norm stop")
+    import torch
+    import paper_2601_05765_amd as L
+    sc = scenes.splash(200_000, 0)
+    x, y, z = _xyz(sc)
+    nu = _t(sc.nu, torch.float64)
+    its = {}
+    for gt in (0.0, 0.01, 0.5):
+        psi = _t(sc.psi0, torch.float64)
+        opts = L.default_opts(tol=1e-5, residual_test=0, continuation=1, stage_tol=0.1, step_start=2,
+                              cg_rtol=1e-3, stage_gtol=gt)
+        st = ctx.solve(x, y, z, nu, psi, opts=opts, check=False)
+        _say(f"  stage_gtol {gt}: {st.as_dict()}")
+        assert st.status == 0 and st.stages >= 2 and st.max_rel_err <= 1e-5
+        its[gt] = st.newton_iters
+    assert its[0.01] <= its[0.0]
+    ph = psi.cpu().numpy()
+    idx = _sample(sc.n, ph, 41, k_top=100, k_rand=200)
+    c = oracle_mod.cells(sc.x, sc.y, sc.z, ph, idx=idx)
+    assert float(np.max(np.abs(c.V - sc.nu[idx]) / sc.nu[idx])) <= 1e-5
+    small = scenes.slab_uniform(300, 1)
+    xs, ys, zs = _xyz(small)
+    for bad in (1.0, -0.1, float("nan")):
+        st = ctx.solve(xs, ys, zs, _t(small.nu, torch.float64), _t(small.psi0, torch.float64),
+                       opts=L.default_opts(continuation=1, stage_gtol=bad), check=False)
+        assert st.status == L.EINVAL
