@@ -25,7 +25,11 @@
  *     lagot_destroy).
  *   - Positions are float32 (x, y, z separate arrays), weights and volumes are
  *     float64. Geometry runs in float32; totals, residuals, CG inner products
- *     and the step-acceptance test run in float64 on the GPU.
+ *     and the step-acceptance test run in float64 on the GPU. Cells whose float32
+ *     result would lose accuracy are redone in float64; in a solve, once a full
+ *     Newton step near the tolerance (max relative error < 100 tol, tol <= 1e-4) fails
+ *     to halve ||nu - V||_2, the cells still off by more than tol/4 are finished in
+ *     float64 for the rest of the call, so tolerances below float32 rounding converge.
  *   - Return value: LAGOT_OK (0) or one of the negative codes below. On a
  *     Newton error, psi_inout holds the last accepted iterate.
  *   - A context is not thread-safe; calls on one context must not overlap.

@@ -122,6 +122,8 @@ struct lagot_ctx {
     int ndom = 0;
     // a non-convex domain as a union of convex pieces (lagot_set_domain_pieces; 0: convex)
     int npieces = 0, nwalls = 0;
+    uint8_t *prec = nullptr;    // [n + 4] cells a solve finishes on the float64 path (sorted order)
+    bool prec_on = false;       // set while a solve runs
     int32_t h_dom_off[PIECE_MAX + 1] = {0};
     int32_t *dom_off_d = nullptr, *dom_wid_d = nullptr;  // [PIECE_MAX + 1], [PIECE_PLANES_MAX]
     // per-piece accumulators of an evaluation (allocated with the sites when pieces are set)
@@ -218,6 +220,7 @@ void free_sites(lagot_ctx *c) {
     free_ptrs(c->pos_orig, c->pos_s, c->psi_s, c->nu_s, c->psi_trial, c->keys, c->perm, c->inst, c->V, c->K, c->wall,
               c->fcol, c->fcnt, c->fb_list, c->ovf_list, c->farea, c->flags, c->hcol, c->hcnt, c->xcnt, c->hval, c->diag,
               c->cg_vec, c->csr_cnt, c->csr_start, c->csr_tmp, c->hrow, c->qbox, c->qent, c->qlarge, c->qdstart);
+    free_ptrs(c->prec);
     c->cap_n = 0;
 }
 
@@ -353,6 +356,7 @@ int ensure_sites(lagot_ctx *c, int64_t n) {
     HIP_TRY(dalloc(&c->csr_cnt, N + 1));
     HIP_TRY(dalloc(&c->csr_start, N + 1));
     HIP_TRY(dalloc(&c->csr_tmp, N / 1024 + 16));
+    HIP_TRY(dalloc(&c->prec, N + 4));
     c->cap_n = n;
     return LAGOT_OK;
 }
@@ -749,6 +753,7 @@ void evaluate_pieces(lagot_ctx *c, int want, const double *psi_eval, bool walls,
         launch_piece_begin(st, k == 0, o.fb_count, o.ovf_count, c->misc + 8);
         if (walls) launch_zero_f32(st, c->wall, (int64_t)bk.ndom * c->n);
         launch_cells(st, c->n, bk, want, c->pos_s, psi_eval, c->perm, c->cell_start, ok, qb, c->tpc, c->crowd);
+        if (c->prec_on) launch_add_precise(st, c->n, bt, want, c->prec, ok);
         launch_cells_fallback(st, c->n, bk, want, c->pos_s, psi_eval, c->perm, c->cell_start, ok, qb, c->crowd,
                               nullptr, nullptr);
         launch_piece_accum(st, c->n, bt, want, k == 0, ok, bk.ndom, c->dom_wid_d + c->h_dom_off[k], c->nwalls, c->perm,
@@ -780,6 +785,7 @@ void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double
     if (timed) (void)hipEventRecord(c->ev0, c->stream);
     launch_cells(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->tpc, c->crowd);
     if (timed) (void)hipEventRecord(c->ev1, c->stream);
+    if (c->prec_on) launch_add_precise(c->stream, c->n, bt, want, c->prec, o);
     if (!c->capturing) c->ev_pending = true;
     const bool tc = timed && c->crowd && !c->capturing;  // the crowded pass is timed outside graphs
     launch_cells_fallback(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->crowd,
@@ -1348,6 +1354,13 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     c->ev_crowd_pending = false;
     rc = prepare(c, B, offs, x, y, z, psi, nu, boxes, &bad);
     if (rc) return fail_all(rc);
+    // cells marked for the float64 path at a stalled final iteration stay marked for the call
+    struct PrecScope {
+        lagot_ctx *c;
+        ~PrecScope() { c->prec_on = false; }
+    } prec_scope{c};
+    launch_zero_i32(c->stream, reinterpret_cast<int32_t *>(c->prec), (c->n + 3) / 4);
+    c->prec_on = true;
     c->tune_key = -1;
     c->cg_lanes = c->cg_lanes_def;
     c->cg_sub = c->cg_sub_def;
@@ -1429,6 +1442,7 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
             launch_ctl_decide(c->stream, bt, co, c->ev, c->fail_inst, c->ctl, c->phase);
             launch_accept_rows(c->stream, bt, c->ctl, c->psi_s, c->psi_trial, c->pos_s);
             launch_ctl_commit(c->stream, bt, co, c->ctl, c->phase, c->counts);
+            launch_mark_precise(c->stream, bt, co, c->ctl, c->V, c->nu_s, c->prec);
         };
         for (int h = 0; h <= o.max_halvings; ++h) {
             if (graph) {

@@ -354,6 +354,18 @@ __global__ void k_piece_accum(int64_t n, Batch bt, int want, int first, EvalOut 
             if (wid[p] >= 0) a.wall[k * nwalls + wid[p]] += o.wall[k * nwp + p];
 }
 
+// Marked cells that the float32 pass finished go to the float64 list as well.
+__global__ void k_add_precise(int64_t n, Batch bt, int want, const uint8_t *__restrict__ prec, EvalOut o) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || !prec[k]) return;
+    const int b = bt.inst[k];
+    if (!selected(bt, want, b)) return;
+    if (o.flags[k] & (CF_FAIL_MASK | CF_PREC | CF_CAND | CF_EMPTY)) return;  // listed, deferred or empty
+    o.flags[k] |= CF_PREC;
+    o.fb_list[atomicAdd(o.fb_count, 1)] = (int32_t)k;
+    atomicAdd(o.fb_inst + b, 1);
+}
+
 // The accumulated sums as the evaluation's outputs; a cell is empty when its parts are.
 __global__ void k_piece_final(int64_t n, Batch bt, int want, EvalOut o, int nwalls, const int32_t *__restrict__ perm,
                               const float4 *__restrict__ pos_s, double *__restrict__ cen_out, PieceAcc a) {
@@ -682,6 +694,10 @@ void launch_piece_accum(hipStream_t st, int64_t n, const Batch &bt, int want, bo
                         int nw_piece, const int32_t *wid_piece, int nwalls, const int32_t *perm, PieceAcc acc) {
     hipLaunchKernelGGL(k_piece_accum, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, first ? 1 : 0, o,
                        nw_piece, wid_piece, nwalls, perm, acc);
+}
+
+void launch_add_precise(hipStream_t st, int64_t n, const Batch &bt, int want, const uint8_t *prec, EvalOut o) {
+    hipLaunchKernelGGL(k_add_precise, dim3(nblocks(n, 256)), dim3(256), 0, st, n, bt, want, prec, o);
 }
 
 void launch_piece_final(hipStream_t st, int64_t n, const Batch &bt, int want, const EvalOut &o, int nwalls,

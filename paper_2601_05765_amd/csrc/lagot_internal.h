@@ -159,6 +159,7 @@ struct InstCtl {
     double alpha_acc;  // last accepted step length (1 at a start or a stage start)
     double alpha_first;  // the first accepted step length of the current continuation stage (0: none)
     double gnorm0;       // ||nu - V||_2 at the start of the current continuation stage
+    double gnorm_prev;   // ||nu - V||_2 at the accepted iterate before the current one (0: none)
 };
 
 // Newton options as the device control kernels see them.
@@ -392,6 +393,12 @@ void launch_ctl_decide(hipStream_t st, const Batch &bt, CtlOpts o, const double 
 void launch_accept_rows(hipStream_t st, const Batch &bt, const InstCtl *ctl, double *psi_s, const double *psi_trial,
                         float4 *pos_s);
 void launch_ctl_commit(hipStream_t st, const Batch &bt, CtlOpts o, InstCtl *ctl, int32_t *phase, int32_t *counts);
+// Near convergence a full Newton step that fails to halve ||nu - V|| has reached the rounding
+// of the float32 cells: the cells still off by more than tol/4 are marked (prec, sorted
+// order), and the evaluations of the rest of the call finish them on the float64 path.
+void launch_mark_precise(hipStream_t st, const Batch &bt, CtlOpts o, const InstCtl *ctl, const double *V,
+                         const double *nu, uint8_t *prec);
+void launch_add_precise(hipStream_t st, int64_t n, const Batch &bt, int want, const uint8_t *prec, EvalOut o);
 // Start of a continuation stage (every instance): the current iterate, with statistics
 // ev against the stage's prescribed volumes (statistics ev_nu), becomes the stage's
 // start: status cleared, eps0 = 0.5 min(min nu_s, min V), the iteration limit counted

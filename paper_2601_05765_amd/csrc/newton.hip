@@ -780,6 +780,7 @@ __global__ __launch_bounds__(1024) void k_ctl_start(Batch bt, CtlOpts o, int fro
         c.sumV = ev[4 * b + 0];
         c.maxrel = ev[4 * b + 1];
         c.gnorm = ev[4 * b + 2];
+        c.gnorm_prev = 0.0;
         c.minV = ev[4 * b + 3];
         // an empty start cell: first raise the empty cells' weights (again while the
         // host allows more rounds), then restart from the default weights, then give up
@@ -836,6 +837,7 @@ __global__ __launch_bounds__(1024) void k_ctl_decide(Batch bt, CtlOpts o, const 
         if (fail_inst[b] == 0 && minV >= c.eps0 && (!o.residual_test || gnorm <= (1.0 - 0.5 * c.alpha) * c.gnorm)) {
             c.sumV = sumV;
             c.maxrel = maxrel;
+            c.gnorm_prev = c.gnorm;
             c.gnorm = gnorm;
             c.minV = minV;
             c.alpha_acc = c.alpha;
@@ -855,6 +857,21 @@ __global__ __launch_bounds__(1024) void k_ctl_decide(Batch bt, CtlOpts o, const 
 }
 
 // accepted trials become the iterate; a failed search puts back the float32 shadow
+// Rows of instances that took a full step (alpha 1) to max relative error < 100 tol (tol
+// <= 1e-4: a final solve) without halving ||nu - V||: the cells off by more than tol/4.
+__global__ __launch_bounds__(TILE) void k_mark_precise(Batch bt, CtlOpts o, const InstCtl *__restrict__ ctl,
+                                                        const double *__restrict__ V, const double *__restrict__ nu,
+                                                        uint8_t *__restrict__ prec) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (bt.phase[b] != PH_ACTIVE || !(o.tol <= 1e-4)) return;
+    const InstCtl &c = ctl[b];
+    if (!(c.alpha_acc == 1.0 && c.gnorm_prev > 0.0 && c.gnorm > 0.5 * c.gnorm_prev && c.maxrel < 100.0 * o.tol)) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    if (i >= bt.off[b + 1]) return;
+    if (fabs(V[i] - nu[i]) > 0.25 * o.tol * nu[i]) prec[i] = 1;
+}
+
 __global__ __launch_bounds__(TILE) void k_accept_rows(Batch bt, const InstCtl *__restrict__ ctl,
                                                        double *__restrict__ psi, const double *__restrict__ trial,
                                                        float4 *__restrict__ pos) {
@@ -908,6 +925,7 @@ __global__ __launch_bounds__(1024) void k_ctl_stage(Batch bt, CtlOpts o, const d
         c.gnorm = ev[4 * b + 2];
         c.minV = ev[4 * b + 3];
         c.gnorm0 = c.gnorm;
+        c.gnorm_prev = 0.0;
         c.eps0 = 0.5 * fmin(ev_nu[4 * b + 3], ev[4 * b + 3]);
         int ph = PH_ACTIVE;
         if (!(c.eps0 > 0.0)) {
@@ -934,6 +952,11 @@ __global__ __launch_bounds__(256) void k_nu_stage(int64_t n, double s, const dou
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_mark_precise(hipStream_t st, const Batch &bt, CtlOpts o, const InstCtl *ctl, const double *V,
+                         const double *nu, uint8_t *prec) {
+    hipLaunchKernelGGL(k_mark_precise, dim3(bt.T), dim3(TILE), 0, st, bt, o, ctl, V, nu, prec);
+}
 
 void launch_ctl_stage(hipStream_t st, const Batch &bt, CtlOpts o, const double *ev, const double *ev_nu,
                       const int32_t *fail_inst, InstCtl *ctl, int32_t *phase, int32_t *counts) {
