@@ -99,7 +99,7 @@ typedef struct {
                             weights, the targets nu(s) = (1 - s) V0 + s nu are solved by Algorithm 1
                             for s rising from 0 to 1, each stage from the previous one's weights:
                             intermediate stages to stage_tol (or stage_gtol) with at most stage_newton iterations
-                            and 4 step halvings per iteration (PCG tolerance max(cg_rtol, 1e-3)),
+                            and 4 step halvings per iteration (PCG tolerance max(cg_rtol, 1e-2)),
                             the last (s = 1) to tol. The step in s starts at stage_step, doubles after
                             a stage of at most 3 iterations without halving, and halves after a stage
                             that fails to converge (or whose step search ends on a cell the kernels

@@ -1243,7 +1243,7 @@ int continuation(lagot_ctx *c, const lagot_opts &o, const CtlOpts &co, CallTimes
     HIP_TRY(hipMemcpyAsync(nu_t, c->nu_s, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(psi_ok, c->psi_s, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     lagot_opts os = o;
-    os.cg_rtol = std::max(o.cg_rtol, 1e-3);  // inexact directions suffice for a loose stage
+    os.cg_rtol = std::max(o.cg_rtol, 1e-2);  // inexact directions suffice for a loose stage
     os.max_newton = o.stage_newton;
     CtlOpts cs = co;
     cs.tol = o.stage_tol;
