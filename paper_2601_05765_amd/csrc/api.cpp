@@ -124,6 +124,7 @@ struct lagot_ctx {
     int npieces = 0, nwalls = 0;
     uint8_t *prec = nullptr;    // [n + 4] cells a solve finishes on the float64 path (sorted order)
     bool prec_on = false;       // set while a solve runs
+    bool start_gate = false;    // set for a one-instance start evaluation (hopeless starts skip the slow passes)
     int32_t h_dom_off[PIECE_MAX + 1] = {0};
     int32_t *dom_off_d = nullptr, *dom_wid_d = nullptr;  // [PIECE_MAX + 1], [PIECE_PLANES_MAX]
     // per-piece accumulators of an evaluation (allocated with the sites when pieces are set)
@@ -789,7 +790,7 @@ void evaluate(lagot_ctx *c, int want, const double *psi_eval, bool walls, double
     if (!c->capturing) c->ev_pending = true;
     const bool tc = timed && c->crowd && !c->capturing;  // the crowded pass is timed outside graphs
     launch_cells_fallback(c->stream, c->n, bt, want, c->pos_s, psi_eval, c->perm, c->cell_start, o, qb, c->crowd,
-                          tc ? c->evc0 : nullptr, tc ? c->evc1 : nullptr);
+                          tc ? c->evc0 : nullptr, tc ? c->evc1 : nullptr, c->start_gate ? c->nempty : nullptr);
     if (tc) c->ev_crowd_pending = true;
     if (ev_out) launch_eval_reduce(c->stream, bt, want, c->V, c->nu_s, c->part_ev, ev_out);
 }
@@ -1382,7 +1383,11 @@ int newton_run_impl(lagot_ctx *c, int B, const int64_t *offs, const float *x, co
     launch_zero_i32(st, c->fb_inst, B);
     launch_ctl_init(st, bt, c->ctl, c->phase);
     double te = now_ms();
+    // a start that the repair gate will send to the restart anyway (judged from the float32
+    // pass's empty cells) skips the crowded and float64 passes of its evaluation
+    c->start_gate = B == 1 && o.empty_start_fallback && !(o.use_learned && c->mlp_set) && c->npieces == 0;
     evaluate(c, PH_START, c->psi_s, false, c->ev);
+    c->start_gate = false;
     if (o.use_learned && c->mlp_set) {
         rc = learned_guess(c, tm, &learned);
         if (rc) return fail_all(rc);

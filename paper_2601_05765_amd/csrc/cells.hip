@@ -1857,7 +1857,7 @@ void launch_cells(hipStream_t st, int64_t n, const Batch &bt, int want, const fl
 // list lengths on the device (no host synchronisation).
 void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                            const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
-                           const QBoxes &qb, bool crowd, hipEvent_t e0, hipEvent_t e1) {
+                           const QBoxes &qb, bool crowd, hipEvent_t e0, hipEvent_t e1, int32_t *start_gate) {
     CellArgs a{n, pos_s, psi, perm, cell_start, bt, want, out, qb, crowd ? 1 : 0};
     if (!crowd) {
         hipLaunchKernelGGL(k_cells_big, dim3(2048), dim3(64), 0, st, a);
@@ -1868,6 +1868,8 @@ void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want,
     launch_scan_i32(st, qb.dcnt, qb.dstart, (int)n, qb.tmp);
     hipLaunchKernelGGL(k_defer_fill, dim3(nb), dim3(256), 0, st, n, qb.dcnt, qb.dstart, out.ovf_list);
     hipLaunchKernelGGL(k_cells_seed, dim3(4096), dim3(64), 0, st, a);
+    // a start that the repair gate would send to the restart skips the rest (empty boxes)
+    if (start_gate) launch_start_gate(st, bt, want, qb.box, out.V, start_gate, out.fb_count, out.ovf_count);
     const unsigned nz = (unsigned)((qb.nq + 256) / 256);
     hipLaunchKernelGGL(k_qbox_zero, dim3(nz), dim3(256), 0, st, qb, false);
     hipLaunchKernelGGL(k_qbox_register<false>, dim3(nb), dim3(256), 0, st, n, bt, want, out.ovf_count, qb);

@@ -482,6 +482,38 @@ __global__ void k_repair_gate(Batch bt, int want, const int32_t *__restrict__ ne
     }
 }
 
+// A one-instance start with more than 64 cells, and more than 1% of the cells, certainly
+// empty goes to the restart whatever the other passes find (the repair gate's rule). After
+// the seed pass every cell's box holds it (the exact cell, or for a crowded cell the cell
+// clipped by its nearest sites): an empty box is an empty cell. Such a start skips the
+// crowded and float64 passes of its evaluation (their lists are emptied). Every empty-box
+// cell gets its volume 0 here (what the crowded pass would write), so the skipped start
+// shows its empty cells to the step control and the repair gate.
+__global__ __launch_bounds__(TILE) void k_count_empty_boxes(Batch bt, int want, const float4 *__restrict__ box,
+                                                             double *__restrict__ V, int32_t *__restrict__ nempty) {
+    const int t = blockIdx.x;
+    const int b = bt.tile_inst[t];
+    if (!selected(bt, want, b)) return;
+    const int i = bt.tile_row[t] + (int)threadIdx.x;
+    bool e = false;
+    if (i < bt.off[b + 1]) {
+        const float4 lo = box[2 * (int64_t)i], hi = box[2 * (int64_t)i + 1];
+        e = !(lo.x <= hi.x && lo.y <= hi.y && lo.z <= hi.z);
+        if (e) V[i] = 0.0;
+    }
+    const int cnt = __syncthreads_count(e);
+    if (threadIdx.x == 0 && cnt > 0) atomicAdd(&nempty[b], cnt);
+}
+
+__global__ void k_start_gate(Batch bt, const int32_t *__restrict__ nempty, int32_t *__restrict__ fb_count,
+                             int32_t *__restrict__ ovf_count) {
+    const int64_t nb = bt.off[1] - bt.off[0];
+    if (nempty[0] > 64 && 100 * (int64_t)nempty[0] > nb) {
+        *fb_count = 0;
+        *ovf_count = 0;
+    }
+}
+
 // A start cell that is empty gets a weight that puts its site strictly inside every
 // power half-space. Let j* maximise psi_j - d_ij^2 over the other sites (value L).
 // With w = psi_j*, every bisector has t_ij = (d_ij^2 + w - psi_j) / (2 d_ij) > 0
@@ -666,6 +698,13 @@ void launch_repair_gate(hipStream_t st, const Batch &bt, int want, const double 
     hipLaunchKernelGGL(k_zero_n, dim3(nblocks(bt.B, 256)), dim3(256), 0, st, bt.B, nempty);
     hipLaunchKernelGGL(k_count_empty, dim3(bt.T), dim3(TILE), 0, st, bt, want, V, nempty);
     hipLaunchKernelGGL(k_repair_gate, dim3(nblocks(bt.B, 256)), dim3(256), 0, st, bt, want, nempty, phase, counts);
+}
+
+void launch_start_gate(hipStream_t st, const Batch &bt, int want, const float4 *box, double *V, int32_t *nempty,
+                       int32_t *fb_count, int32_t *ovf_count) {
+    hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(256), 0, st, 1, nempty);
+    hipLaunchKernelGGL(k_count_empty_boxes, dim3(bt.T), dim3(TILE), 0, st, bt, want, box, V, nempty);
+    hipLaunchKernelGGL(k_start_gate, dim3(1), dim3(1), 0, st, bt, nempty, fb_count, ovf_count);
 }
 
 void launch_repair_empty(hipStream_t st, const Batch &bt, int want, const double *V, const double *nu_s,

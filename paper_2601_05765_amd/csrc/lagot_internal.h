@@ -347,7 +347,8 @@ void launch_cells_kroute(hipStream_t st, int64_t n, const Batch &bt, const float
                          const int32_t *perm, const int32_t *cell_start, EvalOut out, const QBoxes &qb);
 void launch_cells_fallback(hipStream_t st, int64_t n, const Batch &bt, int want, const float4 *pos_s,
                            const double *psi, const int32_t *perm, const int32_t *cell_start, EvalOut out,
-                           const QBoxes &qb, bool crowd, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                           const QBoxes &qb, bool crowd, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                           int32_t *start_gate = nullptr);
 
 // newton.hip
 // ev[4b..4b+3] = sum V, max |V - nu| / nu, ||nu - V||_2, min V of every selected instance
@@ -399,6 +400,11 @@ void launch_ctl_commit(hipStream_t st, const Batch &bt, CtlOpts o, InstCtl *ctl,
 void launch_mark_precise(hipStream_t st, const Batch &bt, CtlOpts o, const InstCtl *ctl, const double *V,
                          const double *nu, uint8_t *prec);
 void launch_add_precise(hipStream_t st, int64_t n, const Batch &bt, int want, const uint8_t *prec, EvalOut o);
+// One instance's start evaluation: when the cell boxes after the seed pass show more empty
+// cells than the repair gate allows (more than 64 and more than 1%), the crowded and float64
+// passes are skipped.
+void launch_start_gate(hipStream_t st, const Batch &bt, int want, const float4 *box, double *V, int32_t *nempty,
+                       int32_t *fb_count, int32_t *ovf_count);
 // Start of a continuation stage (every instance): the current iterate, with statistics
 // ev against the stage's prescribed volumes (statistics ev_nu), becomes the stage's
 // start: status cleared, eps0 = 0.5 min(min nu_s, min V), the iteration limit counted
