@@ -334,3 +334,29 @@ def test_solve_below_the_float32_floor(ctx, oracle_mod):
     err = float(np.max(np.abs(c.V - sc.nu[idx]) / sc.nu[idx]))
     _say(f"  oracle max rel volume error {err:.2e}")
     assert err <= 1e-6
+
+
+def test_hopeless_start_restarts(ctx, oracle_mod, splash_settled):
+    """Settled 200,000-site weights at sites advected far (dt 0.05): many more than 1% of the
+    cells are empty. The start evaluation counts the certainly empty cells from the boxes
+    after the seed pass and skips its crowded and float64 passes; the solve restarts from
+    the default weights and converges to the oracle's volumes."""
+    _say("case: splash 200k, far-moved sites, start gate and restart")
+    import torch
+    import paper_2601_05765_amd as L
+    sc, _, psi = splash_settled
+    cur = scenes.advect(sc, 0.05)
+    x, y, z = _xyz(cur)
+    nu = _t(sc.nu, torch.float64)
+    p = _t(psi, torch.float64)
+    opts = L.default_opts(tol=1e-5, residual_test=0, continuation=1, stage_tol=0.1, step_start=2, cg_rtol=1e-3,
+                          stage_gtol=0.1)
+    st = ctx.solve(x, y, z, nu, p, opts=opts, check=False)
+    _say(f"  {st.as_dict()}")
+    assert st.status == 0 and st.default_start == 1 and st.repaired_start == 0 and st.max_rel_err <= 1e-5
+    ph = p.cpu().numpy()
+    idx = _sample(cur.n, ph, 47, k_top=100, k_rand=200)
+    c = oracle_mod.cells(cur.x, cur.y, cur.z, ph, idx=idx)
+    err = float(np.max(np.abs(c.V - cur.nu[idx]) / cur.nu[idx]))
+    _say(f"  oracle max rel volume error {err:.2e}")
+    assert err <= 1e-5
